@@ -1,0 +1,551 @@
+"""CPU FP64 oracle for Levenberg-Marquardt bundle adjustment.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the device library (no kernels, headers, helpers or tables); both consume the
+same seeded arrays from ``synth``.
+
+What it computes (paper: Sec. 4.3, Iterative Triangulation and Mapping):
+
+* reprojection residual of point X_j in camera i, r = pi(K_i (R_i X_j + t_i)) - z
+  (the reprojection-error equation of Sec. 4.3; the paper's equation indexes the
+  camera by j, its text by i: here i is the camera and j the point);
+* the robust objective of Sec. 4.3 restricted to its reprojection term,
+  C = 1/2 sum_k rho(||r_k||^2) with rho Huber on the squared norm, or rho(s) = s;
+* designated-fixed camera poses (Sec. 4.3), removed from the unknowns;
+* Levenberg-Marquardt with Marquardt diagonal scaling and Nielsen's damping
+  schedule (Madsen, Nielsen, Tingleff 2004, Sec. 3.2), left SE(3) increments;
+* three solvers of the damped normal equations (H + lambda D) delta = -g:
+  - ``lm_dense``: the full H from the sparse Jacobian, dense Cholesky;
+  - ``lm_schur``: points eliminated (Triggs et al. 2000, Sec. 6.1), the reduced
+    camera system solved exactly or by block-Jacobi preconditioned CG
+    (Hestenes-Stiefel), then points back-substituted;
+* ``pose_only_gn``: Gauss-Newton on one 6-DoF pose with the map fixed, the
+  localization mode of Sec. 6.4.2.
+
+Readings where the paper is silent (pose convention, loss form, damping, the
+update map, PCG stopping rule, masking of points behind a camera) are the ones
+listed in the design notes; each function states the reading it uses.
+
+Parity pins: every function here is checked by ``tests/test_oracle_pins.py``
+against closed forms, finite differences, SciPy routines or invariants.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+
+Z_MIN = 1e-6          # depth (camera units) at or below which an observation is masked
+LAMBDA_MIN = 1e-12
+LAMBDA_MAX = 1e16
+D_MIN = 1e-6
+D_MAX = 1e32
+ACCEPT_RHO = 1e-3
+
+STATUS_OK = 0
+STATUS_DAMPING = 1     # lambda reached its upper clamp
+STATUS_NUMERICAL = 2   # non-finite cost
+
+
+# ----------------------------------------------------------------------------- geometry
+
+def quat_to_rot(q: np.ndarray) -> np.ndarray:
+    """Unit quaternion (w, x, y, z) -> rotation matrix (Hamilton convention).
+    The quaternion is normalised first."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    R = np.empty(q.shape[:-1] + (3, 3))
+    R[..., 0, 0] = 1 - 2 * (y * y + z * z)
+    R[..., 0, 1] = 2 * (x * y - w * z)
+    R[..., 0, 2] = 2 * (x * z + w * y)
+    R[..., 1, 0] = 2 * (x * y + w * z)
+    R[..., 1, 1] = 1 - 2 * (x * x + z * z)
+    R[..., 1, 2] = 2 * (y * z - w * x)
+    R[..., 2, 0] = 2 * (x * z - w * y)
+    R[..., 2, 1] = 2 * (y * z + w * x)
+    R[..., 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def hat(v: np.ndarray) -> np.ndarray:
+    """Skew matrix [v]x with [v]x a = v x a."""
+    v = np.asarray(v, dtype=np.float64)
+    M = np.zeros(v.shape[:-1] + (3, 3))
+    M[..., 0, 1] = -v[..., 2]
+    M[..., 0, 2] = v[..., 1]
+    M[..., 1, 0] = v[..., 2]
+    M[..., 1, 2] = -v[..., 0]
+    M[..., 2, 0] = -v[..., 1]
+    M[..., 2, 1] = v[..., 0]
+    return M
+
+
+def se3_exp(xi: np.ndarray):
+    """Exponential map of se(3), xi = (rho, phi) with rho the translational and phi
+    the rotational part.  Returns (R, t) with R = exp([phi]x) (Rodrigues) and
+    t = V(phi) rho, V = I + B [phi]x + C [phi]x^2, A = sin(th)/th,
+    B = (1 - cos th)/th^2, C = (th - sin th)/th^3.  Series in th^2 below 1e-4."""
+    xi = np.asarray(xi, dtype=np.float64)
+    rho = xi[..., 0:3]
+    phi = xi[..., 3:6]
+    th2 = np.sum(phi * phi, axis=-1)
+    th = np.sqrt(th2)
+    small = th < 1e-4
+    ths = np.where(small, 1.0, th)
+    A = np.where(small, 1 - th2 / 6 + th2 * th2 / 120, np.sin(ths) / ths)
+    # (1 - cos th) / th^2 written with the half-angle identity 1 - cos th = 2 sin^2(th/2),
+    # which avoids the cancellation of 1 - cos th for small th
+    sh = np.sin(0.5 * ths) / (0.5 * ths)
+    B = np.where(small, 0.5 - th2 / 24 + th2 * th2 / 720, 0.5 * sh * sh)
+    Cc = np.where(small, 1.0 / 6 - th2 / 120 + th2 * th2 / 5040,
+                  (ths - np.sin(ths)) / (ths * ths * ths))
+    K = hat(phi)
+    K2 = K @ K
+    eye = np.broadcast_to(np.eye(3), K.shape)
+    R = eye + A[..., None, None] * K + B[..., None, None] * K2
+    V = eye + B[..., None, None] * K + Cc[..., None, None] * K2
+    t = np.einsum("...ij,...j->...i", V, rho)
+    return R, t
+
+
+def rot_to_quat(R: np.ndarray) -> np.ndarray:
+    """Rotation matrix -> unit quaternion (w, x, y, z) with w >= 0 (Shepperd 1978)."""
+    R = np.asarray(R, dtype=np.float64)
+    flat = R.reshape(-1, 3, 3)
+    out = np.empty((flat.shape[0], 4))
+    for n, M in enumerate(flat):
+        tr = M[0, 0] + M[1, 1] + M[2, 2]
+        cands = [tr, M[0, 0], M[1, 1], M[2, 2]]
+        k = int(np.argmax(cands))
+        if k == 0:
+            s = math.sqrt(1.0 + tr) * 2
+            q = [0.25 * s, (M[2, 1] - M[1, 2]) / s, (M[0, 2] - M[2, 0]) / s, (M[1, 0] - M[0, 1]) / s]
+        elif k == 1:
+            s = math.sqrt(1.0 + M[0, 0] - M[1, 1] - M[2, 2]) * 2
+            q = [(M[2, 1] - M[1, 2]) / s, 0.25 * s, (M[0, 1] + M[1, 0]) / s, (M[0, 2] + M[2, 0]) / s]
+        elif k == 2:
+            s = math.sqrt(1.0 + M[1, 1] - M[0, 0] - M[2, 2]) * 2
+            q = [(M[0, 2] - M[2, 0]) / s, (M[0, 1] + M[1, 0]) / s, 0.25 * s, (M[1, 2] + M[2, 1]) / s]
+        else:
+            s = math.sqrt(1.0 + M[2, 2] - M[0, 0] - M[1, 1]) * 2
+            q = [(M[1, 0] - M[0, 1]) / s, (M[0, 2] + M[2, 0]) / s, (M[1, 2] + M[2, 1]) / s, 0.25 * s]
+        q = np.array(q)
+        q /= np.linalg.norm(q)
+        if q[0] < 0:
+            q = -q
+        out[n] = q
+    return out.reshape(R.shape[:-2] + (4,))
+
+
+# ----------------------------------------------------------------------------- residual & loss
+
+def project(K: np.ndarray, R: np.ndarray, t: np.ndarray, X: np.ndarray):
+    """Perspective projection of the reprojection-error equation (Sec. 4.3):
+    P_c = R X + t, u = fx x/z + cx, v = fy y/z + cy.  K rows are (fx, fy, cx, cy).
+    Broadcasts over leading dimensions.  Returns (uv, P_c)."""
+    Pc = np.einsum("...ij,...j->...i", R, X) + t
+    z = Pc[..., 2]
+    u = K[..., 0] * Pc[..., 0] / z + K[..., 2]
+    v = K[..., 1] * Pc[..., 1] / z + K[..., 3]
+    return np.stack([u, v], axis=-1), Pc
+
+
+def huber_rho(s: np.ndarray, delta: float) -> np.ndarray:
+    """Robust loss on the squared residual norm s (Sec. 4.3 objective; the paper
+    leaves rho unspecified, Huber 1964 is the reading): rho(s) = s for s <= delta^2,
+    2 delta sqrt(s) - delta^2 otherwise; delta <= 0 means rho(s) = s."""
+    s = np.asarray(s, dtype=np.float64)
+    if delta <= 0:
+        return s.copy()
+    return np.where(s <= delta * delta, s, 2 * delta * np.sqrt(s) - delta * delta)
+
+
+def huber_weight(s: np.ndarray, delta: float) -> np.ndarray:
+    """rho'(s): 1 for s <= delta^2, delta / sqrt(s) otherwise (IRLS weight)."""
+    s = np.asarray(s, dtype=np.float64)
+    if delta <= 0:
+        return np.ones_like(s)
+    return np.where(s <= delta * delta, 1.0, delta / np.sqrt(np.maximum(s, 1e-300)))
+
+
+@dataclasses.dataclass
+class Problem:
+    """A bundle-adjustment problem in FP64.  Poses are world->camera."""
+    K: np.ndarray          # (C, 4)
+    R: np.ndarray          # (C, 3, 3)
+    t: np.ndarray          # (C, 3)
+    X: np.ndarray          # (P, 3)
+    cam: np.ndarray        # (N,)
+    pt: np.ndarray         # (N,)
+    uv: np.ndarray         # (N, 2)
+    fixed: np.ndarray      # (C,) bool
+    delta: float           # Huber delta; <= 0 plain least squares
+
+    @classmethod
+    def from_scene(cls, s) -> "Problem":
+        return cls(K=np.asarray(s.K, np.float64), R=quat_to_rot(s.q0), t=np.array(s.t0, np.float64),
+                   X=np.array(s.X0, np.float64), cam=np.asarray(s.obs_cam, np.int64),
+                   pt=np.asarray(s.obs_pt, np.int64), uv=np.asarray(s.obs_uv, np.float64),
+                   fixed=np.asarray(s.cam_fixed).astype(bool), delta=float(s.huber_delta))
+
+    @property
+    def n_cams(self):
+        return self.R.shape[0]
+
+    @property
+    def n_pts(self):
+        return self.X.shape[0]
+
+    @property
+    def n_obs(self):
+        return self.cam.shape[0]
+
+
+def residuals(p: Problem, R=None, t=None, X=None):
+    """Per-observation residuals r_k = pi(...) - z_k and the validity mask
+    (depth > Z_MIN; masked observations get r = 0)."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    X = p.X if X is None else X
+    uv, Pc = project(p.K[p.cam], R[p.cam], t[p.cam], X[p.pt])
+    valid = Pc[:, 2] > Z_MIN
+    r = np.where(valid[:, None], uv - p.uv, 0.0)
+    return r, valid, Pc
+
+
+def cost(p: Problem, R=None, t=None, X=None) -> float:
+    """C = 1/2 sum_k rho(||r_k||^2) over valid observations."""
+    r, valid, _ = residuals(p, R, t, X)
+    s = np.sum(r * r, axis=1)
+    return 0.5 * float(np.sum(huber_rho(s, p.delta)[valid]))
+
+
+def rms(p: Problem, R=None, t=None, X=None, inlier_px: float | None = None) -> float:
+    """sqrt(sum ||r||^2 / N) in pixels over valid observations (unweighted); with
+    ``inlier_px``, over observations with ||r|| <= inlier_px only."""
+    r, valid, _ = residuals(p, R, t, X)
+    s = np.sum(r * r, axis=1)
+    m = valid
+    if inlier_px is not None:
+        m = m & (s <= inlier_px * inlier_px)
+    return math.sqrt(float(np.sum(s[m])) / max(int(m.sum()), 1))
+
+
+def jacobians(p: Problem, R=None, t=None, X=None):
+    """Analytic Jacobians of r_k for a left increment T <- Exp(xi) T (xi = (rho, phi))
+    and an additive point increment:
+      J_pi = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]],
+      J_c  = J_pi [I | -[P_c]x]   (2 x 6),
+      J_p  = J_pi R               (2 x 3).
+    Masked observations get zero rows."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    X = p.X if X is None else X
+    _, valid, Pc = residuals(p, R, t, X)
+    Kk = p.K[p.cam]
+    x, y, z = Pc[:, 0], Pc[:, 1], Pc[:, 2]
+    zs = np.where(valid, z, 1.0)
+    Jpi = np.zeros((p.n_obs, 2, 3))
+    Jpi[:, 0, 0] = Kk[:, 0] / zs
+    Jpi[:, 0, 2] = -Kk[:, 0] * x / (zs * zs)
+    Jpi[:, 1, 1] = Kk[:, 1] / zs
+    Jpi[:, 1, 2] = -Kk[:, 1] * y / (zs * zs)
+    Jpi[~valid] = 0.0
+    dP = np.concatenate([np.broadcast_to(np.eye(3), (p.n_obs, 3, 3)), -hat(Pc)], axis=2)
+    Jc = Jpi @ dP
+    Jp = Jpi @ R[p.cam]
+    return Jc, Jp
+
+
+# ----------------------------------------------------------------------------- parameter layout
+
+def _free_index(fixed: np.ndarray):
+    idx = -np.ones(fixed.size, np.int64)
+    free = np.nonzero(~fixed)[0]
+    idx[free] = np.arange(free.size)
+    return idx, free.size
+
+
+def apply_step(p: Problem, dc: np.ndarray, dp: np.ndarray):
+    """Trial state: T_i <- Exp(dc_i) T_i for free cameras, X_j <- X_j + dp_j."""
+    fidx, nf = _free_index(p.fixed)
+    R = p.R.copy()
+    t = p.t.copy()
+    free = np.nonzero(~p.fixed)[0]
+    if nf:
+        dR, dt = se3_exp(dc.reshape(nf, 6))
+        R[free] = dR @ p.R[free]
+        t[free] = np.einsum("nij,nj->ni", dR, p.t[free]) + dt
+    X = p.X + dp.reshape(-1, 3)
+    return R, t, X
+
+
+def normal_equations(p: Problem):
+    """Full Gauss-Newton system over [free camera increments | point increments]:
+    H = sum_k w_k J_k^T J_k, g = sum_k w_k J_k^T r_k with w_k = rho'(||r_k||^2),
+    built from the sparse 2N x n Jacobian.  Returns (H sparse CSR, g, J, w, r)."""
+    r, valid, _ = residuals(p)
+    Jc, Jp = jacobians(p)
+    s = np.sum(r * r, axis=1)
+    w = np.where(valid, huber_weight(s, p.delta), 0.0)
+    fidx, nf = _free_index(p.fixed)
+    N = p.n_obs
+    ncam = 6 * nf
+    n = ncam + 3 * p.n_pts
+    rows, cols, vals = [], [], []
+    ci = fidx[p.cam]
+    has_c = ci >= 0
+    for comp in range(2):
+        rr = 2 * np.arange(N) + comp
+        for m in range(6):
+            rows.append(rr[has_c])
+            cols.append(6 * ci[has_c] + m)
+            vals.append(Jc[has_c, comp, m])
+        for m in range(3):
+            rows.append(rr)
+            cols.append(ncam + 3 * p.pt + m)
+            vals.append(Jp[:, comp, m])
+    J = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(2 * N, n))
+    Wd = sp.diags(np.repeat(w, 2))
+    H = (J.T @ Wd @ J).tocsr()
+    g = J.T @ (np.repeat(w, 2) * r.reshape(-1))
+    return H, np.asarray(g).ravel(), J, w, r
+
+
+def damping_diag(Hdiag: np.ndarray) -> np.ndarray:
+    """Marquardt scaling D = diag(H) clamped to [1e-6, 1e32]."""
+    return np.clip(Hdiag, D_MIN, D_MAX)
+
+
+# ----------------------------------------------------------------------------- LM driver
+
+@dataclasses.dataclass
+class LMOptions:
+    max_iters: int = 20
+    lambda0: float = 1e-4
+    solve: str = "exact"        # lm_schur: "exact" or "pcg"
+    pcg_max_iters: int = 50
+    pcg_rel_tol: float = 1e-6
+
+
+@dataclasses.dataclass
+class LMResult:
+    R: np.ndarray
+    t: np.ndarray
+    X: np.ndarray
+    iter_cost: list            # C_0, C_1, ..., C_n (accepted-state cost after each iteration)
+    lambdas: list              # lambda used for the step of each iteration
+    accepted: list             # bool per iteration
+    rhos: list
+    pcg_iters: list
+    status: int
+
+
+def _lm_loop(p: Problem, opts: LMOptions, solve_step):
+    """Levenberg-Marquardt (Madsen-Nielsen-Tingleff 2004, Alg. 3.16 with Marquardt
+    scaling).  One iteration = one (possibly reused) linearisation, one damped
+    solve, one trial cost.  Accept iff gain ratio > 1e-3 and the predicted
+    decrease is positive; on accept lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
+    on reject lambda *= nu, nu *= 2; lambda clamped to [1e-12, 1e16].  The iteration
+    count is fixed (no early stop); a run that ends with lambda at its upper clamp
+    reports STATUS_DAMPING."""
+    p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy())
+    lam = opts.lambda0
+    nu = 2.0
+    C = cost(p)
+    out = LMResult(p.R, p.t, p.X, [C], [], [], [], [], STATUS_OK)
+    lin = None
+    for _ in range(opts.max_iters):
+        if lin is None:
+            lin = normal_equations(p)
+        H, g = lin[0], lin[1]
+        D = damping_diag(H.diagonal())
+        delta, pcg_it = solve_step(p, H, g, D, lam, opts)
+        dL = 0.5 * float(delta @ (lam * D * delta - g))
+        nf = int((~p.fixed).sum())
+        Rn, tn, Xn = apply_step(p, delta[:6 * nf], delta[6 * nf:])
+        Cn = cost(p, Rn, tn, Xn)
+        rho = (C - Cn) / dL if dL != 0 else -np.inf
+        out.lambdas.append(lam)
+        out.rhos.append(rho)
+        out.pcg_iters.append(pcg_it)
+        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO:
+            p.R, p.t, p.X = Rn, tn, Xn
+            C = Cn
+            lam = lam * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+            lin = None
+            out.accepted.append(True)
+        else:
+            lam = lam * nu
+            nu = 2.0 * nu
+            out.accepted.append(False)
+        lam = min(max(lam, LAMBDA_MIN), LAMBDA_MAX)
+        out.iter_cost.append(C)
+    if not np.isfinite(C):
+        out.status = STATUS_NUMERICAL
+    elif lam >= LAMBDA_MAX:
+        out.status = STATUS_DAMPING
+    out.R, out.t, out.X = p.R, p.t, p.X
+    return out
+
+
+def _dense_step(p, H, g, D, lam, opts):
+    A = H.toarray()
+    A[np.diag_indices_from(A)] += lam * D
+    c = scipy.linalg.cho_factor(A, lower=True)
+    return scipy.linalg.cho_solve(c, -g), 0
+
+
+def lm_dense(p: Problem, opts: LMOptions | None = None) -> LMResult:
+    """O1: LM with the full damped normal equations solved by dense Cholesky."""
+    return _lm_loop(p, opts or LMOptions(), _dense_step)
+
+
+# ----------------------------------------------------------------------------- Schur complement
+
+def schur_blocks(H: sp.csr_matrix, g: np.ndarray, D: np.ndarray, lam: float, ncam: int):
+    """Split the damped system [[U*, W], [W^T, V*]] [dc; dp] = [-g_c; -g_p] and form
+    the reduced camera system S dc = b with S = U* - W V*^-1 W^T and
+    b = -g_c + W V*^-1 g_p (Triggs et al. 2000, Sec. 6.1).  V* is block diagonal
+    with 3x3 blocks, inverted block by block.  Returns (S dense, b, Vinv sparse, W)."""
+    Hd = H.tocsr()
+    n = Hd.shape[0]
+    damp = sp.diags(lam * D)
+    A = (Hd + damp).tocsr()
+    U = A[:ncam, :ncam].toarray()
+    W = A[:ncam, ncam:].tocsr()
+    V = A[ncam:, ncam:].tocsr()
+    npts = (n - ncam) // 3
+    Vb = np.zeros((npts, 3, 3))
+    Vcoo = V.tocoo()
+    Vb[Vcoo.row // 3, Vcoo.row % 3, Vcoo.col % 3] = Vcoo.data
+    Vinv_b = np.linalg.inv(Vb)
+    ii = np.repeat(np.arange(npts), 9) * 3 + np.tile(np.repeat(np.arange(3), 3), npts)
+    jj = np.repeat(np.arange(npts), 9) * 3 + np.tile(np.arange(3), 3 * npts)
+    Vinv = sp.csr_matrix((Vinv_b.reshape(-1), (ii, jj)), shape=(3 * npts, 3 * npts))
+    Y = (W @ Vinv).tocsr()
+    S = U - (Y @ W.T).toarray()
+    gc, gp = g[:ncam], g[ncam:]
+    b = -gc + Y @ gp
+    return S, np.asarray(b).ravel(), Vinv, W
+
+
+def pcg_block_jacobi(S: np.ndarray, b: np.ndarray, tol: float, max_iters: int):
+    """Preconditioned CG (Hestenes-Stiefel 1952) on S x = b with the block-Jacobi
+    preconditioner M = blockdiag(S_aa) of 6x6 camera blocks.  x0 = 0.  Stops when
+    ||r||_2 <= tol ||b||_2 (unpreconditioned residual) or after ``max_iters``
+    products with S, or if p^T S p <= 0.  Returns (x, iterations)."""
+    n = b.size
+    nb = n // 6
+    Minv = np.zeros((nb, 6, 6))
+    for a in range(nb):
+        blk = S[6 * a:6 * a + 6, 6 * a:6 * a + 6]
+        L = np.linalg.cholesky(blk)
+        Li = np.linalg.inv(L)
+        Minv[a] = Li.T @ Li
+
+    def prec(r):
+        return np.einsum("aij,aj->ai", Minv, r.reshape(nb, 6)).reshape(-1)
+
+    x = np.zeros(n)
+    r = b.copy()
+    bn = math.sqrt(float(b @ b))
+    if bn == 0.0:
+        return x, 0
+    z = prec(r)
+    pdir = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < max_iters:
+        q = S @ pdir
+        pq = float(pdir @ q)
+        it += 1
+        if not pq > 0:
+            break
+        alpha = rz / pq
+        x = x + alpha * pdir
+        r = r - alpha * q
+        if math.sqrt(float(r @ r)) <= tol * bn:
+            break
+        z = prec(r)
+        rz_new = float(r @ z)
+        beta = rz_new / rz
+        pdir = z + beta * pdir
+        rz = rz_new
+    return x, it
+
+
+def _schur_step(p, H, g, D, lam, opts):
+    nf = int((~p.fixed).sum())
+    ncam = 6 * nf
+    S, b, Vinv, W = schur_blocks(H, g, D, lam, ncam)
+    if opts.solve == "exact":
+        c = scipy.linalg.cho_factor(S, lower=True)
+        dc = scipy.linalg.cho_solve(c, b)
+        it = 0
+    else:
+        dc, it = pcg_block_jacobi(S, b, opts.pcg_rel_tol, opts.pcg_max_iters)
+    gp = g[ncam:]
+    dp = Vinv @ (-gp - W.T @ dc)
+    return np.concatenate([dc, np.asarray(dp).ravel()]), it
+
+
+def lm_schur(p: Problem, opts: LMOptions | None = None) -> LMResult:
+    """O2: LM with points eliminated (explicit Schur complement), the reduced
+    camera system solved exactly (dense Cholesky) or by block-Jacobi PCG."""
+    return _lm_loop(p, opts or LMOptions(solve="exact"), _schur_step)
+
+
+# ----------------------------------------------------------------------------- pose-only GN
+
+def pose_only_gn(K, q0, t0, X, uv, delta: float, iters: int = 10):
+    """Gauss-Newton on one world->camera pose with the map points fixed (the
+    localization mode of Sec. 6.4.2).  Each iteration: IRLS weights w = rho'(s),
+    H = sum w J_c^T J_c, g = sum w J_c^T r, delta = -H^-1 g by Cholesky, T <- Exp(delta) T.
+    No damping and no rejection; if H is not positive definite the update is skipped
+    and the status flag set.  Returns (R, t, status, costs)."""
+    R = quat_to_rot(np.asarray(q0, np.float64))
+    t = np.array(t0, np.float64)
+    X = np.asarray(X, np.float64)
+    uv = np.asarray(uv, np.float64)
+    K = np.asarray(K, np.float64)
+    status = 0
+    costs = []
+    for _ in range(iters):
+        pr, Pc = project(K[None, :], R[None], t[None], X)
+        valid = Pc[:, 2] > Z_MIN
+        r = np.where(valid[:, None], pr - uv, 0.0)
+        s = np.sum(r * r, axis=1)
+        w = np.where(valid, huber_weight(s, delta), 0.0)
+        costs.append(0.5 * float(np.sum(huber_rho(s, delta)[valid])))
+        x, y, z = Pc[:, 0], Pc[:, 1], np.where(valid, Pc[:, 2], 1.0)
+        Jpi = np.zeros((X.shape[0], 2, 3))
+        Jpi[:, 0, 0] = K[0] / z
+        Jpi[:, 0, 2] = -K[0] * x / (z * z)
+        Jpi[:, 1, 1] = K[1] / z
+        Jpi[:, 1, 2] = -K[1] * y / (z * z)
+        dP = np.concatenate([np.broadcast_to(np.eye(3), (X.shape[0], 3, 3)), -hat(Pc)], axis=2)
+        Jc = Jpi @ dP
+        H = np.einsum("n,nki,nkj->ij", w, Jc, Jc)
+        g = np.einsum("n,nki,nk->i", w, Jc, r)
+        try:
+            L = np.linalg.cholesky(H)
+        except np.linalg.LinAlgError:
+            status = 1
+            continue
+        d = -scipy.linalg.cho_solve((L, True), g)
+        dR, dt = se3_exp(d)
+        R = dR @ R
+        t = dR @ t + dt
+    pr, Pc = project(K[None, :], R[None], t[None], X)
+    valid = Pc[:, 2] > Z_MIN
+    r = np.where(valid[:, None], pr - uv, 0.0)
+    costs.append(0.5 * float(np.sum(huber_rho(np.sum(r * r, axis=1), delta)[valid])))
+    return R, t, status, costs
