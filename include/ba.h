@@ -1,0 +1,211 @@
+/* ba.h - C-ABI of the MI355X bundle-adjustment library (libba_mi355x.so).
+ *
+ * What the library computes (paper, Sec. 4.3 "Iterative Triangulation and
+ * Mapping"): Levenberg-Marquardt bundle adjustment of SE(3) camera poses and
+ * 3D points that minimises C = 1/2 sum_k rho(||r_k||^2) over observations k of
+ * point j in camera i, with the reprojection residual of Sec. 4.3,
+ *     r_k = pi(K_i (R_i X_j + t_i)) - z_k,   pi(x, y, z) = (x/z, y/z),
+ * rho the Huber loss on the squared norm (huber_delta > 0) or rho(s) = s,
+ * and arbitrary camera subsets held fixed (Sec. 4.3, fixed-pose designation).
+ * Each iteration linearises, forms the per-camera, per-point and camera-point
+ * Hessian blocks, eliminates the points (Schur complement onto the reduced
+ * camera system), solves that system with block-Jacobi preconditioned CG and
+ * back-substitutes the points.  The pose-only entry refines single poses
+ * against a fixed map (the localization mode of Sec. 6.4.2).
+ *
+ * Conventions
+ *  - Poses are world -> camera: P_c = R X + t, R from the unit quaternion
+ *    (qw, qx, qy, qz), Hamilton convention.  A quaternion whose norm differs
+ *    from 1 by more than 1e-6 is rejected; otherwise it is renormalised.
+ *  - Pixels: origin at the top-left image corner, u to the right, v down.
+ *  - Updates: T <- Exp(xi) T with xi = (rho, phi) in se(3); points additive.
+ *  - Ownership: every input is copied during the call that receives it; the
+ *    caller may free its arrays afterwards.  Outputs go to caller buffers.
+ *    Handles belong to the caller until destroyed.
+ *  - Errors: every entry returns an int status (BA_OK = 0, negative on error).
+ *    Validation happens before any side effect.  ba_last_error() returns a
+ *    thread-local message for the last failing call on this thread.
+ *    Non-convergence is not an error: it is reported in ba_report.status.
+ *  - Threading: a ba_problem handle must not be used from two threads at once.
+ *    All ba_server_* calls are thread-safe.
+ *  - Streams: hip_stream may be NULL (the library then creates its own stream)
+ *    or a hipStream_t owned by the caller (for example PyTorch's current
+ *    stream); the library never destroys a caller's stream.
+ */
+#ifndef BA_MI355X_H
+#define BA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BA_OK 0
+#define BA_EINVAL (-1)   /* invalid argument or problem description            */
+#define BA_ENOMEM (-2)   /* device allocation failed, or request exceeds budget  */
+#define BA_EDEVICE (-3)  /* HIP runtime error                                   */
+#define BA_ESTATE (-4)   /* call not valid in the object's current state        */
+
+/* precision modes */
+#define BA_PREC_F64 0    /* everything in FP64 (parity build)                                */
+#define BA_PREC_F32 1    /* FP32 projection/Jacobians/Schur/SpMV; FP64 state, dot products,
+                            cost and gain reductions and 6x6 preconditioner inverses        */
+#define BA_PREC_F16J 2   /* as F32, Jacobians stored in FP16 (FP32 accumulation)             */
+#define BA_PREC_BF16J 3  /* as F32, Jacobians stored in BF16 (FP32 accumulation)             */
+
+/* ba_report.status */
+#define BA_STATUS_OK 0
+#define BA_STATUS_DAMPING 1    /* lambda ended at its upper clamp (1e16)     */
+#define BA_STATUS_NUMERICAL 2  /* the cost became non-finite                  */
+
+typedef struct { double fx, fy, cx, cy; } ba_intrinsics;         /* pinhole, no distortion  */
+typedef struct { double qw, qx, qy, qz, tx, ty, tz; } ba_pose;   /* world -> camera         */
+typedef struct { int32_t cam, pt; double u, v; } ba_obs;         /* one 2D observation      */
+
+typedef struct {
+  int32_t max_iters;      /* LM iterations (accepted and rejected both count), >= 1      */
+  int32_t pcg_max_iters;  /* products with S per linear solve, >= 1                      */
+  double pcg_rel_tol;     /* stop when ||r||_2 <= tol * ||b||_2                           */
+  double lambda0;         /* initial LM damping, > 0                                      */
+  double huber_delta;     /* <= 0: plain least squares; > 0: Huber threshold in pixels    */
+  int32_t precision;      /* BA_PREC_*                                                    */
+  int32_t reserved;       /* must be 0                                                    */
+} ba_options;
+
+typedef struct {
+  int32_t iters;          /* iterations run                                               */
+  int32_t accepted;       /* accepted steps                                               */
+  int32_t status;         /* BA_STATUS_*                                                  */
+  int32_t n_masked;       /* observations with depth <= 1e-6 at the final state           */
+  double cost0;           /* C at the initial state                                       */
+  double cost;            /* C at the final state                                         */
+  double rms_px;          /* sqrt(sum ||r||^2 / N) over unmasked observations             */
+  double lambda;          /* damping after the last iteration                             */
+  double *iter_cost;      /* caller buffer of max_iters + 1 entries, or NULL: C_0..C_n    */
+  int32_t *pcg_iters;     /* caller buffer of max_iters entries, or NULL                  */
+  double solve_ms;        /* device time of the iteration loop (HIP events)               */
+  double setup_ms;        /* host symbolic analysis + upload time                         */
+} ba_report;
+
+typedef struct {                 /* one problem; all pointers are host memory          */
+  int32_t n_cams;
+  const ba_intrinsics *K;        /* n_cams entries, or 1 entry shared (K_per_cam = 0)  */
+  int32_t K_per_cam;
+  const ba_pose *poses;          /* n_cams initial poses                               */
+  const uint8_t *cam_fixed;      /* n_cams flags (1 = held fixed), or NULL for none    */
+  int32_t n_pts;
+  const double *points_xyz;      /* 3 * n_pts initial points                           */
+  int64_t n_obs;
+  const ba_obs *obs;             /* n_obs observations, any order; each (cam, pt) at most once */
+} ba_problem_desc;
+
+typedef struct ba_problem ba_problem;
+typedef struct ba_server ba_server;
+
+/* Library version string. */
+const char *ba_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *ba_last_error(void);
+/* Fill *opt with the defaults: 10 iterations, PCG 50 / 1e-6, lambda0 1e-4,
+   no robust loss, BA_PREC_F32. */
+void ba_default_options(ba_options *opt);
+
+/* Validate and copy a problem, run the symbolic analysis (observation order,
+   Hessian-block and reduced-camera-system sparsity, pair lists of the Schur
+   complement) and upload it to the current HIP device.  BA_EINVAL: index out
+   of range, non-finite input, bad quaternion, duplicate (cam, pt), n_obs = 0,
+   every camera fixed, or bad options.  BA_ENOMEM: device allocation failed. */
+int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
+              ba_problem **out);
+/* Run opt->max_iters LM iterations from the current state (lambda reset to
+   lambda0) and wait for them.  The state after the call is the last accepted one. */
+int ba_solve(ba_problem *p);
+/* Enqueue the iterations on the problem's stream and return; ba_wait blocks. */
+int ba_solve_async(ba_problem *p);
+int ba_wait(ba_problem *p);
+/* Restore the poses and points given to ba_create (device-side copy; the
+   structure, buffers and options are kept).  The next solve starts from them. */
+int ba_reset(ba_problem *p);
+/* Copy the current state and the report of the last solve.  NULL outputs are
+   skipped.  poses_out: n_cams entries; points_out: 3 * n_pts doubles. */
+int ba_get_result(const ba_problem *p, ba_pose *poses_out, double *points_out, ba_report *rep);
+/* Sizes found by the symbolic analysis. */
+typedef struct {
+  int32_t n_cams, n_free_cams, n_pts, n_obs;
+  int64_t n_pairs;        /* observation pairs (k_a, k_b), a < b, both cameras free   */
+  int32_t n_up_blocks;    /* upper off-diagonal 6x6 blocks of the reduced system       */
+  int32_t nnzb;           /* stored 6x6 blocks of S (both triangles and the diagonal)  */
+  int32_t n_free_obs;     /* observations in free cameras                             */
+  int32_t precision;
+} ba_problem_info;
+int ba_get_info(const ba_problem *p, ba_problem_info *out);
+/* Device bytes held by the problem (the admission byte model of the server). */
+int64_t ba_problem_bytes(const ba_problem *p);
+void ba_destroy(ba_problem *p);
+
+/* Per-kernel device time of the last solve, summed over its launches (HIP
+   events recorded on the problem's stream around each launch).  Enabled by
+   ba_set_profiling(p, mask) before ba_solve: bit i of mask times kernel i in the
+   order ba_get_kernel_times reports them (-1: all, 0: off).  names/ms/launches: caller arrays of max_kernels entries;
+   *n_out receives the number of kernels. */
+int ba_set_profiling(ba_problem *p, int32_t enable);
+int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
+                        double *ms, int32_t *launches, int32_t *n_out);
+
+/* ---------------------------------------------------------------- pose-only */
+typedef struct {                 /* one localization request (host memory)             */
+  ba_intrinsics K;
+  ba_pose pose0;                 /* initial world -> camera pose                       */
+  int32_t n;                     /* correspondences, 1 .. BA_POSE_MAX_CORR              */
+  const double *X;               /* 3n map points (world)                              */
+  const double *uv;              /* 2n pixels                                          */
+} ba_pose_request;
+#define BA_POSE_MAX_CORR 4096
+
+/* Gauss-Newton on each pose with the map fixed: opt->max_iters iterations of
+   delta = -H^-1 g (6x6 FP64 Cholesky), T <- Exp(delta) T, Huber weights from
+   opt->huber_delta; no damping.  All requests run in one launch.  status_out[r]
+   is 0, or 1 if some iteration met a non-positive-definite H (that update is
+   skipped).  cost_out[r] = C at the final pose.  Any output may be NULL. */
+int ba_pose_batch(int32_t n_req, const ba_pose_request *reqs, const ba_options *opt,
+                  void *hip_stream, ba_pose *poses_out, int32_t *status_out, double *cost_out,
+                  double *device_ms);
+
+/* ---------------------------------------------------------------- serving
+   Continuous batching: submitted problems wait in a queue; a scheduler thread
+   admits them while a slot is free and their device bytes fit the budget, and
+   advances every admitted problem by one LM iteration per batched launch
+   sequence; a finished problem retires, frees its bytes and its slot, and the
+   next queued one joins the running batch.  Pose-only requests run in batched
+   pose launches between LM steps.  All problems of a server use the server's
+   precision.  Results do not depend on which other problems share a batch. */
+typedef struct {
+  double p50_ms, p99_ms;   /* submit -> result-ready latency                            */
+  double solves_per_s;     /* completed / (last completion - first submission)           */
+  int64_t done, queued, active;
+  int64_t bytes_in_use, peak_bytes;
+} ba_server_stats_t;
+
+int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precision,
+                     void *hip_stream, ba_server **out);
+/* Copy and analyse the problem and queue it.  BA_ENOMEM if its bytes alone
+   exceed the budget.  *ticket identifies it in ba_server_wait. */
+int ba_server_submit(ba_server *s, const ba_problem_desc *d, const ba_options *opt,
+                     int64_t *ticket);
+int ba_server_submit_pose(ba_server *s, const ba_pose_request *req, const ba_options *opt,
+                          int64_t *ticket);
+/* Block until the ticket finishes and copy its result (each ticket once).
+   For pose tickets, points_out is ignored and rep->iters/status/cost are set. */
+int ba_server_wait(ba_server *s, int64_t ticket, ba_pose *poses_out, double *points_out,
+                   ba_report *rep);
+int ba_server_stats(ba_server *s, ba_server_stats_t *out);
+/* Cancel queued requests, finish active ones, free everything. */
+void ba_server_destroy(ba_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BA_MI355X_H */

@@ -1,0 +1,356 @@
+"""Python binding of libba_mi355x.so (ctypes; argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels.  If the shared
+library is missing this module raises on first use; there is no fallback.
+Functions mirror the C-ABI in ``include/ba.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libba_mi355x.so")
+
+BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE = 0, -1, -2, -3, -4
+PREC = {"f64": 0, "f32": 1, "f16j": 2, "bf16j": 3}
+POSE_MAX_CORR = 4096
+
+
+class BAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ba error {code}: {msg}")
+        self.code = code
+
+
+class Intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Pose(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("qw", "qx", "qy", "qz", "tx", "ty", "tz")]
+
+
+class Options(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("pcg_max_iters", C.c_int32),
+                ("pcg_rel_tol", C.c_double), ("lambda0", C.c_double),
+                ("huber_delta", C.c_double), ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("accepted", C.c_int32), ("status", C.c_int32),
+                ("n_masked", C.c_int32), ("cost0", C.c_double), ("cost", C.c_double),
+                ("rms_px", C.c_double), ("lambda_", C.c_double),
+                ("iter_cost", C.POINTER(C.c_double)), ("pcg_iters", C.POINTER(C.c_int32)),
+                ("solve_ms", C.c_double), ("setup_ms", C.c_double)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("K", C.c_void_p), ("K_per_cam", C.c_int32),
+                ("poses", C.c_void_p), ("cam_fixed", C.c_void_p), ("n_pts", C.c_int32),
+                ("points_xyz", C.c_void_p), ("n_obs", C.c_int64), ("obs", C.c_void_p)]
+
+
+class PoseRequest(C.Structure):
+    _fields_ = [("K", Intrinsics), ("pose0", Pose), ("n", C.c_int32),
+                ("X", C.c_void_p), ("uv", C.c_void_p)]
+
+
+class ProblemInfo(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_free_cams", C.c_int32), ("n_pts", C.c_int32),
+                ("n_obs", C.c_int32), ("n_pairs", C.c_int64), ("n_up_blocks", C.c_int32),
+                ("nnzb", C.c_int32), ("n_free_obs", C.c_int32), ("precision", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("solves_per_s", C.c_double),
+                ("done", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
+                ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64)]
+
+
+OBS_DTYPE = np.dtype([("cam", "<i4"), ("pt", "<i4"), ("u", "<f8"), ("v", "<f8")])
+
+_lib = None
+
+
+def lib():
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with "
+                           "`python -m paper_2510_15271_amd.build_lib`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.ba_version.restype = C.c_char_p
+    L.ba_last_error.restype = C.c_char_p
+    L.ba_default_options.argtypes = [C.POINTER(Options)]
+    L.ba_create.argtypes = [C.POINTER(ProblemDesc), C.POINTER(Options), vp, C.POINTER(vp)]
+    L.ba_solve.argtypes = [vp]
+    L.ba_solve_async.argtypes = [vp]
+    L.ba_wait.argtypes = [vp]
+    L.ba_reset.argtypes = [vp]
+    L.ba_get_result.argtypes = [vp, vp, vp, C.POINTER(Report)]
+    L.ba_get_info.argtypes = [vp, C.POINTER(ProblemInfo)]
+    L.ba_problem_bytes.argtypes = [vp]
+    L.ba_problem_bytes.restype = i64
+    L.ba_destroy.argtypes = [vp]
+    L.ba_destroy.restype = None
+    L.ba_set_profiling.argtypes = [vp, i32]
+    L.ba_get_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_char_p), dp, C.POINTER(i32),
+                                      C.POINTER(i32)]
+    L.ba_pose_batch.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
+                                C.POINTER(i32), dp, dp]
+    L.ba_server_create.argtypes = [i64, i32, i32, vp, C.POINTER(vp)]
+    L.ba_server_submit.argtypes = [vp, C.POINTER(ProblemDesc), C.POINTER(Options), C.POINTER(i64)]
+    L.ba_server_submit_pose.argtypes = [vp, C.POINTER(PoseRequest), C.POINTER(Options),
+                                        C.POINTER(i64)]
+    L.ba_server_wait.argtypes = [vp, i64, vp, vp, C.POINTER(Report)]
+    L.ba_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.ba_server_destroy.argtypes = [vp]
+    L.ba_server_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != BA_OK:
+        raise BAError(rc, lib().ba_last_error().decode())
+
+
+def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,
+            precision="f32") -> Options:
+    o = Options()
+    lib().ba_default_options(C.byref(o))
+    o.max_iters = max_iters
+    o.pcg_max_iters = pcg_max_iters
+    o.pcg_rel_tol = pcg_rel_tol
+    o.lambda0 = lambda0
+    o.huber_delta = huber_delta
+    o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    return o
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class _Desc:
+    """Holds the contiguous host arrays a ProblemDesc points to."""
+
+    def __init__(self, K, q, t, X, obs_cam, obs_pt, obs_uv, cam_fixed=None):
+        K = np.ascontiguousarray(np.atleast_2d(K), dtype=np.float64)
+        self.K = K
+        self.poses = np.ascontiguousarray(np.concatenate([np.asarray(q, np.float64),
+                                                          np.asarray(t, np.float64)], axis=1))
+        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        n = len(obs_cam)
+        obs = np.empty(n, OBS_DTYPE)
+        obs["cam"] = obs_cam
+        obs["pt"] = obs_pt
+        obs["u"] = np.asarray(obs_uv)[:, 0]
+        obs["v"] = np.asarray(obs_uv)[:, 1]
+        self.obs = obs
+        self.fixed = None if cam_fixed is None else np.ascontiguousarray(cam_fixed, dtype=np.uint8)
+        d = ProblemDesc()
+        d.n_cams = self.poses.shape[0]
+        d.K = _ptr(self.K)
+        d.K_per_cam = 1 if K.shape[0] == d.n_cams and d.n_cams > 1 else 0
+        if K.shape[0] not in (1, d.n_cams):
+            raise ValueError("K must have one row or one row per camera")
+        d.poses = _ptr(self.poses)
+        d.cam_fixed = _ptr(self.fixed)
+        d.n_pts = self.X.shape[0]
+        d.points_xyz = _ptr(self.X)
+        d.n_obs = n
+        d.obs = _ptr(self.obs)
+        self.desc = d
+
+
+def scene_desc(scene) -> _Desc:
+    return _Desc(scene.K, scene.q0, scene.t0, scene.X0, scene.obs_cam, scene.obs_pt,
+                 scene.obs_uv, scene.cam_fixed)
+
+
+class Problem:
+    """One bundle-adjustment problem resident on the device."""
+
+    def __init__(self, desc: _Desc, opts: Options, stream=None):
+        self._desc = desc
+        self.opts = opts
+        self.n_cams = desc.desc.n_cams
+        self.n_pts = desc.desc.n_pts
+        h = C.c_void_p()
+        _check(lib().ba_create(C.byref(desc.desc), C.byref(opts), stream, C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_scene(cls, scene, stream=None, **kw):
+        if "huber_delta" not in kw:
+            kw["huber_delta"] = scene.huber_delta
+        return cls(scene_desc(scene), options(**kw), stream)
+
+    def solve(self):
+        _check(lib().ba_solve(self._h))
+        return self
+
+    def reset(self):
+        _check(lib().ba_reset(self._h))
+        return self
+
+    def solve_async(self):
+        _check(lib().ba_solve_async(self._h))
+
+    def wait(self):
+        _check(lib().ba_wait(self._h))
+
+    def set_profiling(self, mask=-1):
+        """mask: -1 all kernels, 0 off, or a bit mask over kernel_names()."""
+        m = int(mask)
+        if m >= 2 ** 31:
+            m -= 2 ** 32
+        _check(lib().ba_set_profiling(self._h, m))
+
+    def info(self):
+        i = ProblemInfo()
+        _check(lib().ba_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in ProblemInfo._fields_}
+
+    def kernel_times(self):
+        n = 16
+        names = (C.c_char_p * n)()
+        ms = (C.c_double * n)()
+        la = (C.c_int32 * n)()
+        cnt = C.c_int32()
+        _check(lib().ba_get_kernel_times(self._h, n, names, ms, la, C.byref(cnt)))
+        return {names[i].decode(): (ms[i], la[i]) for i in range(cnt.value)}
+
+    @property
+    def nbytes(self):
+        return int(lib().ba_problem_bytes(self._h))
+
+    def report(self):
+        """Report of the last solve without downloading the state."""
+        ic = np.zeros(self.opts.max_iters + 1)
+        pi = np.zeros(self.opts.max_iters, np.int32)
+        rep = Report()
+        rep.iter_cost = ic.ctypes.data_as(C.POINTER(C.c_double))
+        rep.pcg_iters = pi.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ba_get_result(self._h, None, None, C.byref(rep)))
+        return _report_dict(rep, np.zeros((0, 7)), None, ic, pi)
+
+    def result(self):
+        poses = np.zeros((self.n_cams, 7))
+        pts = np.zeros((self.n_pts, 3))
+        ic = np.zeros(self.opts.max_iters + 1)
+        pi = np.zeros(self.opts.max_iters, np.int32)
+        rep = Report()
+        rep.iter_cost = ic.ctypes.data_as(C.POINTER(C.c_double))
+        rep.pcg_iters = pi.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ba_get_result(self._h, _ptr(poses), _ptr(pts), C.byref(rep)))
+        return _report_dict(rep, poses, pts, ic, pi)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ba_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _report_dict(rep, poses, pts, ic, pi):
+    it = rep.iters
+    return dict(q=poses[:, :4], t=poses[:, 4:], X=pts, iters=it, accepted=rep.accepted,
+                status=rep.status, n_masked=rep.n_masked, cost0=rep.cost0, cost=rep.cost,
+                rms_px=rep.rms_px, lam=rep.lambda_, iter_cost=ic[:it + 1].copy(),
+                pcg_iters=pi[:it].copy(), solve_ms=rep.solve_ms, setup_ms=rep.setup_ms)
+
+
+def _pose_request(K, q0, t0, X, uv, keep):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    uv = np.ascontiguousarray(uv, dtype=np.float64)
+    keep.append((X, uv))
+    r = PoseRequest()
+    r.K = Intrinsics(*[float(v) for v in K])
+    r.pose0 = Pose(*[float(v) for v in q0], *[float(v) for v in t0])
+    r.n = X.shape[0]
+    r.X = _ptr(X)
+    r.uv = _ptr(uv)
+    return r
+
+
+def pose_batch(requests, iters=10, huber_delta=1.0, stream=None):
+    """Pose-only Gauss-Newton for a list of synth.PoseRequest-like objects."""
+    keep = []
+    arr = (PoseRequest * len(requests))()
+    for i, q in enumerate(requests):
+        arr[i] = _pose_request(q.K, q.q0, q.t0, q.X, q.uv, keep)
+    o = options(max_iters=iters, huber_delta=huber_delta)
+    poses = np.zeros((len(requests), 7))
+    status = np.zeros(len(requests), np.int32)
+    cost = np.zeros(len(requests))
+    ms = C.c_double()
+    _check(lib().ba_pose_batch(len(requests), arr, C.byref(o), stream, _ptr(poses),
+                               status.ctypes.data_as(C.POINTER(C.c_int32)),
+                               cost.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)))
+    return dict(q=poses[:, :4], t=poses[:, 4:], status=status, cost=cost, device_ms=ms.value)
+
+
+class Server:
+    """Continuous-batching server (see ba_server_* in include/ba.h)."""
+
+    def __init__(self, budget_bytes, max_slots, precision="f32", stream=None):
+        h = C.c_void_p()
+        self.precision = precision
+        _check(lib().ba_server_create(int(budget_bytes), int(max_slots),
+                                      PREC[precision] if isinstance(precision, str) else precision,
+                                      stream, C.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit(self, desc: _Desc, opts: Options) -> int:
+        t = C.c_int64()
+        _check(lib().ba_server_submit(self._h, C.byref(desc.desc), C.byref(opts), C.byref(t)))
+        self._meta[t.value] = (desc.desc.n_cams, desc.desc.n_pts, opts.max_iters, False)
+        return t.value
+
+    def submit_pose(self, req, iters=10, huber_delta=1.0) -> int:
+        keep = []
+        r = _pose_request(req.K, req.q0, req.t0, req.X, req.uv, keep)
+        o = options(max_iters=iters, huber_delta=huber_delta, precision=self.precision)
+        t = C.c_int64()
+        _check(lib().ba_server_submit_pose(self._h, C.byref(r), C.byref(o), C.byref(t)))
+        self._meta[t.value] = (1, 0, iters, True)
+        return t.value
+
+    def wait(self, ticket):
+        nc, npt, iters, is_pose = self._meta.pop(ticket)
+        poses = np.zeros((nc, 7))
+        pts = np.zeros((max(npt, 1), 3))
+        ic = np.zeros(iters + 1)
+        pi = np.zeros(max(iters, 1), np.int32)
+        rep = Report()
+        rep.iter_cost = ic.ctypes.data_as(C.POINTER(C.c_double))
+        rep.pcg_iters = pi.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ba_server_wait(self._h, ticket, _ptr(poses), _ptr(pts), C.byref(rep)))
+        d = _report_dict(rep, poses, pts[:npt], ic, pi)
+        d["latency_ms"] = rep.solve_ms
+        d["pose_only"] = is_pose
+        return d
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().ba_server_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ba_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,877 @@
+// Host runtime of the bundle-adjustment library: validation, symbolic
+// analysis, device layout, the Levenberg-Marquardt driver and the C-ABI.
+//
+// The symbolic analysis (done once per problem) orders observations by
+// (point, camera), groups the observations of every free camera, and builds
+// the block sparsity of the reduced camera system S together with, for every
+// upper off-diagonal block (a, b), the list of observation pairs (k_a, k_b) of
+// the points seen by both cameras.  The device then forms S block by block
+// from those lists without atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_internal.h"
+#include "ba_runtime.h"
+
+namespace bax {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? BA_ENOMEM : BA_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ pose conversions
+void quat_to_pose12(const ba_pose &p, double out[12]) {
+  const double n = std::sqrt(p.qw * p.qw + p.qx * p.qx + p.qy * p.qy + p.qz * p.qz);
+  const double w = p.qw / n, x = p.qx / n, y = p.qy / n, z = p.qz / n;
+  out[0] = 1 - 2 * (y * y + z * z);
+  out[1] = 2 * (x * y - w * z);
+  out[2] = 2 * (x * z + w * y);
+  out[3] = 2 * (x * y + w * z);
+  out[4] = 1 - 2 * (x * x + z * z);
+  out[5] = 2 * (y * z - w * x);
+  out[6] = 2 * (x * z - w * y);
+  out[7] = 2 * (y * z + w * x);
+  out[8] = 1 - 2 * (x * x + y * y);
+  out[9] = p.tx;
+  out[10] = p.ty;
+  out[11] = p.tz;
+}
+
+// Rotation matrix -> unit quaternion with qw >= 0 (Shepperd's method: branch on
+// the largest of the trace and the diagonal entries).
+ba_pose pose12_to_quat(const double M[12]) {
+  const double m00 = M[0], m01 = M[1], m02 = M[2], m10 = M[3], m11 = M[4], m12 = M[5];
+  const double m20 = M[6], m21 = M[7], m22 = M[8];
+  const double tr = m00 + m11 + m22;
+  double q[4];
+  if (tr >= m00 && tr >= m11 && tr >= m22) {
+    const double s = std::sqrt(1.0 + tr) * 2;
+    q[0] = 0.25 * s; q[1] = (m21 - m12) / s; q[2] = (m02 - m20) / s; q[3] = (m10 - m01) / s;
+  } else if (m00 >= m11 && m00 >= m22) {
+    const double s = std::sqrt(1.0 + m00 - m11 - m22) * 2;
+    q[0] = (m21 - m12) / s; q[1] = 0.25 * s; q[2] = (m01 + m10) / s; q[3] = (m02 + m20) / s;
+  } else if (m11 >= m22) {
+    const double s = std::sqrt(1.0 + m11 - m00 - m22) * 2;
+    q[0] = (m02 - m20) / s; q[1] = (m01 + m10) / s; q[2] = 0.25 * s; q[3] = (m12 + m21) / s;
+  } else {
+    const double s = std::sqrt(1.0 + m22 - m00 - m11) * 2;
+    q[0] = (m10 - m01) / s; q[1] = (m02 + m20) / s; q[2] = (m12 + m21) / s; q[3] = 0.25 * s;
+  }
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double sg = q[0] < 0 ? -1.0 : 1.0;
+  ba_pose p;
+  p.qw = sg * q[0] / n; p.qx = sg * q[1] / n; p.qy = sg * q[2] / n; p.qz = sg * q[3] / n;
+  p.tx = M[9]; p.ty = M[10]; p.tz = M[11];
+  return p;
+}
+
+static bool finite_pose(const ba_pose &p) {
+  return std::isfinite(p.qw) && std::isfinite(p.qx) && std::isfinite(p.qy) && std::isfinite(p.qz) &&
+         std::isfinite(p.tx) && std::isfinite(p.ty) && std::isfinite(p.tz);
+}
+
+int check_pose(const ba_pose &p, const char *what, int64_t i) {
+  if (!finite_pose(p)) return fail(BA_EINVAL, "%s %lld: non-finite pose", what, (long long)i);
+  const double n = std::sqrt(p.qw * p.qw + p.qx * p.qx + p.qy * p.qy + p.qz * p.qz);
+  if (std::fabs(n - 1.0) > 1e-6)
+    return fail(BA_EINVAL, "%s %lld: quaternion norm %.9g differs from 1 by more than 1e-6", what,
+                (long long)i, n);
+  return BA_OK;
+}
+
+int check_options(const ba_options *o, bool pose_only) {
+  if (!o) return fail(BA_EINVAL, "options is NULL");
+  if (o->max_iters < 1 || o->max_iters > 100000) return fail(BA_EINVAL, "max_iters out of range");
+  if (!pose_only) {
+    if (o->pcg_max_iters < 1 || o->pcg_max_iters > 100000)
+      return fail(BA_EINVAL, "pcg_max_iters out of range");
+    if (!(o->pcg_rel_tol >= 0.0) || !std::isfinite(o->pcg_rel_tol))
+      return fail(BA_EINVAL, "pcg_rel_tol must be finite and >= 0");
+    if (!(o->lambda0 > 0.0) || !std::isfinite(o->lambda0)) return fail(BA_EINVAL, "lambda0 must be > 0");
+  }
+  if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
+  if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
+    return fail(BA_EINVAL, "unknown precision %d", o->precision);
+  if (o->reserved != 0) return fail(BA_EINVAL, "reserved option field must be 0");
+  return BA_OK;
+}
+
+// ------------------------------------------------------------------ symbolic analysis
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
+  if (!d) return fail(BA_EINVAL, "problem description is NULL");
+  if (int e = check_options(opt, false)) return e;
+  if (d->n_cams < 1) return fail(BA_EINVAL, "n_cams must be >= 1");
+  if (d->n_pts < 1) return fail(BA_EINVAL, "n_pts must be >= 1");
+  if (d->n_obs < 1) return fail(BA_EINVAL, "n_obs must be >= 1");
+  if (d->n_obs > (int64_t)INT32_MAX - 1) return fail(BA_EINVAL, "n_obs exceeds 2^31 - 2");
+  if (!d->K || !d->poses || !d->points_xyz || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
+  const int C = d->n_cams, P = d->n_pts;
+  const int64_t N = d->n_obs;
+  const int nK = d->K_per_cam ? C : 1;
+  for (int i = 0; i < nK; ++i) {
+    const ba_intrinsics &k = d->K[i];
+    if (!(std::isfinite(k.fx) && std::isfinite(k.fy) && std::isfinite(k.cx) && std::isfinite(k.cy)) ||
+        k.fx == 0.0 || k.fy == 0.0)
+      return fail(BA_EINVAL, "intrinsics %d invalid", i);
+  }
+  for (int i = 0; i < C; ++i)
+    if (int e = check_pose(d->poses[i], "camera", i)) return e;
+  for (int64_t i = 0; i < 3 * (int64_t)P; ++i)
+    if (!std::isfinite(d->points_xyz[i])) return fail(BA_EINVAL, "point %lld non-finite", (long long)(i / 3));
+  for (int64_t k = 0; k < N; ++k) {
+    const ba_obs &o = d->obs[k];
+    if (o.cam < 0 || o.cam >= C) return fail(BA_EINVAL, "observation %lld: camera %d out of range", (long long)k, o.cam);
+    if (o.pt < 0 || o.pt >= P) return fail(BA_EINVAL, "observation %lld: point %d out of range", (long long)k, o.pt);
+    if (!std::isfinite(o.u) || !std::isfinite(o.v)) return fail(BA_EINVAL, "observation %lld non-finite", (long long)k);
+  }
+  sy.C = C;
+  sy.P = P;
+  sy.N = (int32_t)N;
+  sy.free_idx.assign(C, -1);
+  sy.free_cam.clear();
+  for (int i = 0; i < C; ++i)
+    if (!(d->cam_fixed && d->cam_fixed[i])) {
+      sy.free_idx[i] = (int32_t)sy.free_cam.size();
+      sy.free_cam.push_back(i);
+    }
+  sy.Cf = (int32_t)sy.free_cam.size();
+  if (sy.Cf == 0) return fail(BA_EINVAL, "every camera is fixed");
+
+  // order by (point, camera): stable counting sort by camera, then by point
+  std::vector<int32_t> cnt(std::max(C, P) + 1);
+  std::vector<int32_t> by_cam(N), order(N);
+  std::fill(cnt.begin(), cnt.begin() + C + 1, 0);
+  for (int64_t k = 0; k < N; ++k) cnt[d->obs[k].cam + 1]++;
+  for (int i = 0; i < C; ++i) cnt[i + 1] += cnt[i];
+  for (int64_t k = 0; k < N; ++k) by_cam[cnt[d->obs[k].cam]++] = (int32_t)k;
+  sy.pt_start.assign(P + 1, 0);
+  for (int64_t k = 0; k < N; ++k) sy.pt_start[d->obs[k].pt + 1]++;
+  for (int j = 0; j < P; ++j) sy.pt_start[j + 1] += sy.pt_start[j];
+  std::vector<int32_t> fill(sy.pt_start.begin(), sy.pt_start.end() - 1);
+  for (int64_t t = 0; t < N; ++t) {
+    const int32_t k = by_cam[t];
+    order[fill[d->obs[k].pt]++] = k;
+  }
+  sy.obs_cam.resize(N);
+  sy.obs_pt.resize(N);
+  sy.obs_uv.resize(2 * N);
+  for (int64_t k = 0; k < N; ++k) {
+    const ba_obs &o = d->obs[order[k]];
+    sy.obs_cam[k] = o.cam;
+    sy.obs_pt[k] = o.pt;
+    sy.obs_uv[2 * k] = o.u;
+    sy.obs_uv[2 * k + 1] = o.v;
+  }
+  for (int j = 0; j < P; ++j)
+    for (int k = sy.pt_start[j] + 1; k < sy.pt_start[j + 1]; ++k)
+      if (sy.obs_cam[k] == sy.obs_cam[k - 1])
+        return fail(BA_EINVAL, "point %d observed twice by camera %d", j, sy.obs_cam[k]);
+
+  // observations of each free camera (positions in the point-major order)
+  const int Cf = sy.Cf;
+  sy.cam_obs_start.assign(Cf + 1, 0);
+  for (int64_t k = 0; k < N; ++k) {
+    const int a = sy.free_idx[sy.obs_cam[k]];
+    if (a >= 0) sy.cam_obs_start[a + 1]++;
+  }
+  for (int a = 0; a < Cf; ++a) sy.cam_obs_start[a + 1] += sy.cam_obs_start[a];
+  sy.cam_obs.resize(sy.cam_obs_start[Cf]);
+  {
+    std::vector<int32_t> f(sy.cam_obs_start.begin(), sy.cam_obs_start.end() - 1);
+    for (int64_t k = 0; k < N; ++k) {
+      const int a = sy.free_idx[sy.obs_cam[k]];
+      if (a >= 0) sy.cam_obs[f[a]++] = (int32_t)k;
+    }
+  }
+
+  // upper blocks of S row by row, with their observation-pair lists
+  std::vector<int32_t> up_rowptr(Cf + 1, 0), up_col;
+  std::vector<int64_t> pair_count;  // per upper block
+  std::vector<int32_t> rowcnt(Cf, 0), slot(Cf, -1);
+  std::vector<int32_t> touched;
+  sy.pairs.clear();
+  sy.up_pair_start.assign(1, 0);
+  for (int a = 0; a < Cf; ++a) {
+    touched.clear();
+    for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
+      const int k = sy.cam_obs[o];
+      const int j = sy.obs_pt[k];
+      for (int kb = k + 1; kb < sy.pt_start[j + 1]; ++kb) {
+        const int b = sy.free_idx[sy.obs_cam[kb]];
+        if (b < 0) continue;
+        if (rowcnt[b]++ == 0) touched.push_back(b);
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    const int base_blk = (int)up_col.size();
+    int64_t pbase = sy.pairs.size();
+    std::vector<int64_t> pfill(touched.size());
+    for (size_t t = 0; t < touched.size(); ++t) {
+      const int b = touched[t];
+      slot[b] = base_blk + (int)t;
+      up_col.push_back(b);
+      pfill[t] = pbase;
+      pbase += rowcnt[b];
+      if (pbase > (int64_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 observation pairs");
+      sy.up_pair_start.push_back((int32_t)pbase);
+    }
+    sy.pairs.resize(pbase);
+    for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
+      const int k = sy.cam_obs[o];
+      const int j = sy.obs_pt[k];
+      for (int kb = k + 1; kb < sy.pt_start[j + 1]; ++kb) {
+        const int b = sy.free_idx[sy.obs_cam[kb]];
+        if (b < 0) continue;
+        const int t = slot[b] - base_blk;
+        sy.pairs[pfill[t]++] = int2{k, kb};
+      }
+    }
+    for (int b : touched) {
+      rowcnt[b] = 0;
+      slot[b] = -1;
+    }
+    up_rowptr[a + 1] = (int32_t)up_col.size();
+  }
+  sy.n_up = (int32_t)up_col.size();
+
+  // full block rows of S: lower blocks (transposes), the diagonal, upper blocks
+  std::vector<int32_t> n_low(Cf, 0);
+  for (int u = 0; u < sy.n_up; ++u) n_low[up_col[u]]++;
+  sy.S_rowptr.assign(Cf + 1, 0);
+  for (int a = 0; a < Cf; ++a)
+    sy.S_rowptr[a + 1] = sy.S_rowptr[a] + n_low[a] + 1 + (up_rowptr[a + 1] - up_rowptr[a]);
+  sy.nnzb = sy.S_rowptr[Cf];
+  sy.S_col.assign(sy.nnzb, -1);
+  sy.diag_pos.resize(Cf);
+  sy.up_pos.resize(sy.n_up);
+  sy.up_tpos.resize(sy.n_up);
+  std::vector<int32_t> low_fill(Cf);
+  for (int a = 0; a < Cf; ++a) {
+    low_fill[a] = sy.S_rowptr[a];
+    sy.diag_pos[a] = sy.S_rowptr[a] + n_low[a];
+    sy.S_col[sy.diag_pos[a]] = a;
+  }
+  for (int a = 0; a < Cf; ++a)
+    for (int u = up_rowptr[a]; u < up_rowptr[a + 1]; ++u) {
+      const int b = up_col[u];
+      const int pos = sy.diag_pos[a] + 1 + (u - up_rowptr[a]);
+      sy.S_col[pos] = b;
+      sy.up_pos[u] = pos;
+      const int tpos = low_fill[b]++;  // rows a are visited in increasing order
+      sy.S_col[tpos] = a;
+      sy.up_tpos[u] = tpos;
+    }
+  return BA_OK;
+}
+
+// ------------------------------------------------------------------ device layout
+namespace {
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+}  // namespace
+
+size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offsets &o) {
+  const size_t T = compute_bytes(precision);
+  const size_t C = sy.C, Cf = sy.Cf, P = sy.P, N = sy.N;
+  const size_t npt = (P + kPtTile - 1) / kPtTile;
+  const size_t npcg = (Cf + kPcgRows - 1) / kPcgRows;
+  const size_t ncam = (C + kCamTile - 1) / kCamTile;
+  Layout L;
+  o.st = L.take(sizeof(LMState));
+  o.K = L.take(C * 4 * T);
+  o.free_idx = L.take(C * 4);
+  o.free_cam = L.take(Cf * 4);
+  o.obs_cam = L.take(N * 4);
+  o.obs_pt = L.take(N * 4);
+  o.obs_uv = L.take(N * 2 * T);
+  o.pt_start = L.take((P + 1) * 4);
+  o.cam_obs = L.take(sy.cam_obs.size() * 4 + 4);
+  o.cam_obs_start = L.take((Cf + 1) * 4);
+  o.up_pair_start = L.take((sy.n_up + 1) * 4);
+  o.pairs = L.take(sy.pairs.size() * sizeof(int2) + 8);
+  o.up_pos = L.take(sy.n_up * 4 + 4);
+  o.up_tpos = L.take(sy.n_up * 4 + 4);
+  o.diag_pos = L.take(Cf * 4);
+  o.S_rowptr = L.take((Cf + 1) * 4);
+  o.S_col = L.take(sy.nnzb * 4);
+  for (int b = 0; b < 2; ++b) o.pose[b] = L.take(C * 12 * 8);
+  for (int b = 0; b < 2; ++b) o.X[b] = L.take(P * 3 * 8);
+  o.pose_init = L.take(C * 12 * 8);
+  o.X_init = L.take(P * 3 * 8);
+  o.lin = L.take(N * lin_record_bytes(precision));
+  o.Y = L.take(N * 18 * T);
+  o.V = L.take(P * 6 * T);
+  o.gp = L.take(P * 3 * T);
+  o.Dp = L.take(P * 3 * T);
+  o.Vinv = L.take(P * 6 * T);
+  o.gc = L.take(Cf * 6 * T);
+  o.Dc = L.take(Cf * 6 * T);
+  o.brhs = L.take(Cf * 6 * T);
+  o.S = L.take((size_t)sy.nnzb * 36 * T);
+  o.Minv = L.take(Cf * 36 * 8);
+  for (int i = 0; i < 6; ++i) o.vec[i] = L.take(Cf * 6 * T);
+  o.part_lin_cost = L.take(npt * 8);
+  o.part_masked = L.take(npt * 4);
+  o.part_sq = L.take(npt * 8);
+  o.part_trial_cost = L.take(npt * 8);
+  o.part_dl_pt = L.take(npt * 8);
+  o.part_dl_cam = L.take(ncam * 8);
+  o.part_rz0 = L.take(Cf * 8);
+  o.part_bb = L.take(Cf * 8);
+  o.part_rz[0] = L.take(npcg * 8);
+  o.part_rz[1] = L.take(npcg * 8);
+  o.part_pq = L.take(npcg * 8);
+  o.part_rr = L.take(npcg * 8);
+  o.iter_cost = L.take((max_iters + 1) * 8);
+  o.iter_pcg = L.take(max_iters * 4);
+  o.total = L.off;
+  return L.off;
+}
+
+size_t DevProblem::bytes_for(const Symbolic &sy, int precision, int max_iters) {
+  Offsets o;
+  return plan(sy, precision, max_iters, o);
+}
+
+template <class T>
+static std::vector<T> cast_vec(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_options *opt,
+                     char *base, hipStream_t s) {
+  precision = opt->precision;
+  max_iters = opt->max_iters;
+  pcg_max = opt->pcg_max_iters;
+  lambda0 = opt->lambda0;
+  pcg_tol = opt->pcg_rel_tol;
+  huber = opt->huber_delta;
+  C = sy.C;
+  Cf = sy.Cf;
+  P = sy.P;
+  N = sy.N;
+  plan(sy, precision, max_iters, off);
+  dev = base;
+  auto ptr = [&](size_t o) { return (void *)(base + o); };
+  ProbDev &pd = view;
+  std::memset(&pd, 0, sizeof(pd));
+  pd.C = C;
+  pd.Cf = Cf;
+  pd.P = P;
+  pd.N = N;
+  pd.n_up = sy.n_up;
+  pd.nnzb = sy.nnzb;
+  pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
+  pd.n_pcg_tiles = (Cf + kPcgRows - 1) / kPcgRows;
+  pd.n_cam_tiles = (C + kCamTile - 1) / kCamTile;
+  pd.K = ptr(off.K);
+  pd.free_idx = (const int32_t *)ptr(off.free_idx);
+  pd.free_cam = (const int32_t *)ptr(off.free_cam);
+  pd.obs_cam = (const int32_t *)ptr(off.obs_cam);
+  pd.obs_pt = (const int32_t *)ptr(off.obs_pt);
+  pd.obs_uv = ptr(off.obs_uv);
+  pd.pt_start = (const int32_t *)ptr(off.pt_start);
+  pd.cam_obs = (const int32_t *)ptr(off.cam_obs);
+  pd.cam_obs_start = (const int32_t *)ptr(off.cam_obs_start);
+  pd.up_pair_start = (const int32_t *)ptr(off.up_pair_start);
+  pd.pairs = (const int2 *)ptr(off.pairs);
+  pd.up_pos = (const int32_t *)ptr(off.up_pos);
+  pd.up_tpos = (const int32_t *)ptr(off.up_tpos);
+  pd.diag_pos = (const int32_t *)ptr(off.diag_pos);
+  pd.S_rowptr = (const int32_t *)ptr(off.S_rowptr);
+  pd.S_col = (const int32_t *)ptr(off.S_col);
+  for (int b = 0; b < 2; ++b) {
+    pd.pose[b] = (double *)ptr(off.pose[b]);
+    pd.X[b] = (double *)ptr(off.X[b]);
+  }
+  pd.lin = ptr(off.lin);
+  pd.Y = ptr(off.Y);
+  pd.V = ptr(off.V);
+  pd.gp = ptr(off.gp);
+  pd.Dp = ptr(off.Dp);
+  pd.Vinv = ptr(off.Vinv);
+  pd.gc = ptr(off.gc);
+  pd.Dc = ptr(off.Dc);
+  pd.brhs = ptr(off.brhs);
+  pd.S = ptr(off.S);
+  pd.Minv = (double *)ptr(off.Minv);
+  pd.x = ptr(off.vec[0]);
+  pd.r = ptr(off.vec[1]);
+  pd.z = ptr(off.vec[2]);
+  pd.p0 = ptr(off.vec[3]);
+  pd.p1 = ptr(off.vec[4]);
+  pd.q = ptr(off.vec[5]);
+  pd.part_lin_cost = (double *)ptr(off.part_lin_cost);
+  pd.part_masked = (int32_t *)ptr(off.part_masked);
+  pd.part_sq = (double *)ptr(off.part_sq);
+  pd.part_trial_cost = (double *)ptr(off.part_trial_cost);
+  pd.part_dl_pt = (double *)ptr(off.part_dl_pt);
+  pd.part_dl_cam = (double *)ptr(off.part_dl_cam);
+  pd.part_rz0 = (double *)ptr(off.part_rz0);
+  pd.part_bb = (double *)ptr(off.part_bb);
+  pd.part_rz[0] = (double *)ptr(off.part_rz[0]);
+  pd.part_rz[1] = (double *)ptr(off.part_rz[1]);
+  pd.part_pq = (double *)ptr(off.part_pq);
+  pd.part_rr = (double *)ptr(off.part_rr);
+  pd.st = (LMState *)ptr(off.st);
+  pd.iter_cost = (double *)ptr(off.iter_cost);
+  pd.iter_pcg = (int32_t *)ptr(off.iter_pcg);
+
+  // host staging of every input in its device form
+  std::vector<double> Kd(4 * (size_t)C);
+  for (int i = 0; i < C; ++i) {
+    const ba_intrinsics &k = d->K[d->K_per_cam ? i : 0];
+    Kd[4 * i] = k.fx;
+    Kd[4 * i + 1] = k.fy;
+    Kd[4 * i + 2] = k.cx;
+    Kd[4 * i + 3] = k.cy;
+  }
+  std::vector<double> poses(12 * (size_t)C);
+  for (int i = 0; i < C; ++i) quat_to_pose12(d->poses[i], &poses[12 * (size_t)i]);
+  auto up = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  if (precision == BA_PREC_F64) {
+    chk(up(off.K, Kd.data(), Kd.size() * 8));
+    chk(up(off.obs_uv, sy.obs_uv.data(), sy.obs_uv.size() * 8));
+  } else {
+    staging_f.push_back(cast_vec<float>(Kd));
+    chk(up(off.K, staging_f.back().data(), Kd.size() * 4));
+    staging_f.push_back(cast_vec<float>(sy.obs_uv));
+    chk(up(off.obs_uv, staging_f.back().data(), sy.obs_uv.size() * 4));
+  }
+  chk(up(off.free_idx, sy.free_idx.data(), sy.free_idx.size() * 4));
+  chk(up(off.free_cam, sy.free_cam.data(), sy.free_cam.size() * 4));
+  chk(up(off.obs_cam, sy.obs_cam.data(), sy.obs_cam.size() * 4));
+  chk(up(off.obs_pt, sy.obs_pt.data(), sy.obs_pt.size() * 4));
+  chk(up(off.pt_start, sy.pt_start.data(), sy.pt_start.size() * 4));
+  chk(up(off.cam_obs, sy.cam_obs.data(), sy.cam_obs.size() * 4));
+  chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
+  chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
+  chk(up(off.pairs, sy.pairs.data(), sy.pairs.size() * sizeof(int2)));
+  chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
+  chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));
+  chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));
+  chk(up(off.S_rowptr, sy.S_rowptr.data(), sy.S_rowptr.size() * 4));
+  chk(up(off.S_col, sy.S_col.data(), sy.S_col.size() * 4));
+  staging_d.push_back(std::move(poses));
+  chk(up(off.pose[0], staging_d.back().data(), 12 * (size_t)C * 8));
+  chk(up(off.X[0], d->points_xyz, 3 * (size_t)P * 8));
+  chk(up(off.pose_init, staging_d.back().data(), 12 * (size_t)C * 8));
+  chk(up(off.X_init, d->points_xyz, 3 * (size_t)P * 8));
+  host_state = LMState{};
+  host_state.cur = 0;
+  if (e != hipSuccess) return hip_fail(e, "upload");
+  return BA_OK;
+}
+
+LMState DevProblem::fresh_state() const {
+  LMState st{};
+  st.lambda = lambda0;
+  st.lambda0 = lambda0;
+  st.nu = 2.0;
+  st.pcg_tol = pcg_tol;
+  st.huber_delta = huber;
+  st.iter = 0;
+  st.max_iters = max_iters;
+  st.relin = 1;
+  st.status = 0;
+  st.accepted = 0;
+  st.cur = host_state.cur;
+  st.pcg_max = pcg_max;
+  st.init_done = 0;
+  return st;
+}
+
+// ------------------------------------------------------------------ batches
+void Batch::clear() {
+  probs.clear();
+  tags.clear();
+  for (auto &v : tiles) v.clear();
+}
+
+void Batch::add(const ProbDev &pd, int slot_tag) {
+  const int pi = (int)probs.size();
+  probs.push_back(pd);
+  tags.push_back(slot_tag);
+  for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[0].push_back(Tile{pi, t});
+  for (int a = 0; a < pd.Cf; ++a) tiles[1].push_back(Tile{pi, a});
+  for (int t = 0; t < (pd.n_up + kOffWaves - 1) / kOffWaves; ++t) tiles[2].push_back(Tile{pi, t});
+  for (int t = 0; t < pd.n_pcg_tiles; ++t) tiles[3].push_back(Tile{pi, t});
+  for (int t = 0; t < pd.n_cam_tiles; ++t) tiles[4].push_back(Tile{pi, t});
+  tiles[5].push_back(Tile{pi, 0});
+}
+
+int Batch::upload(hipStream_t s) {
+  size_t need = probs.size() * sizeof(ProbDev);
+  size_t offs[6];
+  for (int i = 0; i < 6; ++i) {
+    need = (need + 255) & ~size_t(255);
+    offs[i] = need;
+    need += tiles[i].size() * sizeof(Tile);
+  }
+  if (need > cap) {
+    if (dev) (void)hipFree(dev);
+    dev = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc(&dev, need * 2);
+    if (e != hipSuccess) return hip_fail(e, "batch table allocation");
+    cap = need * 2;
+  }
+  host.assign(need, 0);
+  std::memcpy(host.data(), probs.data(), probs.size() * sizeof(ProbDev));
+  for (int i = 0; i < 6; ++i)
+    std::memcpy(host.data() + offs[i], tiles[i].data(), tiles[i].size() * sizeof(Tile));
+  hipError_t e = hipMemcpyAsync(dev, host.data(), need, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "batch table upload");
+  char *b = (char *)dev;
+  plan.probs = (const ProbDev *)b;
+  const Tile **dst[6] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam, &plan.ctl};
+  int32_t *cnt[6] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam, &plan.n_ctl};
+  for (int i = 0; i < 6; ++i) {
+    *dst[i] = (const Tile *)(b + offs[i]);
+    *cnt[i] = (int32_t)tiles[i].size();
+  }
+  return BA_OK;
+}
+
+Batch::~Batch() {
+  if (dev) (void)hipFree(dev);
+}
+
+// ------------------------------------------------------------------ timing
+void EventTimer::begin(int id, hipStream_t s) {
+  active = ((mask >> id) & 1u) != 0;
+  if (!active) return;
+  if (used == pool.size()) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    pool.push_back({a, b});
+  }
+  (void)hipEventRecord(pool[used].first, s);
+  ids.push_back(id);
+}
+void EventTimer::end(int, hipStream_t s) {
+  (void)hipEventRecord(pool[used].second, s);
+  ++used;
+}
+void EventTimer::reset() {
+  used = 0;
+  ids.clear();
+}
+void EventTimer::collect(double ms[K_NUM_KERNELS], int32_t launches[K_NUM_KERNELS]) {
+  for (int i = 0; i < K_NUM_KERNELS; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (size_t i = 0; i < used; ++i) {
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, pool[i].first, pool[i].second);
+    ms[ids[i]] += t;
+    launches[ids[i]] += 1;
+  }
+}
+EventTimer::~EventTimer() {
+  for (auto &p : pool) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+}
+
+}  // namespace bax
+
+// ====================================================================== C-ABI
+using namespace bax;
+
+struct ba_problem {
+  Symbolic sy;
+  DevProblem dp;
+  Batch batch;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void *mem = nullptr;
+  size_t bytes = 0;
+  double setup_ms = 0.0;
+  int64_t n_pairs = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool pending = false;
+  bool solved = false;
+  bool profiling = false;
+  EventTimer timer;  // times the kernels selected by timer.mask
+  double kernel_ms[K_NUM_KERNELS] = {};
+  int32_t kernel_launches[K_NUM_KERNELS] = {};
+  double solve_ms = 0.0;
+};
+
+extern "C" {
+
+const char *ba_version(void) { return "ba_mi355x 0.1 (gfx950)"; }
+const char *ba_last_error(void) { return g_last_error.c_str(); }
+
+void ba_default_options(ba_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iters = 10;
+  o->pcg_max_iters = 50;
+  o->pcg_rel_tol = 1e-6;
+  o->lambda0 = 1e-4;
+  o->huber_delta = 0.0;
+  o->precision = BA_PREC_F32;
+}
+
+int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream, ba_problem **out) {
+  if (!out) return fail(BA_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<ba_problem> p(new ba_problem());
+  if (int e = analyse(d, opt, p->sy)) return e;
+  p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
+  if (hip_stream) {
+    p->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreate(&p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    p->own_stream = true;
+  }
+  hipError_t e = hipMalloc(&p->mem, p->bytes);
+  if (e != hipSuccess) {
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+    return hip_fail(e, "problem allocation");
+  }
+  int rc = p->dp.init(p->sy, d, opt, (char *)p->mem, p->stream);
+  if (rc == BA_OK) {
+    p->batch.add(p->dp.view, 0);
+    rc = p->batch.upload(p->stream);
+  }
+  if (rc == BA_OK) {
+    hipError_t e2 = hipEventCreate(&p->ev0);
+    if (e2 == hipSuccess) e2 = hipEventCreate(&p->ev1);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(p->stream);
+    if (e2 != hipSuccess) rc = hip_fail(e2, "setup");
+  }
+  if (rc != BA_OK) {
+    (void)hipFree(p->mem);
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+    return rc;
+  }
+  // the host copies needed later are the sizes only; drop the big arrays
+  p->n_pairs = (int64_t)p->sy.pairs.size();
+  p->sy.pairs.clear();
+  p->sy.pairs.shrink_to_fit();
+  p->dp.staging_f.clear();
+  p->dp.staging_d.clear();
+  p->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p.release();
+  return BA_OK;
+}
+
+int ba_solve_async(ba_problem *p) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (p->pending) return fail(BA_ESTATE, "a solve is already in flight");
+  p->dp.pending_state = p->dp.fresh_state();  // source of the async copy: must outlive it
+  hipError_t e = hipMemcpyAsync(p->dp.view.st, &p->dp.pending_state, sizeof(LMState),
+                                hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "state upload");
+  KernelTimer *tm = p->profiling ? &p->timer : nullptr;
+  p->timer.reset();
+  (void)hipEventRecord(p->ev0, p->stream);
+  for (int it = 0; it < p->dp.max_iters; ++it) {
+    e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  (void)hipEventRecord(p->ev1, p->stream);
+  e = launch_eval(p->dp.precision, p->batch.plan, p->stream, tm);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  p->pending = true;
+  return BA_OK;
+}
+
+int ba_wait(ba_problem *p) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (!p->pending) return BA_OK;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  p->pending = false;
+  if (e != hipSuccess) return hip_fail(e, "solve");
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
+  p->solve_ms = ms;
+  e = hipMemcpy(&p->dp.host_state, p->dp.view.st, sizeof(LMState), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "state download");
+  if (p->profiling) p->timer.collect(p->kernel_ms, p->kernel_launches);
+  p->solved = true;
+  return BA_OK;
+}
+
+int ba_solve(ba_problem *p) {
+  if (int e = ba_solve_async(p)) return e;
+  return ba_wait(p);
+}
+
+int ba_get_result(const ba_problem *pc, ba_pose *poses_out, double *points_out, ba_report *rep) {
+  ba_problem *p = const_cast<ba_problem *>(pc);
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (p->pending)
+    if (int e = ba_wait(p)) return e;
+  return p->dp.read_result(p->stream, poses_out, points_out, rep, p->solved, p->solve_ms, p->setup_ms);
+}
+
+int ba_reset(ba_problem *p) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
+  DevProblem &dp = p->dp;
+  hipError_t e = hipMemcpyAsync(dp.view.pose[0], dp.dev + dp.off.pose_init, 12 * (size_t)dp.C * 8,
+                                hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dp.view.X[0], dp.dev + dp.off.X_init, 3 * (size_t)dp.P * 8,
+                       hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "reset");
+  dp.host_state = LMState{};
+  dp.host_state.cur = 0;
+  p->solved = false;
+  return BA_OK;
+}
+
+int ba_get_info(const ba_problem *p, ba_problem_info *out) {
+  if (!p || !out) return fail(BA_EINVAL, "NULL argument");
+  out->n_cams = p->sy.C;
+  out->n_free_cams = p->sy.Cf;
+  out->n_pts = p->sy.P;
+  out->n_obs = p->sy.N;
+  out->n_pairs = p->n_pairs;
+  out->n_up_blocks = p->sy.n_up;
+  out->nnzb = p->sy.nnzb;
+  out->n_free_obs = (int32_t)p->sy.cam_obs.size();
+  out->precision = p->dp.precision;
+  return BA_OK;
+}
+
+int64_t ba_problem_bytes(const ba_problem *p) { return p ? (int64_t)p->bytes : 0; }
+
+void ba_destroy(ba_problem *p) {
+  if (!p) return;
+  if (p->pending) (void)hipStreamSynchronize(p->stream);
+  if (p->mem) (void)hipFree(p->mem);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->own_stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+int ba_set_profiling(ba_problem *p, int32_t enable) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  p->profiling = enable != 0;
+  p->timer.mask = (uint32_t)enable;
+  return BA_OK;
+}
+
+int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names, double *ms,
+                        int32_t *launches, int32_t *n_out) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  const int n = std::min<int>(max_kernels, K_NUM_KERNELS);
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = kKernelNames[i];
+    if (ms) ms[i] = p->kernel_ms[i];
+    if (launches) launches[i] = p->kernel_launches[i];
+  }
+  if (n_out) *n_out = n;
+  return BA_OK;
+}
+
+}  // extern "C"
+
+namespace bax {
+
+int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
+                            bool solved, double solve_ms, double setup_ms) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  const int cur = host_state.cur;
+  if (poses_out) {
+    std::vector<double> buf(12 * (size_t)C);
+    e = hipMemcpy(buf.data(), view.pose[cur], buf.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "pose download");
+    for (int i = 0; i < C; ++i) poses_out[i] = pose12_to_quat(&buf[12 * (size_t)i]);
+  }
+  if (points_out) {
+    e = hipMemcpy(points_out, view.X[cur], 3 * (size_t)P * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "point download");
+  }
+  if (rep) {
+    double *ic = rep->iter_cost;
+    int32_t *pi = rep->pcg_iters;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->iter_cost = ic;
+    rep->pcg_iters = pi;
+    rep->setup_ms = setup_ms;
+    if (solved) {
+      const LMState &st = host_state;
+      rep->iters = st.iter;
+      rep->accepted = st.accepted;
+      rep->status = st.status;
+      rep->cost0 = st.cost0;
+      rep->cost = st.cost;
+      rep->lambda = st.lambda;
+      rep->solve_ms = solve_ms;
+      const int npt = view.n_pt_tiles;
+      std::vector<double> sq(npt);
+      std::vector<int32_t> nm(npt);
+      e = hipMemcpy(sq.data(), view.part_sq, npt * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(nm.data(), view.part_masked, npt * 4, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "report download");
+      double tot = 0.0;
+      int64_t masked = 0;
+      for (int i = 0; i < npt; ++i) {
+        tot += sq[i];
+        masked += nm[i];
+      }
+      rep->n_masked = (int32_t)masked;
+      rep->rms_px = (N - masked) > 0 ? std::sqrt(tot / (double)(N - masked)) : 0.0;
+      if (ic) {
+        e = hipMemcpy(ic, view.iter_cost, (st.iter + 1) * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "report download");
+      }
+      if (pi && st.iter > 0) {
+        e = hipMemcpy(pi, view.iter_pcg, st.iter * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "report download");
+      }
+    }
+  }
+  return BA_OK;
+}
+
+}  // namespace bax

@@ -1,0 +1,146 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+//
+// One problem lives in one device allocation.  Kernels never see a problem
+// directly: they receive a table of ProbDev descriptors and a list of tiles
+// (problem index, tile index), so one launch advances any mix of problems by
+// the same stage of the Levenberg-Marquardt iteration.  A single solve is the
+// batch of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bax {
+
+constexpr int kPtTile = 256;     // points per point-major tile (one workgroup)
+constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile
+constexpr int kPcgRows = 16;     // reduced-camera-system rows per PCG tile
+constexpr int kCamTile = 256;    // cameras per camera-update tile
+constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
+constexpr int kPoseThreads = 256;
+
+constexpr double kLambdaMin = 1e-12;
+constexpr double kLambdaMax = 1e16;
+constexpr double kDMin = 1e-6;
+constexpr double kDMax = 1e32;
+constexpr double kAcceptRho = 1e-3;
+constexpr double kZMin = 1e-6;
+
+struct Tile {
+  int32_t prob;
+  int32_t idx;
+};
+
+// Per-problem Levenberg-Marquardt scalars, resident on the device.
+struct LMState {
+  double lambda, nu;
+  double cost;        // cost of the accepted state
+  double cost0;
+  double trial_cost, dL, rho;
+  double lambda0, pcg_tol, huber_delta;
+  double pcg_bb, pcg_rz0;  // ||b||^2 and r0.z0 of the current linear solve
+  double sq_sum;           // sum ||r||^2 at the final state (evaluation kernel)
+  int32_t iter, max_iters, relin, status;
+  int32_t accepted, cur, pcg_done, pcg_iters;
+  int32_t pcg_max, init_done, n_masked, pad0;
+};
+
+// Device view of one problem.  Arrays typed T hold the compute type of the
+// precision mode (double or float); S is the Jacobian storage type.
+struct ProbDev {
+  int32_t C, Cf, P, N;
+  int32_t n_up;          // upper off-diagonal blocks of S
+  int32_t nnzb;          // blocks of S stored (both triangles + diagonal)
+  int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
+  int32_t pad;
+  // static structure
+  const void *K;                  // [C][4] T: fx, fy, cx, cy
+  const int32_t *free_idx;        // [C] free-camera index or -1
+  const int32_t *free_cam;        // [Cf] camera of each free index
+  const int32_t *obs_cam;         // [N] observations in (point, camera) order
+  const int32_t *obs_pt;          // [N]
+  const void *obs_uv;             // [N][2] T
+  const int32_t *pt_start;        // [P + 1]
+  const int32_t *cam_obs;         // observation positions of free cameras, grouped by camera
+  const int32_t *cam_obs_start;   // [Cf + 1]
+  const int32_t *up_pair_start;   // [n_up + 1]
+  const int2 *pairs;              // (k_a, k_b): observations of one point in cameras a < b
+  const int32_t *up_pos;          // [n_up] block (a, b) in S
+  const int32_t *up_tpos;         // [n_up] block (b, a) in S
+  const int32_t *diag_pos;        // [Cf]
+  const int32_t *S_rowptr;        // [Cf + 1]
+  const int32_t *S_col;           // [nnzb]
+  // state, double-buffered (LMState::cur selects the accepted copy)
+  double *pose[2];                // [C][12]: R row-major, then t
+  double *X[2];                   // [P][3]
+  // linearisation and Schur complement
+  void *lin;                      // [N] LinRec<T, S>
+  void *Y;                        // [N][18] T: W_k V*_j^-1
+  void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
+  void *gc, *Dc, *brhs;           // [Cf][6] T
+  void *S;                        // [nnzb][36] T
+  double *Minv;                   // [Cf][36]
+  void *x, *r, *z, *p0, *p1, *q;  // [6 Cf] T
+  // reductions (one partial per tile, summed in a fixed order)
+  double *part_lin_cost;          // [n_pt_tiles]
+  int32_t *part_masked;           // [n_pt_tiles]
+  double *part_sq;                // [n_pt_tiles]
+  double *part_trial_cost;        // [n_pt_tiles]
+  double *part_dl_pt;             // [n_pt_tiles]
+  double *part_dl_cam;            // [n_cam_tiles]
+  double *part_rz0;               // [Cf]
+  double *part_bb;                // [Cf]
+  double *part_rz[2];             // [n_pcg_tiles]
+  double *part_pq;                // [n_pcg_tiles]
+  double *part_rr;                // [n_pcg_tiles]
+  LMState *st;
+  double *iter_cost;              // [max_iters + 1]
+  int32_t *iter_pcg;              // [max_iters]
+};
+
+// Tile lists of one batch (device pointers) and their lengths.
+struct BatchPlan {
+  const ProbDev *probs;
+  const Tile *pt, *diag, *off, *pcg, *cam, *ctl;
+  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl;
+};
+
+// One localization request on the device.
+struct PoseDev {
+  double K[4];
+  double pose[12];     // in: initial pose; out: refined pose
+  int64_t off;         // first correspondence
+  int32_t n;
+  int32_t status;
+  double cost;
+};
+
+// Kernel timing hook: the host records events around launches when set.
+struct KernelTimer {
+  virtual void begin(int kernel_id, hipStream_t s) = 0;
+  virtual void end(int kernel_id, hipStream_t s) = 0;
+  virtual ~KernelTimer() {}
+};
+
+enum KernelId {
+  K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
+  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_NUM_KERNELS
+};
+extern const char *const kKernelNames[K_NUM_KERNELS];
+
+// Size in bytes of one stored linearisation record for a precision mode.
+size_t lin_record_bytes(int precision);
+// Size of the compute type (8 or 4).
+size_t compute_bytes(int precision);
+
+// Launch one Levenberg-Marquardt iteration for every problem of the plan.
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
+                               KernelTimer *timer);
+// Evaluate sum ||r||^2 and the masked count at the accepted state.
+hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
+// Pose-only Gauss-Newton, one workgroup per request.
+hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
+                          double huber_delta, hipStream_t s, KernelTimer *timer);
+
+}  // namespace bax

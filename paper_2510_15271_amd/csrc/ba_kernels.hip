@@ -1,0 +1,1269 @@
+// gfx950 kernels of the Levenberg-Marquardt bundle-adjustment iteration.
+//
+// Math (paper Sec. 4.3): residual r = pi(K (R X + t)) - z of one observation,
+// cost 1/2 sum rho(||r||^2) with Huber rho on the squared norm, left SE(3)
+// increments.  Per LM iteration, for every problem of a batch:
+//
+//   linearize    obs-parallel, point tiles: r, Huber weight, sqrt(w)-scaled
+//                J_c (2x6) and J_p (2x3) stored per observation; V_j, g_p,j
+//                and the cost reduced per point / per tile without atomics.
+//   point_prep   V*_j = V_j + lambda D_j inverted (FP64), Y_k = W_k V*_j^-1.
+//   schur_diag   one workgroup per free camera a: U_a, g_c,a, the diagonal
+//                block S_aa = U*_a - sum Y W^T, b_a = -g_c,a + sum Y g_p, the
+//                FP64 6x6 inverse of S_aa (block-Jacobi) and the PCG start.
+//   schur_off    one wavefront per upper block S_ab: sum over the points seen
+//                by a and b of -Y_aj W_bj^T from precomputed pair lists, one
+//                wave reduction, written to S_ab and its transpose.
+//   pcg_spmv /   block-sparse S p with FP64 dot products; direction update
+//   pcg_update   folded into the product; per-tile partial sums reduced in a
+//                fixed order by every consumer, so no grid barrier and no
+//                float atomics are needed.
+//   cam_update   T <- Exp(dc) T, camera part of the predicted decrease.
+//   point_trial  dp_j = V*_j^-1 (-g_p,j - sum W^T dc), X <- X + dp, trial cost.
+//   lm_control   gain ratio, accept/reject, Nielsen damping update.
+//
+// Every reduction is deterministic: a fixed assignment of work to lanes and a
+// fixed summation order, so a problem's result is the same whichever other
+// problems share its launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ba_internal.h"
+
+namespace bax {
+
+const char *const kKernelNames[K_NUM_KERNELS] = {
+    "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn"};
+
+// ------------------------------------------------------------------ storage codecs
+// Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
+// that entries up to 1e6 stay finite; BF16 has the FP32 exponent range.
+struct bf16s {
+  uint16_t b;
+};
+
+template <class S>
+struct Codec;
+template <>
+struct Codec<double> {
+  __device__ static double enc(double v) { return v; }
+  __device__ static double dec(double v) { return v; }
+};
+template <>
+struct Codec<float> {
+  __device__ static float enc(float v) { return v; }
+  __device__ static float dec(float v) { return v; }
+};
+template <>
+struct Codec<_Float16> {
+  __device__ static _Float16 enc(float v) { return (_Float16)(v * 0.0625f); }
+  __device__ static float dec(_Float16 h) { return (float)h * 16.0f; }
+};
+template <>
+struct Codec<bf16s> {
+  __device__ static bf16s enc(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16s{(uint16_t)(u >> 16)};  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return bf16s{(uint16_t)(u >> 16)};
+  }
+  __device__ static float dec(bf16s h) { return __uint_as_float((uint32_t)h.b << 16); }
+};
+
+template <class T, class S>
+struct LinRec {
+  S j[18];  // sqrt(w) J_c row-major (2x6), then sqrt(w) J_p (2x3)
+  T e[2];   // sqrt(w) r
+};
+
+size_t lin_record_bytes(int precision) {
+  switch (precision) {
+    case 0: return sizeof(LinRec<double, double>);
+    case 1: return sizeof(LinRec<float, float>);
+    case 2: return sizeof(LinRec<float, _Float16>);
+    default: return sizeof(LinRec<float, bf16s>);
+  }
+}
+size_t compute_bytes(int precision) { return precision == 0 ? 8 : 4; }
+
+// ------------------------------------------------------------------ small helpers
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of one value per thread over a 256-thread block, fixed order.
+template <class T>
+__device__ inline T block_sum256(T v, T *scratch4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) scratch4[w] = v;
+  __syncthreads();
+  T s = scratch4[0] + scratch4[1] + scratch4[2] + scratch4[3];
+  __syncthreads();
+  return s;
+}
+
+// Sum of n doubles by a 256-thread block in a fixed order (result in every thread).
+__device__ inline double block_sum_array(const double *a, int n, double *scratch4) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += a[i];
+  return block_sum256(v, scratch4);
+}
+
+template <class T>
+__device__ inline T huber_w(T s, T delta) {
+  if (delta <= T(0) || s <= delta * delta) return T(1);
+  return delta / sqrt(s);
+}
+template <class T>
+__device__ inline T huber_rho(T s, T delta) {
+  if (delta <= T(0) || s <= delta * delta) return s;
+  return T(2) * delta * sqrt(s) - delta * delta;
+}
+
+// World -> camera transform in FP64 from the FP64 state.
+__device__ inline void transform(const double *pose, const double *X, double &x, double &y,
+                                 double &z) {
+  x = pose[0] * X[0] + pose[1] * X[1] + pose[2] * X[2] + pose[9];
+  y = pose[3] * X[0] + pose[4] * X[1] + pose[5] * X[2] + pose[10];
+  z = pose[6] * X[0] + pose[7] * X[1] + pose[8] * X[2] + pose[11];
+}
+
+// Residual of one observation in compute type T.  Returns false when the
+// point is at or behind the depth threshold (observation masked).
+template <class T>
+__device__ inline bool residual(const T *K, T x, T y, T z, T uo, T vo, T &r0, T &r1) {
+  if (!(z > T(kZMin))) {
+    r0 = r1 = T(0);
+    return false;
+  }
+  const T iz = T(1) / z;
+  r0 = K[0] * x * iz + K[2] - uo;
+  r1 = K[1] * y * iz + K[3] - vo;
+  return true;
+}
+
+// Jacobians of the residual for a left increment (rho, phi) of the pose and an
+// additive point increment: J_pi = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]],
+// J_c = J_pi [I | -[P]x], J_p = J_pi R.
+template <class T>
+__device__ inline void jacobians(const T *K, const double *pose, T x, T y, T z, T Jc[12],
+                                 T Jp[6]) {
+  const T iz = T(1) / z;
+  const T a = K[0] * iz, b = -K[0] * x * iz * iz;
+  const T c = K[1] * iz, d = -K[1] * y * iz * iz;
+  Jc[0] = a;     Jc[1] = T(0);  Jc[2] = b;
+  Jc[3] = b * y; Jc[4] = a * z - b * x; Jc[5] = -a * y;
+  Jc[6] = T(0);  Jc[7] = c;     Jc[8] = d;
+  Jc[9] = -c * z + d * y; Jc[10] = -d * x; Jc[11] = c * x;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Jp[m] = a * T(pose[m]) + b * T(pose[6 + m]);
+    Jp[3 + m] = c * T(pose[3 + m]) + d * T(pose[6 + m]);
+  }
+}
+
+// se(3) exponential: R = I + A K + B K^2, t = (I + B K + C K^2) rho, K = [phi]x,
+// A = sin th / th, B = (1 - cos th) / th^2 = 2 sin^2(th/2) / th^2,
+// C = (th - sin th) / th^3, series in th^2 below 1e-4.
+__device__ inline void se3_exp(const double xi[6], double R[9], double t[3]) {
+  const double p0 = xi[3], p1 = xi[4], p2 = xi[5];
+  const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
+  double A, B, Cc;
+  if (th2 < 1e-8) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    const double th = sqrt(th2);
+    const double s = sin(th);
+    const double h = sin(0.5 * th) / (0.5 * th);
+    A = s / th;
+    B = 0.5 * h * h;
+    Cc = (th - s) / (th2 * th);
+  }
+  const double K[9] = {0, -p2, p1, p2, 0, -p0, -p1, p0, 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  double Vm[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    R[i] = I + A * K[i] + B * K2[i];
+    Vm[i] = I + B * K[i] + Cc * K2[i];
+  }
+  for (int i = 0; i < 3; ++i) t[i] = Vm[3 * i] * xi[0] + Vm[3 * i + 1] * xi[1] + Vm[3 * i + 2] * xi[2];
+}
+
+// Inverse of a symmetric 3x3 (upper triangle u = [00 01 02 11 12 22]) in FP64.
+__device__ inline void inv_sym3(const double u[6], double o[6]) {
+  const double a = u[0], b = u[1], c = u[2], d = u[3], e = u[4], f = u[5];
+  const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+  const double c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+  const double det = a * c00 + b * c01 + c * c02;
+  const double id = 1.0 / det;
+  o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
+  o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
+}
+
+// Inverse of a symmetric positive definite 6x6 in FP64 by Cholesky (A = L L^T,
+// A^-1 = L^-T L^-1).  Falls back to the inverse diagonal if A is not
+// numerically positive definite.
+__device__ inline void inv_spd6(const double A[36], double out[36]) {
+  double L[36];
+  for (int i = 0; i < 36; ++i) L[i] = 0.0;
+  bool ok = true;
+  for (int j = 0; j < 6 && ok; ++j) {
+    double s = A[6 * j + j];
+    for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+    if (!(s > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double ljj = sqrt(s);
+    L[6 * j + j] = ljj;
+    for (int i = j + 1; i < 6; ++i) {
+      double t = A[6 * i + j];
+      for (int k = 0; k < j; ++k) t -= L[6 * i + k] * L[6 * j + k];
+      L[6 * i + j] = t / ljj;
+    }
+  }
+  if (!ok) {
+    for (int i = 0; i < 36; ++i) out[i] = 0.0;
+    for (int i = 0; i < 6; ++i) out[7 * i] = A[7 * i] > 0.0 ? 1.0 / A[7 * i] : 0.0;
+    return;
+  }
+  double Li[36];  // L^-1, lower triangular
+  for (int i = 0; i < 36; ++i) Li[i] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    Li[6 * j + j] = 1.0 / L[6 * j + j];
+    for (int i = j + 1; i < 6; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s -= L[6 * i + k] * Li[6 * k + j];
+      Li[6 * i + j] = s / L[6 * i + i];
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double s = 0.0;
+      for (int k = (i > j ? i : j); k < 6; ++k) s += Li[6 * k + i] * Li[6 * k + j];
+      out[6 * i + j] = s;
+    }
+}
+
+__device__ inline bool lm_active(const LMState *st) { return st->iter < st->max_iters; }
+
+// ------------------------------------------------------------------ linearize
+// Point tile: points [j0, j1) and their observations [k0, k1) (contiguous, since
+// observations are ordered by point).  Observations are processed 256 at a
+// time, one per thread; per-point sums are formed by the first thread of each
+// point's run inside the chunk, reading the chunk's contributions from LDS in
+// order, so the result does not depend on scheduling.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ probs,
+                                                   const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st) || !st->relin) return;
+  const int cur = st->cur;
+  const T delta = T(st->huber_delta);
+  const int j0 = tl.idx * kPtTile;
+  const int j1 = min(pd.P, j0 + kPtTile);
+  const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+
+  __shared__ T s_acc[kPtTile][9];
+  __shared__ T s_c[kObsChunk][9];
+  __shared__ int s_loc[kObsChunk];
+  __shared__ double s_red[4];
+  for (int i = threadIdx.x; i < kPtTile * 9; i += 256) (&s_acc[0][0])[i] = T(0);
+
+  const T *Kall = (const T *)pd.K;
+  const T *uv = (const T *)pd.obs_uv;
+  LinRec<T, S> *lin = (LinRec<T, S> *)pd.lin;
+  const double *poses = pd.pose[cur];
+  const double *Xs = pd.X[cur];
+  double cost = 0.0;
+  int masked = 0;
+  __syncthreads();
+
+  for (int base = k0; base < k1; base += kObsChunk) {
+    const int k = base + threadIdx.x;
+    T c[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c[i] = T(0);
+    int jl = -1;
+    if (k < k1) {
+      const int j = pd.obs_pt[k];
+      jl = j - j0;
+      const int cam = pd.obs_cam[k];
+      const double *pose = poses + 12 * cam;
+      double xd, yd, zd;
+      transform(pose, Xs + 3 * j, xd, yd, zd);
+      const T x = T(xd), y = T(yd), z = T(zd);
+      const T *K = Kall + 4 * cam;
+      T r0, r1;
+      LinRec<T, S> rec;
+      if (residual<T>(K, x, y, z, uv[2 * k], uv[2 * k + 1], r0, r1)) {
+        const T s = r0 * r0 + r1 * r1;
+        const T w = huber_w(s, delta);
+        const T sw = sqrt(w);
+        cost += 0.5 * (double)huber_rho(s, delta);
+        T Jc[12], Jp[6];
+        jacobians<T>(K, pose, x, y, z, Jc, Jp);
+        T q[18];  // stored-precision values, used for V so that V, U and W agree
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          rec.j[i] = Codec<S>::enc(sw * Jc[i]);
+          q[i] = Codec<S>::dec(rec.j[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          rec.j[12 + i] = Codec<S>::enc(sw * Jp[i]);
+          q[12 + i] = Codec<S>::dec(rec.j[12 + i]);
+        }
+        rec.e[0] = sw * r0;
+        rec.e[1] = sw * r1;
+        const T *P0 = q + 12, *P1 = q + 15;
+        c[0] = P0[0] * P0[0] + P1[0] * P1[0];
+        c[1] = P0[0] * P0[1] + P1[0] * P1[1];
+        c[2] = P0[0] * P0[2] + P1[0] * P1[2];
+        c[3] = P0[1] * P0[1] + P1[1] * P1[1];
+        c[4] = P0[1] * P0[2] + P1[1] * P1[2];
+        c[5] = P0[2] * P0[2] + P1[2] * P1[2];
+        // gradient from the unrounded Jacobian: w J_p^T r
+#pragma unroll
+        for (int m = 0; m < 3; ++m) c[6 + m] = w * (Jp[m] * r0 + Jp[3 + m] * r1);
+      } else {
+        ++masked;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) rec.j[i] = Codec<S>::enc(0.0f);
+        rec.e[0] = rec.e[1] = T(0);
+      }
+      lin[k] = rec;
+    }
+    s_loc[threadIdx.x] = jl;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s_c[threadIdx.x][i] = c[i];
+    __syncthreads();
+    if (jl >= 0 && (threadIdx.x == 0 || s_loc[threadIdx.x - 1] != jl)) {
+      for (int t = threadIdx.x + 1; t < kObsChunk && s_loc[t] == jl; ++t)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) c[i] += s_c[t][i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s_acc[jl][i] += c[i];
+    }
+    __syncthreads();
+  }
+  T *V = (T *)pd.V;
+  T *gp = (T *)pd.gp;
+  T *Dp = (T *)pd.Dp;
+  for (int jl = threadIdx.x; jl < j1 - j0; jl += 256) {
+    const int j = j0 + jl;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) V[6 * j + i] = s_acc[jl][i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gp[3 * j + i] = s_acc[jl][6 + i];
+    const T d[3] = {s_acc[jl][0], s_acc[jl][3], s_acc[jl][5]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Dp[3 * j + i] = T(fmin(fmax((double)d[i], kDMin), kDMax));
+  }
+  const double tot = block_sum256(cost, s_red);
+  const double nm = block_sum256((double)masked, s_red);
+  if (threadIdx.x == 0) {
+    pd.part_lin_cost[tl.idx] = tot;
+    pd.part_masked[tl.idx] = (int32_t)nm;
+  }
+}
+
+// ------------------------------------------------------------------ point prep
+// V*_j = V_j + lambda D_j inverted in FP64; Y_k = (J_c^T J_p) V*_j^-1 per observation.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const double lam = st->lambda;
+  const int j0 = tl.idx * kPtTile;
+  const int j1 = min(pd.P, j0 + kPtTile);
+  __shared__ T s_vi[kPtTile][6];
+  const T *V = (const T *)pd.V;
+  const T *Dp = (const T *)pd.Dp;
+  T *Vinv = (T *)pd.Vinv;
+  for (int jl = threadIdx.x; jl < j1 - j0; jl += 256) {
+    const int j = j0 + jl;
+    double u[6], o[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) u[i] = (double)V[6 * j + i];
+    u[0] += lam * (double)Dp[3 * j + 0];
+    u[3] += lam * (double)Dp[3 * j + 1];
+    u[5] += lam * (double)Dp[3 * j + 2];
+    inv_sym3(u, o);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      s_vi[jl][i] = T(o[i]);
+      Vinv[6 * j + i] = T(o[i]);
+    }
+  }
+  __syncthreads();
+  const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  T *Y = (T *)pd.Y;
+  for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+    const int jl = pd.obs_pt[k] - j0;
+    const LinRec<T, S> rec = lin[k];
+    T J[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+    const T *vi = s_vi[jl];
+    const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
+    T y[18];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      // W[r][n] = J_c[0][r] J_p[0][n] + J_c[1][r] J_p[1][n]
+      T w0 = J[r] * J[12] + J[6 + r] * J[15];
+      T w1 = J[r] * J[13] + J[6 + r] * J[16];
+      T w2 = J[r] * J[14] + J[6 + r] * J[17];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) y[3 * r + m] = w0 * M[m] + w1 * M[3 + m] + w2 * M[6 + m];
+    }
+#pragma unroll
+    for (int i = 0; i < 18; ++i) Y[18 * (size_t)k + i] = y[i];
+  }
+}
+
+// ------------------------------------------------------------------ Schur: diagonal
+// One workgroup per free camera.  Accumulates, over the camera's observations,
+// U (upper 21), sum Y W^T (upper 21), g_c (6) and sum Y g_p (6); then damping,
+// the diagonal block of S, the right-hand side, the FP64 block-Jacobi inverse
+// and the PCG initial vectors of this row.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int a = tl.idx;
+  const int o0 = pd.cam_obs_start[a], o1 = pd.cam_obs_start[a + 1];
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *Yall = (const T *)pd.Y;
+  const T *gp = (const T *)pd.gp;
+  constexpr bool k16 = sizeof(S) == 2;
+
+  T acc[54];
+#pragma unroll
+  for (int i = 0; i < 54; ++i) acc[i] = T(0);
+  // 16-bit storage: the gradient is formed from FP32 Jacobians recomputed here
+  int cam = -1;
+  const double *pose = nullptr;
+  const T *K = nullptr;
+  const T delta = T(st->huber_delta);
+  if (k16) {
+    cam = pd.free_cam[a];
+    pose = pd.pose[st->cur] + 12 * cam;
+    K = (const T *)pd.K + 4 * cam;
+  }
+  for (int o = o0 + threadIdx.x; o < o1; o += 256) {
+    const int k = pd.cam_obs[o];
+    const int j = pd.obs_pt[k];
+    const LinRec<T, S> rec = lin[k];
+    T J[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+    const T *Jc0 = J, *Jc1 = J + 6, *Jp0 = J + 12, *Jp1 = J + 15;
+    T y[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)k + i];
+    // Z = Y J_p^T (6x2)
+    T Z0[6], Z1[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      Z0[r] = y[3 * r] * Jp0[0] + y[3 * r + 1] * Jp0[1] + y[3 * r + 2] * Jp0[2];
+      Z1[r] = y[3 * r] * Jp1[0] + y[3 * r + 1] * Jp1[1] + y[3 * r + 2] * Jp1[2];
+    }
+    int u = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = r; c < 6; ++c, ++u) {
+        acc[u] += Jc0[r] * Jc0[c] + Jc1[r] * Jc1[c];
+        acc[21 + u] += Z0[r] * Jc0[c] + Z1[r] * Jc1[c];
+      }
+    T e0 = rec.e[0], e1 = rec.e[1];
+    T G0[6], G1[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      G0[r] = Jc0[r];
+      G1[r] = Jc1[r];
+    }
+    if (k16) {
+      const double *Xj = pd.X[st->cur] + 3 * j;
+      double xd, yd, zd;
+      transform(pose, Xj, xd, yd, zd);
+      const T x = T(xd), yy = T(yd), z = T(zd);
+      const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
+      T r0, r1;
+      if (residual<T>(K, x, yy, z, uv[0], uv[1], r0, r1)) {
+        const T s = r0 * r0 + r1 * r1;
+        const T sw = sqrt(huber_w(s, delta));
+        T Jc[12], Jp[6];
+        jacobians<T>(K, pose, x, yy, z, Jc, Jp);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          G0[r] = sw * Jc[r];
+          G1[r] = sw * Jc[6 + r];
+        }
+        e0 = sw * r0;
+        e1 = sw * r1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) G0[r] = G1[r] = T(0);
+        e0 = e1 = T(0);
+      }
+    }
+    const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      acc[42 + r] += G0[r] * e0 + G1[r] * e1;
+      acc[48 + r] += y[3 * r] * g0 + y[3 * r + 1] * g1 + y[3 * r + 2] * g2;
+    }
+  }
+  // deterministic block reduction: wave butterflies, then the 4 waves in order
+  __shared__ T s_w[4][54];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 54; ++i) {
+    const T v = wave_sum(acc[i]);
+    if (lane == 0) s_w[w][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[54];
+    for (int i = 0; i < 54; ++i)
+      tot[i] = (double)s_w[0][i] + (double)s_w[1][i] + (double)s_w[2][i] + (double)s_w[3][i];
+    // NB: the FP32 mode sums its four wave totals in FP64; the sums themselves are FP32.
+    const double lam = st->lambda;
+    double Sfull[36], Dc[6];
+    int u = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c, ++u) {
+        const double Uv = (double)T(tot[u]);
+        const double Mv = (double)T(tot[21 + u]);
+        const double sv = Uv - Mv;
+        Sfull[6 * r + c] = sv;
+        Sfull[6 * c + r] = sv;
+        if (r == c) Dc[r] = fmin(fmax(Uv, kDMin), kDMax);
+      }
+    for (int r = 0; r < 6; ++r) Sfull[7 * r] += lam * (double)T(Dc[r]);
+    T *Sblk = (T *)pd.S + 36 * (size_t)pd.diag_pos[a];
+    double Sd[36];
+    for (int i = 0; i < 36; ++i) {
+      Sblk[i] = T(Sfull[i]);
+      Sd[i] = (double)T(Sfull[i]);  // the preconditioner inverts the stored block
+    }
+    double Mi[36];
+    inv_spd6(Sd, Mi);
+    double *Minv = pd.Minv + 36 * (size_t)a;
+    for (int i = 0; i < 36; ++i) Minv[i] = Mi[i];
+    T *gc = (T *)pd.gc + 6 * a;
+    T *Dcv = (T *)pd.Dc + 6 * a;
+    T *bv = (T *)pd.brhs + 6 * a;
+    T *x = (T *)pd.x + 6 * a;
+    T *r = (T *)pd.r + 6 * a;
+    T *z = (T *)pd.z + 6 * a;
+    T *p = (T *)pd.p0 + 6 * a;
+    double bb = 0.0, rz = 0.0;
+    double bvals[6];
+    for (int i = 0; i < 6; ++i) {
+      const T g = T(tot[42 + i]);
+      const T b = T(-(double)g + (double)T(tot[48 + i]));
+      gc[i] = g;
+      Dcv[i] = T(Dc[i]);
+      bv[i] = b;
+      x[i] = T(0);
+      r[i] = b;
+      bvals[i] = (double)b;
+      bb += bvals[i] * bvals[i];
+    }
+    for (int i = 0; i < 6; ++i) {
+      double zi = 0.0;
+      for (int m = 0; m < 6; ++m) zi += Mi[6 * i + m] * bvals[m];
+      const T zt = T(zi);
+      z[i] = zt;
+      p[i] = zt;
+      rz += bvals[i] * (double)zt;
+    }
+    pd.part_rz0[a] = rz;
+    pd.part_bb[a] = bb;
+  }
+}
+
+// ------------------------------------------------------------------ Schur: off-diagonal
+// One wavefront per upper block (a, b): S_ab = -sum_j Y_aj W_bj^T over the
+// block's pair list, W_bj^T = J_p,b^T J_c,b, so each pair costs Z = Y J_p^T
+// (6x2) and Z J_c (6x6).  Lanes stride over pairs; one butterfly reduction.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ probs,
+                                                   const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int u = tl.idx * kOffWaves + w;
+  if (u >= pd.n_up) return;  // wave-uniform; no block-wide barrier follows
+  const int p0 = pd.up_pair_start[u], p1 = pd.up_pair_start[u + 1];
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *Yall = (const T *)pd.Y;
+  T acc[36];
+#pragma unroll
+  for (int i = 0; i < 36; ++i) acc[i] = T(0);
+  for (int p = p0 + lane; p < p1; p += 64) {
+    const int2 kk = pd.pairs[p];
+    T y[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)kk.x + i];
+    const LinRec<T, S> rec = lin[kk.y];
+    T J[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const T z0 = y[3 * r] * J[12] + y[3 * r + 1] * J[13] + y[3 * r + 2] * J[14];
+      const T z1 = y[3 * r] * J[15] + y[3 * r + 1] * J[16] + y[3 * r + 2] * J[17];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * J[c] + z1 * J[6 + c];
+    }
+  }
+  // butterfly: every lane ends with all 36 sums; lane e keeps entry e
+  T mine = T(0);
+#pragma unroll
+  for (int i = 0; i < 36; ++i) {
+    const T v = wave_sum(acc[i]);
+    mine = (lane == i) ? v : mine;
+  }
+  if (lane < 36) {
+    const int r = lane / 6, c = lane % 6;
+    T *Sv = (T *)pd.S;
+    Sv[36 * (size_t)pd.up_pos[u] + lane] = -mine;
+    Sv[36 * (size_t)pd.up_tpos[u] + 6 * c + r] = -mine;
+  }
+}
+
+// ------------------------------------------------------------------ PCG
+// Tile = kPcgRows consecutive rows of one problem; four waves, a row per wave
+// at a time.  Iteration it (0-based):
+//   spmv(it):   it >= 1: stop if ||r_it|| <= tol ||b||; beta = rz_it / rz_{it-1};
+//               p_it = z + beta p_{it-1} (formed on the fly for every column read);
+//               q = S p_it; partial p_it . q.
+//   update(it): alpha = rz_it / (p.q); x += alpha p; r -= alpha q; z = M^-1 r;
+//               partials r.z and r.r.
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st) || st->pcg_done || it >= st->pcg_max) return;
+  __shared__ double s_red[4];
+  __shared__ double s_pq[4];
+  double beta = 0.0;
+  if (it == 0) {
+    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
+    const double rz0 = block_sum_array(pd.part_rz0, pd.Cf, s_red);
+    if (tl.idx == 0 && threadIdx.x == 0) {
+      st->pcg_bb = bb;
+      st->pcg_rz0 = rz0;
+    }
+    if (!(bb > 0.0)) {
+      if (tl.idx == 0 && threadIdx.x == 0) {
+        st->pcg_done = 1;
+        st->pcg_iters = 0;
+      }
+      return;
+    }
+  } else {
+    const double rr = block_sum_array(pd.part_rr, pd.n_pcg_tiles, s_red);
+    const double bb = st->pcg_bb;
+    if (sqrt(rr) <= st->pcg_tol * sqrt(bb)) {
+      if (tl.idx == 0 && threadIdx.x == 0) {
+        st->pcg_done = 1;
+        st->pcg_iters = it;
+      }
+      return;
+    }
+    const double rz_new = block_sum_array(pd.part_rz[it & 1], pd.n_pcg_tiles, s_red);
+    const double rz_old =
+        (it == 1) ? st->pcg_rz0 : block_sum_array(pd.part_rz[(it - 1) & 1], pd.n_pcg_tiles, s_red);
+    beta = rz_new / rz_old;
+  }
+  const T tb = T(beta);
+  const T *z = (const T *)pd.z;
+  const T *pold = (const T *)((it & 1) ? pd.p0 : pd.p1);  // p_{it-1}
+  const T *pin = (const T *)pd.p0;                        // p_0 when it == 0
+  T *pout = (T *)((it & 1) ? pd.p1 : pd.p0);              // p_it
+  T *q = (T *)pd.q;
+  const T *S = (const T *)pd.S;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / 6, i = lane % 6;
+  double pq = 0.0;
+  const int rbeg = tl.idx * kPcgRows;
+  const int rend = min(pd.Cf, rbeg + kPcgRows);
+  for (int a = rbeg + w; a < rend; a += 4) {
+    T acc = T(0);
+    if (lane < 60) {
+      for (int blk = pd.S_rowptr[a] + g; blk < pd.S_rowptr[a + 1]; blk += 10) {
+        const int c = pd.S_col[blk];
+        const T *Srow = S + 36 * (size_t)blk + 6 * i;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const T pc = (it == 0) ? pin[6 * c + m] : z[6 * c + m] + tb * pold[6 * c + m];
+          acc += Srow[m] * pc;
+        }
+      }
+    }
+    // lanes 6g + i hold partial sums of output i; gather them in a fixed order
+    T qi = T(0);
+#pragma unroll
+    for (int gg = 0; gg < 10; ++gg) qi += __shfl(acc, 6 * gg + i, 64);
+    if (lane < 6) {
+      const T pa = (it == 0) ? pin[6 * a + lane] : z[6 * a + lane] + tb * pold[6 * a + lane];
+      q[6 * a + lane] = qi;
+      if (it > 0) pout[6 * a + lane] = pa;
+      pq += (double)pa * (double)qi;
+    }
+  }
+  const double tot = block_sum256(pq, s_pq);
+  if (threadIdx.x == 0) pd.part_pq[tl.idx] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles, int it) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st) || st->pcg_done || it >= st->pcg_max) return;
+  __shared__ double s_red[4];
+  const double pq = block_sum_array(pd.part_pq, pd.n_pcg_tiles, s_red);
+  if (!(pq > 0.0)) {  // breakdown: keep x, stop
+    if (tl.idx == 0 && threadIdx.x == 0) {
+      st->pcg_done = 1;
+      st->pcg_iters = it + 1;
+    }
+    return;
+  }
+  const double rz = (it == 0) ? st->pcg_rz0 : block_sum_array(pd.part_rz[it & 1], pd.n_pcg_tiles, s_red);
+  const double alpha = rz / pq;
+  const T ta = T(alpha);
+  const T *p = (const T *)((it & 1) ? pd.p1 : pd.p0);
+  const T *q = (const T *)pd.q;
+  T *x = (T *)pd.x;
+  T *r = (T *)pd.r;
+  T *z = (T *)pd.z;
+  const int rbeg = tl.idx * kPcgRows;
+  const int rend = min(pd.Cf, rbeg + kPcgRows);
+  double rzp = 0.0, rrp = 0.0;
+  // one thread per row element: 6 * kPcgRows <= 256
+  const int e = threadIdx.x;
+  const int a = rbeg + e / 6;
+  __shared__ T s_r[kPcgRows * 6];
+  if (e < 6 * kPcgRows && a < rend) {
+    const size_t idx = 6 * (size_t)a + (e % 6);
+    x[idx] = x[idx] + ta * p[idx];
+    const T rn = r[idx] - ta * q[idx];
+    r[idx] = rn;
+    s_r[e] = rn;
+  }
+  __syncthreads();
+  if (e < 6 * kPcgRows && a < rend) {
+    const int i = e % 6;
+    const double *Mi = pd.Minv + 36 * (size_t)a + 6 * i;
+    const T *rr = s_r + 6 * (e / 6);
+    double zi = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) zi += Mi[m] * (double)rr[m];
+    const T zt = T(zi);
+    z[6 * (size_t)a + i] = zt;
+    rzp = (double)rr[i] * (double)zt;
+    rrp = (double)rr[i] * (double)rr[i];
+  }
+  __shared__ double s_red2[4];
+  const double trz = block_sum256(rzp, s_red);
+  const double trr = block_sum256(rrp, s_red2);
+  if (threadIdx.x == 0) {
+    pd.part_rz[(it + 1) & 1][tl.idx] = trz;
+    pd.part_rr[tl.idx] = trr;
+  }
+}
+
+// ------------------------------------------------------------------ camera update
+template <class T>
+__global__ __launch_bounds__(256) void k_cam_update(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  __shared__ double s_red[4];
+  const int cur = st->cur;
+  const double lam = st->lambda;
+  const int c = tl.idx * kCamTile + threadIdx.x;
+  double dl = 0.0;
+  if (c < pd.C) {
+    const double *src = pd.pose[cur] + 12 * c;
+    double *dst = pd.pose[1 - cur] + 12 * c;
+    const int a = pd.free_idx[c];
+    if (a < 0) {
+      for (int i = 0; i < 12; ++i) dst[i] = src[i];
+    } else {
+      const T *x = (const T *)pd.x + 6 * a;
+      const T *gc = (const T *)pd.gc + 6 * a;
+      const T *Dc = (const T *)pd.Dc + 6 * a;
+      double xi[6];
+      for (int i = 0; i < 6; ++i) {
+        xi[i] = (double)x[i];
+        dl += lam * (double)Dc[i] * xi[i] * xi[i] - (double)gc[i] * xi[i];
+      }
+      double dR[9], dt[3];
+      se3_exp(xi, dR, dt);
+      for (int r = 0; r < 3; ++r) {
+        for (int cc = 0; cc < 3; ++cc)
+          dst[3 * r + cc] = dR[3 * r] * src[cc] + dR[3 * r + 1] * src[3 + cc] + dR[3 * r + 2] * src[6 + cc];
+        dst[9 + r] = dR[3 * r] * src[9] + dR[3 * r + 1] * src[10] + dR[3 * r + 2] * src[11] + dt[r];
+      }
+    }
+  }
+  const double tot = block_sum256(dl, s_red);
+  if (threadIdx.x == 0) pd.part_dl_cam[tl.idx] = tot;
+}
+
+// ------------------------------------------------------------------ point back-substitution + trial cost
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__ probs,
+                                                     const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int cur = st->cur;
+  const double lam = st->lambda;
+  const T delta = T(st->huber_delta);
+  const int j0 = tl.idx * kPtTile;
+  const int j1 = min(pd.P, j0 + kPtTile);
+  const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+  __shared__ T s_acc[kPtTile][3];
+  __shared__ T s_c[kObsChunk][3];
+  __shared__ int s_loc[kObsChunk];
+  __shared__ double s_X[kPtTile][3];
+  __shared__ double s_red[4];
+  for (int i = threadIdx.x; i < kPtTile * 3; i += 256) (&s_acc[0][0])[i] = T(0);
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *x = (const T *)pd.x;
+  __syncthreads();
+  // phase 1: sum_k W_k^T dc_{cam(k)} = sum_k J_p^T (J_c dc) per point
+  for (int base = k0; base < k1; base += kObsChunk) {
+    const int k = base + threadIdx.x;
+    T c[3] = {T(0), T(0), T(0)};
+    int jl = -1;
+    if (k < k1) {
+      jl = pd.obs_pt[k] - j0;
+      const int a = pd.free_idx[pd.obs_cam[k]];
+      if (a >= 0) {
+        const LinRec<T, S> rec = lin[k];
+        T J[18];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+        const T *dc = x + 6 * a;
+        T u0 = T(0), u1 = T(0);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const T d = dc[m];
+          u0 += J[m] * d;
+          u1 += J[6 + m] * d;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) c[m] = J[12 + m] * u0 + J[15 + m] * u1;
+      }
+    }
+    s_loc[threadIdx.x] = jl;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s_c[threadIdx.x][i] = c[i];
+    __syncthreads();
+    if (jl >= 0 && (threadIdx.x == 0 || s_loc[threadIdx.x - 1] != jl)) {
+      for (int t = threadIdx.x + 1; t < kObsChunk && s_loc[t] == jl; ++t)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) c[i] += s_c[t][i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) s_acc[jl][i] += c[i];
+    }
+    __syncthreads();
+  }
+  // phase 2: dp_j, trial point, point part of the predicted decrease
+  const T *Vinv = (const T *)pd.Vinv;
+  const T *gp = (const T *)pd.gp;
+  const T *Dp = (const T *)pd.Dp;
+  double dl = 0.0;
+  for (int jl = threadIdx.x; jl < j1 - j0; jl += 256) {
+    const int j = j0 + jl;
+    const T *vi = Vinv + 6 * (size_t)j;
+    const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
+    T rhs[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rhs[i] = -gp[3 * j + i] - s_acc[jl][i];
+    const double *X = pd.X[cur] + 3 * (size_t)j;
+    double *Xn = pd.X[1 - cur] + 3 * (size_t)j;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T d = M[3 * i] * rhs[0] + M[3 * i + 1] * rhs[1] + M[3 * i + 2] * rhs[2];
+      const double dd = (double)d;
+      dl += lam * (double)Dp[3 * j + i] * dd * dd - (double)gp[3 * j + i] * dd;
+      const double v = X[i] + dd;
+      Xn[i] = v;
+      s_X[jl][i] = v;
+    }
+  }
+  __syncthreads();
+  // phase 3: trial cost at (T', X')
+  const T *Kall = (const T *)pd.K;
+  const T *uv = (const T *)pd.obs_uv;
+  const double *poses = pd.pose[1 - cur];
+  double cost = 0.0;
+  for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+    const int jl = pd.obs_pt[k] - j0;
+    const int cam = pd.obs_cam[k];
+    double xd, yd, zd;
+    transform(poses + 12 * cam, s_X[jl], xd, yd, zd);
+    T r0, r1;
+    if (residual<T>(Kall + 4 * cam, T(xd), T(yd), T(zd), uv[2 * (size_t)k], uv[2 * (size_t)k + 1], r0, r1))
+      cost += 0.5 * (double)huber_rho(r0 * r0 + r1 * r1, delta);
+  }
+  const double tc = block_sum256(cost, s_red);
+  const double td = block_sum256(dl, s_red);
+  if (threadIdx.x == 0) {
+    pd.part_trial_cost[tl.idx] = tc;
+    pd.part_dl_pt[tl.idx] = td;
+  }
+}
+
+// ------------------------------------------------------------------ LM control
+// One workgroup per problem.  Madsen-Nielsen-Tingleff damping: accept iff the
+// gain ratio exceeds 1e-3 and the predicted decrease is positive; on accept
+// lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; on reject lambda *= nu, nu *= 2.
+__global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  __shared__ double s_red[4];
+  const double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
+  const double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
+  const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
+  const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
+  if (threadIdx.x != 0) return;
+  const int n = st->iter;
+  if (!st->init_done) {
+    st->cost = c0;
+    st->cost0 = c0;
+    st->init_done = 1;
+    pd.iter_cost[0] = c0;
+  }
+  const double C = st->cost;
+  const double dL = 0.5 * (dlc + dlp);
+  const double rho = (dL != 0.0) ? (C - tc) / dL : -INFINITY;
+  st->trial_cost = tc;
+  st->dL = dL;
+  st->rho = rho;
+  double lam = st->lambda;
+  pd.iter_pcg[n] = st->pcg_done ? st->pcg_iters : st->pcg_max;
+  if (isfinite(tc) && dL > 0.0 && rho > kAcceptRho) {
+    st->cost = tc;
+    st->cur = 1 - st->cur;
+    const double t = 2.0 * rho - 1.0;
+    lam *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+    st->nu = 2.0;
+    st->relin = 1;
+    st->accepted += 1;
+  } else {
+    lam *= st->nu;
+    st->nu *= 2.0;
+    st->relin = 0;
+  }
+  lam = fmin(fmax(lam, kLambdaMin), kLambdaMax);
+  st->lambda = lam;
+  pd.iter_cost[n + 1] = st->cost;
+  st->pcg_done = 0;
+  st->pcg_iters = 0;
+  st->iter = n + 1;
+  if (st->iter >= st->max_iters) {
+    if (!isfinite(st->cost)) st->status = 2;
+    else if (lam >= kLambdaMax) st->status = 1;
+    else st->status = 0;
+  }
+}
+
+// ------------------------------------------------------------------ evaluation
+// sum ||r||^2 and the masked count at the accepted state, per point tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_eval(const ProbDev *__restrict__ probs,
+                                              const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  const int cur = st->cur;
+  const int j0 = tl.idx * kPtTile;
+  const int j1 = min(pd.P, j0 + kPtTile);
+  const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+  const T *Kall = (const T *)pd.K;
+  const T *uv = (const T *)pd.obs_uv;
+  __shared__ double s_red[4];
+  double sq = 0.0;
+  int masked = 0;
+  for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+    const int j = pd.obs_pt[k];
+    const int cam = pd.obs_cam[k];
+    double xd, yd, zd;
+    transform(pd.pose[cur] + 12 * cam, pd.X[cur] + 3 * (size_t)j, xd, yd, zd);
+    T r0, r1;
+    if (residual<T>(Kall + 4 * cam, T(xd), T(yd), T(zd), uv[2 * (size_t)k], uv[2 * (size_t)k + 1], r0, r1))
+      sq += (double)(r0 * r0 + r1 * r1);
+    else
+      ++masked;
+  }
+  const double tsq = block_sum256(sq, s_red);
+  const double tm = block_sum256((double)masked, s_red);
+  if (threadIdx.x == 0) {
+    pd.part_sq[tl.idx] = tsq;
+    pd.part_masked[tl.idx] = (int32_t)tm;
+  }
+}
+
+// ------------------------------------------------------------------ pose-only Gauss-Newton
+// One workgroup per request; the whole iteration count runs in the kernel.
+// FP32 projection and Jacobians, FP32 per-thread sums of H (21) and g (6)
+// combined in FP64, FP64 6x6 Cholesky solve and FP64 pose update.
+__global__ __launch_bounds__(kPoseThreads) void k_pose_gn(PoseDev *__restrict__ reqs,
+                                                          const double *__restrict__ Xall,
+                                                          const float *__restrict__ uvall,
+                                                          int iters, float delta) {
+  PoseDev &rq = reqs[blockIdx.x];
+  __shared__ double s_pose[12];
+  __shared__ double s_sum[4][28];
+  __shared__ int s_bad;
+  if (threadIdx.x < 12) s_pose[threadIdx.x] = rq.pose[threadIdx.x];
+  if (threadIdx.x == 0) s_bad = 0;
+  const float K[4] = {(float)rq.K[0], (float)rq.K[1], (float)rq.K[2], (float)rq.K[3]};
+  const double *X = Xall + 3 * rq.off;
+  const float *uv = uvall + 2 * rq.off;
+  const int n = rq.n;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  for (int it = 0; it <= iters; ++it) {
+    float acc[28];
+#pragma unroll
+    for (int i = 0; i < 28; ++i) acc[i] = 0.0f;
+    double cost = 0.0;
+    double pose[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) pose[i] = s_pose[i];
+    for (int c = threadIdx.x; c < n; c += kPoseThreads) {
+      double xd, yd, zd;
+      transform(pose, X + 3 * (size_t)c, xd, yd, zd);
+      const float x = (float)xd, y = (float)yd, z = (float)zd;
+      float r0, r1;
+      if (!residual<float>(K, x, y, z, uv[2 * c], uv[2 * c + 1], r0, r1)) continue;
+      const float s = r0 * r0 + r1 * r1;
+      cost += 0.5 * (double)huber_rho(s, delta);
+      if (it == iters) continue;
+      const float wgt = huber_w(s, delta);
+      float Jc[12], Jp[6];
+      jacobians<float>(K, pose, x, y, z, Jc, Jp);
+      int u = 0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int cc = r; cc < 6; ++cc, ++u) acc[u] += wgt * (Jc[r] * Jc[cc] + Jc[6 + r] * Jc[6 + cc]);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) acc[21 + r] += wgt * (Jc[r] * r0 + Jc[6 + r] * r1);
+    }
+    acc[27] = 0.0f;
+    double dacc[28];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) dacc[i] = wave_sum((double)acc[i]);
+    dacc[27] = wave_sum(cost);
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < 28; ++i) s_sum[w][i] = dacc[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot[28];
+      for (int i = 0; i < 28; ++i) tot[i] = s_sum[0][i] + s_sum[1][i] + s_sum[2][i] + s_sum[3][i];
+      if (it == iters) {
+        rq.cost = tot[27];
+      } else {
+        double H[36];
+        int u = 0;
+        for (int r = 0; r < 6; ++r)
+          for (int cc = r; cc < 6; ++cc, ++u) {
+            H[6 * r + cc] = tot[u];
+            H[6 * cc + r] = tot[u];
+          }
+        // Cholesky solve H d = -g
+        double L[36];
+        bool ok = true;
+        for (int i = 0; i < 36; ++i) L[i] = 0.0;
+        for (int j = 0; j < 6 && ok; ++j) {
+          double s = H[7 * j];
+          for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+          if (!(s > 0.0)) {
+            ok = false;
+            break;
+          }
+          L[7 * j] = sqrt(s);
+          for (int i = j + 1; i < 6; ++i) {
+            double t = H[6 * i + j];
+            for (int k = 0; k < j; ++k) t -= L[6 * i + k] * L[6 * j + k];
+            L[6 * i + j] = t / L[7 * j];
+          }
+        }
+        if (!ok) {
+          s_bad = 1;
+        } else {
+          double yv[6], d[6];
+          for (int i = 0; i < 6; ++i) {
+            double s = -tot[21 + i];
+            for (int k = 0; k < i; ++k) s -= L[6 * i + k] * yv[k];
+            yv[i] = s / L[7 * i];
+          }
+          for (int i = 5; i >= 0; --i) {
+            double s = yv[i];
+            for (int k = i + 1; k < 6; ++k) s -= L[6 * k + i] * d[k];
+            d[i] = s / L[7 * i];
+          }
+          double dR[9], dt[3], np[12];
+          se3_exp(d, dR, dt);
+          for (int r = 0; r < 3; ++r) {
+            for (int cc = 0; cc < 3; ++cc)
+              np[3 * r + cc] = dR[3 * r] * s_pose[cc] + dR[3 * r + 1] * s_pose[3 + cc] + dR[3 * r + 2] * s_pose[6 + cc];
+            np[9 + r] = dR[3 * r] * s_pose[9] + dR[3 * r + 1] * s_pose[10] + dR[3 * r + 2] * s_pose[11] + dt[r];
+          }
+          for (int i = 0; i < 12; ++i) s_pose[i] = np[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 12) rq.pose[threadIdx.x] = s_pose[threadIdx.x];
+  if (threadIdx.x == 0) rq.status = s_bad;
+}
+
+// ------------------------------------------------------------------ launchers
+namespace {
+struct Timed {
+  KernelTimer *t;
+  int id;
+  hipStream_t s;
+  Timed(KernelTimer *t_, int id_, hipStream_t s_) : t(t_), id(id_), s(s_) {
+    if (t) t->begin(id, s);
+  }
+  ~Timed() {
+    if (t) t->end(id, s);
+  }
+};
+}  // namespace
+
+template <class T, class S>
+static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, KernelTimer *tm) {
+  if (bp.n_pt) {
+    Timed t(tm, K_LINEARIZE, s);
+    k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  }
+  if (bp.n_pt) {
+    Timed t(tm, K_POINT_PREP, s);
+    k_point_prep<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  }
+  if (bp.n_diag) {
+    Timed t(tm, K_SCHUR_DIAG, s);
+    k_schur_diag<T, S><<<bp.n_diag, 256, 0, s>>>(bp.probs, bp.diag);
+  }
+  if (bp.n_off) {
+    Timed t(tm, K_SCHUR_OFF, s);
+    k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
+  }
+  for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
+    {
+      Timed t(tm, K_PCG_SPMV, s);
+      k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+    }
+    {
+      Timed t(tm, K_PCG_UPDATE, s);
+      k_pcg_update<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+    }
+  }
+  if (bp.n_cam) {
+    Timed t(tm, K_CAM_UPDATE, s);
+    k_cam_update<T><<<bp.n_cam, 256, 0, s>>>(bp.probs, bp.cam);
+  }
+  if (bp.n_pt) {
+    Timed t(tm, K_POINT_TRIAL, s);
+    k_point_trial<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  }
+  if (bp.n_ctl) {
+    Timed t(tm, K_LM_CONTROL, s);
+    k_lm_control<<<bp.n_ctl, 256, 0, s>>>(bp.probs, bp.ctl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
+                               KernelTimer *timer) {
+  switch (precision) {
+    case 0: return lm_iteration<double, double>(bp, pcg_max, s, timer);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, s, timer);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, s, timer);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, s, timer);
+  }
+}
+
+hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer) {
+  if (!bp.n_pt) return hipSuccess;
+  Timed t(timer, K_EVAL, s);
+  if (precision == 0)
+    k_eval<double><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  else
+    k_eval<float><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  return hipGetLastError();
+}
+
+// Iteration counter of every problem of a batch, in batch order.
+__global__ void k_gather_iters(const ProbDev *__restrict__ probs, const Tile *__restrict__ ctl, int n,
+                               int32_t *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = probs[ctl[i].prob].st->iter;
+}
+
+hipError_t launch_gather_iters(const BatchPlan &bp, int32_t *out, hipStream_t s) {
+  if (!bp.n_ctl) return hipSuccess;
+  k_gather_iters<<<(bp.n_ctl + 255) / 256, 256, 0, s>>>(bp.probs, bp.ctl, bp.n_ctl, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
+                          double huber_delta, hipStream_t s, KernelTimer *timer) {
+  if (n_req <= 0) return hipSuccess;
+  Timed t(timer, K_POSE_GN, s);
+  k_pose_gn<<<n_req, kPoseThreads, 0, s>>>(reqs, X, uv, iters, (float)huber_delta);
+  return hipGetLastError();
+}
+
+}  // namespace bax

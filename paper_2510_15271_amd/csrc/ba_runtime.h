@@ -1,0 +1,113 @@
+// Host-side runtime structures of the bundle-adjustment library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_internal.h"
+
+namespace bax {
+
+extern thread_local std::string g_last_error;
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int check_pose(const ba_pose &p, const char *what, int64_t i);
+int check_options(const ba_options *o, bool pose_only);
+void quat_to_pose12(const ba_pose &p, double out[12]);
+ba_pose pose12_to_quat(const double M[12]);
+
+// Result of the symbolic analysis of one problem (host arrays).
+struct Symbolic {
+  int32_t C = 0, Cf = 0, P = 0, N = 0;
+  int32_t n_up = 0, nnzb = 0;
+  std::vector<int32_t> free_idx, free_cam;
+  std::vector<int32_t> obs_cam, obs_pt;
+  std::vector<double> obs_uv;
+  std::vector<int32_t> pt_start;
+  std::vector<int32_t> cam_obs, cam_obs_start;
+  std::vector<int32_t> up_pair_start;
+  std::vector<int2> pairs;
+  std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
+};
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
+
+struct Offsets {
+  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start;
+  size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col;
+  size_t pose[2], X[2], pose_init, X_init, lin, Y, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[6];
+  size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_dl_pt, part_dl_cam;
+  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, iter_cost, iter_pcg;
+  size_t total;
+};
+
+// One problem placed in a device block: its descriptor and host-side scalars.
+struct DevProblem {
+  int precision = BA_PREC_F32, max_iters = 0, pcg_max = 0;
+  double lambda0 = 1e-4, pcg_tol = 1e-6, huber = 0.0;
+  int32_t C = 0, Cf = 0, P = 0, N = 0;
+  Offsets off{};
+  char *dev = nullptr;
+  ProbDev view{};
+  LMState host_state{};     // state read back after the last solve
+  LMState pending_state{};  // state uploaded for the solve in flight
+  std::vector<std::vector<float>> staging_f;
+  std::vector<std::vector<double>> staging_d;
+
+  static size_t plan(const Symbolic &sy, int precision, int max_iters, Offsets &o);
+  static size_t bytes_for(const Symbolic &sy, int precision, int max_iters);
+  int init(const Symbolic &sy, const ba_problem_desc *d, const ba_options *opt, char *base,
+           hipStream_t s);
+  LMState fresh_state() const;
+  int read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
+                  bool solved, double solve_ms, double setup_ms);
+};
+
+// Tile lists of a set of problems, mirrored on the device.
+struct Batch {
+  std::vector<ProbDev> probs;
+  std::vector<int> tags;
+  std::vector<Tile> tiles[6];  // pt, diag, off, pcg, cam, ctl
+  std::vector<char> host;
+  void *dev = nullptr;
+  size_t cap = 0;
+  BatchPlan plan{};
+  void clear();
+  void add(const ProbDev &pd, int slot_tag);
+  int upload(hipStream_t s);
+  ~Batch();
+};
+
+// Per-kernel device time from pairs of HIP events around each launch.
+struct EventTimer : KernelTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<int> ids;
+  size_t used = 0;
+  uint32_t mask = 0xffffffffu;  // kernels to time (bit = KernelId)
+  bool active = false;
+  void begin(int id, hipStream_t s) override;
+  void end(int id, hipStream_t s) override;
+  void reset();
+  void collect(double ms[K_NUM_KERNELS], int32_t launches[K_NUM_KERNELS]);
+  ~EventTimer() override;
+};
+
+// Pose-only requests packed for one launch.
+struct PoseBatch {
+  int n = 0;
+  int64_t n_corr = 0;
+  std::vector<PoseDev> hdr;
+  std::vector<double> X;
+  std::vector<float> uv;
+  int pack(const std::vector<const ba_pose_request *> &reqs);
+  size_t bytes() const;
+  // Upload, launch and queue the download of the headers into hdr (caller syncs).
+  int run(char *base, int iters, double delta, hipStream_t s, KernelTimer *tm);
+};
+int check_pose_request(const ba_pose_request &r, int64_t i);
+
+}  // namespace bax

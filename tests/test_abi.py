@@ -1,0 +1,93 @@
+"""C-ABI checks that need no GPU: every symbol of include/ba.h is exported, and
+argument validation rejects bad input before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import make_arc_scene, make_config4_requests
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ba.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ba_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(balib):
+    names = _declared_functions()
+    assert len(names) >= 19
+    lib = ctypes.CDLL(balib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_defaults(balib):
+    assert b"gfx950" in balib.lib().ba_version()
+    o = balib.options()
+    assert o.max_iters == 10 and o.pcg_max_iters == 50 and o.precision == 1
+
+
+def _expect(balib, code, fn):
+    with pytest.raises(balib.BAError) as e:
+        fn()
+    assert e.value.code == code
+    return str(e.value)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda d: d.obs.__setitem__(("cam", 0), -1) if False else d.obs["cam"].__setitem__(0, 99), "camera 99"),
+    (lambda d: d.obs["pt"].__setitem__(3, 10**6), "out of range"),
+    (lambda d: d.obs["u"].__setitem__(2, np.nan), "non-finite"),
+    (lambda d: d.X.__setitem__((1, 1), np.inf), "non-finite"),
+    (lambda d: d.poses.__setitem__((1, 0), 2.0), "quaternion"),
+    (lambda d: d.K.__setitem__((0, 0), 0.0), "intrinsics"),
+])
+def test_create_rejects_invalid_input(balib, mutate, needle):
+    s = make_arc_scene(3, 20, seed=1)
+    d = balib.scene_desc(s)
+    mutate(d)
+    msg = _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(d, balib.options()))
+    assert needle in msg
+
+
+def test_create_rejects_duplicates_empty_and_all_fixed(balib):
+    s = make_arc_scene(3, 20, seed=1)
+    d = balib.scene_desc(s)
+    d.obs[1] = d.obs[0]
+    assert "twice" in _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(d, balib.options()))
+    d = balib.scene_desc(s)
+    d.desc.n_obs = 0
+    _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(d, balib.options()))
+    s2 = make_arc_scene(3, 20, seed=1)
+    s2.cam_fixed[:] = 1
+    assert "fixed" in _expect(balib, balib.BA_EINVAL,
+                              lambda: balib.Problem(balib.scene_desc(s2), balib.options()))
+
+
+def test_options_validation(balib):
+    s = make_arc_scene(3, 20, seed=1)
+    for kw in [dict(max_iters=0), dict(pcg_max_iters=0), dict(lambda0=0.0),
+               dict(pcg_rel_tol=-1.0), dict(precision=7), dict(huber_delta=np.inf)]:
+        _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(balib.scene_desc(s), balib.options(**kw)))
+
+
+def test_pose_batch_validation(balib):
+    reqs = make_config4_requests(2, seed=1004)
+    reqs[1].X = reqs[1].X.copy()
+    reqs[1].X[0, 0] = np.nan
+    _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch(reqs))
+    r = make_config4_requests(1, seed=1004)[0]
+    r.X = np.zeros((balib.POSE_MAX_CORR + 1, 3))
+    r.uv = np.zeros((balib.POSE_MAX_CORR + 1, 2))
+    _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch([r]))
+
+
+def test_server_create_validation(balib):
+    _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1024, 4))
+    _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1 << 30, 0))
+    _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1 << 30, 4, precision=9))

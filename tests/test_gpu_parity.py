@@ -1,0 +1,173 @@
+"""Device path vs the FP64 oracle, through the C-ABI.  Needs an MI355X."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ba_oracle as O
+from synth import (make_arc_scene, make_config0, make_config1, make_config4_requests,
+                   make_small_drive)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solve(balib, scene, **kw):
+    _say("device solve:", scene.name, scene.n_cams, scene.n_pts, scene.n_obs, kw)
+    p = balib.Problem.from_scene(scene, **kw)
+    res = p.solve().result()
+    p.close()
+    return res
+
+
+def _oracle_state(scene, res):
+    p = O.Problem.from_scene(scene)
+    return p, O.quat_to_rot(res["q"]), res["t"], res["X"]
+
+
+def test_config0_f64_per_iteration_cost_matches_dense_oracle(balib):
+    """Tiny problem, FP64 build, 20 LM iterations: every C_n within 1e-9 relative
+    of the dense normal-equation oracle."""
+    s = make_config0()
+    ref = O.lm_dense(O.Problem.from_scene(s), O.LMOptions(max_iters=20))
+    res = _solve(balib, s, max_iters=20, pcg_max_iters=200, pcg_rel_tol=1e-14, precision="f64")
+    assert res["iters"] == 20 and len(res["iter_cost"]) == 21
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("max rel cost diff", rel.max())
+    assert rel.max() <= 1e-9
+    # final state: the oracle's cost at the device's state equals the device's cost
+    p, R, t, X = _oracle_state(s, res)
+    assert abs(O.cost(p, R, t, X) - res["cost"]) <= 1e-9 * res["cost"]
+    assert res["status"] == ref.status
+
+
+def test_small_drive_f64_matches_schur_oracle_across_tiles(balib):
+    """Sequential drive with 12 point tiles and a ragged tail, FP64: per-iteration
+    cost within 1e-9 of the explicit-Schur oracle solved exactly."""
+    s = make_small_drive(40, 3000, seed=5)
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=8, solve="exact"))
+    res = _solve(balib, s, max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64")
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("max rel cost diff", rel.max(), res["pcg_iters"])
+    assert rel.max() <= 1e-9
+
+
+def test_small_drive_pcg_schedule_f64_matches_oracle_pcg(balib):
+    """Same schedule on both sides (PCG capped at 50, tol 1e-6): FP64 device vs
+    FP64 oracle PCG, per-iteration cost and PCG iteration counts."""
+    s = make_small_drive(60, 2500, seed=8)
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=6, solve="pcg",
+                                                          pcg_max_iters=50, pcg_rel_tol=1e-6))
+    res = _solve(balib, s, max_iters=6, pcg_max_iters=50, pcg_rel_tol=1e-6, precision="f64")
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("pcg iters device", res["pcg_iters"], "oracle", ref.pcg_iters, "rel", rel.max())
+    assert rel.max() <= 1e-9
+    assert list(res["pcg_iters"]) == list(ref.pcg_iters)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16j", "bf16j"])
+def test_small_drive_mixed_precision_final_rms(balib, prec):
+    """FP32 linearisation / Schur / SpMV (optionally 16-bit Jacobian storage)
+    with FP64 reductions: final RMS within 1e-3 px of the FP64 oracle run with the
+    same schedule; both RMS values recomputed by the oracle from the states."""
+    s = make_small_drive(50, 4000, seed=9)
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=10, solve="pcg",
+                                                          pcg_max_iters=50, pcg_rel_tol=1e-6))
+    res = _solve(balib, s, max_iters=10, precision=prec)
+    p, R, t, X = _oracle_state(s, res)
+    rms_dev = O.rms(p, R, t, X)
+    rms_ref = O.rms(p, ref.R, ref.t, ref.X)
+    _say(prec, "rms device", rms_dev, "oracle", rms_ref, "reported", res["rms_px"])
+    assert abs(rms_dev - rms_ref) <= 1e-3
+    assert abs(res["rms_px"] - rms_dev) <= 1e-4
+    assert all(b <= a for a, b in zip(res["iter_cost"], res["iter_cost"][1:]))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16j"])
+def test_huber_outliers_final_rms(balib, prec):
+    """5 % outliers, Huber delta 1 px: inlier RMS within 1e-3 px of the oracle."""
+    s = make_small_drive(40, 3000, seed=13, outlier_frac=0.05, huber_delta=1.0)
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=10, solve="pcg",
+                                                          pcg_max_iters=50, pcg_rel_tol=1e-6))
+    res = _solve(balib, s, max_iters=10, precision=prec)
+    p, R, t, X = _oracle_state(s, res)
+    a = O.rms(p, R, t, X, inlier_px=3.0)
+    b = O.rms(p, ref.R, ref.t, ref.X, inlier_px=3.0)
+    _say(prec, "inlier rms", a, b)
+    assert abs(a - b) <= 1e-3
+    assert abs(O.cost(p, R, t, X) - ref.iter_cost[-1]) <= 1e-4 * ref.iter_cost[-1]
+
+
+def test_edge_cases_single_tile_fixed_cameras_one_obs_points(balib):
+    """Several fixed cameras, a point with a single observation, a free camera
+    with no observations, a problem smaller than one tile: FP64 per-iteration
+    cost within 1e-9 of the dense oracle."""
+    s = make_arc_scene(6, 120, seed=31, sigma=0.5)
+    s.cam_fixed[:] = 0
+    s.cam_fixed[[0, 3]] = 1
+    # camera 5 loses every observation; point 7 keeps only one
+    keep = s.obs_cam != 5
+    pt7 = np.nonzero((s.obs_pt == 7) & keep)[0]
+    keep[pt7[1:]] = False
+    for f in ("obs_cam", "obs_pt", "obs_uv", "outlier"):
+        setattr(s, f, getattr(s, f)[keep])
+    ref = O.lm_dense(O.Problem.from_scene(s), O.LMOptions(max_iters=10))
+    res = _solve(balib, s, max_iters=10, pcg_max_iters=200, pcg_rel_tol=1e-14, precision="f64")
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("edge rel", rel.max())
+    assert rel.max() <= 1e-9
+    # the camera without observations stays where it was
+    q0 = s.q0[5] * np.sign(s.q0[5, 0])
+    assert np.allclose(res["q"][5], q0, atol=1e-12) and np.allclose(res["t"][5], s.t0[5], atol=1e-12)
+
+
+def test_point_behind_camera_is_masked(balib):
+    s = make_arc_scene(4, 60, seed=17)
+    s.X0 = s.X0.copy()
+    s.X0[0] = [0.0, 0.0, -30.0]
+    ref = O.lm_dense(O.Problem.from_scene(s), O.LMOptions(max_iters=3))
+    res = _solve(balib, s, max_iters=3, pcg_max_iters=200, pcg_rel_tol=1e-14, precision="f64")
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    assert rel.max() <= 1e-9
+    assert res["n_masked"] >= 1
+
+
+def test_pose_only_batch_matches_oracle(balib):
+    """Mixed-size pose-only requests in one launch vs the FP64 pose GN oracle."""
+    reqs = make_config4_requests(64, seed=1004)
+    _say("pose batch", len(reqs), sum(len(r.X) for r in reqs))
+    out = balib.pose_batch(reqs, iters=10, huber_delta=1.0)
+    errs = []
+    for i, q in enumerate(reqs):
+        R, t, st, costs = O.pose_only_gn(q.K, q.q0, q.t0, q.X, q.uv, 1.0, 10)
+        Rd = O.quat_to_rot(out["q"][i])
+        c_dev = -Rd.T @ out["t"][i]
+        c_ref = -R.T @ t
+        errs.append(np.linalg.norm(c_dev - c_ref))
+        assert out["status"][i] == st
+        assert abs(out["cost"][i] - costs[-1]) <= 1e-4 * costs[-1] + 1e-6
+    _say("max centre difference (m)", max(errs))
+    assert max(errs) <= 1e-4
+
+
+def test_config1_full_size_sampled(balib):
+    """The 2M-observation drive in the benchmark's configuration (FP32, 10 LM
+    iterations, PCG 50 / 1e-6): initial cost and final RMS recomputed by the
+    oracle from the same arrays / from the device's final state."""
+    s = make_config1()
+    res = _solve(balib, s, max_iters=10, precision="f32")
+    p = O.Problem.from_scene(s)
+    c0 = O.cost(p)
+    _say("cost0 device", res["cost0"], "oracle", c0)
+    assert abs(res["cost0"] - c0) <= 1e-5 * c0
+    p, R, t, X = _oracle_state(s, res)
+    rms = O.rms(p, R, t, X)
+    _say("final rms device", res["rms_px"], "oracle at device state", rms, "iters", res["pcg_iters"])
+    assert abs(res["rms_px"] - rms) <= 1e-4
+    assert all(b <= a for a, b in zip(res["iter_cost"], res["iter_cost"][1:]))
+    assert res["cost"] < 0.5 * res["cost0"]
