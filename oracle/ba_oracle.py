@@ -354,7 +354,8 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
     decrease is positive; on accept lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
     on reject lambda *= nu, nu *= 2; lambda clamped to [1e-12, 1e16].  The iteration
     count is fixed (no early stop); a run that ends with lambda at its upper clamp
-    reports STATUS_DAMPING."""
+    reports STATUS_DAMPING.  A direct solver that finds the damped system not
+    positive definite makes that iteration a rejected step."""
     p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy())
     lam = opts.lambda0
     nu = 2.0
@@ -367,6 +368,17 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
         H, g = lin[0], lin[1]
         D = damping_diag(H.diagonal())
         delta, pcg_it = solve_step(p, H, g, D, lam, opts)
+        if delta is None:
+            # the damped system is not numerically positive definite (possible only
+            # at the smallest damping, along the scale gauge): a rejected step
+            out.lambdas.append(lam)
+            out.rhos.append(float("nan"))
+            out.pcg_iters.append(pcg_it)
+            out.accepted.append(False)
+            lam = min(max(lam * nu, LAMBDA_MIN), LAMBDA_MAX)
+            nu = 2.0 * nu
+            out.iter_cost.append(C)
+            continue
         dL = 0.5 * float(delta @ (lam * D * delta - g))
         nf = int((~p.fixed).sum())
         Rn, tn, Xn = apply_step(p, delta[:6 * nf], delta[6 * nf:])
@@ -399,7 +411,10 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
 def _dense_step(p, H, g, D, lam, opts):
     A = H.toarray()
     A[np.diag_indices_from(A)] += lam * D
-    c = scipy.linalg.cho_factor(A, lower=True)
+    try:
+        c = scipy.linalg.cho_factor(A, lower=True)
+    except np.linalg.LinAlgError:
+        return None, 0
     return scipy.linalg.cho_solve(c, -g), 0
 
 
@@ -487,7 +502,10 @@ def _schur_step(p, H, g, D, lam, opts):
     ncam = 6 * nf
     S, b, Vinv, W = schur_blocks(H, g, D, lam, ncam)
     if opts.solve == "exact":
-        c = scipy.linalg.cho_factor(S, lower=True)
+        try:
+            c = scipy.linalg.cho_factor(S, lower=True)
+        except np.linalg.LinAlgError:
+            return None, 0
         dc = scipy.linalg.cho_solve(c, b)
         it = 0
     else:

@@ -88,17 +88,33 @@ def test_small_drive_mixed_precision_final_rms(balib, prec):
     assert all(b <= a for a, b in zip(res["iter_cost"], res["iter_cost"][1:]))
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16j"])
-def test_huber_outliers_final_rms(balib, prec):
-    """5 % outliers, Huber delta 1 px: inlier RMS within 1e-3 px of the oracle."""
+def test_huber_outliers_f64_per_iteration_cost(balib):
+    """Huber delta 1 px with 5 % uniform outliers, FP64: per-iteration cost within
+    1e-9 of the Schur oracle solved exactly (IRLS weights, robust cost, gain ratio)."""
     s = make_small_drive(40, 3000, seed=13, outlier_frac=0.05, huber_delta=1.0)
-    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=10, solve="pcg",
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=10, solve="exact"))
+    res = _solve(balib, s, max_iters=10, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64")
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("huber f64 rel", rel.max())
+    assert rel.max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16j", "bf16j"])
+def test_huber_outliers_final_rms(balib, prec):
+    """5 % outliers, Huber delta 1 px, mixed precision, 20 iterations on a scene
+    where the robust problem converges: inlier RMS within 1e-3 px of the FP64
+    oracle with the same schedule.  (On the drifted drives the robust problem is
+    still moving after 40 iterations and some points cross behind a camera, so
+    the end point depends on the accept/reject path; the FP64 test above pins the
+    robust path iterate by iterate instead.)"""
+    s = make_arc_scene(10, 1000, seed=41, sigma=0.5, outlier_frac=0.05, huber_delta=1.0)
+    ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=20, solve="pcg",
                                                           pcg_max_iters=50, pcg_rel_tol=1e-6))
-    res = _solve(balib, s, max_iters=10, precision=prec)
+    res = _solve(balib, s, max_iters=20, precision=prec)
     p, R, t, X = _oracle_state(s, res)
     a = O.rms(p, R, t, X, inlier_px=3.0)
     b = O.rms(p, ref.R, ref.t, ref.X, inlier_px=3.0)
-    _say(prec, "inlier rms", a, b)
+    _say(prec, "inlier rms", a, b, "masked", res["n_masked"])
     assert abs(a - b) <= 1e-3
     assert abs(O.cost(p, R, t, X) - ref.iter_cost[-1]) <= 1e-4 * ref.iter_cost[-1]
 
