@@ -136,6 +136,8 @@ def main():
         r = prob.report()
         dev_ms.append(r["solve_ms"])
         ms, nl = prob.kernel_times()[dominant]
+        print(f"bench: step {r['iters']} iters, {r['solve_ms']:.3f} ms device, {dominant} "
+              f"{ms:.3f} ms over {nl} launches", flush=True, file=sys.stderr)
         dom_ms += ms
         dom_launch += nl
     wall = time.perf_counter() - t0

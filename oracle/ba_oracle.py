@@ -220,9 +220,14 @@ def residuals(p: Problem, R=None, t=None, X=None):
 
 def cost(p: Problem, R=None, t=None, X=None) -> float:
     """C = 1/2 sum_k rho(||r_k||^2) over valid observations."""
+    return cost_and_masked(p, R, t, X)[0]
+
+
+def cost_and_masked(p: Problem, R=None, t=None, X=None):
+    """(C, number of masked observations) at a state."""
     r, valid, _ = residuals(p, R, t, X)
     s = np.sum(r * r, axis=1)
-    return 0.5 * float(np.sum(huber_rho(s, p.delta)[valid]))
+    return 0.5 * float(np.sum(huber_rho(s, p.delta)[valid])), int((~valid).sum())
 
 
 def rms(p: Problem, R=None, t=None, X=None, inlier_px: float | None = None) -> float:
@@ -351,7 +356,9 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
     """Levenberg-Marquardt (Madsen-Nielsen-Tingleff 2004, Alg. 3.16 with Marquardt
     scaling).  One iteration = one (possibly reused) linearisation, one damped
     solve, one trial cost.  Accept iff gain ratio > 1e-3 and the predicted
-    decrease is positive; on accept lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
+    decrease is positive and the trial state masks no more observations (depth
+    <= Z_MIN) than the current one -- a step may not lower the cost by pushing
+    points behind their cameras; on accept lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
     on reject lambda *= nu, nu *= 2; lambda clamped to [1e-12, 1e16].  The iteration
     count is fixed (no early stop); a run that ends with lambda at its upper clamp
     reports STATUS_DAMPING.  A direct solver that finds the damped system not
@@ -359,7 +366,7 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
     p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy())
     lam = opts.lambda0
     nu = 2.0
-    C = cost(p)
+    C, masked = cost_and_masked(p)
     out = LMResult(p.R, p.t, p.X, [C], [], [], [], [], STATUS_OK)
     lin = None
     for _ in range(opts.max_iters):
@@ -382,14 +389,15 @@ def _lm_loop(p: Problem, opts: LMOptions, solve_step):
         dL = 0.5 * float(delta @ (lam * D * delta - g))
         nf = int((~p.fixed).sum())
         Rn, tn, Xn = apply_step(p, delta[:6 * nf], delta[6 * nf:])
-        Cn = cost(p, Rn, tn, Xn)
+        Cn, masked_n = cost_and_masked(p, Rn, tn, Xn)
         rho = (C - Cn) / dL if dL != 0 else -np.inf
         out.lambdas.append(lam)
         out.rhos.append(rho)
         out.pcg_iters.append(pcg_it)
-        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO:
+        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO and masked_n <= masked:
             p.R, p.t, p.X = Rn, tn, Xn
             C = Cn
+            masked = masked_n
             lam = lam * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
             nu = 2.0
             lin = None

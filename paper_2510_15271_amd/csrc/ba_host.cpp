@@ -343,6 +343,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_masked = L.take(npt * 4);
   o.part_sq = L.take(npt * 8);
   o.part_trial_cost = L.take(npt * 8);
+  o.part_trial_masked = L.take(npt * 4);
   o.part_dl_pt = L.take(npt * 8);
   o.part_dl_cam = L.take(ncam * 8);
   o.part_rz0 = L.take(Cf * 8);
@@ -434,6 +435,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_masked = (int32_t *)ptr(off.part_masked);
   pd.part_sq = (double *)ptr(off.part_sq);
   pd.part_trial_cost = (double *)ptr(off.part_trial_cost);
+  pd.part_trial_masked = (int32_t *)ptr(off.part_trial_masked);
   pd.part_dl_pt = (double *)ptr(off.part_dl_pt);
   pd.part_dl_cam = (double *)ptr(off.part_dl_cam);
   pd.part_rz0 = (double *)ptr(off.part_rz0);

@@ -15,7 +15,7 @@ namespace bax {
 
 constexpr int kPtTile = 256;     // points per point-major tile (one workgroup)
 constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile
-constexpr int kPcgRows = 16;     // reduced-camera-system rows per PCG tile
+constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile (one wave each)
 constexpr int kCamTile = 256;    // cameras per camera-update tile
 constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
 constexpr int kPoseThreads = 256;
@@ -87,6 +87,7 @@ struct ProbDev {
   int32_t *part_masked;           // [n_pt_tiles]
   double *part_sq;                // [n_pt_tiles]
   double *part_trial_cost;        // [n_pt_tiles]
+  int32_t *part_trial_masked;     // [n_pt_tiles]
   double *part_dl_pt;             // [n_pt_tiles]
   double *part_dl_cam;            // [n_cam_tiles]
   double *part_rz0;               // [Cf]

@@ -660,8 +660,8 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 }
 
 // ------------------------------------------------------------------ PCG
-// Tile = kPcgRows consecutive rows of one problem; four waves, a row per wave
-// at a time.  Iteration it (0-based):
+// Tile = kPcgRows (= 4) consecutive rows of one problem, one wave per row.
+// Iteration it (0-based):
 //   spmv(it):   it >= 1: stop if ||r_it|| <= tol ||b||; beta = rz_it / rz_{it-1};
 //               p_it = z + beta p_{it-1} (formed on the fly for every column read);
 //               q = S p_it; partial p_it . q.
@@ -716,19 +716,27 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ pr
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / 6, i = lane % 6;
   double pq = 0.0;
-  const int rbeg = tl.idx * kPcgRows;
-  const int rend = min(pd.Cf, rbeg + kPcgRows);
-  for (int a = rbeg + w; a < rend; a += 4) {
+  const int a = tl.idx * kPcgRows + w;  // one wave per row
+  if (a < pd.Cf) {
     T acc = T(0);
     if (lane < 60) {
-      for (int blk = pd.S_rowptr[a] + g; blk < pd.S_rowptr[a + 1]; blk += 10) {
+      const int b1 = pd.S_rowptr[a + 1];
+#pragma unroll 2
+      for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
         const int c = pd.S_col[blk];
         const T *Srow = S + 36 * (size_t)blk + 6 * i;
+        T sv[6], pc[6];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          const T pc = (it == 0) ? pin[6 * c + m] : z[6 * c + m] + tb * pold[6 * c + m];
-          acc += Srow[m] * pc;
+        for (int m = 0; m < 6; ++m) sv[m] = Srow[m];
+        if (it == 0) {
+#pragma unroll
+          for (int m = 0; m < 6; ++m) pc[m] = pin[6 * c + m];
+        } else {
+#pragma unroll
+          for (int m = 0; m < 6; ++m) pc[m] = z[6 * c + m] + tb * pold[6 * c + m];
         }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc += sv[m] * pc[m];
       }
     }
     // lanes 6g + i hold partial sums of output i; gather them in a fixed order
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ pr
       const T pa = (it == 0) ? pin[6 * a + lane] : z[6 * a + lane] + tb * pold[6 * a + lane];
       q[6 * a + lane] = qi;
       if (it > 0) pout[6 * a + lane] = pa;
-      pq += (double)pa * (double)qi;
+      pq = (double)pa * (double)qi;
     }
   }
   const double tot = block_sum256(pq, s_pq);
@@ -773,7 +781,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ 
   const int rbeg = tl.idx * kPcgRows;
   const int rend = min(pd.Cf, rbeg + kPcgRows);
   double rzp = 0.0, rrp = 0.0;
-  // one thread per row element: 6 * kPcgRows <= 256
+  // one thread per row element (6 * kPcgRows of them)
   const int e = threadIdx.x;
   const int a = rbeg + e / 6;
   __shared__ T s_r[kPcgRows * 6];
@@ -938,6 +946,7 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
   const T *uv = (const T *)pd.obs_uv;
   const double *poses = pd.pose[1 - cur];
   double cost = 0.0;
+  int masked = 0;
   for (int k = k0 + threadIdx.x; k < k1; k += 256) {
     const int jl = pd.obs_pt[k] - j0;
     const int cam = pd.obs_cam[k];
@@ -946,18 +955,23 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
     T r0, r1;
     if (residual<T>(Kall + 4 * cam, T(xd), T(yd), T(zd), uv[2 * (size_t)k], uv[2 * (size_t)k + 1], r0, r1))
       cost += 0.5 * (double)huber_rho(r0 * r0 + r1 * r1, delta);
+    else
+      ++masked;
   }
   const double tc = block_sum256(cost, s_red);
   const double td = block_sum256(dl, s_red);
+  const double tm = block_sum256((double)masked, s_red);
   if (threadIdx.x == 0) {
     pd.part_trial_cost[tl.idx] = tc;
     pd.part_dl_pt[tl.idx] = td;
+    pd.part_trial_masked[tl.idx] = (int32_t)tm;
   }
 }
 
 // ------------------------------------------------------------------ LM control
 // One workgroup per problem.  Madsen-Nielsen-Tingleff damping: accept iff the
-// gain ratio exceeds 1e-3 and the predicted decrease is positive; on accept
+// gain ratio exceeds 1e-3, the predicted decrease is positive and the step puts
+// no further observation behind its camera; on accept
 // lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; on reject lambda *= nu, nu *= 2.
 __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ probs,
                                                     const Tile *__restrict__ tiles) {
@@ -970,11 +984,19 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   const double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
   const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
   const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
+  double m0 = 0.0, mt = 0.0;
+  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
+    m0 += (double)pd.part_masked[i];
+    mt += (double)pd.part_trial_masked[i];
+  }
+  m0 = block_sum256(m0, s_red);
+  mt = block_sum256(mt, s_red);
   if (threadIdx.x != 0) return;
   const int n = st->iter;
   if (!st->init_done) {
     st->cost = c0;
     st->cost0 = c0;
+    st->n_masked = (int32_t)m0;
     st->init_done = 1;
     pd.iter_cost[0] = c0;
   }
@@ -986,8 +1008,11 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   st->rho = rho;
   double lam = st->lambda;
   pd.iter_pcg[n] = st->pcg_done ? st->pcg_iters : st->pcg_max;
-  if (isfinite(tc) && dL > 0.0 && rho > kAcceptRho) {
+  // a step that puts more observations behind their cameras is rejected
+  const bool more_masked = (int32_t)mt > st->n_masked;
+  if (isfinite(tc) && dL > 0.0 && rho > kAcceptRho && !more_masked) {
     st->cost = tc;
+    st->n_masked = (int32_t)mt;
     st->cur = 1 - st->cur;
     const double t = 2.0 * rho - 1.0;
     lam *= fmax(1.0 / 3.0, 1.0 - t * t * t);
