@@ -72,8 +72,13 @@ typedef struct {
   double lambda0;         /* initial LM damping, > 0                                      */
   double huber_delta;     /* <= 0: plain least squares; > 0: Huber threshold in pixels    */
   int32_t precision;      /* BA_PREC_*                                                    */
-  int32_t reserved;       /* must be 0                                                    */
+  int32_t flags;          /* BA_FLAG_* bits, 0 for the defaults                           */
 } ba_options;
+
+/* ba_options.flags: run PCG as two launches per iteration instead of one
+   cooperative launch with grid barriers (the default when the device supports
+   cooperative launches). */
+#define BA_FLAG_PCG_LAUNCHES 1
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */

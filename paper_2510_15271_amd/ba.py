@@ -36,7 +36,7 @@ class Pose(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("pcg_max_iters", C.c_int32),
                 ("pcg_rel_tol", C.c_double), ("lambda0", C.c_double),
-                ("huber_delta", C.c_double), ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("huber_delta", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -121,8 +121,11 @@ def _check(rc):
         raise BAError(rc, lib().ba_last_error().decode())
 
 
+FLAG_PCG_LAUNCHES = 1
+
+
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,
-            precision="f32") -> Options:
+            precision="f32", flags=0) -> Options:
     o = Options()
     lib().ba_default_options(C.byref(o))
     o.max_iters = max_iters
@@ -131,6 +134,7 @@ def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, hube
     o.lambda0 = lambda0
     o.huber_delta = huber_delta
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    o.flags = int(flags)
     return o
 
 

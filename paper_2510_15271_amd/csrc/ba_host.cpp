@@ -115,7 +115,7 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->reserved != 0) return fail(BA_EINVAL, "reserved option field must be 0");
+  if (o->flags & ~BA_FLAG_PCG_LAUNCHES) return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   return BA_OK;
 }
 
@@ -589,8 +589,10 @@ void EventTimer::begin(int id, hipStream_t s) {
   ids.push_back(id);
 }
 void EventTimer::end(int, hipStream_t s) {
+  if (!active) return;
   (void)hipEventRecord(pool[used].second, s);
   ++used;
+  active = false;
 }
 void EventTimer::reset() {
   used = 0;
@@ -634,6 +636,7 @@ struct ba_problem {
   bool pending = false;
   bool solved = false;
   bool profiling = false;
+  bool persistent_pcg = true;
   EventTimer timer;  // times the kernels selected by timer.mask
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
@@ -663,6 +666,7 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   std::unique_ptr<ba_problem> p(new ba_problem());
   if (int e = analyse(d, opt, p->sy)) return e;
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
+  p->persistent_pcg = (opt->flags & BA_FLAG_PCG_LAUNCHES) == 0;
   if (hip_stream) {
     p->stream = (hipStream_t)hip_stream;
   } else {
@@ -713,7 +717,8 @@ int ba_solve_async(ba_problem *p) {
   p->timer.reset();
   (void)hipEventRecord(p->ev0, p->stream);
   for (int it = 0; it < p->dp.max_iters; ++it) {
-    e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm);
+    e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm,
+                            p->persistent_pcg);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   (void)hipEventRecord(p->ev1, p->stream);

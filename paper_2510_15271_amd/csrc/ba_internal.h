@@ -126,7 +126,7 @@ struct KernelTimer {
 
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
-  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_NUM_KERNELS
+  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_PERSISTENT, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -135,9 +135,11 @@ size_t lin_record_bytes(int precision);
 // Size of the compute type (8 or 4).
 size_t compute_bytes(int precision);
 
-// Launch one Levenberg-Marquardt iteration for every problem of the plan.
+// Launch one Levenberg-Marquardt iteration for every problem of the plan.  With
+// persistent_pcg the PCG loop is one cooperative launch with grid barriers,
+// otherwise two launches per PCG iteration.
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
-                               KernelTimer *timer);
+                               KernelTimer *timer, bool persistent_pcg);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
 // Pose-only Gauss-Newton, one workgroup per request.

@@ -25,8 +25,10 @@
 // Every reduction is deterministic: a fixed assignment of work to lanes and a
 // fixed summation order, so a problem's result is the same whichever other
 // problems share its launches.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ba_internal.h"
@@ -35,7 +37,7 @@ namespace bax {
 
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
-    "cam_update", "point_trial", "lm_control", "eval", "pose_gn"};
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_persistent"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -667,15 +669,27 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 //               q = S p_it; partial p_it . q.
 //   update(it): alpha = rz_it / (p.q); x += alpha p; r -= alpha q; z = M^-1 r;
 //               partials r.z and r.r.
+// The tile bodies are shared by the two-kernels-per-iteration form and the
+// persistent cooperative form.  A tile reads the problem's PCG flags once, by one
+// thread, and broadcasts them through LDS: another tile of the same problem may
+// set them while this one runs, and every thread must take the same branch.
+
+__device__ inline bool pcg_go(const LMState *st, int it, int *s_flag) {
+  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
+  __syncthreads();
+  const bool go = s_flag[0] != 0;
+  __syncthreads();
+  return go;
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ probs,
-                                                  const Tile *__restrict__ tiles, int it) {
-  const Tile tl = tiles[blockIdx.x];
+__device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
-  if (!lm_active(st) || st->pcg_done || it >= st->pcg_max) return;
+  __shared__ int s_flag[1];
   __shared__ double s_red[4];
   __shared__ double s_pq[4];
+  if (!pcg_go(st, it, s_flag)) return;
   double beta = 0.0;
   if (it == 0) {
     const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
@@ -755,13 +769,14 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ pr
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ probs,
-                                                    const Tile *__restrict__ tiles, int it) {
-  const Tile tl = tiles[blockIdx.x];
+__device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
-  if (!lm_active(st) || st->pcg_done || it >= st->pcg_max) return;
+  __shared__ int s_flag[1];
   __shared__ double s_red[4];
+  __shared__ double s_red2[4];
+  __shared__ T s_r[kPcgRows * 6];
+  if (!pcg_go(st, it, s_flag)) return;
   const double pq = block_sum_array(pd.part_pq, pd.n_pcg_tiles, s_red);
   if (!(pq > 0.0)) {  // breakdown: keep x, stop
     if (tl.idx == 0 && threadIdx.x == 0) {
@@ -784,7 +799,6 @@ __global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ 
   // one thread per row element (6 * kPcgRows of them)
   const int e = threadIdx.x;
   const int a = rbeg + e / 6;
-  __shared__ T s_r[kPcgRows * 6];
   if (e < 6 * kPcgRows && a < rend) {
     const size_t idx = 6 * (size_t)a + (e % 6);
     x[idx] = x[idx] + ta * p[idx];
@@ -805,12 +819,63 @@ __global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ 
     rzp = (double)rr[i] * (double)zt;
     rrp = (double)rr[i] * (double)rr[i];
   }
-  __shared__ double s_red2[4];
   const double trz = block_sum256(rzp, s_red);
   const double trr = block_sum256(rrp, s_red2);
   if (threadIdx.x == 0) {
     pd.part_rz[(it + 1) & 1][tl.idx] = trz;
     pd.part_rr[tl.idx] = trr;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
+  pcg_spmv_tile<T>(probs, tiles[blockIdx.x], it);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles, int it) {
+  pcg_update_tile<T>(probs, tiles[blockIdx.x], it);
+}
+
+// Whether a problem's PCG has nothing left to do after update(it).  Decided from
+// values no tile changes between the grid barrier after update(it) and this
+// check, except pcg_done, which spmv(it + 1) may set -- and only when the
+// residual test below already holds -- so every workgroup decides alike.
+__device__ inline bool pcg_finished(const ProbDev &pd, int it, double *s_red, int *s_flag) {
+  const LMState *st = pd.st;
+  if (threadIdx.x == 0) s_flag[0] = (!lm_active(st) || it + 1 >= st->pcg_max || st->pcg_done) ? 1 : 0;
+  __syncthreads();
+  const bool stop = s_flag[0] != 0;
+  __syncthreads();
+  if (stop) return true;
+  const double rr = block_sum_array(pd.part_rr, pd.n_pcg_tiles, s_red);
+  return sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb);
+}
+
+// Every PCG iteration of every problem of the batch in one cooperative launch:
+// grid barriers replace the kernel boundaries between the two phases.
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_persistent(const ProbDev *__restrict__ probs,
+                                                        const Tile *__restrict__ tiles, int n_tiles,
+                                                        int n_probs, int pcg_max) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ double s_red[4];
+  __shared__ int s_flag[1];
+  __shared__ int s_all;
+  for (int it = 0; it < pcg_max; ++it) {
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) pcg_spmv_tile<T>(probs, tiles[t], it);
+    grid.sync();
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) pcg_update_tile<T>(probs, tiles[t], it);
+    grid.sync();
+    int all = 1;
+    for (int pi = 0; pi < n_probs && all; ++pi) all = pcg_finished(probs[pi], it, s_red, s_flag) ? 1 : 0;
+    if (threadIdx.x == 0) s_all = all;
+    __syncthreads();
+    const bool done = s_all != 0;
+    __syncthreads();
+    if (done) break;
   }
 }
 
@@ -1208,7 +1273,8 @@ struct Timed {
 }  // namespace
 
 template <class T, class S>
-static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, KernelTimer *tm) {
+static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int pcg_grid, hipStream_t s,
+                               KernelTimer *tm) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
@@ -1225,14 +1291,25 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, 
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
-  for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
-    {
-      Timed t(tm, K_PCG_SPMV, s);
-      k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
-    }
-    {
-      Timed t(tm, K_PCG_UPDATE, s);
-      k_pcg_update<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+  if (bp.n_pcg && pcg_grid > 0) {
+    Timed t(tm, K_PCG_PERSISTENT, s);
+    const ProbDev *probs = bp.probs;
+    const Tile *tiles = bp.pcg;
+    int n_tiles = bp.n_pcg, n_probs = bp.n_ctl, pm = pcg_max;
+    void *args[] = {(void *)&probs, (void *)&tiles, (void *)&n_tiles, (void *)&n_probs, (void *)&pm};
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_pcg_persistent<T>, dim3(pcg_grid), dim3(256),
+                                              args, 0, s);
+    if (e != hipSuccess) return e;
+  } else {
+    for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
+      {
+        Timed t(tm, K_PCG_SPMV, s);
+        k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+      }
+      {
+        Timed t(tm, K_PCG_UPDATE, s);
+        k_pcg_update<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+      }
     }
   }
   if (bp.n_cam) {
@@ -1250,13 +1327,35 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, 
   return hipGetLastError();
 }
 
+// Workgroups of the persistent PCG launch: every tile's workgroup must be
+// resident at once for the grid barrier, so the grid is capped by the occupancy
+// of the kernel on this device (0 = use the two-kernel form).
+int pcg_persistent_grid(int precision, int n_tiles) {
+  static int cap[2] = {-1, -1};
+  const int k = precision == 0 ? 0 : 1;
+  if (cap[k] < 0) {
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+      cap[k] = 0;
+    } else {
+      hipError_t e = k == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_persistent<double>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_persistent<float>, 256, 0);
+      cap[k] = (e == hipSuccess && per_cu > 0) ? cus * std::min(per_cu, 2) : 0;
+    }
+  }
+  return std::min(cap[k], n_tiles);
+}
+
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
-                               KernelTimer *timer) {
+                               KernelTimer *timer, bool persistent_pcg) {
+  const int grid = persistent_pcg ? pcg_persistent_grid(precision, bp.n_pcg) : 0;
   switch (precision) {
-    case 0: return lm_iteration<double, double>(bp, pcg_max, s, timer);
-    case 1: return lm_iteration<float, float>(bp, pcg_max, s, timer);
-    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, s, timer);
-    default: return lm_iteration<float, bf16s>(bp, pcg_max, s, timer);
+    case 0: return lm_iteration<double, double>(bp, pcg_max, grid, s, timer);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, grid, s, timer);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, grid, s, timer);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, grid, s, timer);
   }
 }
 
