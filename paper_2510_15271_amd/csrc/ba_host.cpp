@@ -199,11 +199,15 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   }
   for (int a = 0; a < Cf; ++a) sy.cam_obs_start[a + 1] += sy.cam_obs_start[a];
   sy.cam_obs.resize(sy.cam_obs_start[Cf]);
+  sy.obs_cpos.assign(N, -1);
   {
     std::vector<int32_t> f(sy.cam_obs_start.begin(), sy.cam_obs_start.end() - 1);
     for (int64_t k = 0; k < N; ++k) {
       const int a = sy.free_idx[sy.obs_cam[k]];
-      if (a >= 0) sy.cam_obs[f[a]++] = (int32_t)k;
+      if (a >= 0) {
+        sy.obs_cpos[k] = f[a];
+        sy.cam_obs[f[a]++] = (int32_t)k;
+      }
     }
   }
 
@@ -246,7 +250,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
         const int b = sy.free_idx[sy.obs_cam[kb]];
         if (b < 0) continue;
         const int t = slot[b] - base_blk;
-        sy.pairs[pfill[t]++] = int2{k, kb};
+        sy.pairs[pfill[t]++] = int2{o, sy.obs_cpos[kb]};  // camera-major slots
       }
     }
     for (int b : touched) {
@@ -316,6 +320,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.pt_start = L.take((P + 1) * 4);
   o.cam_obs = L.take(sy.cam_obs.size() * 4 + 4);
   o.cam_obs_start = L.take((Cf + 1) * 4);
+  o.obs_cpos = L.take(N * 4);
   o.up_pair_start = L.take((sy.n_up + 1) * 4);
   o.pairs = L.take(sy.pairs.size() * sizeof(int2) + 8);
   o.up_pos = L.take(sy.n_up * 4 + 4);
@@ -327,8 +332,9 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   for (int b = 0; b < 2; ++b) o.X[b] = L.take(P * 3 * 8);
   o.pose_init = L.take(C * 12 * 8);
   o.X_init = L.take(P * 3 * 8);
-  o.lin = L.take(N * lin_record_bytes(precision));
-  o.Y = L.take(N * 18 * T);
+  const size_t Nf = sy.cam_obs.size();
+  o.lin = L.take(Nf * lin_record_bytes(precision) + 16);
+  o.Y = L.take(Nf * 18 * T + 16);
   o.V = L.take(P * 6 * T);
   o.gp = L.take(P * 3 * T);
   o.Dp = L.take(P * 3 * T);
@@ -389,6 +395,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.Cf = Cf;
   pd.P = P;
   pd.N = N;
+  pd.Nf = (int32_t)sy.cam_obs.size();
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
@@ -403,6 +410,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.pt_start = (const int32_t *)ptr(off.pt_start);
   pd.cam_obs = (const int32_t *)ptr(off.cam_obs);
   pd.cam_obs_start = (const int32_t *)ptr(off.cam_obs_start);
+  pd.obs_cpos = (const int32_t *)ptr(off.obs_cpos);
   pd.up_pair_start = (const int32_t *)ptr(off.up_pair_start);
   pd.pairs = (const int2 *)ptr(off.pairs);
   pd.up_pos = (const int32_t *)ptr(off.up_pos);
@@ -483,6 +491,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.pt_start, sy.pt_start.data(), sy.pt_start.size() * 4));
   chk(up(off.cam_obs, sy.cam_obs.data(), sy.cam_obs.size() * 4));
   chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
+  chk(up(off.obs_cpos, sy.obs_cpos.data(), sy.obs_cpos.size() * 4));
   chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
   chk(up(off.pairs, sy.pairs.data(), sy.pairs.size() * sizeof(int2)));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));

@@ -50,10 +50,10 @@ struct LMState {
 // precision mode (double or float); S is the Jacobian storage type.
 struct ProbDev {
   int32_t C, Cf, P, N;
+  int32_t Nf;            // observations in free cameras
   int32_t n_up;          // upper off-diagonal blocks of S
   int32_t nnzb;          // blocks of S stored (both triangles + diagonal)
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
-  int32_t pad;
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -62,10 +62,11 @@ struct ProbDev {
   const int32_t *obs_pt;          // [N]
   const void *obs_uv;             // [N][2] T
   const int32_t *pt_start;        // [P + 1]
-  const int32_t *cam_obs;         // observation positions of free cameras, grouped by camera
-  const int32_t *cam_obs_start;   // [Cf + 1]
+  const int32_t *cam_obs;         // [Nf] point-major position of each camera-major slot
+  const int32_t *cam_obs_start;   // [Cf + 1] camera-major slots of each free camera
+  const int32_t *obs_cpos;        // [N] camera-major slot of each observation, -1 if its camera is fixed
   const int32_t *up_pair_start;   // [n_up + 1]
-  const int2 *pairs;              // (k_a, k_b): observations of one point in cameras a < b
+  const int2 *pairs;              // (c_a, c_b): camera-major slots of one point in cameras a < b
   const int32_t *up_pos;          // [n_up] block (a, b) in S
   const int32_t *up_tpos;         // [n_up] block (b, a) in S
   const int32_t *diag_pos;        // [Cf]
@@ -75,8 +76,8 @@ struct ProbDev {
   double *pose[2];                // [C][12]: R row-major, then t
   double *X[2];                   // [P][3]
   // linearisation and Schur complement
-  void *lin;                      // [N] LinRec<T, S>
-  void *Y;                        // [N][18] T: W_k V*_j^-1
+  void *lin;                      // [Nf] LinRec<T, S>, camera-major
+  void *Y;                        // [Nf][18] T: W_k V*_j^-1, camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
   void *S;                        // [nnzb][36] T

@@ -348,7 +348,8 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
         for (int i = 0; i < 18; ++i) rec.j[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
       }
-      lin[k] = rec;
+      const int cpos = pd.obs_cpos[k];  // records are kept for free cameras only
+      if (cpos >= 0) lin[cpos] = rec;
     }
     s_loc[threadIdx.x] = jl;
 #pragma unroll
@@ -420,8 +421,10 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
   const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
   T *Y = (T *)pd.Y;
   for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+    const int cpos = pd.obs_cpos[k];
+    if (cpos < 0) continue;  // fixed camera: no camera block, no Y
     const int jl = pd.obs_pt[k] - j0;
-    const LinRec<T, S> rec = lin[k];
+    const LinRec<T, S> rec = lin[cpos];
     T J[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
@@ -438,7 +441,7 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
       for (int m = 0; m < 3; ++m) y[3 * r + m] = w0 * M[m] + w1 * M[3 + m] + w2 * M[6 + m];
     }
 #pragma unroll
-    for (int i = 0; i < 18; ++i) Y[18 * (size_t)k + i] = y[i];
+    for (int i = 0; i < 18; ++i) Y[18 * (size_t)cpos + i] = y[i];
   }
 }
 
@@ -477,14 +480,14 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
   for (int o = o0 + threadIdx.x; o < o1; o += 256) {
     const int k = pd.cam_obs[o];
     const int j = pd.obs_pt[k];
-    const LinRec<T, S> rec = lin[k];
+    const LinRec<T, S> rec = lin[o];
     T J[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
     const T *Jc0 = J, *Jc1 = J + 6, *Jp0 = J + 12, *Jp1 = J + 15;
     T y[18];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)k + i];
+    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)o + i];
     // Z = Y J_p^T (6x2)
     T Z0[6], Z1[6];
 #pragma unroll
@@ -950,9 +953,10 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
     int jl = -1;
     if (k < k1) {
       jl = pd.obs_pt[k] - j0;
-      const int a = pd.free_idx[pd.obs_cam[k]];
-      if (a >= 0) {
-        const LinRec<T, S> rec = lin[k];
+      const int cpos = pd.obs_cpos[k];
+      if (cpos >= 0) {
+        const int a = pd.free_idx[pd.obs_cam[k]];
+        const LinRec<T, S> rec = lin[cpos];
         T J[18];
 #pragma unroll
         for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);

@@ -29,7 +29,7 @@ struct Symbolic {
   std::vector<int32_t> obs_cam, obs_pt;
   std::vector<double> obs_uv;
   std::vector<int32_t> pt_start;
-  std::vector<int32_t> cam_obs, cam_obs_start;
+  std::vector<int32_t> cam_obs, cam_obs_start, obs_cpos;
   std::vector<int32_t> up_pair_start;
   std::vector<int2> pairs;
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
@@ -37,7 +37,7 @@ struct Symbolic {
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 
 struct Offsets {
-  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start;
+  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_cpos;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   size_t pose[2], X[2], pose_init, X_init, lin, Y, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[6];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;

@@ -171,12 +171,22 @@ def test_pose_only_batch_matches_oracle(balib):
     assert max(errs) <= 1e-4
 
 
-def test_config1_full_size_sampled(balib):
+def test_config1_full_size_against_stored_oracle_run(balib):
     """The 2M-observation drive in the benchmark's configuration (FP32, 10 LM
-    iterations, PCG 50 / 1e-6): initial cost and final RMS recomputed by the
-    oracle from the same arrays / from the device's final state."""
+    iterations, PCG 50 / 1e-6) against the FP64 oracle's run of the same schedule
+    stored by tests/golden/make_config1_golden.py: final RMS within 1e-3 px,
+    every C_n within 1e-4 relative, same accept/reject pattern and PCG counts;
+    the initial cost and the final RMS are also recomputed by the oracle."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config1_oracle.json")))
     s = make_config1()
     res = _solve(balib, s, max_iters=10, precision="f32")
+    rel = np.abs(res["iter_cost"] - np.array(gold["iter_cost"])) / np.array(gold["iter_cost"])
+    _say("stored oracle rms", gold["final_rms_px"], "device", res["rms_px"], "max rel cost", rel.max())
+    assert abs(res["rms_px"] - gold["final_rms_px"]) <= 1e-3
+    assert rel.max() <= 1e-4
+    assert list(res["pcg_iters"]) == gold["pcg_iters"]
     p = O.Problem.from_scene(s)
     c0 = O.cost(p)
     _say("cost0 device", res["cost0"], "oracle", c0)
