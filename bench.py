@@ -92,8 +92,9 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16j", "bf16j"])
     ap.add_argument("--points", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pcg-launches", action="store_true",
-                    help="two launches per PCG iteration instead of the persistent cooperative kernel")
+    ap.add_argument("--pcg-persistent", action="store_true",
+                    help="one cooperative PCG launch per solve instead of two launches per iteration")
+    ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -111,7 +112,8 @@ def main():
     scene = make_config1(n_pts=args.points)
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
-                                 flags=ba.FLAG_PCG_LAUNCHES if args.pcg_launches else 0)
+                                 flags=(ba.FLAG_PCG_PERSISTENT if args.pcg_persistent else 0)
+                                 | (ba.FLAG_NO_GRAPH if args.no_graph else 0))
     info = prob.info()
     names = list(prob.kernel_times().keys())
 
@@ -182,7 +184,8 @@ def main():
                                f"{LM_ITERS} LM iterations, PCG 50 / 1e-6",
                    "n_obs": info["n_obs"], "n_pairs": info["n_pairs"],
                    "nnzb": info["nnzb"], "precision": args.precision,
-                   "pcg": "launches" if args.pcg_launches else "persistent"},
+                   "pcg": "persistent" if args.pcg_persistent else "launches",
+                   "graph": not args.no_graph},
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),
         "final_rms_px": r["rms_px"],

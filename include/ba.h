@@ -75,10 +75,15 @@ typedef struct {
   int32_t flags;          /* BA_FLAG_* bits, 0 for the defaults                           */
 } ba_options;
 
-/* ba_options.flags: run PCG as two launches per iteration instead of one
-   cooperative launch with grid barriers (the default when the device supports
-   cooperative launches). */
-#define BA_FLAG_PCG_LAUNCHES 1
+/* ba_options.flags bits.
+   BA_FLAG_PCG_PERSISTENT: run each PCG solve as one cooperative launch with grid
+   barriers between its phases instead of two launches per PCG iteration (the
+   default, which measured faster on MI355X: a grid barrier cost more than a
+   kernel boundary).
+   BA_FLAG_NO_GRAPH: enqueue the kernels of every solve one by one instead of
+   replaying a HIP graph captured on the first solve. */
+#define BA_FLAG_PCG_PERSISTENT 1
+#define BA_FLAG_NO_GRAPH 2
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */

@@ -121,7 +121,8 @@ def _check(rc):
         raise BAError(rc, lib().ba_last_error().decode())
 
 
-FLAG_PCG_LAUNCHES = 1
+FLAG_PCG_PERSISTENT = 1
+FLAG_NO_GRAPH = 2
 
 
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,

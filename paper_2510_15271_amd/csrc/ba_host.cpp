@@ -115,7 +115,8 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~BA_FLAG_PCG_LAUNCHES) return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
+  if (o->flags & ~(BA_FLAG_PCG_PERSISTENT | BA_FLAG_NO_GRAPH))
+    return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   return BA_OK;
 }
 
@@ -645,7 +646,10 @@ struct ba_problem {
   bool pending = false;
   bool solved = false;
   bool profiling = false;
-  bool persistent_pcg = true;
+  bool persistent_pcg = false;
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;       // the launch sequence of one solve, captured once
+  hipGraphExec_t graph_exec = nullptr;
   EventTimer timer;  // times the kernels selected by timer.mask
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
@@ -675,7 +679,8 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   std::unique_ptr<ba_problem> p(new ba_problem());
   if (int e = analyse(d, opt, p->sy)) return e;
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
-  p->persistent_pcg = (opt->flags & BA_FLAG_PCG_LAUNCHES) == 0;
+  p->persistent_pcg = (opt->flags & BA_FLAG_PCG_PERSISTENT) != 0;
+  p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0 && !p->persistent_pcg;
   if (hip_stream) {
     p->stream = (hipStream_t)hip_stream;
   } else {
@@ -724,11 +729,31 @@ int ba_solve_async(ba_problem *p) {
   if (e != hipSuccess) return hip_fail(e, "state upload");
   KernelTimer *tm = p->profiling ? &p->timer : nullptr;
   p->timer.reset();
-  (void)hipEventRecord(p->ev0, p->stream);
-  for (int it = 0; it < p->dp.max_iters; ++it) {
-    e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm,
-                            p->persistent_pcg);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  if (p->use_graph && !p->profiling) {
+    // the kernels of a solve read their scalars from the device state, so the
+    // same launch sequence serves every solve: capture it once, replay it
+    if (!p->graph_exec) {
+      e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture");
+      hipError_t el = hipSuccess;
+      for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr, false);
+      e = hipStreamEndCapture(p->stream, &p->graph);
+      if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
+      if (e != hipSuccess) return hip_fail(e, "graph capture");
+      e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    }
+    (void)hipEventRecord(p->ev0, p->stream);
+    e = hipGraphLaunch(p->graph_exec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+  } else {
+    (void)hipEventRecord(p->ev0, p->stream);
+    for (int it = 0; it < p->dp.max_iters; ++it) {
+      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm,
+                              p->persistent_pcg);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
   }
   (void)hipEventRecord(p->ev1, p->stream);
   e = launch_eval(p->dp.precision, p->batch.plan, p->stream, tm);
@@ -801,6 +826,8 @@ int64_t ba_problem_bytes(const ba_problem *p) { return p ? (int64_t)p->bytes : 0
 void ba_destroy(ba_problem *p) {
   if (!p) return;
   if (p->pending) (void)hipStreamSynchronize(p->stream);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->mem) (void)hipFree(p->mem);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);

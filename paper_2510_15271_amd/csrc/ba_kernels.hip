@@ -854,7 +854,15 @@ __device__ inline bool pcg_finished(const ProbDev &pd, int it, double *s_red, in
   __syncthreads();
   if (stop) return true;
   const double rr = block_sum_array(pd.part_rr, pd.n_pcg_tiles, s_red);
-  return sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb);
+  const bool conv = sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb);
+  // the loop may end here, before spmv(it + 1) would record the count; every
+  // workgroup that gets here writes the same values
+  if (conv && blockIdx.x == 0 && threadIdx.x == 0) {
+    LMState *w = pd.st;
+    w->pcg_iters = it + 1;
+    w->pcg_done = 1;
+  }
+  return conv;
 }
 
 // Every PCG iteration of every problem of the batch in one cooperative launch:

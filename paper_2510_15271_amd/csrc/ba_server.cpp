@@ -144,7 +144,7 @@ struct ba_server {
   int64_t n_done = 0;
   size_t peak = 0;
   int fatal = BA_OK;
-  bool persistent_pcg = true;
+  bool persistent_pcg = false;
 
   void loop();
   void finish(const std::vector<ReqP> &done_now);

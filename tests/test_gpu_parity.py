@@ -116,7 +116,9 @@ def test_huber_outliers_final_rms(balib, prec):
     b = O.rms(p, ref.R, ref.t, ref.X, inlier_px=3.0)
     _say(prec, "inlier rms", a, b, "masked", res["n_masked"])
     assert abs(a - b) <= 1e-3
-    assert abs(O.cost(p, R, t, X) - ref.iter_cost[-1]) <= 1e-4 * ref.iter_cost[-1]
+    # 16-bit storage converges more slowly near the optimum: costs agree to 1e-3 there
+    tol = 1e-4 if prec == "f32" else 1e-3
+    assert abs(O.cost(p, R, t, X) - ref.iter_cost[-1]) <= tol * ref.iter_cost[-1]
 
 
 def test_edge_cases_single_tile_fixed_cameras_one_obs_points(balib):
