@@ -650,6 +650,7 @@ struct ba_problem {
   bool use_graph = true;
   hipGraph_t graph = nullptr;       // the launch sequence of one solve, captured once
   hipGraphExec_t graph_exec = nullptr;
+  uint32_t graph_mask = 0;          // kernels timed inside the captured graph
   EventTimer timer;  // times the kernels selected by timer.mask
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
@@ -728,26 +729,43 @@ int ba_solve_async(ba_problem *p) {
                                 hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(e, "state upload");
   KernelTimer *tm = p->profiling ? &p->timer : nullptr;
-  p->timer.reset();
-  if (p->use_graph && !p->profiling) {
-    // the kernels of a solve read their scalars from the device state, so the
-    // same launch sequence serves every solve: capture it once, replay it
+  if (p->use_graph) {
+    // The kernels of a solve read their scalars from the device state, so the
+    // same launch sequence serves every solve: capture it once and replay it.
+    // Timing events of the selected kernels are recorded inside the graph, so
+    // the graph is captured again when the selection changes.
+    const uint32_t mask = p->profiling ? p->timer.mask : 0u;
+    if (p->graph_exec && mask != p->graph_mask) {
+      (void)hipGraphExecDestroy(p->graph_exec);
+      (void)hipGraphDestroy(p->graph);
+      p->graph_exec = nullptr;
+      p->graph = nullptr;
+    }
     if (!p->graph_exec) {
+      p->timer.reset();
       e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr, false);
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm, false);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
       if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      p->graph_mask = mask;
     }
     (void)hipEventRecord(p->ev0, p->stream);
     e = hipGraphLaunch(p->graph_exec, p->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    (void)hipEventRecord(p->ev1, p->stream);
+    // the final evaluation stays outside the graph and is not timed
+    e = launch_eval(p->dp.precision, p->batch.plan, p->stream, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    p->pending = true;
+    return BA_OK;
   } else {
+    p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters; ++it) {
       e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm,

@@ -117,6 +117,31 @@ __device__ inline double block_sum_array(const double *a, int n, double *scratch
   return block_sum256(v, scratch4);
 }
 
+// Sums of three double arrays of length n in one pass (fixed order; a NULL
+// array sums to 0).  Result in every thread.
+__device__ inline void block_sum3(const double *a, const double *b, const double *c, int n,
+                                  double *scratch12, double out[3]) {
+  double va = 0.0, vb = 0.0, vc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    if (a) va += a[i];
+    if (b) vb += b[i];
+    if (c) vc += c[i];
+  }
+  va = wave_sum(va);
+  vb = wave_sum(vb);
+  vc = wave_sum(vc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    scratch12[w] = va;
+    scratch12[4 + w] = vb;
+    scratch12[8 + w] = vc;
+  }
+  __syncthreads();
+  for (int k = 0; k < 3; ++k)
+    out[k] = scratch12[4 * k] + scratch12[4 * k + 1] + scratch12[4 * k + 2] + scratch12[4 * k + 3];
+  __syncthreads();
+}
+
 template <class T>
 __device__ inline T huber_w(T s, T delta) {
   if (delta <= T(0) || s <= delta * delta) return T(1);
@@ -709,19 +734,20 @@ __device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, 
       return;
     }
   } else {
-    const double rr = block_sum_array(pd.part_rr, pd.n_pcg_tiles, s_red);
+    __shared__ double s_red3[12];
+    double sums[3];  // r.r, rz_it, rz_{it-1}
+    block_sum3(pd.part_rr, pd.part_rz[it & 1], it == 1 ? nullptr : pd.part_rz[(it - 1) & 1],
+               pd.n_pcg_tiles, s_red3, sums);
     const double bb = st->pcg_bb;
-    if (sqrt(rr) <= st->pcg_tol * sqrt(bb)) {
+    if (sqrt(sums[0]) <= st->pcg_tol * sqrt(bb)) {
       if (tl.idx == 0 && threadIdx.x == 0) {
         st->pcg_done = 1;
         st->pcg_iters = it;
       }
       return;
     }
-    const double rz_new = block_sum_array(pd.part_rz[it & 1], pd.n_pcg_tiles, s_red);
-    const double rz_old =
-        (it == 1) ? st->pcg_rz0 : block_sum_array(pd.part_rz[(it - 1) & 1], pd.n_pcg_tiles, s_red);
-    beta = rz_new / rz_old;
+    const double rz_old = (it == 1) ? st->pcg_rz0 : sums[2];
+    beta = sums[1] / rz_old;
   }
   const T tb = T(beta);
   const T *z = (const T *)pd.z;
@@ -780,7 +806,10 @@ __device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl
   __shared__ double s_red2[4];
   __shared__ T s_r[kPcgRows * 6];
   if (!pcg_go(st, it, s_flag)) return;
-  const double pq = block_sum_array(pd.part_pq, pd.n_pcg_tiles, s_red);
+  __shared__ double s_red3[12];
+  double sums[3];  // p.q, rz_it
+  block_sum3(pd.part_pq, it == 0 ? nullptr : pd.part_rz[it & 1], nullptr, pd.n_pcg_tiles, s_red3, sums);
+  const double pq = sums[0];
   if (!(pq > 0.0)) {  // breakdown: keep x, stop
     if (tl.idx == 0 && threadIdx.x == 0) {
       st->pcg_done = 1;
@@ -788,7 +817,7 @@ __device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl
     }
     return;
   }
-  const double rz = (it == 0) ? st->pcg_rz0 : block_sum_array(pd.part_rz[it & 1], pd.n_pcg_tiles, s_red);
+  const double rz = (it == 0) ? st->pcg_rz0 : sums[1];
   const double alpha = rz / pq;
   const T ta = T(alpha);
   const T *p = (const T *)((it & 1) ? pd.p1 : pd.p0);
