@@ -608,6 +608,14 @@ void EventTimer::reset() {
   used = 0;
   ids.clear();
 }
+void EventTimer::reserve(size_t pairs) {
+  while (pool.size() < pairs) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    pool.push_back({a, b});
+  }
+}
 void EventTimer::collect(double ms[K_NUM_KERNELS], int32_t launches[K_NUM_KERNELS]) {
   for (int i = 0; i < K_NUM_KERNELS; ++i) {
     ms[i] = 0.0;
@@ -743,6 +751,8 @@ int ba_solve_async(ba_problem *p) {
     }
     if (!p->graph_exec) {
       p->timer.reset();
+      // events cannot be created during capture: create every pair the capture may record
+      if (tm) p->timer.reserve((size_t)p->dp.max_iters * (2 * (size_t)p->dp.pcg_max + 16) + 4);
       e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;

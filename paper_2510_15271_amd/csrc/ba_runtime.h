@@ -92,6 +92,7 @@ struct EventTimer : KernelTimer {
   void begin(int id, hipStream_t s) override;
   void end(int id, hipStream_t s) override;
   void reset();
+  void reserve(size_t pairs);
   void collect(double ms[K_NUM_KERNELS], int32_t launches[K_NUM_KERNELS]);
   ~EventTimer() override;
 };
