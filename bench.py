@@ -34,16 +34,15 @@ def algorithmic_bytes(kernel: str, info: dict, precision: str) -> float:
     S = {"f64": 8, "f32": 4, "f16j": 2, "bf16j": 2}[precision]
     N, P, Cf, C = info["n_obs"], info["n_pts"], info["n_free_cams"], info["n_cams"]
     Nf = info["n_free_obs"]
-    rec = 18 * S + 2 * T
+    rec = 7 * S + 2 * T            # compact record: sqrt(w) J_pi (4), P_c (3), sqrt(w) r (2)
     if kernel == "linearize":      # obs cam/pt/uv/slot + points in; records, V, g_p, D_p out
         return N * (12 + 2 * T) + P * 24 + Nf * rec + P * 12 * T + C * 96
-    if kernel == "point_prep":     # V, D_p, records, obs_pt/slot in; V*^-1, Y out
-        return P * 9 * T + Nf * 18 * S + N * 8 + P * 6 * T + Nf * 18 * T
-    if kernel == "schur_diag":     # per free observation: record, Y, g_p; S diagonal, M^-1 out
-        nf = info["n_free_obs"]
-        return nf * (4 + 4 + rec + 18 * T + 3 * T) + Cf * (36 * T + 36 * 8 + 6 * 6 * T)
-    if kernel == "schur_off":      # pair list + Y and records of both sides once; S blocks out
-        return info["n_pairs"] * 8 + Nf * (18 * T + 18 * S) + info["n_up_blocks"] * 2 * 36 * T
+    if kernel == "point_prep":     # V, D_p, records, obs cam/pt/slot in; V*^-1, Q out
+        return P * 9 * T + Nf * rec + N * 12 + P * 6 * T + Nf * 6 * T
+    if kernel == "schur_diag":     # per free observation: slot, point, record, Q, g_p; S diagonal, M^-1 out
+        return Nf * (4 + 4 + rec + 6 * T + 3 * T) + Cf * (36 * T + 36 * 8 + 6 * 6 * T)
+    if kernel == "schur_off":      # pair list + records and Q once; S blocks out
+        return info["n_pairs"] * 8 + Nf * (rec + 6 * T) + info["n_up_blocks"] * 2 * 36 * T
     if kernel in ("pcg_spmv",):    # S once + vectors
         return info["nnzb"] * (36 * T + 4) + Cf * 6 * T * 4
     if kernel == "point_trial":    # records, x, V*^-1, g_p, D_p, X in; X' out; obs re-read for cost

@@ -335,7 +335,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.X_init = L.take(P * 3 * 8);
   const size_t Nf = sy.cam_obs.size();
   o.lin = L.take(Nf * lin_record_bytes(precision) + 16);
-  o.Y = L.take(Nf * 18 * T + 16);
+  o.Q = L.take(Nf * 6 * T + 16);
   o.V = L.take(P * 6 * T);
   o.gp = L.take(P * 3 * T);
   o.Dp = L.take(P * 3 * T);
@@ -424,7 +424,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
     pd.X[b] = (double *)ptr(off.X[b]);
   }
   pd.lin = ptr(off.lin);
-  pd.Y = ptr(off.Y);
+  pd.Q = ptr(off.Q);
   pd.V = ptr(off.V);
   pd.gp = ptr(off.gp);
   pd.Dp = ptr(off.Dp);

@@ -77,7 +77,7 @@ struct ProbDev {
   double *X[2];                   // [P][3]
   // linearisation and Schur complement
   void *lin;                      // [Nf] LinRec<T, S>, camera-major
-  void *Y;                        // [Nf][18] T: W_k V*_j^-1, camera-major
+  void *Q;                        // [Nf][6] T: J_p,k V*_j^-1 (2x3), camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
   void *S;                        // [nnzb][36] T

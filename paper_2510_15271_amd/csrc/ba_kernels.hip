@@ -74,11 +74,47 @@ struct Codec<bf16s> {
   __device__ static float dec(bf16s h) { return __uint_as_float((uint32_t)h.b << 16); }
 };
 
+// Linearisation record of one observation, kept compact: the four non-zero
+// entries of sqrt(w) J_pi (fx/z, -fx x/z^2, fy/z, -fy y/z^2, each times sqrt(w))
+// and the camera-frame point P_c = (x, y, z).  J_c = J_pi [I | -[P]x] and
+// J_p = J_pi R are rebuilt from them, R being the camera's rotation.
 template <class T, class S>
 struct LinRec {
-  S j[18];  // sqrt(w) J_c row-major (2x6), then sqrt(w) J_p (2x3)
-  T e[2];   // sqrt(w) r
+  S f[7];
+  T e[2];  // sqrt(w) r
 };
+
+template <class T, class S>
+__device__ inline void decode(const LinRec<T, S> &rec, T f[7]) {
+#pragma unroll
+  for (int i = 0; i < 7; ++i) f[i] = Codec<S>::dec(rec.f[i]);
+}
+
+// J_c (2x6, row-major) from the compact record.
+template <class T>
+__device__ inline void jc_from(const T f[7], T Jc[12]) {
+  const T a = f[0], b = f[1], c = f[2], d = f[3], x = f[4], y = f[5], z = f[6];
+  Jc[0] = a;     Jc[1] = T(0);  Jc[2] = b;
+  Jc[3] = b * y; Jc[4] = a * z - b * x; Jc[5] = -a * y;
+  Jc[6] = T(0);  Jc[7] = c;     Jc[8] = d;
+  Jc[9] = -c * z + d * y; Jc[10] = -d * x; Jc[11] = c * x;
+}
+
+// J_p (2x3, row-major) = J_pi R.
+template <class T>
+__device__ inline void jp_from(const T f[4], const T R[9], T Jp[6]) {
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Jp[m] = f[0] * R[m] + f[1] * R[6 + m];
+    Jp[3 + m] = f[2] * R[3 + m] + f[3] * R[6 + m];
+  }
+}
+
+template <class T>
+__device__ inline void load_rot(const double *pose, T R[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = T(pose[i]);
+}
 
 size_t lin_record_bytes(int precision) {
   switch (precision) {
@@ -342,22 +378,23 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
         const T w = huber_w(s, delta);
         const T sw = sqrt(w);
         cost += 0.5 * (double)huber_rho(s, delta);
-        T Jc[12], Jp[6];
-        jacobians<T>(K, pose, x, y, z, Jc, Jp);
-        T q[18];  // stored-precision values, used for V so that V, U and W agree
+        const T iz = T(1) / z;
+        const T fa = K[0] * iz, fb = -K[0] * x * iz * iz;
+        const T fc = K[1] * iz, fd = -K[1] * y * iz * iz;
+        const T raw[7] = {sw * fa, sw * fb, sw * fc, sw * fd, x, y, z};
+        T fq[7];  // stored-precision values: V is formed from them so that V, U and W agree
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-          rec.j[i] = Codec<S>::enc(sw * Jc[i]);
-          q[i] = Codec<S>::dec(rec.j[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          rec.j[12 + i] = Codec<S>::enc(sw * Jp[i]);
-          q[12 + i] = Codec<S>::dec(rec.j[12 + i]);
+        for (int i = 0; i < 7; ++i) {
+          rec.f[i] = Codec<S>::enc(raw[i]);
+          fq[i] = Codec<S>::dec(rec.f[i]);
         }
         rec.e[0] = sw * r0;
         rec.e[1] = sw * r1;
-        const T *P0 = q + 12, *P1 = q + 15;
+        T R[9];
+        load_rot(pose, R);
+        T Jq[6];
+        jp_from(fq, R, Jq);
+        const T *P0 = Jq, *P1 = Jq + 3;
         c[0] = P0[0] * P0[0] + P1[0] * P1[0];
         c[1] = P0[0] * P0[1] + P1[0] * P1[1];
         c[2] = P0[0] * P0[2] + P1[0] * P1[2];
@@ -365,12 +402,15 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
         c[4] = P0[1] * P0[2] + P1[1] * P1[2];
         c[5] = P0[2] * P0[2] + P1[2] * P1[2];
         // gradient from the unrounded Jacobian: w J_p^T r
+        const T fr[4] = {fa, fb, fc, fd};
+        T Jp[6];
+        jp_from(fr, R, Jp);
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[6 + m] = w * (Jp[m] * r0 + Jp[3 + m] * r1);
       } else {
         ++masked;
 #pragma unroll
-        for (int i = 0; i < 18; ++i) rec.j[i] = Codec<S>::enc(0.0f);
+        for (int i = 0; i < 7; ++i) rec.f[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
       }
       const int cpos = pd.obs_cpos[k];  // records are kept for free cameras only
@@ -411,7 +451,8 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
 }
 
 // ------------------------------------------------------------------ point prep
-// V*_j = V_j + lambda D_j inverted in FP64; Y_k = (J_c^T J_p) V*_j^-1 per observation.
+// V*_j = V_j + lambda D_j inverted in FP64; per free observation Q_k = J_p,k V*_j^-1
+// (2x3), from which Y_k = W_k V*_j^-1 = J_c,k^T Q_k is formed where needed.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ probs,
                                                     const Tile *__restrict__ tiles) {
@@ -444,35 +485,30 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
   __syncthreads();
   const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
   const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-  T *Y = (T *)pd.Y;
+  const double *poses = pd.pose[st->cur];
+  T *Q = (T *)pd.Q;
   for (int k = k0 + threadIdx.x; k < k1; k += 256) {
     const int cpos = pd.obs_cpos[k];
-    if (cpos < 0) continue;  // fixed camera: no camera block, no Y
+    if (cpos < 0) continue;  // fixed camera: no camera block
     const int jl = pd.obs_pt[k] - j0;
-    const LinRec<T, S> rec = lin[cpos];
-    T J[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+    T f[7], R[9], Jp[6];
+    decode(lin[cpos], f);
+    load_rot(poses + 12 * pd.obs_cam[k], R);
+    jp_from(f, R, Jp);
     const T *vi = s_vi[jl];
     const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
-    T y[18];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      // W[r][n] = J_c[0][r] J_p[0][n] + J_c[1][r] J_p[1][n]
-      T w0 = J[r] * J[12] + J[6 + r] * J[15];
-      T w1 = J[r] * J[13] + J[6 + r] * J[16];
-      T w2 = J[r] * J[14] + J[6 + r] * J[17];
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) y[3 * r + m] = w0 * M[m] + w1 * M[3 + m] + w2 * M[6 + m];
-    }
-#pragma unroll
-    for (int i = 0; i < 18; ++i) Y[18 * (size_t)cpos + i] = y[i];
+      for (int m = 0; m < 3; ++m)
+        Q[6 * (size_t)cpos + 3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
   }
 }
 
 // ------------------------------------------------------------------ Schur: diagonal
 // One workgroup per free camera.  Accumulates, over the camera's observations,
-// U (upper 21), sum Y W^T (upper 21), g_c (6) and sum Y g_p (6); then damping,
+// U (upper 21), sum Y W^T = sum J_c^T (Q J_p^T) J_c (upper 21), g_c (6) and
+// sum Y g_p = sum J_c^T (Q g_p) (6); then damping,
 // the diagonal block of S, the right-hand side, the FP64 block-Jacobi inverse
 // and the PCG initial vectors of this row.
 template <class T, class S>
@@ -485,7 +521,7 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
   const int a = tl.idx;
   const int o0 = pd.cam_obs_start[a], o1 = pd.cam_obs_start[a + 1];
   const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-  const T *Yall = (const T *)pd.Y;
+  const T *Qall = (const T *)pd.Q;
   const T *gp = (const T *)pd.gp;
   constexpr bool k16 = sizeof(S) == 2;
 
@@ -502,23 +538,29 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
     pose = pd.pose[st->cur] + 12 * cam;
     K = (const T *)pd.K + 4 * cam;
   }
+  T Ra[9];
+  load_rot(pd.pose[st->cur] + 12 * pd.free_cam[a], Ra);
   for (int o = o0 + threadIdx.x; o < o1; o += 256) {
     const int k = pd.cam_obs[o];
     const int j = pd.obs_pt[k];
     const LinRec<T, S> rec = lin[o];
-    T J[18];
+    T f[7], Jc[12], Jp[6], q[6];
+    decode(rec, f);
+    jc_from(f, Jc);
+    jp_from(f, Ra, Jp);
+    const T *Jc0 = Jc, *Jc1 = Jc + 6;
 #pragma unroll
-    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
-    const T *Jc0 = J, *Jc1 = J + 6, *Jp0 = J + 12, *Jp1 = J + 15;
-    T y[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)o + i];
-    // Z = Y J_p^T (6x2)
+    for (int i = 0; i < 6; ++i) q[i] = Qall[6 * (size_t)o + i];
+    // M = Q J_p^T (2x2); Y W^T = J_c^T M J_c
+    const T m00 = q[0] * Jp[0] + q[1] * Jp[1] + q[2] * Jp[2];
+    const T m01 = q[0] * Jp[3] + q[1] * Jp[4] + q[2] * Jp[5];
+    const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
+    const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
     T Z0[6], Z1[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
-      Z0[r] = y[3 * r] * Jp0[0] + y[3 * r + 1] * Jp0[1] + y[3 * r + 2] * Jp0[2];
-      Z1[r] = y[3 * r] * Jp1[0] + y[3 * r + 1] * Jp1[1] + y[3 * r + 2] * Jp1[2];
+      Z0[r] = Jc0[r] * m00 + Jc1[r] * m10;
+      Z1[r] = Jc0[r] * m01 + Jc1[r] * m11;
     }
     int u = 0;
 #pragma unroll
@@ -560,11 +602,14 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
         e0 = e1 = T(0);
       }
     }
+    // Y g_p = J_c^T (Q g_p)
     const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
+    const T qg0 = q[0] * g0 + q[1] * g1 + q[2] * g2;
+    const T qg1 = q[3] * g0 + q[4] * g1 + q[5] * g2;
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
       acc[42 + r] += G0[r] * e0 + G1[r] * e1;
-      acc[48 + r] += y[3 * r] * g0 + y[3 * r + 1] * g1 + y[3 * r + 2] * g2;
+      acc[48 + r] += Jc0[r] * qg0 + Jc1[r] * qg1;
     }
   }
   // deterministic block reduction: wave butterflies, then the 4 waves in order
@@ -639,8 +684,10 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
 
 // ------------------------------------------------------------------ Schur: off-diagonal
 // One wavefront per upper block (a, b): S_ab = -sum_j Y_aj W_bj^T over the
-// block's pair list, W_bj^T = J_p,b^T J_c,b, so each pair costs Z = Y J_p^T
-// (6x2) and Z J_c (6x6).  Lanes stride over pairs; one butterfly reduction.
+// block's pair list.  With Y = J_c,a^T Q_a and W_b^T = J_p,b^T J_c,b a pair costs
+// M = Q_a J_p,b^T (2x2), Z = J_c,a^T M (6x2) and Z J_c,b (6x6); each side's
+// Jacobians come from its compact record (camera b's rotation is shared by the
+// whole block).  Lanes stride over pairs; one butterfly reduction per block.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ probs,
                                                    const Tile *__restrict__ tiles) {
@@ -653,25 +700,32 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
   if (u >= pd.n_up) return;  // wave-uniform; no block-wide barrier follows
   const int p0 = pd.up_pair_start[u], p1 = pd.up_pair_start[u + 1];
   const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-  const T *Yall = (const T *)pd.Y;
+  const T *Qall = (const T *)pd.Q;
+  T Rb[9];
+  load_rot(pd.pose[st->cur] + 12 * pd.free_cam[pd.S_col[pd.up_pos[u]]], Rb);
   T acc[36];
 #pragma unroll
   for (int i = 0; i < 36; ++i) acc[i] = T(0);
   for (int p = p0 + lane; p < p1; p += 64) {
     const int2 kk = pd.pairs[p];
-    T y[18];
+    T fa[7], fb[7], Jca[12], Jcb[12], Jpb[6], q[6];
+    decode(lin[kk.x], fa);
+    decode(lin[kk.y], fb);
 #pragma unroll
-    for (int i = 0; i < 18; ++i) y[i] = Yall[18 * (size_t)kk.x + i];
-    const LinRec<T, S> rec = lin[kk.y];
-    T J[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+    for (int i = 0; i < 6; ++i) q[i] = Qall[6 * (size_t)kk.x + i];
+    jc_from(fa, Jca);
+    jc_from(fb, Jcb);
+    jp_from(fb, Rb, Jpb);
+    const T m00 = q[0] * Jpb[0] + q[1] * Jpb[1] + q[2] * Jpb[2];
+    const T m01 = q[0] * Jpb[3] + q[1] * Jpb[4] + q[2] * Jpb[5];
+    const T m10 = q[3] * Jpb[0] + q[4] * Jpb[1] + q[5] * Jpb[2];
+    const T m11 = q[3] * Jpb[3] + q[4] * Jpb[4] + q[5] * Jpb[5];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
-      const T z0 = y[3 * r] * J[12] + y[3 * r + 1] * J[13] + y[3 * r + 2] * J[14];
-      const T z1 = y[3 * r] * J[15] + y[3 * r + 1] * J[16] + y[3 * r + 2] * J[17];
+      const T z0 = Jca[r] * m00 + Jca[6 + r] * m10;
+      const T z1 = Jca[r] * m01 + Jca[6 + r] * m11;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * J[c] + z1 * J[6 + c];
+      for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * Jcb[c] + z1 * Jcb[6 + c];
     }
   }
   // butterfly: every lane ends with all 36 sums; lane e keeps entry e
@@ -992,21 +1046,23 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
       jl = pd.obs_pt[k] - j0;
       const int cpos = pd.obs_cpos[k];
       if (cpos >= 0) {
-        const int a = pd.free_idx[pd.obs_cam[k]];
-        const LinRec<T, S> rec = lin[cpos];
-        T J[18];
-#pragma unroll
-        for (int i = 0; i < 18; ++i) J[i] = Codec<S>::dec(rec.j[i]);
+        const int cam = pd.obs_cam[k];
+        const int a = pd.free_idx[cam];
+        T f[7], R[9], Jc[12], Jp[6];
+        decode(lin[cpos], f);
+        load_rot(pd.pose[cur] + 12 * cam, R);  // the linearisation state
+        jc_from(f, Jc);
+        jp_from(f, R, Jp);
         const T *dc = x + 6 * a;
         T u0 = T(0), u1 = T(0);
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
           const T d = dc[m];
-          u0 += J[m] * d;
-          u1 += J[6 + m] * d;
+          u0 += Jc[m] * d;
+          u1 += Jc[6 + m] * d;
         }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) c[m] = J[12 + m] * u0 + J[15 + m] * u1;
+        for (int m = 0; m < 3; ++m) c[m] = Jp[m] * u0 + Jp[3 + m] * u1;
       }
     }
     s_loc[threadIdx.x] = jl;
