@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--pcg-persistent", action="store_true",
                     help="one cooperative PCG launch per solve instead of two launches per iteration")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time only whole steps (lets solves replay their graph)")
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -131,7 +133,7 @@ def main():
                   file=sys.stderr)
 
     # timed region: the dominant kernel is timed with HIP events on its stream
-    prob.set_profiling(1 << names.index(dominant))
+    prob.set_profiling(0 if args.no_kernel_timing else 1 << names.index(dominant))
     dev_ms = []
     dom_ms, dom_launch = 0.0, 0
     print(f"bench: timing {args.steps} steps", flush=True, file=sys.stderr)

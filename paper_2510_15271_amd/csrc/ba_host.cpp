@@ -658,7 +658,6 @@ struct ba_problem {
   bool use_graph = true;
   hipGraph_t graph = nullptr;       // the launch sequence of one solve, captured once
   hipGraphExec_t graph_exec = nullptr;
-  uint32_t graph_mask = 0;          // kernels timed inside the captured graph
   EventTimer timer;  // times the kernels selected by timer.mask
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
@@ -737,33 +736,22 @@ int ba_solve_async(ba_problem *p) {
                                 hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(e, "state upload");
   KernelTimer *tm = p->profiling ? &p->timer : nullptr;
-  if (p->use_graph) {
+  if (p->use_graph && !p->profiling) {
     // The kernels of a solve read their scalars from the device state, so the
     // same launch sequence serves every solve: capture it once and replay it.
-    // Timing events of the selected kernels are recorded inside the graph, so
-    // the graph is captured again when the selection changes.
-    const uint32_t mask = p->profiling ? p->timer.mask : 0u;
-    if (p->graph_exec && mask != p->graph_mask) {
-      (void)hipGraphExecDestroy(p->graph_exec);
-      (void)hipGraphDestroy(p->graph);
-      p->graph_exec = nullptr;
-      p->graph = nullptr;
-    }
+    // (Per-kernel timing needs events between launches: profiled solves are
+    // enqueued kernel by kernel instead.)
     if (!p->graph_exec) {
-      p->timer.reset();
-      // events cannot be created during capture: create every pair the capture may record
-      if (tm) p->timer.reserve((size_t)p->dp.max_iters * (2 * (size_t)p->dp.pcg_max + 16) + 4);
       e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm, false);
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr, false);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
       if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-      p->graph_mask = mask;
     }
     (void)hipEventRecord(p->ev0, p->stream);
     e = hipGraphLaunch(p->graph_exec, p->stream);
