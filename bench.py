@@ -43,7 +43,7 @@ def algorithmic_bytes(kernel: str, info: dict, precision: str) -> float:
         return Nf * (4 + 4 + rec + 6 * T + 3 * T) + Cf * (36 * T + 36 * 8 + 6 * 6 * T)
     if kernel == "schur_off":      # pair list + records and Q once; S blocks out
         return info["n_pairs"] * 8 + Nf * (rec + 6 * T) + info["n_up_blocks"] * 2 * 36 * T
-    if kernel in ("pcg_spmv",):    # S once + vectors
+    if kernel == "pcg_iter":       # S once + vectors (x, r, z, p, q, M^-1 of the update)
         return info["nnzb"] * (36 * T + 4) + Cf * 6 * T * 4
     if kernel == "point_trial":    # records, x, V*^-1, g_p, D_p, X in; X' out; obs re-read for cost
         return Nf * rec + N * (12 + 2 * T) + P * (12 * T + 48) + Cf * 6 * T
@@ -91,8 +91,6 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16j", "bf16j"])
     ap.add_argument("--points", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pcg-persistent", action="store_true",
-                    help="one cooperative PCG launch per solve instead of two launches per iteration")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time only whole steps (lets solves replay their graph)")
@@ -113,8 +111,7 @@ def main():
     scene = make_config1(n_pts=args.points)
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
-                                 flags=(ba.FLAG_PCG_PERSISTENT if args.pcg_persistent else 0)
-                                 | (ba.FLAG_NO_GRAPH if args.no_graph else 0))
+                                 flags=ba.FLAG_NO_GRAPH if args.no_graph else 0)
     info = prob.info()
     names = list(prob.kernel_times().keys())
 
@@ -132,8 +129,10 @@ def main():
             print(f"  {k:12s} {ms:9.3f} ms  {n:5d} launches  {100 * ms / tot:5.1f} %",
                   file=sys.stderr)
 
-    # timed region: the dominant kernel is timed with HIP events on its stream
-    prob.set_profiling(0 if args.no_kernel_timing else 1 << names.index(dominant))
+    # timed region: every 10th launch of the dominant kernel (one in each LM
+    # iteration for the per-iteration kernels) is timed with HIP events on its stream
+    stride = 10 if kt[dominant][1] >= 100 else 1
+    prob.set_profiling(0 if args.no_kernel_timing else 1 << names.index(dominant), stride)
     dev_ms = []
     dom_ms, dom_launch = 0.0, 0
     print(f"bench: timing {args.steps} steps", flush=True, file=sys.stderr)
@@ -185,7 +184,6 @@ def main():
                                f"{LM_ITERS} LM iterations, PCG 50 / 1e-6",
                    "n_obs": info["n_obs"], "n_pairs": info["n_pairs"],
                    "nnzb": info["nnzb"], "precision": args.precision,
-                   "pcg": "persistent" if args.pcg_persistent else "launches",
                    "graph": not args.no_graph},
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),

@@ -76,13 +76,8 @@ typedef struct {
 } ba_options;
 
 /* ba_options.flags bits.
-   BA_FLAG_PCG_PERSISTENT: run each PCG solve as one cooperative launch with grid
-   barriers between its phases instead of two launches per PCG iteration (the
-   default, which measured faster on MI355X: a grid barrier cost more than a
-   kernel boundary).
    BA_FLAG_NO_GRAPH: enqueue the kernels of every solve one by one instead of
    replaying a HIP graph captured on the first solve. */
-#define BA_FLAG_PCG_PERSISTENT 1
 #define BA_FLAG_NO_GRAPH 2
 
 typedef struct {
@@ -156,12 +151,14 @@ int ba_get_info(const ba_problem *p, ba_problem_info *out);
 int64_t ba_problem_bytes(const ba_problem *p);
 void ba_destroy(ba_problem *p);
 
-/* Per-kernel device time of the last solve, summed over its launches (HIP
-   events recorded on the problem's stream around each launch).  Enabled by
-   ba_set_profiling(p, mask) before ba_solve: bit i of mask times kernel i in the
-   order ba_get_kernel_times reports them (-1: all, 0: off).  names/ms/launches: caller arrays of max_kernels entries;
-   *n_out receives the number of kernels. */
-int ba_set_profiling(ba_problem *p, int32_t enable);
+/* Per-kernel device time of the last solve, summed over the timed launches
+   (HIP events recorded on the problem's stream around each timed launch).
+   ba_set_profiling(p, mask, stride) selects the kernels (bit i of mask = kernel
+   i in the order ba_get_kernel_times reports them; -1 all, 0 off) and times
+   every stride-th launch of each (events between launches cost time, so a
+   stride keeps the measured solve close to an unmeasured one).  Profiled
+   solves are enqueued launch by launch, not replayed from a graph. */
+int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride);
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
                         double *ms, int32_t *launches, int32_t *n_out);
 

@@ -99,7 +99,7 @@ def lib():
     L.ba_problem_bytes.restype = i64
     L.ba_destroy.argtypes = [vp]
     L.ba_destroy.restype = None
-    L.ba_set_profiling.argtypes = [vp, i32]
+    L.ba_set_profiling.argtypes = [vp, i32, i32]
     L.ba_get_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_char_p), dp, C.POINTER(i32),
                                       C.POINTER(i32)]
     L.ba_pose_batch.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
@@ -121,7 +121,6 @@ def _check(rc):
         raise BAError(rc, lib().ba_last_error().decode())
 
 
-FLAG_PCG_PERSISTENT = 1
 FLAG_NO_GRAPH = 2
 
 
@@ -212,12 +211,13 @@ class Problem:
     def wait(self):
         _check(lib().ba_wait(self._h))
 
-    def set_profiling(self, mask=-1):
-        """mask: -1 all kernels, 0 off, or a bit mask over kernel_names()."""
+    def set_profiling(self, mask=-1, stride=1):
+        """mask: -1 all kernels, 0 off, or a bit mask over kernel_times() order;
+        stride: time every stride-th launch of each selected kernel."""
         m = int(mask)
         if m >= 2 ** 31:
             m -= 2 ** 32
-        _check(lib().ba_set_profiling(self._h, m))
+        _check(lib().ba_set_profiling(self._h, m, int(stride)))
 
     def info(self):
         i = ProblemInfo()

@@ -115,7 +115,7 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~(BA_FLAG_PCG_PERSISTENT | BA_FLAG_NO_GRAPH))
+  if (o->flags & ~BA_FLAG_NO_GRAPH)
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   return BA_OK;
 }
@@ -355,10 +355,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_dl_cam = L.take(ncam * 8);
   o.part_rz0 = L.take(Cf * 8);
   o.part_bb = L.take(Cf * 8);
-  o.part_rz[0] = L.take(npcg * 8);
-  o.part_rz[1] = L.take(npcg * 8);
   o.part_pq = L.take(npcg * 8);
-  o.part_rr = L.take(npcg * 8);
   o.iter_cost = L.take((max_iters + 1) * 8);
   o.iter_pcg = L.take(max_iters * 4);
   o.total = L.off;
@@ -449,10 +446,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_dl_cam = (double *)ptr(off.part_dl_cam);
   pd.part_rz0 = (double *)ptr(off.part_rz0);
   pd.part_bb = (double *)ptr(off.part_bb);
-  pd.part_rz[0] = (double *)ptr(off.part_rz[0]);
-  pd.part_rz[1] = (double *)ptr(off.part_rz[1]);
   pd.part_pq = (double *)ptr(off.part_pq);
-  pd.part_rr = (double *)ptr(off.part_rr);
   pd.st = (LMState *)ptr(off.st);
   pd.iter_cost = (double *)ptr(off.iter_cost);
   pd.iter_pcg = (int32_t *)ptr(off.iter_pcg);
@@ -587,7 +581,7 @@ Batch::~Batch() {
 
 // ------------------------------------------------------------------ timing
 void EventTimer::begin(int id, hipStream_t s) {
-  active = ((mask >> id) & 1u) != 0;
+  active = ((mask >> id) & 1u) != 0 && (seen[id]++ % stride) == 0;
   if (!active) return;
   if (used == pool.size()) {
     hipEvent_t a, b;
@@ -607,6 +601,7 @@ void EventTimer::end(int, hipStream_t s) {
 void EventTimer::reset() {
   used = 0;
   ids.clear();
+  for (int i = 0; i < K_NUM_KERNELS; ++i) seen[i] = 0;
 }
 void EventTimer::reserve(size_t pairs) {
   while (pool.size() < pairs) {
@@ -654,7 +649,6 @@ struct ba_problem {
   bool pending = false;
   bool solved = false;
   bool profiling = false;
-  bool persistent_pcg = false;
   bool use_graph = true;
   hipGraph_t graph = nullptr;       // the launch sequence of one solve, captured once
   hipGraphExec_t graph_exec = nullptr;
@@ -687,8 +681,7 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   std::unique_ptr<ba_problem> p(new ba_problem());
   if (int e = analyse(d, opt, p->sy)) return e;
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
-  p->persistent_pcg = (opt->flags & BA_FLAG_PCG_PERSISTENT) != 0;
-  p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0 && !p->persistent_pcg;
+  p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0;
   if (hip_stream) {
     p->stream = (hipStream_t)hip_stream;
   } else {
@@ -746,7 +739,7 @@ int ba_solve_async(ba_problem *p) {
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr, false);
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
       if (e != hipSuccess) return hip_fail(e, "graph capture");
@@ -766,8 +759,7 @@ int ba_solve_async(ba_problem *p) {
     p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters; ++it) {
-      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm,
-                              p->persistent_pcg);
+      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm);
       if (e != hipSuccess) return hip_fail(e, "kernel launch");
     }
   }
@@ -851,10 +843,12 @@ void ba_destroy(ba_problem *p) {
   delete p;
 }
 
-int ba_set_profiling(ba_problem *p, int32_t enable) {
+int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride) {
   if (!p) return fail(BA_EINVAL, "problem is NULL");
-  p->profiling = enable != 0;
-  p->timer.mask = (uint32_t)enable;
+  if (stride < 1) return fail(BA_EINVAL, "stride must be >= 1");
+  p->profiling = mask != 0;
+  p->timer.mask = (uint32_t)mask;
+  p->timer.stride = stride;
   return BA_OK;
 }
 

@@ -14,10 +14,11 @@
 //   schur_off    one wavefront per upper block S_ab: sum over the points seen
 //                by a and b of -Y_aj W_bj^T from precomputed pair lists, one
 //                wave reduction, written to S_ab and its transpose.
-//   pcg_spmv /   block-sparse S p with FP64 dot products; direction update
-//   pcg_update   folded into the product; per-tile partial sums reduced in a
-//                fixed order by every consumer, so no grid barrier and no
-//                float atomics are needed.
+//   pcg_iter     one launch per PCG iteration: block-sparse S p with the
+//                direction update folded into the product; the workgroup that
+//                finishes last (an atomic ticket, nothing waits on it) sums the
+//                per-tile partials in tile order and updates x, r, z for all
+//                rows with FP64 dot products.  No grid barrier, no float atomics.
 //   cam_update   T <- Exp(dc) T, camera part of the predicted decrease.
 //   point_trial  dp_j = V*_j^-1 (-g_p,j - sum W^T dc), X <- X + dp, trial cost.
 //   lm_control   gain ratio, accept/reject, Nielsen damping update.
@@ -25,7 +26,6 @@
 // Every reduction is deterministic: a fixed assignment of work to lanes and a
 // fixed summation order, so a problem's result is the same whichever other
 // problems share its launches.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,8 +36,8 @@
 namespace bax {
 
 const char *const kKernelNames[K_NUM_KERNELS] = {
-    "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
-    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_persistent"};
+    "linearize", "point_prep", "schur_diag", "schur_off", "pcg_iter",
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -151,31 +151,6 @@ __device__ inline double block_sum_array(const double *a, int n, double *scratch
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) v += a[i];
   return block_sum256(v, scratch4);
-}
-
-// Sums of three double arrays of length n in one pass (fixed order; a NULL
-// array sums to 0).  Result in every thread.
-__device__ inline void block_sum3(const double *a, const double *b, const double *c, int n,
-                                  double *scratch12, double out[3]) {
-  double va = 0.0, vb = 0.0, vc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    if (a) va += a[i];
-    if (b) vb += b[i];
-    if (c) vc += c[i];
-  }
-  va = wave_sum(va);
-  vb = wave_sum(vb);
-  vc = wave_sum(vc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) {
-    scratch12[w] = va;
-    scratch12[4 + w] = vb;
-    scratch12[8 + w] = vc;
-  }
-  __syncthreads();
-  for (int k = 0; k < 3; ++k)
-    out[k] = scratch12[4 * k] + scratch12[4 * k + 1] + scratch12[4 * k + 2] + scratch12[4 * k + 3];
-  __syncthreads();
 }
 
 template <class T>
@@ -614,6 +589,7 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
   }
   // deterministic block reduction: wave butterflies, then the 4 waves in order
   __shared__ T s_w[4][54];
+  __shared__ int s_last[1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 54; ++i) {
@@ -679,6 +655,24 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
     }
     pd.part_rz0[a] = rz;
     pd.part_bb[a] = bb;
+    __threadfence();
+    const unsigned t = atomicAdd(&st->diag_ticket, 1u);
+    s_last[0] = (t == (unsigned)pd.Cf - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last[0]) return;
+  // the last camera row of the problem starts its PCG: ||b||^2 and r0.z0 in row order
+  __threadfence();
+  __shared__ double s_red[4];
+  const double bbs = block_sum_array(pd.part_bb, pd.Cf, s_red);
+  const double rzs = block_sum_array(pd.part_rz0, pd.Cf, s_red);
+  if (threadIdx.x == 0) {
+    st->pcg_bb = bbs;
+    st->pcg_rz = rzs;
+    st->pcg_beta = 0.0;
+    st->pcg_iters = 0;
+    st->pcg_done = (bbs > 0.0) ? 0 : 1;
+    st->diag_ticket = 0u;
   }
 }
 
@@ -744,66 +738,30 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 }
 
 // ------------------------------------------------------------------ PCG
-// Tile = kPcgRows (= 4) consecutive rows of one problem, one wave per row.
-// Iteration it (0-based):
-//   spmv(it):   it >= 1: stop if ||r_it|| <= tol ||b||; beta = rz_it / rz_{it-1};
-//               p_it = z + beta p_{it-1} (formed on the fly for every column read);
-//               q = S p_it; partial p_it . q.
-//   update(it): alpha = rz_it / (p.q); x += alpha p; r -= alpha q; z = M^-1 r;
-//               partials r.z and r.r.
-// The tile bodies are shared by the two-kernels-per-iteration form and the
-// persistent cooperative form.  A tile reads the problem's PCG flags once, by one
-// thread, and broadcasts them through LDS: another tile of the same problem may
-// set them while this one runs, and every thread must take the same branch.
-
-__device__ inline bool pcg_go(const LMState *st, int it, int *s_flag) {
-  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
-  __syncthreads();
-  const bool go = s_flag[0] != 0;
-  __syncthreads();
-  return go;
-}
-
+// One launch per PCG iteration.  Tile = kPcgRows (= 4) consecutive rows of one
+// problem, one wave per row.  Iteration it (0-based):
+//   every tile:  p_it = z + beta_it p_{it-1} (p_0 = z_0), formed on the fly for
+//                each column it reads; q = S p_it for its rows; partial p_it . q;
+//   last tile:   the workgroup that finishes last (an atomic ticket per problem,
+//                nothing waits) sums the partials in tile order, takes
+//                alpha = rz_it / p.q, updates x, r and z = M^-1 r for every row,
+//                forms rz_{it+1} and ||r||^2 in a fixed order, tests convergence
+//                (||r|| <= tol ||b||) and stores beta_{it+1} for the next launch.
+// The PCG scalars live in the problem's LMState; a tile reads its flags once,
+// by one thread, and broadcasts them through LDS.
 template <class T>
-__device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
+__global__ __launch_bounds__(256) void k_pcg_iter(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
+  const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
   __shared__ int s_flag[1];
   __shared__ double s_red[4];
-  __shared__ double s_pq[4];
-  if (!pcg_go(st, it, s_flag)) return;
-  double beta = 0.0;
-  if (it == 0) {
-    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
-    const double rz0 = block_sum_array(pd.part_rz0, pd.Cf, s_red);
-    if (tl.idx == 0 && threadIdx.x == 0) {
-      st->pcg_bb = bb;
-      st->pcg_rz0 = rz0;
-    }
-    if (!(bb > 0.0)) {
-      if (tl.idx == 0 && threadIdx.x == 0) {
-        st->pcg_done = 1;
-        st->pcg_iters = 0;
-      }
-      return;
-    }
-  } else {
-    __shared__ double s_red3[12];
-    double sums[3];  // r.r, rz_it, rz_{it-1}
-    block_sum3(pd.part_rr, pd.part_rz[it & 1], it == 1 ? nullptr : pd.part_rz[(it - 1) & 1],
-               pd.n_pcg_tiles, s_red3, sums);
-    const double bb = st->pcg_bb;
-    if (sqrt(sums[0]) <= st->pcg_tol * sqrt(bb)) {
-      if (tl.idx == 0 && threadIdx.x == 0) {
-        st->pcg_done = 1;
-        st->pcg_iters = it;
-      }
-      return;
-    }
-    const double rz_old = (it == 1) ? st->pcg_rz0 : sums[2];
-    beta = sums[1] / rz_old;
-  }
-  const T tb = T(beta);
+  __shared__ double s_red2[4];
+  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
+  __syncthreads();
+  if (!s_flag[0]) return;
+  const T tb = T(it == 0 ? 0.0 : st->pcg_beta);
   const T *z = (const T *)pd.z;
   const T *pold = (const T *)((it & 1) ? pd.p0 : pd.p1);  // p_{it-1}
   const T *pin = (const T *)pd.p0;                        // p_0 when it == 0
@@ -847,129 +805,67 @@ __device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, 
       pq = (double)pa * (double)qi;
     }
   }
-  const double tot = block_sum256(pq, s_pq);
-  if (threadIdx.x == 0) pd.part_pq[tl.idx] = tot;
-}
-
-template <class T>
-__device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
-  const ProbDev &pd = probs[tl.prob];
-  LMState *st = pd.st;
-  __shared__ int s_flag[1];
-  __shared__ double s_red[4];
-  __shared__ double s_red2[4];
-  __shared__ T s_r[kPcgRows * 6];
-  if (!pcg_go(st, it, s_flag)) return;
-  __shared__ double s_red3[12];
-  double sums[3];  // p.q, rz_it
-  block_sum3(pd.part_pq, it == 0 ? nullptr : pd.part_rz[it & 1], nullptr, pd.n_pcg_tiles, s_red3, sums);
-  const double pq = sums[0];
-  if (!(pq > 0.0)) {  // breakdown: keep x, stop
-    if (tl.idx == 0 && threadIdx.x == 0) {
+  const double tot = block_sum256(pq, s_red);
+  // hand in this tile's partial; the last tile of the problem performs the update
+  __threadfence();  // every thread's q / p stores become visible device-wide
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pd.part_pq[tl.idx] = tot;
+    __threadfence();
+    const unsigned t = atomicAdd(&st->pcg_ticket, 1u);
+    s_flag[0] = (t == (unsigned)pd.n_pcg_tiles - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_flag[0]) return;
+  __threadfence();
+  const double pqs = block_sum_array(pd.part_pq, pd.n_pcg_tiles, s_red);
+  if (!(pqs > 0.0)) {  // breakdown: keep x, stop
+    if (threadIdx.x == 0) {
       st->pcg_done = 1;
       st->pcg_iters = it + 1;
+      st->pcg_ticket = 0u;
     }
     return;
   }
-  const double rz = (it == 0) ? st->pcg_rz0 : sums[1];
-  const double alpha = rz / pq;
+  const double alpha = st->pcg_rz / pqs;
   const T ta = T(alpha);
   const T *p = (const T *)((it & 1) ? pd.p1 : pd.p0);
-  const T *q = (const T *)pd.q;
   T *x = (T *)pd.x;
   T *r = (T *)pd.r;
-  T *z = (T *)pd.z;
-  const int rbeg = tl.idx * kPcgRows;
-  const int rend = min(pd.Cf, rbeg + kPcgRows);
+  T *zw = (T *)pd.z;
   double rzp = 0.0, rrp = 0.0;
-  // one thread per row element (6 * kPcgRows of them)
-  const int e = threadIdx.x;
-  const int a = rbeg + e / 6;
-  if (e < 6 * kPcgRows && a < rend) {
-    const size_t idx = 6 * (size_t)a + (e % 6);
-    x[idx] = x[idx] + ta * p[idx];
-    const T rn = r[idx] - ta * q[idx];
-    r[idx] = rn;
-    s_r[e] = rn;
-  }
-  __syncthreads();
-  if (e < 6 * kPcgRows && a < rend) {
-    const int i = e % 6;
-    const double *Mi = pd.Minv + 36 * (size_t)a + 6 * i;
-    const T *rr = s_r + 6 * (e / 6);
-    double zi = 0.0;
+  for (int row = threadIdx.x; row < pd.Cf; row += 256) {
+    double rn[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) zi += Mi[m] * (double)rr[m];
-    const T zt = T(zi);
-    z[6 * (size_t)a + i] = zt;
-    rzp = (double)rr[i] * (double)zt;
-    rrp = (double)rr[i] * (double)rr[i];
+    for (int m = 0; m < 6; ++m) {
+      const size_t idx = 6 * (size_t)row + m;
+      x[idx] = x[idx] + ta * p[idx];
+      const T rv = r[idx] - ta * q[idx];
+      r[idx] = rv;
+      rn[m] = (double)rv;
+    }
+    const double *Mi = pd.Minv + 36 * (size_t)row;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double zi = 0.0;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) zi += Mi[6 * m + n] * rn[n];
+      const T zt = T(zi);
+      zw[6 * (size_t)row + m] = zt;
+      rzp += rn[m] * (double)zt;
+      rrp += rn[m] * rn[m];
+    }
   }
-  const double trz = block_sum256(rzp, s_red);
-  const double trr = block_sum256(rrp, s_red2);
+  const double rz_new = block_sum256(rzp, s_red);
+  const double rr = block_sum256(rrp, s_red2);
   if (threadIdx.x == 0) {
-    pd.part_rz[(it + 1) & 1][tl.idx] = trz;
-    pd.part_rr[tl.idx] = trr;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ probs,
-                                                  const Tile *__restrict__ tiles, int it) {
-  pcg_spmv_tile<T>(probs, tiles[blockIdx.x], it);
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ probs,
-                                                    const Tile *__restrict__ tiles, int it) {
-  pcg_update_tile<T>(probs, tiles[blockIdx.x], it);
-}
-
-// Whether a problem's PCG has nothing left to do after update(it).  Decided from
-// values no tile changes between the grid barrier after update(it) and this
-// check, except pcg_done, which spmv(it + 1) may set -- and only when the
-// residual test below already holds -- so every workgroup decides alike.
-__device__ inline bool pcg_finished(const ProbDev &pd, int it, double *s_red, int *s_flag) {
-  const LMState *st = pd.st;
-  if (threadIdx.x == 0) s_flag[0] = (!lm_active(st) || it + 1 >= st->pcg_max || st->pcg_done) ? 1 : 0;
-  __syncthreads();
-  const bool stop = s_flag[0] != 0;
-  __syncthreads();
-  if (stop) return true;
-  const double rr = block_sum_array(pd.part_rr, pd.n_pcg_tiles, s_red);
-  const bool conv = sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb);
-  // the loop may end here, before spmv(it + 1) would record the count; every
-  // workgroup that gets here writes the same values
-  if (conv && blockIdx.x == 0 && threadIdx.x == 0) {
-    LMState *w = pd.st;
-    w->pcg_iters = it + 1;
-    w->pcg_done = 1;
-  }
-  return conv;
-}
-
-// Every PCG iteration of every problem of the batch in one cooperative launch:
-// grid barriers replace the kernel boundaries between the two phases.
-template <class T>
-__global__ __launch_bounds__(256) void k_pcg_persistent(const ProbDev *__restrict__ probs,
-                                                        const Tile *__restrict__ tiles, int n_tiles,
-                                                        int n_probs, int pcg_max) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  __shared__ double s_red[4];
-  __shared__ int s_flag[1];
-  __shared__ int s_all;
-  for (int it = 0; it < pcg_max; ++it) {
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) pcg_spmv_tile<T>(probs, tiles[t], it);
-    grid.sync();
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) pcg_update_tile<T>(probs, tiles[t], it);
-    grid.sync();
-    int all = 1;
-    for (int pi = 0; pi < n_probs && all; ++pi) all = pcg_finished(probs[pi], it, s_red, s_flag) ? 1 : 0;
-    if (threadIdx.x == 0) s_all = all;
-    __syncthreads();
-    const bool done = s_all != 0;
-    __syncthreads();
-    if (done) break;
+    if (sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {
+      st->pcg_done = 1;
+      st->pcg_iters = it + 1;
+    }
+    st->pcg_beta = rz_new / st->pcg_rz;
+    st->pcg_rz = rz_new;
+    st->pcg_ticket = 0u;
   }
 }
 
@@ -1370,8 +1266,7 @@ struct Timed {
 }  // namespace
 
 template <class T, class S>
-static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int pcg_grid, hipStream_t s,
-                               KernelTimer *tm) {
+static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, KernelTimer *tm) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
@@ -1388,26 +1283,9 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int pcg_grid, h
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
-  if (bp.n_pcg && pcg_grid > 0) {
-    Timed t(tm, K_PCG_PERSISTENT, s);
-    const ProbDev *probs = bp.probs;
-    const Tile *tiles = bp.pcg;
-    int n_tiles = bp.n_pcg, n_probs = bp.n_ctl, pm = pcg_max;
-    void *args[] = {(void *)&probs, (void *)&tiles, (void *)&n_tiles, (void *)&n_probs, (void *)&pm};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_pcg_persistent<T>, dim3(pcg_grid), dim3(256),
-                                              args, 0, s);
-    if (e != hipSuccess) return e;
-  } else {
-    for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
-      {
-        Timed t(tm, K_PCG_SPMV, s);
-        k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
-      }
-      {
-        Timed t(tm, K_PCG_UPDATE, s);
-        k_pcg_update<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
-      }
-    }
+  for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
+    Timed t(tm, K_PCG, s);
+    k_pcg_iter<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
   }
   if (bp.n_cam) {
     Timed t(tm, K_CAM_UPDATE, s);
@@ -1424,35 +1302,13 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int pcg_grid, h
   return hipGetLastError();
 }
 
-// Workgroups of the persistent PCG launch: every tile's workgroup must be
-// resident at once for the grid barrier, so the grid is capped by the occupancy
-// of the kernel on this device (0 = use the two-kernel form).
-int pcg_persistent_grid(int precision, int n_tiles) {
-  static int cap[2] = {-1, -1};
-  const int k = precision == 0 ? 0 : 1;
-  if (cap[k] < 0) {
-    int dev = 0, cus = 0, per_cu = 0, coop = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
-      cap[k] = 0;
-    } else {
-      hipError_t e = k == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_persistent<double>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_persistent<float>, 256, 0);
-      cap[k] = (e == hipSuccess && per_cu > 0) ? cus * std::min(per_cu, 2) : 0;
-    }
-  }
-  return std::min(cap[k], n_tiles);
-}
-
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
-                               KernelTimer *timer, bool persistent_pcg) {
-  const int grid = persistent_pcg ? pcg_persistent_grid(precision, bp.n_pcg) : 0;
+                               KernelTimer *timer) {
   switch (precision) {
-    case 0: return lm_iteration<double, double>(bp, pcg_max, grid, s, timer);
-    case 1: return lm_iteration<float, float>(bp, pcg_max, grid, s, timer);
-    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, grid, s, timer);
-    default: return lm_iteration<float, bf16s>(bp, pcg_max, grid, s, timer);
+    case 0: return lm_iteration<double, double>(bp, pcg_max, s, timer);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, s, timer);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, s, timer);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, s, timer);
   }
 }
 

@@ -41,7 +41,7 @@ struct Offsets {
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[6];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
-  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, iter_cost, iter_pcg;
+  size_t part_rz0, part_bb, part_pq, iter_cost, iter_pcg;
   size_t total;
 };
 
@@ -88,6 +88,8 @@ struct EventTimer : KernelTimer {
   std::vector<int> ids;
   size_t used = 0;
   uint32_t mask = 0xffffffffu;  // kernels to time (bit = KernelId)
+  int32_t stride = 1;            // time every stride-th launch of each selected kernel
+  int32_t seen[K_NUM_KERNELS] = {};
   bool active = false;
   void begin(int id, hipStream_t s) override;
   void end(int id, hipStream_t s) override;

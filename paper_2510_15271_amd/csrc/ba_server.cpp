@@ -144,8 +144,6 @@ struct ba_server {
   int64_t n_done = 0;
   size_t peak = 0;
   int fatal = BA_OK;
-  bool persistent_pcg = false;
-
   void loop();
   void finish(const std::vector<ReqP> &done_now);
 };
@@ -237,7 +235,7 @@ void ba_server::loop() {
         dirty = false;
       }
       for (auto &r : active) pcg_max = std::max(pcg_max, r->dp.pcg_max);
-      if (fatal == BA_OK && launch_lm_iteration(precision, batch.plan, pcg_max, stream, nullptr, persistent_pcg) != hipSuccess)
+      if (fatal == BA_OK && launch_lm_iteration(precision, batch.plan, pcg_max, stream, nullptr) != hipSuccess)
         fatal = BA_EDEVICE;
       if (fatal == BA_OK && launch_gather_iters(batch.plan, d_iters, stream) != hipSuccess)
         fatal = BA_EDEVICE;
