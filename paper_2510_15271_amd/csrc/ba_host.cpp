@@ -345,7 +345,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.brhs = L.take(Cf * 6 * T);
   o.S = L.take((size_t)sy.nnzb * 36 * T);
   o.Minv = L.take(Cf * 36 * 8);
-  for (int i = 0; i < 6; ++i) o.vec[i] = L.take(Cf * 6 * T);
+  for (int i = 0; i < 8; ++i) o.vec[i] = L.take(Cf * 6 * T);
   o.part_lin_cost = L.take(npt * 8);
   o.part_masked = L.take(npt * 4);
   o.part_sq = L.take(npt * 8);
@@ -355,7 +355,11 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_dl_cam = L.take(ncam * 8);
   o.part_rz0 = L.take(Cf * 8);
   o.part_bb = L.take(Cf * 8);
+  o.part_rz[0] = L.take(npcg * 8);
+  o.part_rz[1] = L.take(npcg * 8);
   o.part_pq = L.take(npcg * 8);
+  o.part_pq1 = L.take(npcg * 8);
+  o.part_rr = L.take(npcg * 8);
   o.iter_cost = L.take((max_iters + 1) * 8);
   o.iter_pcg = L.take(max_iters * 4);
   o.total = L.off;
@@ -437,6 +441,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.p0 = ptr(off.vec[3]);
   pd.p1 = ptr(off.vec[4]);
   pd.q = ptr(off.vec[5]);
+  pd.r1 = ptr(off.vec[6]);
+  pd.q1 = ptr(off.vec[7]);
   pd.part_lin_cost = (double *)ptr(off.part_lin_cost);
   pd.part_masked = (int32_t *)ptr(off.part_masked);
   pd.part_sq = (double *)ptr(off.part_sq);
@@ -446,7 +452,11 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_dl_cam = (double *)ptr(off.part_dl_cam);
   pd.part_rz0 = (double *)ptr(off.part_rz0);
   pd.part_bb = (double *)ptr(off.part_bb);
+  pd.part_rz[0] = (double *)ptr(off.part_rz[0]);
+  pd.part_rz[1] = (double *)ptr(off.part_rz[1]);
   pd.part_pq = (double *)ptr(off.part_pq);
+  pd.part_pq1 = (double *)ptr(off.part_pq1);
+  pd.part_rr = (double *)ptr(off.part_rr);
   pd.st = (LMState *)ptr(off.st);
   pd.iter_cost = (double *)ptr(off.iter_cost);
   pd.iter_pcg = (int32_t *)ptr(off.iter_pcg);
@@ -739,7 +749,8 @@ int ba_solve_async(ba_problem *p) {
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, nullptr);
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.Cf, p->stream,
+                                 nullptr);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
       if (e != hipSuccess) return hip_fail(e, "graph capture");
@@ -759,7 +770,7 @@ int ba_solve_async(ba_problem *p) {
     p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters; ++it) {
-      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->stream, tm);
+      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.Cf, p->stream, tm);
       if (e != hipSuccess) return hip_fail(e, "kernel launch");
     }
   }

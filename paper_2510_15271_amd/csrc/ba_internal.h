@@ -39,10 +39,9 @@ struct LMState {
   double cost0;
   double trial_cost, dL, rho;
   double lambda0, pcg_tol, huber_delta;
-  double pcg_bb;     // ||b||^2 of the current linear solve
-  double pcg_rz;     // r.z of the current PCG iterate
-  double pcg_beta;   // beta of the next PCG iteration
-  uint32_t diag_ticket, pcg_ticket;  // arrival counters of the last-workgroup steps
+  double pcg_bb, pcg_rz0;  // ||b||^2 and r0.z0 of the current linear solve
+  double pcg_rzh[2];       // r_it . z_it of the fused form, by iteration parity
+  double sq_sum;           // sum ||r||^2 at the final state (evaluation kernel)
   int32_t iter, max_iters, relin, status;
   int32_t accepted, cur, pcg_done, pcg_iters;
   int32_t pcg_max, init_done, n_masked, pad0;
@@ -85,6 +84,7 @@ struct ProbDev {
   void *S;                        // [nnzb][36] T
   double *Minv;                   // [Cf][36]
   void *x, *r, *z, *p0, *p1, *q;  // [6 Cf] T
+  void *r1, *q1;                  // [6 Cf] T: second buffers of the fused PCG form
   // reductions (one partial per tile, summed in a fixed order)
   double *part_lin_cost;          // [n_pt_tiles]
   int32_t *part_masked;           // [n_pt_tiles]
@@ -95,7 +95,10 @@ struct ProbDev {
   double *part_dl_cam;            // [n_cam_tiles]
   double *part_rz0;               // [Cf]
   double *part_bb;                // [Cf]
+  double *part_rz[2];             // [n_pcg_tiles]
   double *part_pq;                // [n_pcg_tiles]
+  double *part_pq1;               // [n_pcg_tiles] second buffer of the fused PCG form
+  double *part_rr;                // [n_pcg_tiles]
   LMState *st;
   double *iter_cost;              // [max_iters + 1]
   int32_t *iter_pcg;              // [max_iters]
@@ -126,8 +129,8 @@ struct KernelTimer {
 };
 
 enum KernelId {
-  K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG, K_CAM_UPDATE, K_POINT_TRIAL,
-  K_LM_CONTROL, K_EVAL, K_POSE_GN, K_NUM_KERNELS
+  K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
+  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_FUSED, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -137,8 +140,9 @@ size_t lin_record_bytes(int precision);
 size_t compute_bytes(int precision);
 
 // Launch one Levenberg-Marquardt iteration for every problem of the plan.
-hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
-                               KernelTimer *timer);
+// max_cf: the largest free-camera count of the plan (selects the PCG form).
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_cf,
+                               hipStream_t s, KernelTimer *timer);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
 // Pose-only Gauss-Newton, one workgroup per request.

@@ -14,11 +14,10 @@
 //   schur_off    one wavefront per upper block S_ab: sum over the points seen
 //                by a and b of -Y_aj W_bj^T from precomputed pair lists, one
 //                wave reduction, written to S_ab and its transpose.
-//   pcg_iter     one launch per PCG iteration: block-sparse S p with the
-//                direction update folded into the product; the workgroup that
-//                finishes last (an atomic ticket, nothing waits on it) sums the
-//                per-tile partials in tile order and updates x, r, z for all
-//                rows with FP64 dot products.  No grid barrier, no float atomics.
+//   pcg_spmv /   block-sparse S p with FP64 dot products; direction update
+//   pcg_update   folded into the product; per-tile partial sums reduced in a
+//                fixed order by every consumer, so no grid barrier and no
+//                float atomics are needed.
 //   cam_update   T <- Exp(dc) T, camera part of the predicted decrease.
 //   point_trial  dp_j = V*_j^-1 (-g_p,j - sum W^T dc), X <- X + dp, trial cost.
 //   lm_control   gain ratio, accept/reject, Nielsen damping update.
@@ -36,8 +35,8 @@
 namespace bax {
 
 const char *const kKernelNames[K_NUM_KERNELS] = {
-    "linearize", "point_prep", "schur_diag", "schur_off", "pcg_iter",
-    "cam_update", "point_trial", "lm_control", "eval", "pose_gn"};
+    "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_fused"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -151,6 +150,31 @@ __device__ inline double block_sum_array(const double *a, int n, double *scratch
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) v += a[i];
   return block_sum256(v, scratch4);
+}
+
+// Sums of three double arrays of length n in one pass (fixed order; a NULL
+// array sums to 0).  Result in every thread.
+__device__ inline void block_sum3(const double *a, const double *b, const double *c, int n,
+                                  double *scratch12, double out[3]) {
+  double va = 0.0, vb = 0.0, vc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    if (a) va += a[i];
+    if (b) vb += b[i];
+    if (c) vc += c[i];
+  }
+  va = wave_sum(va);
+  vb = wave_sum(vb);
+  vc = wave_sum(vc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    scratch12[w] = va;
+    scratch12[4 + w] = vb;
+    scratch12[8 + w] = vc;
+  }
+  __syncthreads();
+  for (int k = 0; k < 3; ++k)
+    out[k] = scratch12[4 * k] + scratch12[4 * k + 1] + scratch12[4 * k + 2] + scratch12[4 * k + 3];
+  __syncthreads();
 }
 
 template <class T>
@@ -589,7 +613,6 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
   }
   // deterministic block reduction: wave butterflies, then the 4 waves in order
   __shared__ T s_w[4][54];
-  __shared__ int s_last[1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 54; ++i) {
@@ -655,24 +678,6 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
     }
     pd.part_rz0[a] = rz;
     pd.part_bb[a] = bb;
-    __threadfence();
-    const unsigned t = atomicAdd(&st->diag_ticket, 1u);
-    s_last[0] = (t == (unsigned)pd.Cf - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last[0]) return;
-  // the last camera row of the problem starts its PCG: ||b||^2 and r0.z0 in row order
-  __threadfence();
-  __shared__ double s_red[4];
-  const double bbs = block_sum_array(pd.part_bb, pd.Cf, s_red);
-  const double rzs = block_sum_array(pd.part_rz0, pd.Cf, s_red);
-  if (threadIdx.x == 0) {
-    st->pcg_bb = bbs;
-    st->pcg_rz = rzs;
-    st->pcg_beta = 0.0;
-    st->pcg_iters = 0;
-    st->pcg_done = (bbs > 0.0) ? 0 : 1;
-    st->diag_ticket = 0u;
   }
 }
 
@@ -738,30 +743,73 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 }
 
 // ------------------------------------------------------------------ PCG
-// One launch per PCG iteration.  Tile = kPcgRows (= 4) consecutive rows of one
-// problem, one wave per row.  Iteration it (0-based):
-//   every tile:  p_it = z + beta_it p_{it-1} (p_0 = z_0), formed on the fly for
-//                each column it reads; q = S p_it for its rows; partial p_it . q;
-//   last tile:   the workgroup that finishes last (an atomic ticket per problem,
-//                nothing waits) sums the partials in tile order, takes
-//                alpha = rz_it / p.q, updates x, r and z = M^-1 r for every row,
-//                forms rz_{it+1} and ||r||^2 in a fixed order, tests convergence
-//                (||r|| <= tol ||b||) and stores beta_{it+1} for the next launch.
-// The PCG scalars live in the problem's LMState; a tile reads its flags once,
-// by one thread, and broadcasts them through LDS.
+// Tile = kPcgRows (= 4) consecutive rows of one problem, one wave per row.
+// Iteration it (0-based):
+//   spmv(it):   it >= 1: stop if ||r_it|| <= tol ||b||; beta = rz_it / rz_{it-1};
+//               p_it = z + beta p_{it-1} (formed on the fly for every column read);
+//               q = S p_it; partial p_it . q.
+//   update(it): alpha = rz_it / (p.q); x += alpha p; r -= alpha q; z = M^-1 r;
+//               partials r.z and r.r.
+// A tile reads the problem's PCG flags once, by one thread, and broadcasts them
+// through LDS: another tile of the same problem may set them while this one
+// runs, and every thread must take the same branch.  (A single launch per
+// iteration, with the last workgroup doing the update, measured slower on
+// MI355X: the device-scope fences it needs cost more than a kernel boundary;
+// so did a cooperative kernel with grid barriers.)
+
+__device__ inline bool pcg_go(const LMState *st, int it, int lim, int *s_flag);
+__device__ inline bool pcg_go(const LMState *st, int it, int *s_flag) {
+  return pcg_go(st, it, it + 1, s_flag);
+}
+// go while the problem is active, not done, and lim <= pcg_max
+__device__ inline bool pcg_go(const LMState *st, int it, int lim, int *s_flag) {
+  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && lim <= st->pcg_max) ? 1 : 0;
+  __syncthreads();
+  const bool go = s_flag[0] != 0;
+  __syncthreads();
+  return go;
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void k_pcg_iter(const ProbDev *__restrict__ probs,
-                                                  const Tile *__restrict__ tiles, int it) {
-  const Tile tl = tiles[blockIdx.x];
+__device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
   __shared__ int s_flag[1];
   __shared__ double s_red[4];
-  __shared__ double s_red2[4];
-  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
-  __syncthreads();
-  if (!s_flag[0]) return;
-  const T tb = T(it == 0 ? 0.0 : st->pcg_beta);
+  __shared__ double s_pq[4];
+  if (!pcg_go(st, it, s_flag)) return;
+  double beta = 0.0;
+  if (it == 0) {
+    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
+    const double rz0 = block_sum_array(pd.part_rz0, pd.Cf, s_red);
+    if (tl.idx == 0 && threadIdx.x == 0) {
+      st->pcg_bb = bb;
+      st->pcg_rz0 = rz0;
+    }
+    if (!(bb > 0.0)) {
+      if (tl.idx == 0 && threadIdx.x == 0) {
+        st->pcg_done = 1;
+        st->pcg_iters = 0;
+      }
+      return;
+    }
+  } else {
+    __shared__ double s_red3[12];
+    double sums[3];  // r.r, rz_it, rz_{it-1}
+    block_sum3(pd.part_rr, pd.part_rz[it & 1], it == 1 ? nullptr : pd.part_rz[(it - 1) & 1],
+               pd.n_pcg_tiles, s_red3, sums);
+    const double bb = st->pcg_bb;
+    if (sqrt(sums[0]) <= st->pcg_tol * sqrt(bb)) {
+      if (tl.idx == 0 && threadIdx.x == 0) {
+        st->pcg_done = 1;
+        st->pcg_iters = it;
+      }
+      return;
+    }
+    const double rz_old = (it == 1) ? st->pcg_rz0 : sums[2];
+    beta = sums[1] / rz_old;
+  }
+  const T tb = T(beta);
   const T *z = (const T *)pd.z;
   const T *pold = (const T *)((it & 1) ? pd.p0 : pd.p1);  // p_{it-1}
   const T *pin = (const T *)pd.p0;                        // p_0 when it == 0
@@ -805,68 +853,207 @@ __global__ __launch_bounds__(256) void k_pcg_iter(const ProbDev *__restrict__ pr
       pq = (double)pa * (double)qi;
     }
   }
-  const double tot = block_sum256(pq, s_red);
-  // hand in this tile's partial; the last tile of the problem performs the update
-  __threadfence();  // every thread's q / p stores become visible device-wide
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    pd.part_pq[tl.idx] = tot;
-    __threadfence();
-    const unsigned t = atomicAdd(&st->pcg_ticket, 1u);
-    s_flag[0] = (t == (unsigned)pd.n_pcg_tiles - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_flag[0]) return;
-  __threadfence();
-  const double pqs = block_sum_array(pd.part_pq, pd.n_pcg_tiles, s_red);
-  if (!(pqs > 0.0)) {  // breakdown: keep x, stop
-    if (threadIdx.x == 0) {
+  const double tot = block_sum256(pq, s_pq);
+  if (threadIdx.x == 0) pd.part_pq[tl.idx] = tot;
+}
+
+template <class T>
+__device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl, int it) {
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  __shared__ int s_flag[1];
+  __shared__ double s_red[4];
+  __shared__ double s_red2[4];
+  __shared__ T s_r[kPcgRows * 6];
+  if (!pcg_go(st, it, s_flag)) return;
+  __shared__ double s_red3[12];
+  double sums[3];  // p.q, rz_it
+  block_sum3(pd.part_pq, it == 0 ? nullptr : pd.part_rz[it & 1], nullptr, pd.n_pcg_tiles, s_red3, sums);
+  const double pq = sums[0];
+  if (!(pq > 0.0)) {  // breakdown: keep x, stop
+    if (tl.idx == 0 && threadIdx.x == 0) {
       st->pcg_done = 1;
       st->pcg_iters = it + 1;
-      st->pcg_ticket = 0u;
     }
     return;
   }
-  const double alpha = st->pcg_rz / pqs;
+  const double rz = (it == 0) ? st->pcg_rz0 : sums[1];
+  const double alpha = rz / pq;
   const T ta = T(alpha);
   const T *p = (const T *)((it & 1) ? pd.p1 : pd.p0);
+  const T *q = (const T *)pd.q;
   T *x = (T *)pd.x;
   T *r = (T *)pd.r;
-  T *zw = (T *)pd.z;
+  T *z = (T *)pd.z;
+  const int rbeg = tl.idx * kPcgRows;
+  const int rend = min(pd.Cf, rbeg + kPcgRows);
   double rzp = 0.0, rrp = 0.0;
+  // one thread per row element (6 * kPcgRows of them)
+  const int e = threadIdx.x;
+  const int a = rbeg + e / 6;
+  if (e < 6 * kPcgRows && a < rend) {
+    const size_t idx = 6 * (size_t)a + (e % 6);
+    x[idx] = x[idx] + ta * p[idx];
+    const T rn = r[idx] - ta * q[idx];
+    r[idx] = rn;
+    s_r[e] = rn;
+  }
+  __syncthreads();
+  if (e < 6 * kPcgRows && a < rend) {
+    const int i = e % 6;
+    const double *Mi = pd.Minv + 36 * (size_t)a + 6 * i;
+    const T *rr = s_r + 6 * (e / 6);
+    double zi = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) zi += Mi[m] * (double)rr[m];
+    const T zt = T(zi);
+    z[6 * (size_t)a + i] = zt;
+    rzp = (double)rr[i] * (double)zt;
+    rrp = (double)rr[i] * (double)rr[i];
+  }
+  const double trz = block_sum256(rzp, s_red);
+  const double trr = block_sum256(rrp, s_red2);
+  if (threadIdx.x == 0) {
+    pd.part_rz[(it + 1) & 1][tl.idx] = trz;
+    pd.part_rr[tl.idx] = trr;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_spmv(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
+  pcg_spmv_tile<T>(probs, tiles[blockIdx.x], it);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles, int it) {
+  pcg_update_tile<T>(probs, tiles[blockIdx.x], it);
+}
+
+// Fused form: one launch per PCG iteration when the reduced system's vectors fit
+// in LDS.  Launch it (1 <= it <= pcg_max) first completes iteration it - 1 --
+// alpha = rz_{it-1} / (p.q) from the previous launch's tile partials, x += alpha p
+// for its own rows -- then forms r_it = r_{it-1} - alpha q_{it-1} and
+// z_it = M^-1 r_it for EVERY row into LDS (each workgroup redundantly, in the same
+// order, so all agree on rz_it and ||r_it|| without a grid barrier), tests
+// convergence, and runs the product q_it = S p_it, p_it = z_it + beta p_{it-1}, for
+// its own rows.  Launch it = pcg_max only completes the last iteration.
+// r, q, p and the p.q partials alternate between two buffers by parity.
+template <class T>
+__global__ __launch_bounds__(256) void k_pcg_fused(const ProbDev *__restrict__ probs,
+                                                   const Tile *__restrict__ tiles, int it) {
+  extern __shared__ double s_dyn[];
+  T *zl = (T *)s_dyn;  // [6 Cf]
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  __shared__ int s_flag[1];
+  __shared__ double s_red[4];
+  __shared__ double s_red2[4];
+  if (!pcg_go(st, it, it, s_flag)) return;  // it == pcg_max still completes the last iteration
+  const int pr = (it - 1) & 1, cu = it & 1;
+  const T *rprev = (const T *)(pr ? pd.r1 : pd.r);
+  const T *qprev = (const T *)(pr ? pd.q1 : pd.q);
+  const T *pprev = (const T *)(pr ? pd.p1 : pd.p0);
+  const double *pq_prev = pr ? pd.part_pq1 : pd.part_pq;
+  T *rcur = (T *)(cu ? pd.r1 : pd.r);
+  T *qcur = (T *)(cu ? pd.q1 : pd.q);
+  T *pcur = (T *)(cu ? pd.p1 : pd.p0);
+  double *pq_cur = cu ? pd.part_pq1 : pd.part_pq;
+  const double rz_prev = (it == 1) ? st->pcg_rz0 : st->pcg_rzh[pr];
+  const double pq = block_sum_array(pq_prev, pd.n_pcg_tiles, s_red);
+  const bool first = tl.idx == 0 && threadIdx.x == 0;
+  if (!(pq > 0.0)) {  // breakdown in iteration it - 1: keep x, stop
+    if (first) {
+      st->pcg_done = 1;
+      st->pcg_iters = it;
+    }
+    return;
+  }
+  const T ta = T(rz_prev / pq);
+  // x_it = x_{it-1} + alpha p_{it-1} for this tile's rows
+  {
+    T *x = (T *)pd.x;
+    const int e = threadIdx.x;
+    const int a = tl.idx * kPcgRows + e / 6;
+    if (e < 6 * kPcgRows && a < pd.Cf) {
+      const size_t idx = 6 * (size_t)a + (e % 6);
+      x[idx] = x[idx] + ta * pprev[idx];
+    }
+  }
+  if (it >= st->pcg_max) {  // the cap: iteration it - 1 was the last one
+    if (first) {
+      st->pcg_done = 1;
+      st->pcg_iters = it;
+    }
+    return;
+  }
+  // r_it and z_it for every row (same assignment of rows to threads in every tile)
+  double rzp = 0.0, rrp = 0.0;
+  const int r0 = tl.idx * kPcgRows, r1 = min(pd.Cf, r0 + kPcgRows);
   for (int row = threadIdx.x; row < pd.Cf; row += 256) {
-    double rn[6];
+    T rn[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       const size_t idx = 6 * (size_t)row + m;
-      x[idx] = x[idx] + ta * p[idx];
-      const T rv = r[idx] - ta * q[idx];
-      r[idx] = rv;
-      rn[m] = (double)rv;
+      rn[m] = rprev[idx] - ta * qprev[idx];
     }
     const double *Mi = pd.Minv + 36 * (size_t)row;
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       double zi = 0.0;
 #pragma unroll
-      for (int n = 0; n < 6; ++n) zi += Mi[6 * m + n] * rn[n];
+      for (int n = 0; n < 6; ++n) zi += Mi[6 * m + n] * (double)rn[n];
       const T zt = T(zi);
-      zw[6 * (size_t)row + m] = zt;
-      rzp += rn[m] * (double)zt;
-      rrp += rn[m] * rn[m];
+      zl[6 * row + m] = zt;
+      rzp += (double)rn[m] * (double)zt;
+      rrp += (double)rn[m] * (double)rn[m];
     }
+    if (row >= r0 && row < r1)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) rcur[6 * (size_t)row + m] = rn[m];
   }
-  const double rz_new = block_sum256(rzp, s_red);
+  const double rz = block_sum256(rzp, s_red);  // includes the barrier that publishes zl
   const double rr = block_sum256(rrp, s_red2);
-  if (threadIdx.x == 0) {
-    if (sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {
+  if (sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {
+    if (first) {
       st->pcg_done = 1;
-      st->pcg_iters = it + 1;
+      st->pcg_iters = it;
     }
-    st->pcg_beta = rz_new / st->pcg_rz;
-    st->pcg_rz = rz_new;
-    st->pcg_ticket = 0u;
+    return;
   }
+  if (first) st->pcg_rzh[cu] = rz;
+  const T tb = T(rz / rz_prev);
+  const T *S = (const T *)pd.S;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / 6, i = lane % 6;
+  double pqp = 0.0;
+  const int a = tl.idx * kPcgRows + w;  // one wave per row
+  if (a < pd.Cf) {
+    T acc = T(0);
+    if (lane < 60) {
+      const int b1 = pd.S_rowptr[a + 1];
+#pragma unroll 2
+      for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
+        const int c = pd.S_col[blk];
+        const T *Srow = S + 36 * (size_t)blk + 6 * i;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc += Srow[m] * (zl[6 * c + m] + tb * pprev[6 * c + m]);
+      }
+    }
+    T qi = T(0);
+#pragma unroll
+    for (int gg = 0; gg < 10; ++gg) qi += __shfl(acc, 6 * gg + i, 64);
+    if (lane < 6) {
+      const T pa = zl[6 * a + lane] + tb * pprev[6 * a + lane];
+      qcur[6 * a + lane] = qi;
+      pcur[6 * a + lane] = pa;
+      pqp = (double)pa * (double)qi;
+    }
+  }
+  const double tot = block_sum256(pqp, s_red);
+  if (threadIdx.x == 0) pq_cur[tl.idx] = tot;
 }
 
 // ------------------------------------------------------------------ camera update
@@ -1265,8 +1452,12 @@ struct Timed {
 };
 }  // namespace
 
+// LDS available to the fused PCG form for z (bytes).
+constexpr size_t kFusedLds = 48 * 1024;
+
 template <class T, class S>
-static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, KernelTimer *tm) {
+static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hipStream_t s,
+                               KernelTimer *tm) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
@@ -1283,9 +1474,27 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, 
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
-  for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
-    Timed t(tm, K_PCG, s);
-    k_pcg_iter<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+  const size_t zbytes = 6 * (size_t)max_cf * sizeof(T);
+  if (bp.n_pcg && zbytes <= kFusedLds) {
+    {
+      Timed t(tm, K_PCG_SPMV, s);
+      k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, 0);
+    }
+    for (int it = 1; it <= pcg_max; ++it) {
+      Timed t(tm, K_PCG_FUSED, s);
+      k_pcg_fused<T><<<bp.n_pcg, 256, zbytes, s>>>(bp.probs, bp.pcg, it);
+    }
+  } else {
+    for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
+      {
+        Timed t(tm, K_PCG_SPMV, s);
+        k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+      }
+      {
+        Timed t(tm, K_PCG_UPDATE, s);
+        k_pcg_update<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, it);
+      }
+    }
   }
   if (bp.n_cam) {
     Timed t(tm, K_CAM_UPDATE, s);
@@ -1302,13 +1511,13 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, hipStream_t s, 
   return hipGetLastError();
 }
 
-hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, hipStream_t s,
-                               KernelTimer *timer) {
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_cf,
+                               hipStream_t s, KernelTimer *timer) {
   switch (precision) {
-    case 0: return lm_iteration<double, double>(bp, pcg_max, s, timer);
-    case 1: return lm_iteration<float, float>(bp, pcg_max, s, timer);
-    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, s, timer);
-    default: return lm_iteration<float, bf16s>(bp, pcg_max, s, timer);
+    case 0: return lm_iteration<double, double>(bp, pcg_max, max_cf, s, timer);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, max_cf, s, timer);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, max_cf, s, timer);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, max_cf, s, timer);
   }
 }
 

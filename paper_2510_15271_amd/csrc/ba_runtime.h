@@ -39,9 +39,9 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_cpos;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col;
-  size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[6];
+  size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[8];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
-  size_t part_rz0, part_bb, part_pq, iter_cost, iter_pcg;
+  size_t part_rz0, part_bb, part_rz[2], part_pq, part_pq1, part_rr, iter_cost, iter_pcg;
   size_t total;
 };
 

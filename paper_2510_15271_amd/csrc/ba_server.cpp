@@ -234,8 +234,13 @@ void ba_server::loop() {
         }
         dirty = false;
       }
-      for (auto &r : active) pcg_max = std::max(pcg_max, r->dp.pcg_max);
-      if (fatal == BA_OK && launch_lm_iteration(precision, batch.plan, pcg_max, stream, nullptr) != hipSuccess)
+      int max_cf = 1;
+      for (auto &r : active) {
+        pcg_max = std::max(pcg_max, r->dp.pcg_max);
+        max_cf = std::max(max_cf, (int)r->dp.Cf);
+      }
+      if (fatal == BA_OK &&
+          launch_lm_iteration(precision, batch.plan, pcg_max, max_cf, stream, nullptr) != hipSuccess)
         fatal = BA_EDEVICE;
       if (fatal == BA_OK && launch_gather_iters(batch.plan, d_iters, stream) != hipSuccess)
         fatal = BA_EDEVICE;
