@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time only whole steps (lets solves replay their graph)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (3 times), to calibrate HBM counters")
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -103,6 +105,16 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the problem is not sharded)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
 
     from paper_2510_15271_amd import ba, build_lib
     if not os.path.exists(ba.LIB_PATH):
