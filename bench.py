@@ -85,17 +85,81 @@ print(json.dumps({"seconds": dt, "n_obs": p.n_obs, "iters": 1}))
                       f"{sec:.1f} s on 1 thread"}
 
 
+def serving_leg(ba, n_ba: int, precision: str) -> dict:
+    """p50/p99 latency of mixed-size streams through the continuous-batching server
+    (submission to result on the host): the 4096-request pose-only localization
+    stream submitted at once, and the first n_ba problems of the 512-problem BA
+    stream (cameras and points log-uniform), first saturated (all submitted at
+    t = 0), then with seeded Poisson arrivals at 0.8 of the saturated rate."""
+    import numpy as np
+    from synth import make_config3_problem, make_config3_sizes, make_config4_requests
+    out = {}
+    reqs = make_config4_requests(4096)
+    srv = ba.Server(8 << 30, 64, precision)
+    t0 = time.perf_counter()
+    tk = [srv.submit_pose(r, iters=10, huber_delta=1.0) for r in reqs]
+    for t in tk:
+        srv.wait(t)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    out["pose_stream"] = {"requests": len(reqs), "correspondences": int(sum(len(r.X) for r in reqs)),
+                          "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                          "requests_per_s": round(len(reqs) / wall, 1), "gn_iters": 10}
+    if n_ba <= 0:
+        return out
+    nc, npt = make_config3_sizes()
+    print(f"bench: generating {n_ba} BA stream problems", flush=True, file=sys.stderr)
+    descs = [ba.scene_desc(make_config3_problem(r, int(nc[r]), int(npt[r]))) for r in range(n_ba)]
+    nobs = [int(d.desc.n_obs) for d in descs]
+    opts = ba.options(max_iters=20, pcg_max_iters=50, pcg_rel_tol=1e-6, precision=precision)
+
+    def run(gaps):
+        srv = ba.Server(8 << 30, 16, precision)
+        t0 = time.perf_counter()
+        tks = []
+        for d, g in zip(descs, gaps):
+            if g > 0:
+                time.sleep(g)
+            tks.append(srv.submit(d, opts))
+        res = [srv.wait(t) for t in tks]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return wall, st, res
+
+    wall, st, res = run([0.0] * n_ba)
+    rate = n_ba / wall
+    out["ba_stream_saturated"] = {"problems": n_ba, "obs_total": sum(nobs), "obs_max": max(nobs),
+                                  "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                                  "solves_per_s": round(rate, 2), "lm_iters": 20,
+                                  "peak_bytes": st["peak_bytes"]}
+    rng = np.random.default_rng(3003)
+    gaps = rng.exponential(1.0 / (0.8 * rate), n_ba)
+    gaps[0] = 0.0
+    wall, st, _ = run(list(gaps))
+    out["ba_stream_poisson_0.8"] = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                                    "solves_per_s": round(n_ba / wall, 2)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16j", "bf16j"])
-    ap.add_argument("--points", type=int, default=250_000)
+    ap.add_argument("--points", type=int, default=None)
+    ap.add_argument("--workload", default="drive", choices=["drive", "loop"],
+                    help="drive: 500-camera sequential drive, ~2M observations, 10 LM iterations "
+                         "(the metric's workload); loop: 3000-camera loop-closed drive, ~11M "
+                         "observations, Huber, 15 LM iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time only whole steps (lets solves replay their graph)")
+    ap.add_argument("--serving", type=int, default=24, metavar="N",
+                    help="BA problems of the mixed-size stream in the serving leg (0: pose stream only, -1: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (3 times), to calibrate HBM counters")
     ap.add_argument("--profile-all", action="store_true",
@@ -119,10 +183,15 @@ def main():
     from paper_2510_15271_amd import ba, build_lib
     if not os.path.exists(ba.LIB_PATH):
         build_lib.build()
-    from synth import make_config1
+    from synth import make_config1, make_config2
 
     print("bench: generating scene", flush=True, file=sys.stderr)
-    scene = make_config1(n_pts=args.points)
+    global LM_ITERS
+    if args.workload == "drive":
+        scene = make_config1(n_pts=args.points or 250_000)
+    else:
+        scene = make_config2(n_pts=args.points or 1_500_000)
+        LM_ITERS = 15
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
                                  flags=ba.FLAG_NO_GRAPH if args.no_graph else 0)
@@ -169,7 +238,7 @@ def main():
     abytes = algorithmic_bytes(dominant, info, args.precision)
     achieved = abytes / avg_launch_s / 1e9 if abytes else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_config1_{args.precision}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}_{args.precision}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             traffic = json.load(f).get("bytes_per_launch")
@@ -193,7 +262,8 @@ def main():
         "dtype": {"f32": "f32", "f64": "f64", "f16j": "f32+f16 storage",
                   "bf16j": "f32+bf16 storage"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"sequential drive BA: {info['n_cams']} cameras (1 fixed), "
+        "config": {"workload": f"{'sequential' if args.workload == 'drive' else 'loop-closed Huber'} "
+                               f"drive BA: {info['n_cams']} cameras (1 fixed), "
                                f"{info['n_pts']} points, {info['n_obs']} observations, "
                                f"{LM_ITERS} LM iterations, PCG 50 / 1e-6",
                    "n_obs": info["n_obs"], "n_pairs": info["n_pairs"],
@@ -202,13 +272,17 @@ def main():
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),
         "final_rms_px": r["rms_px"],
+        "final_cost": r["cost"],
         "roofline": roofline,
     }
+    prob.close()
+    if args.serving >= 0:
+        print("bench: serving streams", flush=True, file=sys.stderr)
+        out["serving"] = serving_leg(ba, args.serving, args.precision)
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", flush=True, file=sys.stderr)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
-    prob.close()
 
 
 if __name__ == "__main__":

@@ -690,6 +690,7 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<ba_problem> p(new ba_problem());
   if (int e = analyse(d, opt, p->sy)) return e;
+  if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
   p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0;
   if (hip_stream) {

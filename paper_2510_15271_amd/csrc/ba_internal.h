@@ -139,6 +139,8 @@ size_t lin_record_bytes(int precision);
 // Size of the compute type (8 or 4).
 size_t compute_bytes(int precision);
 
+// Query device limits that select kernel forms; call before any graph capture.
+int prepare_kernels();
 // Launch one Levenberg-Marquardt iteration for every problem of the plan.
 // max_cf: the largest free-camera count of the plan (selects the PCG form).
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_cf,

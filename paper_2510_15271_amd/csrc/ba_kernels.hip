@@ -1452,8 +1452,32 @@ struct Timed {
 };
 }  // namespace
 
-// LDS available to the fused PCG form for z (bytes).
-constexpr size_t kFusedLds = 48 * 1024;
+// LDS available to the fused PCG form for z (bytes): the device's per-workgroup
+// limit less room for the kernel's static LDS, set once by prepare_kernels().
+static size_t g_fused_lds = 48 * 1024;
+
+int prepare_kernels() {
+  static bool done = false;
+  if (done) return 0;
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return -1;
+  size_t use = lim > 8192 ? (size_t)lim - 4096 : 0;
+  if (use > 48 * 1024) {
+    // dynamic LDS beyond 48 KB must be allowed per kernel
+    if (hipFuncSetAttribute((const void *)k_pcg_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)use) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_pcg_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)use) != hipSuccess) {
+      (void)hipGetLastError();
+      use = 48 * 1024;
+    }
+  }
+  g_fused_lds = use;
+  done = true;
+  return 0;
+}
 
 template <class T, class S>
 static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hipStream_t s,
@@ -1475,7 +1499,7 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hip
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
   const size_t zbytes = 6 * (size_t)max_cf * sizeof(T);
-  if (bp.n_pcg && zbytes <= kFusedLds) {
+  if (bp.n_pcg && zbytes <= g_fused_lds) {
     {
       Timed t(tm, K_PCG_SPMV, s);
       k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, 0);

@@ -345,6 +345,7 @@ int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precis
   if (hbm_budget_bytes < (1 << 20)) return fail(BA_EINVAL, "budget below 1 MiB");
   if (max_slots < 1 || max_slots > 4096) return fail(BA_EINVAL, "max_slots outside [1, 4096]");
   if (precision < BA_PREC_F64 || precision > BA_PREC_BF16J) return fail(BA_EINVAL, "unknown precision");
+  if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
   std::unique_ptr<ba_server> s(new ba_server());
   s->budget = hbm_budget_bytes;
   s->max_slots = max_slots;
