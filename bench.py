@@ -43,8 +43,8 @@ def algorithmic_bytes(kernel: str, info: dict, precision: str) -> float:
         return Nf * (4 + 4 + rec + 6 * T + 3 * T) + Cf * (36 * T + 36 * 8 + 6 * 6 * T)
     if kernel == "schur_off":      # pair list + records and Q once; S blocks out
         return info["n_pairs"] * 8 + Nf * (rec + 6 * T) + info["n_up_blocks"] * 2 * 36 * T
-    if kernel == "pcg_fused":      # S once; r, q, p in and out, x, M^-1 once
-        return info["nnzb"] * (36 * T + 4) + Cf * (6 * T * 7 + 36 * 8)
+    if kernel == "pcg_cg":         # S once; r, u, w, s, p, x in and out once, M^-1 once
+        return info["nnzb"] * (36 * T + 4) + Cf * (6 * T * 12 + 36 * 8)
     if kernel == "pcg_spmv":       # S once + column vectors
         return info["nnzb"] * (36 * T + 4) + Cf * 6 * T * 4
     if kernel == "point_trial":    # records, x, V*^-1, g_p, D_p, X in; X' out; obs re-read for cost

@@ -289,6 +289,25 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
       sy.S_col[tpos] = a;
       sy.up_tpos[u] = tpos;
     }
+  // distinct columns of each PCG tile and each block's position in its tile's list
+  const int ntile = (Cf + kPcgRows - 1) / kPcgRows;
+  sy.tcol_start.assign(ntile + 1, 0);
+  sy.tcol.clear();
+  sy.S_lcol.assign(sy.nnzb, 0);
+  sy.max_tcols = 0;
+  std::vector<int32_t> where(Cf, -1), cols;
+  for (int t = 0; t < ntile; ++t) {
+    cols.clear();
+    const int r0 = t * kPcgRows, r1 = std::min(Cf, r0 + kPcgRows);
+    for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) cols.push_back(sy.S_col[pos]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (size_t i = 0; i < cols.size(); ++i) where[cols[i]] = (int32_t)i;
+    for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) sy.S_lcol[pos] = where[sy.S_col[pos]];
+    sy.tcol.insert(sy.tcol.end(), cols.begin(), cols.end());
+    sy.tcol_start[t + 1] = (int32_t)sy.tcol.size();
+    sy.max_tcols = std::max(sy.max_tcols, (int32_t)cols.size());
+  }
   return BA_OK;
 }
 
@@ -329,6 +348,9 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.diag_pos = L.take(Cf * 4);
   o.S_rowptr = L.take((Cf + 1) * 4);
   o.S_col = L.take(sy.nnzb * 4);
+  o.tcol_start = L.take(sy.tcol_start.size() * 4);
+  o.tcol = L.take(sy.tcol.size() * 4 + 4);
+  o.S_lcol = L.take(sy.nnzb * 4);
   for (int b = 0; b < 2; ++b) o.pose[b] = L.take(C * 12 * 8);
   for (int b = 0; b < 2; ++b) o.X[b] = L.take(P * 3 * 8);
   o.pose_init = L.take(C * 12 * 8);
@@ -345,7 +367,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.brhs = L.take(Cf * 6 * T);
   o.S = L.take((size_t)sy.nnzb * 36 * T);
   o.Minv = L.take(Cf * 36 * 8);
-  for (int i = 0; i < 8; ++i) o.vec[i] = L.take(Cf * 6 * T);
+  for (int i = 0; i < 14; ++i) o.vec[i] = L.take(Cf * 6 * T);
   o.part_lin_cost = L.take(npt * 8);
   o.part_masked = L.take(npt * 4);
   o.part_sq = L.take(npt * 8);
@@ -358,7 +380,8 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_rz[0] = L.take(npcg * 8);
   o.part_rz[1] = L.take(npcg * 8);
   o.part_pq = L.take(npcg * 8);
-  o.part_pq1 = L.take(npcg * 8);
+  o.part_cg[0] = L.take(3 * npcg * 8);
+  o.part_cg[1] = L.take(3 * npcg * 8);
   o.part_rr = L.take(npcg * 8);
   o.iter_cost = L.take((max_iters + 1) * 8);
   o.iter_pcg = L.take(max_iters * 4);
@@ -388,6 +411,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   Cf = sy.Cf;
   P = sy.P;
   N = sy.N;
+  max_tcols = sy.max_tcols;
   plan(sy, precision, max_iters, off);
   dev = base;
   auto ptr = [&](size_t o) { return (void *)(base + o); };
@@ -420,6 +444,10 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.diag_pos = (const int32_t *)ptr(off.diag_pos);
   pd.S_rowptr = (const int32_t *)ptr(off.S_rowptr);
   pd.S_col = (const int32_t *)ptr(off.S_col);
+  pd.tcol_start = (const int32_t *)ptr(off.tcol_start);
+  pd.tcol = (const int32_t *)ptr(off.tcol);
+  pd.S_lcol = (const int32_t *)ptr(off.S_lcol);
+  pd.max_tcols = sy.max_tcols;
   for (int b = 0; b < 2; ++b) {
     pd.pose[b] = (double *)ptr(off.pose[b]);
     pd.X[b] = (double *)ptr(off.X[b]);
@@ -441,8 +469,15 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.p0 = ptr(off.vec[3]);
   pd.p1 = ptr(off.vec[4]);
   pd.q = ptr(off.vec[5]);
-  pd.r1 = ptr(off.vec[6]);
-  pd.q1 = ptr(off.vec[7]);
+  // one-reduction form: r and u of parity 0 alias r and z (written by the diagonal kernel)
+  pd.cg_r[0] = pd.r;
+  pd.cg_u[0] = pd.z;
+  pd.cg_r[1] = ptr(off.vec[6]);
+  pd.cg_u[1] = ptr(off.vec[7]);
+  pd.cg_w[0] = ptr(off.vec[8]);
+  pd.cg_w[1] = ptr(off.vec[9]);
+  pd.cg_s[0] = ptr(off.vec[10]);
+  pd.cg_s[1] = ptr(off.vec[11]);
   pd.part_lin_cost = (double *)ptr(off.part_lin_cost);
   pd.part_masked = (int32_t *)ptr(off.part_masked);
   pd.part_sq = (double *)ptr(off.part_sq);
@@ -455,7 +490,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_rz[0] = (double *)ptr(off.part_rz[0]);
   pd.part_rz[1] = (double *)ptr(off.part_rz[1]);
   pd.part_pq = (double *)ptr(off.part_pq);
-  pd.part_pq1 = (double *)ptr(off.part_pq1);
+  pd.part_cg[0] = (double *)ptr(off.part_cg[0]);
+  pd.part_cg[1] = (double *)ptr(off.part_cg[1]);
   pd.part_rr = (double *)ptr(off.part_rr);
   pd.st = (LMState *)ptr(off.st);
   pd.iter_cost = (double *)ptr(off.iter_cost);
@@ -504,6 +540,9 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));
   chk(up(off.S_rowptr, sy.S_rowptr.data(), sy.S_rowptr.size() * 4));
   chk(up(off.S_col, sy.S_col.data(), sy.S_col.size() * 4));
+  chk(up(off.tcol_start, sy.tcol_start.data(), sy.tcol_start.size() * 4));
+  chk(up(off.tcol, sy.tcol.data(), sy.tcol.size() * 4));
+  chk(up(off.S_lcol, sy.S_lcol.data(), sy.S_lcol.size() * 4));
   staging_d.push_back(std::move(poses));
   chk(up(off.pose[0], staging_d.back().data(), 12 * (size_t)C * 8));
   chk(up(off.X[0], d->points_xyz, 3 * (size_t)P * 8));
@@ -750,7 +789,7 @@ int ba_solve_async(ba_problem *p) {
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.Cf, p->stream,
+        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream,
                                  nullptr);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
@@ -771,7 +810,7 @@ int ba_solve_async(ba_problem *p) {
     p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters; ++it) {
-      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.Cf, p->stream, tm);
+      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream, tm);
       if (e != hipSuccess) return hip_fail(e, "kernel launch");
     }
   }

@@ -40,7 +40,7 @@ struct LMState {
   double trial_cost, dL, rho;
   double lambda0, pcg_tol, huber_delta;
   double pcg_bb, pcg_rz0;  // ||b||^2 and r0.z0 of the current linear solve
-  double pcg_rzh[2];       // r_it . z_it of the fused form, by iteration parity
+  double cg_alpha[2], cg_gamma[2];  // alpha_i, gamma_i of the one-reduction form, by parity
   double sq_sum;           // sum ||r||^2 at the final state (evaluation kernel)
   int32_t iter, max_iters, relin, status;
   int32_t accepted, cur, pcg_done, pcg_iters;
@@ -55,6 +55,7 @@ struct ProbDev {
   int32_t n_up;          // upper off-diagonal blocks of S
   int32_t nnzb;          // blocks of S stored (both triangles + diagonal)
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
+  int32_t max_tcols;     // longest tile column list
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -73,6 +74,9 @@ struct ProbDev {
   const int32_t *diag_pos;        // [Cf]
   const int32_t *S_rowptr;        // [Cf + 1]
   const int32_t *S_col;           // [nnzb]
+  const int32_t *tcol_start;      // [n_pcg_tiles + 1] distinct columns read by each PCG tile
+  const int32_t *tcol;            // their free-camera indices
+  const int32_t *S_lcol;          // [nnzb] position of each block's column in its tile's list
   // state, double-buffered (LMState::cur selects the accepted copy)
   double *pose[2];                // [C][12]: R row-major, then t
   double *X[2];                   // [P][3]
@@ -84,7 +88,8 @@ struct ProbDev {
   void *S;                        // [nnzb][36] T
   double *Minv;                   // [Cf][36]
   void *x, *r, *z, *p0, *p1, *q;  // [6 Cf] T
-  void *r1, *q1;                  // [6 Cf] T: second buffers of the fused PCG form
+  // one-reduction PCG form: u = M^-1 r, w = S u, s = S p; two buffers each (parity)
+  void *cg_r[2], *cg_u[2], *cg_w[2], *cg_s[2];
   // reductions (one partial per tile, summed in a fixed order)
   double *part_lin_cost;          // [n_pt_tiles]
   int32_t *part_masked;           // [n_pt_tiles]
@@ -97,7 +102,7 @@ struct ProbDev {
   double *part_bb;                // [Cf]
   double *part_rz[2];             // [n_pcg_tiles]
   double *part_pq;                // [n_pcg_tiles]
-  double *part_pq1;               // [n_pcg_tiles] second buffer of the fused PCG form
+  double *part_cg[2];             // [3][n_pcg_tiles] r.u, w.u, r.r partials by parity
   double *part_rr;                // [n_pcg_tiles]
   LMState *st;
   double *iter_cost;              // [max_iters + 1]
@@ -130,7 +135,7 @@ struct KernelTimer {
 
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
-  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_FUSED, K_NUM_KERNELS
+  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -142,8 +147,8 @@ size_t compute_bytes(int precision);
 // Query device limits that select kernel forms; call before any graph capture.
 int prepare_kernels();
 // Launch one Levenberg-Marquardt iteration for every problem of the plan.
-// max_cf: the largest free-camera count of the plan (selects the PCG form).
-hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_cf,
+// max_tcols: the longest PCG-tile column list of the plan (selects the PCG form).
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,
                                hipStream_t s, KernelTimer *timer);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);

@@ -14,10 +14,12 @@
 //   schur_off    one wavefront per upper block S_ab: sum over the points seen
 //                by a and b of -Y_aj W_bj^T from precomputed pair lists, one
 //                wave reduction, written to S_ab and its transpose.
-//   pcg_spmv /   block-sparse S p with FP64 dot products; direction update
-//   pcg_update   folded into the product; per-tile partial sums reduced in a
-//                fixed order by every consumer, so no grid barrier and no
-//                float atomics are needed.
+//   cg_start /   block-Jacobi PCG in its one-reduction form, one launch per
+//   cg_step      iteration: block-sparse S u over the columns a tile reads,
+//                FP64 dot products from per-tile partials reduced in a fixed
+//                order by every consumer -- no grid barrier, no float atomics.
+//                (pcg_spmv / pcg_update: the textbook form, two launches per
+//                iteration, for systems whose tile columns exceed LDS.)
 //   cam_update   T <- Exp(dc) T, camera part of the predicted decrease.
 //   point_trial  dp_j = V*_j^-1 (-g_p,j - sum W^T dc), X <- X + dp, trial cost.
 //   lm_control   gain ratio, accept/reject, Nielsen damping update.
@@ -36,7 +38,7 @@ namespace bax {
 
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
-    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_fused"};
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -931,129 +933,222 @@ __global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ 
   pcg_update_tile<T>(probs, tiles[blockIdx.x], it);
 }
 
-// Fused form: one launch per PCG iteration when the reduced system's vectors fit
-// in LDS.  Launch it (1 <= it <= pcg_max) first completes iteration it - 1 --
-// alpha = rz_{it-1} / (p.q) from the previous launch's tile partials, x += alpha p
-// for its own rows -- then forms r_it = r_{it-1} - alpha q_{it-1} and
-// z_it = M^-1 r_it for EVERY row into LDS (each workgroup redundantly, in the same
-// order, so all agree on rz_it and ||r_it|| without a grid barrier), tests
-// convergence, and runs the product q_it = S p_it, p_it = z_it + beta p_{it-1}, for
-// its own rows.  Launch it = pcg_max only completes the last iteration.
-// r, q, p and the p.q partials alternate between two buffers by parity.
+// One-reduction form (Chronopoulos & Gear 1989): the same block-Jacobi PCG
+// iterates with both inner products of an iteration taken in one reduction, so
+// one launch per iteration suffices and a launch reads only the columns its own
+// rows touch.  With u = M^-1 r, w = S u, s = S p:
+//   gamma_i = r_i.u_i, delta_i = w_i.u_i,
+//   beta_i = gamma_i / gamma_{i-1} (beta_0 = 0),
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})   (= gamma_i / p_i.S p_i),
+//   p_i = u_i + beta_i p_{i-1}, s_i = w_i + beta_i s_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i,
+//   u_{i+1} = M^-1 r_{i+1}, w_{i+1} = S u_{i+1}.
+// Launch i sums the tile partials of gamma_i, delta_i and ||r_i||^2 handed in by
+// launch i - 1 (fixed order), tests ||r_i|| <= tol ||b||, then forms s_i, r_{i+1}
+// and u_{i+1} for every column its rows read (into LDS; each column's owner
+// writes them), p_i and x_{i+1} for its rows, w_{i+1} = S u_{i+1} for its rows,
+// and its partials of gamma_{i+1}, delta_{i+1} and ||r_{i+1}||^2.  Vectors and
+// partials alternate between two buffers by parity; the cg_start launch forms
+// w_0 = S u_0 and the first partials.
+__device__ inline void cg_partials(double *part, int n_tiles, int tile, double g, double d, double rr,
+                                   double *s12) {
+  g = wave_sum(g);
+  d = wave_sum(d);
+  rr = wave_sum(rr);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    s12[w] = g;
+    s12[4 + w] = d;
+    s12[8 + w] = rr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[tile] = s12[0] + s12[1] + s12[2] + s12[3];
+    part[n_tiles + tile] = s12[4] + s12[5] + s12[6] + s12[7];
+    part[2 * n_tiles + tile] = s12[8] + s12[9] + s12[10] + s12[11];
+  }
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void k_pcg_fused(const ProbDev *__restrict__ probs,
-                                                   const Tile *__restrict__ tiles, int it) {
-  extern __shared__ double s_dyn[];
-  T *zl = (T *)s_dyn;  // [6 Cf]
+__global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
   __shared__ int s_flag[1];
-  __shared__ double s_red[4];
-  __shared__ double s_red2[4];
-  if (!pcg_go(st, it, it, s_flag)) return;  // it == pcg_max still completes the last iteration
-  const int pr = (it - 1) & 1, cu = it & 1;
-  const T *rprev = (const T *)(pr ? pd.r1 : pd.r);
-  const T *qprev = (const T *)(pr ? pd.q1 : pd.q);
-  const T *pprev = (const T *)(pr ? pd.p1 : pd.p0);
-  const double *pq_prev = pr ? pd.part_pq1 : pd.part_pq;
-  T *rcur = (T *)(cu ? pd.r1 : pd.r);
-  T *qcur = (T *)(cu ? pd.q1 : pd.q);
-  T *pcur = (T *)(cu ? pd.p1 : pd.p0);
-  double *pq_cur = cu ? pd.part_pq1 : pd.part_pq;
-  const double rz_prev = (it == 1) ? st->pcg_rz0 : st->pcg_rzh[pr];
-  const double pq = block_sum_array(pq_prev, pd.n_pcg_tiles, s_red);
-  const bool first = tl.idx == 0 && threadIdx.x == 0;
-  if (!(pq > 0.0)) {  // breakdown in iteration it - 1: keep x, stop
-    if (first) {
-      st->pcg_done = 1;
-      st->pcg_iters = it;
-    }
-    return;
+  __shared__ double s_red[12];
+  if (threadIdx.x == 0) s_flag[0] = lm_active(st) ? 1 : 0;
+  __syncthreads();
+  if (!s_flag[0]) return;
+  const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
+  if (tl.idx == 0 && threadIdx.x == 0) {
+    st->pcg_bb = bb;
+    st->pcg_done = (bb > 0.0) ? 0 : 1;
+    st->pcg_iters = 0;
   }
-  const T ta = T(rz_prev / pq);
-  // x_it = x_{it-1} + alpha p_{it-1} for this tile's rows
-  {
-    T *x = (T *)pd.x;
-    const int e = threadIdx.x;
-    const int a = tl.idx * kPcgRows + e / 6;
-    if (e < 6 * kPcgRows && a < pd.Cf) {
-      const size_t idx = 6 * (size_t)a + (e % 6);
-      x[idx] = x[idx] + ta * pprev[idx];
-    }
-  }
-  if (it >= st->pcg_max) {  // the cap: iteration it - 1 was the last one
-    if (first) {
-      st->pcg_done = 1;
-      st->pcg_iters = it;
-    }
-    return;
-  }
-  // r_it and z_it for every row (same assignment of rows to threads in every tile)
-  double rzp = 0.0, rrp = 0.0;
-  const int r0 = tl.idx * kPcgRows, r1 = min(pd.Cf, r0 + kPcgRows);
-  for (int row = threadIdx.x; row < pd.Cf; row += 256) {
-    T rn[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      const size_t idx = 6 * (size_t)row + m;
-      rn[m] = rprev[idx] - ta * qprev[idx];
-    }
-    const double *Mi = pd.Minv + 36 * (size_t)row;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      double zi = 0.0;
-#pragma unroll
-      for (int n = 0; n < 6; ++n) zi += Mi[6 * m + n] * (double)rn[n];
-      const T zt = T(zi);
-      zl[6 * row + m] = zt;
-      rzp += (double)rn[m] * (double)zt;
-      rrp += (double)rn[m] * (double)rn[m];
-    }
-    if (row >= r0 && row < r1)
-#pragma unroll
-      for (int m = 0; m < 6; ++m) rcur[6 * (size_t)row + m] = rn[m];
-  }
-  const double rz = block_sum256(rzp, s_red);  // includes the barrier that publishes zl
-  const double rr = block_sum256(rrp, s_red2);
-  if (sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {
-    if (first) {
-      st->pcg_done = 1;
-      st->pcg_iters = it;
-    }
-    return;
-  }
-  if (first) st->pcg_rzh[cu] = rz;
-  const T tb = T(rz / rz_prev);
+  if (!(bb > 0.0)) return;
+  const T *u = (const T *)pd.cg_u[0];
+  const T *r = (const T *)pd.cg_r[0];
+  T *w = (T *)pd.cg_w[0];
+  T *sv = (T *)pd.cg_s[0];
+  T *p = (T *)pd.p0;
   const T *S = (const T *)pd.S;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane / 6, i = lane % 6;
-  double pqp = 0.0;
-  const int a = tl.idx * kPcgRows + w;  // one wave per row
+  double pg = 0.0, pdl = 0.0, prr = 0.0;
+  const int a = tl.idx * kPcgRows + wv;
+  if (a < pd.Cf) {
+    T acc = T(0);
+    if (lane < 60) {
+      const int b1 = pd.S_rowptr[a + 1];
+      for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
+        const int c = pd.S_col[blk];
+        const T *Srow = S + 36 * (size_t)blk + 6 * i;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc += Srow[m] * u[6 * c + m];
+      }
+    }
+    T wi = T(0);
+#pragma unroll
+    for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
+    if (lane < 6) {
+      const size_t idx = 6 * (size_t)a + lane;
+      w[idx] = wi;
+      sv[idx] = T(0);  // s_{-1}
+      p[idx] = T(0);   // p_{-1}
+      const double ui = (double)u[idx], ri = (double)r[idx];
+      pg = ri * ui;
+      pdl = (double)wi * ui;
+      prr = ri * ri;
+    }
+  }
+  cg_partials(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_step(const ProbDev *__restrict__ probs,
+                                                 const Tile *__restrict__ tiles, int it) {
+  extern __shared__ double s_dyn[];
+  T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  __shared__ int s_flag[1];
+  __shared__ double s_red[12];
+  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
+  __syncthreads();
+  if (!s_flag[0]) return;
+  const int pr = it & 1, cu = (it + 1) & 1;
+  const int nt = pd.n_pcg_tiles;
+  const double *part = pd.part_cg[pr];
+  double sums[3];
+  block_sum3(part, part + nt, part + 2 * nt, nt, s_red, sums);
+  const double gam = sums[0], del = sums[1], rr = sums[2];
+  const bool first = tl.idx == 0 && threadIdx.x == 0;
+  if (it > 0 && sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {  // converged after it updates
+    if (first) {
+      st->pcg_done = 1;
+      st->pcg_iters = it;
+    }
+    return;
+  }
+  double beta = 0.0, den = del;
+  if (it > 0) {
+    beta = gam / st->cg_gamma[pr];
+    den = del - beta * gam / st->cg_alpha[pr];
+  }
+  if (!(den > 0.0)) {  // p.S p <= 0: breakdown, keep x
+    if (first) {
+      st->pcg_done = 1;
+      st->pcg_iters = it + 1;
+    }
+    return;
+  }
+  const double alpha = gam / den;
+  if (first) {
+    st->cg_alpha[cu] = alpha;
+    st->cg_gamma[cu] = gam;
+  }
+  const T ta = T(alpha), tb = T(beta);
+  const T *r0 = (const T *)pd.cg_r[pr];
+  const T *u0 = (const T *)pd.cg_u[pr];
+  const T *w0 = (const T *)pd.cg_w[pr];
+  const T *s0 = (const T *)pd.cg_s[pr];
+  const T *p0 = (const T *)(pr ? pd.p1 : pd.p0);
+  T *r1 = (T *)pd.cg_r[cu];
+  T *u1 = (T *)pd.cg_u[cu];
+  T *w1 = (T *)pd.cg_w[cu];
+  T *s1 = (T *)pd.cg_s[cu];
+  T *p1 = (T *)(cu ? pd.p1 : pd.p0);
+  T *x = (T *)pd.x;
+  const int row0 = tl.idx * kPcgRows, row1 = min(pd.Cf, row0 + kPcgRows);
+  const int c0 = pd.tcol_start[tl.idx], nc = pd.tcol_start[tl.idx + 1] - c0;
+  // columns: s_it, r_{it+1}, u_{it+1} = M^-1 r_{it+1}; own rows also p_it and x_{it+1}
+  for (int l = threadIdx.x; l < nc; l += 256) {
+    const int c = pd.tcol[c0 + l];
+    const size_t b = 6 * (size_t)c;
+    T sn[6], rn[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      sn[m] = w0[b + m] + tb * s0[b + m];
+      rn[m] = r0[b + m] - ta * sn[m];
+    }
+    const double *Mi = pd.Minv + 36 * (size_t)c;
+    T un[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double z = 0.0;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) z += Mi[6 * m + n] * (double)rn[n];
+      un[m] = T(z);
+      ul[6 * l + m] = un[m];
+    }
+    if (c >= row0 && c < row1) {
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const T pn = u0[b + m] + tb * p0[b + m];
+        p1[b + m] = pn;
+        x[b + m] = x[b + m] + ta * pn;
+        s1[b + m] = sn[m];
+        r1[b + m] = rn[m];
+        u1[b + m] = un[m];
+      }
+    }
+  }
+  __syncthreads();
+  // w_{it+1} = S u_{it+1} for this tile's rows, and the partials of the next iteration
+  const T *S = (const T *)pd.S;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane / 6, i = lane % 6;
+  double pg = 0.0, pdl = 0.0, prr = 0.0;
+  const int a = row0 + wv;
   if (a < pd.Cf) {
     T acc = T(0);
     if (lane < 60) {
       const int b1 = pd.S_rowptr[a + 1];
 #pragma unroll 2
       for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
-        const int c = pd.S_col[blk];
         const T *Srow = S + 36 * (size_t)blk + 6 * i;
+        const T *uc = ul + 6 * pd.S_lcol[blk];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) acc += Srow[m] * (zl[6 * c + m] + tb * pprev[6 * c + m]);
+        for (int m = 0; m < 6; ++m) acc += Srow[m] * uc[m];
       }
     }
-    T qi = T(0);
+    T wi = T(0);
 #pragma unroll
-    for (int gg = 0; gg < 10; ++gg) qi += __shfl(acc, 6 * gg + i, 64);
+    for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
     if (lane < 6) {
-      const T pa = zl[6 * a + lane] + tb * pprev[6 * a + lane];
-      qcur[6 * a + lane] = qi;
-      pcur[6 * a + lane] = pa;
-      pqp = (double)pa * (double)qi;
+      const size_t idx = 6 * (size_t)a + lane;
+      w1[idx] = wi;
+      const int la = pd.S_lcol[pd.diag_pos[a]];
+      const double ui = (double)ul[6 * la + lane];
+      const double ri = (double)r1[idx];  // written by this workgroup's column pass
+      pg = ri * ui;
+      pdl = (double)wi * ui;
+      prr = ri * ri;
     }
   }
-  const double tot = block_sum256(pqp, s_red);
-  if (threadIdx.x == 0) pq_cur[tl.idx] = tot;
+  cg_partials(pd.part_cg[cu], nt, tl.idx, pg, pdl, prr, s_red);
 }
 
 // ------------------------------------------------------------------ camera update
@@ -1466,9 +1561,9 @@ int prepare_kernels() {
   size_t use = lim > 8192 ? (size_t)lim - 4096 : 0;
   if (use > 48 * 1024) {
     // dynamic LDS beyond 48 KB must be allowed per kernel
-    if (hipFuncSetAttribute((const void *)k_pcg_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void *)k_cg_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)use) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_pcg_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipFuncSetAttribute((const void *)k_cg_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)use) != hipSuccess) {
       (void)hipGetLastError();
       use = 48 * 1024;
@@ -1480,7 +1575,7 @@ int prepare_kernels() {
 }
 
 template <class T, class S>
-static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hipStream_t s,
+static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, hipStream_t s,
                                KernelTimer *tm) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
@@ -1498,15 +1593,15 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hip
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
-  const size_t zbytes = 6 * (size_t)max_cf * sizeof(T);
-  if (bp.n_pcg && zbytes <= g_fused_lds) {
+  const size_t ubytes = 6 * (size_t)max_tcols * sizeof(T);
+  if (bp.n_pcg && ubytes <= g_fused_lds) {
     {
       Timed t(tm, K_PCG_SPMV, s);
-      k_pcg_spmv<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg, 0);
+      k_cg_start<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg);
     }
-    for (int it = 1; it <= pcg_max; ++it) {
-      Timed t(tm, K_PCG_FUSED, s);
-      k_pcg_fused<T><<<bp.n_pcg, 256, zbytes, s>>>(bp.probs, bp.pcg, it);
+    for (int it = 0; it < pcg_max; ++it) {
+      Timed t(tm, K_PCG_CG, s);
+      k_cg_step<T><<<bp.n_pcg, 256, ubytes, s>>>(bp.probs, bp.pcg, it);
     }
   } else {
     for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
@@ -1535,13 +1630,13 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_cf, hip
   return hipGetLastError();
 }
 
-hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_cf,
+hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,
                                hipStream_t s, KernelTimer *timer) {
   switch (precision) {
-    case 0: return lm_iteration<double, double>(bp, pcg_max, max_cf, s, timer);
-    case 1: return lm_iteration<float, float>(bp, pcg_max, max_cf, s, timer);
-    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, max_cf, s, timer);
-    default: return lm_iteration<float, bf16s>(bp, pcg_max, max_cf, s, timer);
+    case 0: return lm_iteration<double, double>(bp, pcg_max, max_tcols, s, timer);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, max_tcols, s, timer);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, max_tcols, s, timer);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, max_tcols, s, timer);
   }
 }
 

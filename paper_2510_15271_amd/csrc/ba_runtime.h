@@ -33,15 +33,19 @@ struct Symbolic {
   std::vector<int32_t> up_pair_start;
   std::vector<int2> pairs;
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
+  // distinct columns read by each PCG tile (kPcgRows rows) and, per block, the
+  // position of its column in its tile's list
+  std::vector<int32_t> tcol_start, tcol, S_lcol;
+  int32_t max_tcols = 0;
 };
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_cpos;
-  size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col;
-  size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[8];
+  size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol_start, tcol, S_lcol;
+  size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
-  size_t part_rz0, part_bb, part_rz[2], part_pq, part_pq1, part_rr, iter_cost, iter_pcg;
+  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
   size_t total;
 };
 
@@ -50,6 +54,7 @@ struct DevProblem {
   int precision = BA_PREC_F32, max_iters = 0, pcg_max = 0;
   double lambda0 = 1e-4, pcg_tol = 1e-6, huber = 0.0;
   int32_t C = 0, Cf = 0, P = 0, N = 0;
+  int32_t max_tcols = 0;
   Offsets off{};
   char *dev = nullptr;
   ProbDev view{};

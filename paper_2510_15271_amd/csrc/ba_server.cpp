@@ -237,7 +237,7 @@ void ba_server::loop() {
       int max_cf = 1;
       for (auto &r : active) {
         pcg_max = std::max(pcg_max, r->dp.pcg_max);
-        max_cf = std::max(max_cf, (int)r->dp.Cf);
+        max_cf = std::max(max_cf, (int)r->dp.max_tcols);
       }
       if (fatal == BA_OK &&
           launch_lm_iteration(precision, batch.plan, pcg_max, max_cf, stream, nullptr) != hipSuccess)
