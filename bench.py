@@ -212,9 +212,10 @@ def main():
             print(f"  {k:12s} {ms:9.3f} ms  {n:5d} launches  {100 * ms / tot:5.1f} %",
                   file=sys.stderr)
 
-    # timed region: every 10th launch of the dominant kernel (one in each LM
-    # iteration for the per-iteration kernels) is timed with HIP events on its stream
-    stride = 10 if kt[dominant][1] >= 100 else 1
+    # timed region: the dominant kernel is timed with HIP events on its stream.  The
+    # PCG step is bracketed once per run of launches (50 per LM iteration); other
+    # kernels launched more than 100 times per solve are sampled every 10th launch.
+    stride = 1 if dominant == "pcg_cg" else (10 if kt[dominant][1] >= 100 else 1)
     prob.set_profiling(0 if args.no_kernel_timing else 1 << names.index(dominant), stride)
     dev_ms = []
     dom_ms, dom_launch = 0.0, 0

@@ -156,8 +156,12 @@ void ba_destroy(ba_problem *p);
    ba_set_profiling(p, mask, stride) selects the kernels (bit i of mask = kernel
    i in the order ba_get_kernel_times reports them; -1 all, 0 off) and times
    every stride-th launch of each (events between launches cost time, so a
-   stride keeps the measured solve close to an unmeasured one).  Profiled
-   solves are enqueued launch by launch, not replayed from a graph. */
+   stride keeps the measured solve close to an unmeasured one).  The PCG step
+   kernel ("pcg_cg") is timed once per run of launches (one run per LM
+   iteration) and reports that run's launch count.  Profiled solves are
+   enqueued launch by launch, except when pcg_cg alone is selected: then each
+   LM iteration replays three graphs (before, during and after the PCG run)
+   with the events between them. */
 int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride);
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
                         double *ms, int32_t *launches, int32_t *n_out);

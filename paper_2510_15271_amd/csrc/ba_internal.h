@@ -74,8 +74,7 @@ struct ProbDev {
   const int32_t *diag_pos;        // [Cf]
   const int32_t *S_rowptr;        // [Cf + 1]
   const int32_t *S_col;           // [nnzb]
-  const int32_t *tcol_start;      // [n_pcg_tiles + 1] distinct columns read by each PCG tile
-  const int32_t *tcol;            // their free-camera indices
+  const int32_t *tcol;            // [n_pcg_tiles][max_tcols] distinct columns read by each PCG tile, -1 padded
   const int32_t *S_lcol;          // [nnzb] position of each block's column in its tile's list
   // state, double-buffered (LMState::cur selects the accepted copy)
   double *pose[2];                // [C][12]: R row-major, then t
@@ -127,8 +126,9 @@ struct PoseDev {
 };
 
 // Kernel timing hook: the host records events around launches when set.
+// begin/end bracket `launches` consecutive launches of one kernel.
 struct KernelTimer {
-  virtual void begin(int kernel_id, hipStream_t s) = 0;
+  virtual void begin(int kernel_id, hipStream_t s, int launches) = 0;
   virtual void end(int kernel_id, hipStream_t s) = 0;
   virtual ~KernelTimer() {}
 };
@@ -146,10 +146,16 @@ size_t compute_bytes(int precision);
 
 // Query device limits that select kernel forms; call before any graph capture.
 int prepare_kernels();
-// Launch one Levenberg-Marquardt iteration for every problem of the plan.
-// max_tcols: the longest PCG-tile column list of the plan (selects the PCG form).
+// Whether the PCG runs in its one-reduction form (one launch per iteration) for
+// a plan whose longest tile column list is max_tcols.
+bool one_reduction_pcg(int precision, int max_tcols);
+// Parts of one LM iteration: everything, or the launches before the PCG run, the
+// PCG run itself, and the launches after it (so the run can be timed between graphs).
+enum LmPart { LM_ALL = 0, LM_BEFORE_PCG, LM_PCG, LM_AFTER_PCG };
+// Launch one Levenberg-Marquardt iteration (or a part of it) for every problem of
+// the plan.  max_tcols: the longest PCG-tile column list of the plan (selects the PCG form).
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,
-                               hipStream_t s, KernelTimer *timer);
+                               hipStream_t s, KernelTimer *timer, int part = LM_ALL);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
 // Pose-only Gauss-Newton, one workgroup per request.

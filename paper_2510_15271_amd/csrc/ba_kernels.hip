@@ -1025,130 +1025,277 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   cg_partials(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
 }
 
+// One PCG iteration per launch, 1024 threads per tile of kPcgRows rows.  A
+// launch is short and its data sit in L2 / the Infinity Cache, so its time is
+// set by dependent memory round trips, not bandwidth: every load that does not
+// need this iteration's alpha and beta (the S blocks of the tile's rows, the
+// previous vectors of every column the tile reads, the M^-1 rows, the partial
+// sums and the LM scalars) is issued before the one reduction barrier.
+//   column pass: thread (l, m) owns component m of column l (up to 170 columns
+//                in registers, the rest in a second sweep);
+//   product:     row = one quarter of the block (4 waves x 10 groups of 6 lanes),
+//                cg_pre<T>() S blocks per lane held in registers, group sums by a
+//                fixed shuffle tree, the four waves of a row in order.
+constexpr int kCgThreads = 1024;
 template <class T>
-__global__ __launch_bounds__(256) void k_cg_step(const ProbDev *__restrict__ probs,
-                                                 const Tile *__restrict__ tiles, int it) {
+constexpr int cg_pre() { return sizeof(T) == 4 ? 4 : 1; }  // within 128 VGPRs at 16 waves per CU
+constexpr int kCgColThreads = 1020;  // 170 columns x 6 components
+
+template <class T>
+__device__ inline void cg_column(int m, T tb, T ta, const T (&w0)[6], const T (&s0)[6], const T (&r0)[6],
+                                 const double (&mrow)[6], T &sm, T &rm, T &um) {
+  T sn[6], rn[6];
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    sn[n] = w0[n] + tb * s0[n];
+    rn[n] = r0[n] - ta * sn[n];
+  }
+  double z = 0.0;
+#pragma unroll
+  for (int n = 0; n < 6; ++n) z += mrow[n] * (double)rn[n];
+  um = T(z);
+  sm = sn[0];
+  rm = rn[0];
+#pragma unroll
+  for (int n = 1; n < 6; ++n)
+    if (n == m) {
+      sm = sn[n];
+      rm = rn[n];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_cg_step(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
   extern __shared__ double s_dyn[];
   T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
+  __shared__ double s_red[48];
+  __shared__ T s_w[kPcgRows][4][6];
+  __shared__ T s_ro[kPcgRows][6], s_uo[kPcgRows][6];
+  __shared__ int s_flag[1];
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
-  LMState *st = pd.st;
-  __shared__ int s_flag[1];
-  __shared__ double s_red[12];
-  if (threadIdx.x == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
-  __syncthreads();
-  if (!s_flag[0]) return;
+  const LMState *st = pd.st;
+  const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
   const int nt = pd.n_pcg_tiles;
-  const double *part = pd.part_cg[pr];
-  double sums[3];
-  block_sum3(part, part + nt, part + 2 * nt, nt, s_red, sums);
-  const double gam = sums[0], del = sums[1], rr = sums[2];
-  const bool first = tl.idx == 0 && threadIdx.x == 0;
-  if (it > 0 && sqrt(rr) <= st->pcg_tol * sqrt(st->pcg_bb)) {  // converged after it updates
-    if (first) {
-      st->pcg_done = 1;
-      st->pcg_iters = it;
-    }
-    return;
-  }
-  double beta = 0.0, den = del;
-  if (it > 0) {
-    beta = gam / st->cg_gamma[pr];
-    den = del - beta * gam / st->cg_alpha[pr];
-  }
-  if (!(den > 0.0)) {  // p.S p <= 0: breakdown, keep x
-    if (first) {
-      st->pcg_done = 1;
-      st->pcg_iters = it + 1;
-    }
-    return;
-  }
-  const double alpha = gam / den;
-  if (first) {
-    st->cg_alpha[cu] = alpha;
-    st->cg_gamma[cu] = gam;
-  }
-  const T ta = T(alpha), tb = T(beta);
+  const int row0 = tl.idx * kPcgRows, row1 = min(pd.Cf, row0 + kPcgRows);
+  const int ncmax = pd.max_tcols;
+  const int32_t *tcol = pd.tcol + (size_t)tl.idx * ncmax;
   const T *r0 = (const T *)pd.cg_r[pr];
   const T *u0 = (const T *)pd.cg_u[pr];
   const T *w0 = (const T *)pd.cg_w[pr];
   const T *s0 = (const T *)pd.cg_s[pr];
   const T *p0 = (const T *)(pr ? pd.p1 : pd.p0);
+  const T *S = (const T *)pd.S;
+  T *x = (T *)pd.x;
+  // ---- loads that do not depend on this iteration's scalars
+  const double tol = st->pcg_tol, bb = st->pcg_bb;
+  const double gprev = st->cg_gamma[pr], aprev = st->cg_alpha[pr];
+  double pg = 0.0, pdl = 0.0, prr = 0.0;
+  {
+    const double *part = pd.part_cg[pr];
+    for (int k = t; k < nt; k += kCgThreads) {
+      pg += part[k];
+      pdl += part[nt + k];
+      prr += part[2 * nt + k];
+    }
+  }
+  const int l = t / 6, m = t - 6 * (t / 6);
+  const int c = (t < kCgColThreads && l < ncmax) ? tcol[l] : -1;
+  const bool has_col = c >= 0;
+  T cw[6], cs[6], cr[6];
+  double mrow[6];
+  T u0m = T(0), p0m = T(0), xm = T(0);
+  if (has_col) {
+    const size_t b = 6 * (size_t)c;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      cw[n] = w0[b + n];
+      cs[n] = s0[b + n];
+      cr[n] = r0[b + n];
+      mrow[n] = pd.Minv[36 * (size_t)c + 6 * m + n];
+    }
+  }
+  const bool own = has_col && c >= row0 && c < row1;
+  if (own) {
+    u0m = u0[6 * (size_t)c + m];
+    p0m = p0[6 * (size_t)c + m];
+    xm = x[6 * (size_t)c + m];
+  }
+  const int lane = t & 63, q = (t >> 6) & 3;
+  const int g = lane / 6, i = lane - 6 * (lane / 6);
+  const int a = row0 + (t >> 8);
+  const bool spl = lane < 60 && a < row1;
+  int b0 = 0, b1 = 0;
+  if (spl) {
+    b0 = pd.S_rowptr[a] + 10 * q + g;
+    b1 = pd.S_rowptr[a + 1];
+  }
+  constexpr int kCgPre = cg_pre<T>();
+  T sreg[kCgPre][6];
+  int lreg[kCgPre];
+#pragma unroll
+  for (int k = 0; k < kCgPre; ++k) {
+    const int blk = b0 + 40 * k;
+    lreg[k] = -1;
+    if (blk < b1) {
+      lreg[k] = pd.S_lcol[blk];
+#pragma unroll
+      for (int n = 0; n < 6; ++n) sreg[k][n] = S[36 * (size_t)blk + 6 * i + n];
+    } else {
+#pragma unroll
+      for (int n = 0; n < 6; ++n) sreg[k][n] = T(0);
+    }
+  }
+  // ---- the one reduction: gamma_it, delta_it, ||r_it||^2 and the activity flag
+  if (t == 0) s_flag[0] = (lm_active(st) && !st->pcg_done && it < st->pcg_max) ? 1 : 0;
+  pg = wave_sum(pg);
+  pdl = wave_sum(pdl);
+  prr = wave_sum(prr);
+  if (lane == 0) {
+    s_red[t >> 6] = pg;
+    s_red[16 + (t >> 6)] = pdl;
+    s_red[32 + (t >> 6)] = prr;
+  }
+  __syncthreads();
+  if (!s_flag[0]) return;
+  double gam = 0.0, del = 0.0, rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    gam += s_red[k];
+    del += s_red[16 + k];
+    rr += s_red[32 + k];
+  }
+  const bool first = tl.idx == 0 && t == 0;
+  LMState *stw = pd.st;
+  if (it > 0 && sqrt(rr) <= tol * sqrt(bb)) {  // converged after it updates
+    if (first) {
+      stw->pcg_done = 1;
+      stw->pcg_iters = it;
+    }
+    return;
+  }
+  double beta = 0.0, den = del;
+  if (it > 0) {
+    beta = gam / gprev;
+    den = del - beta * gam / aprev;
+  }
+  if (!(den > 0.0)) {  // p.S p <= 0: breakdown, keep x
+    if (first) {
+      stw->pcg_done = 1;
+      stw->pcg_iters = it + 1;
+    }
+    return;
+  }
+  const double alpha = gam / den;
+  if (first) {
+    stw->cg_alpha[cu] = alpha;
+    stw->cg_gamma[cu] = gam;
+  }
+  const T ta = T(alpha), tb = T(beta);
   T *r1 = (T *)pd.cg_r[cu];
   T *u1 = (T *)pd.cg_u[cu];
   T *w1 = (T *)pd.cg_w[cu];
   T *s1 = (T *)pd.cg_s[cu];
   T *p1 = (T *)(cu ? pd.p1 : pd.p0);
-  T *x = (T *)pd.x;
-  const int row0 = tl.idx * kPcgRows, row1 = min(pd.Cf, row0 + kPcgRows);
-  const int c0 = pd.tcol_start[tl.idx], nc = pd.tcol_start[tl.idx + 1] - c0;
-  // columns: s_it, r_{it+1}, u_{it+1} = M^-1 r_{it+1}; own rows also p_it and x_{it+1}
-  for (int l = threadIdx.x; l < nc; l += 256) {
-    const int c = pd.tcol[c0 + l];
-    const size_t b = 6 * (size_t)c;
-    T sn[6], rn[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      sn[m] = w0[b + m] + tb * s0[b + m];
-      rn[m] = r0[b + m] - ta * sn[m];
+  // ---- columns: s_it, r_{it+1}, u_{it+1} = M^-1 r_{it+1}; own rows also p_it, x_{it+1}
+  // (own-row stores wait until after the last barrier so no barrier waits on them)
+  T sm = T(0), rm = T(0), um = T(0), pn = T(0);
+  if (has_col) {
+    cg_column<T>(m, tb, ta, cw, cs, cr, mrow, sm, rm, um);
+    ul[6 * l + m] = um;
+    if (own) {
+      pn = u0m + tb * p0m;
+      s_ro[c - row0][m] = rm;
+      s_uo[c - row0][m] = um;
     }
-    const double *Mi = pd.Minv + 36 * (size_t)c;
-    T un[6];
+  }
+  for (int k = t + kCgColThreads; k < 6 * ncmax && t < kCgColThreads; k += kCgColThreads) {
+    const int l2 = k / 6, m2 = k - 6 * (k / 6);
+    const int c2 = tcol[l2];
+    if (c2 < 0) break;  // lists are -1 padded: k grows, so no later column follows
+    const size_t b = 6 * (size_t)c2;
+    T w2[6], s2[6], r2[6];
+    double mr2[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      double z = 0.0;
-#pragma unroll
-      for (int n = 0; n < 6; ++n) z += Mi[6 * m + n] * (double)rn[n];
-      un[m] = T(z);
-      ul[6 * l + m] = un[m];
+    for (int n = 0; n < 6; ++n) {
+      w2[n] = w0[b + n];
+      s2[n] = s0[b + n];
+      r2[n] = r0[b + n];
+      mr2[n] = pd.Minv[36 * (size_t)c2 + 6 * m2 + n];
     }
-    if (c >= row0 && c < row1) {
-#pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const T pn = u0[b + m] + tb * p0[b + m];
-        p1[b + m] = pn;
-        x[b + m] = x[b + m] + ta * pn;
-        s1[b + m] = sn[m];
-        r1[b + m] = rn[m];
-        u1[b + m] = un[m];
-      }
+    T sm2, rm2, um2;
+    cg_column<T>(m2, tb, ta, w2, s2, r2, mr2, sm2, rm2, um2);
+    ul[6 * l2 + m2] = um2;
+    if (c2 >= row0 && c2 < row1) {
+      const size_t idx = b + m2;
+      const T pn2 = u0[idx] + tb * p0[idx];
+      p1[idx] = pn2;
+      x[idx] = x[idx] + ta * pn2;
+      s1[idx] = sm2;
+      r1[idx] = rm2;
+      u1[idx] = um2;
+      s_ro[c2 - row0][m2] = rm2;
+      s_uo[c2 - row0][m2] = um2;
     }
   }
   __syncthreads();
-  // w_{it+1} = S u_{it+1} for this tile's rows, and the partials of the next iteration
-  const T *S = (const T *)pd.S;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int g = lane / 6, i = lane % 6;
-  double pg = 0.0, pdl = 0.0, prr = 0.0;
-  const int a = row0 + wv;
-  if (a < pd.Cf) {
-    T acc = T(0);
-    if (lane < 60) {
-      const int b1 = pd.S_rowptr[a + 1];
-#pragma unroll 2
-      for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
-        const T *Srow = S + 36 * (size_t)blk + 6 * i;
-        const T *uc = ul + 6 * pd.S_lcol[blk];
+  // ---- w_{it+1} = S u_{it+1} for the tile's rows
+  T acc = T(0);
+  if (spl) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) acc += Srow[m] * uc[m];
+    for (int k = 0; k < kCgPre; ++k)
+      if (lreg[k] >= 0) {
+        const T *uc = ul + 6 * lreg[k];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) acc += sreg[k][n] * uc[n];
       }
-    }
-    T wi = T(0);
+    for (int blk = b0 + 40 * kCgPre; blk < b1; blk += 40) {
+      const T *Srow = S + 36 * (size_t)blk + 6 * i;
+      const T *uc = ul + 6 * pd.S_lcol[blk];
 #pragma unroll
-    for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
-    if (lane < 6) {
-      const size_t idx = 6 * (size_t)a + lane;
-      w1[idx] = wi;
-      const int la = pd.S_lcol[pd.diag_pos[a]];
-      const double ui = (double)ul[6 * la + lane];
-      const double ri = (double)r1[idx];  // written by this workgroup's column pass
-      pg = ri * ui;
-      pdl = (double)wi * ui;
-      prr = ri * ri;
+      for (int n = 0; n < 6; ++n) acc += Srow[n] * uc[n];
     }
   }
-  cg_partials(pd.part_cg[cu], nt, tl.idx, pg, pdl, prr, s_red);
+  T wi = T(0);
+#pragma unroll
+  for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
+  if (lane < 6 && a < row1) s_w[t >> 8][q][lane] = wi;
+  __syncthreads();
+  if (own) {
+    const size_t idx = 6 * (size_t)c + m;
+    p1[idx] = pn;
+    x[idx] = xm + ta * pn;
+    s1[idx] = sm;
+    r1[idx] = rm;
+    u1[idx] = um;
+  }
+  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (wave 0)
+  if (t < 64) {
+    double g2 = 0.0, d2 = 0.0, q2 = 0.0;
+    if (t < 6 * kPcgRows) {
+      const int rr_ = t / 6, mm = t - 6 * (t / 6);
+      const int a2 = row0 + rr_;
+      if (a2 < row1) {
+        const T w = s_w[rr_][0][mm] + s_w[rr_][1][mm] + s_w[rr_][2][mm] + s_w[rr_][3][mm];
+        w1[6 * (size_t)a2 + mm] = w;
+        const double ui = (double)s_uo[rr_][mm], ri = (double)s_ro[rr_][mm];
+        g2 = ri * ui;
+        d2 = (double)w * ui;
+        q2 = ri * ri;
+      }
+    }
+    g2 = wave_sum(g2);
+    d2 = wave_sum(d2);
+    q2 = wave_sum(q2);
+    if (t == 0) {
+      double *pn = pd.part_cg[cu];
+      pn[tl.idx] = g2;
+      pn[nt + tl.idx] = d2;
+      pn[2 * nt + tl.idx] = q2;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ camera update
@@ -1538,8 +1685,8 @@ struct Timed {
   KernelTimer *t;
   int id;
   hipStream_t s;
-  Timed(KernelTimer *t_, int id_, hipStream_t s_) : t(t_), id(id_), s(s_) {
-    if (t) t->begin(id, s);
+  Timed(KernelTimer *t_, int id_, hipStream_t s_, int launches = 1) : t(t_), id(id_), s(s_) {
+    if (t) t->begin(id, s, launches);
   }
   ~Timed() {
     if (t) t->end(id, s);
@@ -1574,9 +1721,19 @@ int prepare_kernels() {
   return 0;
 }
 
+bool one_reduction_pcg(int precision, int max_tcols) {
+  return 6 * (size_t)max_tcols * (precision == 0 ? 8 : 4) <= g_fused_lds;
+}
+
 template <class T, class S>
 static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, hipStream_t s,
-                               KernelTimer *tm) {
+                               KernelTimer *tm, int part) {
+  const bool before = part == LM_ALL || part == LM_BEFORE_PCG;
+  const bool pcg = part == LM_ALL || part == LM_PCG;
+  const bool after = part == LM_ALL || part == LM_AFTER_PCG;
+  const size_t ubytes = 6 * (size_t)max_tcols * sizeof(T);
+  const bool one_reduction = ubytes <= g_fused_lds;
+  if (before) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
@@ -1593,17 +1750,18 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
   }
-  const size_t ubytes = 6 * (size_t)max_tcols * sizeof(T);
-  if (bp.n_pcg && ubytes <= g_fused_lds) {
-    {
-      Timed t(tm, K_PCG_SPMV, s);
-      k_cg_start<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg);
-    }
-    for (int it = 0; it < pcg_max; ++it) {
-      Timed t(tm, K_PCG_CG, s);
-      k_cg_step<T><<<bp.n_pcg, 256, ubytes, s>>>(bp.probs, bp.pcg, it);
-    }
-  } else {
+  if (bp.n_pcg && one_reduction) {
+    Timed t(tm, K_PCG_SPMV, s);
+    k_cg_start<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg);
+  }
+  }
+  if (pcg && bp.n_pcg && one_reduction) {
+    // one event pair around the whole run: per-launch events would add their own
+    // overhead to launches this short
+    Timed t(tm, K_PCG_CG, s, pcg_max);
+    for (int it = 0; it < pcg_max; ++it)
+      k_cg_step<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.probs, bp.pcg, it);
+  } else if (pcg) {
     for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
       {
         Timed t(tm, K_PCG_SPMV, s);
@@ -1615,6 +1773,7 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
       }
     }
   }
+  if (after) {
   if (bp.n_cam) {
     Timed t(tm, K_CAM_UPDATE, s);
     k_cam_update<T><<<bp.n_cam, 256, 0, s>>>(bp.probs, bp.cam);
@@ -1627,16 +1786,17 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     Timed t(tm, K_LM_CONTROL, s);
     k_lm_control<<<bp.n_ctl, 256, 0, s>>>(bp.probs, bp.ctl);
   }
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,
-                               hipStream_t s, KernelTimer *timer) {
+                               hipStream_t s, KernelTimer *timer, int part) {
   switch (precision) {
-    case 0: return lm_iteration<double, double>(bp, pcg_max, max_tcols, s, timer);
-    case 1: return lm_iteration<float, float>(bp, pcg_max, max_tcols, s, timer);
-    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, max_tcols, s, timer);
-    default: return lm_iteration<float, bf16s>(bp, pcg_max, max_tcols, s, timer);
+    case 0: return lm_iteration<double, double>(bp, pcg_max, max_tcols, s, timer, part);
+    case 1: return lm_iteration<float, float>(bp, pcg_max, max_tcols, s, timer, part);
+    case 2: return lm_iteration<float, _Float16>(bp, pcg_max, max_tcols, s, timer, part);
+    default: return lm_iteration<float, bf16s>(bp, pcg_max, max_tcols, s, timer, part);
   }
 }
 

@@ -35,14 +35,14 @@ struct Symbolic {
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   // distinct columns read by each PCG tile (kPcgRows rows) and, per block, the
   // position of its column in its tile's list
-  std::vector<int32_t> tcol_start, tcol, S_lcol;
+  std::vector<int32_t> tcol, S_lcol;
   int32_t max_tcols = 0;
 };
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_cpos;
-  size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol_start, tcol, S_lcol;
+  size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
   size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
@@ -90,13 +90,13 @@ struct Batch {
 // Per-kernel device time from pairs of HIP events around each launch.
 struct EventTimer : KernelTimer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-  std::vector<int> ids;
+  std::vector<int> ids, counts;
   size_t used = 0;
   uint32_t mask = 0xffffffffu;  // kernels to time (bit = KernelId)
   int32_t stride = 1;            // time every stride-th launch of each selected kernel
   int32_t seen[K_NUM_KERNELS] = {};
   bool active = false;
-  void begin(int id, hipStream_t s) override;
+  void begin(int id, hipStream_t s, int launches) override;
   void end(int id, hipStream_t s) override;
   void reset();
   void reserve(size_t pairs);

@@ -199,3 +199,23 @@ def test_config1_full_size_against_stored_oracle_run(balib):
     assert abs(res["rms_px"] - rms) <= 1e-4
     assert all(b <= a for a, b in zip(res["iter_cost"], res["iter_cost"][1:]))
     assert res["cost"] < 0.5 * res["cost0"]
+
+
+def test_profiled_solves_equal_unprofiled(balib):
+    """Timing changes how launches are issued (graph, segment graphs with events,
+    launch by launch), never what they compute: all three give identical results."""
+    s = make_small_drive(30, 2000, seed=21)
+    p = balib.Problem.from_scene(s, max_iters=5, precision="f32")
+    names = list(p.kernel_times().keys())
+    a = p.solve().result()
+    p.set_profiling(1 << names.index("pcg_cg"))
+    b = p.reset().solve().result()
+    ms, n = p.kernel_times()["pcg_cg"]
+    p.set_profiling(-1)
+    c = p.reset().solve().result()
+    p.close()
+    _say("pcg_cg", ms, "ms over", n, "launches")
+    assert n == 5 * 50 and ms > 0
+    for r in (b, c):
+        assert np.array_equal(r["iter_cost"], a["iter_cost"])
+        assert np.array_equal(r["X"], a["X"]) and np.array_equal(r["q"], a["q"])
