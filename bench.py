@@ -43,6 +43,11 @@ def algorithmic_bytes(kernel: str, info: dict, precision: str) -> float:
         return Nf * (4 + 4 + rec + 6 * T + 3 * T) + Cf * (36 * T + 36 * 8 + 6 * 6 * T)
     if kernel == "schur_off":      # pair list + records and Q once; S blocks out
         return info["n_pairs"] * 8 + Nf * (rec + 6 * T) + info["n_up_blocks"] * 2 * 36 * T
+    if kernel == "schur_chunk":    # records, point blocks, items once; partials out
+        return (Nf * rec + N * 12 + P * (15 * T + 6 * T) + (Nf + info["n_pairs"]) * 4
+                + info["n_entries"] * (16 + 36 * T))
+    if kernel == "schur_reduce":   # partials in; S blocks out (both triangles), M^-1
+        return info["n_entries"] * (4 + 36 * T) + info["nnzb"] * 36 * T + Cf * 36 * 8
     if kernel == "pcg_cg":         # S once; r, u, w, s, p, x in and out once, M^-1 once
         return info["nnzb"] * (36 * T + 4) + Cf * (6 * T * 12 + 36 * 8)
     if kernel == "pcg_spmv":       # S once + column vectors
@@ -269,6 +274,7 @@ def main():
                                f"{LM_ITERS} LM iterations, PCG 50 / 1e-6",
                    "n_obs": info["n_obs"], "n_pairs": info["n_pairs"],
                    "nnzb": info["nnzb"], "precision": args.precision,
+                   "schur_form": "point chunks" if info["schur_form"] else "pair lists",
                    "graph": not args.no_graph},
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),

@@ -77,8 +77,13 @@ typedef struct {
 
 /* ba_options.flags bits.
    BA_FLAG_NO_GRAPH: enqueue the kernels of every solve one by one instead of
-   replaying a HIP graph captured on the first solve. */
+   replaying a HIP graph captured on the first solve.
+   BA_FLAG_PAIR_LISTS: form the Schur complement from per-block observation-pair
+   lists (one wavefront per block of S) instead of point chunks staged in LDS.
+   The pair-list form is also used whenever one point has more free-camera
+   observations than a chunk holds (2048; 1024 in BA_PREC_F64). */
 #define BA_FLAG_NO_GRAPH 2
+#define BA_FLAG_PAIR_LISTS 4
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */
@@ -145,6 +150,9 @@ typedef struct {
   int32_t nnzb;           /* stored 6x6 blocks of S (both triangles and the diagonal)  */
   int32_t n_free_obs;     /* observations in free cameras                             */
   int32_t precision;
+  int32_t schur_form;     /* 1: point chunks staged in LDS, 0: per-block pair lists    */
+  int32_t n_chunks;       /* point chunks (chunk form)                                 */
+  int64_t n_entries;      /* (chunk, block) partial sums (chunk form)                  */
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);
 /* Device bytes held by the problem (the admission byte model of the server). */

@@ -61,7 +61,8 @@ class PoseRequest(C.Structure):
 class ProblemInfo(C.Structure):
     _fields_ = [("n_cams", C.c_int32), ("n_free_cams", C.c_int32), ("n_pts", C.c_int32),
                 ("n_obs", C.c_int32), ("n_pairs", C.c_int64), ("n_up_blocks", C.c_int32),
-                ("nnzb", C.c_int32), ("n_free_obs", C.c_int32), ("precision", C.c_int32)]
+                ("nnzb", C.c_int32), ("n_free_obs", C.c_int32), ("precision", C.c_int32),
+                ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64)]
 
 
 class ServerStats(C.Structure):
@@ -122,6 +123,7 @@ def _check(rc):
 
 
 FLAG_NO_GRAPH = 2
+FLAG_PAIR_LISTS = 4
 
 
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,

@@ -115,12 +115,151 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~BA_FLAG_NO_GRAPH)
+  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   return BA_OK;
 }
 
 // ------------------------------------------------------------------ symbolic analysis
+// Point chunks and their entries (chunk form of the Schur complement).  A chunk
+// is a run of internal points with at most pcap points and ocap records.  For
+// every S block it touches, an entry lists its items in point order: for the
+// diagonal block of camera a the chunk's observations in a; for the upper block
+// (a, b) the chunk's observation pairs (p in a, q in b) of one point.  Entries
+// with many items are handled by a whole wavefront and come first in the chunk.
+static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
+                        const std::vector<int32_t> &up_col, int pcap, int ocap, int ccap) {
+  const int P = sy.P, Cf = sy.Cf;
+  std::vector<int32_t> nf(P, 0);
+  for (int j = 0; j < P; ++j)
+    for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) nf[j] += sy.obs_rpos[k] >= 0;
+  // a chunk closes before it would exceed pcap points, ocap records or ccap cameras
+  sy.ch_pt.assign(1, 0);
+  sy.ch_f0.assign(1, 0);
+  sy.ch_cam_start.assign(1, 0);
+  sy.ch_cam.clear();
+  std::vector<int32_t> lcam(Cf, -1), cams;
+  int32_t rec = 0;
+  for (int j = 0; j < P;) {
+    const int j0 = j;
+    int c = 0;
+    cams.clear();
+    while (j < P && j - j0 < pcap && c + nf[j] <= ocap) {
+      int fresh = 0;
+      for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k)
+        if (sy.obs_rpos[k] >= 0 && lcam[sy.free_idx[sy.obs_cam[k]]] < 0) ++fresh;
+      if ((int)cams.size() + fresh > ccap) break;
+      for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k)
+        if (sy.obs_rpos[k] >= 0) {
+          const int a = sy.free_idx[sy.obs_cam[k]];
+          if (lcam[a] < 0) {
+            lcam[a] = 0;
+            cams.push_back(a);
+          }
+        }
+      c += nf[j++];
+    }
+    if (j == j0) return fail(BA_EDEVICE, "internal: point %d does not fit a chunk", j0);
+    std::sort(cams.begin(), cams.end());
+    for (int a : cams) {
+      lcam[a] = -1;
+      sy.ch_cam.push_back(sy.free_cam[a]);
+    }
+    rec += c;
+    sy.ch_pt.push_back(j);
+    sy.ch_f0.push_back(rec);
+    sy.ch_cam_start.push_back((int32_t)sy.ch_cam.size());
+  }
+  const int n_ch = (int)sy.ch_pt.size() - 1;
+  sy.ch_ent.assign(1, 0);
+  sy.ch_nwave.clear();
+  sy.ent_tgt.clear();
+  sy.ent_cam.clear();
+  sy.ent_slot.clear();
+  sy.ent_start.assign(1, 0);
+  sy.ent_items.clear();
+  sy.n_dent = sy.n_oent = 0;
+  std::vector<std::pair<uint64_t, uint32_t>> it;
+  std::vector<int32_t> la, ll;  // free camera and local record of one point's observations
+  struct Ent {
+    int32_t a, b;
+    size_t i0, i1;
+  };
+  std::vector<Ent> wave, thread;
+  for (int c = 0; c < n_ch; ++c) {
+    it.clear();
+    const int f0 = sy.ch_f0[c];
+    // chunk-local camera index of each free camera of the chunk
+    for (int x = sy.ch_cam_start[c]; x < sy.ch_cam_start[c + 1]; ++x)
+      lcam[sy.free_idx[sy.ch_cam[x]]] = x - sy.ch_cam_start[c];
+    for (int j = sy.ch_pt[c]; j < sy.ch_pt[c + 1]; ++j) {
+      la.clear();
+      ll.clear();
+      for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k)
+        if (sy.obs_rpos[k] >= 0) {
+          la.push_back(sy.free_idx[sy.obs_cam[k]]);
+          ll.push_back(sy.obs_rpos[k] - f0);
+        }
+      for (size_t x = 0; x < la.size(); ++x) {
+        it.push_back({((uint64_t)la[x] << 32) | (uint32_t)la[x], (uint32_t)ll[x]});
+        for (size_t y = x + 1; y < la.size(); ++y)
+          it.push_back({((uint64_t)la[x] << 32) | (uint32_t)la[y], (uint32_t)ll[x] | ((uint32_t)ll[y] << 16)});
+      }
+    }
+    std::stable_sort(it.begin(), it.end(),
+                     [](const std::pair<uint64_t, uint32_t> &p, const std::pair<uint64_t, uint32_t> &q) {
+                       return p.first < q.first;
+                     });
+    wave.clear();
+    thread.clear();
+    for (size_t i = 0; i < it.size();) {
+      size_t e = i;
+      while (e < it.size() && it[e].first == it[i].first) ++e;
+      const int32_t a = (int32_t)(it[i].first >> 32), b = (int32_t)(it[i].first & 0xffffffffu);
+      const Ent en{a, b, i, e};
+      if (a == b || e - i >= (size_t)kChWaveItems) wave.push_back(en);
+      else thread.push_back(en);
+      i = e;
+    }
+    // lanes of a wavefront run their thread-mode entries side by side: group equal lengths
+    std::stable_sort(thread.begin(), thread.end(),
+                     [](const Ent &p, const Ent &q) { return p.i1 - p.i0 > q.i1 - q.i0; });
+    sy.ch_nwave.push_back((int32_t)wave.size());
+    for (const std::vector<Ent> *lst : {&wave, &thread})
+      for (const Ent &en : *lst) {
+        if (en.a == en.b) {
+          sy.ent_tgt.push_back(en.a);
+          sy.ent_cam.push_back(lcam[en.a]);
+          sy.ent_slot.push_back(sy.n_dent++);
+        } else {
+          const auto beg = up_col.begin() + up_rowptr[en.a], end = up_col.begin() + up_rowptr[en.a + 1];
+          const auto pos = std::lower_bound(beg, end, en.b);
+          if (pos == end || *pos != en.b) return fail(BA_EDEVICE, "internal: block (%d, %d) missing", en.a, en.b);
+          sy.ent_tgt.push_back(Cf + (int32_t)(pos - up_col.begin()));
+          sy.ent_cam.push_back(lcam[en.b]);
+          sy.ent_slot.push_back(sy.n_oent++);
+        }
+        for (size_t i = en.i0; i < en.i1; ++i) sy.ent_items.push_back(it[i].second);
+        if (sy.ent_items.size() > (size_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 chunk items");
+        sy.ent_start.push_back((int32_t)sy.ent_items.size());
+      }
+    sy.ch_ent.push_back((int32_t)sy.ent_tgt.size());
+    for (int x = sy.ch_cam_start[c]; x < sy.ch_cam_start[c + 1]; ++x) lcam[sy.free_idx[sy.ch_cam[x]]] = -1;
+  }
+  // entries of each block in chunk order; an entry's partial is stored at its
+  // position in that list (diagonal blocks first), so a block's partials are contiguous
+  const int nblk = Cf + sy.n_up;
+  sy.blk_start.assign(nblk + 1, 0);
+  for (int32_t t : sy.ent_tgt) sy.blk_start[t + 1]++;
+  for (int b = 0; b < nblk; ++b) sy.blk_start[b + 1] += sy.blk_start[b];
+  std::vector<int32_t> bf(sy.blk_start.begin(), sy.blk_start.end() - 1);
+  for (size_t e = 0; e < sy.ent_tgt.size(); ++e) {
+    const int32_t pos = bf[sy.ent_tgt[e]]++;
+    sy.ent_slot[e] = sy.ent_tgt[e] < Cf ? pos : pos - sy.n_dent;
+  }
+  return BA_OK;
+}
+
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   if (!d) return fail(BA_EINVAL, "problem description is NULL");
   if (int e = check_options(opt, false)) return e;
@@ -161,7 +300,28 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   sy.Cf = (int32_t)sy.free_cam.size();
   if (sy.Cf == 0) return fail(BA_EINVAL, "every camera is fixed");
 
-  // order by (point, camera): stable counting sort by camera, then by point
+  const int Cf = sy.Cf;
+  // Internal point order: by first free camera, then the caller's index, so that
+  // consecutive points share a narrow window of cameras (the chunk form's
+  // locality).  Results are returned in the caller's order.
+  std::vector<int32_t> first(P, Cf);
+  for (int64_t k = 0; k < N; ++k) {
+    const int a = sy.free_idx[d->obs[k].cam];
+    if (a >= 0 && a < first[d->obs[k].pt]) first[d->obs[k].pt] = a;
+  }
+  std::vector<int32_t> rank(P);
+  {
+    std::vector<int32_t> c(Cf + 2, 0);
+    for (int j = 0; j < P; ++j) c[first[j] + 1]++;
+    for (int a = 0; a <= Cf; ++a) c[a + 1] += c[a];
+    sy.pt_order.resize(P);
+    for (int j = 0; j < P; ++j) {
+      rank[j] = c[first[j]]++;
+      sy.pt_order[rank[j]] = j;
+    }
+  }
+
+  // order by (internal point, camera): stable counting sort by camera, then by point
   std::vector<int32_t> cnt(std::max(C, P) + 1);
   std::vector<int32_t> by_cam(N), order(N);
   std::fill(cnt.begin(), cnt.begin() + C + 1, 0);
@@ -169,12 +329,12 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   for (int i = 0; i < C; ++i) cnt[i + 1] += cnt[i];
   for (int64_t k = 0; k < N; ++k) by_cam[cnt[d->obs[k].cam]++] = (int32_t)k;
   sy.pt_start.assign(P + 1, 0);
-  for (int64_t k = 0; k < N; ++k) sy.pt_start[d->obs[k].pt + 1]++;
+  for (int64_t k = 0; k < N; ++k) sy.pt_start[rank[d->obs[k].pt] + 1]++;
   for (int j = 0; j < P; ++j) sy.pt_start[j + 1] += sy.pt_start[j];
   std::vector<int32_t> fill(sy.pt_start.begin(), sy.pt_start.end() - 1);
   for (int64_t t = 0; t < N; ++t) {
     const int32_t k = by_cam[t];
-    order[fill[d->obs[k].pt]++] = k;
+    order[fill[rank[d->obs[k].pt]]++] = k;
   }
   sy.obs_cam.resize(N);
   sy.obs_pt.resize(N);
@@ -182,17 +342,30 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   for (int64_t k = 0; k < N; ++k) {
     const ba_obs &o = d->obs[order[k]];
     sy.obs_cam[k] = o.cam;
-    sy.obs_pt[k] = o.pt;
+    sy.obs_pt[k] = rank[o.pt];
     sy.obs_uv[2 * k] = o.u;
     sy.obs_uv[2 * k + 1] = o.v;
   }
   for (int j = 0; j < P; ++j)
     for (int k = sy.pt_start[j] + 1; k < sy.pt_start[j + 1]; ++k)
       if (sy.obs_cam[k] == sy.obs_cam[k - 1])
-        return fail(BA_EINVAL, "point %d observed twice by camera %d", j, sy.obs_cam[k]);
+        return fail(BA_EINVAL, "point %d observed twice by camera %d", sy.pt_order[j], sy.obs_cam[k]);
 
-  // observations of each free camera (positions in the point-major order)
-  const int Cf = sy.Cf;
+  // records: one per observation in a free camera
+  int max_free = 0;
+  sy.Nf = 0;
+  for (int j = 0; j < P; ++j) {
+    int nfj = 0;
+    for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) nfj += sy.free_idx[sy.obs_cam[k]] >= 0;
+    max_free = std::max(max_free, nfj);
+    sy.Nf += nfj;
+  }
+  const int prec = opt->precision;
+  sy.chunked = !(opt->flags & BA_FLAG_PAIR_LISTS) && max_free <= chunk_obs_cap(prec) &&
+               max_free <= chunk_cam_cap(prec) &&
+               chunk_lds_bytes(prec) <= device_lds_limit();
+
+  // observations of each free camera (camera-major slots)
   sy.cam_obs_start.assign(Cf + 1, 0);
   for (int64_t k = 0; k < N; ++k) {
     const int a = sy.free_idx[sy.obs_cam[k]];
@@ -200,25 +373,34 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   }
   for (int a = 0; a < Cf; ++a) sy.cam_obs_start[a + 1] += sy.cam_obs_start[a];
   sy.cam_obs.resize(sy.cam_obs_start[Cf]);
-  sy.obs_cpos.assign(N, -1);
+  std::vector<int32_t> cpos(N, -1);
   {
     std::vector<int32_t> f(sy.cam_obs_start.begin(), sy.cam_obs_start.end() - 1);
     for (int64_t k = 0; k < N; ++k) {
       const int a = sy.free_idx[sy.obs_cam[k]];
       if (a >= 0) {
-        sy.obs_cpos[k] = f[a];
+        cpos[k] = f[a];
         sy.cam_obs[f[a]++] = (int32_t)k;
       }
     }
   }
+  // record of each observation: point-major in the chunk form, camera-major otherwise
+  if (sy.chunked) {
+    sy.obs_rpos.assign(N, -1);
+    int32_t r = 0;
+    for (int64_t k = 0; k < N; ++k)
+      if (sy.free_idx[sy.obs_cam[k]] >= 0) sy.obs_rpos[k] = r++;
+  } else {
+    sy.obs_rpos = cpos;
+  }
 
-  // upper blocks of S row by row, with their observation-pair lists
+  // upper blocks of S row by row (and their observation-pair lists in the pair-list form)
   std::vector<int32_t> up_rowptr(Cf + 1, 0), up_col;
-  std::vector<int64_t> pair_count;  // per upper block
   std::vector<int32_t> rowcnt(Cf, 0), slot(Cf, -1);
   std::vector<int32_t> touched;
   sy.pairs.clear();
   sy.up_pair_start.assign(1, 0);
+  sy.n_pairs = 0;
   for (int a = 0; a < Cf; ++a) {
     touched.clear();
     for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
@@ -232,7 +414,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
     }
     std::sort(touched.begin(), touched.end());
     const int base_blk = (int)up_col.size();
-    int64_t pbase = sy.pairs.size();
+    int64_t pbase = sy.n_pairs;
     std::vector<int64_t> pfill(touched.size());
     for (size_t t = 0; t < touched.size(); ++t) {
       const int b = touched[t];
@@ -241,17 +423,20 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
       pfill[t] = pbase;
       pbase += rowcnt[b];
       if (pbase > (int64_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 observation pairs");
-      sy.up_pair_start.push_back((int32_t)pbase);
+      if (!sy.chunked) sy.up_pair_start.push_back((int32_t)pbase);
     }
-    sy.pairs.resize(pbase);
-    for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
-      const int k = sy.cam_obs[o];
-      const int j = sy.obs_pt[k];
-      for (int kb = k + 1; kb < sy.pt_start[j + 1]; ++kb) {
-        const int b = sy.free_idx[sy.obs_cam[kb]];
-        if (b < 0) continue;
-        const int t = slot[b] - base_blk;
-        sy.pairs[pfill[t]++] = int2{o, sy.obs_cpos[kb]};  // camera-major slots
+    sy.n_pairs = pbase;
+    if (!sy.chunked) {
+      sy.pairs.resize(pbase);
+      for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
+        const int k = sy.cam_obs[o];
+        const int j = sy.obs_pt[k];
+        for (int kb = k + 1; kb < sy.pt_start[j + 1]; ++kb) {
+          const int b = sy.free_idx[sy.obs_cam[kb]];
+          if (b < 0) continue;
+          const int t = slot[b] - base_blk;
+          sy.pairs[pfill[t]++] = int2{o, cpos[kb]};  // camera-major slots
+        }
       }
     }
     for (int b : touched) {
@@ -261,6 +446,11 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
     up_rowptr[a + 1] = (int32_t)up_col.size();
   }
   sy.n_up = (int32_t)up_col.size();
+  if (sy.chunked) {
+    sy.cam_obs.clear();
+    sy.cam_obs.shrink_to_fit();
+    sy.cam_obs_start.clear();
+  }
 
   // full block rows of S: lower blocks (transposes), the diagonal, upper blocks
   std::vector<int32_t> n_low(Cf, 0);
@@ -309,6 +499,8 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   sy.tcol.assign((size_t)ntile * sy.max_tcols, -1);
   for (int t = 0; t < ntile; ++t)
     std::copy(lists[t].begin(), lists[t].end(), sy.tcol.begin() + (size_t)t * sy.max_tcols);
+  if (sy.chunked)
+    return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
   return BA_OK;
 }
 
@@ -339,11 +531,25 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.obs_pt = L.take(N * 4);
   o.obs_uv = L.take(N * 2 * T);
   o.pt_start = L.take((P + 1) * 4);
+  o.obs_rpos = L.take(N * 4);
   o.cam_obs = L.take(sy.cam_obs.size() * 4 + 4);
-  o.cam_obs_start = L.take((Cf + 1) * 4);
-  o.obs_cpos = L.take(N * 4);
-  o.up_pair_start = L.take((sy.n_up + 1) * 4);
+  o.cam_obs_start = L.take(sy.cam_obs_start.size() * 4 + 4);
+  o.up_pair_start = L.take(sy.up_pair_start.size() * 4 + 4);
   o.pairs = L.take(sy.pairs.size() * sizeof(int2) + 8);
+  o.ch_pt = L.take(sy.ch_pt.size() * 4 + 4);
+  o.ch_f0 = L.take(sy.ch_f0.size() * 4 + 4);
+  o.ch_ent = L.take(sy.ch_ent.size() * 4 + 4);
+  o.ch_nwave = L.take(sy.ch_nwave.size() * 4 + 4);
+  o.ch_cam_start = L.take(sy.ch_cam_start.size() * 4 + 4);
+  o.ch_cam = L.take(sy.ch_cam.size() * 4 + 4);
+  o.ent_tgt = L.take(sy.ent_tgt.size() * 4 + 4);
+  o.ent_cam = L.take(sy.ent_cam.size() * 4 + 4);
+  o.ent_slot = L.take(sy.ent_slot.size() * 4 + 4);
+  o.ent_start = L.take(sy.ent_start.size() * 4 + 4);
+  o.ent_items = L.take(sy.ent_items.size() * 4 + 4);
+  o.blk_start = L.take(sy.blk_start.size() * 4 + 4);
+  o.part_d = L.take((size_t)sy.n_dent * 54 * T + 16);
+  o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
   o.up_pos = L.take(sy.n_up * 4 + 4);
   o.up_tpos = L.take(sy.n_up * 4 + 4);
   o.diag_pos = L.take(Cf * 4);
@@ -355,9 +561,9 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   for (int b = 0; b < 2; ++b) o.X[b] = L.take(P * 3 * 8);
   o.pose_init = L.take(C * 12 * 8);
   o.X_init = L.take(P * 3 * 8);
-  const size_t Nf = sy.cam_obs.size();
+  const size_t Nf = sy.Nf;
   o.lin = L.take(Nf * lin_record_bytes(precision) + 16);
-  o.Q = L.take(Nf * 6 * T + 16);
+  o.Q = L.take((sy.chunked ? 0 : Nf * 6 * T) + 16);
   o.V = L.take(P * 6 * T);
   o.gp = L.take(P * 3 * T);
   o.Dp = L.take(P * 3 * T);
@@ -412,6 +618,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   P = sy.P;
   N = sy.N;
   max_tcols = sy.max_tcols;
+  pt_order = sy.pt_order;
   plan(sy, precision, max_iters, off);
   dev = base;
   auto ptr = [&](size_t o) { return (void *)(base + o); };
@@ -421,7 +628,11 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.Cf = Cf;
   pd.P = P;
   pd.N = N;
-  pd.Nf = (int32_t)sy.cam_obs.size();
+  pd.Nf = sy.Nf;
+  pd.chunked = sy.chunked ? 1 : 0;
+  pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
+  pd.n_red_tiles = sy.chunked ? (sy.n_up + 3) / 4 : 0;
+  pd.n_fin_tiles = sy.chunked ? (Cf + 3) / 4 : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
@@ -434,11 +645,26 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.obs_pt = (const int32_t *)ptr(off.obs_pt);
   pd.obs_uv = ptr(off.obs_uv);
   pd.pt_start = (const int32_t *)ptr(off.pt_start);
+  pd.obs_rpos = (const int32_t *)ptr(off.obs_rpos);
   pd.cam_obs = (const int32_t *)ptr(off.cam_obs);
   pd.cam_obs_start = (const int32_t *)ptr(off.cam_obs_start);
-  pd.obs_cpos = (const int32_t *)ptr(off.obs_cpos);
   pd.up_pair_start = (const int32_t *)ptr(off.up_pair_start);
   pd.pairs = (const int2 *)ptr(off.pairs);
+  pd.ch_pt = (const int32_t *)ptr(off.ch_pt);
+  pd.ch_f0 = (const int32_t *)ptr(off.ch_f0);
+  pd.ch_ent = (const int32_t *)ptr(off.ch_ent);
+  pd.ch_nwave = (const int32_t *)ptr(off.ch_nwave);
+  pd.ch_cam_start = (const int32_t *)ptr(off.ch_cam_start);
+  pd.ch_cam = (const int32_t *)ptr(off.ch_cam);
+  pd.ent_tgt = (const int32_t *)ptr(off.ent_tgt);
+  pd.ent_cam = (const int32_t *)ptr(off.ent_cam);
+  pd.ent_slot = (const int32_t *)ptr(off.ent_slot);
+  pd.ent_start = (const int32_t *)ptr(off.ent_start);
+  pd.ent_items = (const uint32_t *)ptr(off.ent_items);
+  pd.blk_start = (const int32_t *)ptr(off.blk_start);
+  pd.n_dent = sy.n_dent;
+  pd.part_d = ptr(off.part_d);
+  pd.part_o = ptr(off.part_o);
   pd.up_pos = (const int32_t *)ptr(off.up_pos);
   pd.up_tpos = (const int32_t *)ptr(off.up_tpos);
   pd.diag_pos = (const int32_t *)ptr(off.diag_pos);
@@ -529,11 +755,23 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.obs_cam, sy.obs_cam.data(), sy.obs_cam.size() * 4));
   chk(up(off.obs_pt, sy.obs_pt.data(), sy.obs_pt.size() * 4));
   chk(up(off.pt_start, sy.pt_start.data(), sy.pt_start.size() * 4));
+  chk(up(off.obs_rpos, sy.obs_rpos.data(), sy.obs_rpos.size() * 4));
   chk(up(off.cam_obs, sy.cam_obs.data(), sy.cam_obs.size() * 4));
   chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
-  chk(up(off.obs_cpos, sy.obs_cpos.data(), sy.obs_cpos.size() * 4));
   chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
   chk(up(off.pairs, sy.pairs.data(), sy.pairs.size() * sizeof(int2)));
+  chk(up(off.ch_pt, sy.ch_pt.data(), sy.ch_pt.size() * 4));
+  chk(up(off.ch_f0, sy.ch_f0.data(), sy.ch_f0.size() * 4));
+  chk(up(off.ch_ent, sy.ch_ent.data(), sy.ch_ent.size() * 4));
+  chk(up(off.ch_nwave, sy.ch_nwave.data(), sy.ch_nwave.size() * 4));
+  chk(up(off.ch_cam_start, sy.ch_cam_start.data(), sy.ch_cam_start.size() * 4));
+  chk(up(off.ch_cam, sy.ch_cam.data(), sy.ch_cam.size() * 4));
+  chk(up(off.ent_tgt, sy.ent_tgt.data(), sy.ent_tgt.size() * 4));
+  chk(up(off.ent_cam, sy.ent_cam.data(), sy.ent_cam.size() * 4));
+  chk(up(off.ent_slot, sy.ent_slot.data(), sy.ent_slot.size() * 4));
+  chk(up(off.ent_start, sy.ent_start.data(), sy.ent_start.size() * 4));
+  chk(up(off.ent_items, sy.ent_items.data(), sy.ent_items.size() * 4));
+  chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
   chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));
   chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));
@@ -543,9 +781,13 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.S_lcol, sy.S_lcol.data(), sy.S_lcol.size() * 4));
   staging_d.push_back(std::move(poses));
   chk(up(off.pose[0], staging_d.back().data(), 12 * (size_t)C * 8));
-  chk(up(off.X[0], d->points_xyz, 3 * (size_t)P * 8));
   chk(up(off.pose_init, staging_d.back().data(), 12 * (size_t)C * 8));
-  chk(up(off.X_init, d->points_xyz, 3 * (size_t)P * 8));
+  std::vector<double> Xi(3 * (size_t)P);  // points in the internal order
+  for (int j = 0; j < P; ++j)
+    for (int m = 0; m < 3; ++m) Xi[3 * (size_t)j + m] = d->points_xyz[3 * (size_t)pt_order[j] + m];
+  staging_d.push_back(std::move(Xi));
+  chk(up(off.X[0], staging_d.back().data(), 3 * (size_t)P * 8));
+  chk(up(off.X_init, staging_d.back().data(), 3 * (size_t)P * 8));
   host_state = LMState{};
   host_state.cur = 0;
   if (e != hipSuccess) return hip_fail(e, "upload");
@@ -582,8 +824,15 @@ void Batch::add(const ProbDev &pd, int slot_tag) {
   probs.push_back(pd);
   tags.push_back(slot_tag);
   for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[0].push_back(Tile{pi, t});
-  for (int a = 0; a < pd.Cf; ++a) tiles[1].push_back(Tile{pi, a});
-  for (int t = 0; t < (pd.n_up + kOffWaves - 1) / kOffWaves; ++t) tiles[2].push_back(Tile{pi, t});
+  if (pd.chunked) {
+    for (int c = 0; c < pd.n_ch; ++c) tiles[7].push_back(Tile{pi, c});
+    for (int t = 0; t < pd.n_red_tiles; ++t) tiles[8].push_back(Tile{pi, t});
+    for (int t = 0; t < pd.n_fin_tiles; ++t) tiles[9].push_back(Tile{pi, t});
+  } else {
+    for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[6].push_back(Tile{pi, t});
+    for (int a = 0; a < pd.Cf; ++a) tiles[1].push_back(Tile{pi, a});
+    for (int t = 0; t < (pd.n_up + kOffWaves - 1) / kOffWaves; ++t) tiles[2].push_back(Tile{pi, t});
+  }
   for (int t = 0; t < pd.n_pcg_tiles; ++t) tiles[3].push_back(Tile{pi, t});
   for (int t = 0; t < pd.n_cam_tiles; ++t) tiles[4].push_back(Tile{pi, t});
   tiles[5].push_back(Tile{pi, 0});
@@ -607,9 +856,11 @@ static void xcd_contiguous(std::vector<Tile> &v) {
 
 int Batch::upload(hipStream_t s) {
   xcd_contiguous(tiles[2]);
+  xcd_contiguous(tiles[7]);
   size_t need = probs.size() * sizeof(ProbDev);
-  size_t offs[6];
-  for (int i = 0; i < 6; ++i) {
+  constexpr int NL = 10;
+  size_t offs[NL];
+  for (int i = 0; i < NL; ++i) {
     need = (need + 255) & ~size_t(255);
     offs[i] = need;
     need += tiles[i].size() * sizeof(Tile);
@@ -624,15 +875,17 @@ int Batch::upload(hipStream_t s) {
   }
   host.assign(need, 0);
   std::memcpy(host.data(), probs.data(), probs.size() * sizeof(ProbDev));
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < NL; ++i)
     std::memcpy(host.data() + offs[i], tiles[i].data(), tiles[i].size() * sizeof(Tile));
   hipError_t e = hipMemcpyAsync(dev, host.data(), need, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "batch table upload");
   char *b = (char *)dev;
   plan.probs = (const ProbDev *)b;
-  const Tile **dst[6] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam, &plan.ctl};
-  int32_t *cnt[6] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam, &plan.n_ctl};
-  for (int i = 0; i < 6; ++i) {
+  const Tile **dst[NL] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam,
+                          &plan.ctl, &plan.pp, &plan.ch, &plan.red, &plan.fin};
+  int32_t *cnt[NL] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam,
+                      &plan.n_ctl, &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin};
+  for (int i = 0; i < NL; ++i) {
     *dst[i] = (const Tile *)(b + offs[i]);
     *cnt[i] = (int32_t)tiles[i].size();
   }
@@ -780,9 +1033,11 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
     return rc;
   }
   // the host copies needed later are the sizes only; drop the big arrays
-  p->n_pairs = (int64_t)p->sy.pairs.size();
+  p->n_pairs = p->sy.n_pairs;
   p->sy.pairs.clear();
   p->sy.pairs.shrink_to_fit();
+  p->sy.ent_items.clear();
+  p->sy.ent_items.shrink_to_fit();
   p->dp.staging_f.clear();
   p->dp.staging_d.clear();
   p->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -921,8 +1176,11 @@ int ba_get_info(const ba_problem *p, ba_problem_info *out) {
   out->n_pairs = p->n_pairs;
   out->n_up_blocks = p->sy.n_up;
   out->nnzb = p->sy.nnzb;
-  out->n_free_obs = (int32_t)p->sy.cam_obs.size();
+  out->n_free_obs = p->sy.Nf;
   out->precision = p->dp.precision;
+  out->schur_form = p->sy.chunked ? 1 : 0;
+  out->n_chunks = p->sy.chunked ? (int32_t)p->sy.ch_pt.size() - 1 : 0;
+  out->n_entries = (int64_t)p->sy.ent_tgt.size();
   return BA_OK;
 }
 
@@ -982,8 +1240,11 @@ int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_ou
     for (int i = 0; i < C; ++i) poses_out[i] = pose12_to_quat(&buf[12 * (size_t)i]);
   }
   if (points_out) {
-    e = hipMemcpy(points_out, view.X[cur], 3 * (size_t)P * 8, hipMemcpyDeviceToHost);
+    std::vector<double> buf(3 * (size_t)P);
+    e = hipMemcpy(buf.data(), view.X[cur], buf.size() * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "point download");
+    for (int j = 0; j < P; ++j)
+      for (int m = 0; m < 3; ++m) points_out[3 * (size_t)pt_order[j] + m] = buf[3 * (size_t)j + m];
   }
   if (rep) {
     double *ic = rep->iter_cost;

@@ -19,6 +19,22 @@ constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile (one
 constexpr int kCamTile = 256;    // cameras per camera-update tile
 constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
 constexpr int kPoseThreads = 256;
+// Point-chunk Schur form: a chunk is at most kChPts points (F64: half) whose free
+// observations (at most chunk_obs_cap) are staged in LDS by one workgroup of
+// kChThreads threads (F64: half).
+constexpr int kChPts = 256;
+constexpr int kChThreads = 1024;
+constexpr int kChWaveItems = 32;  // entries with at least this many items use a whole wave
+inline int chunk_obs_cap(int precision) { return precision == 0 ? 1024 : 1984; }
+inline int chunk_pts_cap(int precision) { return precision == 0 ? kChPts / 2 : kChPts; }
+inline int chunk_cam_cap(int precision) { return precision == 0 ? 128 : 256; }
+// LDS bytes of one chunk workgroup: per observation f[7], Q[6], Q g_p[2], e[2] in T
+// and its observation index; per point V*^-1 (6 T); per camera R (9 T) and its index.
+inline size_t chunk_lds_bytes(int precision) {
+  const size_t T = precision == 0 ? 8 : 4;
+  return (size_t)chunk_obs_cap(precision) * (17 * T + 4) + (size_t)chunk_pts_cap(precision) * 6 * T +
+         (size_t)chunk_cam_cap(precision) * (9 * T + 4);
+}
 
 constexpr double kLambdaMin = 1e-12;
 constexpr double kLambdaMax = 1e16;
@@ -56,6 +72,10 @@ struct ProbDev {
   int32_t nnzb;          // blocks of S stored (both triangles + diagonal)
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
   int32_t max_tcols;     // longest tile column list
+  int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
+  int32_t n_ch;          // point chunks (chunk form)
+  int32_t n_red_tiles;   // reduction tiles (chunk form): 4 upper blocks each
+  int32_t n_fin_tiles;   // camera-row tiles (chunk form): 4 diagonal blocks each
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -64,11 +84,29 @@ struct ProbDev {
   const int32_t *obs_pt;          // [N]
   const void *obs_uv;             // [N][2] T
   const int32_t *pt_start;        // [P + 1]
-  const int32_t *cam_obs;         // [Nf] point-major position of each camera-major slot
-  const int32_t *cam_obs_start;   // [Cf + 1] camera-major slots of each free camera
-  const int32_t *obs_cpos;        // [N] camera-major slot of each observation, -1 if its camera is fixed
+  const int32_t *obs_rpos;        // [N] record of each observation, -1 if its camera is fixed
+  // pair-list form: records are camera-major
+  const int32_t *cam_obs;         // [Nf] observation of each camera-major record
+  const int32_t *cam_obs_start;   // [Cf + 1] records of each free camera
   const int32_t *up_pair_start;   // [n_up + 1]
-  const int2 *pairs;              // (c_a, c_b): camera-major slots of one point in cameras a < b
+  const int2 *pairs;              // (c_a, c_b): records of one point in cameras a < b
+  // point-chunk form: records are point-major; a chunk's entries are the S blocks
+  // it contributes to, each with its items (diagonal: local observation; upper:
+  // local observation pair p | q << 16), wave-mode entries first
+  const int32_t *ch_pt;           // [n_ch + 1] point range of each chunk
+  const int32_t *ch_f0;           // [n_ch + 1] record range of each chunk
+  const int32_t *ch_ent;          // [n_ch + 1] entry range of each chunk
+  const int32_t *ch_nwave;        // [n_ch] wave-mode entries at the start of the range
+  const int32_t *ch_cam_start;    // [n_ch + 1] range in ch_cam
+  const int32_t *ch_cam;          // cameras (caller's index) of each chunk's entries
+  const int32_t *ent_tgt;         // target block: a < Cf diagonal of camera a, Cf + u upper block u
+  const int32_t *ent_cam;         // chunk-local camera whose rotation the entry needs
+  const int32_t *ent_slot;        // position of the entry's partial in part_d / part_o (its
+                                  // position in its block's list, upper blocks counted from 0)
+  const int32_t *ent_start;       // [n_ent + 1] item range
+  const uint32_t *ent_items;
+  const int32_t *blk_start;       // [Cf + n_up + 1] entries of each block, in chunk order
+  int32_t n_dent;                 // diagonal entries (part_d rows)
   const int32_t *up_pos;          // [n_up] block (a, b) in S
   const int32_t *up_tpos;         // [n_up] block (b, a) in S
   const int32_t *diag_pos;        // [Cf]
@@ -80,7 +118,9 @@ struct ProbDev {
   double *pose[2];                // [C][12]: R row-major, then t
   double *X[2];                   // [P][3]
   // linearisation and Schur complement
-  void *lin;                      // [Nf] LinRec<T, S>, camera-major
+  void *lin;                      // [Nf] LinRec<T, S>
+  void *part_d;                   // [diagonal entries][54] T: U, Y W^T (upper 21 each), g_c, Y g_p
+  void *part_o;                   // [upper entries][36] T: sum Y W^T of the entry
   void *Q;                        // [Nf][6] T: J_p,k V*_j^-1 (2x3), camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
@@ -111,8 +151,8 @@ struct ProbDev {
 // Tile lists of one batch (device pointers) and their lengths.
 struct BatchPlan {
   const ProbDev *probs;
-  const Tile *pt, *diag, *off, *pcg, *cam, *ctl;
-  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl;
+  const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin;
+  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin;
 };
 
 // One localization request on the device.
@@ -135,7 +175,8 @@ struct KernelTimer {
 
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
-  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_NUM_KERNELS
+  K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
+  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -146,6 +187,8 @@ size_t compute_bytes(int precision);
 
 // Query device limits that select kernel forms; call before any graph capture.
 int prepare_kernels();
+// Dynamic LDS a workgroup may use on the current device (bytes).
+size_t device_lds_limit();
 // Whether the PCG runs in its one-reduction form (one launch per iteration) for
 // a plan whose longest tile column list is max_tcols.
 bool one_reduction_pcg(int precision, int max_tcols);

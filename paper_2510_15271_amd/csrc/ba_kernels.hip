@@ -38,7 +38,8 @@ namespace bax {
 
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
-    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg"};
+    "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
+    "schur_reduce", "schur_rows"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -133,6 +134,47 @@ __device__ inline T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Reduce-scatter of M values over the 64 lanes of a wavefront by recursive
+// halving: at each of the six steps a lane keeps one half of its vector (by one
+// bit of its lane index), adds its partner's copy of that half and sends the
+// other half, so 36 values cost 38 shuffles instead of 36 x 6.  On return lane l
+// holds the wave sum of value `idx` (idx >= M: a padding slot, nothing to write).
+// Odd lengths are padded with a zero; len tracks how many of a lane's current
+// slots are real values.
+template <class T, int M, int O>
+struct RedScatter {
+  static __device__ inline void run(T *a, int lane, int &idx, int &len) {
+    constexpr int H = (M + 1) / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const T lo = a[i];
+      const T hi = (i + H < M) ? a[i + H] : T(0);
+      const T send = up ? lo : hi;
+      a[i] = (up ? hi : lo) + __shfl_xor(send, O, 64);
+    }
+    if (up) {
+      idx += H;
+      len -= H;
+    } else {
+      len = min(len, H);
+    }
+    RedScatter<T, H, O / 2>::run(a, lane, idx, len);
+  }
+};
+template <class T, int M>
+struct RedScatter<T, M, 0> {
+  static __device__ inline void run(T *, int, int &, int &) {}
+};
+template <class T, int M>
+__device__ inline T wave_reduce_scatter(T (&a)[M], int lane, int &idx) {
+  idx = 0;
+  int len = M;
+  RedScatter<T, M, 32>::run(a, lane, idx, len);
+  if (len <= 0) idx = 1 << 30;
+  return a[0];
 }
 
 // Sum of one value per thread over a 256-thread block, fixed order.
@@ -281,10 +323,13 @@ __device__ inline void inv_sym3(const double u[6], double o[6]) {
 // numerically positive definite.
 __device__ inline void inv_spd6(const double A[36], double out[36]) {
   double L[36];
+#pragma unroll
   for (int i = 0; i < 36; ++i) L[i] = 0.0;
   bool ok = true;
+#pragma unroll
   for (int j = 0; j < 6 && ok; ++j) {
     double s = A[6 * j + j];
+#pragma unroll
     for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
     if (!(s > 0.0)) {
       ok = false;
@@ -292,30 +337,41 @@ __device__ inline void inv_spd6(const double A[36], double out[36]) {
     }
     const double ljj = sqrt(s);
     L[6 * j + j] = ljj;
+#pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       double t = A[6 * i + j];
+#pragma unroll
       for (int k = 0; k < j; ++k) t -= L[6 * i + k] * L[6 * j + k];
       L[6 * i + j] = t / ljj;
     }
   }
   if (!ok) {
+#pragma unroll
     for (int i = 0; i < 36; ++i) out[i] = 0.0;
+#pragma unroll
     for (int i = 0; i < 6; ++i) out[7 * i] = A[7 * i] > 0.0 ? 1.0 / A[7 * i] : 0.0;
     return;
   }
   double Li[36];  // L^-1, lower triangular
+#pragma unroll
   for (int i = 0; i < 36; ++i) Li[i] = 0.0;
+#pragma unroll
   for (int j = 0; j < 6; ++j) {
     Li[6 * j + j] = 1.0 / L[6 * j + j];
+#pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       double s = 0.0;
+#pragma unroll
       for (int k = j; k < i; ++k) s -= L[6 * i + k] * Li[6 * k + j];
       Li[6 * i + j] = s / L[6 * i + i];
     }
   }
+#pragma unroll
   for (int i = 0; i < 6; ++i)
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int k = (i > j ? i : j); k < 6; ++k) s += Li[6 * k + i] * Li[6 * k + j];
       out[6 * i + j] = s;
     }
@@ -414,7 +470,7 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
         for (int i = 0; i < 7; ++i) rec.f[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
       }
-      const int cpos = pd.obs_cpos[k];  // records are kept for free cameras only
+      const int cpos = pd.obs_rpos[k];  // records are kept for free cameras only
       if (cpos >= 0) lin[cpos] = rec;
     }
     s_loc[threadIdx.x] = jl;
@@ -489,7 +545,7 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
   const double *poses = pd.pose[st->cur];
   T *Q = (T *)pd.Q;
   for (int k = k0 + threadIdx.x; k < k1; k += 256) {
-    const int cpos = pd.obs_cpos[k];
+    const int cpos = pd.obs_rpos[k];
     if (cpos < 0) continue;  // fixed camera: no camera block
     const int jl = pd.obs_pt[k] - j0;
     T f[7], R[9], Jp[6];
@@ -504,6 +560,75 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
       for (int m = 0; m < 3; ++m)
         Q[6 * (size_t)cpos + 3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
   }
+}
+
+// Row a of the reduced system from its camera sums tot = [U (upper 21), sum Y W^T
+// (upper 21), g_c (6), sum Y g_p (6)]: Marquardt damping, the diagonal block of S,
+// the right-hand side b = -g_c + sum Y g_p, the FP64 block-Jacobi inverse, and the
+// PCG start (x = 0, r = b, z = p = M^-1 b) with this row's partials of b.b and r.z.
+template <class T>
+__device__ void finish_camera_row(const ProbDev &pd, const LMState *st, int a, const double tot[54]) {
+  const double lam = st->lambda;
+  double Sfull[36], Dc[6];
+  int u = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r; c < 6; ++c, ++u) {
+      const double Uv = (double)T(tot[u]);
+      const double Mv = (double)T(tot[21 + u]);
+      const double sv = Uv - Mv;
+      Sfull[6 * r + c] = sv;
+      Sfull[6 * c + r] = sv;
+      if (r == c) Dc[r] = fmin(fmax(Uv, kDMin), kDMax);
+    }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) Sfull[7 * r] += lam * (double)T(Dc[r]);
+  T *Sblk = (T *)pd.S + 36 * (size_t)pd.diag_pos[a];
+  double Sd[36];
+#pragma unroll
+  for (int i = 0; i < 36; ++i) {
+    Sblk[i] = T(Sfull[i]);
+    Sd[i] = (double)T(Sfull[i]);  // the preconditioner inverts the stored block
+  }
+  double Mi[36];
+  inv_spd6(Sd, Mi);
+  double *Minv = pd.Minv + 36 * (size_t)a;
+#pragma unroll
+  for (int i = 0; i < 36; ++i) Minv[i] = Mi[i];
+  T *gc = (T *)pd.gc + 6 * a;
+  T *Dcv = (T *)pd.Dc + 6 * a;
+  T *bv = (T *)pd.brhs + 6 * a;
+  T *x = (T *)pd.x + 6 * a;
+  T *r = (T *)pd.r + 6 * a;
+  T *z = (T *)pd.z + 6 * a;
+  T *p = (T *)pd.p0 + 6 * a;
+  double bb = 0.0, rz = 0.0;
+  double bvals[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const T g = T(tot[42 + i]);
+    const T b = T(-(double)g + (double)T(tot[48 + i]));
+    gc[i] = g;
+    Dcv[i] = T(Dc[i]);
+    bv[i] = b;
+    x[i] = T(0);
+    r[i] = b;
+    bvals[i] = (double)b;
+    bb += bvals[i] * bvals[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double zi = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) zi += Mi[6 * i + m] * bvals[m];
+    const T zt = T(zi);
+    z[i] = zt;
+    p[i] = zt;
+    rz += bvals[i] * (double)zt;
+  }
+  pd.part_rz0[a] = rz;
+  pd.part_bb[a] = bb;
 }
 
 // ------------------------------------------------------------------ Schur: diagonal
@@ -627,59 +752,7 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
     for (int i = 0; i < 54; ++i)
       tot[i] = (double)s_w[0][i] + (double)s_w[1][i] + (double)s_w[2][i] + (double)s_w[3][i];
     // NB: the FP32 mode sums its four wave totals in FP64; the sums themselves are FP32.
-    const double lam = st->lambda;
-    double Sfull[36], Dc[6];
-    int u = 0;
-    for (int r = 0; r < 6; ++r)
-      for (int c = r; c < 6; ++c, ++u) {
-        const double Uv = (double)T(tot[u]);
-        const double Mv = (double)T(tot[21 + u]);
-        const double sv = Uv - Mv;
-        Sfull[6 * r + c] = sv;
-        Sfull[6 * c + r] = sv;
-        if (r == c) Dc[r] = fmin(fmax(Uv, kDMin), kDMax);
-      }
-    for (int r = 0; r < 6; ++r) Sfull[7 * r] += lam * (double)T(Dc[r]);
-    T *Sblk = (T *)pd.S + 36 * (size_t)pd.diag_pos[a];
-    double Sd[36];
-    for (int i = 0; i < 36; ++i) {
-      Sblk[i] = T(Sfull[i]);
-      Sd[i] = (double)T(Sfull[i]);  // the preconditioner inverts the stored block
-    }
-    double Mi[36];
-    inv_spd6(Sd, Mi);
-    double *Minv = pd.Minv + 36 * (size_t)a;
-    for (int i = 0; i < 36; ++i) Minv[i] = Mi[i];
-    T *gc = (T *)pd.gc + 6 * a;
-    T *Dcv = (T *)pd.Dc + 6 * a;
-    T *bv = (T *)pd.brhs + 6 * a;
-    T *x = (T *)pd.x + 6 * a;
-    T *r = (T *)pd.r + 6 * a;
-    T *z = (T *)pd.z + 6 * a;
-    T *p = (T *)pd.p0 + 6 * a;
-    double bb = 0.0, rz = 0.0;
-    double bvals[6];
-    for (int i = 0; i < 6; ++i) {
-      const T g = T(tot[42 + i]);
-      const T b = T(-(double)g + (double)T(tot[48 + i]));
-      gc[i] = g;
-      Dcv[i] = T(Dc[i]);
-      bv[i] = b;
-      x[i] = T(0);
-      r[i] = b;
-      bvals[i] = (double)b;
-      bb += bvals[i] * bvals[i];
-    }
-    for (int i = 0; i < 6; ++i) {
-      double zi = 0.0;
-      for (int m = 0; m < 6; ++m) zi += Mi[6 * i + m] * bvals[m];
-      const T zt = T(zi);
-      z[i] = zt;
-      p[i] = zt;
-      rz += bvals[i] * (double)zt;
-    }
-    pd.part_rz0[a] = rz;
-    pd.part_bb[a] = bb;
+    finish_camera_row<T>(pd, st, a, tot);
   }
 }
 
@@ -742,6 +815,356 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
     Sv[36 * (size_t)pd.up_pos[u] + lane] = -mine;
     Sv[36 * (size_t)pd.up_tpos[u] + 6 * c + r] = -mine;
   }
+}
+
+// ------------------------------------------------------------------ Schur: point chunks
+// Chunk form.  One 1024-thread workgroup per chunk of consecutive points:
+//   a. V*_j = V_j + lambda D_j inverted in FP64 for the chunk's points;
+//   b. for each of the chunk's records: decoded J_pi and P_c, Q = J_p V*^-1
+//      (2x3), Q g_p (2) and the weighted residual, all staged in LDS;
+//   c. every S block the chunk touches (an entry) is summed over its items in
+//      point order -- by a whole wavefront (lanes over items, then a butterfly)
+//      for diagonal blocks and long entries, by one thread otherwise -- and
+//      written as the chunk's partial of that block.
+// A block's partials are then summed in chunk order by k_schur_reduce, so S does
+// not depend on scheduling and each record is read from HBM once per iteration.
+// FP64 runs 512 threads so that the accumulators fit in registers.
+template <class T>
+constexpr int chunk_threads() { return sizeof(T) == 8 ? kChThreads / 2 : kChThreads; }
+
+template <class T>
+__device__ inline void pair_accumulate(T acc[36], const T *fa, const T *q, const T *fb, const T *Rb) {
+  T Jca[12], Jcb[12], Jpb[6];
+  jc_from(fa, Jca);
+  jc_from(fb, Jcb);
+  jp_from(fb, Rb, Jpb);
+  const T m00 = q[0] * Jpb[0] + q[1] * Jpb[1] + q[2] * Jpb[2];
+  const T m01 = q[0] * Jpb[3] + q[1] * Jpb[4] + q[2] * Jpb[5];
+  const T m10 = q[3] * Jpb[0] + q[4] * Jpb[1] + q[5] * Jpb[2];
+  const T m11 = q[3] * Jpb[3] + q[4] * Jpb[4] + q[5] * Jpb[5];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const T z0 = Jca[r] * m00 + Jca[6 + r] * m10;
+    const T z1 = Jca[r] * m01 + Jca[6 + r] * m11;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * Jcb[c] + z1 * Jcb[6 + c];
+  }
+}
+
+template <class T, class S>
+__global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDev *__restrict__ probs,
+                                                            const Tile *__restrict__ tiles) {
+  constexpr int cap = sizeof(T) == 8 ? 1024 : 1984;  // chunk_obs_cap / _pts_cap / _cam_cap
+  constexpr int pcap = sizeof(T) == 8 ? kChPts / 2 : kChPts;
+  constexpr int ccap = sizeof(T) == 8 ? 128 : 256;
+  constexpr bool k16 = sizeof(S) == 2;
+  constexpr int nth = chunk_threads<T>();
+  extern __shared__ double s_dyn[];
+  T *s_vi = (T *)s_dyn;           // [pcap][6]
+  T *s_f = s_vi + 6 * pcap;       // [cap][7]
+  T *s_q = s_f + 7 * cap;         // [cap][6]
+  T *s_qg = s_q + 6 * cap;        // [cap][2]
+  T *s_e = s_qg + 2 * cap;        // [cap][2]
+  T *s_R = s_e + 2 * cap;         // [ccap][9] rotations of the chunk's cameras
+  int *s_k = (int *)(s_R + 9 * ccap);  // [cap]
+  int *s_cam = s_k + cap;         // [ccap]
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int c = tl.idx;
+  const int j0 = pd.ch_pt[c], j1 = pd.ch_pt[c + 1];
+  const int f0 = pd.ch_f0[c];
+  const double *poses = pd.pose[st->cur];
+  // a. point inverses
+  {
+    const double lam = st->lambda;
+    const T *V = (const T *)pd.V;
+    const T *Dp = (const T *)pd.Dp;
+    T *Vinv = (T *)pd.Vinv;
+    for (int jl = threadIdx.x; jl < j1 - j0; jl += nth) {
+      const int j = j0 + jl;
+      double u[6], o[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) u[i] = (double)V[6 * j + i];
+      u[0] += lam * (double)Dp[3 * j + 0];
+      u[3] += lam * (double)Dp[3 * j + 1];
+      u[5] += lam * (double)Dp[3 * j + 2];
+      inv_sym3(u, o);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        s_vi[6 * jl + i] = T(o[i]);
+        Vinv[6 * j + i] = T(o[i]);
+      }
+    }
+  }
+  __syncthreads();
+  // b. rotations of the chunk's cameras, records of the chunk (two observations
+  // per thread in flight)
+  {
+    const int q0 = pd.ch_cam_start[c], nq = pd.ch_cam_start[c + 1] - q0;
+    for (int x = threadIdx.x; x < nq; x += nth) {
+      const int cam = pd.ch_cam[q0 + x];
+      T R[9];
+      load_rot(poses + 12 * cam, R);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s_R[9 * x + i] = R[i];
+      s_cam[x] = cam;
+    }
+  }
+  {
+    const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+    const T *gp = (const T *)pd.gp;
+    const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+    for (int base = k0; base < k1; base += 2 * nth) {
+      int kk[2], rp[2], cam[2], jj[2];
+      LinRec<T, S> rec[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        kk[h] = base + h * nth + (int)threadIdx.x;
+        rp[h] = kk[h] < k1 ? pd.obs_rpos[kk[h]] : -1;
+        cam[h] = kk[h] < k1 ? pd.obs_cam[kk[h]] : 0;
+        jj[h] = kk[h] < k1 ? pd.obs_pt[kk[h]] : j0;
+        if (rp[h] >= 0) rec[h] = lin[rp[h]];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (rp[h] < 0) continue;  // past the chunk, or a fixed camera: no record
+        const int l = rp[h] - f0;
+        const int j = jj[h];
+        T f[7], R[9], Jp[6];
+        decode(rec[h], f);
+        load_rot(poses + 12 * cam[h], R);
+        jp_from(f, R, Jp);
+        const T *vi = s_vi + 6 * (j - j0);
+        const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
+        T q[6];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            q[3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) s_f[7 * l + i] = f[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s_q[6 * l + i] = q[i];
+        const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
+        s_qg[2 * l] = q[0] * g0 + q[1] * g1 + q[2] * g2;
+        s_qg[2 * l + 1] = q[3] * g0 + q[4] * g1 + q[5] * g2;
+        s_e[2 * l] = rec[h].e[0];
+        s_e[2 * l + 1] = rec[h].e[1];
+        s_k[l] = kk[h];
+      }
+    }
+  }
+  __syncthreads();
+  // c. entries.  Wave-mode entries: wave w takes entries w, w + 16, ... of the
+  // chunk; lane x first loads the descriptor and camera rotation of the wave's
+  // x-th entry, so the descriptors arrive together and are broadcast by shuffles.
+  const int e0 = pd.ch_ent[c], ew = e0 + pd.ch_nwave[c], e1 = pd.ch_ent[c + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int nw = nth / 64;
+  T *pdg = (T *)pd.part_d;
+  T *pof = (T *)pd.part_o;
+  for (int eb = e0 + wv; eb < ew; eb += 64 * nw) {
+    const int my = eb + nw * lane;
+    int m_tgt = 0, m_i0 = 0, m_i1 = 0, m_slot = 0, m_lc = 0;
+    if (my < ew) {
+      m_tgt = pd.ent_tgt[my];
+      m_i0 = pd.ent_start[my];
+      m_i1 = pd.ent_start[my + 1];
+      m_slot = pd.ent_slot[my];
+      m_lc = pd.ent_cam[my];
+    }
+    const int cnt = min(64, (ew - eb + nw - 1) / nw);
+    for (int x = 0; x < cnt; ++x) {
+      const int tgt = __shfl(m_tgt, x, 64);
+      const int i0 = __shfl(m_i0, x, 64), i1 = __shfl(m_i1, x, 64);
+      const int slot = __shfl(m_slot, x, 64);
+      const int lc = __shfl(m_lc, x, 64);
+      const int cam = s_cam[lc];
+      const T *R = s_R + 9 * lc;
+      if (tgt < pd.Cf) {
+        // diagonal block of camera cam over its observations, in two passes to
+        // bound the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
+        const T *K = (const T *)pd.K + 4 * cam;
+        const T delta = T(st->huber_delta);
+        T acc[33];
+#pragma unroll
+        for (int i = 0; i < 33; ++i) acc[i] = T(0);
+        for (int it = i0 + lane; it < i1; it += 64) {
+          const int l = (int)pd.ent_items[it];
+          T Jc[12];
+          jc_from(s_f + 7 * l, Jc);
+          const T *Jc0 = Jc, *Jc1 = Jc + 6;
+          int u = 0;
+#pragma unroll
+          for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
+          const T qg0 = s_qg[2 * l], qg1 = s_qg[2 * l + 1];
+#pragma unroll
+          for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qg0 + Jc1[r] * qg1;
+          if (k16) {
+            // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here
+            const int k = s_k[l];
+            const double *pose = poses + 12 * cam;
+            double xd, yd, zd;
+            transform(pose, pd.X[st->cur] + 3 * pd.obs_pt[k], xd, yd, zd);
+            const T xv = T(xd), yv = T(yd), zv = T(zd);
+            const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
+            T r0, r1;
+            if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+              const T sq = r0 * r0 + r1 * r1;
+              const T w = huber_w(sq, delta);
+              T Jg[12], Jpg[6];
+              jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
+#pragma unroll
+              for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
+            }
+          } else {
+            const T e0v = s_e[2 * l], e1v = s_e[2 * l + 1];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) acc[21 + r] += Jc0[r] * e0v + Jc1[r] * e1v;
+          }
+        }
+        T *o = pdg + 54 * (size_t)slot;
+        int idx;
+        T mine = wave_reduce_scatter(acc, lane, idx);
+        // partial layout: U (21), Y W^T (21), g_c (6), Y g_p (6)
+        if (idx < 21) o[idx] = mine;
+        else if (idx < 33) o[21 + idx] = mine;
+        T acw[21];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) acw[i] = T(0);
+        for (int it = i0 + lane; it < i1; it += 64) {
+          const int l = (int)pd.ent_items[it];
+          const T *f = s_f + 7 * l;
+          const T *q = s_q + 6 * l;
+          T Jc[12], Jp[6];
+          jc_from(f, Jc);
+          jp_from(f, R, Jp);
+          const T *Jc0 = Jc, *Jc1 = Jc + 6;
+          const T m00 = q[0] * Jp[0] + q[1] * Jp[1] + q[2] * Jp[2];
+          const T m01 = q[0] * Jp[3] + q[1] * Jp[4] + q[2] * Jp[5];
+          const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
+          const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
+          int u = 0;
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const T z0 = Jc0[r] * m00 + Jc1[r] * m10;
+            const T z1 = Jc0[r] * m01 + Jc1[r] * m11;
+#pragma unroll
+            for (int cc = r; cc < 6; ++cc, ++u) acw[u] += z0 * Jc0[cc] + z1 * Jc1[cc];
+          }
+        }
+        mine = wave_reduce_scatter(acw, lane, idx);
+        if (idx < 21) o[21 + idx] = mine;
+      } else {
+        T acc[36];
+#pragma unroll
+        for (int i = 0; i < 36; ++i) acc[i] = T(0);
+        // items of this lane: i0 + lane, i0 + lane + 64, ... (four loads in flight)
+        for (int it = i0 + lane; it < i1; it += 256) {
+          uint32_t pq[4];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) pq[h] = it + 64 * h < i1 ? pd.ent_items[it + 64 * h] : 0u;
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            if (it + 64 * h < i1) {
+              const int p = (int)(pq[h] & 0xffffu), qq = (int)(pq[h] >> 16);
+              pair_accumulate<T>(acc, s_f + 7 * p, s_q + 6 * p, s_f + 7 * qq, R);
+            }
+        }
+        int idx;
+        const T mine = wave_reduce_scatter(acc, lane, idx);
+        if (idx < 36) pof[36 * (size_t)slot + idx] = mine;
+      }
+    }
+  }
+  // short upper entries (fewer than kChWaveItems items), one thread each, all
+  // items loaded before the arithmetic
+  for (int e = ew + threadIdx.x; e < e1; e += nth) {
+    const int i0 = pd.ent_start[e], i1 = pd.ent_start[e + 1];
+    const int slot = pd.ent_slot[e];
+    const T *R = s_R + 9 * pd.ent_cam[e];
+    T acc[36];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) acc[i] = T(0);
+    for (int it = i0; it < i1; it += 8) {
+      uint32_t pq[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) pq[h] = it + h < i1 ? pd.ent_items[it + h] : 0u;
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        if (it + h < i1) {
+          const int p = (int)(pq[h] & 0xffffu), qq = (int)(pq[h] >> 16);
+          pair_accumulate<T>(acc, s_f + 7 * p, s_q + 6 * p, s_f + 7 * qq, R);
+        }
+    }
+    T *o = pof + 36 * (size_t)slot;
+#pragma unroll
+    for (int i = 0; i < 36; ++i) o[i] = acc[i];
+  }
+}
+
+// Upper blocks, one wavefront each: the block's chunk partials (contiguous rows
+// of 36, chunk order) summed in FP64, written as S_ab = -sum and S_ba = its
+// transpose.
+template <class T>
+__global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict__ probs,
+                                                      const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int u = 4 * tl.idx + wv;
+  if (u >= pd.n_up || lane >= 36) return;  // no workgroup barrier follows
+  const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
+  const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent);
+  double t = 0.0;
+  for (int x = 0; x < n; x += 16) {  // sixteen partials in flight, summed in order
+    T v[16];
+#pragma unroll
+    for (int h = 0; h < 16; ++h) v[h] = x + h < n ? part[36 * (size_t)(x + h) + lane] : T(0);
+#pragma unroll
+    for (int h = 0; h < 16; ++h) t += (double)v[h];
+  }
+  const int r = lane / 6, cc = lane % 6;
+  const T v = T(-t);
+  T *Sv = (T *)pd.S;
+  Sv[36 * (size_t)pd.up_pos[u] + lane] = v;
+  Sv[36 * (size_t)pd.up_tpos[u] + 6 * cc + r] = v;
+}
+
+// Camera rows, one wavefront each: the diagonal partials (rows of 54) summed in
+// FP64, then finish_camera_row by lane 0.
+template <class T>
+__global__ __launch_bounds__(256) void k_schur_rows(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int a = 4 * tl.idx + wv;
+  if (a >= pd.Cf) return;  // wave-uniform; no workgroup barrier follows
+  const int b0 = pd.blk_start[a], n = pd.blk_start[a + 1] - b0;
+  const T *part = (const T *)pd.part_d + 54 * (size_t)b0;
+  double t = 0.0;
+  if (lane < 54)
+    for (int x = 0; x < n; x += 8) {
+      T v[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) v[h] = x + h < n ? part[54 * (size_t)(x + h) + lane] : T(0);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) t += (double)v[h];
+    }
+  double tot[54];
+#pragma unroll
+  for (int i = 0; i < 54; ++i) tot[i] = __shfl(t, i, 64);
+  if (lane == 0) finish_camera_row<T>(pd, st, a, tot);
 }
 
 // ------------------------------------------------------------------ PCG
@@ -1369,7 +1792,7 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
     int jl = -1;
     if (k < k1) {
       jl = pd.obs_pt[k] - j0;
-      const int cpos = pd.obs_cpos[k];
+      const int cpos = pd.obs_rpos[k];
       if (cpos >= 0) {
         const int cam = pd.obs_cam[k];
         const int a = pd.free_idx[cam];
@@ -1697,6 +2120,8 @@ struct Timed {
 // LDS available to the fused PCG form for z (bytes): the device's per-workgroup
 // limit less room for the kernel's static LDS, set once by prepare_kernels().
 static size_t g_fused_lds = 48 * 1024;
+// Per-workgroup LDS of the device (0 when the chunk form cannot be used).
+static size_t g_lds_limit = 0;
 
 int prepare_kernels() {
   static bool done = false;
@@ -1717,8 +2142,28 @@ int prepare_kernels() {
     }
   }
   g_fused_lds = use;
+  g_lds_limit = lim > 0 ? (size_t)lim : 0;
+  // the chunk form stages a chunk in up to chunk_lds_bytes of dynamic LDS
+  const void *chunk_kernels[4] = {(const void *)k_schur_chunk<double, double>,
+                                  (const void *)k_schur_chunk<float, float>,
+                                  (const void *)k_schur_chunk<float, _Float16>,
+                                  (const void *)k_schur_chunk<float, bf16s>};
+  for (int p = 0; p < 4; ++p) {
+    const size_t need = chunk_lds_bytes(p);
+    if (need + 4096 > g_lds_limit ||
+        hipFuncSetAttribute(chunk_kernels[p], hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      g_lds_limit = 0;  // chunk form unavailable on this device
+    }
+  }
   done = true;
   return 0;
+}
+
+size_t device_lds_limit() {
+  if (prepare_kernels() != 0) return 0;
+  return g_lds_limit;
 }
 
 bool one_reduction_pcg(int precision, int max_tcols) {
@@ -1738,9 +2183,22 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
   }
-  if (bp.n_pt) {
+  if (bp.n_ch) {
+    Timed t(tm, K_SCHUR_CHUNK, s);
+    k_schur_chunk<T, S><<<bp.n_ch, chunk_threads<T>(), chunk_lds_bytes(sizeof(T) == 8 ? 0 : 1), s>>>(bp.probs,
+                                                                                                 bp.ch);
+  }
+  if (bp.n_red) {
+    Timed t(tm, K_SCHUR_REDUCE, s);
+    k_schur_reduce<T><<<bp.n_red, 256, 0, s>>>(bp.probs, bp.red);
+  }
+  if (bp.n_fin) {
+    Timed t(tm, K_SCHUR_ROWS, s);
+    k_schur_rows<T><<<bp.n_fin, 256, 0, s>>>(bp.probs, bp.fin);
+  }
+  if (bp.n_pp) {
     Timed t(tm, K_POINT_PREP, s);
-    k_point_prep<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+    k_point_prep<T, S><<<bp.n_pp, 256, 0, s>>>(bp.probs, bp.pp);
   }
   if (bp.n_diag) {
     Timed t(tm, K_SCHUR_DIAG, s);

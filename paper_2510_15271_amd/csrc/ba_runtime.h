@@ -29,9 +29,21 @@ struct Symbolic {
   std::vector<int32_t> obs_cam, obs_pt;
   std::vector<double> obs_uv;
   std::vector<int32_t> pt_start;
-  std::vector<int32_t> cam_obs, cam_obs_start, obs_cpos;
+  std::vector<int32_t> pt_order;  // internal point -> caller's point index
+  std::vector<int32_t> obs_rpos;  // record of each observation (-1: fixed camera)
+  int32_t Nf = 0;                 // observations in free cameras (records)
+  int64_t n_pairs = 0;            // observation pairs of one point in two free cameras
+  bool chunked = false;           // point-chunk Schur form (else pair lists)
+  // pair-list form
+  std::vector<int32_t> cam_obs, cam_obs_start;
   std::vector<int32_t> up_pair_start;
   std::vector<int2> pairs;
+  // point-chunk form (see ProbDev)
+  std::vector<int32_t> ch_pt, ch_f0, ch_ent, ch_nwave, ch_cam_start, ch_cam;
+  std::vector<int32_t> ent_tgt, ent_cam, ent_slot, ent_start;
+  std::vector<uint32_t> ent_items;
+  std::vector<int32_t> blk_start;
+  int32_t n_dent = 0, n_oent = 0;
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   // distinct columns read by each PCG tile (kPcgRows rows) and, per block, the
   // position of its column in its tile's list
@@ -41,8 +53,10 @@ struct Symbolic {
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 
 struct Offsets {
-  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_cpos;
+  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
+  size_t ch_pt, ch_f0, ch_ent, ch_nwave, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
+  size_t part_d, part_o;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
   size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
@@ -55,6 +69,7 @@ struct DevProblem {
   double lambda0 = 1e-4, pcg_tol = 1e-6, huber = 0.0;
   int32_t C = 0, Cf = 0, P = 0, N = 0;
   int32_t max_tcols = 0;
+  std::vector<int32_t> pt_order;  // internal point -> caller's point index
   Offsets off{};
   char *dev = nullptr;
   ProbDev view{};
@@ -76,7 +91,7 @@ struct DevProblem {
 struct Batch {
   std::vector<ProbDev> probs;
   std::vector<int> tags;
-  std::vector<Tile> tiles[6];  // pt, diag, off, pcg, cam, ctl
+  std::vector<Tile> tiles[10];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin
   std::vector<char> host;
   void *dev = nullptr;
   size_t cap = 0;

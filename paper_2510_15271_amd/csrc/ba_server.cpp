@@ -263,6 +263,7 @@ void ba_server::loop() {
       r->dp.staging_f.clear();
       r->dp.staging_d.clear();
       r->sy.pairs = std::vector<int2>();
+      r->sy.ent_items = std::vector<uint32_t>();
     }
     if (!pose_now.empty()) {
       if (pb_ok) {

@@ -57,6 +57,31 @@ def test_small_drive_f64_matches_schur_oracle_across_tiles(balib):
     assert rel.max() <= 1e-9
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_chunk_and_pair_list_forms(balib, prec):
+    """Both Schur forms on the same drive (40 cameras, 12 point tiles, ragged
+    tail): FP64 per-iteration cost within 1e-9 of the explicit-Schur oracle for
+    each form; in FP32 the two forms agree with each other to 1e-5 per iteration."""
+    s = make_small_drive(40, 3000, seed=5)
+    kw = dict(max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14 if prec == "f64" else 1e-6, precision=prec)
+    out = {}
+    for form, flags in (("chunk", 0), ("pairs", balib.FLAG_PAIR_LISTS)):
+        p = balib.Problem.from_scene(s, flags=flags, **kw)
+        info = p.info()
+        assert info["schur_form"] == (1 if form == "chunk" else 0)
+        out[form] = p.solve().result()
+        p.close()
+        _say(form, info["n_chunks"], info["n_entries"], out[form]["iter_cost"][-1])
+    if prec == "f64":
+        ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=8, solve="exact"))
+        for form in out:
+            rel = np.abs(out[form]["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+            assert rel.max() <= 1e-9, form
+    else:
+        a, b = out["chunk"]["iter_cost"], out["pairs"]["iter_cost"]
+        assert np.max(np.abs(a - b) / b) <= 1e-5
+
+
 def test_small_drive_pcg_schedule_f64_matches_oracle_pcg(balib):
     """Same schedule on both sides (PCG capped at 50, tol 1e-6): FP64 device vs
     FP64 oracle PCG, per-iteration cost and PCG iteration counts."""
