@@ -122,11 +122,13 @@ int check_options(const ba_options *o, bool pose_only) {
 
 // ------------------------------------------------------------------ symbolic analysis
 // Point chunks and their entries (chunk form of the Schur complement).  A chunk
-// is a run of internal points with at most pcap points and ocap records.  For
-// every S block it touches, an entry lists its items in point order: for the
-// diagonal block of camera a the chunk's observations in a; for the upper block
-// (a, b) the chunk's observation pairs (p in a, q in b) of one point.  Entries
-// with many items are handled by a whole wavefront and come first in the chunk.
+// is a run of internal points with at most pcap points, ocap records and ccap
+// cameras.  For every S block it touches, the chunk's items of that block are
+// listed in point order (diagonal block of camera a: the chunk's observations in
+// a; upper block (a, b): the pairs (p in a, q in b) of one point) and cut into
+// entries of at most kChSubItems items; each entry is summed by one thread into
+// its own partial.  Entries are ordered diagonal first, then by decreasing
+// length, so the threads of a wavefront have similar work.
 static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
                         const std::vector<int32_t> &up_col, int pcap, int ocap, int ccap) {
   const int P = sy.P, Cf = sy.Cf;
@@ -172,7 +174,6 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
   }
   const int n_ch = (int)sy.ch_pt.size() - 1;
   sy.ch_ent.assign(1, 0);
-  sy.ch_nwave.clear();
   sy.ent_tgt.clear();
   sy.ent_cam.clear();
   sy.ent_slot.clear();
@@ -185,7 +186,7 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
     int32_t a, b;
     size_t i0, i1;
   };
-  std::vector<Ent> wave, thread;
+  std::vector<Ent> wave, thread;  // diagonal and upper entries of one chunk
   for (int c = 0; c < n_ch; ++c) {
     it.clear();
     const int f0 = sy.ch_f0[c];
@@ -216,15 +217,16 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
       size_t e = i;
       while (e < it.size() && it[e].first == it[i].first) ++e;
       const int32_t a = (int32_t)(it[i].first >> 32), b = (int32_t)(it[i].first & 0xffffffffu);
-      const Ent en{a, b, i, e};
-      if (a == b || e - i >= (size_t)kChWaveItems) wave.push_back(en);
-      else thread.push_back(en);
+      for (size_t x = i; x < e; x += kChSubItems) {
+        const Ent en{a, b, x, std::min(e, x + kChSubItems)};
+        (a == b ? wave : thread).push_back(en);
+      }
       i = e;
     }
-    // lanes of a wavefront run their thread-mode entries side by side: group equal lengths
-    std::stable_sort(thread.begin(), thread.end(),
-                     [](const Ent &p, const Ent &q) { return p.i1 - p.i0 > q.i1 - q.i0; });
-    sy.ch_nwave.push_back((int32_t)wave.size());
+    // threads of a wavefront run their entries side by side: group equal lengths
+    const auto longer = [](const Ent &p, const Ent &q) { return p.i1 - p.i0 > q.i1 - q.i0; };
+    std::stable_sort(wave.begin(), wave.end(), longer);
+    std::stable_sort(thread.begin(), thread.end(), longer);
     for (const std::vector<Ent> *lst : {&wave, &thread})
       for (const Ent &en : *lst) {
         if (en.a == en.b) {
@@ -539,7 +541,6 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.ch_pt = L.take(sy.ch_pt.size() * 4 + 4);
   o.ch_f0 = L.take(sy.ch_f0.size() * 4 + 4);
   o.ch_ent = L.take(sy.ch_ent.size() * 4 + 4);
-  o.ch_nwave = L.take(sy.ch_nwave.size() * 4 + 4);
   o.ch_cam_start = L.take(sy.ch_cam_start.size() * 4 + 4);
   o.ch_cam = L.take(sy.ch_cam.size() * 4 + 4);
   o.ent_tgt = L.take(sy.ent_tgt.size() * 4 + 4);
@@ -631,8 +632,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.Nf = sy.Nf;
   pd.chunked = sy.chunked ? 1 : 0;
   pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
-  pd.n_red_tiles = sy.chunked ? (sy.n_up + 3) / 4 : 0;
-  pd.n_fin_tiles = sy.chunked ? (Cf + 3) / 4 : 0;
+  pd.n_red_tiles = sy.chunked ? (int32_t)(((int64_t)sy.n_up * 36 + 255) / 256) : 0;
+  pd.n_fin_tiles = sy.chunked ? Cf : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
@@ -653,7 +654,6 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.ch_pt = (const int32_t *)ptr(off.ch_pt);
   pd.ch_f0 = (const int32_t *)ptr(off.ch_f0);
   pd.ch_ent = (const int32_t *)ptr(off.ch_ent);
-  pd.ch_nwave = (const int32_t *)ptr(off.ch_nwave);
   pd.ch_cam_start = (const int32_t *)ptr(off.ch_cam_start);
   pd.ch_cam = (const int32_t *)ptr(off.ch_cam);
   pd.ent_tgt = (const int32_t *)ptr(off.ent_tgt);
@@ -763,7 +763,6 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.ch_pt, sy.ch_pt.data(), sy.ch_pt.size() * 4));
   chk(up(off.ch_f0, sy.ch_f0.data(), sy.ch_f0.size() * 4));
   chk(up(off.ch_ent, sy.ch_ent.data(), sy.ch_ent.size() * 4));
-  chk(up(off.ch_nwave, sy.ch_nwave.data(), sy.ch_nwave.size() * 4));
   chk(up(off.ch_cam_start, sy.ch_cam_start.data(), sy.ch_cam_start.size() * 4));
   chk(up(off.ch_cam, sy.ch_cam.data(), sy.ch_cam.size() * 4));
   chk(up(off.ent_tgt, sy.ent_tgt.data(), sy.ent_tgt.size() * 4));

@@ -24,12 +24,13 @@ constexpr int kPoseThreads = 256;
 // kChThreads threads (F64: half).
 constexpr int kChPts = 256;
 constexpr int kChThreads = 1024;
-constexpr int kChWaveItems = 32;  // entries with at least this many items use a whole wave
+constexpr int kChSubItems = 32;  // items per chunk entry (one thread each)
 inline int chunk_obs_cap(int precision) { return precision == 0 ? 1024 : 1984; }
 inline int chunk_pts_cap(int precision) { return precision == 0 ? kChPts / 2 : kChPts; }
 inline int chunk_cam_cap(int precision) { return precision == 0 ? 128 : 256; }
 // LDS bytes of one chunk workgroup: per observation f[7], Q[6], Q g_p[2], e[2] in T
-// and its observation index; per point V*^-1 (6 T); per camera R (9 T) and its index.
+// (as two rows of 8 and one value) and its observation index; per point V*^-1
+// (6 T); per camera R (9 T) and its index.
 inline size_t chunk_lds_bytes(int precision) {
   const size_t T = precision == 0 ? 8 : 4;
   return (size_t)chunk_obs_cap(precision) * (17 * T + 4) + (size_t)chunk_pts_cap(precision) * 6 * T +
@@ -74,8 +75,8 @@ struct ProbDev {
   int32_t max_tcols;     // longest tile column list
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
-  int32_t n_red_tiles;   // reduction tiles (chunk form): 4 upper blocks each
-  int32_t n_fin_tiles;   // camera-row tiles (chunk form): 4 diagonal blocks each
+  int32_t n_red_tiles;   // reduction tiles (chunk form): 256 elements of the upper blocks each
+  int32_t n_fin_tiles;   // camera-row tiles (chunk form): one camera each
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -90,13 +91,12 @@ struct ProbDev {
   const int32_t *cam_obs_start;   // [Cf + 1] records of each free camera
   const int32_t *up_pair_start;   // [n_up + 1]
   const int2 *pairs;              // (c_a, c_b): records of one point in cameras a < b
-  // point-chunk form: records are point-major; a chunk's entries are the S blocks
-  // it contributes to, each with its items (diagonal: local observation; upper:
-  // local observation pair p | q << 16), wave-mode entries first
+  // point-chunk form: records are point-major; a chunk's entries are runs of at
+  // most kChSubItems items of one S block (diagonal: local observation; upper:
+  // local observation pair p | q << 16), diagonal entries first
   const int32_t *ch_pt;           // [n_ch + 1] point range of each chunk
   const int32_t *ch_f0;           // [n_ch + 1] record range of each chunk
   const int32_t *ch_ent;          // [n_ch + 1] entry range of each chunk
-  const int32_t *ch_nwave;        // [n_ch] wave-mode entries at the start of the range
   const int32_t *ch_cam_start;    // [n_ch + 1] range in ch_cam
   const int32_t *ch_cam;          // cameras (caller's index) of each chunk's entries
   const int32_t *ent_tgt;         // target block: a < Cf diagonal of camera a, Cf + u upper block u

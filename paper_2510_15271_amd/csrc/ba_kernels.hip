@@ -822,18 +822,43 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 //   a. V*_j = V_j + lambda D_j inverted in FP64 for the chunk's points;
 //   b. for each of the chunk's records: decoded J_pi and P_c, Q = J_p V*^-1
 //      (2x3), Q g_p (2) and the weighted residual, all staged in LDS;
-//   c. every S block the chunk touches (an entry) is summed over its items in
-//      point order -- by a whole wavefront (lanes over items, then a butterfly)
-//      for diagonal blocks and long entries, by one thread otherwise -- and
-//      written as the chunk's partial of that block.
+//   c. each entry (a run of at most kChSubItems items of one S block, in point
+//      order) is summed by one thread and written as its own partial.
 // A block's partials are then summed in chunk order by k_schur_reduce, so S does
 // not depend on scheduling and each record is read from HBM once per iteration.
 // FP64 runs 512 threads so that the accumulators fit in registers.
 template <class T>
 constexpr int chunk_threads() { return sizeof(T) == 8 ? kChThreads / 2 : kChThreads; }
 
+// Rows of 8 values in LDS (16-byte aligned), moved with 16-byte accesses.
+__device__ inline void load8(const float *p, float o[8]) {
+  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+  o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+  o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+}
+__device__ inline void load8(const double *p, double o[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 a = *(const double2 *)(p + 2 * i);
+    o[2 * i] = a.x;
+    o[2 * i + 1] = a.y;
+  }
+}
+__device__ inline void store8(float *p, const float v[8]) {
+  *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+  *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+}
+__device__ inline void store8(double *p, const double v[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) *(double2 *)(p + 2 * i) = make_double2(v[2 * i], v[2 * i + 1]);
+}
+
 template <class T>
-__device__ inline void pair_accumulate(T acc[36], const T *fa, const T *q, const T *fb, const T *Rb) {
+__device__ inline void pair_accumulate(T acc[36], const T *fa_lds, const T *q_lds, const T *fb_lds, const T *Rb) {
+  T fa[8], q[8], fb[8];
+  load8(fa_lds, fa);
+  load8(q_lds, q);
+  load8(fb_lds, fb);
   T Jca[12], Jcb[12], Jpb[6];
   jc_from(fa, Jca);
   jc_from(fb, Jcb);
@@ -859,13 +884,14 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   constexpr int ccap = sizeof(T) == 8 ? 128 : 256;
   constexpr bool k16 = sizeof(S) == 2;
   constexpr int nth = chunk_threads<T>();
-  extern __shared__ double s_dyn[];
+  extern __shared__ __align__(16) double s_dyn[];
+  // per record two rows of 8 (16-byte aligned, read with vector loads):
+  // fe = f[0..6], e[0]; qq = Q[0..5], Q g_p[0..1]
   T *s_vi = (T *)s_dyn;           // [pcap][6]
-  T *s_f = s_vi + 6 * pcap;       // [cap][7]
-  T *s_q = s_f + 7 * cap;         // [cap][6]
-  T *s_qg = s_q + 6 * cap;        // [cap][2]
-  T *s_e = s_qg + 2 * cap;        // [cap][2]
-  T *s_R = s_e + 2 * cap;         // [ccap][9] rotations of the chunk's cameras
+  T *s_fe = s_vi + 6 * pcap;      // [cap][8]
+  T *s_qq = s_fe + 8 * cap;       // [cap][8]
+  T *s_e1 = s_qq + 8 * cap;       // [cap]: e[1]
+  T *s_R = s_e1 + cap;            // [ccap][9] rotations of the chunk's cameras
   int *s_k = (int *)(s_R + 9 * ccap);  // [cap]
   int *s_cam = s_k + cap;         // [ccap]
   const Tile tl = tiles[blockIdx.x];
@@ -944,172 +970,141 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
 #pragma unroll
           for (int m = 0; m < 3; ++m)
             q[3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
-#pragma unroll
-        for (int i = 0; i < 7; ++i) s_f[7 * l + i] = f[i];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) s_q[6 * l + i] = q[i];
         const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
-        s_qg[2 * l] = q[0] * g0 + q[1] * g1 + q[2] * g2;
-        s_qg[2 * l + 1] = q[3] * g0 + q[4] * g1 + q[5] * g2;
-        s_e[2 * l] = rec[h].e[0];
-        s_e[2 * l + 1] = rec[h].e[1];
+        T fe[8], qq[8];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) fe[i] = f[i];
+        fe[7] = rec[h].e[0];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) qq[i] = q[i];
+        qq[6] = q[0] * g0 + q[1] * g1 + q[2] * g2;
+        qq[7] = q[3] * g0 + q[4] * g1 + q[5] * g2;
+        store8(s_fe + 8 * l, fe);
+        store8(s_qq + 8 * l, qq);
+        s_e1[l] = rec[h].e[1];
         s_k[l] = kk[h];
       }
     }
   }
   __syncthreads();
-  // c. entries.  Wave-mode entries: wave w takes entries w, w + 16, ... of the
-  // chunk; lane x first loads the descriptor and camera rotation of the wave's
-  // x-th entry, so the descriptors arrive together and are broadcast by shuffles.
-  const int e0 = pd.ch_ent[c], ew = e0 + pd.ch_nwave[c], e1 = pd.ch_ent[c + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int nw = nth / 64;
+  // c. entries, one thread each: sums over at most kChSubItems items of one
+  // block, all item indices loaded before the arithmetic
+  const int e0 = pd.ch_ent[c], e1 = pd.ch_ent[c + 1];
   T *pdg = (T *)pd.part_d;
   T *pof = (T *)pd.part_o;
-  for (int eb = e0 + wv; eb < ew; eb += 64 * nw) {
-    const int my = eb + nw * lane;
-    int m_tgt = 0, m_i0 = 0, m_i1 = 0, m_slot = 0, m_lc = 0;
-    if (my < ew) {
-      m_tgt = pd.ent_tgt[my];
-      m_i0 = pd.ent_start[my];
-      m_i1 = pd.ent_start[my + 1];
-      m_slot = pd.ent_slot[my];
-      m_lc = pd.ent_cam[my];
-    }
-    const int cnt = min(64, (ew - eb + nw - 1) / nw);
-    for (int x = 0; x < cnt; ++x) {
-      const int tgt = __shfl(m_tgt, x, 64);
-      const int i0 = __shfl(m_i0, x, 64), i1 = __shfl(m_i1, x, 64);
-      const int slot = __shfl(m_slot, x, 64);
-      const int lc = __shfl(m_lc, x, 64);
-      const int cam = s_cam[lc];
-      const T *R = s_R + 9 * lc;
-      if (tgt < pd.Cf) {
-        // diagonal block of camera cam over its observations, in two passes to
-        // bound the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
-        const T *K = (const T *)pd.K + 4 * cam;
-        const T delta = T(st->huber_delta);
-        T acc[33];
-#pragma unroll
-        for (int i = 0; i < 33; ++i) acc[i] = T(0);
-        for (int it = i0 + lane; it < i1; it += 64) {
-          const int l = (int)pd.ent_items[it];
-          T Jc[12];
-          jc_from(s_f + 7 * l, Jc);
-          const T *Jc0 = Jc, *Jc1 = Jc + 6;
-          int u = 0;
-#pragma unroll
-          for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
-          const T qg0 = s_qg[2 * l], qg1 = s_qg[2 * l + 1];
-#pragma unroll
-          for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qg0 + Jc1[r] * qg1;
-          if (k16) {
-            // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here
-            const int k = s_k[l];
-            const double *pose = poses + 12 * cam;
-            double xd, yd, zd;
-            transform(pose, pd.X[st->cur] + 3 * pd.obs_pt[k], xd, yd, zd);
-            const T xv = T(xd), yv = T(yd), zv = T(zd);
-            const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
-            T r0, r1;
-            if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
-              const T sq = r0 * r0 + r1 * r1;
-              const T w = huber_w(sq, delta);
-              T Jg[12], Jpg[6];
-              jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
-#pragma unroll
-              for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
-            }
-          } else {
-            const T e0v = s_e[2 * l], e1v = s_e[2 * l + 1];
-#pragma unroll
-            for (int r = 0; r < 6; ++r) acc[21 + r] += Jc0[r] * e0v + Jc1[r] * e1v;
-          }
-        }
-        T *o = pdg + 54 * (size_t)slot;
-        int idx;
-        T mine = wave_reduce_scatter(acc, lane, idx);
-        // partial layout: U (21), Y W^T (21), g_c (6), Y g_p (6)
-        if (idx < 21) o[idx] = mine;
-        else if (idx < 33) o[21 + idx] = mine;
-        T acw[21];
-#pragma unroll
-        for (int i = 0; i < 21; ++i) acw[i] = T(0);
-        for (int it = i0 + lane; it < i1; it += 64) {
-          const int l = (int)pd.ent_items[it];
-          const T *f = s_f + 7 * l;
-          const T *q = s_q + 6 * l;
-          T Jc[12], Jp[6];
-          jc_from(f, Jc);
-          jp_from(f, R, Jp);
-          const T *Jc0 = Jc, *Jc1 = Jc + 6;
-          const T m00 = q[0] * Jp[0] + q[1] * Jp[1] + q[2] * Jp[2];
-          const T m01 = q[0] * Jp[3] + q[1] * Jp[4] + q[2] * Jp[5];
-          const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
-          const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
-          int u = 0;
-#pragma unroll
-          for (int r = 0; r < 6; ++r) {
-            const T z0 = Jc0[r] * m00 + Jc1[r] * m10;
-            const T z1 = Jc0[r] * m01 + Jc1[r] * m11;
-#pragma unroll
-            for (int cc = r; cc < 6; ++cc, ++u) acw[u] += z0 * Jc0[cc] + z1 * Jc1[cc];
-          }
-        }
-        mine = wave_reduce_scatter(acw, lane, idx);
-        if (idx < 21) o[21 + idx] = mine;
-      } else {
-        T acc[36];
-#pragma unroll
-        for (int i = 0; i < 36; ++i) acc[i] = T(0);
-        // items of this lane: i0 + lane, i0 + lane + 64, ... (four loads in flight)
-        for (int it = i0 + lane; it < i1; it += 256) {
-          uint32_t pq[4];
-#pragma unroll
-          for (int h = 0; h < 4; ++h) pq[h] = it + 64 * h < i1 ? pd.ent_items[it + 64 * h] : 0u;
-#pragma unroll
-          for (int h = 0; h < 4; ++h)
-            if (it + 64 * h < i1) {
-              const int p = (int)(pq[h] & 0xffffu), qq = (int)(pq[h] >> 16);
-              pair_accumulate<T>(acc, s_f + 7 * p, s_q + 6 * p, s_f + 7 * qq, R);
-            }
-        }
-        int idx;
-        const T mine = wave_reduce_scatter(acc, lane, idx);
-        if (idx < 36) pof[36 * (size_t)slot + idx] = mine;
-      }
-    }
-  }
-  // short upper entries (fewer than kChWaveItems items), one thread each, all
-  // items loaded before the arithmetic
-  for (int e = ew + threadIdx.x; e < e1; e += nth) {
-    const int i0 = pd.ent_start[e], i1 = pd.ent_start[e + 1];
+  for (int e = e0 + threadIdx.x; e < e1; e += nth) {
+    const int tgt = pd.ent_tgt[e];
+    const int i0 = pd.ent_start[e], n = pd.ent_start[e + 1] - i0;
     const int slot = pd.ent_slot[e];
-    const T *R = s_R + 9 * pd.ent_cam[e];
-    T acc[36];
+    const int lc = pd.ent_cam[e];
+    const T *R = s_R + 9 * lc;
+    uint32_t items[kChSubItems];
 #pragma unroll
-    for (int i = 0; i < 36; ++i) acc[i] = T(0);
-    for (int it = i0; it < i1; it += 8) {
-      uint32_t pq[8];
+    for (int h = 0; h < kChSubItems; ++h) items[h] = h < n ? pd.ent_items[i0 + h] : 0u;
+    if (tgt < pd.Cf) {
+      // diagonal block of camera cam over its observations, in two passes to bound
+      // the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
+      const int cam = s_cam[lc];
+      T *o = pdg + 54 * (size_t)slot;
+      T acc[33];
 #pragma unroll
-      for (int h = 0; h < 8; ++h) pq[h] = it + h < i1 ? pd.ent_items[it + h] : 0u;
+      for (int i = 0; i < 33; ++i) acc[i] = T(0);
 #pragma unroll
-      for (int h = 0; h < 8; ++h)
-        if (it + h < i1) {
-          const int p = (int)(pq[h] & 0xffffu), qq = (int)(pq[h] >> 16);
-          pair_accumulate<T>(acc, s_f + 7 * p, s_q + 6 * p, s_f + 7 * qq, R);
+      for (int h = 0; h < kChSubItems; ++h) {
+        if (h >= n) break;
+        const int l = (int)items[h];
+        T fe[8], qq[8];
+        load8(s_fe + 8 * l, fe);
+        load8(s_qq + 8 * l, qq);
+        T Jc[12];
+        jc_from(fe, Jc);
+        const T *Jc0 = Jc, *Jc1 = Jc + 6;
+        int u = 0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qq[6] + Jc1[r] * qq[7];
+        if (k16) {
+          // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here
+          const T *K = (const T *)pd.K + 4 * cam;
+          const T delta = T(st->huber_delta);
+          const int k = s_k[l];
+          const double *pose = poses + 12 * cam;
+          double xd, yd, zd;
+          transform(pose, pd.X[st->cur] + 3 * pd.obs_pt[k], xd, yd, zd);
+          const T xv = T(xd), yv = T(yd), zv = T(zd);
+          const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
+          T r0, r1;
+          if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+            const T sq = r0 * r0 + r1 * r1;
+            const T w = huber_w(sq, delta);
+            T Jg[12], Jpg[6];
+            jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
+#pragma unroll
+            for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
+          }
+        } else {
+          const T e0v = fe[7], e1v = s_e1[l];
+#pragma unroll
+          for (int r = 0; r < 6; ++r) acc[21 + r] += Jc0[r] * e0v + Jc1[r] * e1v;
         }
-    }
-    T *o = pof + 36 * (size_t)slot;
+      }
+      // partial layout: U (21), Y W^T (21), g_c (6), Y g_p (6)
 #pragma unroll
-    for (int i = 0; i < 36; ++i) o[i] = acc[i];
+      for (int i = 0; i < 21; ++i) o[i] = acc[i];
+#pragma unroll
+      for (int i = 21; i < 33; ++i) o[21 + i] = acc[i];
+      T acw[21];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) acw[i] = T(0);
+#pragma unroll
+      for (int h = 0; h < kChSubItems; ++h) {
+        if (h >= n) break;
+        const int l = (int)items[h];
+        T f[8], q[8];
+        load8(s_fe + 8 * l, f);
+        load8(s_qq + 8 * l, q);
+        T Jc[12], Jp[6];
+        jc_from(f, Jc);
+        jp_from(f, R, Jp);
+        const T *Jc0 = Jc, *Jc1 = Jc + 6;
+        const T m00 = q[0] * Jp[0] + q[1] * Jp[1] + q[2] * Jp[2];
+        const T m01 = q[0] * Jp[3] + q[1] * Jp[4] + q[2] * Jp[5];
+        const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
+        const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
+        int u = 0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          const T z0 = Jc0[r] * m00 + Jc1[r] * m10;
+          const T z1 = Jc0[r] * m01 + Jc1[r] * m11;
+#pragma unroll
+          for (int cc = r; cc < 6; ++cc, ++u) acw[u] += z0 * Jc0[cc] + z1 * Jc1[cc];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 21; ++i) o[21 + i] = acw[i];
+    } else {
+      T acc[36];
+#pragma unroll
+      for (int i = 0; i < 36; ++i) acc[i] = T(0);
+#pragma unroll
+      for (int h = 0; h < kChSubItems; ++h) {
+        if (h >= n) break;
+        const int p = (int)(items[h] & 0xffffu), qq = (int)(items[h] >> 16);
+        pair_accumulate<T>(acc, s_fe + 8 * p, s_qq + 8 * p, s_fe + 8 * qq, R);
+      }
+      T *o = pof + 36 * (size_t)slot;
+#pragma unroll
+      for (int i = 0; i < 36; ++i) o[i] = acc[i];
+    }
   }
 }
 
-// Upper blocks, one wavefront each: the block's chunk partials (contiguous rows
-// of 36, chunk order) summed in FP64, written as S_ab = -sum and S_ba = its
+// Upper blocks: one thread per (block, element), 256 elements per tile.  The
+// block's chunk partials are contiguous rows of 36 in chunk order; the element
+// is summed over them in FP64 and written as S_ab = -sum and into S_ba, its
 // transpose.
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict__ probs,
@@ -1118,28 +1113,29 @@ __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict_
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int u = 4 * tl.idx + wv;
-  if (u >= pd.n_up || lane >= 36) return;  // no workgroup barrier follows
+  const int g = 256 * tl.idx + (int)threadIdx.x;
+  const int u = g / 36, e = g - 36 * (g / 36);
+  if (u >= pd.n_up) return;  // no workgroup barrier follows
   const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
-  const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent);
+  const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent) + e;
   double t = 0.0;
   for (int x = 0; x < n; x += 16) {  // sixteen partials in flight, summed in order
     T v[16];
 #pragma unroll
-    for (int h = 0; h < 16; ++h) v[h] = x + h < n ? part[36 * (size_t)(x + h) + lane] : T(0);
+    for (int h = 0; h < 16; ++h) v[h] = x + h < n ? part[36 * (size_t)(x + h)] : T(0);
 #pragma unroll
     for (int h = 0; h < 16; ++h) t += (double)v[h];
   }
-  const int r = lane / 6, cc = lane % 6;
+  const int r = e / 6, cc = e - 6 * (e / 6);
   const T v = T(-t);
   T *Sv = (T *)pd.S;
-  Sv[36 * (size_t)pd.up_pos[u] + lane] = v;
+  Sv[36 * (size_t)pd.up_pos[u] + e] = v;
   Sv[36 * (size_t)pd.up_tpos[u] + 6 * cc + r] = v;
 }
 
-// Camera rows, one wavefront each: the diagonal partials (rows of 54) summed in
-// FP64, then finish_camera_row by lane 0.
+// Camera rows, one workgroup each: wave w sums the w-th quarter of the row's
+// diagonal partials (rows of 54), the four quarter sums are added in order in
+// FP64, then finish_camera_row by thread 0.
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_rows(const ProbDev *__restrict__ probs,
                                                     const Tile *__restrict__ tiles) {
@@ -1148,23 +1144,28 @@ __global__ __launch_bounds__(256) void k_schur_rows(const ProbDev *__restrict__ 
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int a = 4 * tl.idx + wv;
-  if (a >= pd.Cf) return;  // wave-uniform; no workgroup barrier follows
+  const int a = tl.idx;
   const int b0 = pd.blk_start[a], n = pd.blk_start[a + 1] - b0;
+  const int q = (n + 3) / 4, x0 = wv * q, x1 = min(n, x0 + q);
   const T *part = (const T *)pd.part_d + 54 * (size_t)b0;
+  __shared__ double s_t[4][54];
   double t = 0.0;
   if (lane < 54)
-    for (int x = 0; x < n; x += 8) {
-      T v[8];
+    for (int x = x0; x < x1; x += 16) {
+      T v[16];
 #pragma unroll
-      for (int h = 0; h < 8; ++h) v[h] = x + h < n ? part[54 * (size_t)(x + h) + lane] : T(0);
+      for (int h = 0; h < 16; ++h) v[h] = x + h < x1 ? part[54 * (size_t)(x + h) + lane] : T(0);
 #pragma unroll
-      for (int h = 0; h < 8; ++h) t += (double)v[h];
+      for (int h = 0; h < 16; ++h) t += (double)v[h];
     }
-  double tot[54];
+  if (lane < 54) s_t[wv][lane] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[54];
 #pragma unroll
-  for (int i = 0; i < 54; ++i) tot[i] = __shfl(t, i, 64);
-  if (lane == 0) finish_camera_row<T>(pd, st, a, tot);
+    for (int i = 0; i < 54; ++i) tot[i] = s_t[0][i] + s_t[1][i] + s_t[2][i] + s_t[3][i];
+    finish_camera_row<T>(pd, st, a, tot);
+  }
 }
 
 // ------------------------------------------------------------------ PCG

@@ -39,7 +39,7 @@ struct Symbolic {
   std::vector<int32_t> up_pair_start;
   std::vector<int2> pairs;
   // point-chunk form (see ProbDev)
-  std::vector<int32_t> ch_pt, ch_f0, ch_ent, ch_nwave, ch_cam_start, ch_cam;
+  std::vector<int32_t> ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam;
   std::vector<int32_t> ent_tgt, ent_cam, ent_slot, ent_start;
   std::vector<uint32_t> ent_items;
   std::vector<int32_t> blk_start;
@@ -55,7 +55,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
-  size_t ch_pt, ch_f0, ch_ent, ch_nwave, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
+  size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
   size_t part_d, part_o;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
