@@ -1026,29 +1026,54 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
           for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
 #pragma unroll
         for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qq[6] + Jc1[r] * qq[7];
-        if (k16) {
-          // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here
-          const T *K = (const T *)pd.K + 4 * cam;
-          const T delta = T(st->huber_delta);
-          const int k = s_k[l];
-          const double *pose = poses + 12 * cam;
-          double xd, yd, zd;
-          transform(pose, pd.X[st->cur] + 3 * pd.obs_pt[k], xd, yd, zd);
-          const T xv = T(xd), yv = T(yd), zv = T(zd);
-          const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
-          T r0, r1;
-          if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
-            const T sq = r0 * r0 + r1 * r1;
-            const T w = huber_w(sq, delta);
-            T Jg[12], Jpg[6];
-            jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
-#pragma unroll
-            for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
-          }
-        } else {
+        if (!k16) {
           const T e0v = fe[7], e1v = s_e1[l];
 #pragma unroll
           for (int r = 0; r < 6; ++r) acc[21 + r] += Jc0[r] * e0v + Jc1[r] * e1v;
+        }
+      }
+      if (k16) {
+        // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here,
+        // four observations at a time so that their loads overlap
+        const T *K = (const T *)pd.K + 4 * cam;
+        const T delta = T(st->huber_delta);
+        const double *pose = poses + 12 * cam;
+        const double *Xs = pd.X[st->cur];
+        const T *uvs = (const T *)pd.obs_uv;
+#pragma unroll
+        for (int h0 = 0; h0 < kChSubItems; h0 += 4) {
+          if (h0 >= n) break;
+          int kk[4], jj[4];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) kk[h] = h0 + h < n ? s_k[items[h0 + h]] : -1;
+#pragma unroll
+          for (int h = 0; h < 4; ++h) jj[h] = kk[h] >= 0 ? pd.obs_pt[kk[h]] : 0;
+          double Xv[4][3];
+          T uv[4][2];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int ko = kk[h] >= 0 ? kk[h] : 0;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Xv[h][m] = Xs[3 * (size_t)jj[h] + m];
+            uv[h][0] = uvs[2 * (size_t)ko];
+            uv[h][1] = uvs[2 * (size_t)ko + 1];
+          }
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            if (kk[h] < 0) continue;
+            double xd, yd, zd;
+            transform(pose, Xv[h], xd, yd, zd);
+            const T xv = T(xd), yv = T(yd), zv = T(zd);
+            T r0, r1;
+            if (residual<T>(K, xv, yv, zv, uv[h][0], uv[h][1], r0, r1)) {
+              const T sq = r0 * r0 + r1 * r1;
+              const T w = huber_w(sq, delta);
+              T Jg[12], Jpg[6];
+              jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
+#pragma unroll
+              for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
+            }
+          }
         }
       }
       // partial layout: U (21), Y W^T (21), g_c (6), Y g_p (6)

@@ -247,3 +247,30 @@ def test_profiled_solves_equal_unprofiled(balib):
     for r in (b, c):
         assert np.array_equal(r["iter_cost"], a["iter_cost"])
         assert np.array_equal(r["X"], a["X"]) and np.array_equal(r["q"], a["q"])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16j", "bf16j"])
+def test_loop_scene_against_stored_oracle_run(balib, prec):
+    """The 11M-observation loop-closed drive (3000 cameras, 5 % outliers, Huber
+    1 px, 15 LM iterations, PCG 50 / 1e-6) against the FP64 oracle's run of the
+    same schedule stored by tests/golden/make_config2_golden.py: same accepted
+    steps and PCG counts, every C_n within 1e-6 (FP32) / 1e-5 (16-bit storage)
+    relative, and the final RMS over all observations and over inliers (<= 3 px),
+    both recomputed by the oracle at the device's state, within 1e-3 px."""
+    import json
+    import os
+    from synth import make_config2
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config2_oracle.json")))
+    s = make_config2()
+    res = _solve(balib, s, max_iters=15, precision=prec)
+    rel = np.abs(res["iter_cost"] - np.array(gold["iter_cost"])) / np.array(gold["iter_cost"])
+    _say(prec, "max rel cost", rel.max(), "pcg", list(res["pcg_iters"]))
+    assert rel.max() <= (1e-6 if prec == "f32" else 1e-5)
+    assert list(res["pcg_iters"]) == gold["pcg_iters"]
+    p, R, t, X = _oracle_state(s, res)
+    rms = O.rms(p, R, t, X)
+    irms = O.rms(p, R, t, X, inlier_px=3.0)
+    _say(prec, "rms", rms, gold["final_rms_px"], "inlier rms", irms, gold["final_inlier_rms_px"])
+    assert abs(rms - gold["final_rms_px"]) <= 1e-3
+    assert abs(irms - gold["final_inlier_rms_px"]) <= 1e-3
+    assert res["n_masked"] == gold["n_masked"]
