@@ -227,7 +227,7 @@ class Problem:
         return {f: getattr(i, f) for f, _ in ProblemInfo._fields_}
 
     def kernel_times(self):
-        n = 16
+        n = 32
         names = (C.c_char_p * n)()
         ms = (C.c_double * n)()
         la = (C.c_int32 * n)()

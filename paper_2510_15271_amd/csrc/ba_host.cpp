@@ -180,48 +180,60 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
   sy.ent_start.assign(1, 0);
   sy.ent_items.clear();
   sy.n_dent = sy.n_oent = 0;
-  std::vector<std::pair<uint64_t, uint32_t>> it;
-  std::vector<int32_t> la, ll;  // free camera and local record of one point's observations
+  std::vector<int32_t> la, ll;  // local camera and local record of one point's observations
+  std::vector<int32_t> kcnt;     // items per (local camera a, local camera b) key
+  std::vector<uint32_t> items, sorted;
+  std::vector<int32_t> keys;
   struct Ent {
     int32_t a, b;
     size_t i0, i1;
   };
   std::vector<Ent> wave, thread;  // diagonal and upper entries of one chunk
   for (int c = 0; c < n_ch; ++c) {
-    it.clear();
     const int f0 = sy.ch_f0[c];
-    // chunk-local camera index of each free camera of the chunk
-    for (int x = sy.ch_cam_start[c]; x < sy.ch_cam_start[c + 1]; ++x)
-      lcam[sy.free_idx[sy.ch_cam[x]]] = x - sy.ch_cam_start[c];
+    const int q0 = sy.ch_cam_start[c], nq = sy.ch_cam_start[c + 1] - q0;
+    // chunk-local camera index of each free camera of the chunk (cameras sorted)
+    for (int x = 0; x < nq; ++x) lcam[sy.free_idx[sy.ch_cam[q0 + x]]] = x;
+    // items keyed by (a, b) in local camera indices, stably counting-sorted by key
+    keys.clear();
+    items.clear();
     for (int j = sy.ch_pt[c]; j < sy.ch_pt[c + 1]; ++j) {
       la.clear();
       ll.clear();
       for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k)
         if (sy.obs_rpos[k] >= 0) {
-          la.push_back(sy.free_idx[sy.obs_cam[k]]);
+          la.push_back(lcam[sy.free_idx[sy.obs_cam[k]]]);
           ll.push_back(sy.obs_rpos[k] - f0);
         }
       for (size_t x = 0; x < la.size(); ++x) {
-        it.push_back({((uint64_t)la[x] << 32) | (uint32_t)la[x], (uint32_t)ll[x]});
-        for (size_t y = x + 1; y < la.size(); ++y)
-          it.push_back({((uint64_t)la[x] << 32) | (uint32_t)la[y], (uint32_t)ll[x] | ((uint32_t)ll[y] << 16)});
+        keys.push_back(la[x] * nq + la[x]);
+        items.push_back((uint32_t)ll[x]);
+        for (size_t y = x + 1; y < la.size(); ++y) {
+          keys.push_back(la[x] * nq + la[y]);
+          items.push_back((uint32_t)ll[x] | ((uint32_t)ll[y] << 16));
+        }
       }
     }
-    std::stable_sort(it.begin(), it.end(),
-                     [](const std::pair<uint64_t, uint32_t> &p, const std::pair<uint64_t, uint32_t> &q) {
-                       return p.first < q.first;
-                     });
+    kcnt.assign((size_t)nq * nq + 1, 0);
+    for (int32_t kk : keys) kcnt[kk + 1]++;
+    for (size_t x = 0; x < (size_t)nq * nq; ++x) kcnt[x + 1] += kcnt[x];
+    sorted.resize(items.size());
+    {
+      std::vector<int32_t> fillk(kcnt.begin(), kcnt.end() - 1);
+      for (size_t x = 0; x < items.size(); ++x) sorted[fillk[keys[x]]++] = items[x];
+    }
     wave.clear();
     thread.clear();
-    for (size_t i = 0; i < it.size();) {
-      size_t e = i;
-      while (e < it.size() && it[e].first == it[i].first) ++e;
-      const int32_t a = (int32_t)(it[i].first >> 32), b = (int32_t)(it[i].first & 0xffffffffu);
+    for (int key = 0; key < nq * nq; ++key) {
+      const size_t i = kcnt[key], e = kcnt[key + 1];
+      if (i == e) continue;
+      // one observation (pair) per point and block: the kernel relies on this bound
+      if (e - i > (size_t)pcap) return fail(BA_EDEVICE, "internal: entry with %zu items", e - i);
+      const int32_t a = sy.free_idx[sy.ch_cam[q0 + key / nq]], b = sy.free_idx[sy.ch_cam[q0 + key % nq]];
       for (size_t x = i; x < e; x += kChSubItems) {
         const Ent en{a, b, x, std::min(e, x + kChSubItems)};
         (a == b ? wave : thread).push_back(en);
       }
-      i = e;
     }
     // threads of a wavefront run their entries side by side: group equal lengths
     const auto longer = [](const Ent &p, const Ent &q) { return p.i1 - p.i0 > q.i1 - q.i0; };
@@ -241,7 +253,7 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
           sy.ent_cam.push_back(lcam[en.b]);
           sy.ent_slot.push_back(sy.n_oent++);
         }
-        for (size_t i = en.i0; i < en.i1; ++i) sy.ent_items.push_back(it[i].second);
+        for (size_t i = en.i0; i < en.i1; ++i) sy.ent_items.push_back(sorted[i]);
         if (sy.ent_items.size() > (size_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 chunk items");
         sy.ent_start.push_back((int32_t)sy.ent_items.size());
       }
@@ -551,6 +563,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.blk_start = L.take(sy.blk_start.size() * 4 + 4);
   o.part_d = L.take((size_t)sy.n_dent * 54 * T + 16);
   o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
+  o.row_tot = L.take(sy.chunked ? Cf * 54 * 8 : 16);
   o.up_pos = L.take(sy.n_up * 4 + 4);
   o.up_tpos = L.take(sy.n_up * 4 + 4);
   o.diag_pos = L.take(Cf * 4);
@@ -632,8 +645,9 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.Nf = sy.Nf;
   pd.chunked = sy.chunked ? 1 : 0;
   pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
-  pd.n_red_tiles = sy.chunked ? (int32_t)(((int64_t)sy.n_up * 36 + 255) / 256) : 0;
+  pd.n_red_tiles = sy.chunked ? (int32_t)(((int64_t)sy.n_up * 36 + 63) / 64) : 0;
   pd.n_fin_tiles = sy.chunked ? Cf : 0;
+  pd.n_fsh_tiles = sy.chunked ? (Cf + 63) / 64 : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
@@ -665,6 +679,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_dent = sy.n_dent;
   pd.part_d = ptr(off.part_d);
   pd.part_o = ptr(off.part_o);
+  pd.row_tot = (double *)ptr(off.row_tot);
   pd.up_pos = (const int32_t *)ptr(off.up_pos);
   pd.up_tpos = (const int32_t *)ptr(off.up_tpos);
   pd.diag_pos = (const int32_t *)ptr(off.diag_pos);
@@ -827,6 +842,7 @@ void Batch::add(const ProbDev &pd, int slot_tag) {
     for (int c = 0; c < pd.n_ch; ++c) tiles[7].push_back(Tile{pi, c});
     for (int t = 0; t < pd.n_red_tiles; ++t) tiles[8].push_back(Tile{pi, t});
     for (int t = 0; t < pd.n_fin_tiles; ++t) tiles[9].push_back(Tile{pi, t});
+    for (int t = 0; t < pd.n_fsh_tiles; ++t) tiles[10].push_back(Tile{pi, t});
   } else {
     for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[6].push_back(Tile{pi, t});
     for (int a = 0; a < pd.Cf; ++a) tiles[1].push_back(Tile{pi, a});
@@ -857,7 +873,7 @@ int Batch::upload(hipStream_t s) {
   xcd_contiguous(tiles[2]);
   xcd_contiguous(tiles[7]);
   size_t need = probs.size() * sizeof(ProbDev);
-  constexpr int NL = 10;
+  constexpr int NL = 11;
   size_t offs[NL];
   for (int i = 0; i < NL; ++i) {
     need = (need + 255) & ~size_t(255);
@@ -880,10 +896,10 @@ int Batch::upload(hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "batch table upload");
   char *b = (char *)dev;
   plan.probs = (const ProbDev *)b;
-  const Tile **dst[NL] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam,
-                          &plan.ctl, &plan.pp, &plan.ch, &plan.red, &plan.fin};
-  int32_t *cnt[NL] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam,
-                      &plan.n_ctl, &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin};
+  const Tile **dst[NL] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam, &plan.ctl,
+                          &plan.pp, &plan.ch, &plan.red, &plan.fin, &plan.fsh};
+  int32_t *cnt[NL] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam, &plan.n_ctl,
+                      &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin, &plan.n_fsh};
   for (int i = 0; i < NL; ++i) {
     *dst[i] = (const Tile *)(b + offs[i]);
     *cnt[i] = (int32_t)tiles[i].size();

@@ -75,8 +75,9 @@ struct ProbDev {
   int32_t max_tcols;     // longest tile column list
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
-  int32_t n_red_tiles;   // reduction tiles (chunk form): 256 elements of the upper blocks each
+  int32_t n_red_tiles;   // reduction tiles (chunk form): 64 elements of the upper blocks each
   int32_t n_fin_tiles;   // camera-row tiles (chunk form): one camera each
+  int32_t n_fsh_tiles;   // camera-finish tiles (chunk form): 64 cameras each
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -121,6 +122,7 @@ struct ProbDev {
   void *lin;                      // [Nf] LinRec<T, S>
   void *part_d;                   // [diagonal entries][54] T: U, Y W^T (upper 21 each), g_c, Y g_p
   void *part_o;                   // [upper entries][36] T: sum Y W^T of the entry
+  double *row_tot;                // [Cf][54] camera-row sums of the diagonal partials
   void *Q;                        // [Nf][6] T: J_p,k V*_j^-1 (2x3), camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
@@ -151,8 +153,8 @@ struct ProbDev {
 // Tile lists of one batch (device pointers) and their lengths.
 struct BatchPlan {
   const ProbDev *probs;
-  const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin;
-  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin;
+  const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh;
+  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh;
 };
 
 // One localization request on the device.
@@ -176,7 +178,7 @@ struct KernelTimer {
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
-  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_NUM_KERNELS
+  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 

@@ -39,7 +39,7 @@ namespace bax {
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
-    "schur_reduce", "schur_rows"};
+    "schur_reduce", "schur_rows", "schur_finish"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -1127,10 +1127,10 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   }
 }
 
-// Upper blocks: one thread per (block, element), 256 elements per tile.  The
-// block's chunk partials are contiguous rows of 36 in chunk order; the element
-// is summed over them in FP64 and written as S_ab = -sum and into S_ba, its
-// transpose.
+// Upper blocks: 64 (block, element) pairs per tile, each summed by four waves
+// over four consecutive segments of the block's chunk partials (contiguous rows
+// of 36, chunk order) in FP64; the four segment sums are added in order and the
+// element is written as S_ab = -sum and into S_ba, its transpose.
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict__ probs,
                                                       const Tile *__restrict__ tiles) {
@@ -1138,32 +1138,43 @@ __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict_
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
-  const int g = 256 * tl.idx + (int)threadIdx.x;
+  __shared__ double s_seg[4][64];
+  const int el = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int g = 64 * tl.idx + el;
   const int u = g / 36, e = g - 36 * (g / 36);
-  if (u >= pd.n_up) return;  // no workgroup barrier follows
-  const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
-  const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent) + e;
+  const bool live = u < pd.n_up;
   double t = 0.0;
-  for (int x = 0; x < n; x += 16) {  // sixteen partials in flight, summed in order
-    T v[16];
+  if (live) {
+    const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
+    const int q = (n + 3) / 4, x0 = seg * q, x1 = min(n, x0 + q);
+    const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent) + e;
+    for (int x = x0; x < x1; x += 16) {  // sixteen partials in flight, summed in order
+      T v[16];
 #pragma unroll
-    for (int h = 0; h < 16; ++h) v[h] = x + h < n ? part[36 * (size_t)(x + h)] : T(0);
+      for (int h = 0; h < 16; ++h) v[h] = x + h < x1 ? part[36 * (size_t)(x + h)] : T(0);
 #pragma unroll
-    for (int h = 0; h < 16; ++h) t += (double)v[h];
+      for (int h = 0; h < 16; ++h) t += (double)v[h];
+    }
   }
-  const int r = e / 6, cc = e - 6 * (e / 6);
-  const T v = T(-t);
-  T *Sv = (T *)pd.S;
-  Sv[36 * (size_t)pd.up_pos[u] + e] = v;
-  Sv[36 * (size_t)pd.up_tpos[u] + 6 * cc + r] = v;
+  s_seg[seg][el] = t;
+  __syncthreads();
+  if (seg == 0 && live) {
+    const double tot = s_seg[0][el] + s_seg[1][el] + s_seg[2][el] + s_seg[3][el];
+    const int r = e / 6, cc = e - 6 * (e / 6);
+    const T v = T(-tot);
+    T *Sv = (T *)pd.S;
+    Sv[36 * (size_t)pd.up_pos[u] + e] = v;
+    Sv[36 * (size_t)pd.up_tpos[u] + 6 * cc + r] = v;
+  }
 }
 
-// Camera rows, one workgroup each: wave w sums the w-th quarter of the row's
-// diagonal partials (rows of 54), the four quarter sums are added in order in
-// FP64, then finish_camera_row by thread 0.
+// Camera rows, one 1024-thread workgroup each: wave w sums the w-th of 16
+// consecutive segments of the row's diagonal partials (rows of 54) in FP64 and
+// the segment sums are added in order into row_tot; k_schur_finish then runs
+// finish_camera_row, one thread per camera (kept apart for its registers).
 template <class T>
-__global__ __launch_bounds__(256) void k_schur_rows(const ProbDev *__restrict__ probs,
-                                                    const Tile *__restrict__ tiles) {
+__global__ __launch_bounds__(1024) void k_schur_rows(const ProbDev *__restrict__ probs,
+                                                     const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
@@ -1171,26 +1182,41 @@ __global__ __launch_bounds__(256) void k_schur_rows(const ProbDev *__restrict__ 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int a = tl.idx;
   const int b0 = pd.blk_start[a], n = pd.blk_start[a + 1] - b0;
-  const int q = (n + 3) / 4, x0 = wv * q, x1 = min(n, x0 + q);
+  const int q = (n + 15) / 16, x0 = wv * q, x1 = min(n, x0 + q);
   const T *part = (const T *)pd.part_d + 54 * (size_t)b0;
-  __shared__ double s_t[4][54];
+  __shared__ double s_t[16][54];
   double t = 0.0;
   if (lane < 54)
-    for (int x = x0; x < x1; x += 16) {
-      T v[16];
+    for (int x = x0; x < x1; x += 8) {
+      T v[8];
 #pragma unroll
-      for (int h = 0; h < 16; ++h) v[h] = x + h < x1 ? part[54 * (size_t)(x + h) + lane] : T(0);
+      for (int h = 0; h < 8; ++h) v[h] = x + h < x1 ? part[54 * (size_t)(x + h) + lane] : T(0);
 #pragma unroll
-      for (int h = 0; h < 16; ++h) t += (double)v[h];
+      for (int h = 0; h < 8; ++h) t += (double)v[h];
     }
   if (lane < 54) s_t[wv][lane] = t;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot[54];
+  if (threadIdx.x < 54) {
+    double v = 0.0;
 #pragma unroll
-    for (int i = 0; i < 54; ++i) tot[i] = s_t[0][i] + s_t[1][i] + s_t[2][i] + s_t[3][i];
-    finish_camera_row<T>(pd, st, a, tot);
+    for (int w = 0; w < 16; ++w) v += s_t[w][threadIdx.x];
+    pd.row_tot[54 * (size_t)a + threadIdx.x] = v;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_schur_finish(const ProbDev *__restrict__ probs,
+                                                     const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int a = 64 * tl.idx + (int)threadIdx.x;
+  if (a >= pd.Cf) return;
+  double tot[54];
+#pragma unroll
+  for (int i = 0; i < 54; ++i) tot[i] = pd.row_tot[54 * (size_t)a + i];
+  finish_camera_row<T>(pd, st, a, tot);
 }
 
 // ------------------------------------------------------------------ PCG
@@ -2220,7 +2246,11 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   }
   if (bp.n_fin) {
     Timed t(tm, K_SCHUR_ROWS, s);
-    k_schur_rows<T><<<bp.n_fin, 256, 0, s>>>(bp.probs, bp.fin);
+    k_schur_rows<T><<<bp.n_fin, 1024, 0, s>>>(bp.probs, bp.fin);
+  }
+  if (bp.n_fsh) {
+    Timed t(tm, K_SCHUR_FINISH, s);
+    k_schur_finish<T><<<bp.n_fsh, 64, 0, s>>>(bp.probs, bp.fsh);
   }
   if (bp.n_pp) {
     Timed t(tm, K_POINT_PREP, s);

@@ -56,7 +56,7 @@ struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
-  size_t part_d, part_o;
+  size_t part_d, part_o, row_tot;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
   size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
@@ -91,7 +91,7 @@ struct DevProblem {
 struct Batch {
   std::vector<ProbDev> probs;
   std::vector<int> tags;
-  std::vector<Tile> tiles[10];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin
+  std::vector<Tile> tiles[11];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin, fsh
   std::vector<char> host;
   void *dev = nullptr;
   size_t cap = 0;
