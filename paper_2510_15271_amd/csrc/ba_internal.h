@@ -25,15 +25,17 @@ constexpr int kPoseThreads = 256;
 constexpr int kChPts = 256;
 constexpr int kChThreads = 1024;
 constexpr int kChSubItems = 32;  // items per chunk entry (one thread each)
-inline int chunk_obs_cap(int precision) { return precision == 0 ? 1024 : 1984; }
+inline int chunk_obs_cap(int precision) { return precision == 0 ? 1024 : precision == 1 ? 1984 : 1600; }
 inline int chunk_pts_cap(int precision) { return precision == 0 ? kChPts / 2 : kChPts; }
 inline int chunk_cam_cap(int precision) { return precision == 0 ? 128 : 256; }
-// LDS bytes of one chunk workgroup: per observation f[7], Q[6], Q g_p[2], e[2] in T
-// (as two rows of 8 and one value) and its observation index; per point V*^-1
-// (6 T); per camera R (9 T) and its index.
+// LDS bytes of one chunk workgroup: per observation two rows of 8 T (f[7], e[0];
+// Q[6], Q g_p[2]) and e[1] -- or, with 16-bit storage, the FP32 gradient
+// contribution (6 T) in place of e; per point V*^-1 (6 T); per camera R (9 T)
+// and its index.
 inline size_t chunk_lds_bytes(int precision) {
   const size_t T = precision == 0 ? 8 : 4;
-  return (size_t)chunk_obs_cap(precision) * (17 * T + 4) + (size_t)chunk_pts_cap(precision) * 6 * T +
+  const size_t per_obs = precision >= 2 ? 22 * T : 17 * T;
+  return (size_t)chunk_obs_cap(precision) * per_obs + (size_t)chunk_pts_cap(precision) * 6 * T +
          (size_t)chunk_cam_cap(precision) * (9 * T + 4);
 }
 

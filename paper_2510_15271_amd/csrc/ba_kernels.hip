@@ -879,10 +879,11 @@ __device__ inline void pair_accumulate(T acc[36], const T *fa_lds, const T *q_ld
 template <class T, class S>
 __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDev *__restrict__ probs,
                                                             const Tile *__restrict__ tiles) {
-  constexpr int cap = sizeof(T) == 8 ? 1024 : 1984;  // chunk_obs_cap / _pts_cap / _cam_cap
+  constexpr bool k16 = sizeof(S) == 2;
+  // chunk_obs_cap / chunk_pts_cap / chunk_cam_cap of the precision mode
+  constexpr int cap = sizeof(T) == 8 ? 1024 : k16 ? 1600 : 1984;
   constexpr int pcap = sizeof(T) == 8 ? kChPts / 2 : kChPts;
   constexpr int ccap = sizeof(T) == 8 ? 128 : 256;
-  constexpr bool k16 = sizeof(S) == 2;
   constexpr int nth = chunk_threads<T>();
   extern __shared__ __align__(16) double s_dyn[];
   // per record two rows of 8 (16-byte aligned, read with vector loads):
@@ -890,10 +891,9 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   T *s_vi = (T *)s_dyn;           // [pcap][6]
   T *s_fe = s_vi + 6 * pcap;      // [cap][8]
   T *s_qq = s_fe + 8 * cap;       // [cap][8]
-  T *s_e1 = s_qq + 8 * cap;       // [cap]: e[1]
-  T *s_R = s_e1 + cap;            // [ccap][9] rotations of the chunk's cameras
-  int *s_k = (int *)(s_R + 9 * ccap);  // [cap]
-  int *s_cam = s_k + cap;         // [ccap]
+  T *s_e1 = s_qq + 8 * cap;       // [cap] e[1]; 16-bit storage: [cap][6] FP32 gradient terms
+  T *s_R = s_e1 + (k16 ? 6 : 1) * cap;  // [ccap][9] rotations of the chunk's cameras
+  int *s_cam = (int *)(s_R + 9 * ccap);  // [ccap]
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
@@ -981,8 +981,30 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         qq[7] = q[3] * g0 + q[4] * g1 + q[5] * g2;
         store8(s_fe + 8 * l, fe);
         store8(s_qq + 8 * l, qq);
-        s_e1[l] = rec[h].e[1];
-        s_k[l] = kk[h];
+        if (k16) {
+          // 16-bit storage: this record's gradient term w J_c^T r from FP32 Jacobians
+          const int cm = cam[h];
+          const double *pose = poses + 12 * cm;
+          const T *K = (const T *)pd.K + 4 * cm;
+          const T *uv = (const T *)pd.obs_uv + 2 * (size_t)kk[h];
+          double xd, yd, zd;
+          transform(pose, pd.X[st->cur] + 3 * (size_t)j, xd, yd, zd);
+          const T xv = T(xd), yv = T(yd), zv = T(zd);
+          T r0, r1, gk[6];
+#pragma unroll
+          for (int r = 0; r < 6; ++r) gk[r] = T(0);
+          if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+            const T w = huber_w(r0 * r0 + r1 * r1, T(st->huber_delta));
+            T Jg[12], Jpg[6];
+            jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
+#pragma unroll
+            for (int r = 0; r < 6; ++r) gk[r] = w * (Jg[r] * r0 + Jg[6 + r] * r1);
+          }
+#pragma unroll
+          for (int r = 0; r < 6; ++r) s_e1[6 * l + r] = gk[r];
+        } else {
+          s_e1[l] = rec[h].e[1];
+        }
       }
     }
   }
@@ -1026,54 +1048,13 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
           for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
 #pragma unroll
         for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qq[6] + Jc1[r] * qq[7];
-        if (!k16) {
+        if (k16) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) acc[21 + r] += s_e1[6 * l + r];
+        } else {
           const T e0v = fe[7], e1v = s_e1[l];
 #pragma unroll
           for (int r = 0; r < 6; ++r) acc[21 + r] += Jc0[r] * e0v + Jc1[r] * e1v;
-        }
-      }
-      if (k16) {
-        // 16-bit storage: the gradient comes from FP32 Jacobians recomputed here,
-        // four observations at a time so that their loads overlap
-        const T *K = (const T *)pd.K + 4 * cam;
-        const T delta = T(st->huber_delta);
-        const double *pose = poses + 12 * cam;
-        const double *Xs = pd.X[st->cur];
-        const T *uvs = (const T *)pd.obs_uv;
-#pragma unroll
-        for (int h0 = 0; h0 < kChSubItems; h0 += 4) {
-          if (h0 >= n) break;
-          int kk[4], jj[4];
-#pragma unroll
-          for (int h = 0; h < 4; ++h) kk[h] = h0 + h < n ? s_k[items[h0 + h]] : -1;
-#pragma unroll
-          for (int h = 0; h < 4; ++h) jj[h] = kk[h] >= 0 ? pd.obs_pt[kk[h]] : 0;
-          double Xv[4][3];
-          T uv[4][2];
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const int ko = kk[h] >= 0 ? kk[h] : 0;
-#pragma unroll
-            for (int m = 0; m < 3; ++m) Xv[h][m] = Xs[3 * (size_t)jj[h] + m];
-            uv[h][0] = uvs[2 * (size_t)ko];
-            uv[h][1] = uvs[2 * (size_t)ko + 1];
-          }
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            if (kk[h] < 0) continue;
-            double xd, yd, zd;
-            transform(pose, Xv[h], xd, yd, zd);
-            const T xv = T(xd), yv = T(yd), zv = T(zd);
-            T r0, r1;
-            if (residual<T>(K, xv, yv, zv, uv[h][0], uv[h][1], r0, r1)) {
-              const T sq = r0 * r0 + r1 * r1;
-              const T w = huber_w(sq, delta);
-              T Jg[12], Jpg[6];
-              jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
-#pragma unroll
-              for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
-            }
-          }
         }
       }
       // partial layout: U (21), Y W^T (21), g_c (6), Y g_p (6)
