@@ -904,6 +904,8 @@ int Batch::upload(hipStream_t s) {
     *dst[i] = (const Tile *)(b + offs[i]);
     *cnt[i] = (int32_t)tiles[i].size();
   }
+  plan.n_probs = (int32_t)probs.size();
+  if (probs.size() == 1) plan.single = probs[0];
   return BA_OK;
 }
 

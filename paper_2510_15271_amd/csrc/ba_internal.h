@@ -14,7 +14,7 @@
 namespace bax {
 
 constexpr int kPtTile = 256;     // points per point-major tile (one workgroup)
-constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile
+constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile (one per thread)
 constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile (one wave each)
 constexpr int kCamTile = 256;    // cameras per camera-update tile
 constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
@@ -157,6 +157,8 @@ struct BatchPlan {
   const ProbDev *probs;
   const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh;
   int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh;
+  int32_t n_probs;
+  ProbDev single;  // host copy of the descriptor when n_probs == 1 (passed by value to short kernels)
 };
 
 // One localization request on the device.

@@ -189,6 +189,20 @@ __device__ inline T block_sum256(T v, T *scratch4) {
   return s;
 }
 
+// Sum of one value per thread over a block of NW wavefronts, fixed order.
+template <int NW, class T>
+__device__ inline T block_sum_w(T v, T *scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  T s = scratch[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
 // Sum of n doubles by a 256-thread block in a fixed order (result in every thread).
 __device__ inline double block_sum_array(const double *a, int n, double *scratch4) {
   double v = 0.0;
@@ -386,7 +400,7 @@ __device__ inline bool lm_active(const LMState *st) { return st->iter < st->max_
 // point's run inside the chunk, reading the chunk's contributions from LDS in
 // order, so the result does not depend on scheduling.
 template <class T, class S>
-__global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ probs,
+__global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restrict__ probs,
                                                    const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
@@ -401,8 +415,8 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
   __shared__ T s_acc[kPtTile][9];
   __shared__ T s_c[kObsChunk][9];
   __shared__ int s_loc[kObsChunk];
-  __shared__ double s_red[4];
-  for (int i = threadIdx.x; i < kPtTile * 9; i += 256) (&s_acc[0][0])[i] = T(0);
+  __shared__ double s_red[kObsChunk / 64];
+  for (int i = threadIdx.x; i < kPtTile * 9; i += kObsChunk) (&s_acc[0][0])[i] = T(0);
 
   const T *Kall = (const T *)pd.K;
   const T *uv = (const T *)pd.obs_uv;
@@ -489,7 +503,7 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
   T *V = (T *)pd.V;
   T *gp = (T *)pd.gp;
   T *Dp = (T *)pd.Dp;
-  for (int jl = threadIdx.x; jl < j1 - j0; jl += 256) {
+  for (int jl = threadIdx.x; jl < j1 - j0; jl += kObsChunk) {
     const int j = j0 + jl;
 #pragma unroll
     for (int i = 0; i < 6; ++i) V[6 * j + i] = s_acc[jl][i];
@@ -499,8 +513,8 @@ __global__ __launch_bounds__(256) void k_linearize(const ProbDev *__restrict__ p
 #pragma unroll
     for (int i = 0; i < 3; ++i) Dp[3 * j + i] = T(fmin(fmax((double)d[i], kDMin), kDMax));
   }
-  const double tot = block_sum256(cost, s_red);
-  const double nm = block_sum256((double)masked, s_red);
+  const double tot = block_sum_w<kObsChunk / 64>(cost, s_red);
+  const double nm = block_sum_w<kObsChunk / 64>((double)masked, s_red);
   if (threadIdx.x == 0) {
     pd.part_lin_cost[tl.idx] = tot;
     pd.part_masked[tl.idx] = (int32_t)nm;
@@ -1521,16 +1535,14 @@ __device__ inline void cg_column(int m, T tb, T ta, const T (&w0)[6], const T (&
 }
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_cg_step(const ProbDev *__restrict__ probs,
-                                                  const Tile *__restrict__ tiles, int it) {
+__device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, int it) {
   extern __shared__ double s_dyn[];
   T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
   __shared__ double s_red[48];
   __shared__ T s_w[kPcgRows][4][6];
   __shared__ T s_ro[kPcgRows][6], s_uo[kPcgRows][6];
   __shared__ int s_flag[1];
-  const Tile tl = tiles[blockIdx.x];
-  const ProbDev &pd = probs[tl.prob];
+  const Tile tl{0, tile};
   const LMState *st = pd.st;
   const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
@@ -1754,6 +1766,21 @@ __global__ __launch_bounds__(1024) void k_cg_step(const ProbDev *__restrict__ pr
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(1024) void k_cg_step(const ProbDev *__restrict__ probs,
+                                                  const Tile *__restrict__ tiles, int it) {
+  const Tile tl = tiles[blockIdx.x];
+  cg_step_body<T>(probs[tl.prob], tl.idx, it);
+}
+
+// The same step for a batch of one problem, its descriptor passed by value: the
+// launch saves the two dependent loads (tile table, descriptor) that precede
+// every other load of the step.
+template <class T>
+__global__ __launch_bounds__(1024) void k_cg_step1(const ProbDev pd, int it) {
+  cg_step_body<T>(pd, blockIdx.x, it);
+}
+
 // ------------------------------------------------------------------ camera update
 template <class T>
 __global__ __launch_bounds__(256) void k_cam_update(const ProbDev *__restrict__ probs,
@@ -1797,7 +1824,7 @@ __global__ __launch_bounds__(256) void k_cam_update(const ProbDev *__restrict__ 
 
 // ------------------------------------------------------------------ point back-substitution + trial cost
 template <class T, class S>
-__global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__ probs,
+__global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__restrict__ probs,
                                                      const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
@@ -1813,8 +1840,8 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
   __shared__ T s_c[kObsChunk][3];
   __shared__ int s_loc[kObsChunk];
   __shared__ double s_X[kPtTile][3];
-  __shared__ double s_red[4];
-  for (int i = threadIdx.x; i < kPtTile * 3; i += 256) (&s_acc[0][0])[i] = T(0);
+  __shared__ double s_red[kObsChunk / 64];
+  for (int i = threadIdx.x; i < kPtTile * 3; i += kObsChunk) (&s_acc[0][0])[i] = T(0);
   const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
   const T *x = (const T *)pd.x;
   __syncthreads();
@@ -1864,7 +1891,7 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
   const T *gp = (const T *)pd.gp;
   const T *Dp = (const T *)pd.Dp;
   double dl = 0.0;
-  for (int jl = threadIdx.x; jl < j1 - j0; jl += 256) {
+  for (int jl = threadIdx.x; jl < j1 - j0; jl += kObsChunk) {
     const int j = j0 + jl;
     const T *vi = Vinv + 6 * (size_t)j;
     const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
@@ -1890,7 +1917,7 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
   const double *poses = pd.pose[1 - cur];
   double cost = 0.0;
   int masked = 0;
-  for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+  for (int k = k0 + threadIdx.x; k < k1; k += kObsChunk) {
     const int jl = pd.obs_pt[k] - j0;
     const int cam = pd.obs_cam[k];
     double xd, yd, zd;
@@ -1901,9 +1928,9 @@ __global__ __launch_bounds__(256) void k_point_trial(const ProbDev *__restrict__
     else
       ++masked;
   }
-  const double tc = block_sum256(cost, s_red);
-  const double td = block_sum256(dl, s_red);
-  const double tm = block_sum256((double)masked, s_red);
+  const double tc = block_sum_w<kObsChunk / 64>(cost, s_red);
+  const double td = block_sum_w<kObsChunk / 64>(dl, s_red);
+  const double tm = block_sum_w<kObsChunk / 64>((double)masked, s_red);
   if (threadIdx.x == 0) {
     pd.part_trial_cost[tl.idx] = tc;
     pd.part_dl_pt[tl.idx] = td;
@@ -2169,6 +2196,10 @@ int prepare_kernels() {
     if (hipFuncSetAttribute((const void *)k_cg_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)use) != hipSuccess ||
         hipFuncSetAttribute((const void *)k_cg_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)use) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_cg_step1<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)use) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_cg_step1<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)use) != hipSuccess) {
       (void)hipGetLastError();
       use = 48 * 1024;
@@ -2214,7 +2245,7 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   if (before) {
   if (bp.n_pt) {
     Timed t(tm, K_LINEARIZE, s);
-    k_linearize<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+    k_linearize<T, S><<<bp.n_pt, kObsChunk, 0, s>>>(bp.probs, bp.pt);
   }
   if (bp.n_ch) {
     Timed t(tm, K_SCHUR_CHUNK, s);
@@ -2254,8 +2285,12 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     // one event pair around the whole run: per-launch events would add their own
     // overhead to launches this short
     Timed t(tm, K_PCG_CG, s, pcg_max);
-    for (int it = 0; it < pcg_max; ++it)
-      k_cg_step<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.probs, bp.pcg, it);
+    if (bp.n_probs == 1)
+      for (int it = 0; it < pcg_max; ++it)
+        k_cg_step1<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.single, it);
+    else
+      for (int it = 0; it < pcg_max; ++it)
+        k_cg_step<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.probs, bp.pcg, it);
   } else if (pcg) {
     for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
       {
@@ -2275,7 +2310,7 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   }
   if (bp.n_pt) {
     Timed t(tm, K_POINT_TRIAL, s);
-    k_point_trial<T, S><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+    k_point_trial<T, S><<<bp.n_pt, kObsChunk, 0, s>>>(bp.probs, bp.pt);
   }
   if (bp.n_ctl) {
     Timed t(tm, K_LM_CONTROL, s);
