@@ -13,6 +13,11 @@ What it computes (paper: Sec. 4.3, Iterative Triangulation and Mapping):
 * the robust objective of Sec. 4.3 restricted to its reprojection term,
   C = 1/2 sum_k rho(||r_k||^2) with rho Huber on the squared norm, or rho(s) = s;
 * designated-fixed camera poses (Sec. 4.3), removed from the unknowns;
+* optionally the prior terms of the Sec. 4.3 objective: the absolute pose
+  constraint e_a = ||T_i - T_i,init||^2 (Eq. abs) and the sequential constraint
+  e_c = ||T_i T_{i+k}^-1 - T_i,init T_{i+k,init}^-1||^2 (Eq. seq), read as squared
+  Frobenius norms of the 3x4 upper parts, weighted by lambda_a and lambda_c and
+  entering C with the same factor 1/2 as the reprojection term;
 * Levenberg-Marquardt with Marquardt diagonal scaling and Nielsen's damping
   schedule (Madsen, Nielsen, Tingleff 2004, Sec. 3.2), left SE(3) increments;
 * three solvers of the damped normal equations (H + lambda D) delta = -g:
@@ -185,13 +190,26 @@ class Problem:
     uv: np.ndarray         # (N, 2)
     fixed: np.ndarray      # (C,) bool
     delta: float           # Huber delta; <= 0 plain least squares
+    # prior terms (Sec. 4.3 objective); weights 0 disable them
+    prior_abs: float = 0.0        # lambda_a
+    prior_seq: float = 0.0        # lambda_c
+    seq_k: int = 1                # sequential pairs (i, i + k), k = 1..seq_k, in camera order
+    R0: np.ndarray | None = None  # T_init: the initial poses
+    t0: np.ndarray | None = None
+
+    def __post_init__(self):
+        if self.R0 is None:
+            self.R0 = np.array(self.R, np.float64)
+        if self.t0 is None:
+            self.t0 = np.array(self.t, np.float64)
 
     @classmethod
-    def from_scene(cls, s) -> "Problem":
+    def from_scene(cls, s, prior_abs: float = 0.0, prior_seq: float = 0.0, seq_k: int = 1) -> "Problem":
         return cls(K=np.asarray(s.K, np.float64), R=quat_to_rot(s.q0), t=np.array(s.t0, np.float64),
                    X=np.array(s.X0, np.float64), cam=np.asarray(s.obs_cam, np.int64),
                    pt=np.asarray(s.obs_pt, np.int64), uv=np.asarray(s.obs_uv, np.float64),
-                   fixed=np.asarray(s.cam_fixed).astype(bool), delta=float(s.huber_delta))
+                   fixed=np.asarray(s.cam_fixed).astype(bool), delta=float(s.huber_delta),
+                   prior_abs=float(prior_abs), prior_seq=float(prior_seq), seq_k=int(seq_k))
 
     @property
     def n_cams(self):
@@ -219,7 +237,7 @@ def residuals(p: Problem, R=None, t=None, X=None):
 
 
 def cost(p: Problem, R=None, t=None, X=None) -> float:
-    """C = 1/2 sum_k rho(||r_k||^2) over valid observations."""
+    """C = 1/2 sum_k rho(||r_k||^2) over valid observations, plus the prior terms."""
     return cost_and_masked(p, R, t, X)[0]
 
 
@@ -227,7 +245,120 @@ def cost_and_masked(p: Problem, R=None, t=None, X=None):
     """(C, number of masked observations) at a state."""
     r, valid, _ = residuals(p, R, t, X)
     s = np.sum(r * r, axis=1)
-    return 0.5 * float(np.sum(huber_rho(s, p.delta)[valid])), int((~valid).sum())
+    C = 0.5 * float(np.sum(huber_rho(s, p.delta)[valid]))
+    if p.prior_abs > 0 or p.prior_seq > 0:
+        C += prior_cost(p, R, t)
+    return C, int((~valid).sum())
+
+
+# ----------------------------------------------------------------------------- prior terms
+
+def _pose_rows(R: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """The 3x4 upper part [R | t] of a pose, flattened row-major with R first:
+    (R00 R01 R02 R10 ... R22, t0 t1 t2)."""
+    return np.concatenate([R.reshape(-1), t])
+
+
+def prior_pairs(p: Problem):
+    """Sequential constraint pairs (i, i + k), k = 1..seq_k, in camera order."""
+    C = p.n_cams
+    return [(i, i + k) for i in range(C) for k in range(1, p.seq_k + 1) if i + k < C]
+
+
+def prior_residuals(p: Problem, R=None, t=None):
+    """Residual 12-vectors of the prior terms: r_a,i = [R_i - R0_i | t_i - t0_i] for every
+    camera (Eq. abs), and r_c,(i,j) = A - A0 with A = T_i T_j^-1 = [R_i R_j^T | t_i - R_i R_j^T t_j]
+    and A0 the same from the initial poses, for every sequential pair (Eq. seq)."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    ra = np.stack([_pose_rows(R[i], t[i]) - _pose_rows(p.R0[i], p.t0[i]) for i in range(p.n_cams)])
+    rc = []
+    for i, j in prior_pairs(p):
+        RA = R[i] @ R[j].T
+        RA0 = p.R0[i] @ p.R0[j].T
+        rc.append(_pose_rows(RA, t[i] - RA @ t[j]) - _pose_rows(RA0, p.t0[i] - RA0 @ p.t0[j]))
+    return ra, np.array(rc).reshape(-1, 12)
+
+
+def prior_cost(p: Problem, R=None, t=None) -> float:
+    """1/2 (lambda_a sum_i ||r_a,i||^2 + lambda_c sum_pairs ||r_c||^2)."""
+    ra, rc = prior_residuals(p, R, t)
+    return 0.5 * (p.prior_abs * float(np.sum(ra * ra)) + p.prior_seq * float(np.sum(rc * rc)))
+
+
+def _rows_of_left_increment(R: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """d[R | t]/d xi for T <- Exp(xi) T, xi = (rho, phi): the rotation rows change by
+    [e_m]x R for phi_m, the translation rows by rho and by [phi]x t = -[t]x phi.
+    Returns the 12 x 6 Jacobian in the _pose_rows order."""
+    J = np.zeros((12, 6))
+    for m in range(3):
+        e = np.zeros(3)
+        e[m] = 1.0
+        J[:9, 3 + m] = (hat(e) @ R).reshape(-1)
+    J[9:, :3] = np.eye(3)
+    J[9:, 3:] = -hat(t)
+    return J
+
+
+def prior_jacobians(p: Problem, R=None, t=None):
+    """Jacobians of the prior residuals for left increments of the poses.
+    Absolute term of camera i: _rows_of_left_increment(R_i, t_i).  Sequential term of
+    (i, j): A <- Exp(xi_i) A Exp(-xi_j), so d/dxi_i = _rows_of_left_increment(R_A, t_A)
+    and d/dxi_j has rotation rows -R_A [e_m]x (phi_m) and translation rows -R_A (rho).
+    Returns (Ja (C, 12, 6), Jci (n, 12, 6), Jcj (n, 12, 6))."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    Ja = np.stack([_rows_of_left_increment(R[i], t[i]) for i in range(p.n_cams)])
+    Jci, Jcj = [], []
+    for i, j in prior_pairs(p):
+        RA = R[i] @ R[j].T
+        tA = t[i] - RA @ t[j]
+        Jci.append(_rows_of_left_increment(RA, tA))
+        Jj = np.zeros((12, 6))
+        for m in range(3):
+            e = np.zeros(3)
+            e[m] = 1.0
+            Jj[:9, 3 + m] = (-RA @ hat(e)).reshape(-1)
+        Jj[9:, :3] = -RA
+        Jcj.append(Jj)
+    return Ja, np.array(Jci).reshape(-1, 12, 6), np.array(Jcj).reshape(-1, 12, 6)
+
+
+def prior_system(p: Problem, n: int):
+    """Rows of the weighted prior residuals over the unknowns [free camera increments |
+    point increments] (n columns): sqrt(lambda) J and sqrt(lambda) r, so that they add
+    J^T J to H and J^T r to g.  Fixed cameras contribute no columns."""
+    fidx, _ = _free_index(p.fixed)
+    ra, rc = prior_residuals(p)
+    Ja, Jci, Jcj = prior_jacobians(p)
+    rows, cols, vals, rhs = [], [], [], []
+    row = 0
+    sa, sc = math.sqrt(p.prior_abs), math.sqrt(p.prior_seq)
+    if p.prior_abs > 0:
+        for i in range(p.n_cams):
+            if fidx[i] >= 0:
+                for q in range(12):
+                    for m in range(6):
+                        rows.append(row + q)
+                        cols.append(6 * fidx[i] + m)
+                        vals.append(sa * Ja[i, q, m])
+                rhs.append(sa * ra[i])
+                row += 12
+    if p.prior_seq > 0:
+        for x, (i, j) in enumerate(prior_pairs(p)):
+            if fidx[i] < 0 and fidx[j] < 0:
+                continue
+            for cam, Jx in ((i, Jci[x]), (j, Jcj[x])):
+                if fidx[cam] >= 0:
+                    for q in range(12):
+                        for m in range(6):
+                            rows.append(row + q)
+                            cols.append(6 * fidx[cam] + m)
+                            vals.append(sc * Jx[q, m])
+            rhs.append(sc * rc[x])
+            row += 12
+    Jp = sp.csr_matrix((np.array(vals), (np.array(rows, np.int64), np.array(cols, np.int64))), shape=(row, n))
+    return Jp, (np.concatenate(rhs) if rhs else np.zeros(0))
 
 
 def rms(p: Problem, R=None, t=None, X=None, inlier_px: float | None = None) -> float:
@@ -320,6 +451,10 @@ def normal_equations(p: Problem):
     Wd = sp.diags(np.repeat(w, 2))
     H = (J.T @ Wd @ J).tocsr()
     g = J.T @ (np.repeat(w, 2) * r.reshape(-1))
+    if p.prior_abs > 0 or p.prior_seq > 0:
+        Jp, rp = prior_system(p, n)
+        H = (H + Jp.T @ Jp).tocsr()
+        g = g + Jp.T @ rp
     return H, np.asarray(g).ravel(), J, w, r
 
 

@@ -331,3 +331,114 @@ def test_pose_only_matches_scipy_on_inliers():
         c = -R.T @ t
         c_ref = -R_ref.T @ ref.x[3:]
         assert np.linalg.norm(c - c_ref) <= 1e-8  # both at the same minimum; noise-level error is ~1e-3 m
+
+
+# ----------------------------------------------------------------------------- prior terms
+
+def _perturbed(p, cam, xi):
+    """Poses with camera `cam` moved by the left increment Exp(xi)."""
+    R, t = p.R.copy(), p.t.copy()
+    dR, dt = O.se3_exp(xi)
+    R[cam] = dR @ p.R[cam]
+    t[cam] = dR @ p.t[cam] + dt
+    return R, t
+
+
+def _drifted_problem(seed=31, **kw):
+    """A drive whose poses have moved away from their initial values (the prior
+    anchors), so that every prior residual is nonzero."""
+    s = make_small_drive(8, 200, seed=seed)
+    p = O.Problem.from_scene(s, **kw)
+    rng = np.random.default_rng(seed)
+    for c in range(p.n_cams):
+        p.R[c], p.t[c] = _perturbed(p, c, rng.normal(0, 0.02, 6))[0][c], _perturbed(p, c, rng.normal(0, 0.02, 6))[1][c]
+    return p
+
+
+def test_prior_jacobians_match_central_differences():
+    """Both prior terms against central differences along Exp(+-h e_m) applied on
+    the left of each camera they involve."""
+    p = _drifted_problem(prior_abs=1.0, prior_seq=1.0, seq_k=2)
+    Ja, Jci, Jcj = O.prior_jacobians(p)
+    pairs = O.prior_pairs(p)
+    h = 1e-6
+    for cam in range(p.n_cams):
+        for m in range(6):
+            e = np.zeros(6)
+            e[m] = h
+            ra_p, rc_p = O.prior_residuals(p, *_perturbed(p, cam, e))
+            ra_m, rc_m = O.prior_residuals(p, *_perturbed(p, cam, -e))
+            fd_a = (ra_p - ra_m) / (2 * h)
+            assert np.max(np.abs(fd_a[cam] - Ja[cam, :, m])) < 1e-8, (cam, m)
+            fd_c = (rc_p - rc_m) / (2 * h)
+            for x, (i, j) in enumerate(pairs):
+                ref = Jci[x, :, m] if cam == i else Jcj[x, :, m] if cam == j else np.zeros(12)
+                assert np.max(np.abs(fd_c[x] - ref)) < 1e-8, (cam, m, i, j)
+
+
+def test_prior_residuals_vanish_at_the_initial_poses():
+    s = make_small_drive(8, 200, seed=32)
+    p = O.Problem.from_scene(s, prior_abs=3.0, prior_seq=5.0, seq_k=3)
+    ra, rc = O.prior_residuals(p)
+    assert np.all(ra == 0) and np.all(rc == 0)
+    assert O.prior_cost(p) == 0.0
+    assert O.cost(p) == O.cost(O.Problem.from_scene(s))
+
+
+def test_sequential_prior_is_invariant_to_a_change_of_world_frame():
+    """T_i T_j^-1 is unchanged when every pose is right-multiplied by the same
+    rigid transform G (a change of world frame), so e_c is too; e_a is not."""
+    p = _drifted_problem(prior_abs=1.0, prior_seq=1.0, seq_k=2)
+    G_R, G_t = O.se3_exp(np.array([0.3, -0.2, 0.5, 0.1, 0.2, -0.3]))
+    # T G: R' = R G_R, t' = R G_t + t
+    R2 = p.R @ G_R
+    t2 = np.einsum("nij,j->ni", p.R, G_t) + p.t
+    ra1, rc1 = O.prior_residuals(p)
+    ra2, rc2 = O.prior_residuals(p, R2, t2)
+    assert np.max(np.abs(rc1 - rc2)) < 1e-12
+    assert np.max(np.abs(ra1 - ra2)) > 1e-3
+
+
+def test_prior_lm_minimum_matches_scipy_least_squares():
+    """Reprojection plus both priors (camera 0 fixed, the rest free): LM run to
+    convergence reaches the minimum of SciPy least_squares on the stacked residual
+    [r_k; sqrt(lambda_a) r_a; sqrt(lambda_c) r_c]."""
+    s = make_arc_scene(5, 60, seed=23, sigma=0.5)
+    p = O.Problem.from_scene(s, prior_abs=50.0, prior_seq=200.0, seq_k=2)
+    unpack, x0 = _ls_residual_fn(p)
+
+    def fun(x):
+        R, t, X = unpack(x)
+        r, _, _ = O.residuals(p, R, t, X)
+        ra, rc = O.prior_residuals(p, R, t)
+        return np.concatenate([r.ravel(), math.sqrt(p.prior_abs) * ra.ravel(), math.sqrt(p.prior_seq) * rc.ravel()])
+
+    ref = scipy.optimize.least_squares(fun, x0, method="trf", xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    c_ref = 0.5 * float(ref.fun @ ref.fun)
+    res = O.lm_dense(p, O.LMOptions(max_iters=60))
+    assert O.prior_cost(p, res.R, res.t) > 0
+    assert abs(res.iter_cost[-1] - c_ref) <= 1e-8 * c_ref
+    res_s = O.lm_schur(p, O.LMOptions(max_iters=60, solve="exact"))
+    assert abs(res_s.iter_cost[-1] - c_ref) <= 1e-8 * c_ref
+
+
+def test_strong_absolute_prior_reproduces_hard_fixed_poses():
+    """Sec. 4.3 realises fixed poses through the absolute constraint: as lambda_a
+    grows the free cameras approach their initial poses and the optimum approaches
+    that of the problem with every camera held fixed (points only).  To first order
+    the displacement is H^-1 g / lambda_a and the cost gain over the fixed problem
+    g^T g / (2 lambda_a): both shrink 100-fold from lambda_a = 1e10 to 1e12."""
+    s = make_arc_scene(4, 50, seed=24, sigma=0.5)
+    q = O.Problem.from_scene(s)
+    q.fixed = np.ones(q.n_cams, bool)
+    c_fixed = O.lm_dense(q, O.LMOptions(max_iters=40)).iter_cost[-1]
+    moves, gains = [], []
+    for lam in (1e10, 1e12):
+        p = O.Problem.from_scene(s, prior_abs=lam)
+        res = O.lm_dense(p, O.LMOptions(max_iters=40))
+        moves.append(np.max(np.abs(res.t - p.t0)))
+        gains.append(c_fixed - res.iter_cost[-1])
+    assert moves[0] < 1e-5 and gains[0] > 0 and gains[1] > 0
+    assert 0.009 < moves[1] / moves[0] < 0.011
+    assert 0.009 < gains[1] / gains[0] < 0.011
+    assert gains[1] < 1e-5 * c_fixed
