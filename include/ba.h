@@ -73,6 +73,17 @@ typedef struct {
   double huber_delta;     /* <= 0: plain least squares; > 0: Huber threshold in pixels    */
   int32_t precision;      /* BA_PREC_*                                                    */
   int32_t flags;          /* BA_FLAG_* bits, 0 for the defaults                           */
+  /* Prior terms of the objective (paper Sec. 4.3: absolute pose constraint, Eq. abs;
+     sequential constraint, Eq. seq), read as squared Frobenius norms of 3x4 pose
+     differences and added to C as 1/2 weight * e:
+       e_a(i)   = ||[R_i | t_i] - [R_i0 | t_i0]||^2 for every camera,
+       e_c(i,j) = ||A_ij - A_ij0||^2, A_ij = T_i T_j^-1, for j = i + k, k = 1..prior_seq_k
+     in the caller's camera order; T_0 are the poses given to ba_create.  Weights 0
+     (the defaults) disable a term.  Not robustified. */
+  double prior_abs;       /* lambda_a >= 0                                                  */
+  double prior_seq;       /* lambda_c >= 0                                                  */
+  int32_t prior_seq_k;    /* 1..64 when prior_seq > 0 (default 1: adjacent frames)          */
+  int32_t reserved;       /* 0                                                              */
 } ba_options;
 
 /* ba_options.flags bits.

@@ -36,7 +36,9 @@ class Pose(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("pcg_max_iters", C.c_int32),
                 ("pcg_rel_tol", C.c_double), ("lambda0", C.c_double),
-                ("huber_delta", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32)]
+                ("huber_delta", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32),
+                ("prior_abs", C.c_double), ("prior_seq", C.c_double), ("prior_seq_k", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -127,7 +129,7 @@ FLAG_PAIR_LISTS = 4
 
 
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,
-            precision="f32", flags=0) -> Options:
+            precision="f32", flags=0, prior_abs=0.0, prior_seq=0.0, prior_seq_k=1) -> Options:
     o = Options()
     lib().ba_default_options(C.byref(o))
     o.max_iters = max_iters
@@ -137,6 +139,9 @@ def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, hube
     o.huber_delta = huber_delta
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.flags = int(flags)
+    o.prior_abs = float(prior_abs)
+    o.prior_seq = float(prior_seq)
+    o.prior_seq_k = int(prior_seq_k)
     return o
 
 

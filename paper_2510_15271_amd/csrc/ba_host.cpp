@@ -117,6 +117,14 @@ int check_options(const ba_options *o, bool pose_only) {
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
   if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
+  if (!pose_only) {
+    if (!(o->prior_abs >= 0.0) || !std::isfinite(o->prior_abs))
+      return fail(BA_EINVAL, "prior_abs must be finite and >= 0");
+    if (!(o->prior_seq >= 0.0) || !std::isfinite(o->prior_seq))
+      return fail(BA_EINVAL, "prior_seq must be finite and >= 0");
+    if (o->prior_seq > 0.0 && (o->prior_seq_k < 1 || o->prior_seq_k > 64))
+      return fail(BA_EINVAL, "prior_seq_k must be in [1, 64]");
+  }
   return BA_OK;
 }
 
@@ -408,6 +416,17 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
     sy.obs_rpos = cpos;
   }
 
+  // prior terms: sequential pairs (i, i + k) in the caller's camera order with at least
+  // one free camera (pairs of two fixed cameras are constant)
+  sy.prior_abs = opt->prior_abs;
+  sy.prior_seq = opt->prior_seq;
+  sy.pp_cam.clear();
+  if (opt->prior_seq > 0.0)
+    for (int i = 0; i < C; ++i)
+      for (int k = 1; k <= opt->prior_seq_k && i + k < C; ++k)
+        if (sy.free_idx[i] >= 0 || sy.free_idx[i + k] >= 0) sy.pp_cam.push_back(int2{i, i + k});
+  std::vector<uint8_t> pmark(Cf, 0);
+
   // upper blocks of S row by row (and their observation-pair lists in the pair-list form)
   std::vector<int32_t> up_rowptr(Cf + 1, 0), up_col;
   std::vector<int32_t> rowcnt(Cf, 0), slot(Cf, -1);
@@ -426,6 +445,16 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
         if (rowcnt[b]++ == 0) touched.push_back(b);
       }
     }
+    // a sequential prior couples camera a with later free cameras: those blocks exist
+    // even where no point is seen by both
+    if (opt->prior_seq > 0.0)
+      for (int k = 1; k <= opt->prior_seq_k && sy.free_cam[a] + k < C; ++k) {
+        const int b = sy.free_idx[sy.free_cam[a] + k];
+        if (b >= 0 && rowcnt[b] == 0 && !pmark[b]) {
+          pmark[b] = 1;
+          touched.push_back(b);
+        }
+      }
     std::sort(touched.begin(), touched.end());
     const int base_blk = (int)up_col.size();
     int64_t pbase = sy.n_pairs;
@@ -456,10 +485,35 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
     for (int b : touched) {
       rowcnt[b] = 0;
       slot[b] = -1;
+      pmark[b] = 0;
     }
     up_rowptr[a + 1] = (int32_t)up_col.size();
   }
   sy.n_up = (int32_t)up_col.size();
+  // prior pairs: upper block of each pair of free cameras, pairs of each free camera
+  sy.pp_up.assign(sy.pp_cam.size(), -1);
+  sy.cam_pp_start.assign(Cf + 1, 0);
+  for (size_t p = 0; p < sy.pp_cam.size(); ++p) {
+    const int a = sy.free_idx[sy.pp_cam[p].x], b = sy.free_idx[sy.pp_cam[p].y];
+    if (a >= 0) sy.cam_pp_start[a + 1]++;
+    if (b >= 0) sy.cam_pp_start[b + 1]++;
+    if (a >= 0 && b >= 0) {
+      const auto beg = up_col.begin() + up_rowptr[a], end = up_col.begin() + up_rowptr[a + 1];
+      const auto pos = std::lower_bound(beg, end, b);
+      if (pos == end || *pos != b) return fail(BA_EDEVICE, "internal: prior block (%d, %d) missing", a, b);
+      sy.pp_up[p] = (int32_t)(pos - up_col.begin());
+    }
+  }
+  for (int a = 0; a < Cf; ++a) sy.cam_pp_start[a + 1] += sy.cam_pp_start[a];
+  sy.cam_pp.resize(sy.cam_pp_start[Cf]);
+  {
+    std::vector<int32_t> f(sy.cam_pp_start.begin(), sy.cam_pp_start.end() - 1);
+    for (size_t p = 0; p < sy.pp_cam.size(); ++p) {
+      const int a = sy.free_idx[sy.pp_cam[p].x], b = sy.free_idx[sy.pp_cam[p].y];
+      if (a >= 0) sy.cam_pp[f[a]++] = (int32_t)p;
+      if (b >= 0) sy.cam_pp[f[b]++] = (int32_t)p;
+    }
+  }
   if (sy.chunked) {
     sy.cam_obs.clear();
     sy.cam_obs.shrink_to_fit();
@@ -564,6 +618,13 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_d = L.take((size_t)sy.n_dent * 54 * T + 16);
   o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
   o.row_tot = L.take(sy.chunked ? Cf * 54 * 8 : 16);
+  o.pp_cam = L.take(sy.pp_cam.size() * sizeof(int2) + 8);
+  o.pp_up = L.take(sy.pp_up.size() * 4 + 4);
+  o.cam_pp_start = L.take(sy.cam_pp_start.size() * 4 + 4);
+  o.cam_pp = L.take(sy.cam_pp.size() * 4 + 4);
+  const bool prior_on = sy.prior_abs > 0.0 || !sy.pp_cam.empty();
+  o.prior_diag = L.take(prior_on ? Cf * 27 * 8 : 16);
+  o.prior_off = L.take(sy.pp_cam.size() * 36 * 8 + 16);
   o.up_pos = L.take(sy.n_up * 4 + 4);
   o.up_tpos = L.take(sy.n_up * 4 + 4);
   o.diag_pos = L.take(Cf * 4);
@@ -680,6 +741,18 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_d = ptr(off.part_d);
   pd.part_o = ptr(off.part_o);
   pd.row_tot = (double *)ptr(off.row_tot);
+  pd.prior_abs = sy.prior_abs;
+  pd.prior_seq = sy.prior_seq;
+  pd.n_pp = (int32_t)sy.pp_cam.size();
+  pd.prior_on = (sy.prior_abs > 0.0 || pd.n_pp > 0) ? 1 : 0;
+  pd.n_pri_tiles = pd.prior_on ? (std::max(Cf, pd.n_pp) + 255) / 256 : 0;
+  pd.pose0 = (const double *)ptr(off.pose_init);
+  pd.pp_cam = (const int2 *)ptr(off.pp_cam);
+  pd.pp_up = (const int32_t *)ptr(off.pp_up);
+  pd.cam_pp_start = (const int32_t *)ptr(off.cam_pp_start);
+  pd.cam_pp = (const int32_t *)ptr(off.cam_pp);
+  pd.prior_diag = (double *)ptr(off.prior_diag);
+  pd.prior_off = (double *)ptr(off.prior_off);
   pd.up_pos = (const int32_t *)ptr(off.up_pos);
   pd.up_tpos = (const int32_t *)ptr(off.up_tpos);
   pd.diag_pos = (const int32_t *)ptr(off.diag_pos);
@@ -775,6 +848,10 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
   chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
   chk(up(off.pairs, sy.pairs.data(), sy.pairs.size() * sizeof(int2)));
+  chk(up(off.pp_cam, sy.pp_cam.data(), sy.pp_cam.size() * sizeof(int2)));
+  chk(up(off.pp_up, sy.pp_up.data(), sy.pp_up.size() * 4));
+  chk(up(off.cam_pp_start, sy.cam_pp_start.data(), sy.cam_pp_start.size() * 4));
+  chk(up(off.cam_pp, sy.cam_pp.data(), sy.cam_pp.size() * 4));
   chk(up(off.ch_pt, sy.ch_pt.data(), sy.ch_pt.size() * 4));
   chk(up(off.ch_f0, sy.ch_f0.data(), sy.ch_f0.size() * 4));
   chk(up(off.ch_ent, sy.ch_ent.data(), sy.ch_ent.size() * 4));
@@ -851,6 +928,7 @@ void Batch::add(const ProbDev &pd, int slot_tag) {
   for (int t = 0; t < pd.n_pcg_tiles; ++t) tiles[3].push_back(Tile{pi, t});
   for (int t = 0; t < pd.n_cam_tiles; ++t) tiles[4].push_back(Tile{pi, t});
   tiles[5].push_back(Tile{pi, 0});
+  for (int t = 0; t < pd.n_pri_tiles; ++t) tiles[11].push_back(Tile{pi, t});
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup j to XCD j mod 8),
@@ -873,7 +951,7 @@ int Batch::upload(hipStream_t s) {
   xcd_contiguous(tiles[2]);
   xcd_contiguous(tiles[7]);
   size_t need = probs.size() * sizeof(ProbDev);
-  constexpr int NL = 11;
+  constexpr int NL = 12;
   size_t offs[NL];
   for (int i = 0; i < NL; ++i) {
     need = (need + 255) & ~size_t(255);
@@ -897,9 +975,9 @@ int Batch::upload(hipStream_t s) {
   char *b = (char *)dev;
   plan.probs = (const ProbDev *)b;
   const Tile **dst[NL] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam, &plan.ctl,
-                          &plan.pp, &plan.ch, &plan.red, &plan.fin, &plan.fsh};
+                          &plan.pp, &plan.ch, &plan.red, &plan.fin, &plan.fsh, &plan.pri};
   int32_t *cnt[NL] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam, &plan.n_ctl,
-                      &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin, &plan.n_fsh};
+                      &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin, &plan.n_fsh, &plan.n_pri};
   for (int i = 0; i < NL; ++i) {
     *dst[i] = (const Tile *)(b + offs[i]);
     *cnt[i] = (int32_t)tiles[i].size();
@@ -1010,6 +1088,7 @@ void ba_default_options(ba_options *o) {
   o->lambda0 = 1e-4;
   o->huber_delta = 0.0;
   o->precision = BA_PREC_F32;
+  o->prior_seq_k = 1;
 }
 
 int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream, ba_problem **out) {

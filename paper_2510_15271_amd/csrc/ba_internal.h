@@ -125,6 +125,17 @@ struct ProbDev {
   void *part_d;                   // [diagonal entries][54] T: U, Y W^T (upper 21 each), g_c, Y g_p
   void *part_o;                   // [upper entries][36] T: sum Y W^T of the entry
   double *row_tot;                // [Cf][54] camera-row sums of the diagonal partials
+  // prior terms (FP64): weights, sequential pairs, per-camera U (21) and g (6)
+  // contributions, per-pair off-diagonal blocks lambda_c J_i^T J_j
+  double prior_abs, prior_seq;
+  int32_t prior_on, n_pp, n_pri_tiles, pad1;
+  const double *pose0;            // [C][12] the initial poses (prior anchors)
+  const int2 *pp_cam;             // [n_pp] (i, j), j = i + k
+  const int32_t *pp_up;           // [n_pp] upper block of (free i, free j), or -1
+  const int32_t *cam_pp_start;    // [Cf + 1]
+  const int32_t *cam_pp;          // pairs of each free camera, ascending
+  double *prior_diag;             // [Cf][27]
+  double *prior_off;              // [n_pp][36]
   void *Q;                        // [Nf][6] T: J_p,k V*_j^-1 (2x3), camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
@@ -155,8 +166,8 @@ struct ProbDev {
 // Tile lists of one batch (device pointers) and their lengths.
 struct BatchPlan {
   const ProbDev *probs;
-  const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh;
-  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh;
+  const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh, *pri;
+  int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh, n_pri;
   int32_t n_probs;
   ProbDev single;  // host copy of the descriptor when n_probs == 1 (passed by value to short kernels)
 };
@@ -182,7 +193,7 @@ struct KernelTimer {
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
-  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_NUM_KERNELS
+  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 

@@ -39,7 +39,7 @@ namespace bax {
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
-    "schur_reduce", "schur_rows", "schur_finish"};
+    "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -576,13 +576,198 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ prior terms
+// The prior terms of the Sec. 4.3 objective (Eq. abs, Eq. seq) as squared
+// Frobenius norms of 3x4 pose differences, in FP64.  A pose is held as 12 values,
+// R row-major then t; so are the 12-value residuals.  For a left increment
+// T <- Exp(xi) T, xi = (rho, phi), row q of d[R | t]/d xi is: for q < 9 (entry
+// (a, b) of R) 0 for rho and ([e_m]x R)_ab for phi_m; for q >= 9 (t_r) e_r for rho and
+// (-[t]x)_rm for phi_m.  A sequential pair (i, j) has A = T_i T_j^-1, which moves as
+// Exp(xi_i) A Exp(-xi_j): d/dxi_i is the same rule at A, d/dxi_j has -(R_A [e_m]x)_ab
+// for phi_m (q < 9) and -R_A rows for rho (q >= 9).
+__device__ inline void hat3(const double v[3], double H[9]) {
+  H[0] = 0.0;   H[1] = -v[2]; H[2] = v[1];
+  H[3] = v[2];  H[4] = 0.0;   H[5] = -v[0];
+  H[6] = -v[1]; H[7] = v[0];  H[8] = 0.0;
+}
+
+// Row q of the left-increment Jacobian of [R | t].
+__device__ inline void left_inc_row(const double *R, const double *t, int q, double out[6]) {
+  for (int m = 0; m < 6; ++m) out[m] = 0.0;
+  if (q < 9) {
+    const int a = q / 3, b = q % 3;
+    for (int m = 0; m < 3; ++m) {
+      double e[3] = {0.0, 0.0, 0.0}, H[9];
+      e[m] = 1.0;
+      hat3(e, H);
+      out[3 + m] = H[3 * a] * R[b] + H[3 * a + 1] * R[3 + b] + H[3 * a + 2] * R[6 + b];
+    }
+  } else {
+    const int r = q - 9;
+    double H[9];
+    hat3(t, H);
+    out[r] = 1.0;
+    for (int m = 0; m < 3; ++m) out[3 + m] = -H[3 * r + m];
+  }
+}
+
+// Row q of d A / d xi_j for A = T_i T_j^-1.
+__device__ inline void seq_j_row(const double *RA, int q, double out[6]) {
+  for (int m = 0; m < 6; ++m) out[m] = 0.0;
+  if (q < 9) {
+    const int a = q / 3, b = q % 3;
+    for (int m = 0; m < 3; ++m) {
+      double e[3] = {0.0, 0.0, 0.0}, H[9];
+      e[m] = 1.0;
+      hat3(e, H);
+      out[3 + m] = -(RA[3 * a] * H[b] + RA[3 * a + 1] * H[3 + b] + RA[3 * a + 2] * H[6 + b]);
+    }
+  } else {
+    const int r = q - 9;
+    for (int c = 0; c < 3; ++c) out[c] = -RA[3 * r + c];
+  }
+}
+
+// A = T_i T_j^-1 = [R_i R_j^T | t_i - R_i R_j^T t_j] as 12 values.
+__device__ inline void rel_pose(const double *Ti, const double *Tj, double A[12]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      A[3 * a + b] = Ti[3 * a] * Tj[3 * b] + Ti[3 * a + 1] * Tj[3 * b + 1] + Ti[3 * a + 2] * Tj[3 * b + 2];
+  for (int r = 0; r < 3; ++r)
+    A[9 + r] = Ti[9 + r] - (A[3 * r] * Tj[9] + A[3 * r + 1] * Tj[10] + A[3 * r + 2] * Tj[11]);
+}
+
+// 1/2 (lambda_a sum_i e_a + lambda_c sum_pairs e_c) at the poses P; the block's
+// threads split the terms and sum them in a fixed order.
+__device__ inline double prior_cost(const ProbDev &pd, const double *P, double *s_red) {
+  double c = 0.0;
+  if (pd.prior_abs > 0.0)
+    for (int i = threadIdx.x; i < pd.C; i += 256) {
+      double e = 0.0;
+      for (int q = 0; q < 12; ++q) {
+        const double d = P[12 * i + q] - pd.pose0[12 * i + q];
+        e += d * d;
+      }
+      c += 0.5 * pd.prior_abs * e;
+    }
+  for (int p = threadIdx.x; p < pd.n_pp; p += 256) {
+    const int2 ij = pd.pp_cam[p];
+    double A[12], A0[12];
+    rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
+    rel_pose(pd.pose0 + 12 * ij.x, pd.pose0 + 12 * ij.y, A0);
+    double e = 0.0;
+    for (int q = 0; q < 12; ++q) e += (A[q] - A0[q]) * (A[q] - A0[q]);
+    c += 0.5 * pd.prior_seq * e;
+  }
+  return block_sum256(c, s_red);
+}
+
+// Linearisation of the priors at the current poses: thread g < Cf forms the U (upper
+// 21) and g (6) contributions of free camera g (its absolute term, then its pairs in
+// order); thread g < n_pp forms lambda_c J_i^T J_j of pair g when both cameras are free.
+template <class T>
+__global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ probs,
+                                                   const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const double *P = pd.pose[st->cur];
+  const int g = 256 * tl.idx + (int)threadIdx.x;
+  if (g < pd.Cf) {
+    const int cam = pd.free_cam[g];
+    double U[21], gv[6];
+    for (int i = 0; i < 21; ++i) U[i] = 0.0;
+    for (int i = 0; i < 6; ++i) gv[i] = 0.0;
+    auto add_rows = [&](double lam, const double *r, auto row_of) {
+      for (int q = 0; q < 12; ++q) {
+        double J[6];
+        row_of(q, J);
+        int u = 0;
+        for (int a = 0; a < 6; ++a) {
+          for (int b = a; b < 6; ++b, ++u) U[u] += lam * J[a] * J[b];
+          gv[a] += lam * J[a] * r[q];
+        }
+      }
+    };
+    const double *Tc = P + 12 * cam;
+    if (pd.prior_abs > 0.0) {
+      double r[12];
+      for (int q = 0; q < 12; ++q) r[q] = Tc[q] - pd.pose0[12 * cam + q];
+      add_rows(pd.prior_abs, r, [&](int q, double J[6]) { left_inc_row(Tc, Tc + 9, q, J); });
+    }
+    for (int x = pd.cam_pp_start[g]; x < pd.cam_pp_start[g + 1]; ++x) {
+      const int2 ij = pd.pp_cam[pd.cam_pp[x]];
+      double A[12], A0[12], r[12];
+      rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
+      rel_pose(pd.pose0 + 12 * ij.x, pd.pose0 + 12 * ij.y, A0);
+      for (int q = 0; q < 12; ++q) r[q] = A[q] - A0[q];
+      if (ij.x == cam)
+        add_rows(pd.prior_seq, r, [&](int q, double J[6]) { left_inc_row(A, A + 9, q, J); });
+      else
+        add_rows(pd.prior_seq, r, [&](int q, double J[6]) { seq_j_row(A, q, J); });
+    }
+    double *o = pd.prior_diag + 27 * (size_t)g;
+    for (int i = 0; i < 21; ++i) o[i] = U[i];
+    for (int i = 0; i < 6; ++i) o[21 + i] = gv[i];
+  }
+  if (g < pd.n_pp && pd.pp_up[g] >= 0) {
+    const int2 ij = pd.pp_cam[g];
+    double A[12];
+    rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
+    double off[36];
+    for (int i = 0; i < 36; ++i) off[i] = 0.0;
+    for (int q = 0; q < 12; ++q) {
+      double Ji[6], Jj[6];
+      left_inc_row(A, A + 9, q, Ji);
+      seq_j_row(A, q, Jj);
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) off[6 * a + b] += pd.prior_seq * Ji[a] * Jj[b];
+    }
+    double *o = pd.prior_off + 36 * (size_t)g;
+    for (int i = 0; i < 36; ++i) o[i] = off[i];
+  }
+}
+
+// The pair blocks lambda_c J_i^T J_j added to S_ab and (transposed) S_ba, after the
+// Schur complement has written them.
+template <class T>
+__global__ __launch_bounds__(256) void k_prior_apply(const ProbDev *__restrict__ probs,
+                                                     const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int g = 256 * tl.idx + (int)threadIdx.x;
+  if (g >= pd.n_pp || pd.pp_up[g] < 0) return;
+  const int u = pd.pp_up[g];
+  const double *off = pd.prior_off + 36 * (size_t)g;
+  T *Sv = (T *)pd.S;
+  T *Sab = Sv + 36 * (size_t)pd.up_pos[u];
+  T *Sba = Sv + 36 * (size_t)pd.up_tpos[u];
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) {
+      Sab[6 * a + b] = T((double)Sab[6 * a + b] + off[6 * a + b]);
+      Sba[6 * b + a] = T((double)Sba[6 * b + a] + off[6 * a + b]);
+    }
+}
+
 // Row a of the reduced system from its camera sums tot = [U (upper 21), sum Y W^T
-// (upper 21), g_c (6), sum Y g_p (6)]: Marquardt damping, the diagonal block of S,
+// (upper 21), g_c (6), sum Y g_p (6)] and the prior terms: Marquardt damping, the diagonal block of S,
 // the right-hand side b = -g_c + sum Y g_p, the FP64 block-Jacobi inverse, and the
 // PCG start (x = 0, r = b, z = p = M^-1 b) with this row's partials of b.b and r.z.
 template <class T>
-__device__ void finish_camera_row(const ProbDev &pd, const LMState *st, int a, const double tot[54]) {
+__device__ void finish_camera_row(const ProbDev &pd, const LMState *st, int a, const double tot_in[54]) {
   const double lam = st->lambda;
+  // the prior terms add to U and g_c (their contributions, formed by k_prior_lin)
+  double tot[54];
+#pragma unroll
+  for (int i = 0; i < 54; ++i) tot[i] = tot_in[i];
+  if (pd.prior_on) {
+    const double *pr = pd.prior_diag + 27 * (size_t)a;
+    for (int i = 0; i < 21; ++i) tot[i] += pr[i];
+    for (int i = 0; i < 6; ++i) tot[42 + i] += pr[21 + i];
+  }
   double Sfull[36], Dc[6];
   int u = 0;
 #pragma unroll
@@ -1950,8 +2135,12 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   LMState *st = pd.st;
   if (!lm_active(st)) return;
   __shared__ double s_red[4];
-  const double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
-  const double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
+  double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
+  double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
+  if (pd.prior_on) {  // the prior terms at the current (first call only) and trial poses
+    if (!st->init_done) c0 += prior_cost(pd, pd.pose[st->cur], s_red);
+    tc += prior_cost(pd, pd.pose[1 - st->cur], s_red);
+  }
   const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
   const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
   double m0 = 0.0, mt = 0.0;
@@ -2247,6 +2436,10 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     Timed t(tm, K_LINEARIZE, s);
     k_linearize<T, S><<<bp.n_pt, kObsChunk, 0, s>>>(bp.probs, bp.pt);
   }
+  if (bp.n_pri) {
+    Timed t(tm, K_PRIOR_LIN, s);
+    k_prior_lin<T><<<bp.n_pri, 256, 0, s>>>(bp.probs, bp.pri);
+  }
   if (bp.n_ch) {
     Timed t(tm, K_SCHUR_CHUNK, s);
     k_schur_chunk<T, S><<<bp.n_ch, chunk_threads<T>(), chunk_lds_bytes(sizeof(T) == 8 ? 0 : 1), s>>>(bp.probs,
@@ -2275,6 +2468,10 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   if (bp.n_off) {
     Timed t(tm, K_SCHUR_OFF, s);
     k_schur_off<T, S><<<bp.n_off, 256, 0, s>>>(bp.probs, bp.off);
+  }
+  if (bp.n_pri) {
+    Timed t(tm, K_PRIOR_APPLY, s);
+    k_prior_apply<T><<<bp.n_pri, 256, 0, s>>>(bp.probs, bp.pri);
   }
   if (bp.n_pcg && one_reduction) {
     Timed t(tm, K_PCG_SPMV, s);

@@ -44,6 +44,11 @@ struct Symbolic {
   std::vector<uint32_t> ent_items;
   std::vector<int32_t> blk_start;
   int32_t n_dent = 0, n_oent = 0;
+  // prior terms: sequential pairs (caller's camera indices, camera order), their upper
+  // block (both cameras free) or -1, and the pairs of each free camera
+  double prior_abs = 0.0, prior_seq = 0.0;
+  std::vector<int2> pp_cam;
+  std::vector<int32_t> pp_up, cam_pp_start, cam_pp;
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   // distinct columns read by each PCG tile (kPcgRows rows) and, per block, the
   // position of its column in its tile's list
@@ -57,6 +62,7 @@ struct Offsets {
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
   size_t part_d, part_o, row_tot;
+  size_t pp_cam, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
   size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
@@ -91,7 +97,7 @@ struct DevProblem {
 struct Batch {
   std::vector<ProbDev> probs;
   std::vector<int> tags;
-  std::vector<Tile> tiles[11];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin, fsh
+  std::vector<Tile> tiles[12];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin, fsh, pri
   std::vector<char> host;
   void *dev = nullptr;
   size_t cap = 0;

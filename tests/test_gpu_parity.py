@@ -276,3 +276,39 @@ def test_loop_scene_against_stored_oracle_run(balib, prec):
     assert abs(rms - gold["final_rms_px"]) <= 1e-3
     assert abs(irms - gold["final_inlier_rms_px"]) <= 1e-3
     assert res["n_masked"] == gold["n_masked"]
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_pose_priors_f64_per_iteration_cost(balib, flags):
+    """Absolute and sequential pose priors (Sec. 4.3 objective) in both Schur forms
+    (flags 4: pair lists), FP64: every C_n within 1e-9 of the explicit-Schur oracle.
+    Sequential pairs reach 12 frames ahead, beyond any shared point (track length
+    ~8), so some S blocks come from the priors alone; cameras 0 and 7 are fixed."""
+    s = make_small_drive(30, 1500, seed=51)
+    s.cam_fixed[:] = 0
+    s.cam_fixed[[0, 7]] = 1
+    kw = dict(prior_abs=20.0, prior_seq=500.0, seq_k=12)
+    ref = O.lm_schur(O.Problem.from_scene(s, **kw), O.LMOptions(max_iters=8, solve="exact"))
+    res = _solve(balib, s, max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64",
+                 flags=flags, prior_abs=20.0, prior_seq=500.0, prior_seq_k=12)
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("priors f64 rel", rel.max(), res["iter_cost"][-1])
+    assert rel.max() <= 1e-9
+    p, R, t, X = _oracle_state(s, res)
+    p = O.Problem.from_scene(s, **kw)
+    assert abs(O.cost(p, R, t, X) - res["cost"]) <= 1e-9 * res["cost"]
+    assert O.prior_cost(p, R, t) > 0
+
+
+def test_pose_priors_f32_final_cost(balib):
+    """The same priors in FP32 with the benchmark's PCG schedule: final cost within
+    1e-5 of the FP64 oracle run with that schedule, recomputed by the oracle."""
+    s = make_small_drive(40, 3000, seed=52)
+    kw = dict(prior_abs=5.0, prior_seq=100.0, seq_k=1)
+    p = O.Problem.from_scene(s, **kw)
+    ref = O.lm_schur(p, O.LMOptions(max_iters=10, solve="pcg", pcg_max_iters=50, pcg_rel_tol=1e-6))
+    res = _solve(balib, s, max_iters=10, precision="f32", prior_abs=5.0, prior_seq=100.0, prior_seq_k=1)
+    _, R, t, X = _oracle_state(s, res)
+    c_dev = O.cost(p, R, t, X)
+    _say("priors f32", c_dev, ref.iter_cost[-1])
+    assert abs(c_dev - ref.iter_cost[-1]) <= 1e-5 * ref.iter_cost[-1]
