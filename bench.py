@@ -167,6 +167,11 @@ def main():
                     help="BA problems of the mixed-size stream in the serving leg (0: pose stream only, -1: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (3 times), to calibrate HBM counters")
+    ap.add_argument("--prior-abs", type=float, default=0.0,
+                    help="weight of the absolute pose prior (0: off)")
+    ap.add_argument("--prior-seq", type=float, default=0.0,
+                    help="weight of the sequential pose prior between frames i and i+k (0: off)")
+    ap.add_argument("--prior-seq-k", type=int, default=1)
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -199,7 +204,9 @@ def main():
         LM_ITERS = 15
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
-                                 flags=ba.FLAG_NO_GRAPH if args.no_graph else 0)
+                                 flags=ba.FLAG_NO_GRAPH if args.no_graph else 0,
+                                 prior_abs=args.prior_abs, prior_seq=args.prior_seq,
+                                 prior_seq_k=args.prior_seq_k)
     info = prob.info()
     names = list(prob.kernel_times().keys())
 
@@ -275,6 +282,8 @@ def main():
                    "n_obs": info["n_obs"], "n_pairs": info["n_pairs"],
                    "nnzb": info["nnzb"], "precision": args.precision,
                    "schur_form": "point chunks" if info["schur_form"] else "pair lists",
+                   "pose_priors": ({"abs": args.prior_abs, "seq": args.prior_seq, "seq_k": args.prior_seq_k}
+                                   if args.prior_abs > 0 or args.prior_seq > 0 else None),
                    "graph": not args.no_graph},
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),

@@ -312,3 +312,21 @@ def test_pose_priors_f32_final_cost(balib):
     c_dev = O.cost(p, R, t, X)
     _say("priors f32", c_dev, ref.iter_cost[-1])
     assert abs(c_dev - ref.iter_cost[-1]) <= 1e-5 * ref.iter_cost[-1]
+
+
+def test_pose_priors_full_size_cost_matches_oracle_at_device_state(balib):
+    """The 2M-observation drive with both priors (lambda_a 10, lambda_c 1000, k = 1..2)
+    in the benchmark's configuration (FP32, 10 LM iterations, PCG 50 / 1e-6): the
+    device's accepted cost equals the oracle's cost (reprojection + priors)
+    recomputed at the device's final state within 1e-5, the priors are active, and
+    the accepted costs never increase."""
+    s = make_config1()
+    res = _solve(balib, s, max_iters=10, precision="f32", prior_abs=10.0, prior_seq=1000.0, prior_seq_k=2)
+    p = O.Problem.from_scene(s, prior_abs=10.0, prior_seq=1000.0, seq_k=2)
+    R, t, X = O.quat_to_rot(res["q"]), res["t"], res["X"]
+    c = O.cost(p, R, t, X)
+    pc = O.prior_cost(p, R, t)
+    _say("full-size priors: device", res["cost"], "oracle", c, "prior part", pc)
+    assert abs(res["cost"] - c) <= 1e-5 * c
+    assert pc > 1e-3 * c
+    assert all(b <= a for a, b in zip(res["iter_cost"], res["iter_cost"][1:]))
