@@ -196,12 +196,15 @@ class Problem:
     seq_k: int = 1                # sequential pairs (i, i + k), k = 1..seq_k, in camera order
     R0: np.ndarray | None = None  # T_init: the initial poses
     t0: np.ndarray | None = None
+    active: np.ndarray | None = None  # (N,) bool: observations kept by the culling step
 
     def __post_init__(self):
         if self.R0 is None:
             self.R0 = np.array(self.R, np.float64)
         if self.t0 is None:
             self.t0 = np.array(self.t, np.float64)
+        if self.active is None:
+            self.active = np.ones(self.cam.shape[0], bool)
 
     @classmethod
     def from_scene(cls, s, prior_abs: float = 0.0, prior_seq: float = 0.0, seq_k: int = 1) -> "Problem":
@@ -226,13 +229,15 @@ class Problem:
 
 def residuals(p: Problem, R=None, t=None, X=None):
     """Per-observation residuals r_k = pi(...) - z_k and the validity mask
-    (depth > Z_MIN; masked observations get r = 0)."""
+    (depth > Z_MIN; masked observations get r = 0).  Observations removed by the
+    culling step (``p.active`` false) also get r = 0 and count as valid: they are
+    out of the problem, not masked."""
     R = p.R if R is None else R
     t = p.t if t is None else t
     X = p.X if X is None else X
     uv, Pc = project(p.K[p.cam], R[p.cam], t[p.cam], X[p.pt])
-    valid = Pc[:, 2] > Z_MIN
-    r = np.where(valid[:, None], uv - p.uv, 0.0)
+    valid = (Pc[:, 2] > Z_MIN) | ~p.active
+    r = np.where((valid & p.active)[:, None], uv - p.uv, 0.0)
     return r, valid, Pc
 
 
@@ -245,7 +250,7 @@ def cost_and_masked(p: Problem, R=None, t=None, X=None):
     """(C, number of masked observations) at a state."""
     r, valid, _ = residuals(p, R, t, X)
     s = np.sum(r * r, axis=1)
-    C = 0.5 * float(np.sum(huber_rho(s, p.delta)[valid]))
+    C = 0.5 * float(np.sum(huber_rho(s, p.delta)[valid & p.active]))
     if p.prior_abs > 0 or p.prior_seq > 0:
         C += prior_cost(p, R, t)
     return C, int((~valid).sum())
@@ -362,11 +367,11 @@ def prior_system(p: Problem, n: int):
 
 
 def rms(p: Problem, R=None, t=None, X=None, inlier_px: float | None = None) -> float:
-    """sqrt(sum ||r||^2 / N) in pixels over valid observations (unweighted); with
-    ``inlier_px``, over observations with ||r|| <= inlier_px only."""
+    """sqrt(sum ||r||^2 / N) in pixels over valid active observations (unweighted);
+    with ``inlier_px``, over observations with ||r|| <= inlier_px only."""
     r, valid, _ = residuals(p, R, t, X)
     s = np.sum(r * r, axis=1)
-    m = valid
+    m = valid & p.active
     if inlier_px is not None:
         m = m & (s <= inlier_px * inlier_px)
     return math.sqrt(float(np.sum(s[m])) / max(int(m.sum()), 1))
@@ -385,13 +390,13 @@ def jacobians(p: Problem, R=None, t=None, X=None):
     _, valid, Pc = residuals(p, R, t, X)
     Kk = p.K[p.cam]
     x, y, z = Pc[:, 0], Pc[:, 1], Pc[:, 2]
-    zs = np.where(valid, z, 1.0)
+    zs = np.where(valid & (z > Z_MIN), z, 1.0)
     Jpi = np.zeros((p.n_obs, 2, 3))
     Jpi[:, 0, 0] = Kk[:, 0] / zs
     Jpi[:, 0, 2] = -Kk[:, 0] * x / (zs * zs)
     Jpi[:, 1, 1] = Kk[:, 1] / zs
     Jpi[:, 1, 2] = -Kk[:, 1] * y / (zs * zs)
-    Jpi[~valid] = 0.0
+    Jpi[~(valid & p.active)] = 0.0
     dP = np.concatenate([np.broadcast_to(np.eye(3), (p.n_obs, 3, 3)), -hat(Pc)], axis=2)
     Jc = Jpi @ dP
     Jp = Jpi @ R[p.cam]
@@ -428,7 +433,7 @@ def normal_equations(p: Problem):
     r, valid, _ = residuals(p)
     Jc, Jp = jacobians(p)
     s = np.sum(r * r, axis=1)
-    w = np.where(valid, huber_weight(s, p.delta), 0.0)
+    w = np.where(valid & p.active, huber_weight(s, p.delta), 0.0)
     fidx, nf = _free_index(p.fixed)
     N = p.n_obs
     ncam = 6 * nf
@@ -710,3 +715,79 @@ def pose_only_gn(K, q0, t0, X, uv, delta: float, iters: int = 10):
     r = np.where(valid[:, None], pr - uv, 0.0)
     costs.append(0.5 * float(np.sum(huber_rho(np.sum(r * r, axis=1), delta)[valid])))
     return R, t, status, costs
+
+
+# ----------------------------------------------------------------------------- triangulation and culling
+
+def triangulate_midpoint(p: Problem, j: int, R=None, t=None):
+    """Multi-view midpoint triangulation of point j from its active observations
+    (Sec. 4.3 names the DLT of Eq. dlt and a midpoint method; this is the latter):
+    X = argmin sum_k ||(I - d_k d_k^T)(X - c_k)||^2 with camera centre c_k = -R_k^T t_k and
+    unit ray d_k along R_k^T K_k^-1 (u, v, 1), i.e. the solution of
+    (sum_k (I - d_k d_k^T)) X = sum_k (I - d_k d_k^T) c_k (numpy.linalg.solve).
+    Returns (X, ok): ok iff at least two active observations, det of the 3x3 system
+    > 1e-12 and every active observation has depth > Z_MIN at X."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    ks = np.nonzero((p.pt == j) & p.active)[0]
+    if ks.size < 2:
+        return None, False
+    A = np.zeros((3, 3))
+    b = np.zeros(3)
+    for k in ks:
+        i = p.cam[k]
+        fx, fy, cx, cy = p.K[i]
+        d = R[i].T @ np.array([(p.uv[k, 0] - cx) / fx, (p.uv[k, 1] - cy) / fy, 1.0])
+        d = d / np.linalg.norm(d)
+        c = -R[i].T @ t[i]
+        M = np.eye(3) - np.outer(d, d)
+        A += M
+        b += M @ c
+    if not np.linalg.det(A) > 1e-12:
+        return None, False
+    X = np.linalg.solve(A, b)
+    for k in ks:
+        i = p.cam[k]
+        if not (R[i][2] @ X + t[i][2]) > Z_MIN:
+            return None, False
+    return X, True
+
+
+def cull_and_triangulate(p: Problem, tau_px: float):
+    """The culling step after a BA round (Sec. 4.3): an active observation stays
+    active iff ||r_k|| <= tau_px at the current state; a point left with fewer than two
+    active observations leaves the problem (all its observations inactive); a point
+    that lost observations is re-triangulated from the ones that remain (midpoint),
+    and leaves the problem if that fails.  Updates p.active and p.X in place and
+    returns (active observations, points in the problem)."""
+    r, valid, _ = residuals(p)
+    s = np.sum(r * r, axis=1)
+    keep = p.active & valid & (s <= tau_px * tau_px)
+    lost = p.active & ~keep
+    p.active = keep
+    for j in np.unique(p.pt[lost]):
+        n = int(np.count_nonzero((p.pt == j) & p.active))
+        X, ok = triangulate_midpoint(p, j) if n >= 2 else (None, False)
+        if ok:
+            p.X[j] = X
+        else:
+            p.active[p.pt == j] = False
+    counts = np.bincount(p.pt[p.active], minlength=p.n_pts)
+    return int(p.active.sum()), int(np.count_nonzero(counts > 0))
+
+
+def refine(p: Problem, stages, rounds: int, opts: LMOptions):
+    """The two-stage iterative framework of Sec. 4.3: for each stage (huber_delta,
+    tau_px) -- first a robust loss with a relaxed threshold, then no loss with a strict
+    one -- ``rounds`` times: an LM solve from lambda0, then cull_and_triangulate.
+    Returns (p, history) with one (stage, round, cost, active obs, points) per round."""
+    p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy(), active=p.active.copy())
+    hist = []
+    for si, (delta, tau) in enumerate(stages):
+        p.delta = float(delta)
+        for rd in range(rounds):
+            res = lm_schur(p, opts)
+            p.R, p.t, p.X = res.R, res.t, res.X
+            n_act, n_pts = cull_and_triangulate(p, tau)
+            hist.append((si, rd, res.iter_cost[-1], n_act, n_pts))
+    return p, hist

@@ -442,3 +442,71 @@ def test_strong_absolute_prior_reproduces_hard_fixed_poses():
     assert 0.009 < moves[1] / moves[0] < 0.011
     assert 0.009 < gains[1] / gains[0] < 0.011
     assert gains[1] < 1e-5 * c_fixed
+
+
+# ----------------------------------------------------------------------------- triangulation and culling
+
+def test_midpoint_triangulation_is_exact_on_noiseless_rays():
+    s = make_small_drive(10, 200, seed=41, sigma=0.0)
+    p = _gt_problem(s)
+    for j in range(0, p.n_pts, 7):
+        X, ok = O.triangulate_midpoint(p, j)
+        assert ok
+        assert np.linalg.norm(X - p.X[j]) <= 1e-9 * (1 + np.linalg.norm(p.X[j]))
+
+
+def test_midpoint_triangulation_matches_scipy_least_squares():
+    """The closed-form 3x3 solve against an iterative minimisation of the same
+    objective, sum of squared distances from X to the observation rays."""
+    s = make_small_drive(10, 120, seed=42, sigma=1.0)
+    p = O.Problem.from_scene(s)
+    for j in range(0, p.n_pts, 11):
+        ks = np.nonzero(p.pt == j)[0]
+        if ks.size < 2:
+            continue
+        X, ok = O.triangulate_midpoint(p, j)
+        rays = []
+        for k in ks:
+            i = p.cam[k]
+            d = p.R[i].T @ np.array([(p.uv[k, 0] - p.K[i, 2]) / p.K[i, 0], (p.uv[k, 1] - p.K[i, 3]) / p.K[i, 1], 1.0])
+            rays.append((-p.R[i].T @ p.t[i], d / np.linalg.norm(d)))
+
+        def f(x):
+            return np.concatenate([(x - c) - d * (d @ (x - c)) for c, d in rays])
+
+        ref = scipy.optimize.least_squares(f, p.X[j], xtol=1e-15, ftol=1e-15, gtol=1e-15)
+        assert ok and np.linalg.norm(X - ref.x) <= 1e-7 * (1 + np.linalg.norm(ref.x))
+
+
+def test_midpoint_triangulation_follows_a_similarity_transform():
+    """World X -> s Q X + tau, cameras R -> R Q^T, t -> s t - R Q^T tau: the triangulated
+    point moves the same way."""
+    s = make_small_drive(8, 80, seed=43, sigma=0.5)
+    p = O.Problem.from_scene(s)
+    Q = Rotation.from_rotvec([0.2, -0.4, 0.3]).as_matrix()
+    sc, tau = 2.5, np.array([3.0, -1.0, 7.0])
+    q = O.Problem.from_scene(s)
+    q.R = p.R @ Q.T
+    q.t = sc * p.t - np.einsum("nij,j->ni", q.R, tau)
+    for j in range(0, p.n_pts, 5):
+        X, ok = O.triangulate_midpoint(p, j)
+        Y, ok2 = O.triangulate_midpoint(q, j)
+        if ok:
+            assert ok2 and np.linalg.norm(Y - (sc * Q @ X + tau)) <= 1e-9 * np.linalg.norm(Y)
+
+
+def test_two_stage_refine_removes_planted_outliers_and_reaches_noise_level():
+    """10 % uniform outliers: after the robust stage (Huber 1 px, cull at 8 px) and the
+    strict stage (no loss, cull at 3 px) at least 99 % of the planted outliers are out,
+    and the RMS over the remaining observations matches the noise statistics
+    sigma sqrt((2N - d) / N) within 5 % (N, d counted over what remains)."""
+    s = make_small_drive(20, 1000, seed=61, outlier_frac=0.1, huber_delta=1.0)
+    p = O.Problem.from_scene(s)
+    q, hist = O.refine(p, [(1.0, 8.0), (0.0, 3.0)], 2, O.LMOptions(max_iters=6, solve="exact"))
+    assert (~q.active & s.outlier).sum() >= 0.99 * s.outlier.sum()
+    n = int(q.active.sum())
+    pts = int(np.count_nonzero(np.bincount(q.pt[q.active], minlength=q.n_pts) > 0))
+    d = 6 * int((~q.fixed).sum()) + 3 * pts - 1
+    expected = s.sigma * math.sqrt((2 * n - d) / n)
+    assert abs(O.rms(q) - expected) <= 0.05 * expected
+    assert hist[-1][3] == n and hist[-1][4] == pts
