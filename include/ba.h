@@ -103,7 +103,7 @@ typedef struct {
   int32_t n_masked;       /* observations with depth <= 1e-6 at the final state           */
   double cost0;           /* C at the initial state                                       */
   double cost;            /* C at the final state                                         */
-  double rms_px;          /* sqrt(sum ||r||^2 / N) over unmasked observations             */
+  double rms_px;          /* sqrt(sum ||r||^2 / N) over unmasked observations in the problem */
   double lambda;          /* damping after the last iteration                             */
   double *iter_cost;      /* caller buffer of max_iters + 1 entries, or NULL: C_0..C_n    */
   int32_t *pcg_iters;     /* caller buffer of max_iters entries, or NULL                  */
@@ -148,8 +148,51 @@ int ba_solve(ba_problem *p);
 int ba_solve_async(ba_problem *p);
 int ba_wait(ba_problem *p);
 /* Restore the poses and points given to ba_create (device-side copy; the
-   structure, buffers and options are kept).  The next solve starts from them. */
+   structure, buffers and options are kept) and put every observation back in
+   the problem.  The next solve starts from them. */
 int ba_reset(ba_problem *p);
+
+/* ---------------------------------------------------------------- iterative refinement
+   The alternation of BA and triangulation of paper Sec. 4.3 ("Iterative
+   Triangulation and Mapping"): after each BA round, observations whose
+   reprojection error exceeds the outlier threshold leave the problem and the
+   points that lost observations are triangulated again from the ones that
+   remain; a first stage uses a robust loss and a relaxed threshold, a second no
+   loss and a strict one.  Each stage runs `rounds` times: a solve of
+   opt->max_iters LM iterations from the current state (lambda reset to lambda0)
+   with the stage's loss, then the culling step at the accepted state:
+     - an active observation stays iff its depth is > 1e-6 and ||r_k|| <= cull_px
+       (FP64 residual from the stored pixels);
+     - a point that lost an observation is re-triangulated by the multi-view
+       midpoint method (the X minimising the summed squared distances to its
+       observation rays, Sec. 4.3's midpoint variant), in FP64, from its active
+       observations; if fewer than two remain, the 3x3 system is singular
+       (determinant <= 1e-12) or the new point is not in front of every camera
+       that observes it, all its observations leave the problem instead.
+   Observations out of the problem contribute nothing to C, the Hessian blocks or
+   the gradient and are not counted as masked.  ba_reset puts them back.
+   BA_EINVAL: n_stages < 1, rounds < 1, stages NULL, a non-finite huber_delta, or
+   a cull_px that is not positive and finite (checked before any side effect).
+   hist: NULL or n_stages * rounds entries, stage-major.  After the call,
+   ba_get_result returns the final state; its report is that of the last solve,
+   with n_masked and rms_px evaluated again at the final state over the
+   observations still in the problem. */
+typedef struct {
+  double huber_delta;     /* the stage's loss: <= 0 none, > 0 Huber threshold in pixels  */
+  double cull_px;         /* outlier threshold on ||r_k|| in pixels, > 0                 */
+} ba_refine_stage;
+typedef struct {
+  int32_t stage, round;
+  int32_t iters, status;  /* of the round's solve                                        */
+  double cost;            /* C at the end of the round's solve (before its culling)      */
+  int64_t n_active_obs;   /* observations in the problem after the round's culling       */
+  int32_t n_active_pts;   /* points with at least one observation in the problem         */
+  int32_t reserved;
+} ba_refine_round;
+int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, int32_t rounds,
+              ba_refine_round *hist);
+/* n_obs flags in the caller's observation order: 1 = in the problem. */
+int ba_get_active(const ba_problem *p, uint8_t *active_out);
 /* Copy the current state and the report of the last solve.  NULL outputs are
    skipped.  poses_out: n_cams entries; points_out: 3 * n_pts doubles. */
 int ba_get_result(const ba_problem *p, ba_pose *poses_out, double *points_out, ba_report *rep);

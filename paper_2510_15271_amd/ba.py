@@ -67,6 +67,16 @@ class ProblemInfo(C.Structure):
                 ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64)]
 
 
+class RefineStage(C.Structure):
+    _fields_ = [("huber_delta", C.c_double), ("cull_px", C.c_double)]
+
+
+class RefineRound(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("round", C.c_int32), ("iters", C.c_int32),
+                ("status", C.c_int32), ("cost", C.c_double), ("n_active_obs", C.c_int64),
+                ("n_active_pts", C.c_int32), ("reserved", C.c_int32)]
+
+
 class ServerStats(C.Structure):
     _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("solves_per_s", C.c_double),
                 ("done", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
@@ -98,6 +108,8 @@ def lib():
     L.ba_reset.argtypes = [vp]
     L.ba_get_result.argtypes = [vp, vp, vp, C.POINTER(Report)]
     L.ba_get_info.argtypes = [vp, C.POINTER(ProblemInfo)]
+    L.ba_refine.argtypes = [vp, i32, C.POINTER(RefineStage), i32, C.POINTER(RefineRound)]
+    L.ba_get_active.argtypes = [vp, vp]
     L.ba_problem_bytes.argtypes = [vp]
     L.ba_problem_bytes.restype = i64
     L.ba_destroy.argtypes = [vp]
@@ -214,6 +226,21 @@ class Problem:
 
     def solve_async(self):
         _check(lib().ba_solve_async(self._h))
+
+    def refine(self, stages, rounds):
+        """ba_refine: stages is a sequence of (huber_delta, cull_px); returns one
+        dict per (stage, round), stage-major."""
+        st = (RefineStage * len(stages))(*[RefineStage(float(d), float(t)) for d, t in stages])
+        hist = (RefineRound * max(len(stages) * int(rounds), 1))()
+        _check(lib().ba_refine(self._h, len(stages), st, int(rounds), hist))
+        return [{f: getattr(h, f) for f, _ in RefineRound._fields_ if f != "reserved"}
+                for h in hist[:len(stages) * int(rounds)]]
+
+    def active(self):
+        """Observations in the problem (1) or removed by culling (0), caller's order."""
+        a = np.zeros(int(self._desc.desc.n_obs), np.uint8)
+        _check(lib().ba_get_active(self._h, a.ctypes.data_as(C.c_void_p)))
+        return a
 
     def wait(self):
         _check(lib().ba_wait(self._h))

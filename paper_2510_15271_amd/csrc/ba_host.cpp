@@ -345,7 +345,9 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
 
   // order by (internal point, camera): stable counting sort by camera, then by point
   std::vector<int32_t> cnt(std::max(C, P) + 1);
-  std::vector<int32_t> by_cam(N), order(N);
+  std::vector<int32_t> by_cam(N);
+  std::vector<int32_t> &order = sy.obs_order;
+  order.assign(N, 0);
   std::fill(cnt.begin(), cnt.begin() + C + 1, 0);
   for (int64_t k = 0; k < N; ++k) cnt[d->obs[k].cam + 1]++;
   for (int i = 0; i < C; ++i) cnt[i + 1] += cnt[i];
@@ -600,6 +602,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.obs_uv = L.take(N * 2 * T);
   o.pt_start = L.take((P + 1) * 4);
   o.obs_rpos = L.take(N * 4);
+  o.obs_act = L.take(N);
   o.cam_obs = L.take(sy.cam_obs.size() * 4 + 4);
   o.cam_obs_start = L.take(sy.cam_obs_start.size() * 4 + 4);
   o.up_pair_start = L.take(sy.up_pair_start.size() * 4 + 4);
@@ -664,6 +667,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_cg[0] = L.take(3 * npcg * 8);
   o.part_cg[1] = L.take(3 * npcg * 8);
   o.part_rr = L.take(npcg * 8);
+  o.part_cull = L.take(npt * 8);
   o.iter_cost = L.take((max_iters + 1) * 8);
   o.iter_pcg = L.take(max_iters * 4);
   o.total = L.off;
@@ -694,6 +698,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   N = sy.N;
   max_tcols = sy.max_tcols;
   pt_order = sy.pt_order;
+  obs_order = sy.obs_order;
+  n_active = N;
   plan(sy, precision, max_iters, off);
   dev = base;
   auto ptr = [&](size_t o) { return (void *)(base + o); };
@@ -722,6 +728,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.obs_uv = ptr(off.obs_uv);
   pd.pt_start = (const int32_t *)ptr(off.pt_start);
   pd.obs_rpos = (const int32_t *)ptr(off.obs_rpos);
+  pd.obs_act = (uint8_t *)ptr(off.obs_act);
   pd.cam_obs = (const int32_t *)ptr(off.cam_obs);
   pd.cam_obs_start = (const int32_t *)ptr(off.cam_obs_start);
   pd.up_pair_start = (const int32_t *)ptr(off.up_pair_start);
@@ -806,6 +813,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_cg[0] = (double *)ptr(off.part_cg[0]);
   pd.part_cg[1] = (double *)ptr(off.part_cg[1]);
   pd.part_rr = (double *)ptr(off.part_rr);
+  pd.part_cull = (int32_t *)ptr(off.part_cull);
   pd.st = (LMState *)ptr(off.st);
   pd.iter_cost = (double *)ptr(off.iter_cost);
   pd.iter_pcg = (int32_t *)ptr(off.iter_pcg);
@@ -844,6 +852,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.obs_pt, sy.obs_pt.data(), sy.obs_pt.size() * 4));
   chk(up(off.pt_start, sy.pt_start.data(), sy.pt_start.size() * 4));
   chk(up(off.obs_rpos, sy.obs_rpos.data(), sy.obs_rpos.size() * 4));
+  chk(hipMemsetAsync(base + off.obs_act, 1, (size_t)N, s));
   chk(up(off.cam_obs, sy.cam_obs.data(), sy.cam_obs.size() * 4));
   chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
   chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
@@ -1134,6 +1143,8 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   p->sy.pairs.shrink_to_fit();
   p->sy.ent_items.clear();
   p->sy.ent_items.shrink_to_fit();
+  p->sy.obs_order.clear();
+  p->sy.obs_order.shrink_to_fit();
   p->dp.staging_f.clear();
   p->dp.staging_d.clear();
   p->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1256,10 +1267,82 @@ int ba_reset(ba_problem *p) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(dp.view.X[0], dp.dev + dp.off.X_init, 3 * (size_t)dp.P * 8,
                        hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(dp.view.obs_act, 1, (size_t)dp.N, p->stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
+  dp.n_active = dp.N;
   dp.host_state = LMState{};
   dp.host_state.cur = 0;
   p->solved = false;
+  return BA_OK;
+}
+
+int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, int32_t rounds,
+              ba_refine_round *hist) {
+  if (n_stages < 1 || !stages) return fail(BA_EINVAL, "n_stages must be >= 1, with a stage array");
+  if (rounds < 1) return fail(BA_EINVAL, "rounds must be >= 1");
+  for (int i = 0; i < n_stages; ++i) {
+    if (!std::isfinite(stages[i].huber_delta))
+      return fail(BA_EINVAL, "stage %d: huber_delta must be finite", i);
+    if (!std::isfinite(stages[i].cull_px) || !(stages[i].cull_px > 0.0))
+      return fail(BA_EINVAL, "stage %d: cull_px must be positive and finite", i);
+  }
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
+  DevProblem &dp = p->dp;
+  const double huber0 = dp.huber;
+  std::vector<int32_t> cnt(2 * (size_t)dp.view.n_pt_tiles);
+  int rc = BA_OK;
+  for (int si = 0; si < n_stages && rc == BA_OK; ++si) {
+    dp.huber = stages[si].huber_delta > 0.0 ? stages[si].huber_delta : 0.0;
+    for (int r = 0; r < rounds; ++r) {
+      rc = ba_solve(p);
+      if (rc != BA_OK) break;
+      const double tau = stages[si].cull_px;
+      hipError_t e = launch_cull(dp.precision, p->batch.plan, tau * tau, p->stream, nullptr);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), dp.view.part_cull, cnt.size() * 4, hipMemcpyDeviceToHost, p->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "culling");
+        break;
+      }
+      int64_t na = 0, np = 0;
+      for (size_t i = 0; i < cnt.size(); i += 2) {
+        na += cnt[i];
+        np += cnt[i + 1];
+      }
+      dp.n_active = na;
+      if (hist) {
+        ba_refine_round &h = hist[(size_t)si * rounds + r];
+        std::memset(&h, 0, sizeof(h));
+        h.stage = si;
+        h.round = r;
+        h.iters = dp.host_state.iter;
+        h.status = dp.host_state.status;
+        h.cost = dp.host_state.cost;
+        h.n_active_obs = na;
+        h.n_active_pts = (int32_t)np;
+      }
+    }
+  }
+  dp.huber = huber0;
+  if (rc != BA_OK) return rc;
+  // the report's rms and masked count describe the final state and mask
+  hipError_t e = launch_eval(dp.precision, p->batch.plan, p->stream, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "evaluation");
+  return BA_OK;
+}
+
+int ba_get_active(const ba_problem *p, uint8_t *active_out) {
+  if (!p || !active_out) return fail(BA_EINVAL, "NULL argument");
+  if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
+  const DevProblem &dp = p->dp;
+  std::vector<uint8_t> buf((size_t)dp.N);
+  hipError_t e = hipMemcpyAsync(buf.data(), dp.view.obs_act, buf.size(), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "mask download");
+  for (size_t k = 0; k < buf.size(); ++k) active_out[dp.obs_order[k]] = buf[k];
   return BA_OK;
 }
 
@@ -1371,7 +1454,7 @@ int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_ou
         masked += nm[i];
       }
       rep->n_masked = (int32_t)masked;
-      rep->rms_px = (N - masked) > 0 ? std::sqrt(tot / (double)(N - masked)) : 0.0;
+      rep->rms_px = (n_active - masked) > 0 ? std::sqrt(tot / (double)(n_active - masked)) : 0.0;
       if (ic) {
         e = hipMemcpy(ic, view.iter_cost, (st.iter + 1) * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "report download");

@@ -89,6 +89,8 @@ struct ProbDev {
   const void *obs_uv;             // [N][2] T
   const int32_t *pt_start;        // [P + 1]
   const int32_t *obs_rpos;        // [N] record of each observation, -1 if its camera is fixed
+  uint8_t *obs_act;               // [N] 1: in the problem; 0: removed by culling (contributes
+                                  // nothing and is not counted as masked)
   // pair-list form: records are camera-major
   const int32_t *cam_obs;         // [Nf] observation of each camera-major record
   const int32_t *cam_obs_start;   // [Cf + 1] records of each free camera
@@ -158,6 +160,7 @@ struct ProbDev {
   double *part_pq;                // [n_pcg_tiles]
   double *part_cg[2];             // [3][n_pcg_tiles] r.u, w.u, r.r partials by parity
   double *part_rr;                // [n_pcg_tiles]
+  int32_t *part_cull;             // [n_pt_tiles][2] active observations, points with one, after culling
   LMState *st;
   double *iter_cost;              // [max_iters + 1]
   int32_t *iter_pcg;              // [max_iters]
@@ -193,7 +196,7 @@ struct KernelTimer {
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
-  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_NUM_KERNELS
+  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_CULL, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -218,6 +221,10 @@ hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, 
                                hipStream_t s, KernelTimer *timer, int part = LM_ALL);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
+// Culling and re-triangulation at the accepted state: observations with
+// ||r||^2 > tau2 (or depth <= the threshold) leave the problem; points that lost
+// one are re-triangulated (midpoint) from the rest, or leave if that fails.
+hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, hipStream_t s, KernelTimer *timer);
 // Pose-only Gauss-Newton, one workgroup per request.
 hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
                           double huber_delta, hipStream_t s, KernelTimer *timer);

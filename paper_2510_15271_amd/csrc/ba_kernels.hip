@@ -39,7 +39,7 @@ namespace bax {
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
-    "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply"};
+    "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -444,7 +444,8 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
       const T *K = Kall + 4 * cam;
       T r0, r1;
       LinRec<T, S> rec;
-      if (residual<T>(K, x, y, z, uv[2 * k], uv[2 * k + 1], r0, r1)) {
+      const bool on = pd.obs_act[k] != 0;
+      if (on && residual<T>(K, x, y, z, uv[2 * k], uv[2 * k + 1], r0, r1)) {
         const T s = r0 * r0 + r1 * r1;
         const T w = huber_w(s, delta);
         const T sw = sqrt(w);
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[6 + m] = w * (Jp[m] * r0 + Jp[3 + m] * r1);
       } else {
-        ++masked;
+        masked += on;
 #pragma unroll
         for (int i = 0; i < 7; ++i) rec.f[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
@@ -909,7 +910,7 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
       const T x = T(xd), yy = T(yd), z = T(zd);
       const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
       T r0, r1;
-      if (residual<T>(K, x, yy, z, uv[0], uv[1], r0, r1)) {
+      if (pd.obs_act[k] && residual<T>(K, x, yy, z, uv[0], uv[1], r0, r1)) {
         const T s = r0 * r0 + r1 * r1;
         const T sw = sqrt(huber_w(s, delta));
         T Jc[12], Jp[6];
@@ -1192,7 +1193,7 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
           T r0, r1, gk[6];
 #pragma unroll
           for (int r = 0; r < 6; ++r) gk[r] = T(0);
-          if (residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+          if (pd.obs_act[kk[h]] && residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
             const T w = huber_w(r0 * r0 + r1 * r1, T(st->huber_delta));
             T Jg[12], Jpg[6];
             jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
@@ -2103,6 +2104,7 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
   double cost = 0.0;
   int masked = 0;
   for (int k = k0 + threadIdx.x; k < k1; k += kObsChunk) {
+    if (!pd.obs_act[k]) continue;
     const int jl = pd.obs_pt[k] - j0;
     const int cam = pd.obs_cam[k];
     double xd, yd, zd;
@@ -2214,6 +2216,7 @@ __global__ __launch_bounds__(256) void k_eval(const ProbDev *__restrict__ probs,
   double sq = 0.0;
   int masked = 0;
   for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+    if (!pd.obs_act[k]) continue;
     const int j = pd.obs_pt[k];
     const int cam = pd.obs_cam[k];
     double xd, yd, zd;
@@ -2229,6 +2232,131 @@ __global__ __launch_bounds__(256) void k_eval(const ProbDev *__restrict__ probs,
   if (threadIdx.x == 0) {
     pd.part_sq[tl.idx] = tsq;
     pd.part_masked[tl.idx] = (int32_t)tm;
+  }
+}
+
+// ------------------------------------------------------------------ culling and re-triangulation
+// The step between BA rounds of the iterative triangulation framework (Sec. 4.3).
+// At the accepted state an active observation stays iff its point is in front of
+// the camera and ||r||^2 <= tau2 (residual in FP64 from the stored pixels).  A point
+// that lost an observation is re-triangulated from the active ones that remain by
+// the multi-view midpoint method; it leaves the problem (all its observations
+// inactive) when fewer than two remain or the triangulation fails.  One thread per
+// point; per-tile counts of active observations and of points with at least one
+// go to part_cull.
+
+// Midpoint triangulation from the active observations [k0, k1) of one point: the X
+// minimising the summed squared distances to the observation rays, i.e. the solution
+// of (sum_k (I - d_k d_k^T)) X = sum_k (I - d_k d_k^T) c_k with centre c_k = -R^T t and
+// unit ray d_k along R^T K^-1 (u, v, 1), by the adjugate in FP64.  Fails when the 3x3
+// determinant is <= 1e-12 or some active observation has depth <= kZMin at X.
+template <class T>
+__device__ bool triangulate_midpoint(const ProbDev &pd, const double *poses, int k0, int k1,
+                                     double out[3]) {
+  const T *Kall = (const T *)pd.K;
+  const T *uv = (const T *)pd.obs_uv;
+  double A[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // xx, xy, xz, yy, yz, zz
+  double b[3] = {0.0, 0.0, 0.0};
+  for (int k = k0; k < k1; ++k) {
+    if (!pd.obs_act[k]) continue;
+    const int cam = pd.obs_cam[k];
+    const double *P = poses + 12 * cam;
+    const T *K = Kall + 4 * cam;
+    const double a0 = ((double)uv[2 * (size_t)k] - (double)K[2]) / (double)K[0];
+    const double a1 = ((double)uv[2 * (size_t)k + 1] - (double)K[3]) / (double)K[1];
+    double d[3], c[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      d[m] = P[m] * a0 + P[3 + m] * a1 + P[6 + m];
+      c[m] = -(P[m] * P[9] + P[3 + m] * P[10] + P[6 + m] * P[11]);
+    }
+    const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) d[m] *= inv;
+    A[0] += 1.0 - d[0] * d[0];
+    A[1] -= d[0] * d[1];
+    A[2] -= d[0] * d[2];
+    A[3] += 1.0 - d[1] * d[1];
+    A[4] -= d[1] * d[2];
+    A[5] += 1.0 - d[2] * d[2];
+    const double dc = d[0] * c[0] + d[1] * c[1] + d[2] * c[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) b[m] += c[m] - d[m] * dc;
+  }
+  const double c00 = A[3] * A[5] - A[4] * A[4];
+  const double c01 = A[2] * A[4] - A[1] * A[5];
+  const double c02 = A[1] * A[4] - A[2] * A[3];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  if (!(det > 1e-12)) return false;
+  const double c11 = A[0] * A[5] - A[2] * A[2];
+  const double c12 = A[1] * A[2] - A[0] * A[4];
+  const double c22 = A[0] * A[3] - A[1] * A[1];
+  const double id = 1.0 / det;
+  out[0] = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
+  out[1] = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
+  out[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+  for (int k = k0; k < k1; ++k) {
+    if (!pd.obs_act[k]) continue;
+    const double *P = poses + 12 * pd.obs_cam[k];
+    if (!(P[6] * out[0] + P[7] * out[1] + P[8] * out[2] + P[11] > kZMin)) return false;
+  }
+  return true;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cull(const ProbDev *__restrict__ probs,
+                                              const Tile *__restrict__ tiles, double tau2) {
+  static_assert(kPtTile == 256, "one thread per point of a tile");
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const int cur = pd.st->cur;
+  const int j = tl.idx * kPtTile + (int)threadIdx.x;
+  __shared__ double s_red[4];
+  int n_act = 0;
+  if (j < pd.P) {
+    const int k0 = pd.pt_start[j], k1 = pd.pt_start[j + 1];
+    const T *Kall = (const T *)pd.K;
+    const T *uv = (const T *)pd.obs_uv;
+    const double *poses = pd.pose[cur];
+    double *X = pd.X[cur] + 3 * (size_t)j;
+    const double Xj[3] = {X[0], X[1], X[2]};
+    bool lost = false;
+    for (int k = k0; k < k1; ++k) {
+      if (!pd.obs_act[k]) continue;
+      const int cam = pd.obs_cam[k];
+      const T *K = Kall + 4 * cam;
+      double x, y, z;
+      transform(poses + 12 * cam, Xj, x, y, z);
+      bool keep = z > kZMin;
+      if (keep) {
+        const double r0 = (double)K[0] * x / z + (double)K[2] - (double)uv[2 * (size_t)k];
+        const double r1 = (double)K[1] * y / z + (double)K[3] - (double)uv[2 * (size_t)k + 1];
+        keep = r0 * r0 + r1 * r1 <= tau2;
+      }
+      if (keep) {
+        ++n_act;
+      } else {
+        pd.obs_act[k] = 0;
+        lost = true;
+      }
+    }
+    if (lost) {
+      double Xn[3];
+      if (n_act >= 2 && triangulate_midpoint<T>(pd, poses, k0, k1, Xn)) {
+        X[0] = Xn[0];
+        X[1] = Xn[1];
+        X[2] = Xn[2];
+      } else {
+        for (int k = k0; k < k1; ++k) pd.obs_act[k] = 0;
+        n_act = 0;
+      }
+    }
+  }
+  const double ta = block_sum256((double)n_act, s_red);
+  const double tp = block_sum256(n_act > 0 ? 1.0 : 0.0, s_red);
+  if (threadIdx.x == 0) {
+    pd.part_cull[2 * tl.idx] = (int32_t)ta;
+    pd.part_cull[2 * tl.idx + 1] = (int32_t)tp;
   }
 }
 
@@ -2534,6 +2662,16 @@ hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, Kernel
     k_eval<double><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
   else
     k_eval<float><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, hipStream_t s, KernelTimer *timer) {
+  if (!bp.n_pt) return hipSuccess;
+  Timed t(timer, K_CULL, s);
+  if (precision == 0)
+    k_cull<double><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2);
+  else
+    k_cull<float><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct Symbolic {
   std::vector<int32_t> pt_start;
   std::vector<int32_t> pt_order;  // internal point -> caller's point index
   std::vector<int32_t> obs_rpos;  // record of each observation (-1: fixed camera)
+  std::vector<int32_t> obs_order; // internal observation -> caller's observation index
   int32_t Nf = 0;                 // observations in free cameras (records)
   int64_t n_pairs = 0;            // observation pairs of one point in two free cameras
   bool chunked = false;           // point-chunk Schur form (else pair lists)
@@ -58,14 +59,14 @@ struct Symbolic {
 int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
 
 struct Offsets {
-  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos;
+  size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos, obs_act;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
   size_t part_d, part_o, row_tot;
   size_t pp_cam, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
-  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], iter_cost, iter_pcg;
+  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], part_cull, iter_cost, iter_pcg;
   size_t total;
 };
 
@@ -76,6 +77,8 @@ struct DevProblem {
   int32_t C = 0, Cf = 0, P = 0, N = 0;
   int32_t max_tcols = 0;
   std::vector<int32_t> pt_order;  // internal point -> caller's point index
+  std::vector<int32_t> obs_order; // internal observation -> caller's observation index
+  int64_t n_active = 0;           // observations in the problem (after the last culling)
   Offsets off{};
   char *dev = nullptr;
   ProbDev view{};

@@ -344,12 +344,14 @@ def _track_lengths(rng, n, p, n_frames, starts):
 
 
 def make_config1(n_pts: int = 250_000, n_cams: int = 500, seed: int = 1001,
-                 sigma: float = 0.7, name: str | None = None) -> Scene:
+                 sigma: float = 0.7, name: str | None = None, outlier_frac: float = 0.0,
+                 huber_delta: float = 0.0) -> Scene:
     """Sequential drive: cameras 1 m apart along a curve with heading
     0.3 sin(2 pi s / 500) rad, optical axis along the direction of travel; track
     length 1 + Geom(1/7) over consecutive frames (mean 8); points 3-40 m from the
     last frame of their track; drift 0.002 rad and 0.01 m per frame per axis.
-    The default 250k points gives about 2M observations; 200k is the literal count."""
+    The default 250k points gives about 2M observations; 200k is the literal count.
+    outlier_frac > 0 replaces that fraction of the pixels by uniform ones."""
     rng = np.random.default_rng(seed)
     s_idx = np.arange(n_cams, dtype=np.float64)
     R_wc, c = _drive_poses(0.3 * np.sin(2 * np.pi * s_idx / 500.0))
@@ -364,8 +366,8 @@ def make_config1(n_pts: int = 250_000, n_cams: int = 500, seed: int = 1001,
     segs = [(remap[pidx[keep]], starts[keep], L[keep])]
     meta = dict(kind="drive", seed=seed, n_cams=n_cams, n_pts_requested=n_pts,
                 n_pts=int(keep.sum()), mean_track=float(L[keep].mean()))
-    return _drive_scene(name or f"config1_{n_pts}", rng, R_wc, c, segs, X, sigma, 0.0, 0.0,
-                        0.002, 0.01, 0.05, meta)
+    return _drive_scene(name or f"config1_{n_pts}", rng, R_wc, c, segs, X, sigma, outlier_frac,
+                        huber_delta, 0.002, 0.01, 0.05, meta)
 
 
 def make_small_drive(n_cams: int = 40, n_pts: int = 3000, seed: int = 77, sigma: float = 0.7,

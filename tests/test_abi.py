@@ -93,3 +93,24 @@ def test_server_create_validation(balib):
     _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1024, 4))
     _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1 << 30, 0))
     _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1 << 30, 4, precision=9))
+
+
+def test_refine_validation(balib):
+    """ba_refine checks its stage list before the problem handle, so every rule
+    is visible without a device."""
+    L = balib.lib()
+
+    def call(stages, rounds, n=None):
+        st = (balib.RefineStage * max(len(stages), 1))(*[balib.RefineStage(d, t) for d, t in stages])
+        rc = L.ba_refine(None, len(stages) if n is None else n, st, rounds, None)
+        return rc, L.ba_last_error().decode()
+
+    assert call([], 1)[1].startswith("n_stages")
+    assert call([(1.0, 8.0)], 0)[1].startswith("rounds")
+    for bad, needle in [((np.nan, 8.0), "huber_delta"), ((1.0, 0.0), "cull_px"),
+                        ((1.0, -2.0), "cull_px"), ((0.0, np.inf), "cull_px")]:
+        rc, msg = call([(1.0, 8.0), bad], 2)
+        assert rc == balib.BA_EINVAL and "stage 1" in msg and needle in msg, msg
+    rc, msg = call([(1.0, 8.0), (0.0, 3.0)], 2)
+    assert rc == balib.BA_EINVAL and "NULL" in msg
+    assert L.ba_get_active(None, None) == balib.BA_EINVAL
