@@ -176,7 +176,9 @@ int ba_reset(ba_problem *p);
    hist: NULL or n_stages * rounds entries, stage-major.  After the call,
    ba_get_result returns the final state; its report is that of the last solve,
    with n_masked and rms_px evaluated again at the final state over the
-   observations still in the problem. */
+   observations still in the problem.  With profiling on and the "cull" kernel
+   selected, ba_get_kernel_times reports the culling launches of the call (HIP
+   events around each) and, for the other kernels, the last solve's times. */
 typedef struct {
   double huber_delta;     /* the stage's loss: <= 0 none, > 0 Huber threshold in pixels  */
   double cull_px;         /* outlier threshold on ||r_k|| in pixels, > 0                 */

@@ -1291,6 +1291,19 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
   DevProblem &dp = p->dp;
   const double huber0 = dp.huber;
   std::vector<int32_t> cnt(2 * (size_t)dp.view.n_pt_tiles);
+  // the culling launches are timed with their own events when profiling selects them
+  const bool time_cull = p->profiling && (p->timer.mask & (1u << K_CULL)) != 0;
+  hipEvent_t c0 = nullptr, c1 = nullptr;
+  if (time_cull) {
+    hipError_t e = hipEventCreate(&c0);
+    if (e == hipSuccess) e = hipEventCreate(&c1);
+    if (e != hipSuccess) {
+      if (c0) (void)hipEventDestroy(c0);
+      return hip_fail(e, "event");
+    }
+  }
+  double cull_ms = 0.0;
+  int32_t n_cull = 0;
   int rc = BA_OK;
   for (int si = 0; si < n_stages && rc == BA_OK; ++si) {
     dp.huber = stages[si].huber_delta > 0.0 ? stages[si].huber_delta : 0.0;
@@ -1298,13 +1311,21 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
       rc = ba_solve(p);
       if (rc != BA_OK) break;
       const double tau = stages[si].cull_px;
+      if (time_cull) (void)hipEventRecord(c0, p->stream);
       hipError_t e = launch_cull(dp.precision, p->batch.plan, tau * tau, p->stream, nullptr);
+      if (time_cull) (void)hipEventRecord(c1, p->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(cnt.data(), dp.view.part_cull, cnt.size() * 4, hipMemcpyDeviceToHost, p->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
       if (e != hipSuccess) {
         rc = hip_fail(e, "culling");
         break;
+      }
+      if (time_cull) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, c0, c1);
+        cull_ms += ms;
+        ++n_cull;
       }
       int64_t na = 0, np = 0;
       for (size_t i = 0; i < cnt.size(); i += 2) {
@@ -1326,6 +1347,12 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
     }
   }
   dp.huber = huber0;
+  if (time_cull) {
+    (void)hipEventDestroy(c0);
+    (void)hipEventDestroy(c1);
+    p->kernel_ms[K_CULL] = cull_ms;
+    p->kernel_launches[K_CULL] = n_cull;
+  }
   if (rc != BA_OK) return rc;
   // the report's rms and masked count describe the final state and mask
   hipError_t e = launch_eval(dp.precision, p->batch.plan, p->stream, nullptr);
