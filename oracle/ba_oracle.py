@@ -18,6 +18,13 @@ What it computes (paper: Sec. 4.3, Iterative Triangulation and Mapping):
   e_c = ||T_i T_{i+k}^-1 - T_i,init T_{i+k,init}^-1||^2 (Eq. seq), read as squared
   Frobenius norms of the 3x4 upper parts, weighted by lambda_a and lambda_c and
   entering C with the same factor 1/2 as the reprojection term;
+* pose-graph optimisation (Sec. 4.2): nodes are poses, edges (i, j) carry a
+  measured relative pose M_ij and the error T_i T_j^-1 - M_ij, the form of the
+  sequential and extrinsic constraints (Eq. seq, Eq. extrinsic) that loop-closure
+  edges share; the objective sum e^T Omega e with Omega diagonal, one weight for
+  the nine rotation entries and one for the three translation entries.  It is the
+  same machinery as the sequential prior with explicit pairs, measurements and
+  weights, and no observations (``pose_graph_problem``);
 * Levenberg-Marquardt with Marquardt diagonal scaling and Nielsen's damping
   schedule (Madsen, Nielsen, Tingleff 2004, Sec. 3.2), left SE(3) increments;
 * three solvers of the damped normal equations (H + lambda D) delta = -g:
@@ -197,6 +204,10 @@ class Problem:
     R0: np.ndarray | None = None  # T_init: the initial poses
     t0: np.ndarray | None = None
     active: np.ndarray | None = None  # (N,) bool: observations kept by the culling step
+    # explicit pose-graph edges (Sec. 4.2); when given they replace the sequential pairs
+    pairs: np.ndarray | None = None      # (E, 2) node indices (i, j): error T_i T_j^-1 - M_ij
+    pair_meas: np.ndarray | None = None  # (E, 12) M_ij as [R | t] rows, R first
+    pair_w: np.ndarray | None = None     # (E, 2) weights of the rotation and translation entries
 
     def __post_init__(self):
         if self.R0 is None:
@@ -251,7 +262,7 @@ def cost_and_masked(p: Problem, R=None, t=None, X=None):
     r, valid, _ = residuals(p, R, t, X)
     s = np.sum(r * r, axis=1)
     C = 0.5 * float(np.sum(huber_rho(s, p.delta)[valid & p.active]))
-    if p.prior_abs > 0 or p.prior_seq > 0:
+    if has_priors(p):
         C += prior_cost(p, R, t)
     return C, int((~valid).sum())
 
@@ -265,30 +276,53 @@ def _pose_rows(R: np.ndarray, t: np.ndarray) -> np.ndarray:
 
 
 def prior_pairs(p: Problem):
-    """Sequential constraint pairs (i, i + k), k = 1..seq_k, in camera order."""
+    """The relative-pose pairs: the explicit pose-graph edges when given, else the
+    sequential constraint pairs (i, i + k), k = 1..seq_k, in camera order."""
+    if p.pairs is not None:
+        return [(int(i), int(j)) for i, j in p.pairs]
     C = p.n_cams
     return [(i, i + k) for i in range(C) for k in range(1, p.seq_k + 1) if i + k < C]
 
 
+def has_priors(p: Problem) -> bool:
+    return p.prior_abs > 0 or p.prior_seq > 0 or (p.pairs is not None and len(p.pairs) > 0)
+
+
+def pair_row_weights(p: Problem) -> np.ndarray:
+    """(n_pairs, 12) weight of each residual entry: the edge's rotation weight on the
+    nine R entries and its translation weight on the three t entries; lambda_c on
+    all twelve for the sequential prior."""
+    n = len(prior_pairs(p))
+    if p.pairs is not None:
+        w = np.asarray(p.pair_w, np.float64).reshape(n, 2)
+        return np.concatenate([np.repeat(w[:, :1], 9, axis=1), np.repeat(w[:, 1:], 3, axis=1)], axis=1)
+    return np.full((n, 12), p.prior_seq)
+
+
 def prior_residuals(p: Problem, R=None, t=None):
     """Residual 12-vectors of the prior terms: r_a,i = [R_i - R0_i | t_i - t0_i] for every
-    camera (Eq. abs), and r_c,(i,j) = A - A0 with A = T_i T_j^-1 = [R_i R_j^T | t_i - R_i R_j^T t_j]
-    and A0 the same from the initial poses, for every sequential pair (Eq. seq)."""
+    camera (Eq. abs), and r_c,(i,j) = A - M_ij with A = T_i T_j^-1 = [R_i R_j^T | t_i - R_i R_j^T t_j]
+    for every pair (Eq. seq): M_ij is the edge's measurement for explicit edges, and
+    for sequential pairs A of the initial poses."""
     R = p.R if R is None else R
     t = p.t if t is None else t
     ra = np.stack([_pose_rows(R[i], t[i]) - _pose_rows(p.R0[i], p.t0[i]) for i in range(p.n_cams)])
     rc = []
-    for i, j in prior_pairs(p):
+    for x, (i, j) in enumerate(prior_pairs(p)):
         RA = R[i] @ R[j].T
-        RA0 = p.R0[i] @ p.R0[j].T
-        rc.append(_pose_rows(RA, t[i] - RA @ t[j]) - _pose_rows(RA0, p.t0[i] - RA0 @ p.t0[j]))
+        if p.pairs is not None:
+            M = np.asarray(p.pair_meas[x], np.float64)
+        else:
+            RA0 = p.R0[i] @ p.R0[j].T
+            M = _pose_rows(RA0, p.t0[i] - RA0 @ p.t0[j])
+        rc.append(_pose_rows(RA, t[i] - RA @ t[j]) - M)
     return ra, np.array(rc).reshape(-1, 12)
 
 
 def prior_cost(p: Problem, R=None, t=None) -> float:
-    """1/2 (lambda_a sum_i ||r_a,i||^2 + lambda_c sum_pairs ||r_c||^2)."""
+    """1/2 (lambda_a sum_i ||r_a,i||^2 + sum_pairs sum_q w_q r_c,q^2)."""
     ra, rc = prior_residuals(p, R, t)
-    return 0.5 * (p.prior_abs * float(np.sum(ra * ra)) + p.prior_seq * float(np.sum(rc * rc)))
+    return 0.5 * (p.prior_abs * float(np.sum(ra * ra)) + float(np.sum(pair_row_weights(p) * rc * rc)))
 
 
 def _rows_of_left_increment(R: np.ndarray, t: np.ndarray) -> np.ndarray:
@@ -338,7 +372,8 @@ def prior_system(p: Problem, n: int):
     Ja, Jci, Jcj = prior_jacobians(p)
     rows, cols, vals, rhs = [], [], [], []
     row = 0
-    sa, sc = math.sqrt(p.prior_abs), math.sqrt(p.prior_seq)
+    sa = math.sqrt(p.prior_abs)
+    sw = np.sqrt(pair_row_weights(p))
     if p.prior_abs > 0:
         for i in range(p.n_cams):
             if fidx[i] >= 0:
@@ -349,19 +384,18 @@ def prior_system(p: Problem, n: int):
                         vals.append(sa * Ja[i, q, m])
                 rhs.append(sa * ra[i])
                 row += 12
-    if p.prior_seq > 0:
-        for x, (i, j) in enumerate(prior_pairs(p)):
-            if fidx[i] < 0 and fidx[j] < 0:
-                continue
-            for cam, Jx in ((i, Jci[x]), (j, Jcj[x])):
-                if fidx[cam] >= 0:
-                    for q in range(12):
-                        for m in range(6):
-                            rows.append(row + q)
-                            cols.append(6 * fidx[cam] + m)
-                            vals.append(sc * Jx[q, m])
-            rhs.append(sc * rc[x])
-            row += 12
+    for x, (i, j) in enumerate(prior_pairs(p)):
+        if fidx[i] < 0 and fidx[j] < 0:
+            continue
+        for cam, Jx in ((i, Jci[x]), (j, Jcj[x])):
+            if fidx[cam] >= 0:
+                for q in range(12):
+                    for m in range(6):
+                        rows.append(row + q)
+                        cols.append(6 * fidx[cam] + m)
+                        vals.append(sw[x, q] * Jx[q, m])
+        rhs.append(sw[x] * rc[x])
+        row += 12
     Jp = sp.csr_matrix((np.array(vals), (np.array(rows, np.int64), np.array(cols, np.int64))), shape=(row, n))
     return Jp, (np.concatenate(rhs) if rhs else np.zeros(0))
 
@@ -456,7 +490,7 @@ def normal_equations(p: Problem):
     Wd = sp.diags(np.repeat(w, 2))
     H = (J.T @ Wd @ J).tocsr()
     g = J.T @ (np.repeat(w, 2) * r.reshape(-1))
-    if p.prior_abs > 0 or p.prior_seq > 0:
+    if has_priors(p):
         Jp, rp = prior_system(p, n)
         H = (H + Jp.T @ Jp).tocsr()
         g = g + Jp.T @ rp
@@ -791,3 +825,26 @@ def refine(p: Problem, stages, rounds: int, opts: LMOptions):
             n_act, n_pts = cull_and_triangulate(p, tau)
             hist.append((si, rd, res.iter_cost[-1], n_act, n_pts))
     return p, hist
+
+
+# ----------------------------------------------------------------------------- pose graph
+
+def pose_graph_problem(R0, t0, fixed, edges, meas_R, meas_t, w_rot, w_trans, prior_abs: float = 0.0):
+    """A pose graph (Sec. 4.2) as a Problem with no observations: nodes with initial
+    world->camera poses (R0, t0), hard-fixed nodes, and edges (i, j) with measured
+    relative poses M_ij = (meas_R, meas_t) of A_ij = T_i T_j^-1 and per-edge weights of
+    the rotation and translation entries, so that
+    C = 1/2 sum_e (w_rot ||R_A - R_M||_F^2 + w_trans ||t_A - t_M||^2)
+        + 1/2 prior_abs sum_i ||T_i - T_i,init||^2.
+    Sequential, loop-closure and extrinsic edges differ only in where M comes from."""
+    R0 = np.asarray(R0, np.float64)
+    C = R0.shape[0]
+    edges = np.asarray(edges, np.int64).reshape(-1, 2)
+    meas = np.concatenate([np.asarray(meas_R, np.float64).reshape(-1, 9),
+                           np.asarray(meas_t, np.float64).reshape(-1, 3)], axis=1)
+    w = np.stack([np.broadcast_to(np.asarray(w_rot, np.float64), edges.shape[0]),
+                  np.broadcast_to(np.asarray(w_trans, np.float64), edges.shape[0])], axis=1)
+    return Problem(K=np.ones((C, 4)), R=R0.copy(), t=np.array(t0, np.float64), X=np.zeros((0, 3)),
+                   cam=np.zeros(0, np.int64), pt=np.zeros(0, np.int64), uv=np.zeros((0, 2)),
+                   fixed=np.asarray(fixed).astype(bool), delta=0.0, prior_abs=float(prior_abs),
+                   pairs=edges, pair_meas=meas, pair_w=w)

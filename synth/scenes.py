@@ -494,3 +494,170 @@ def load_scene(path: str) -> Scene:
                  obs_pt=z["obs_pt"], obs_uv=z["obs_uv"], cam_fixed=z["cam_fixed"],
                  outlier=z["outlier"], huber_delta=float(z["huber_delta"]),
                  sigma=float(z["sigma"]), meta={})
+
+
+# ----------------------------------------------------------------------------- pose graphs
+
+@dataclasses.dataclass
+class PoseGraph:
+    """A pose graph: nodes with ground-truth and initial world->node poses, hard-fixed
+    nodes, and edges (i, j) with a measured relative pose of T_i T_j^-1 and the
+    weights of its rotation and translation entries."""
+    name: str
+    q_gt: np.ndarray      # (n, 4) ground-truth world->node rotation (w, x, y, z)
+    t_gt: np.ndarray      # (n, 3)
+    q0: np.ndarray        # (n, 4) initial poses (integrated noisy odometry)
+    t0: np.ndarray        # (n, 3)
+    fixed: np.ndarray     # (n,) uint8
+    edge_i: np.ndarray    # (E,) int32
+    edge_j: np.ndarray    # (E,) int32
+    meas_q: np.ndarray    # (E, 4) measured relative rotation
+    meas_t: np.ndarray    # (E, 3) measured relative translation
+    w_rot: np.ndarray     # (E,)
+    w_trans: np.ndarray   # (E,)
+    edge_type: np.ndarray  # (E,) int32: 0 sequential, 1 loop closure, 2 extrinsic
+    meta: dict
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.q0.shape[0])
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.edge_i.shape[0])
+
+
+EDGE_SEQUENTIAL, EDGE_LOOP, EDGE_EXTRINSIC = 0, 1, 2
+
+
+def _rig_extrinsics(n_rig: int):
+    """Vehicle->camera transforms of a rig: camera c yawed by c * 60 degrees
+    (alternating sides) about the vehicle's down axis, mounted 0.5 m from the
+    vehicle origin along its optical axis."""
+    yaws = [0.0] + [s * (60.0 * ((c + 1) // 2)) for c, s in zip(range(n_rig - 1), [1, -1] * n_rig)]
+    out = []
+    for yaw in yaws:
+        Ry = Rotation.from_euler("y", yaw, degrees=True)  # camera axes in the vehicle frame
+        p = Ry.apply(np.array([0.0, 0.0, 0.5]))
+        R_e = Ry.inv()
+        out.append((R_e, -R_e.apply(p)))
+    return out
+
+
+def make_pose_graph(n_frames: int = 1500, laps: int = 2, n_rig: int = 3, mode: str = "camera",
+                    seq_k: int = 2, loop_every: int = 2, odo_rot: float = 1e-3, odo_trans: float = 1e-2,
+                    loop_rot: float = 1e-3, loop_trans: float = 2e-2, weight_scale: float = 1e-4,
+                    seed: int = 1005, noiseless: bool = False, name: str | None = None) -> PoseGraph:
+    """Pose graph of a vehicle with an ``n_rig``-camera rig driving a circular loop of
+    ``n_frames`` frames (1 m apart) ``laps`` times, each lap 1 m inside the previous one.
+
+    Nodes: one per camera and frame (``mode="camera"``) or one per frame with the
+    vehicle pose (``mode="rig"``).  The initial trajectory integrates odometry whose
+    per-frame relative motions carry Gaussian noise (odo_rot rad, odo_trans m per
+    axis, as a left perturbation).  Edges:
+      - sequential: node pairs of frames f, f + k (k = 1..seq_k, same camera), measured
+        from the initial trajectory;
+      - loop closure: every ``loop_every``-th frame of laps 2.. with the frame at the same
+        angle one lap earlier (front camera, or vehicle in rig mode), measured as the
+        true relative pose with noise (loop_rot, loop_trans);
+      - extrinsic (camera mode): the front camera with each other camera of the same
+        frame, measured by the exact rig calibration.
+    Weights are weight_scale / sigma^2 of each entry group; extrinsic edges get 100
+    times the sequential ones.  Node 0 is fixed.  Pose compositions here only
+    synthesise measurements (scipy Rotation); no solver arithmetic lives here."""
+    rng = np.random.default_rng(seed)
+    T = n_frames * laps
+    f = np.arange(T)
+    h = 2 * np.pi * (f % n_frames) / n_frames
+    radius = n_frames / (2 * np.pi)
+    lap = f // n_frames
+    c = np.stack([radius * (1 - np.cos(h)), np.zeros(T), radius * np.sin(h)], axis=1)
+    c = c + lap[:, None] * np.stack([np.cos(h), np.zeros(T), -np.sin(h)], axis=1)
+    fwd = np.stack([np.sin(h), np.zeros(T), np.cos(h)], axis=1)
+    R_wv = _cam_to_world_look(fwd)              # vehicle-to-world rotation per frame
+    Rv = Rotation.from_matrix(np.transpose(R_wv, (0, 2, 1)))  # world->vehicle
+    tv = -Rv.apply(c)
+    # noisy odometry: D_f = T_{f+1} T_f^-1 perturbed on the left, integrated from frame 0
+    Rd = Rv[1:] * Rv[:-1].inv()
+    td = tv[1:] - Rd.apply(tv[:-1])
+    if noiseless:
+        nr, nt = np.zeros((T - 1, 3)), np.zeros((T - 1, 3))
+    else:
+        nr, nt = rng.normal(0.0, odo_rot, (T - 1, 3)), rng.normal(0.0, odo_trans, (T - 1, 3))
+    En = Rotation.from_rotvec(nr)
+    Rd_n = En * Rd
+    td_n = En.apply(td) + nt
+    R0 = [Rv[0]]
+    t0 = [tv[0]]
+    for k in range(T - 1):
+        R0.append(Rd_n[k] * R0[-1])
+        t0.append(Rd_n[k].apply(t0[-1]) + td_n[k])
+    R0 = Rotation.concatenate(R0)
+    t0 = np.array(t0)
+    ext = _rig_extrinsics(n_rig) if mode == "camera" else [(Rotation.identity(), np.zeros(3))]
+    nc = len(ext)
+
+    def node_pose(Rw, tw, cam):
+        Re, te = ext[cam]
+        return Re * Rw, Re.apply(tw) + te
+
+    def node(fr, cam):
+        return fr * nc + cam
+
+    gt = [node_pose(Rv[fr], tv[fr], cam) for fr in range(T) for cam in range(nc)]
+    ini = [node_pose(R0[fr], t0[fr], cam) for fr in range(T) for cam in range(nc)]
+    R_gt = Rotation.concatenate([g[0] for g in gt])
+    t_gt = np.array([g[1] for g in gt])
+    R_in = Rotation.concatenate([g[0] for g in ini])
+    t_in = np.array([g[1] for g in ini])
+
+    def rel(Ra, ta, Rb, tb):  # A = T_a T_b^-1
+        RA = Ra * Rb.inv()
+        return RA, ta - RA.apply(tb)
+
+    ei, ej, mq, mt, wr, wt, ty = [], [], [], [], [], [], []
+
+    def add(i, j, RA, tA, w_r, w_t, typ):
+        ei.append(i)
+        ej.append(j)
+        mq.append(RA.as_quat()[[3, 0, 1, 2]])
+        mt.append(tA)
+        wr.append(w_r)
+        wt.append(w_t)
+        ty.append(typ)
+
+    ws_r, ws_t = weight_scale / odo_rot ** 2, weight_scale / odo_trans ** 2
+    for fr in range(T):
+        for k in range(1, seq_k + 1):
+            if fr + k >= T:
+                continue
+            for cam in range(nc):
+                a, b = node(fr, cam), node(fr + k, cam)
+                RA, tA = rel(R_in[a], t_in[a], R_in[b], t_in[b])
+                add(a, b, RA, tA, ws_r, ws_t, EDGE_SEQUENTIAL)
+    for fr in range(n_frames, T):
+        if (fr - n_frames) % loop_every:
+            continue
+        a, b = node(fr, 0), node(fr - n_frames, 0)
+        RA, tA = rel(R_gt[a], t_gt[a], R_gt[b], t_gt[b])
+        if not noiseless:
+            E = Rotation.from_rotvec(rng.normal(0.0, loop_rot, 3))
+            RA, tA = E * RA, E.apply(tA) + rng.normal(0.0, loop_trans, 3)
+        add(a, b, RA, tA, weight_scale / loop_rot ** 2, weight_scale / loop_trans ** 2, EDGE_LOOP)
+    if nc > 1:
+        for fr in range(T):
+            for cam in range(1, nc):
+                a, b = node(fr, 0), node(fr, cam)
+                RA, tA = rel(ext[0][0], ext[0][1], ext[cam][0], ext[cam][1])
+                add(a, b, RA, tA, 100 * ws_r, 100 * ws_t, EDGE_EXTRINSIC)
+    n = T * nc
+    fixed = np.zeros(n, np.uint8)
+    fixed[0] = 1
+    q_gt = R_gt.as_quat()[:, [3, 0, 1, 2]]
+    q0 = R_in.as_quat()[:, [3, 0, 1, 2]]
+    meta = dict(kind="pose_graph", mode=mode, n_frames=n_frames, laps=laps, n_rig=n_rig, seq_k=seq_k,
+                seed=seed, n_nodes=n, n_edges=len(ei))
+    return PoseGraph(name=name or f"pose_graph_{mode}_{T}x{nc}", q_gt=q_gt, t_gt=t_gt, q0=q0, t0=t_in,
+                     fixed=fixed, edge_i=np.array(ei, np.int32), edge_j=np.array(ej, np.int32),
+                     meas_q=np.array(mq), meas_t=np.array(mt), w_rot=np.array(wr), w_trans=np.array(wt),
+                     edge_type=np.array(ty, np.int32), meta=meta)

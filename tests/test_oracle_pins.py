@@ -510,3 +510,98 @@ def test_two_stage_refine_removes_planted_outliers_and_reaches_noise_level():
     expected = s.sigma * math.sqrt((2 * n - d) / n)
     assert abs(O.rms(q) - expected) <= 0.05 * expected
     assert hist[-1][3] == n and hist[-1][4] == pts
+
+
+# ----------------------------------------------------------------------------- pose graphs
+
+def _graph_problem(g, R0=None, t0=None, prior_abs=0.0):
+    return O.pose_graph_problem(O.quat_to_rot(g.q0) if R0 is None else R0, g.t0 if t0 is None else t0,
+                                g.fixed, np.stack([g.edge_i, g.edge_j], axis=1), O.quat_to_rot(g.meas_q),
+                                g.meas_t, g.w_rot, g.w_trans, prior_abs=prior_abs)
+
+
+@pytest.mark.parametrize("mode", ["camera", "rig"])
+def test_pose_graph_noiseless_measurements_recover_truth(mode):
+    """Measurements that agree with the true poses, a perturbed start (0.05 rad, 0.3 m
+    per node, node 0 fixed): LM reaches zero cost and the true poses."""
+    from synth import make_pose_graph
+    g = make_pose_graph(12, mode=mode, noiseless=True)
+    rng = np.random.default_rng(3)
+    Rg, tg = O.quat_to_rot(g.q_gt), np.array(g.t_gt)
+    dR = Rotation.from_rotvec(rng.normal(0, 0.05, (g.n_nodes, 3))).as_matrix()
+    R0 = dR @ Rg
+    t0 = tg + rng.normal(0, 0.3, tg.shape)
+    R0[0], t0[0] = Rg[0], tg[0]
+    p = _graph_problem(g, R0, t0)
+    r = O.lm_dense(p, O.LMOptions(max_iters=25))
+    assert r.iter_cost[-1] <= 1e-18 * r.iter_cost[0]
+    assert np.max(np.abs(r.R - Rg)) <= 1e-8 and np.max(np.abs(r.t - tg)) <= 1e-7
+
+
+def test_pose_graph_gradient_matches_central_differences():
+    """g = J^T W r of the edge terms (reversed edges i > j, unequal rotation and
+    translation weights, an absolute prior) against central differences of C over
+    left increments of every free node."""
+    from synth import make_pose_graph
+    g = make_pose_graph(6, seq_k=2)
+    flip = np.arange(g.n_edges) % 3 == 0
+    ei, ej = np.where(flip, g.edge_j, g.edge_i), np.where(flip, g.edge_i, g.edge_j)
+    rng = np.random.default_rng(4)
+    p = O.pose_graph_problem(O.quat_to_rot(g.q0), g.t0, g.fixed, np.stack([ei, ej], axis=1),
+                             Rotation.random(g.n_edges, random_state=5).as_matrix(),
+                             rng.normal(0, 1, (g.n_edges, 3)), rng.uniform(0.5, 3, g.n_edges),
+                             rng.uniform(0.1, 2, g.n_edges), prior_abs=0.7)
+    _, grad, _, _, _ = O.normal_equations(p)
+    free = np.nonzero(~p.fixed)[0]
+    h = 1e-6
+    fd = np.zeros_like(grad)
+    for a, cam in enumerate(free):
+        for m in range(6):
+            xi = np.zeros(6)
+            xi[m] = h
+            cs = []
+            for sgn in (1, -1):
+                dR, dt = O.se3_exp(sgn * xi)
+                R, t = p.R.copy(), p.t.copy()
+                R[cam] = dR @ p.R[cam]
+                t[cam] = dR @ p.t[cam] + dt
+                cs.append(O.prior_cost(p, R, t))
+            fd[6 * a + m] = (cs[0] - cs[1]) / (2 * h)
+    assert np.max(np.abs(fd - grad)) <= 1e-6 * (1 + np.max(np.abs(grad)))
+
+
+def test_pose_graph_optimum_matches_scipy_least_squares():
+    """A noisy camera-mode graph with loop closures: the cost LM reaches equals the
+    minimum SciPy least_squares finds over rotation vectors and translations."""
+    from synth import make_pose_graph
+    g = make_pose_graph(10, seq_k=2, loop_every=2)
+    p = _graph_problem(g)
+    r = O.lm_dense(p, O.LMOptions(max_iters=40))
+    free = np.nonzero(~p.fixed)[0]
+    sw = np.sqrt(O.pair_row_weights(p))
+
+    def f(x):
+        R, t = p.R.copy(), p.t.copy()
+        R[free] = Rotation.from_rotvec(x[:3 * free.size].reshape(-1, 3)).as_matrix()
+        t[free] = x[3 * free.size:].reshape(-1, 3)
+        _, rc = O.prior_residuals(p, R, t)
+        return (sw * rc).reshape(-1)
+
+    x0 = np.concatenate([Rotation.from_matrix(p.R[free]).as_rotvec().reshape(-1), p.t[free].reshape(-1)])
+    ref = scipy.optimize.least_squares(f, x0, xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    c_ref = 0.5 * float(ref.fun @ ref.fun)
+    assert abs(r.iter_cost[-1] - c_ref) <= 1e-9 * c_ref
+    assert r.iter_cost[-1] < r.iter_cost[0]
+
+
+def test_pose_graph_cost_is_invariant_to_the_world_frame():
+    """T_i -> T_i G for every node leaves every T_i T_j^-1, hence the edge cost, unchanged."""
+    from synth import make_pose_graph
+    g = make_pose_graph(8)
+    p = _graph_problem(g)
+    G = Rotation.from_rotvec([0.3, -0.2, 0.5]).as_matrix()
+    tau = np.array([2.0, -1.0, 4.0])
+    R2 = p.R @ G
+    t2 = p.t + np.einsum("nij,j->ni", p.R, tau)
+    c1, c2 = O.prior_cost(p), O.prior_cost(p, R2, t2)
+    assert abs(c1 - c2) <= 1e-10 * c1
