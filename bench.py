@@ -116,6 +116,48 @@ def refine_leg(ba, precision: str, n_pts: int, flags: int = 0, reps: int = 3) ->
                      "share_of_refine": round(cull_ms / 1000.0 / wall, 5)}}
 
 
+def pose_graph_leg(ba, precision: str, n_frames: int, flags: int = 0, steps: int = 10) -> dict:
+    """Pose-graph optimisation of a 3-camera rig driving a circular loop twice
+    (camera-frame nodes; sequential k = 1, 2, loop-closure and extrinsic edges): 10 LM
+    iterations with PCG 50 / 1e-6 per solve, inputs resident in HBM (ba_reset +
+    ba_solve), `steps` timed solves; then one solve with the PCG step timed by HIP events."""
+    import numpy as np
+    from synth import make_pose_graph
+    print("bench: generating the pose graph", flush=True, file=sys.stderr)
+    g = make_pose_graph(n_frames)
+    p = ba.Problem.from_pose_graph(g, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
+                                   precision=precision, flags=flags)
+    info = p.info()
+    p.reset().solve()  # warm-up (graph capture)
+    walls, dev = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        p.reset().solve()
+        walls.append(time.perf_counter() - t0)
+        dev.append(p.report()["solve_ms"])
+    rep = p.report()
+    names = list(p.kernel_times().keys())
+    p.set_profiling(1 << names.index("pcg_cg"))
+    p.reset().solve()
+    cg_ms, cg_n = p.kernel_times()["pcg_cg"]
+    p.set_profiling(0)
+    p.close()
+    wall = float(np.median(walls))
+    cg_s = cg_ms / 1000.0 / max(cg_n, 1)
+    abytes = algorithmic_bytes("pcg_cg", info, precision)
+    return {"workload": f"pose graph: {g.meta['n_frames'] * g.meta['laps']} frames x 3 cameras = "
+                        f"{info['n_cams']} nodes (1 fixed), {g.n_edges} edges "
+                        f"(sequential k = 1, 2; loop closures; extrinsic)",
+            "lm_iters": LM_ITERS, "ms_per_solve": round(1000 * wall, 3),
+            "device_ms_per_solve": round(float(np.median(dev)), 3),
+            "lm_iters_per_s": round(LM_ITERS / wall, 2), "edges_per_s": round(g.n_edges * LM_ITERS / wall, 1),
+            "nnzb": info["nnzb"], "cost0": rep["cost0"], "cost": rep["cost"],
+            "pcg_iters": [int(x) for x in rep["pcg_iters"]],
+            "pcg_cg": {"avg_launch_us": round(cg_s * 1e6, 2), "algorithmic_bytes": abytes,
+                       "achieved_gbs": round(abytes / cg_s / 1e9, 1),
+                       "frac_of_hbm_peak": round(abytes / cg_s / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def cpu_baseline(budget_s: float = 30.0) -> dict:
     """The FP64 oracle (explicit Schur complement + block-Jacobi PCG, the same
     schedule) timed on one host core for one LM iteration of the same scene."""
@@ -231,6 +273,8 @@ def main():
     ap.add_argument("--prior-seq", type=float, default=0.0,
                     help="weight of the sequential pose prior between frames i and i+k (0: off)")
     ap.add_argument("--prior-seq-k", type=int, default=1)
+    ap.add_argument("--no-pose-graph", action="store_true",
+                    help="skip the pose-graph leg (9000 nodes, 24.7k edges)")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the iterative-refinement leg (outlier drive, two stages)")
     ap.add_argument("--profile-all", action="store_true",
@@ -356,6 +400,8 @@ def main():
     if not args.no_refine and args.workload == "drive":
         out["refine"] = refine_leg(ba, args.precision, args.points or 250_000,
                                    ba.FLAG_NO_GRAPH if args.no_graph else 0)
+    if not args.no_pose_graph and args.workload == "drive":
+        out["pose_graph"] = pose_graph_leg(ba, args.precision, 1500, ba.FLAG_NO_GRAPH if args.no_graph else 0)
     if args.serving >= 0:
         print("bench: serving streams", flush=True, file=sys.stderr)
         out["serving"] = serving_leg(ba, args.serving, args.precision)

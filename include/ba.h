@@ -230,6 +230,47 @@ int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride);
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
                         double *ms, int32_t *launches, int32_t *n_out);
 
+/* ---------------------------------------------------------------- pose graphs
+   Pose-graph optimisation (paper Sec. 4.2): nodes are poses, edges carry a measured
+   relative pose.  Sequential constraints (Eq. seq), loop-closure constraints and
+   extrinsic constraints between the cameras of one rig (Eq. extrinsic) all have the
+   error e = T_i T_j^-1 - M_ij over the 3x4 upper parts, and the objective
+   sum_e e^T Omega_e e is read with Omega_e diagonal: w_rot on the nine rotation
+   entries, w_trans on the three translation entries, with the factor 1/2 of C.
+   A node is a camera (camera-frame mode) or a vehicle rig (vehicle-rig mode, where
+   the rig's cameras follow from fixed extrinsics and extrinsic edges do not arise);
+   the solver does not distinguish them.  The problem runs through the same
+   Levenberg-Marquardt iteration, reduced-system assembly and block-Jacobi PCG as
+   bundle adjustment, with no points: ba_solve, ba_solve_async / ba_wait, ba_reset,
+   ba_get_result (points_out ignored; n_masked and rms_px are 0), ba_get_info,
+   profiling and ba_destroy apply; ba_refine does not (BA_EINVAL).
+   Options: max_iters, pcg_*, lambda0, precision and flags as for BA; prior_abs > 0
+   adds the absolute prior on every node (anchored at the given poses); huber_delta
+   must be <= 0 and prior_seq 0.
+   BA_EINVAL: fewer than 2 nodes or 1 edge, a node index out of range, an edge from a
+   node to itself, two edges between the same two nodes (either direction), a bad
+   quaternion (node pose or measurement), weights not finite and >= 0 or both 0,
+   every node fixed, or bad options. */
+#define BA_EDGE_SEQUENTIAL 0
+#define BA_EDGE_LOOP 1
+#define BA_EDGE_EXTRINSIC 2
+typedef struct {
+  int32_t i, j;           /* nodes: the edge measures A_ij = T_i T_j^-1                   */
+  int32_t type;           /* BA_EDGE_*: where the measurement came from (not used)        */
+  int32_t reserved;
+  ba_pose meas;           /* measured A_ij as (quaternion, t) of [R | t]                 */
+  double w_rot, w_trans;  /* weights of the rotation and translation entries             */
+} ba_pose_edge;
+typedef struct {                 /* host memory                                          */
+  int32_t n_nodes;
+  const ba_pose *poses;          /* n_nodes initial poses (world -> node)               */
+  const uint8_t *node_fixed;     /* n_nodes flags (1 = held fixed), or NULL              */
+  int64_t n_edges;
+  const ba_pose_edge *edges;
+} ba_pose_graph_desc;
+int ba_pose_graph_create(const ba_pose_graph_desc *g, const ba_options *opt, void *hip_stream,
+                         ba_problem **out);
+
 /* ---------------------------------------------------------------- pose-only */
 typedef struct {                 /* one localization request (host memory)             */
   ba_intrinsics K;

@@ -67,6 +67,16 @@ class ProblemInfo(C.Structure):
                 ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64)]
 
 
+class PoseEdge(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("type", C.c_int32), ("reserved", C.c_int32),
+                ("meas", Pose), ("w_rot", C.c_double), ("w_trans", C.c_double)]
+
+
+class PoseGraphDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("poses", C.c_void_p), ("node_fixed", C.c_void_p),
+                ("n_edges", C.c_int64), ("edges", C.c_void_p)]
+
+
 class RefineStage(C.Structure):
     _fields_ = [("huber_delta", C.c_double), ("cull_px", C.c_double)]
 
@@ -84,6 +94,8 @@ class ServerStats(C.Structure):
 
 
 OBS_DTYPE = np.dtype([("cam", "<i4"), ("pt", "<i4"), ("u", "<f8"), ("v", "<f8")])
+EDGE_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("type", "<i4"), ("reserved", "<i4"),
+                       ("q", "<f8", (4,)), ("t", "<f8", (3,)), ("w_rot", "<f8"), ("w_trans", "<f8")])
 
 _lib = None
 
@@ -109,6 +121,7 @@ def lib():
     L.ba_get_result.argtypes = [vp, vp, vp, C.POINTER(Report)]
     L.ba_get_info.argtypes = [vp, C.POINTER(ProblemInfo)]
     L.ba_refine.argtypes = [vp, i32, C.POINTER(RefineStage), i32, C.POINTER(RefineRound)]
+    L.ba_pose_graph_create.argtypes = [C.POINTER(PoseGraphDesc), C.POINTER(Options), vp, C.POINTER(vp)]
     L.ba_get_active.argtypes = [vp, vp]
     L.ba_problem_bytes.argtypes = [vp]
     L.ba_problem_bytes.restype = i64
@@ -193,6 +206,35 @@ class _Desc:
         self.desc = d
 
 
+class _GraphDesc:
+    """Holds the contiguous host arrays a PoseGraphDesc points to."""
+
+    def __init__(self, q, t, edge_i, edge_j, meas_q, meas_t, w_rot, w_trans, fixed=None, edge_type=None):
+        self.poses = np.ascontiguousarray(np.concatenate([np.asarray(q, np.float64),
+                                                          np.asarray(t, np.float64)], axis=1))
+        n = len(edge_i)
+        e = np.zeros(n, EDGE_DTYPE)
+        e["i"], e["j"] = edge_i, edge_j
+        e["type"] = 0 if edge_type is None else edge_type
+        e["q"], e["t"] = meas_q, meas_t
+        e["w_rot"], e["w_trans"] = w_rot, w_trans
+        assert EDGE_DTYPE.itemsize == C.sizeof(PoseEdge)
+        self.edges = e
+        self.fixed = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        d = PoseGraphDesc()
+        d.n_nodes = self.poses.shape[0]
+        d.poses = _ptr(self.poses)
+        d.node_fixed = _ptr(self.fixed)
+        d.n_edges = n
+        d.edges = _ptr(self.edges)
+        self.desc = d
+
+
+def pose_graph_desc(g) -> _GraphDesc:
+    return _GraphDesc(g.q0, g.t0, g.edge_i, g.edge_j, g.meas_q, g.meas_t, g.w_rot, g.w_trans,
+                      g.fixed, g.edge_type)
+
+
 def scene_desc(scene) -> _Desc:
     return _Desc(scene.K, scene.q0, scene.t0, scene.X0, scene.obs_cam, scene.obs_pt,
                  scene.obs_uv, scene.cam_fixed)
@@ -209,6 +251,20 @@ class Problem:
         h = C.c_void_p()
         _check(lib().ba_create(C.byref(desc.desc), C.byref(opts), stream, C.byref(h)))
         self._h = h
+
+    @classmethod
+    def from_pose_graph(cls, graph, stream=None, **kw):
+        """ba_pose_graph_create from a synth.PoseGraph (or a _GraphDesc)."""
+        gd = graph if isinstance(graph, _GraphDesc) else pose_graph_desc(graph)
+        self = cls.__new__(cls)
+        self._desc = gd
+        self.opts = options(**kw)
+        self.n_cams = gd.desc.n_nodes
+        self.n_pts = 0
+        h = C.c_void_p()
+        _check(lib().ba_pose_graph_create(C.byref(gd.desc), C.byref(self.opts), stream, C.byref(h)))
+        self._h = h
+        return self
 
     @classmethod
     def from_scene(cls, scene, stream=None, **kw):
@@ -238,7 +294,7 @@ class Problem:
 
     def active(self):
         """Observations in the problem (1) or removed by culling (0), caller's order."""
-        a = np.zeros(int(self._desc.desc.n_obs), np.uint8)
+        a = np.zeros(int(getattr(self._desc.desc, "n_obs", 0)), np.uint8)
         _check(lib().ba_get_active(self._h, a.ctypes.data_as(C.c_void_p)))
         return a
 

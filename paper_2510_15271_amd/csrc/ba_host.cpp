@@ -60,6 +60,15 @@ void quat_to_pose12(const ba_pose &p, double out[12]) {
   out[11] = p.tz;
 }
 
+// A = T_i T_j^-1 = [R_i R_j^T | t_i - R_i R_j^T t_j] for poses held as 12 values.
+void relative_pose12(const double Ti[12], const double Tj[12], double A[12]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      A[3 * a + b] = Ti[3 * a] * Tj[3 * b] + Ti[3 * a + 1] * Tj[3 * b + 1] + Ti[3 * a + 2] * Tj[3 * b + 2];
+  for (int r = 0; r < 3; ++r)
+    A[9 + r] = Ti[9 + r] - (A[3 * r] * Tj[9] + A[3 * r + 1] * Tj[10] + A[3 * r + 2] * Tj[11]);
+}
+
 // Rotation matrix -> unit quaternion with qw >= 0 (Shepperd's method: branch on
 // the largest of the trace and the diagonal entries).
 ba_pose pose12_to_quat(const double M[12]) {
@@ -282,14 +291,19 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
   return BA_OK;
 }
 
-int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges) {
   if (!d) return fail(BA_EINVAL, "problem description is NULL");
   if (int e = check_options(opt, false)) return e;
   if (d->n_cams < 1) return fail(BA_EINVAL, "n_cams must be >= 1");
-  if (d->n_pts < 1) return fail(BA_EINVAL, "n_pts must be >= 1");
-  if (d->n_obs < 1) return fail(BA_EINVAL, "n_obs must be >= 1");
+  if (!edges) {
+    if (d->n_pts < 1) return fail(BA_EINVAL, "n_pts must be >= 1");
+    if (d->n_obs < 1) return fail(BA_EINVAL, "n_obs must be >= 1");
+    if (!d->points_xyz || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
+  } else if (d->n_pts != 0 || d->n_obs != 0) {
+    return fail(BA_EDEVICE, "internal: a pose graph has no points or observations");
+  }
   if (d->n_obs > (int64_t)INT32_MAX - 1) return fail(BA_EINVAL, "n_obs exceeds 2^31 - 2");
-  if (!d->K || !d->poses || !d->points_xyz || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
+  if (!d->K || !d->poses) return fail(BA_EINVAL, "NULL array in problem");
   const int C = d->n_cams, P = d->n_pts;
   const int64_t N = d->n_obs;
   const int nK = d->K_per_cam ? C : 1;
@@ -418,15 +432,51 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
     sy.obs_rpos = cpos;
   }
 
-  // prior terms: sequential pairs (i, i + k) in the caller's camera order with at least
-  // one free camera (pairs of two fixed cameras are constant)
+  // relative-pose pairs with at least one free camera (pairs of two fixed cameras are
+  // constant): the pose-graph edges, or the sequential prior pairs (i, i + k) in the
+  // caller's camera order, measured from the initial poses with weight lambda_c
   sy.prior_abs = opt->prior_abs;
-  sy.prior_seq = opt->prior_seq;
   sy.pp_cam.clear();
-  if (opt->prior_seq > 0.0)
+  sy.pp_meas.clear();
+  sy.pp_w.clear();
+  if (edges) {
+    for (size_t e = 0; e < edges->pairs.size(); ++e) {
+      const int2 ij = edges->pairs[e];
+      if (sy.free_idx[ij.x] < 0 && sy.free_idx[ij.y] < 0) continue;
+      sy.pp_cam.push_back(ij);
+      sy.pp_meas.insert(sy.pp_meas.end(), edges->meas.begin() + 12 * e, edges->meas.begin() + 12 * e + 12);
+      sy.pp_w.insert(sy.pp_w.end(), edges->w.begin() + 2 * e, edges->w.begin() + 2 * e + 2);
+    }
+  } else if (opt->prior_seq > 0.0) {
     for (int i = 0; i < C; ++i)
       for (int k = 1; k <= opt->prior_seq_k && i + k < C; ++k)
-        if (sy.free_idx[i] >= 0 || sy.free_idx[i + k] >= 0) sy.pp_cam.push_back(int2{i, i + k});
+        if (sy.free_idx[i] >= 0 || sy.free_idx[i + k] >= 0) {
+          double Ti[12], Tj[12], A[12];
+          quat_to_pose12(d->poses[i], Ti);
+          quat_to_pose12(d->poses[i + k], Tj);
+          relative_pose12(Ti, Tj, A);
+          sy.pp_cam.push_back(int2{i, i + k});
+          sy.pp_meas.insert(sy.pp_meas.end(), A, A + 12);
+          sy.pp_w.push_back(opt->prior_seq);
+          sy.pp_w.push_back(opt->prior_seq);
+        }
+  }
+  // later free partners of each free camera through a pair: their blocks of S exist even
+  // where no point is seen by both
+  std::vector<int32_t> padj_start(Cf + 1, 0), padj;
+  for (const int2 &ij : sy.pp_cam) {
+    const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
+    if (a >= 0 && b >= 0) padj_start[std::min(a, b) + 1]++;
+  }
+  for (int a = 0; a < Cf; ++a) padj_start[a + 1] += padj_start[a];
+  padj.resize(padj_start[Cf]);
+  {
+    std::vector<int32_t> f(padj_start.begin(), padj_start.end() - 1);
+    for (const int2 &ij : sy.pp_cam) {
+      const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
+      if (a >= 0 && b >= 0) padj[f[std::min(a, b)]++] = std::max(a, b);
+    }
+  }
   std::vector<uint8_t> pmark(Cf, 0);
 
   // upper blocks of S row by row (and their observation-pair lists in the pair-list form)
@@ -447,16 +497,13 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
         if (rowcnt[b]++ == 0) touched.push_back(b);
       }
     }
-    // a sequential prior couples camera a with later free cameras: those blocks exist
-    // even where no point is seen by both
-    if (opt->prior_seq > 0.0)
-      for (int k = 1; k <= opt->prior_seq_k && sy.free_cam[a] + k < C; ++k) {
-        const int b = sy.free_idx[sy.free_cam[a] + k];
-        if (b >= 0 && rowcnt[b] == 0 && !pmark[b]) {
-          pmark[b] = 1;
-          touched.push_back(b);
-        }
+    for (int x = padj_start[a]; x < padj_start[a + 1]; ++x) {
+      const int b = padj[x];
+      if (rowcnt[b] == 0 && !pmark[b]) {
+        pmark[b] = 1;
+        touched.push_back(b);
       }
+    }
     std::sort(touched.begin(), touched.end());
     const int base_blk = (int)up_col.size();
     int64_t pbase = sy.n_pairs;
@@ -496,10 +543,11 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy) {
   sy.pp_up.assign(sy.pp_cam.size(), -1);
   sy.cam_pp_start.assign(Cf + 1, 0);
   for (size_t p = 0; p < sy.pp_cam.size(); ++p) {
-    const int a = sy.free_idx[sy.pp_cam[p].x], b = sy.free_idx[sy.pp_cam[p].y];
-    if (a >= 0) sy.cam_pp_start[a + 1]++;
-    if (b >= 0) sy.cam_pp_start[b + 1]++;
-    if (a >= 0 && b >= 0) {
+    const int fa = sy.free_idx[sy.pp_cam[p].x], fb = sy.free_idx[sy.pp_cam[p].y];
+    if (fa >= 0) sy.cam_pp_start[fa + 1]++;
+    if (fb >= 0) sy.cam_pp_start[fb + 1]++;
+    if (fa >= 0 && fb >= 0) {
+      const int a = std::min(fa, fb), b = std::max(fa, fb);
       const auto beg = up_col.begin() + up_rowptr[a], end = up_col.begin() + up_rowptr[a + 1];
       const auto pos = std::lower_bound(beg, end, b);
       if (pos == end || *pos != b) return fail(BA_EDEVICE, "internal: prior block (%d, %d) missing", a, b);
@@ -622,6 +670,8 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
   o.row_tot = L.take(sy.chunked ? Cf * 54 * 8 : 16);
   o.pp_cam = L.take(sy.pp_cam.size() * sizeof(int2) + 8);
+  o.pp_meas = L.take(sy.pp_meas.size() * 8 + 8);
+  o.pp_w = L.take(sy.pp_w.size() * 8 + 8);
   o.pp_up = L.take(sy.pp_up.size() * 4 + 4);
   o.cam_pp_start = L.take(sy.cam_pp_start.size() * 4 + 4);
   o.cam_pp = L.take(sy.cam_pp.size() * 4 + 4);
@@ -713,7 +763,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.chunked = sy.chunked ? 1 : 0;
   pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
   pd.n_red_tiles = sy.chunked ? (int32_t)(((int64_t)sy.n_up * 36 + 63) / 64) : 0;
-  pd.n_fin_tiles = sy.chunked ? Cf : 0;
+  pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
   pd.n_fsh_tiles = sy.chunked ? (Cf + 63) / 64 : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
@@ -749,12 +799,13 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_o = ptr(off.part_o);
   pd.row_tot = (double *)ptr(off.row_tot);
   pd.prior_abs = sy.prior_abs;
-  pd.prior_seq = sy.prior_seq;
   pd.n_pp = (int32_t)sy.pp_cam.size();
   pd.prior_on = (sy.prior_abs > 0.0 || pd.n_pp > 0) ? 1 : 0;
   pd.n_pri_tiles = pd.prior_on ? (std::max(Cf, pd.n_pp) + 255) / 256 : 0;
   pd.pose0 = (const double *)ptr(off.pose_init);
   pd.pp_cam = (const int2 *)ptr(off.pp_cam);
+  pd.pp_meas = (const double *)ptr(off.pp_meas);
+  pd.pp_w = (const double *)ptr(off.pp_w);
   pd.pp_up = (const int32_t *)ptr(off.pp_up);
   pd.cam_pp_start = (const int32_t *)ptr(off.cam_pp_start);
   pd.cam_pp = (const int32_t *)ptr(off.cam_pp);
@@ -852,12 +903,14 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.obs_pt, sy.obs_pt.data(), sy.obs_pt.size() * 4));
   chk(up(off.pt_start, sy.pt_start.data(), sy.pt_start.size() * 4));
   chk(up(off.obs_rpos, sy.obs_rpos.data(), sy.obs_rpos.size() * 4));
-  chk(hipMemsetAsync(base + off.obs_act, 1, (size_t)N, s));
+  if (N > 0) chk(hipMemsetAsync(base + off.obs_act, 1, (size_t)N, s));
   chk(up(off.cam_obs, sy.cam_obs.data(), sy.cam_obs.size() * 4));
   chk(up(off.cam_obs_start, sy.cam_obs_start.data(), sy.cam_obs_start.size() * 4));
   chk(up(off.up_pair_start, sy.up_pair_start.data(), sy.up_pair_start.size() * 4));
   chk(up(off.pairs, sy.pairs.data(), sy.pairs.size() * sizeof(int2)));
   chk(up(off.pp_cam, sy.pp_cam.data(), sy.pp_cam.size() * sizeof(int2)));
+  chk(up(off.pp_meas, sy.pp_meas.data(), sy.pp_meas.size() * 8));
+  chk(up(off.pp_w, sy.pp_w.data(), sy.pp_w.size() * 8));
   chk(up(off.pp_up, sy.pp_up.data(), sy.pp_up.size() * 4));
   chk(up(off.cam_pp_start, sy.cam_pp_start.data(), sy.cam_pp_start.size() * 4));
   chk(up(off.cam_pp, sy.cam_pp.data(), sy.cam_pp.size() * 4));
@@ -1100,12 +1153,13 @@ void ba_default_options(ba_options *o) {
   o->prior_seq_k = 1;
 }
 
-int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream, ba_problem **out) {
+static int create_problem(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
+                          const GraphEdges *edges, ba_problem **out) {
   if (!out) return fail(BA_EINVAL, "out is NULL");
   *out = nullptr;
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<ba_problem> p(new ba_problem());
-  if (int e = analyse(d, opt, p->sy)) return e;
+  if (int e = analyse(d, opt, p->sy, edges)) return e;
   if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
   p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0;
@@ -1150,6 +1204,60 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
   p->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();
   return BA_OK;
+}
+
+int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream, ba_problem **out) {
+  return create_problem(d, opt, hip_stream, nullptr, out);
+}
+
+int ba_pose_graph_create(const ba_pose_graph_desc *g, const ba_options *opt, void *hip_stream,
+                         ba_problem **out) {
+  if (out) *out = nullptr;
+  if (!g) return fail(BA_EINVAL, "pose graph description is NULL");
+  if (!opt) return fail(BA_EINVAL, "options are NULL");
+  if (g->n_nodes < 2) return fail(BA_EINVAL, "n_nodes must be >= 2");
+  if (g->n_edges < 1) return fail(BA_EINVAL, "n_edges must be >= 1");
+  if (g->n_edges > (int64_t)INT32_MAX / 2) return fail(BA_EINVAL, "n_edges exceeds 2^30");
+  if (!g->poses || !g->edges) return fail(BA_EINVAL, "NULL array in pose graph");
+  if (opt->huber_delta > 0.0) return fail(BA_EINVAL, "a pose graph takes no robust loss (huber_delta must be <= 0)");
+  if (opt->prior_seq != 0.0) return fail(BA_EINVAL, "a pose graph takes its relative terms as edges (prior_seq must be 0)");
+  const int n = g->n_nodes;
+  GraphEdges ge;
+  ge.pairs.reserve(g->n_edges);
+  ge.meas.resize(12 * (size_t)g->n_edges);
+  ge.w.resize(2 * (size_t)g->n_edges);
+  std::vector<int64_t> keys(g->n_edges);
+  for (int64_t e = 0; e < g->n_edges; ++e) {
+    const ba_pose_edge &ed = g->edges[e];
+    if (ed.i < 0 || ed.i >= n || ed.j < 0 || ed.j >= n)
+      return fail(BA_EINVAL, "edge %lld: node out of range", (long long)e);
+    if (ed.i == ed.j) return fail(BA_EINVAL, "edge %lld joins node %d to itself", (long long)e, ed.i);
+    if (int rc = check_pose(ed.meas, "edge", e)) return rc;
+    if (!(std::isfinite(ed.w_rot) && std::isfinite(ed.w_trans) && ed.w_rot >= 0.0 && ed.w_trans >= 0.0 &&
+          ed.w_rot + ed.w_trans > 0.0))
+      return fail(BA_EINVAL, "edge %lld: weights must be finite, >= 0 and not both 0", (long long)e);
+    ge.pairs.push_back(int2{ed.i, ed.j});
+    quat_to_pose12(ed.meas, &ge.meas[12 * (size_t)e]);
+    ge.w[2 * e] = ed.w_rot;
+    ge.w[2 * e + 1] = ed.w_trans;
+    keys[e] = (int64_t)std::min(ed.i, ed.j) * n + std::max(ed.i, ed.j);
+  }
+  std::sort(keys.begin(), keys.end());
+  for (size_t e = 1; e < keys.size(); ++e)
+    if (keys[e] == keys[e - 1])
+      return fail(BA_EINVAL, "two edges join nodes %lld and %lld", (long long)(keys[e] / n), (long long)(keys[e] % n));
+  const ba_intrinsics K1{1.0, 1.0, 0.0, 0.0};  // unused: a pose graph has no observations
+  ba_problem_desc d{};
+  d.n_cams = n;
+  d.K = &K1;
+  d.K_per_cam = 0;
+  d.poses = g->poses;
+  d.cam_fixed = g->node_fixed;
+  d.n_pts = 0;
+  d.points_xyz = nullptr;
+  d.n_obs = 0;
+  d.obs = nullptr;
+  return create_problem(&d, opt, hip_stream, &ge, out);
 }
 
 int ba_solve_async(ba_problem *p) {
@@ -1267,7 +1375,7 @@ int ba_reset(ba_problem *p) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(dp.view.X[0], dp.dev + dp.off.X_init, 3 * (size_t)dp.P * 8,
                        hipMemcpyDeviceToDevice, p->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(dp.view.obs_act, 1, (size_t)dp.N, p->stream);
+  if (e == hipSuccess && dp.N > 0) e = hipMemsetAsync(dp.view.obs_act, 1, (size_t)dp.N, p->stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
   dp.n_active = dp.N;
   dp.host_state = LMState{};
@@ -1288,6 +1396,7 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
   }
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
+  if (p->sy.N == 0) return fail(BA_EINVAL, "a pose graph has no observations to cull");
   DevProblem &dp = p->dp;
   const double huber0 = dp.huber;
   std::vector<int32_t> cnt(2 * (size_t)dp.view.n_pt_tiles);
@@ -1365,6 +1474,7 @@ int ba_get_active(const ba_problem *p, uint8_t *active_out) {
   if (!p || !active_out) return fail(BA_EINVAL, "NULL argument");
   if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
   const DevProblem &dp = p->dp;
+  if (dp.N == 0) return BA_OK;
   std::vector<uint8_t> buf((size_t)dp.N);
   hipError_t e = hipMemcpyAsync(buf.data(), dp.view.obs_act, buf.size(), hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -1445,7 +1555,7 @@ int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_ou
     if (e != hipSuccess) return hip_fail(e, "pose download");
     for (int i = 0; i < C; ++i) poses_out[i] = pose12_to_quat(&buf[12 * (size_t)i]);
   }
-  if (points_out) {
+  if (points_out && P > 0) {
     std::vector<double> buf(3 * (size_t)P);
     e = hipMemcpy(buf.data(), view.X[cur], buf.size() * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "point download");

@@ -127,12 +127,16 @@ struct ProbDev {
   void *part_d;                   // [diagonal entries][54] T: U, Y W^T (upper 21 each), g_c, Y g_p
   void *part_o;                   // [upper entries][36] T: sum Y W^T of the entry
   double *row_tot;                // [Cf][54] camera-row sums of the diagonal partials
-  // prior terms (FP64): weights, sequential pairs, per-camera U (21) and g (6)
-  // contributions, per-pair off-diagonal blocks lambda_c J_i^T J_j
-  double prior_abs, prior_seq;
+  // relative-pose terms (FP64): the absolute prior's weight, the pairs (i, j) with
+  // their measured A_ij = T_i T_j^-1 and rotation / translation weights (sequential
+  // priors or pose-graph edges), per-camera U (21) and g (6) contributions, per-pair
+  // off-diagonal blocks J_i^T W J_j oriented as the upper block of S
+  double prior_abs;
   int32_t prior_on, n_pp, n_pri_tiles, pad1;
   const double *pose0;            // [C][12] the initial poses (prior anchors)
-  const int2 *pp_cam;             // [n_pp] (i, j), j = i + k
+  const int2 *pp_cam;             // [n_pp] (i, j), caller's camera indices, i != j
+  const double *pp_meas;          // [n_pp][12] measured A_ij, R row-major then t
+  const double *pp_w;             // [n_pp][2] weights of the 9 rotation and 3 translation entries
   const int32_t *pp_up;           // [n_pp] upper block of (free i, free j), or -1
   const int32_t *cam_pp_start;    // [Cf + 1]
   const int32_t *cam_pp;          // pairs of each free camera, ascending

@@ -578,8 +578,11 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
 }
 
 // ------------------------------------------------------------------ prior terms
-// The prior terms of the Sec. 4.3 objective (Eq. abs, Eq. seq) as squared
-// Frobenius norms of 3x4 pose differences, in FP64.  A pose is held as 12 values,
+// The prior terms of the Sec. 4.3 objective (Eq. abs, Eq. seq) and the edges of a
+// pose graph (Sec. 4.2: sequential, loop-closure and extrinsic constraints, all of
+// the form T_i T_j^-1 - M_ij) as weighted squared Frobenius norms of 3x4 pose
+// differences, in FP64: the nine rotation entries of a pair carry one weight, the
+// three translation entries another.  A pose is held as 12 values,
 // R row-major then t; so are the 12-value residuals.  For a left increment
 // T <- Exp(xi) T, xi = (rho, phi), row q of d[R | t]/d xi is: for q < 9 (entry
 // (a, b) of R) 0 for rho and ([e_m]x R)_ab for phi_m; for q >= 9 (t_r) e_r for rho and
@@ -638,8 +641,8 @@ __device__ inline void rel_pose(const double *Ti, const double *Tj, double A[12]
     A[9 + r] = Ti[9 + r] - (A[3 * r] * Tj[9] + A[3 * r + 1] * Tj[10] + A[3 * r + 2] * Tj[11]);
 }
 
-// 1/2 (lambda_a sum_i e_a + lambda_c sum_pairs e_c) at the poses P; the block's
-// threads split the terms and sum them in a fixed order.
+// 1/2 (lambda_a sum_i e_a + sum_pairs (w_rot |dR|^2 + w_trans |dt|^2)) at the poses P;
+// the block's threads split the terms and sum them in a fixed order.
 __device__ inline double prior_cost(const ProbDev &pd, const double *P, double *s_red) {
   double c = 0.0;
   if (pd.prior_abs > 0.0)
@@ -653,19 +656,21 @@ __device__ inline double prior_cost(const ProbDev &pd, const double *P, double *
     }
   for (int p = threadIdx.x; p < pd.n_pp; p += 256) {
     const int2 ij = pd.pp_cam[p];
-    double A[12], A0[12];
+    const double *M = pd.pp_meas + 12 * (size_t)p;
+    double A[12];
     rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
-    rel_pose(pd.pose0 + 12 * ij.x, pd.pose0 + 12 * ij.y, A0);
-    double e = 0.0;
-    for (int q = 0; q < 12; ++q) e += (A[q] - A0[q]) * (A[q] - A0[q]);
-    c += 0.5 * pd.prior_seq * e;
+    double er = 0.0, et = 0.0;
+    for (int q = 0; q < 9; ++q) er += (A[q] - M[q]) * (A[q] - M[q]);
+    for (int q = 9; q < 12; ++q) et += (A[q] - M[q]) * (A[q] - M[q]);
+    c += 0.5 * (pd.pp_w[2 * p] * er + pd.pp_w[2 * p + 1] * et);
   }
   return block_sum256(c, s_red);
 }
 
 // Linearisation of the priors at the current poses: thread g < Cf forms the U (upper
 // 21) and g (6) contributions of free camera g (its absolute term, then its pairs in
-// order); thread g < n_pp forms lambda_c J_i^T J_j of pair g when both cameras are free.
+// order); thread g < n_pp forms J_i^T W J_j of pair g when both cameras are free, stored
+// as the upper block of S (transposed when i comes after j).
 template <class T>
 __global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ probs,
                                                    const Tile *__restrict__ tiles) {
@@ -680,10 +685,11 @@ __global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ p
     double U[21], gv[6];
     for (int i = 0; i < 21; ++i) U[i] = 0.0;
     for (int i = 0; i < 6; ++i) gv[i] = 0.0;
-    auto add_rows = [&](double lam, const double *r, auto row_of) {
+    auto add_rows = [&](double lam_r, double lam_t, const double *r, auto row_of) {
       for (int q = 0; q < 12; ++q) {
         double J[6];
         row_of(q, J);
+        const double lam = q < 9 ? lam_r : lam_t;
         int u = 0;
         for (int a = 0; a < 6; ++a) {
           for (int b = a; b < 6; ++b, ++u) U[u] += lam * J[a] * J[b];
@@ -695,18 +701,20 @@ __global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ p
     if (pd.prior_abs > 0.0) {
       double r[12];
       for (int q = 0; q < 12; ++q) r[q] = Tc[q] - pd.pose0[12 * cam + q];
-      add_rows(pd.prior_abs, r, [&](int q, double J[6]) { left_inc_row(Tc, Tc + 9, q, J); });
+      add_rows(pd.prior_abs, pd.prior_abs, r, [&](int q, double J[6]) { left_inc_row(Tc, Tc + 9, q, J); });
     }
     for (int x = pd.cam_pp_start[g]; x < pd.cam_pp_start[g + 1]; ++x) {
-      const int2 ij = pd.pp_cam[pd.cam_pp[x]];
-      double A[12], A0[12], r[12];
+      const int pp = pd.cam_pp[x];
+      const int2 ij = pd.pp_cam[pp];
+      const double *M = pd.pp_meas + 12 * (size_t)pp;
+      const double wr = pd.pp_w[2 * pp], wt = pd.pp_w[2 * pp + 1];
+      double A[12], r[12];
       rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
-      rel_pose(pd.pose0 + 12 * ij.x, pd.pose0 + 12 * ij.y, A0);
-      for (int q = 0; q < 12; ++q) r[q] = A[q] - A0[q];
+      for (int q = 0; q < 12; ++q) r[q] = A[q] - M[q];
       if (ij.x == cam)
-        add_rows(pd.prior_seq, r, [&](int q, double J[6]) { left_inc_row(A, A + 9, q, J); });
+        add_rows(wr, wt, r, [&](int q, double J[6]) { left_inc_row(A, A + 9, q, J); });
       else
-        add_rows(pd.prior_seq, r, [&](int q, double J[6]) { seq_j_row(A, q, J); });
+        add_rows(wr, wt, r, [&](int q, double J[6]) { seq_j_row(A, q, J); });
     }
     double *o = pd.prior_diag + 27 * (size_t)g;
     for (int i = 0; i < 21; ++i) o[i] = U[i];
@@ -718,20 +726,26 @@ __global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ p
     rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
     double off[36];
     for (int i = 0; i < 36; ++i) off[i] = 0.0;
+    const double wr = pd.pp_w[2 * g], wt = pd.pp_w[2 * g + 1];
     for (int q = 0; q < 12; ++q) {
       double Ji[6], Jj[6];
       left_inc_row(A, A + 9, q, Ji);
       seq_j_row(A, q, Jj);
+      const double lam = q < 9 ? wr : wt;
       for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) off[6 * a + b] += pd.prior_seq * Ji[a] * Jj[b];
+        for (int b = 0; b < 6; ++b) off[6 * a + b] += lam * Ji[a] * Jj[b];
     }
+    // block (i, j) of S; the upper block is (min, max) in camera order
+    const bool flip = ij.x > ij.y;
     double *o = pd.prior_off + 36 * (size_t)g;
-    for (int i = 0; i < 36; ++i) o[i] = off[i];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) o[6 * a + b] = flip ? off[6 * b + a] : off[6 * a + b];
   }
 }
 
-// The pair blocks lambda_c J_i^T J_j added to S_ab and (transposed) S_ba, after the
-// Schur complement has written them.
+// The pair blocks J_i^T W J_j (oriented as the upper block) added to S_ab and
+// (transposed) S_ba, after the Schur complement has written them.  Every upper block
+// carries at most one pair (pairs are distinct), so no two threads touch one block.
 template <class T>
 __global__ __launch_bounds__(256) void k_prior_apply(const ProbDev *__restrict__ probs,
                                                      const Tile *__restrict__ tiles) {
@@ -1395,8 +1409,9 @@ __global__ __launch_bounds__(64) void k_schur_finish(const ProbDev *__restrict__
   const int a = 64 * tl.idx + (int)threadIdx.x;
   if (a >= pd.Cf) return;
   double tot[54];
+  // no records (a pose graph): the rows kernel does not run and every row sum is zero
 #pragma unroll
-  for (int i = 0; i < 54; ++i) tot[i] = pd.row_tot[54 * (size_t)a + i];
+  for (int i = 0; i < 54; ++i) tot[i] = pd.Nf > 0 ? pd.row_tot[54 * (size_t)a + i] : 0.0;
   finish_camera_row<T>(pd, st, a, tot);
 }
 

@@ -19,6 +19,7 @@ int hip_fail(hipError_t e, const char *what);
 int check_pose(const ba_pose &p, const char *what, int64_t i);
 int check_options(const ba_options *o, bool pose_only);
 void quat_to_pose12(const ba_pose &p, double out[12]);
+void relative_pose12(const double Ti[12], const double Tj[12], double A[12]);
 ba_pose pose12_to_quat(const double M[12]);
 
 // Result of the symbolic analysis of one problem (host arrays).
@@ -45,10 +46,12 @@ struct Symbolic {
   std::vector<uint32_t> ent_items;
   std::vector<int32_t> blk_start;
   int32_t n_dent = 0, n_oent = 0;
-  // prior terms: sequential pairs (caller's camera indices, camera order), their upper
+  // relative-pose pairs (caller's camera indices): sequential prior pairs or pose-graph
+  // edges, their measured A_ij (12 each) and weights (rotation, translation), their upper
   // block (both cameras free) or -1, and the pairs of each free camera
-  double prior_abs = 0.0, prior_seq = 0.0;
+  double prior_abs = 0.0;
   std::vector<int2> pp_cam;
+  std::vector<double> pp_meas, pp_w;
   std::vector<int32_t> pp_up, cam_pp_start, cam_pp;
   std::vector<int32_t> up_pos, up_tpos, diag_pos, S_rowptr, S_col;
   // distinct columns read by each PCG tile (kPcgRows rows) and, per block, the
@@ -56,14 +59,22 @@ struct Symbolic {
   std::vector<int32_t> tcol, S_lcol;
   int32_t max_tcols = 0;
 };
-int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy);
+// Edges of a pose graph: node pairs (i, j), measured A_ij (12 values each, R row-major
+// then t) and weights (rotation, translation).
+struct GraphEdges {
+  std::vector<int2> pairs;
+  std::vector<double> meas, w;
+};
+// Symbolic analysis of a problem.  With edges, the description holds the nodes only
+// (no points or observations) and the edges replace the sequential prior pairs.
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges = nullptr);
 
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos, obs_act;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
   size_t part_d, part_o, row_tot;
-  size_t pp_cam, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
+  size_t pp_cam, pp_meas, pp_w, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
   size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], part_cull, iter_cost, iter_pcg;

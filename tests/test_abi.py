@@ -114,3 +114,46 @@ def test_refine_validation(balib):
     rc, msg = call([(1.0, 8.0), (0.0, 3.0)], 2)
     assert rc == balib.BA_EINVAL and "NULL" in msg
     assert L.ba_get_active(None, None) == balib.BA_EINVAL
+
+
+def test_pose_graph_validation(balib):
+    """ba_pose_graph_create rejects bad graphs before touching the device."""
+    from synth import make_pose_graph
+    g = make_pose_graph(4, mode="rig")
+
+    def expect(mutate, needle, **kw):
+        gd = balib.pose_graph_desc(g)
+        mutate(gd)
+        h = ctypes.c_void_p()
+        rc = balib.lib().ba_pose_graph_create(ctypes.byref(gd.desc), ctypes.byref(balib.options(**kw)), None,
+                                              ctypes.byref(h))
+        msg = balib.lib().ba_last_error().decode()
+        assert rc == balib.BA_EINVAL and needle in msg, (needle, msg)
+
+    def set_edge(k, field, value):
+        def f(gd):
+            gd.edges[field][k] = value
+        return f
+
+    expect(set_edge(3, "j", g.n_nodes), "out of range")
+    expect(set_edge(3, "i", -1), "out of range")
+    expect(set_edge(2, "j", int(g.edge_i[2])), "itself")
+    expect(set_edge(1, "w_rot", -1.0), "weights")
+    expect(set_edge(1, "w_trans", np.nan), "weights")
+
+    def both_zero(gd):
+        gd.edges["w_rot"][0] = 0.0
+        gd.edges["w_trans"][0] = 0.0
+    expect(both_zero, "weights")
+    expect(set_edge(0, "q", [2.0, 0.0, 0.0, 0.0]), "quaternion")
+
+    def duplicate(gd):  # the reverse of edge 0
+        gd.edges["i"][1], gd.edges["j"][1] = gd.edges["j"][0], gd.edges["i"][0]
+    expect(duplicate, "two edges")
+
+    def all_fixed(gd):
+        gd.fixed = np.ones(g.n_nodes, np.uint8)
+        gd.desc.node_fixed = gd.fixed.ctypes.data_as(ctypes.c_void_p)
+    expect(all_fixed, "fixed")
+    expect(lambda gd: None, "robust loss", huber_delta=1.0)
+    expect(lambda gd: None, "prior_seq", prior_seq=1.0)
