@@ -209,6 +209,10 @@ typedef struct {
   int32_t schur_form;     /* 1: point chunks staged in LDS, 0: per-block pair lists    */
   int32_t n_chunks;       /* point chunks (chunk form)                                 */
   int64_t n_entries;      /* (chunk, block) partial sums (chunk form)                  */
+  int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4, or 16 for many
+                             sparse rows (at least 1024 free cameras, at most 24 blocks
+                             per row on average)                                      */
+  int32_t reserved;
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);
 /* Device bytes held by the problem (the admission byte model of the server). */

@@ -64,7 +64,8 @@ class ProblemInfo(C.Structure):
     _fields_ = [("n_cams", C.c_int32), ("n_free_cams", C.c_int32), ("n_pts", C.c_int32),
                 ("n_obs", C.c_int32), ("n_pairs", C.c_int64), ("n_up_blocks", C.c_int32),
                 ("nnzb", C.c_int32), ("n_free_obs", C.c_int32), ("precision", C.c_int32),
-                ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64)]
+                ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64),
+                ("pcg_rows", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PoseEdge(C.Structure):

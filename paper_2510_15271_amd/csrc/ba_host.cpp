@@ -598,25 +598,34 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
       sy.up_tpos[u] = tpos;
     }
   // distinct columns of each PCG tile and each block's position in its tile's list;
-  // the lists are stored at a fixed stride (the longest list), padded with -1
-  const int ntile = (Cf + kPcgRows - 1) / kPcgRows;
-  sy.S_lcol.assign(sy.nnzb, 0);
-  sy.max_tcols = 0;
-  std::vector<std::vector<int32_t>> lists(ntile);
-  std::vector<int32_t> where(Cf, -1);
-  for (int t = 0; t < ntile; ++t) {
-    std::vector<int32_t> &cols = lists[t];
-    const int r0 = t * kPcgRows, r1 = std::min(Cf, r0 + kPcgRows);
-    for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) cols.push_back(sy.S_col[pos]);
-    std::sort(cols.begin(), cols.end());
-    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-    for (size_t i = 0; i < cols.size(); ++i) where[cols[i]] = (int32_t)i;
-    for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) sy.S_lcol[pos] = where[sy.S_col[pos]];
-    sy.max_tcols = std::max(sy.max_tcols, (int32_t)cols.size());
-  }
-  sy.tcol.assign((size_t)ntile * sy.max_tcols, -1);
-  for (int t = 0; t < ntile; ++t)
-    std::copy(lists[t].begin(), lists[t].end(), sy.tcol.begin() + (size_t)t * sy.max_tcols);
+  // the lists are stored at a fixed stride (the longest list), padded with -1.
+  // A tile holds kPcgRows rows, or kPcgRowsSparse when the rows hold few blocks and
+  // there are many of them: each launch sums every tile's partials in every tile, so
+  // the tile count must stay modest, and sparse rows leave most of a 4-row tile idle.
+  auto tile_lists = [&](int R) {
+    const int ntile = (Cf + R - 1) / R;
+    sy.pcg_rows = R;
+    sy.S_lcol.assign(sy.nnzb, 0);
+    sy.max_tcols = 0;
+    std::vector<std::vector<int32_t>> lists(ntile);
+    std::vector<int32_t> where(Cf, -1);
+    for (int t = 0; t < ntile; ++t) {
+      std::vector<int32_t> &cols = lists[t];
+      const int r0 = t * R, r1 = std::min(Cf, r0 + R);
+      for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) cols.push_back(sy.S_col[pos]);
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      for (size_t i = 0; i < cols.size(); ++i) where[cols[i]] = (int32_t)i;
+      for (int pos = sy.S_rowptr[r0]; pos < sy.S_rowptr[r1]; ++pos) sy.S_lcol[pos] = where[sy.S_col[pos]];
+      sy.max_tcols = std::max(sy.max_tcols, (int32_t)cols.size());
+    }
+    sy.tcol.assign((size_t)ntile * sy.max_tcols, -1);
+    for (int t = 0; t < ntile; ++t)
+      std::copy(lists[t].begin(), lists[t].end(), sy.tcol.begin() + (size_t)t * sy.max_tcols);
+  };
+  const bool sparse_rows = Cf >= 1024 && sy.nnzb <= 24 * (int64_t)Cf;
+  tile_lists(sparse_rows ? kPcgRowsSparse : kPcgRows);
+  if (sy.pcg_rows != kPcgRows && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
   if (sy.chunked)
     return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
   return BA_OK;
@@ -638,7 +647,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   const size_t T = compute_bytes(precision);
   const size_t C = sy.C, Cf = sy.Cf, P = sy.P, N = sy.N;
   const size_t npt = (P + kPtTile - 1) / kPtTile;
-  const size_t npcg = (Cf + kPcgRows - 1) / kPcgRows;
+  const size_t npcg = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   const size_t ncam = (C + kCamTile - 1) / kCamTile;
   Layout L;
   o.st = L.take(sizeof(LMState));
@@ -768,7 +777,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
-  pd.n_pcg_tiles = (Cf + kPcgRows - 1) / kPcgRows;
+  pd.n_pcg_tiles = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
+  pd.pcg_rows = sy.pcg_rows;
   pd.n_cam_tiles = (C + kCamTile - 1) / kCamTile;
   pd.K = ptr(off.K);
   pd.free_idx = (const int32_t *)ptr(off.free_idx);
@@ -1497,6 +1507,8 @@ int ba_get_info(const ba_problem *p, ba_problem_info *out) {
   out->schur_form = p->sy.chunked ? 1 : 0;
   out->n_chunks = p->sy.chunked ? (int32_t)p->sy.ch_pt.size() - 1 : 0;
   out->n_entries = (int64_t)p->sy.ent_tgt.size();
+  out->pcg_rows = p->sy.pcg_rows;
+  out->reserved = 0;
   return BA_OK;
 }
 

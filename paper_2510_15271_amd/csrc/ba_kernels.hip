@@ -1416,7 +1416,8 @@ __global__ __launch_bounds__(64) void k_schur_finish(const ProbDev *__restrict__
 }
 
 // ------------------------------------------------------------------ PCG
-// Tile = kPcgRows (= 4) consecutive rows of one problem, one wave per row.
+// Tile = pd.pcg_rows (4 or 16) consecutive rows of one problem; in the two-kernel
+// form each wave of the 256-thread workgroup takes every fourth row of the tile.
 // Iteration it (0-based):
 //   spmv(it):   it >= 1: stop if ||r_it|| <= tol ||b||; beta = rz_it / rz_{it-1};
 //               p_it = z + beta p_{it-1} (formed on the fly for every column read);
@@ -1453,18 +1454,22 @@ __device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, 
   if (!pcg_go(st, it, s_flag)) return;
   double beta = 0.0;
   if (it == 0) {
-    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
-    const double rz0 = block_sum_array(pd.part_rz0, pd.Cf, s_red);
-    if (tl.idx == 0 && threadIdx.x == 0) {
-      st->pcg_bb = bb;
-      st->pcg_rz0 = rz0;
-    }
-    if (!(bb > 0.0)) {
-      if (tl.idx == 0 && threadIdx.x == 0) {
-        st->pcg_done = 1;
-        st->pcg_iters = 0;
+    // tile 0 alone sums ||b||^2 and r.z over the cameras (the next launch reads them);
+    // with b = 0 the other tiles' products are zero and harmless
+    if (tl.idx == 0) {
+      const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
+      const double rz0 = block_sum_array(pd.part_rz0, pd.Cf, s_red);
+      if (threadIdx.x == 0) {
+        st->pcg_bb = bb;
+        st->pcg_rz0 = rz0;
       }
-      return;
+      if (!(bb > 0.0)) {
+        if (threadIdx.x == 0) {
+          st->pcg_done = 1;
+          st->pcg_iters = 0;
+        }
+        return;
+      }
     }
   } else {
     __shared__ double s_red3[12];
@@ -1492,8 +1497,9 @@ __device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / 6, i = lane % 6;
   double pq = 0.0;
-  const int a = tl.idx * kPcgRows + w;  // one wave per row
-  if (a < pd.Cf) {
+  for (int rr = w; rr < pd.pcg_rows; rr += 4) {
+    const int a = tl.idx * pd.pcg_rows + rr;
+    if (a >= pd.Cf) break;
     T acc = T(0);
     if (lane < 60) {
       const int b1 = pd.S_rowptr[a + 1];
@@ -1523,7 +1529,7 @@ __device__ void pcg_spmv_tile(const ProbDev *__restrict__ probs, const Tile tl, 
       const T pa = (it == 0) ? pin[6 * a + lane] : z[6 * a + lane] + tb * pold[6 * a + lane];
       q[6 * a + lane] = qi;
       if (it > 0) pout[6 * a + lane] = pa;
-      pq = (double)pa * (double)qi;
+      pq += (double)pa * (double)qi;
     }
   }
   const double tot = block_sum256(pq, s_pq);
@@ -1537,7 +1543,7 @@ __device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl
   __shared__ int s_flag[1];
   __shared__ double s_red[4];
   __shared__ double s_red2[4];
-  __shared__ T s_r[kPcgRows * 6];
+  __shared__ T s_r[kPcgRowsMax * 6];
   if (!pcg_go(st, it, s_flag)) return;
   __shared__ double s_red3[12];
   double sums[3];  // p.q, rz_it
@@ -1558,13 +1564,13 @@ __device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl
   T *x = (T *)pd.x;
   T *r = (T *)pd.r;
   T *z = (T *)pd.z;
-  const int rbeg = tl.idx * kPcgRows;
-  const int rend = min(pd.Cf, rbeg + kPcgRows);
+  const int rbeg = tl.idx * pd.pcg_rows;
+  const int rend = min(pd.Cf, rbeg + pd.pcg_rows);
   double rzp = 0.0, rrp = 0.0;
-  // one thread per row element (6 * kPcgRows of them)
+  // one thread per row element (6 * pcg_rows of them)
   const int e = threadIdx.x;
   const int a = rbeg + e / 6;
-  if (e < 6 * kPcgRows && a < rend) {
+  if (e < 6 * pd.pcg_rows && a < rend) {
     const size_t idx = 6 * (size_t)a + (e % 6);
     x[idx] = x[idx] + ta * p[idx];
     const T rn = r[idx] - ta * q[idx];
@@ -1572,7 +1578,7 @@ __device__ void pcg_update_tile(const ProbDev *__restrict__ probs, const Tile tl
     s_r[e] = rn;
   }
   __syncthreads();
-  if (e < 6 * kPcgRows && a < rend) {
+  if (e < 6 * pd.pcg_rows && a < rend) {
     const int i = e % 6;
     const double *Mi = pd.Minv + 36 * (size_t)a + 6 * i;
     const T *rr = s_r + 6 * (e / 6);
@@ -1651,13 +1657,17 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   if (threadIdx.x == 0) s_flag[0] = lm_active(st) ? 1 : 0;
   __syncthreads();
   if (!s_flag[0]) return;
-  const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
-  if (tl.idx == 0 && threadIdx.x == 0) {
-    st->pcg_bb = bb;
-    st->pcg_done = (bb > 0.0) ? 0 : 1;
-    st->pcg_iters = 0;
+  // tile 0 alone sums ||b||^2 over the cameras and sets the flags the first step
+  // reads; with b = 0 every other tile's products are zero and harmless
+  if (tl.idx == 0) {
+    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
+    if (threadIdx.x == 0) {
+      st->pcg_bb = bb;
+      st->pcg_done = (bb > 0.0) ? 0 : 1;
+      st->pcg_iters = 0;
+    }
+    if (!(bb > 0.0)) return;
   }
-  if (!(bb > 0.0)) return;
   const T *u = (const T *)pd.cg_u[0];
   const T *r = (const T *)pd.cg_r[0];
   T *w = (T *)pd.cg_w[0];
@@ -1667,8 +1677,9 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane / 6, i = lane % 6;
   double pg = 0.0, pdl = 0.0, prr = 0.0;
-  const int a = tl.idx * kPcgRows + wv;
-  if (a < pd.Cf) {
+  for (int rr = wv; rr < pd.pcg_rows; rr += 4) {  // each wave takes every fourth row
+    const int a = tl.idx * pd.pcg_rows + rr;
+    if (a >= pd.Cf) break;
     T acc = T(0);
     if (lane < 60) {
       const int b1 = pd.S_rowptr[a + 1];
@@ -1688,15 +1699,15 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
       sv[idx] = T(0);  // s_{-1}
       p[idx] = T(0);   // p_{-1}
       const double ui = (double)u[idx], ri = (double)r[idx];
-      pg = ri * ui;
-      pdl = (double)wi * ui;
-      prr = ri * ri;
+      pg += ri * ui;
+      pdl += (double)wi * ui;
+      prr += ri * ri;
     }
   }
   cg_partials(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
 }
 
-// One PCG iteration per launch, 1024 threads per tile of kPcgRows rows.  A
+// One PCG iteration per launch, 1024 threads per tile of pd.pcg_rows rows.  A
 // launch is short and its data sit in L2 / the Infinity Cache, so its time is
 // set by dependent memory round trips, not bandwidth: every load that does not
 // need this iteration's alpha and beta (the S blocks of the tile's rows, the
@@ -1704,9 +1715,10 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
 // sums and the LM scalars) is issued before the one reduction barrier.
 //   column pass: thread (l, m) owns component m of column l (up to 170 columns
 //                in registers, the rest in a second sweep);
-//   product:     row = one quarter of the block (4 waves x 10 groups of 6 lanes),
-//                cg_pre<T>() S blocks per lane held in registers, group sums by a
-//                fixed shuffle tree, the four waves of a row in order.
+//   product:     row = 16 / pcg_rows waves (4 for 4-row tiles, 1 for 16-row tiles)
+//                of 10 groups of 6 lanes, cg_pre<T>() S blocks per lane held in
+//                registers, group sums by a fixed shuffle tree, the waves of a row
+//                in order.
 constexpr int kCgThreads = 1024;
 template <class T>
 constexpr int cg_pre() { return sizeof(T) == 4 ? 4 : 1; }  // within 128 VGPRs at 16 waves per CU
@@ -1740,15 +1752,17 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   extern __shared__ double s_dyn[];
   T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
   __shared__ double s_red[48];
-  __shared__ T s_w[kPcgRows][4][6];
-  __shared__ T s_ro[kPcgRows][6], s_uo[kPcgRows][6];
+  __shared__ T s_w[kPcgRowsMax][4][6];
+  __shared__ T s_ro[kPcgRowsMax][6], s_uo[kPcgRowsMax][6];
+  __shared__ double s_fin[6];
   __shared__ int s_flag[1];
   const Tile tl{0, tile};
   const LMState *st = pd.st;
   const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
   const int nt = pd.n_pcg_tiles;
-  const int row0 = tl.idx * kPcgRows, row1 = min(pd.Cf, row0 + kPcgRows);
+  const int R = pd.pcg_rows, wpr = 16 / R;  // rows per tile, waves per row
+  const int row0 = tl.idx * R, row1 = min(pd.Cf, row0 + R);
   const int ncmax = pd.max_tcols;
   const int32_t *tcol = pd.tcol + (size_t)tl.idx * ncmax;
   const T *r0 = (const T *)pd.cg_r[pr];
@@ -1792,9 +1806,10 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     p0m = p0[6 * (size_t)c + m];
     xm = x[6 * (size_t)c + m];
   }
-  const int lane = t & 63, q = (t >> 6) & 3;
+  const int lane = t & 63, rw = (t >> 6) / wpr, q = (t >> 6) - wpr * ((t >> 6) / wpr);
   const int g = lane / 6, i = lane - 6 * (lane / 6);
-  const int a = row0 + (t >> 8);
+  const int a = row0 + rw;
+  const int bstep = 10 * wpr;  // blocks between one lane group's consecutive blocks
   const bool spl = lane < 60 && a < row1;
   int b0 = 0, b1 = 0;
   if (spl) {
@@ -1806,7 +1821,7 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   int lreg[kCgPre];
 #pragma unroll
   for (int k = 0; k < kCgPre; ++k) {
-    const int blk = b0 + 40 * k;
+    const int blk = b0 + bstep * k;
     lreg[k] = -1;
     if (blk < b1) {
       lreg[k] = pd.S_lcol[blk];
@@ -1920,7 +1935,7 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
 #pragma unroll
         for (int n = 0; n < 6; ++n) acc += sreg[k][n] * uc[n];
       }
-    for (int blk = b0 + 40 * kCgPre; blk < b1; blk += 40) {
+    for (int blk = b0 + bstep * kCgPre; blk < b1; blk += bstep) {
       const T *Srow = S + 36 * (size_t)blk + 6 * i;
       const T *uc = ul + 6 * pd.S_lcol[blk];
 #pragma unroll
@@ -1930,7 +1945,7 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   T wi = T(0);
 #pragma unroll
   for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
-  if (lane < 6 && a < row1) s_w[t >> 8][q][lane] = wi;
+  if (lane < 6 && a < row1) s_w[rw][q][lane] = wi;
   __syncthreads();
   if (own) {
     const size_t idx = 6 * (size_t)c + m;
@@ -1940,14 +1955,15 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     r1[idx] = rm;
     u1[idx] = um;
   }
-  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (wave 0)
-  if (t < 64) {
+  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (waves 0 and 1)
+  if (t < 128) {
     double g2 = 0.0, d2 = 0.0, q2 = 0.0;
-    if (t < 6 * kPcgRows) {
+    if (t < 6 * R) {
       const int rr_ = t / 6, mm = t - 6 * (t / 6);
       const int a2 = row0 + rr_;
       if (a2 < row1) {
-        const T w = s_w[rr_][0][mm] + s_w[rr_][1][mm] + s_w[rr_][2][mm] + s_w[rr_][3][mm];
+        T w = s_w[rr_][0][mm];
+        for (int qq = 1; qq < wpr; ++qq) w += s_w[rr_][qq][mm];
         w1[6 * (size_t)a2 + mm] = w;
         const double ui = (double)s_uo[rr_][mm], ri = (double)s_ro[rr_][mm];
         g2 = ri * ui;
@@ -1958,12 +1974,18 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     g2 = wave_sum(g2);
     d2 = wave_sum(d2);
     q2 = wave_sum(q2);
-    if (t == 0) {
-      double *pn = pd.part_cg[cu];
-      pn[tl.idx] = g2;
-      pn[nt + tl.idx] = d2;
-      pn[2 * nt + tl.idx] = q2;
+    if ((t & 63) == 0) {
+      s_fin[3 * (t >> 6)] = g2;
+      s_fin[3 * (t >> 6) + 1] = d2;
+      s_fin[3 * (t >> 6) + 2] = q2;
     }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double *pn = pd.part_cg[cu];
+    pn[tl.idx] = s_fin[0] + s_fin[3];
+    pn[nt + tl.idx] = s_fin[1] + s_fin[4];
+    pn[2 * nt + tl.idx] = s_fin[2] + s_fin[5];
   }
 }
 

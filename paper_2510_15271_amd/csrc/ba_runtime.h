@@ -58,6 +58,7 @@ struct Symbolic {
   // position of its column in its tile's list
   std::vector<int32_t> tcol, S_lcol;
   int32_t max_tcols = 0;
+  int32_t pcg_rows = kPcgRows;    // rows per PCG tile
 };
 // Edges of a pose graph: node pairs (i, j), measured A_ij (12 values each, R row-major
 // then t) and weights (rotation, translation).

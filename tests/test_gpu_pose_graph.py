@@ -53,6 +53,22 @@ def test_pose_graph_f64_per_iteration_cost(balib, mode, flags, prior_abs):
     assert res["n_masked"] == 0 and res["rms_px"] == 0.0
 
 
+def test_pose_graph_sparse_tiles_f64_pcg_schedule(balib):
+    """1080 nodes (360 frames of the 3-camera rig): the reduced system has many sparse
+    rows, so the PCG runs 16 rows per workgroup.  FP64 with PCG capped at 100 products
+    and tol 1e-8 against the oracle's textbook PCG with the same schedule: PCG counts
+    identical and every C_n within 1e-8."""
+    g = make_pose_graph(180)
+    ref = O.lm_schur(_oracle_problem(g), O.LMOptions(max_iters=6, solve="pcg", pcg_max_iters=100,
+                                                     pcg_rel_tol=1e-8))
+    res, info = _solve(balib, g, max_iters=6, pcg_max_iters=100, pcg_rel_tol=1e-8, precision="f64")
+    assert info["pcg_rows"] == 16
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("sparse tiles: max rel cost diff", rel.max(), list(res["pcg_iters"]), ref.pcg_iters)
+    assert list(res["pcg_iters"]) == list(ref.pcg_iters)
+    assert rel.max() <= 1e-8
+
+
 def test_pose_graph_f32_final_cost(balib):
     """600 nodes, 1641 edges, FP32 with the benchmark's PCG schedule (50 / 1e-6), 10
     iterations: the final cost within 1e-4 of the FP64 oracle run with that schedule,
@@ -74,6 +90,7 @@ def test_pose_graph_full_size_cost_matches_oracle_at_device_state(balib):
     loop closures pull the second lap onto the first (cost below half the start)."""
     g = make_pose_graph(1500)
     res, info = _solve(balib, g, max_iters=10, precision="f32")
+    assert info["pcg_rows"] == 16
     p = _oracle_problem(g)
     c = O.prior_cost(p, O.quat_to_rot(res["q"]), res["t"])
     _say("full-size pose graph: device", res["cost"], "oracle", c, "start", res["iter_cost"][0], info["nnzb"])
