@@ -95,6 +95,10 @@ typedef struct {
    observations than a chunk holds (2048; 1024 in BA_PREC_F64). */
 #define BA_FLAG_NO_GRAPH 2
 #define BA_FLAG_PAIR_LISTS 4
+/* BA_FLAG_PCG_WIDE: run the PCG with 32 reduced-system rows per workgroup (half a
+   wave per row) whatever the row density, when the tile's columns fit in LDS.  By
+   default that layout is used only for more than 8192 free cameras with sparse rows. */
+#define BA_FLAG_PCG_WIDE 8
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */
@@ -209,9 +213,9 @@ typedef struct {
   int32_t schur_form;     /* 1: point chunks staged in LDS, 0: per-block pair lists    */
   int32_t n_chunks;       /* point chunks (chunk form)                                 */
   int64_t n_entries;      /* (chunk, block) partial sums (chunk form)                  */
-  int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4, or 16 for many
-                             sparse rows (at least 1024 free cameras, at most 24 blocks
-                             per row on average)                                      */
+  int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for many sparse
+                             rows (at least 1024 free cameras, at most 24 blocks per row
+                             on average) 16, or 32 beyond 8192 free cameras            */
   int32_t reserved;
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);

@@ -124,7 +124,7 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS))
+  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   if (!pose_only) {
     if (!(o->prior_abs >= 0.0) || !std::isfinite(o->prior_abs))
@@ -623,9 +623,14 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
     for (int t = 0; t < ntile; ++t)
       std::copy(lists[t].begin(), lists[t].end(), sy.tcol.begin() + (size_t)t * sy.max_tcols);
   };
+  // Sparse rows take 16 rows per tile, or 32 (half a wave each) once 16-row tiles
+  // would outnumber what the device runs at once (two 1024-thread workgroups per CU);
+  // a tile whose columns do not fit in LDS falls back to fewer rows.
   const bool sparse_rows = Cf >= 1024 && sy.nnzb <= 24 * (int64_t)Cf;
-  tile_lists(sparse_rows ? kPcgRowsSparse : kPcgRows);
-  if (sy.pcg_rows != kPcgRows && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
+  const bool wide = (opt->flags & BA_FLAG_PCG_WIDE) || (Cf + kPcgRowsSparse - 1) / kPcgRowsSparse > 512;
+  tile_lists(!(sparse_rows || (opt->flags & BA_FLAG_PCG_WIDE)) ? kPcgRows : wide ? kPcgRowsMax : kPcgRowsSparse);
+  if (sy.pcg_rows == kPcgRowsMax && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRowsSparse);
+  if (sy.pcg_rows == kPcgRowsSparse && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
   if (sy.chunked)
     return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
   return BA_OK;

@@ -17,7 +17,7 @@ constexpr int kPtTile = 256;     // points per point-major tile (one workgroup)
 constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile (one per thread)
 constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile, dense rows
 constexpr int kPcgRowsSparse = 16;  // rows per PCG tile when rows hold few blocks
-constexpr int kPcgRowsMax = 16;
+constexpr int kPcgRowsMax = 32;     // ... and when there are more than 512 such tiles
 constexpr int kCamTile = 256;    // cameras per camera-update tile
 constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
 constexpr int kPoseThreads = 256;
@@ -77,7 +77,7 @@ struct ProbDev {
   int32_t nnzb;          // blocks of S stored (both triangles + diagonal)
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
   int32_t max_tcols;     // longest tile column list
-  int32_t pcg_rows;      // rows per PCG tile: kPcgRows or kPcgRowsSparse
+  int32_t pcg_rows;      // rows per PCG tile: kPcgRows, kPcgRowsSparse or kPcgRowsMax
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
   int32_t n_red_tiles;   // reduction tiles (chunk form): 64 elements of the upper blocks each

@@ -1715,10 +1715,10 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
 // sums and the LM scalars) is issued before the one reduction barrier.
 //   column pass: thread (l, m) owns component m of column l (up to 170 columns
 //                in registers, the rest in a second sweep);
-//   product:     row = 16 / pcg_rows waves (4 for 4-row tiles, 1 for 16-row tiles)
-//                of 10 groups of 6 lanes, cg_pre<T>() S blocks per lane held in
-//                registers, group sums by a fixed shuffle tree, the waves of a row
-//                in order.
+//   product:     row = 1024 / pcg_rows lanes (4 waves for 4-row tiles, 1 for 16,
+//                half a wave for 32) in groups of 6 lanes (10 per wave, 5 per half
+//                wave), cg_pre<T>() S blocks per lane held in registers, group sums
+//                by a fixed shuffle tree, the waves of a row in order.
 constexpr int kCgThreads = 1024;
 template <class T>
 constexpr int cg_pre() { return sizeof(T) == 4 ? 4 : 1; }  // within 128 VGPRs at 16 waves per CU
@@ -1754,14 +1754,16 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   __shared__ double s_red[48];
   __shared__ T s_w[kPcgRowsMax][4][6];
   __shared__ T s_ro[kPcgRowsMax][6], s_uo[kPcgRowsMax][6];
-  __shared__ double s_fin[6];
+  __shared__ double s_fin[12];
   __shared__ int s_flag[1];
   const Tile tl{0, tile};
   const LMState *st = pd.st;
   const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
   const int nt = pd.n_pcg_tiles;
-  const int R = pd.pcg_rows, wpr = 16 / R;  // rows per tile, waves per row
+  const int R = pd.pcg_rows;              // rows per tile: 4, 16 or 32
+  const int Lr = kCgThreads / R;          // lanes per row: 256, 64 or 32
+  const int wpr = Lr >= 64 ? Lr / 64 : 1;  // waves per row (a half-wave row counts as one)
   const int row0 = tl.idx * R, row1 = min(pd.Cf, row0 + R);
   const int ncmax = pd.max_tcols;
   const int32_t *tcol = pd.tcol + (size_t)tl.idx * ncmax;
@@ -1806,14 +1808,18 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     p0m = p0[6 * (size_t)c + m];
     xm = x[6 * (size_t)c + m];
   }
-  const int lane = t & 63, rw = (t >> 6) / wpr, q = (t >> 6) - wpr * ((t >> 6) / wpr);
-  const int g = lane / 6, i = lane - 6 * (lane / 6);
+  const int lane = t & 63, rw = t / Lr;
+  const int h = t - Lr * rw;                         // lane within the row
+  const int q = Lr >= 64 ? (h >> 6) : 0;             // wave within the row
+  const int hs = Lr >= 64 ? (h & 63) : h;            // lane within the row's wave segment
+  const int gps = Lr >= 64 ? 10 : 5;                 // groups of 6 lanes per segment
+  const int g = hs / 6, i = hs - 6 * (hs / 6);
   const int a = row0 + rw;
-  const int bstep = 10 * wpr;  // blocks between one lane group's consecutive blocks
-  const bool spl = lane < 60 && a < row1;
+  const int bstep = gps * wpr;  // blocks between one lane group's consecutive blocks
+  const bool spl = g < gps && a < row1;
   int b0 = 0, b1 = 0;
   if (spl) {
-    b0 = pd.S_rowptr[a] + 10 * q + g;
+    b0 = pd.S_rowptr[a] + gps * q + g;
     b1 = pd.S_rowptr[a + 1];
   }
   constexpr int kCgPre = cg_pre<T>();
@@ -1943,9 +1949,15 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     }
   }
   T wi = T(0);
+  if (Lr >= 64) {
 #pragma unroll
-  for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
-  if (lane < 6 && a < row1) s_w[rw][q][lane] = wi;
+    for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
+  } else {  // half-wave rows: the five groups of this half
+    const int sbase = t & 32;
+#pragma unroll
+    for (int gg = 0; gg < 5; ++gg) wi += __shfl(acc, sbase + 6 * gg + i, 64);
+  }
+  if (hs < 6 && a < row1) s_w[rw][q][hs] = wi;
   __syncthreads();
   if (own) {
     const size_t idx = 6 * (size_t)c + m;
@@ -1955,8 +1967,8 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     r1[idx] = rm;
     u1[idx] = um;
   }
-  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (waves 0 and 1)
-  if (t < 128) {
+  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (waves 0 to 3)
+  if (t < 256) {
     double g2 = 0.0, d2 = 0.0, q2 = 0.0;
     if (t < 6 * R) {
       const int rr_ = t / 6, mm = t - 6 * (t / 6);
@@ -1983,9 +1995,9 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   __syncthreads();
   if (t == 0) {
     double *pn = pd.part_cg[cu];
-    pn[tl.idx] = s_fin[0] + s_fin[3];
-    pn[nt + tl.idx] = s_fin[1] + s_fin[4];
-    pn[2 * nt + tl.idx] = s_fin[2] + s_fin[5];
+    pn[tl.idx] = s_fin[0] + s_fin[3] + s_fin[6] + s_fin[9];
+    pn[nt + tl.idx] = s_fin[1] + s_fin[4] + s_fin[7] + s_fin[10];
+    pn[2 * nt + tl.idx] = s_fin[2] + s_fin[5] + s_fin[8] + s_fin[11];
   }
 }
 

@@ -49,12 +49,14 @@ def test_config0_f64_per_iteration_cost_matches_dense_oracle(balib):
     assert res["status"] in (0, 1) and ref.status in (0, 1)
 
 
-def test_small_drive_f64_matches_schur_oracle_across_tiles(balib):
+@pytest.mark.parametrize("flags", [0, 8])
+def test_small_drive_f64_matches_schur_oracle_across_tiles(balib, flags):
     """Sequential drive with 12 point tiles and a ragged tail, FP64: per-iteration
-    cost within 1e-9 of the explicit-Schur oracle solved exactly."""
+    cost within 1e-9 of the explicit-Schur oracle solved exactly; also with the PCG
+    at 32 rows per workgroup (BA_FLAG_PCG_WIDE: one full and one ragged tile)."""
     s = make_small_drive(40, 3000, seed=5)
     ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=8, solve="exact"))
-    res = _solve(balib, s, max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64")
+    res = _solve(balib, s, max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64", flags=flags)
     rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
     _say("max rel cost diff", rel.max(), res["pcg_iters"])
     assert rel.max() <= 1e-9

@@ -53,16 +53,19 @@ def test_pose_graph_f64_per_iteration_cost(balib, mode, flags, prior_abs):
     assert res["n_masked"] == 0 and res["rms_px"] == 0.0
 
 
-def test_pose_graph_sparse_tiles_f64_pcg_schedule(balib):
+@pytest.mark.parametrize("flags,rows", [(0, 16), (8, 32)])
+def test_pose_graph_sparse_tiles_f64_pcg_schedule(balib, flags, rows):
     """1080 nodes (360 frames of the 3-camera rig): the reduced system has many sparse
-    rows, so the PCG runs 16 rows per workgroup.  FP64 with PCG capped at 100 products
-    and tol 1e-8 against the oracle's textbook PCG with the same schedule: PCG counts
-    identical and every C_n within 1e-8."""
+    rows, so the PCG runs 16 rows per workgroup (32, half a wave per row, with
+    BA_FLAG_PCG_WIDE).  FP64 with PCG capped at 100 products and tol 1e-8 against the
+    oracle's textbook PCG with the same schedule: PCG counts identical and every C_n
+    within 1e-8."""
     g = make_pose_graph(180)
     ref = O.lm_schur(_oracle_problem(g), O.LMOptions(max_iters=6, solve="pcg", pcg_max_iters=100,
                                                      pcg_rel_tol=1e-8))
-    res, info = _solve(balib, g, max_iters=6, pcg_max_iters=100, pcg_rel_tol=1e-8, precision="f64")
-    assert info["pcg_rows"] == 16
+    res, info = _solve(balib, g, max_iters=6, pcg_max_iters=100, pcg_rel_tol=1e-8, precision="f64",
+                       flags=flags)
+    assert info["pcg_rows"] == rows
     rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
     _say("sparse tiles: max rel cost diff", rel.max(), list(res["pcg_iters"]), ref.pcg_iters)
     assert list(res["pcg_iters"]) == list(ref.pcg_iters)
@@ -90,7 +93,7 @@ def test_pose_graph_full_size_cost_matches_oracle_at_device_state(balib):
     loop closures pull the second lap onto the first (cost below half the start)."""
     g = make_pose_graph(1500)
     res, info = _solve(balib, g, max_iters=10, precision="f32")
-    assert info["pcg_rows"] == 16
+    assert info["pcg_rows"] == 32
     p = _oracle_problem(g)
     c = O.prior_cost(p, O.quat_to_rot(res["q"]), res["t"])
     _say("full-size pose graph: device", res["cost"], "oracle", c, "start", res["iter_cost"][0], info["nnzb"])
