@@ -1060,6 +1060,9 @@ int Batch::upload(hipStream_t s) {
     *cnt[i] = (int32_t)tiles[i].size();
   }
   plan.n_probs = (int32_t)probs.size();
+  plan.pcg_rows = probs.empty() ? kPcgRows : probs[0].pcg_rows;
+  for (const ProbDev &pd : probs)
+    if (pd.pcg_rows != plan.pcg_rows) plan.pcg_rows = 0;
   if (probs.size() == 1) plan.single = probs[0];
   return BA_OK;
 }

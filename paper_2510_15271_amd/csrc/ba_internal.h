@@ -179,6 +179,7 @@ struct BatchPlan {
   const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh, *pri;
   int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh, n_pri;
   int32_t n_probs;
+  int32_t pcg_rows;  // rows per PCG tile shared by every problem of the batch, 0 if mixed
   ProbDev single;  // host copy of the descriptor when n_probs == 1 (passed by value to short kernels)
 };
 

@@ -1747,7 +1747,8 @@ __device__ inline void cg_column(int m, T tb, T ta, const T (&w0)[6], const T (&
     }
 }
 
-template <class T>
+// RC: the rows per tile when the launch knows them (4, 16, 32), else 0 (read per problem).
+template <class T, int RC>
 __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, int it) {
   extern __shared__ double s_dyn[];
   T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
@@ -1761,7 +1762,7 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
   const int nt = pd.n_pcg_tiles;
-  const int R = pd.pcg_rows;              // rows per tile: 4, 16 or 32
+  const int R = RC ? RC : pd.pcg_rows;    // rows per tile: 4, 16 or 32
   const int Lr = kCgThreads / R;          // lanes per row: 256, 64 or 32
   const int wpr = Lr >= 64 ? Lr / 64 : 1;  // waves per row (a half-wave row counts as one)
   const int row0 = tl.idx * R, row1 = min(pd.Cf, row0 + R);
@@ -1808,8 +1809,9 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     p0m = p0[6 * (size_t)c + m];
     xm = x[6 * (size_t)c + m];
   }
-  const int lane = t & 63, rw = t / Lr;
-  const int h = t - Lr * rw;                         // lane within the row
+  const int lrs = R == kPcgRows ? 8 : (R == kPcgRowsSparse ? 6 : 5);  // log2(Lr)
+  const int lane = t & 63, rw = t >> lrs;
+  const int h = t & (Lr - 1);                        // lane within the row
   const int q = Lr >= 64 ? (h >> 6) : 0;             // wave within the row
   const int hs = Lr >= 64 ? (h & 63) : h;            // lane within the row's wave segment
   const int gps = Lr >= 64 ? 10 : 5;                 // groups of 6 lanes per segment
@@ -1967,8 +1969,10 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     r1[idx] = rm;
     u1[idx] = um;
   }
-  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2 (waves 0 to 3)
-  if (t < 256) {
+  // ---- partials of gamma_{it+1}, delta_{it+1}, ||r_{it+1}||^2: wave 0 alone when the
+  // tile's 6 R elements fit in it, else waves 0 to 3 and one more barrier
+  const bool one_wave = 6 * R <= 64;
+  if (one_wave ? t < 64 : t < 256) {
     double g2 = 0.0, d2 = 0.0, q2 = 0.0;
     if (t < 6 * R) {
       const int rr_ = t / 6, mm = t - 6 * (t / 6);
@@ -1986,12 +1990,22 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
     g2 = wave_sum(g2);
     d2 = wave_sum(d2);
     q2 = wave_sum(q2);
+    if (one_wave) {
+      if (t == 0) {
+        double *pn = pd.part_cg[cu];
+        pn[tl.idx] = g2;
+        pn[nt + tl.idx] = d2;
+        pn[2 * nt + tl.idx] = q2;
+      }
+      return;
+    }
     if ((t & 63) == 0) {
       s_fin[3 * (t >> 6)] = g2;
       s_fin[3 * (t >> 6) + 1] = d2;
       s_fin[3 * (t >> 6) + 2] = q2;
     }
   }
+  if (one_wave) return;
   __syncthreads();
   if (t == 0) {
     double *pn = pd.part_cg[cu];
@@ -2001,20 +2015,42 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   }
 }
 
-template <class T>
+template <class T, int RC>
 __global__ __launch_bounds__(1024) void k_cg_step(const ProbDev *__restrict__ probs,
                                                   const Tile *__restrict__ tiles, int it) {
   const Tile tl = tiles[blockIdx.x];
-  cg_step_body<T>(probs[tl.prob], tl.idx, it);
+  cg_step_body<T, RC>(probs[tl.prob], tl.idx, it);
 }
 
 // The same step for a batch of one problem, its descriptor passed by value: the
 // launch saves the two dependent loads (tile table, descriptor) that precede
 // every other load of the step.
-template <class T>
+template <class T, int RC>
 __global__ __launch_bounds__(1024) void k_cg_step1(const ProbDev pd, int it) {
-  cg_step_body<T>(pd, blockIdx.x, it);
+  cg_step_body<T, RC>(pd, blockIdx.x, it);
 }
+
+// The step kernels of one compute type for a launch whose problems all tile their rows
+// by R (0: mixed, read per problem).
+template <class T>
+struct CgStep {
+  static const void *multi(int R) {
+    switch (R) {
+      case kPcgRows: return (const void *)k_cg_step<T, kPcgRows>;
+      case kPcgRowsSparse: return (const void *)k_cg_step<T, kPcgRowsSparse>;
+      case kPcgRowsMax: return (const void *)k_cg_step<T, kPcgRowsMax>;
+      default: return (const void *)k_cg_step<T, 0>;
+    }
+  }
+  static const void *single(int R) {
+    switch (R) {
+      case kPcgRows: return (const void *)k_cg_step1<T, kPcgRows>;
+      case kPcgRowsSparse: return (const void *)k_cg_step1<T, kPcgRowsSparse>;
+      case kPcgRowsMax: return (const void *)k_cg_step1<T, kPcgRowsMax>;
+      default: return (const void *)k_cg_step1<T, 0>;
+    }
+  }
+};
 
 // ------------------------------------------------------------------ camera update
 template <class T>
@@ -2559,14 +2595,12 @@ int prepare_kernels() {
   size_t use = lim > 8192 ? (size_t)lim - 4096 : 0;
   if (use > 48 * 1024) {
     // dynamic LDS beyond 48 KB must be allowed per kernel
-    if (hipFuncSetAttribute((const void *)k_cg_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)use) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_cg_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)use) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_cg_step1<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)use) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_cg_step1<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)use) != hipSuccess) {
+    bool ok = true;
+    for (int R : {0, kPcgRows, kPcgRowsSparse, kPcgRowsMax})
+      for (const void *f : {CgStep<float>::multi(R), CgStep<double>::multi(R), CgStep<float>::single(R),
+                            CgStep<double>::single(R)})
+        ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)use) == hipSuccess;
+    if (!ok) {
       (void)hipGetLastError();
       use = 48 * 1024;
     }
@@ -2659,12 +2693,21 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     // one event pair around the whole run: per-launch events would add their own
     // overhead to launches this short
     Timed t(tm, K_PCG_CG, s, pcg_max);
-    if (bp.n_probs == 1)
-      for (int it = 0; it < pcg_max; ++it)
-        k_cg_step1<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.single, it);
-    else
-      for (int it = 0; it < pcg_max; ++it)
-        k_cg_step<T><<<bp.n_pcg, kCgThreads, ubytes, s>>>(bp.probs, bp.pcg, it);
+    hipError_t le = hipSuccess;
+    if (bp.n_probs == 1) {
+      const void *f = CgStep<T>::single(bp.pcg_rows);
+      for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
+        void *args[] = {(void *)&bp.single, (void *)&it};
+        le = hipLaunchKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+      }
+    } else {
+      const void *f = CgStep<T>::multi(bp.pcg_rows);
+      for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
+        void *args[] = {(void *)&bp.probs, (void *)&bp.pcg, (void *)&it};
+        le = hipLaunchKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+      }
+    }
+    if (le != hipSuccess) return le;
   } else if (pcg) {
     for (int it = 0; it < pcg_max && bp.n_pcg; ++it) {
       {
