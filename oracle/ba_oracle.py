@@ -25,6 +25,9 @@ What it computes (paper: Sec. 4.3, Iterative Triangulation and Mapping):
   the nine rotation entries and one for the three translation entries.  It is the
   same machinery as the sequential prior with explicit pairs, measurements and
   weights, and no observations (``pose_graph_problem``);
+* vehicle-rig BA (Sec. 4.4): camera poses composed from shared camera-to-vehicle
+  extrinsics and per-frame vehicle poses, both unknown, with the absolute prior on the
+  extrinsics and the rigidity constraints of Eq. extrinsic (``RigProblem``, ``lm_rig``);
 * Levenberg-Marquardt with Marquardt diagonal scaling and Nielsen's damping
   schedule (Madsen, Nielsen, Tingleff 2004, Sec. 3.2), left SE(3) increments;
 * three solvers of the damped normal equations (H + lambda D) delta = -g:
@@ -848,3 +851,216 @@ def pose_graph_problem(R0, t0, fixed, edges, meas_R, meas_t, w_rot, w_trans, pri
                    cam=np.zeros(0, np.int64), pt=np.zeros(0, np.int64), uv=np.zeros((0, 2)),
                    fixed=np.asarray(fixed).astype(bool), delta=0.0, prior_abs=float(prior_abs),
                    pairs=edges, pair_meas=meas, pair_w=w)
+
+
+# ----------------------------------------------------------------------------- vehicle-rig BA
+
+@dataclasses.dataclass
+class RigProblem:
+    """Bundle adjustment in the vehicle-rig configuration (Sec. 4.4): the pose of rig
+    camera c at frame f is the composition T_(f,c) = E_c T_v(f) of the camera's extrinsic
+    E_c = T_c^v (vehicle -> camera) and the vehicle pose T_v(f) (world -> vehicle), both
+    unknown; extrinsics are shared by every frame.  Terms: the reprojection error of
+    Sec. 4.4 (with rho and the masking of the BA problem), the absolute prior on the
+    extrinsics 1/2 lambda_e sum_c ||E_c - E_c,init||^2 and the rigidity constraints
+    of Eq. extrinsic between rig cameras, which in this configuration depend on the
+    extrinsics alone: 1/2 lambda_r ||E_c E_d^-1 - E_c,init E_d,init^-1||^2."""
+    K: np.ndarray          # (nr, 4) intrinsics of each rig camera
+    Rv: np.ndarray         # (F, 3, 3) world -> vehicle
+    tv: np.ndarray         # (F, 3)
+    Re: np.ndarray         # (nr, 3, 3) vehicle -> camera
+    te: np.ndarray         # (nr, 3)
+    X: np.ndarray          # (P, 3)
+    frame: np.ndarray      # (N,)
+    rcam: np.ndarray       # (N,)
+    pt: np.ndarray         # (N,)
+    uv: np.ndarray         # (N, 2)
+    fixed_v: np.ndarray    # (F,) bool
+    fixed_e: np.ndarray    # (nr,) bool
+    delta: float
+    prior_ext: float = 0.0             # lambda_e
+    rig_pairs: np.ndarray | None = None  # (E, 2) rig camera pairs of the rigidity terms
+    prior_rig: float = 0.0             # lambda_r
+    Re0: np.ndarray | None = None
+    te0: np.ndarray | None = None
+
+    def __post_init__(self):
+        if self.Re0 is None:
+            self.Re0 = np.array(self.Re, np.float64)
+        if self.te0 is None:
+            self.te0 = np.array(self.te, np.float64)
+        if self.rig_pairs is None:
+            self.rig_pairs = np.zeros((0, 2), np.int64)
+
+    @property
+    def n_frames(self):
+        return self.Rv.shape[0]
+
+    @property
+    def n_rig(self):
+        return self.Re.shape[0]
+
+
+def rig_adjoint(R: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Ad_E for E = (R, t) acting on xi = (rho, phi): E Exp(xi) E^-1 = Exp(Ad_E xi),
+    Ad_E = [[R, [t]x R], [0, R]]."""
+    A = np.zeros((6, 6))
+    A[:3, :3] = R
+    A[:3, 3:] = hat(t) @ R
+    A[3:, 3:] = R
+    return A
+
+
+def rig_camera_problem(q: RigProblem, Rv=None, tv=None, Re=None, te=None, X=None) -> Problem:
+    """The same observations as a BA problem over the composed cameras (f, c), camera
+    index f * nr + c, T_(f,c) = E_c T_v(f): R = R_e R_v, t = R_e t_v + t_e."""
+    Rv = q.Rv if Rv is None else Rv
+    tv = q.tv if tv is None else tv
+    Re = q.Re if Re is None else Re
+    te = q.te if te is None else te
+    X = q.X if X is None else X
+    F, nr = Rv.shape[0], Re.shape[0]
+    R = np.einsum("cij,fjk->fcik", Re, Rv).reshape(F * nr, 3, 3)
+    t = (np.einsum("cij,fj->fci", Re, tv) + te[None]).reshape(F * nr, 3)
+    return Problem(K=np.tile(q.K, (F, 1)), R=R, t=t, X=X, cam=q.frame * nr + q.rcam, pt=q.pt, uv=q.uv,
+                   fixed=np.zeros(F * nr, bool), delta=q.delta)
+
+
+def rig_extrinsic_view(q: RigProblem, Re=None, te=None) -> Problem:
+    """The extrinsic terms as relative-pose priors over the extrinsics: the absolute
+    prior (lambda_e, anchored at the initial extrinsics) and the rigidity pairs (weight
+    lambda_r on every entry, measured from the initial extrinsics)."""
+    Re = q.Re if Re is None else Re
+    te = q.te if te is None else te
+    nr = Re.shape[0]
+    meas = []
+    for c, d in q.rig_pairs:
+        RA = q.Re0[c] @ q.Re0[d].T
+        meas.append(_pose_rows(RA, q.te0[c] - RA @ q.te0[d]))
+    return Problem(K=np.ones((nr, 4)), R=Re, t=te, X=np.zeros((0, 3)), cam=np.zeros(0, np.int64),
+                   pt=np.zeros(0, np.int64), uv=np.zeros((0, 2)), fixed=np.asarray(q.fixed_e, bool), delta=0.0,
+                   prior_abs=q.prior_ext, R0=q.Re0, t0=q.te0, pairs=np.asarray(q.rig_pairs, np.int64).reshape(-1, 2),
+                   pair_meas=np.array(meas).reshape(-1, 12),
+                   pair_w=np.full((len(q.rig_pairs), 2), q.prior_rig))
+
+
+def rig_cost_and_masked(q: RigProblem, Rv=None, tv=None, Re=None, te=None, X=None):
+    C, masked = cost_and_masked(rig_camera_problem(q, Rv, tv, Re, te, X))
+    v = rig_extrinsic_view(q, Re, te)
+    if has_priors(v):
+        C += prior_cost(v)
+    return C, masked
+
+
+def rig_normal_equations(q: RigProblem):
+    """H = J^T W J and g = J^T W r over [free vehicle increments | free extrinsic
+    increments | point increments], with the camera Jacobian of each observation split
+    by the chain rule: d/dxi_v = J_c Ad_(E_c) (T_v <- Exp(xi_v) T_v moves the camera by
+    Exp(Ad_E xi_v)), d/dxi_e = J_c; plus the extrinsic prior rows."""
+    p = rig_camera_problem(q)
+    r, valid, _ = residuals(p)
+    Jc, Jp = jacobians(p)
+    s = np.sum(r * r, axis=1)
+    w = np.where(valid & p.active, huber_weight(s, p.delta), 0.0)
+    vidx, nv = _free_index(np.asarray(q.fixed_v, bool))
+    eidx, ne = _free_index(np.asarray(q.fixed_e, bool))
+    N = p.n_obs
+    n = 6 * nv + 6 * ne + 3 * q.X.shape[0]
+    Ad = np.stack([rig_adjoint(q.Re[c], q.te[c]) for c in range(q.n_rig)])
+    Jv = np.einsum("nij,njk->nik", Jc, Ad[q.rcam])
+    rows, cols, vals = [], [], []
+    fv, fe = vidx[q.frame], eidx[q.rcam]
+    for comp in range(2):
+        rr = 2 * np.arange(N) + comp
+        for m in range(6):
+            hv, he = fv >= 0, fe >= 0
+            rows += [rr[hv], rr[he]]
+            cols += [6 * fv[hv] + m, 6 * nv + 6 * fe[he] + m]
+            vals += [Jv[hv, comp, m], Jc[he, comp, m]]
+        for m in range(3):
+            rows.append(rr)
+            cols.append(6 * nv + 6 * ne + 3 * q.pt + m)
+            vals.append(Jp[:, comp, m])
+    J = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(2 * N, n))
+    Wd = sp.diags(np.repeat(w, 2))
+    H = (J.T @ Wd @ J).tocsr()
+    g = J.T @ (np.repeat(w, 2) * r.reshape(-1))
+    v = rig_extrinsic_view(q)
+    if has_priors(v):
+        Jr, rp = prior_system(v, 6 * ne)
+        Jr = sp.hstack([sp.csr_matrix((Jr.shape[0], 6 * nv)), Jr, sp.csr_matrix((Jr.shape[0], 3 * q.X.shape[0]))])
+        H = (H + Jr.T @ Jr).tocsr()
+        g = g + Jr.T @ rp
+    return H, np.asarray(g).ravel()
+
+
+def rig_apply_step(q: RigProblem, delta: np.ndarray):
+    """T_v(f) <- Exp(d_v) T_v(f), E_c <- Exp(d_e) E_c for free ones, X <- X + d_p."""
+    vidx, nv = _free_index(np.asarray(q.fixed_v, bool))
+    eidx, ne = _free_index(np.asarray(q.fixed_e, bool))
+    Rv, tv, Re, te = q.Rv.copy(), q.tv.copy(), q.Re.copy(), q.te.copy()
+    fv, fe = np.nonzero(vidx >= 0)[0], np.nonzero(eidx >= 0)[0]
+    if nv:
+        dR, dt = se3_exp(delta[:6 * nv].reshape(nv, 6))
+        Rv[fv] = dR @ q.Rv[fv]
+        tv[fv] = np.einsum("nij,nj->ni", dR, q.tv[fv]) + dt
+    if ne:
+        dR, dt = se3_exp(delta[6 * nv:6 * (nv + ne)].reshape(ne, 6))
+        Re[fe] = dR @ q.Re[fe]
+        te[fe] = np.einsum("nij,nj->ni", dR, q.te[fe]) + dt
+    X = q.X + delta[6 * (nv + ne):].reshape(-1, 3)
+    return Rv, tv, Re, te, X
+
+
+def lm_rig(q: RigProblem, opts: LMOptions | None = None) -> LMResult:
+    """Levenberg-Marquardt on the vehicle-rig problem with the schedule of _lm_loop
+    (Marquardt scaling on the rig Hessian's diagonal, Nielsen damping, rejection of steps
+    that mask more observations, fixed iteration count), the damped normal equations
+    solved by dense Cholesky.  The result's R, t hold the vehicle poses; the extrinsics
+    are returned in ``ext`` = (Re, te)."""
+    opts = opts or LMOptions()
+    q = dataclasses.replace(q, Rv=q.Rv.copy(), tv=q.tv.copy(), Re=q.Re.copy(), te=q.te.copy(), X=q.X.copy())
+    lam, nu = opts.lambda0, 2.0
+    C, masked = rig_cost_and_masked(q)
+    out = LMResult(q.Rv, q.tv, q.X, [C], [], [], [], [], STATUS_OK)
+    lin = None
+    for _ in range(opts.max_iters):
+        if lin is None:
+            lin = rig_normal_equations(q)
+        H, g = lin
+        D = damping_diag(H.diagonal())
+        delta, _ = _dense_step(None, H, g, D, lam, opts)
+        out.lambdas.append(lam)
+        out.pcg_iters.append(0)
+        if delta is None:
+            out.rhos.append(float("nan"))
+            out.accepted.append(False)
+            lam = min(max(lam * nu, LAMBDA_MIN), LAMBDA_MAX)
+            nu = 2.0 * nu
+            out.iter_cost.append(C)
+            continue
+        dL = 0.5 * float(delta @ (lam * D * delta - g))
+        Rv, tv, Re, te, X = rig_apply_step(q, delta)
+        Cn, masked_n = rig_cost_and_masked(q, Rv, tv, Re, te, X)
+        rho = (C - Cn) / dL if dL != 0 else -np.inf
+        out.rhos.append(rho)
+        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO and masked_n <= masked:
+            q.Rv, q.tv, q.Re, q.te, q.X = Rv, tv, Re, te, X
+            C, masked = Cn, masked_n
+            lam = lam * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+            lin = None
+            out.accepted.append(True)
+        else:
+            lam = lam * nu
+            nu = 2.0 * nu
+            out.accepted.append(False)
+        lam = min(max(lam, LAMBDA_MIN), LAMBDA_MAX)
+        out.iter_cost.append(C)
+    if not np.isfinite(C):
+        out.status = STATUS_NUMERICAL
+    elif lam >= LAMBDA_MAX:
+        out.status = STATUS_DAMPING
+    out.R, out.t, out.X = q.Rv, q.tv, q.X
+    out.ext = (q.Re, q.te)
+    return out

@@ -8,5 +8,5 @@ from .scenes import (  # noqa: F401
     Scene, PoseRequest, make_config0, make_config1, make_config2, make_arc_scene,
     make_config3_sizes, make_config3_problem, make_config4_requests, make_small_drive,
     save_scene, load_scene, IMG_W, IMG_H, FX, FY, CX, CY,
-    PoseGraph, make_pose_graph, EDGE_SEQUENTIAL, EDGE_LOOP, EDGE_EXTRINSIC,
+    PoseGraph, make_pose_graph, EDGE_SEQUENTIAL, EDGE_LOOP, EDGE_EXTRINSIC, RigScene, make_rig_drive,
 )

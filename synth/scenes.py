@@ -534,7 +534,7 @@ def _rig_extrinsics(n_rig: int):
     """Vehicle->camera transforms of a rig: camera c yawed by c * 60 degrees
     (alternating sides) about the vehicle's down axis, mounted 0.5 m from the
     vehicle origin along its optical axis."""
-    yaws = [0.0] + [s * (60.0 * ((c + 1) // 2)) for c, s in zip(range(n_rig - 1), [1, -1] * n_rig)]
+    yaws = [0.0] + [(1 if k % 2 else -1) * 60.0 * ((k + 1) // 2) for k in range(1, n_rig)]
     out = []
     for yaw in yaws:
         Ry = Rotation.from_euler("y", yaw, degrees=True)  # camera axes in the vehicle frame
@@ -661,3 +661,144 @@ def make_pose_graph(n_frames: int = 1500, laps: int = 2, n_rig: int = 3, mode: s
                      fixed=fixed, edge_i=np.array(ei, np.int32), edge_j=np.array(ej, np.int32),
                      meas_q=np.array(mq), meas_t=np.array(mt), w_rot=np.array(wr), w_trans=np.array(wt),
                      edge_type=np.array(ty, np.int32), meta=meta)
+
+
+# ----------------------------------------------------------------------------- vehicle-rig drives
+
+@dataclasses.dataclass
+class RigScene:
+    """Observations of a multi-camera rig on a vehicle: rig camera c at frame f has the
+    world->camera pose E_c T_v(f) (extrinsic E_c = vehicle -> camera, T_v(f) = world ->
+    vehicle).  Quaternions are (w, x, y, z)."""
+    name: str
+    K: np.ndarray          # (nr, 4)
+    qv_gt: np.ndarray      # (F, 4) world -> vehicle
+    tv_gt: np.ndarray      # (F, 3)
+    qe_gt: np.ndarray      # (nr, 4) vehicle -> camera
+    te_gt: np.ndarray      # (nr, 3)
+    qv0: np.ndarray        # initial vehicle poses (drifted)
+    tv0: np.ndarray
+    qe0: np.ndarray        # initial extrinsics (calibration error)
+    te0: np.ndarray
+    X_gt: np.ndarray       # (P, 3)
+    X0: np.ndarray
+    frame: np.ndarray      # (N,) int32
+    rcam: np.ndarray       # (N,) int32
+    obs_pt: np.ndarray     # (N,) int32
+    obs_uv: np.ndarray     # (N, 2)
+    fixed_v: np.ndarray    # (F,) uint8
+    fixed_e: np.ndarray    # (nr,) uint8
+    sigma: float
+    meta: dict
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.qv0.shape[0])
+
+    @property
+    def n_rig(self) -> int:
+        return int(self.qe0.shape[0])
+
+    @property
+    def n_pts(self) -> int:
+        return int(self.X0.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.frame.shape[0])
+
+
+def make_rig_drive(n_frames: int = 200, n_pts: int = 20000, n_rig: int = 3, seed: int = 1006,
+                   sigma: float = 0.7, ext_rot: float = 0.01, ext_trans: float = 0.02,
+                   mean_track: float = 8.0, cross_frames: int = 20, name: str | None = None) -> RigScene:
+    """A drive of ``n_frames`` frames 1 m apart (heading 0.3 sin(2 pi s / 500), as the
+    sequential drive) with an ``n_rig``-camera rig (yaws 0, +-60 degrees, 0.5 m from the
+    vehicle origin).  Each point is tracked by one rig camera over consecutive frames
+    (track length 1 + Geom, mean ``mean_track``, points 3-40 m away); the other rig
+    cameras observe it too wherever it is in their view during the track's frames and
+    the ``cross_frames`` frames after them (a point ahead of the vehicle passes into a
+    side camera), which ties the extrinsics together.  Pixel noise sigma.
+    Initial state: vehicle poses with the drive's random-walk drift (0.002 rad, 0.01 m
+    per frame), extrinsics off their true values by Exp of (ext_trans, ext_rot) noise per
+    axis (the calibration error the refinement corrects), points carried with the
+    drifted pose plus 0.05 m noise.  Frame 0 is fixed; the extrinsics are free."""
+    rng = np.random.default_rng(seed)
+    s_idx = np.arange(n_frames, dtype=np.float64)
+    R_wv, cv = _drive_poses(0.3 * np.sin(2 * np.pi * s_idx / 500.0))
+    ext = _rig_extrinsics(n_rig)
+    Rv = Rotation.from_matrix(np.transpose(R_wv, (0, 2, 1)))
+    tv = -Rv.apply(cv)
+    cams, pts, uvs, Xs, tracks = [], [], [], [], []
+    per = n_pts // n_rig
+    base = 0
+    for c, (Re, te) in enumerate(ext):
+        Rc = Re * Rv                          # world -> camera c at every frame
+        tcm = Re.apply(tv) + te
+        R_wc = np.transpose(Rc.as_matrix(), (0, 2, 1))
+        cc = -np.einsum("nij,nj->ni", R_wc, tcm)  # camera centres
+        starts = rng.integers(0, n_frames - 1, per)
+        L = _track_lengths(rng, per, 1.0 / (mean_track - 1.0), n_frames, starts)
+        X, starts, L = _place_tracks(rng, R_wc, cc, starts, L, 3.0, 40.0)
+        keep = L >= 2
+        X, starts, L = X[keep], starts[keep], L[keep]
+        tracks.append((base, X, starts, L, c))
+        Xs.append(X)
+        base += X.shape[0]
+    # every rig camera's view of every point over its track's frames (plus cross_frames)
+    cam_R_wc, cam_c = [], []
+    for Re, te in ext:
+        Rc = Re * Rv
+        R_wc = np.transpose(Rc.as_matrix(), (0, 2, 1))
+        cam_R_wc.append(R_wc)
+        cam_c.append(-np.einsum("nij,nj->ni", R_wc, Re.apply(tv) + te))
+    for b0, X, starts, L, c0 in tracks:
+        for c in range(n_rig):
+            span = L if c == c0 else np.minimum(L + cross_frames, n_frames - starts)
+            for o in range(int(span.max()) if span.size else 0):
+                m = o < span
+                f = (starts[m] + o).astype(np.int32)
+                j = np.nonzero(m)[0]
+                vis, u, v = _in_view(np.transpose(cam_R_wc[c][f], (0, 2, 1)), cam_c[c][f], X[j])
+                cams.append(np.stack([f[vis], np.full(int(vis.sum()), c, np.int32)], axis=1))
+                pts.append((b0 + j[vis]).astype(np.int32))
+                uvs.append(np.stack([u[vis], v[vis]], axis=1))
+    fc = np.concatenate(cams)
+    pt = np.concatenate(pts)
+    uv = np.concatenate(uvs) + sigma * rng.standard_normal((pt.size, 2))
+    X_gt = np.concatenate(Xs)
+    # drifted vehicle trajectory (frame 0 exact), perturbed extrinsics
+    wdr, tdr = _drift(rng, n_frames, 0.002, 0.01)
+    Rt_wv = np.einsum("nij,njk->nik", _rotvec_to_matrix(wdr), R_wv)
+    ct = cv + tdr
+    Rv0 = Rotation.from_matrix(np.transpose(Rt_wv, (0, 2, 1)))
+    tv0 = -Rv0.apply(ct)
+    Ee = [(Rotation.from_rotvec(rng.normal(0, ext_rot, 3)) * Re, te + rng.normal(0, ext_trans, 3))
+          for Re, te in ext]
+    # initial points: true point seen from its first frame and camera, carried with the
+    # drifted vehicle pose and the perturbed extrinsic of that camera
+    first_f = np.zeros(X_gt.shape[0], np.int64)
+    cam_of = np.zeros(X_gt.shape[0], np.int32)
+    for b0, X, starts, L, c0 in tracks:
+        first_f[b0:b0 + X.shape[0]] = starts
+        cam_of[b0:b0 + X.shape[0]] = c0
+    X0 = np.empty_like(X_gt)
+    for c, (Re, te) in enumerate(ext):
+        m = cam_of == c
+        f = first_f[m]
+        Pc = Re.apply(Rv[f].apply(X_gt[m]) + tv[f]) + te          # true camera frame
+        Re0, te0 = Ee[c]
+        Pv = Re0.inv().apply(Pc - te0)                                 # through the initial extrinsic
+        X0[m] = Rv0[f].inv().apply(Pv - tv0[f])                        # and the drifted vehicle pose
+    X0 = X0 + rng.normal(0.0, 0.05, X0.shape)
+    fixed_v = np.zeros(n_frames, np.uint8)
+    fixed_v[0] = 1
+    q = lambda R: R.as_quat()[..., [3, 0, 1, 2]]
+    meta = dict(kind="rig_drive", seed=seed, n_frames=n_frames, n_rig=n_rig, n_pts=int(X_gt.shape[0]),
+                n_obs=int(pt.size))
+    return RigScene(name=name or f"rig_drive_{n_frames}x{n_rig}", K=np.tile(np.array([FX, FY, CX, CY]), (n_rig, 1)),
+                    qv_gt=q(Rv), tv_gt=tv, qe_gt=np.stack([q(R) for R, _ in ext]),
+                    te_gt=np.stack([t for _, t in ext]), qv0=q(Rv0), tv0=tv0,
+                    qe0=np.stack([q(R) for R, _ in Ee]), te0=np.stack([t for _, t in Ee]),
+                    X_gt=X_gt, X0=X0, frame=fc[:, 0].astype(np.int32), rcam=fc[:, 1].astype(np.int32),
+                    obs_pt=pt, obs_uv=uv, fixed_v=fixed_v, fixed_e=np.zeros(n_rig, np.uint8),
+                    sigma=float(sigma), meta=meta)

@@ -605,3 +605,125 @@ def test_pose_graph_cost_is_invariant_to_the_world_frame():
     t2 = p.t + np.einsum("nij,j->ni", p.R, tau)
     c1, c2 = O.prior_cost(p), O.prior_cost(p, R2, t2)
     assert abs(c1 - c2) <= 1e-10 * c1
+
+
+# ----------------------------------------------------------------------------- vehicle-rig BA
+
+def _rig_problem(s, gt=False, **kw):
+    qv, tv, qe, te, X = (s.qv_gt, s.tv_gt, s.qe_gt, s.te_gt, s.X_gt) if gt else (s.qv0, s.tv0, s.qe0, s.te0, s.X0)
+    return O.RigProblem(K=s.K, Rv=O.quat_to_rot(qv), tv=np.array(tv), Re=O.quat_to_rot(qe), te=np.array(te),
+                        X=np.array(X), frame=s.frame.astype(np.int64), rcam=s.rcam.astype(np.int64),
+                        pt=s.obs_pt.astype(np.int64), uv=s.obs_uv, fixed_v=s.fixed_v.astype(bool),
+                        fixed_e=s.fixed_e.astype(bool), delta=kw.pop("delta", 0.0), **kw)
+
+
+def test_rig_gradient_matches_central_differences():
+    """g = J^T W r of the rig problem (Huber, extrinsic prior, rigidity pairs) against
+    central differences of C over left increments of every free vehicle pose and
+    extrinsic and over every point coordinate."""
+    from synth import make_rig_drive
+    s = make_rig_drive(6, 60, seed=7)
+    q = _rig_problem(s, delta=1.0, prior_ext=3.0, rig_pairs=np.array([[0, 1], [2, 0]]), prior_rig=5.0)
+    _, g = O.rig_normal_equations(q)
+    vfree, efree = np.nonzero(~q.fixed_v)[0], np.nonzero(~q.fixed_e)[0]
+    h = 1e-6
+    fd = np.zeros_like(g)
+    col = 0
+    for kind, idx in (("v", vfree), ("e", efree)):
+        for a in idx:
+            for m in range(6):
+                xi = np.zeros(6)
+                xi[m] = h
+                cs = []
+                for sgn in (1, -1):
+                    dR, dt = O.se3_exp(sgn * xi)
+                    Rv, tv, Re, te = q.Rv.copy(), q.tv.copy(), q.Re.copy(), q.te.copy()
+                    if kind == "v":
+                        Rv[a], tv[a] = dR @ q.Rv[a], dR @ q.tv[a] + dt
+                    else:
+                        Re[a], te[a] = dR @ q.Re[a], dR @ q.te[a] + dt
+                    cs.append(O.rig_cost_and_masked(q, Rv, tv, Re, te)[0])
+                fd[col] = (cs[0] - cs[1]) / (2 * h)
+                col += 1
+    for j in range(q.X.shape[0]):
+        for m in range(3):
+            cs = []
+            for sgn in (1, -1):
+                X = q.X.copy()
+                X[j, m] += sgn * h
+                cs.append(O.rig_cost_and_masked(q, X=X)[0])
+            fd[col] = (cs[0] - cs[1]) / (2 * h)
+            col += 1
+    assert np.max(np.abs(fd - g)) <= 1e-5 * (1 + np.max(np.abs(g)))
+
+
+def test_rig_with_one_identity_camera_is_plain_ba():
+    """One rig camera whose extrinsic is the identity and held fixed: the vehicle poses
+    are the camera poses, and lm_rig takes the iterates of lm_dense on that BA problem."""
+    from synth import make_rig_drive
+    s = make_rig_drive(8, 200, n_rig=1, seed=8)
+    q = _rig_problem(s)
+    q.Re[:] = np.eye(3)
+    q.te[:] = 0.0
+    q.Re0, q.te0 = q.Re.copy(), q.te.copy()
+    q.fixed_e[:] = True
+    p = O.rig_camera_problem(q)
+    p.fixed = q.fixed_v.copy()
+    a = O.lm_rig(q, O.LMOptions(max_iters=8))
+    b = O.lm_dense(p, O.LMOptions(max_iters=8))
+    rel = np.abs(np.array(a.iter_cost) - np.array(b.iter_cost)) / np.array(b.iter_cost)
+    assert rel.max() <= 1e-12
+    assert np.max(np.abs(a.R - b.R)) <= 1e-12
+
+
+def test_rig_noiseless_recovers_truth():
+    """Noiseless pixels, drifted vehicles, perturbed extrinsics and points, frame 0 fixed,
+    and the extrinsic prior anchored at the true calibration: the truth is the one state
+    of zero cost, and LM reaches it (vehicle poses, extrinsics and points).  (Without an
+    anchor the rig keeps a gauge: a point seen by one camera can follow a change of that
+    camera's extrinsic translation together with the vehicle translations, so only the
+    prior, or more cameras sharing points, fixes the extrinsic translations.)"""
+    from synth import make_rig_drive
+    s = make_rig_drive(10, 300, seed=9, sigma=0.0)
+    q = _rig_problem(s, prior_ext=1.0, Re0=O.quat_to_rot(s.qe_gt), te0=np.array(s.te_gt))
+    r = O.lm_rig(q, O.LMOptions(max_iters=30))
+    Re, te = r.ext
+    assert r.iter_cost[-1] <= 1e-20 * r.iter_cost[0]
+    assert np.max(np.abs(Re - O.quat_to_rot(s.qe_gt))) <= 1e-8
+    assert np.max(np.abs(te - s.te_gt)) <= 1e-8
+    assert np.max(np.abs(r.R - O.quat_to_rot(s.qv_gt))) <= 1e-8
+    assert np.max(np.abs(r.t - s.tv_gt)) <= 1e-7 and np.max(np.abs(r.X - s.X_gt)) <= 1e-6
+
+
+def test_rig_optimum_matches_scipy_least_squares():
+    """Pixel noise, extrinsic prior and rigidity pairs: the cost lm_rig reaches equals
+    the minimum SciPy least_squares finds over rotation vectors, translations and points."""
+    from synth import make_rig_drive
+    s = make_rig_drive(6, 80, seed=10)
+    q = _rig_problem(s, prior_ext=10.0, rig_pairs=np.array([[0, 1], [0, 2]]), prior_rig=10.0)
+    r = O.lm_rig(q, O.LMOptions(max_iters=40))
+    vf, ef = np.nonzero(~q.fixed_v)[0], np.nonzero(~q.fixed_e)[0]
+
+    def unpack(x):
+        Rv, tv, Re, te = q.Rv.copy(), q.tv.copy(), q.Re.copy(), q.te.copy()
+        o = 0
+        Rv[vf] = Rotation.from_rotvec(x[o:o + 3 * vf.size].reshape(-1, 3)).as_matrix(); o += 3 * vf.size
+        tv[vf] = x[o:o + 3 * vf.size].reshape(-1, 3); o += 3 * vf.size
+        Re[ef] = Rotation.from_rotvec(x[o:o + 3 * ef.size].reshape(-1, 3)).as_matrix(); o += 3 * ef.size
+        te[ef] = x[o:o + 3 * ef.size].reshape(-1, 3); o += 3 * ef.size
+        return Rv, tv, Re, te, x[o:].reshape(-1, 3)
+
+    def f(x):
+        Rv, tv, Re, te, X = unpack(x)
+        r_, _, _ = O.residuals(O.rig_camera_problem(q, Rv, tv, Re, te, X))
+        v = O.rig_extrinsic_view(q, Re, te)
+        ra, rc = O.prior_residuals(v)
+        return np.concatenate([r_.reshape(-1), math.sqrt(q.prior_ext) * ra.reshape(-1),
+                               (np.sqrt(O.pair_row_weights(v)) * rc).reshape(-1)])
+
+    x0 = np.concatenate([Rotation.from_matrix(q.Rv[vf]).as_rotvec().reshape(-1), q.tv[vf].reshape(-1),
+                         Rotation.from_matrix(q.Re[ef]).as_rotvec().reshape(-1), q.te[ef].reshape(-1),
+                         q.X.reshape(-1)])
+    ref = scipy.optimize.least_squares(f, x0, xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    c_ref = 0.5 * float(ref.fun @ ref.fun)
+    assert abs(r.iter_cost[-1] - c_ref) <= 1e-9 * c_ref
