@@ -279,6 +279,51 @@ typedef struct {                 /* host memory                                 
 int ba_pose_graph_create(const ba_pose_graph_desc *g, const ba_options *opt, void *hip_stream,
                          ba_problem **out);
 
+/* ---------------------------------------------------------------- vehicle rigs
+   Extrinsic refinement in the vehicle-rig configuration (paper Sec. 4.4): the pose
+   of rig camera c at frame f is the composition T_(f,c) = E_c T_v(f) of the camera's
+   extrinsic E_c = T_c^v (vehicle -> camera, shared by every frame) and the vehicle pose
+   T_v(f) (world -> vehicle), and both are unknowns next to the points.  C gains
+     1/2 prior_ext sum_c ||E_c - E_c,init||^2                 (Sec. 4.4 absolute prior)
+     1/2 prior_rig sum_pairs ||E_c E_d^-1 - E_c,init E_d,init^-1||^2
+   (the rigidity constraint of Eq. extrinsic between rig cameras, which in this
+   configuration depends on the extrinsics alone), as 3x4 Frobenius norms.  Updates:
+   T_v <- Exp(xi_v) T_v, E_c <- Exp(xi_e) E_c.  The reprojection terms, loss, masking,
+   damping schedule and PCG are those of BA; the Marquardt diagonal is that of the rig
+   unknowns.  Without prior_ext (or a fixed extrinsic) the rig keeps a gauge: the
+   vehicle frame is only defined up to a rigid motion shared by the extrinsics.
+   ba_solve, ba_solve_async / ba_wait, ba_reset, ba_get_info, profiling and ba_destroy
+   apply; ba_get_result returns the composed camera poses (n_frames * n_rig, camera
+   f * n_rig + c), ba_rig_get_result the vehicle poses and extrinsics; ba_refine does
+   not apply (BA_EINVAL).
+   Options as for BA; prior_abs and prior_seq must be 0 (the rig's priors are given
+   here).  BA_EINVAL: n_frames < 1, n_rig outside 1..16, a camera, frame or point index
+   out of range, a duplicate (frame, camera, point), a bad quaternion, non-finite data,
+   negative or non-finite prior weights, a rigidity pair of one camera with itself or
+   given twice, nothing free, or bad options. */
+#define BA_RIG_MAX_CAMS 16
+typedef struct { int32_t frame, cam, pt, reserved; double u, v; } ba_rig_obs;
+typedef struct {                 /* host memory                                           */
+  int32_t n_frames, n_rig;
+  const ba_intrinsics *K;        /* n_rig, one per rig camera                             */
+  const ba_pose *vehicle_poses;  /* n_frames initial world -> vehicle poses               */
+  const ba_pose *extrinsics;     /* n_rig initial vehicle -> camera poses (T_c^v)         */
+  const uint8_t *vehicle_fixed;  /* n_frames flags, or NULL                               */
+  const uint8_t *extrinsic_fixed; /* n_rig flags, or NULL                                  */
+  int32_t n_pts;
+  const double *points_xyz;      /* 3 * n_pts                                             */
+  int64_t n_obs;
+  const ba_rig_obs *obs;
+  double prior_ext;              /* lambda_e >= 0                                          */
+  double prior_rig;              /* lambda_r >= 0                                          */
+  int32_t n_rig_pairs;
+  const int32_t *rig_pairs;      /* 2 * n_rig_pairs rig camera indices                    */
+} ba_rig_desc;
+int ba_rig_create(const ba_rig_desc *r, const ba_options *opt, void *hip_stream, ba_problem **out);
+/* vehicles_out: n_frames, extrinsics_out: n_rig, points_out: 3 * n_pts; NULL skips. */
+int ba_rig_get_result(const ba_problem *p, ba_pose *vehicles_out, ba_pose *extrinsics_out, double *points_out,
+                      ba_report *rep);
+
 /* ---------------------------------------------------------------- pose-only */
 typedef struct {                 /* one localization request (host memory)             */
   ba_intrinsics K;

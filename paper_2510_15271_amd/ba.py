@@ -78,6 +78,14 @@ class PoseGraphDesc(C.Structure):
                 ("n_edges", C.c_int64), ("edges", C.c_void_p)]
 
 
+class RigDesc(C.Structure):
+    _fields_ = [("n_frames", C.c_int32), ("n_rig", C.c_int32), ("K", C.c_void_p),
+                ("vehicle_poses", C.c_void_p), ("extrinsics", C.c_void_p), ("vehicle_fixed", C.c_void_p),
+                ("extrinsic_fixed", C.c_void_p), ("n_pts", C.c_int32), ("points_xyz", C.c_void_p),
+                ("n_obs", C.c_int64), ("obs", C.c_void_p), ("prior_ext", C.c_double), ("prior_rig", C.c_double),
+                ("n_rig_pairs", C.c_int32), ("rig_pairs", C.c_void_p)]
+
+
 class RefineStage(C.Structure):
     _fields_ = [("huber_delta", C.c_double), ("cull_px", C.c_double)]
 
@@ -95,6 +103,8 @@ class ServerStats(C.Structure):
 
 
 OBS_DTYPE = np.dtype([("cam", "<i4"), ("pt", "<i4"), ("u", "<f8"), ("v", "<f8")])
+RIG_OBS_DTYPE = np.dtype([("frame", "<i4"), ("cam", "<i4"), ("pt", "<i4"), ("reserved", "<i4"),
+                          ("u", "<f8"), ("v", "<f8")])
 EDGE_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("type", "<i4"), ("reserved", "<i4"),
                        ("q", "<f8", (4,)), ("t", "<f8", (3,)), ("w_rot", "<f8"), ("w_trans", "<f8")])
 
@@ -123,6 +133,8 @@ def lib():
     L.ba_get_info.argtypes = [vp, C.POINTER(ProblemInfo)]
     L.ba_refine.argtypes = [vp, i32, C.POINTER(RefineStage), i32, C.POINTER(RefineRound)]
     L.ba_pose_graph_create.argtypes = [C.POINTER(PoseGraphDesc), C.POINTER(Options), vp, C.POINTER(vp)]
+    L.ba_rig_create.argtypes = [C.POINTER(RigDesc), C.POINTER(Options), vp, C.POINTER(vp)]
+    L.ba_rig_get_result.argtypes = [vp, vp, vp, vp, C.POINTER(Report)]
     L.ba_get_active.argtypes = [vp, vp]
     L.ba_problem_bytes.argtypes = [vp]
     L.ba_problem_bytes.restype = i64
@@ -232,6 +244,40 @@ class _GraphDesc:
         self.desc = d
 
 
+class _RigDesc:
+    """Holds the contiguous host arrays a RigDesc points to."""
+
+    def __init__(self, K, qv, tv, qe, te, X, frame, rcam, pt, uv, vehicle_fixed=None, extrinsic_fixed=None,
+                 prior_ext=0.0, prior_rig=0.0, rig_pairs=None):
+        self.K = np.ascontiguousarray(K, dtype=np.float64)
+        self.vp = np.ascontiguousarray(np.concatenate([np.asarray(qv, np.float64), np.asarray(tv, np.float64)], 1))
+        self.ep = np.ascontiguousarray(np.concatenate([np.asarray(qe, np.float64), np.asarray(te, np.float64)], 1))
+        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        o = np.zeros(len(frame), RIG_OBS_DTYPE)
+        o["frame"], o["cam"], o["pt"] = frame, rcam, pt
+        o["u"], o["v"] = np.asarray(uv)[:, 0], np.asarray(uv)[:, 1]
+        self.obs = o
+        self.vf = None if vehicle_fixed is None else np.ascontiguousarray(vehicle_fixed, dtype=np.uint8)
+        self.ef = None if extrinsic_fixed is None else np.ascontiguousarray(extrinsic_fixed, dtype=np.uint8)
+        self.pairs = (np.zeros(0, np.int32) if rig_pairs is None
+                      else np.ascontiguousarray(np.asarray(rig_pairs).reshape(-1), dtype=np.int32))
+        d = RigDesc()
+        d.n_frames, d.n_rig = self.vp.shape[0], self.ep.shape[0]
+        d.K = _ptr(self.K)
+        d.vehicle_poses, d.extrinsics = _ptr(self.vp), _ptr(self.ep)
+        d.vehicle_fixed, d.extrinsic_fixed = _ptr(self.vf), _ptr(self.ef)
+        d.n_pts, d.points_xyz = self.X.shape[0], _ptr(self.X)
+        d.n_obs, d.obs = len(o), _ptr(self.obs)
+        d.prior_ext, d.prior_rig = float(prior_ext), float(prior_rig)
+        d.n_rig_pairs, d.rig_pairs = self.pairs.size // 2, _ptr(self.pairs)
+        self.desc = d
+
+
+def rig_desc(s, prior_ext=0.0, prior_rig=0.0, rig_pairs=None) -> _RigDesc:
+    return _RigDesc(s.K, s.qv0, s.tv0, s.qe0, s.te0, s.X0, s.frame, s.rcam, s.obs_pt, s.obs_uv, s.fixed_v,
+                    s.fixed_e, prior_ext, prior_rig, rig_pairs)
+
+
 def pose_graph_desc(g) -> _GraphDesc:
     return _GraphDesc(g.q0, g.t0, g.edge_i, g.edge_j, g.meas_q, g.meas_t, g.w_rot, g.w_trans,
                       g.fixed, g.edge_type)
@@ -267,6 +313,36 @@ class Problem:
         _check(lib().ba_pose_graph_create(C.byref(gd.desc), C.byref(self.opts), stream, C.byref(h)))
         self._h = h
         return self
+
+    @classmethod
+    def from_rig(cls, scene, prior_ext=0.0, prior_rig=0.0, rig_pairs=None, stream=None, **kw):
+        """ba_rig_create from a synth.RigScene (or a _RigDesc)."""
+        rd = scene if isinstance(scene, _RigDesc) else rig_desc(scene, prior_ext, prior_rig, rig_pairs)
+        self = cls.__new__(cls)
+        self._desc = rd
+        self.opts = options(**kw)
+        self.n_frames, self.n_rig = rd.desc.n_frames, rd.desc.n_rig
+        self.n_cams = self.n_frames * self.n_rig
+        self.n_pts = rd.desc.n_pts
+        h = C.c_void_p()
+        _check(lib().ba_rig_create(C.byref(rd.desc), C.byref(self.opts), stream, C.byref(h)))
+        self._h = h
+        return self
+
+    def rig_result(self):
+        """Vehicle poses, extrinsics, points and the report (ba_rig_get_result)."""
+        vp = np.zeros((self.n_frames, 7))
+        ep = np.zeros((self.n_rig, 7))
+        pts = np.zeros((self.n_pts, 3))
+        ic = np.zeros(self.opts.max_iters + 1)
+        pi = np.zeros(self.opts.max_iters, np.int32)
+        rep = Report()
+        rep.iter_cost = ic.ctypes.data_as(C.POINTER(C.c_double))
+        rep.pcg_iters = pi.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ba_rig_get_result(self._h, _ptr(vp), _ptr(ep), _ptr(pts), C.byref(rep)))
+        out = _report_dict(rep, vp, pts, ic, pi)
+        out["qe"], out["te"] = ep[:, :4], ep[:, 4:]
+        return out
 
     @classmethod
     def from_scene(cls, scene, stream=None, **kw):

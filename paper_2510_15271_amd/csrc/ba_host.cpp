@@ -10,11 +10,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -464,18 +466,22 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   // later free partners of each free camera through a pair: their blocks of S exist even
   // where no point is seen by both
   std::vector<int32_t> padj_start(Cf + 1, 0), padj;
-  for (const int2 &ij : sy.pp_cam) {
-    const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
-    if (a >= 0 && b >= 0) padj_start[std::min(a, b) + 1]++;
-  }
+  const std::vector<int2> no_pattern;
+  const std::vector<int2> &pattern = edges ? edges->pattern : no_pattern;
+  for (const std::vector<int2> *lst : {(const std::vector<int2> *)&sy.pp_cam, &pattern})
+    for (const int2 &ij : *lst) {
+      const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
+      if (a >= 0 && b >= 0 && a != b) padj_start[std::min(a, b) + 1]++;
+    }
   for (int a = 0; a < Cf; ++a) padj_start[a + 1] += padj_start[a];
   padj.resize(padj_start[Cf]);
   {
     std::vector<int32_t> f(padj_start.begin(), padj_start.end() - 1);
-    for (const int2 &ij : sy.pp_cam) {
-      const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
-      if (a >= 0 && b >= 0) padj[f[std::min(a, b)]++] = std::max(a, b);
-    }
+    for (const std::vector<int2> *lst : {(const std::vector<int2> *)&sy.pp_cam, &pattern})
+      for (const int2 &ij : *lst) {
+        const int a = sy.free_idx[ij.x], b = sy.free_idx[ij.y];
+        if (a >= 0 && b >= 0 && a != b) padj[f[std::min(a, b)]++] = std::max(a, b);
+      }
   }
   std::vector<uint8_t> pmark(Cf, 0);
 
@@ -816,6 +822,8 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.prior_abs = sy.prior_abs;
   pd.n_pp = (int32_t)sy.pp_cam.size();
   pd.prior_on = (sy.prior_abs > 0.0 || pd.n_pp > 0) ? 1 : 0;
+  pd.prior_abs_from = 0;
+  pd.prior_nodes = C;
   pd.n_pri_tiles = pd.prior_on ? (std::max(Cf, pd.n_pp) + 255) / 256 : 0;
   pd.pose0 = (const double *)ptr(off.pose_init);
   pd.pp_cam = (const int2 *)ptr(off.pp_cam);
@@ -1129,10 +1137,28 @@ EventTimer::~EventTimer() {
 // ====================================================================== C-ABI
 using namespace bax;
 
+// The rig unknowns of a vehicle-rig problem: their view (vehicle poses, then
+// extrinsics, as nodes), its batch, and the lists that project the composed cameras'
+// reduced system onto them.
+struct RigPart {
+  int F = 0, nr = 0;
+  Symbolic sy;
+  DevProblem dp;
+  Batch batch;
+  void *mem = nullptr;    // the rig view's arrays
+  void *extra = nullptr;  // Ucam, rdiag, contribution and row lists
+  size_t bytes = 0;
+  ~RigPart() {
+    if (mem) (void)hipFree(mem);
+    if (extra) (void)hipFree(extra);
+  }
+};
+
 struct ba_problem {
   Symbolic sy;
   DevProblem dp;
   Batch batch;
+  std::unique_ptr<RigPart> rig;  // vehicle-rig problems only
   hipStream_t stream = nullptr;
   bool own_stream = false;
   void *mem = nullptr;
@@ -1172,7 +1198,8 @@ void ba_default_options(ba_options *o) {
 }
 
 static int create_problem(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
-                          const GraphEdges *edges, ba_problem **out) {
+                          const GraphEdges *edges, ba_problem **out,
+                          const std::function<int(ba_problem *)> &before_upload = nullptr) {
   if (!out) return fail(BA_EINVAL, "out is NULL");
   *out = nullptr;
   auto t0 = std::chrono::steady_clock::now();
@@ -1194,6 +1221,7 @@ static int create_problem(const ba_problem_desc *d, const ba_options *opt, void 
     return hip_fail(e, "problem allocation");
   }
   int rc = p->dp.init(p->sy, d, opt, (char *)p->mem, p->stream);
+  if (rc == BA_OK && before_upload) rc = before_upload(p.get());
   if (rc == BA_OK) {
     p->batch.add(p->dp.view, 0);
     rc = p->batch.upload(p->stream);
@@ -1226,6 +1254,302 @@ static int create_problem(const ba_problem_desc *d, const ba_options *opt, void 
 
 int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream, ba_problem **out) {
   return create_problem(d, opt, hip_stream, nullptr, out);
+}
+
+// Builds the rig view over the composed-camera problem p (analysed and initialised,
+// not yet uploaded) and ties the two views together.
+static int build_rig(ba_problem *p, const ba_rig_desc *r, const ba_options *opt) {
+  RigPart &rg = *p->rig;
+  const int F = rg.F, nr = rg.nr, nodes = F + nr;
+  const Symbolic &sc = p->sy;
+  // rig nodes: vehicles 0..F-1, then extrinsics
+  std::vector<ba_pose> npose(nodes);
+  std::vector<uint8_t> nfixed(nodes, 0);
+  for (int f = 0; f < F; ++f) {
+    npose[f] = r->vehicle_poses[f];
+    nfixed[f] = r->vehicle_fixed ? r->vehicle_fixed[f] : 0;
+  }
+  for (int c = 0; c < nr; ++c) {
+    npose[F + c] = r->extrinsics[c];
+    nfixed[F + c] = r->extrinsic_fixed ? r->extrinsic_fixed[c] : 0;
+  }
+  std::vector<int32_t> nfree(nodes, -1);
+  {
+    int k = 0;
+    for (int n = 0; n < nodes; ++n)
+      if (!nfixed[n]) nfree[n] = k++;
+    if (k == 0) return fail(BA_EINVAL, "every vehicle pose and extrinsic is fixed");
+  }
+  // rigidity pairs, measured from the initial extrinsics; couplings of the composed
+  // cameras' reduced system carried over to the rig unknowns
+  GraphEdges ge;
+  for (int k = 0; k < r->n_rig_pairs; ++k) {
+    const int c = r->rig_pairs[2 * k], d = r->rig_pairs[2 * k + 1];
+    double Ec[12], Ed[12], A[12];
+    quat_to_pose12(r->extrinsics[c], Ec);
+    quat_to_pose12(r->extrinsics[d], Ed);
+    relative_pose12(Ec, Ed, A);
+    ge.pairs.push_back(int2{F + c, F + d});
+    ge.meas.insert(ge.meas.end(), A, A + 12);
+    ge.w.push_back(r->prior_rig);
+    ge.w.push_back(r->prior_rig);
+  }
+  auto nodes_of = [&](int cam, int out[2]) {
+    out[0] = cam / nr;           // vehicle of its frame
+    out[1] = F + cam % nr;       // its extrinsic
+  };
+  for (int a = 0; a < sc.Cf; ++a)
+    for (int pos = sc.S_rowptr[a]; pos < sc.S_rowptr[a + 1]; ++pos) {
+      const int b = sc.S_col[pos];
+      if (b < a) continue;  // the upper triangle carries every coupling
+      int na[2], nb[2];
+      nodes_of(sc.free_cam[a], na);
+      nodes_of(sc.free_cam[b], nb);
+      for (int x : na)
+        for (int y : nb)
+          if (x != y) ge.pattern.push_back(int2{std::min(x, y), std::max(x, y)});
+    }
+  std::sort(ge.pattern.begin(), ge.pattern.end(),
+            [](const int2 &u, const int2 &v) { return u.x < v.x || (u.x == v.x && u.y < v.y); });
+  ge.pattern.erase(std::unique(ge.pattern.begin(), ge.pattern.end(),
+                               [](const int2 &u, const int2 &v) { return u.x == v.x && u.y == v.y; }),
+                   ge.pattern.end());
+  const ba_intrinsics K1{1.0, 1.0, 0.0, 0.0};
+  ba_problem_desc dn{};
+  dn.n_cams = nodes;
+  dn.K = &K1;
+  dn.poses = npose.data();
+  dn.cam_fixed = nfixed.data();
+  ba_options on = *opt;
+  on.prior_abs = r->prior_ext;
+  on.prior_seq = 0.0;
+  on.huber_delta = 0.0;
+  on.flags &= ~BA_FLAG_PAIR_LISTS;
+  if (int e = analyse(&dn, &on, rg.sy, &ge)) return e;
+  if (!rg.sy.chunked) return fail(BA_EDEVICE, "internal: the rig view needs the chunk layout");
+  const Symbolic &sr = rg.sy;
+  rg.bytes = DevProblem::bytes_for(sr, opt->precision, opt->max_iters);
+  hipError_t e = hipMalloc(&rg.mem, rg.bytes);
+  if (e != hipSuccess) return hip_fail(e, "rig allocation");
+  if (int rc = rg.dp.init(sr, &dn, &on, (char *)rg.mem, p->stream)) return rc;
+  // contributions of camera blocks to rig blocks (rig BSR position order, camera order)
+  auto rig_pos = [&](int x, int y) -> int {
+    const auto beg = sr.S_col.begin() + sr.S_rowptr[x], end = sr.S_col.begin() + sr.S_rowptr[x + 1];
+    const auto it = std::lower_bound(beg, end, y);
+    return (it != end && *it == y) ? (int)(it - sr.S_col.begin()) : -1;
+  };
+  const int nnzb = sr.nnzb, Cfr = sr.Cf;
+  std::vector<int32_t> rb_start(nnzb + 1, 0), rb_pos, rb_lr, rb_diag(nnzb, -1);
+  std::vector<std::array<int32_t, 3>> contrib;  // rig position, camera position, transforms
+  for (int a = 0; a < sc.Cf; ++a)
+    for (int pos = sc.S_rowptr[a]; pos < sc.S_rowptr[a + 1]; ++pos) {
+      const int b = sc.S_col[pos];
+      const int ca = sc.free_cam[a], cb = sc.free_cam[b];
+      int na[2], nb[2];
+      nodes_of(ca, na);
+      nodes_of(cb, nb);
+      for (int s1 = 0; s1 < 2; ++s1)
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int x = nfree[na[s1]], y = nfree[nb[s2]];
+          if (x < 0 || y < 0) continue;
+          const int rp = rig_pos(x, y);
+          if (rp < 0) return fail(BA_EDEVICE, "internal: rig block (%d, %d) missing", x, y);
+          const int lc = s1 == 0 ? ca % nr : -1, rc2 = s2 == 0 ? cb % nr : -1;
+          contrib.push_back({rp, pos, (lc + 1) | ((rc2 + 1) << 16)});
+        }
+    }
+  for (const auto &c : contrib) rb_start[c[0] + 1]++;
+  for (int i = 0; i < nnzb; ++i) rb_start[i + 1] += rb_start[i];
+  rb_pos.resize(contrib.size());
+  rb_lr.resize(contrib.size());
+  {
+    std::vector<int32_t> f(rb_start.begin(), rb_start.end() - 1);
+    for (const auto &c : contrib) {
+      rb_pos[f[c[0]]] = c[1];
+      rb_lr[f[c[0]]++] = c[2];
+    }
+  }
+  for (int x = 0; x < Cfr; ++x) rb_diag[sr.diag_pos[x]] = x;
+  // composed cameras of each free rig unknown
+  std::vector<int32_t> rr_start(Cfr + 1, 0), rr_cam;
+  for (int x = 0; x < Cfr; ++x) {
+    const int node = sr.free_cam[x];
+    if (node < F)
+      for (int c = 0; c < nr; ++c) rr_cam.push_back(node * nr + c);
+    else
+      for (int f = 0; f < F; ++f) rr_cam.push_back(f * nr + (node - F));
+    rr_start[x + 1] = (int32_t)rr_cam.size();
+  }
+  // one more allocation: Ucam, rdiag and the lists
+  const size_t C = (size_t)sc.C;
+  size_t off[8], tot = 0;
+  const size_t sizes[8] = {C * 21 * 8, (size_t)Cfr * 36 * 8, rb_start.size() * 4, rb_pos.size() * 4 + 4,
+                           rb_lr.size() * 4 + 4, rb_diag.size() * 4 + 4, rr_start.size() * 4, rr_cam.size() * 4 + 4};
+  for (int i = 0; i < 8; ++i) {
+    off[i] = tot;
+    tot += (sizes[i] + 255) & ~size_t(255);
+  }
+  e = hipMalloc(&rg.extra, tot);
+  if (e != hipSuccess) return hip_fail(e, "rig allocation");
+  char *xb = (char *)rg.extra;
+  const void *src[8] = {nullptr, nullptr, rb_start.data(), rb_pos.data(), rb_lr.data(), rb_diag.data(),
+                        rr_start.data(), rr_cam.data()};
+  const size_t nbytes[8] = {0, 0, rb_start.size() * 4, rb_pos.size() * 4, rb_lr.size() * 4, rb_diag.size() * 4,
+                            rr_start.size() * 4, rr_cam.size() * 4};
+  for (int i = 2; i < 8 && e == hipSuccess; ++i)
+    if (nbytes[i]) e = hipMemcpy(xb + off[i], src[i], nbytes[i], hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "rig upload");
+  // the rig view: its LM state is the composed-camera problem's
+  ProbDev &rv = rg.dp.view;
+  ProbDev &cv = p->dp.view;
+  rv.st = cv.st;
+  rv.rig_mode = 2;
+  rv.n_frames = F;
+  rv.n_rigcam = nr;
+  rv.prior_abs_from = F;
+  rv.prior_nodes = nodes;
+  rv.Nf = 1;  // its row sums come from k_rig_rows
+  rv.chunked = 1;
+  rv.n_ch = 0;
+  rv.n_red_tiles = (nnzb + 3) / 4;  // rig-block tiles (4 blocks each)
+  rv.n_fin_tiles = Cfr;             // rig-row tiles
+  rv.n_fsh_tiles = (Cfr + 63) / 64;
+  rv.n_pt_tiles = 0;
+  rv.n_cam_tiles = 0;
+  rv.rdiag = (double *)(xb + off[1]);
+  rv.rb_start = (const int32_t *)(xb + off[2]);
+  rv.rb_pos = (const int32_t *)(xb + off[3]);
+  rv.rb_lr = (const int32_t *)(xb + off[4]);
+  rv.rb_diag = (const int32_t *)(xb + off[5]);
+  rv.rr_start = (const int32_t *)(xb + off[6]);
+  rv.rr_cam = (const int32_t *)(xb + off[7]);
+  rv.cam_S = cv.S;
+  rv.cam_gc = cv.gc;
+  rv.cam_brhs = cv.brhs;
+  rv.cam_U = (const double *)(xb + off[0]);
+  rg.batch.add(rv, 0);
+  if (int rc = rg.batch.upload(p->stream)) return rc;
+  // the composed-camera view: undamped blocks, the rig's priors for the cost, the rig update
+  cv.rig_mode = 1;
+  cv.n_frames = F;
+  cv.n_rigcam = nr;
+  cv.Ucam = (double *)(xb + off[0]);
+  cv.rig_pose[0] = rv.pose[0];
+  cv.rig_pose[1] = rv.pose[1];
+  cv.rig_x = rv.x;
+  cv.rig_gc = rv.gc;
+  cv.rig_Dc = rv.Dc;
+  cv.rig_free_idx = rv.free_idx;
+  cv.prior_on = 0;
+  cv.prior_abs = rv.prior_abs;
+  cv.prior_abs_from = F;
+  cv.prior_nodes = nodes;
+  cv.pose0 = rv.pose0;
+  cv.n_pp = rv.n_pp;
+  cv.pp_cam = rv.pp_cam;
+  cv.pp_meas = rv.pp_meas;
+  cv.pp_w = rv.pp_w;
+  cv.n_pri_tiles = 0;
+  cv.n_cam_tiles = (std::max(cv.C, nodes) + kCamTile - 1) / kCamTile;
+  // the update's per-tile partials go to part_dl_cam, sized for the camera tiles (256-byte padded)
+  const size_t dl_slots = ((((size_t)cv.C + kCamTile - 1) / kCamTile * 8 + 255) & ~size_t(255)) / 8;
+  if ((size_t)cv.n_cam_tiles > dl_slots) return fail(BA_EINVAL, "rig too large for one camera per frame");
+  return BA_OK;
+}
+
+int ba_rig_create(const ba_rig_desc *r, const ba_options *opt, void *hip_stream, ba_problem **out) {
+  if (out) *out = nullptr;
+  if (!r) return fail(BA_EINVAL, "rig description is NULL");
+  if (!opt) return fail(BA_EINVAL, "options are NULL");
+  if (r->n_frames < 1) return fail(BA_EINVAL, "n_frames must be >= 1");
+  if (r->n_rig < 1 || r->n_rig > BA_RIG_MAX_CAMS) return fail(BA_EINVAL, "n_rig must be in 1..%d", BA_RIG_MAX_CAMS);
+  if ((int64_t)r->n_frames * r->n_rig > INT32_MAX / 2) return fail(BA_EINVAL, "n_frames * n_rig too large");
+  if (r->n_pts < 1 || r->n_obs < 1) return fail(BA_EINVAL, "n_pts and n_obs must be >= 1");
+  if (!r->K || !r->vehicle_poses || !r->extrinsics || !r->points_xyz || !r->obs)
+    return fail(BA_EINVAL, "NULL array in rig description");
+  if (opt->prior_abs != 0.0 || opt->prior_seq != 0.0)
+    return fail(BA_EINVAL, "a rig problem takes its priors from the rig description (prior_abs, prior_seq must be 0)");
+  if (!(std::isfinite(r->prior_ext) && r->prior_ext >= 0.0) || !(std::isfinite(r->prior_rig) && r->prior_rig >= 0.0))
+    return fail(BA_EINVAL, "prior_ext and prior_rig must be finite and >= 0");
+  if (r->n_rig_pairs < 0 || (r->n_rig_pairs > 0 && !r->rig_pairs)) return fail(BA_EINVAL, "bad rig pairs");
+  const int F = r->n_frames, nr = r->n_rig;
+  for (int f = 0; f < F; ++f)
+    if (int e = check_pose(r->vehicle_poses[f], "vehicle", f)) return e;
+  for (int c = 0; c < nr; ++c)
+    if (int e = check_pose(r->extrinsics[c], "extrinsic", c)) return e;
+  {
+    std::vector<int32_t> keys;
+    for (int k = 0; k < r->n_rig_pairs; ++k) {
+      const int c = r->rig_pairs[2 * k], d = r->rig_pairs[2 * k + 1];
+      if (c < 0 || c >= nr || d < 0 || d >= nr || c == d) return fail(BA_EINVAL, "rig pair %d invalid", k);
+      keys.push_back(std::min(c, d) * nr + std::max(c, d));
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(BA_EINVAL, "a rig pair is given twice");
+  }
+  // the composed cameras, camera f * nr + c
+  std::vector<ba_intrinsics> K((size_t)F * nr);
+  std::vector<ba_pose> poses((size_t)F * nr);
+  for (int f = 0; f < F; ++f) {
+    double Tv[12];
+    quat_to_pose12(r->vehicle_poses[f], Tv);
+    for (int c = 0; c < nr; ++c) {
+      double Te[12], Tc[12];
+      quat_to_pose12(r->extrinsics[c], Te);
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+          Tc[3 * i + j] = Te[3 * i] * Tv[j] + Te[3 * i + 1] * Tv[3 + j] + Te[3 * i + 2] * Tv[6 + j];
+        Tc[9 + i] = Te[3 * i] * Tv[9] + Te[3 * i + 1] * Tv[10] + Te[3 * i + 2] * Tv[11] + Te[9 + i];
+      }
+      poses[(size_t)f * nr + c] = pose12_to_quat(Tc);
+      K[(size_t)f * nr + c] = r->K[c];
+    }
+  }
+  std::vector<ba_obs> obs(r->n_obs);
+  for (int64_t k = 0; k < r->n_obs; ++k) {
+    const ba_rig_obs &o = r->obs[k];
+    if (o.frame < 0 || o.frame >= F || o.cam < 0 || o.cam >= nr)
+      return fail(BA_EINVAL, "observation %lld: frame or rig camera out of range", (long long)k);
+    obs[k] = ba_obs{o.frame * nr + o.cam, o.pt, o.u, o.v};
+  }
+  ba_problem_desc d{};
+  d.n_cams = F * nr;
+  d.K = K.data();
+  d.K_per_cam = 1;
+  d.poses = poses.data();
+  d.cam_fixed = nullptr;
+  d.n_pts = r->n_pts;
+  d.points_xyz = r->points_xyz;
+  d.n_obs = r->n_obs;
+  d.obs = obs.data();
+  return create_problem(&d, opt, hip_stream, nullptr, out, [&](ba_problem *p) {
+    p->rig.reset(new RigPart());
+    p->rig->F = F;
+    p->rig->nr = nr;
+    return build_rig(p, r, opt);
+  });
+}
+
+int ba_rig_get_result(const ba_problem *pc, ba_pose *vehicles_out, ba_pose *extrinsics_out, double *points_out,
+                      ba_report *rep) {
+  ba_problem *p = const_cast<ba_problem *>(pc);
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (!p->rig) return fail(BA_EINVAL, "not a rig problem");
+  if (p->pending)
+    if (int e = ba_wait(p)) return e;
+  if (vehicles_out || extrinsics_out) {
+    const RigPart &rg = *p->rig;
+    std::vector<double> buf(12 * (size_t)(rg.F + rg.nr));
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy(buf.data(), rg.dp.view.pose[p->dp.host_state.cur], buf.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "rig pose download");
+    if (vehicles_out)
+      for (int f = 0; f < rg.F; ++f) vehicles_out[f] = pose12_to_quat(&buf[12 * (size_t)f]);
+    if (extrinsics_out)
+      for (int c = 0; c < rg.nr; ++c) extrinsics_out[c] = pose12_to_quat(&buf[12 * (size_t)(rg.F + c)]);
+  }
+  return p->dp.read_result(p->stream, nullptr, points_out, rep, p->solved, p->solve_ms, p->setup_ms);
 }
 
 int ba_pose_graph_create(const ba_pose_graph_desc *g, const ba_options *opt, void *hip_stream,
@@ -1296,8 +1620,10 @@ int ba_solve_async(ba_problem *p) {
       if (e != hipSuccess) return hip_fail(e, "graph capture");
       hipError_t el = hipSuccess;
       for (int it = 0; it < p->dp.max_iters && el == hipSuccess; ++it)
-        el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream,
-                                 nullptr);
+        el = p->rig ? launch_rig_iteration(p->dp.precision, p->batch.plan, p->rig->batch.plan, p->dp.pcg_max,
+                                           p->rig->sy.max_tcols, p->stream, nullptr)
+                    : launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols,
+                                          p->stream, nullptr);
       e = hipStreamEndCapture(p->stream, &p->graph);
       if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
       if (e != hipSuccess) return hip_fail(e, "graph capture");
@@ -1313,7 +1639,7 @@ int ba_solve_async(ba_problem *p) {
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     p->pending = true;
     return BA_OK;
-  } else if (p->use_graph && p->timer.mask == (1u << K_PCG_CG) &&
+  } else if (p->use_graph && !p->rig && p->timer.mask == (1u << K_PCG_CG) &&
              one_reduction_pcg(p->dp.precision, p->dp.max_tcols)) {
     // Only the PCG run is timed: replay one LM iteration as three graphs (their
     // launches are the same in every iteration) with the timing events between them.
@@ -1344,7 +1670,9 @@ int ba_solve_async(ba_problem *p) {
     p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters; ++it) {
-      e = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream, tm);
+      e = p->rig ? launch_rig_iteration(p->dp.precision, p->batch.plan, p->rig->batch.plan, p->dp.pcg_max,
+                                        p->rig->sy.max_tcols, p->stream, tm)
+                 : launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream, tm);
       if (e != hipSuccess) return hip_fail(e, "kernel launch");
     }
   }
@@ -1394,6 +1722,11 @@ int ba_reset(ba_problem *p) {
     e = hipMemcpyAsync(dp.view.X[0], dp.dev + dp.off.X_init, 3 * (size_t)dp.P * 8,
                        hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess && dp.N > 0) e = hipMemsetAsync(dp.view.obs_act, 1, (size_t)dp.N, p->stream);
+  if (e == hipSuccess && p->rig) {
+    DevProblem &rd = p->rig->dp;
+    e = hipMemcpyAsync(rd.view.pose[0], rd.dev + rd.off.pose_init, 12 * (size_t)rd.C * 8, hipMemcpyDeviceToDevice,
+                       p->stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "reset");
   dp.n_active = dp.N;
   dp.host_state = LMState{};
@@ -1415,6 +1748,7 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
   if (p->sy.N == 0) return fail(BA_EINVAL, "a pose graph has no observations to cull");
+  if (p->rig) return fail(BA_EINVAL, "ba_refine does not take rig problems");
   DevProblem &dp = p->dp;
   const double huber0 = dp.huber;
   std::vector<int32_t> cnt(2 * (size_t)dp.view.n_pt_tiles);

@@ -145,6 +145,25 @@ struct ProbDev {
   const int32_t *cam_pp;          // pairs of each free camera, ascending
   double *prior_diag;             // [Cf][27]
   double *prior_off;              // [n_pp][36]
+  int32_t prior_abs_from;         // the absolute prior covers nodes [prior_abs_from, prior_nodes)
+  int32_t prior_nodes;
+  // vehicle-rig problems: rig_mode 1 is the view over composed cameras (f, c), camera
+  // f * n_rigcam + c, whose S blocks are formed undamped; rig_mode 2 is the view over the
+  // rig unknowns (vehicle poses, then extrinsics), whose reduced system the PCG solves
+  int32_t rig_mode, n_frames, n_rigcam, pad2;
+  double *Ucam;                   // (1) [C][21] undamped U of each composed camera
+  double *rig_pose[2];            // (1) [n_frames + n_rigcam][12] rig poses (the rig view's pose)
+  const void *rig_x, *rig_gc, *rig_Dc;  // (1) the rig view's x, g and D
+  const int32_t *rig_free_idx;    // (1) rig node -> free rig block
+  const int32_t *rb_start;        // (2) [nnzb + 1] contributions of camera S blocks to each rig block
+  const int32_t *rb_pos;          // (2) camera S block of each contribution
+  const int32_t *rb_lr;           // (2) (left rig camera + 1) | (right rig camera + 1) << 16; 0: identity
+  const int32_t *rb_diag;         // (2) [nnzb] row of a diagonal rig block, -1 for the others
+  double *rdiag;                  // (2) [Cf][36] undamped diagonal rig blocks
+  const int32_t *rr_start;        // (2) [Cf + 1] composed cameras of each rig row
+  const int32_t *rr_cam;
+  const void *cam_S, *cam_gc, *cam_brhs;  // (2) the camera view's S, g and b
+  const double *cam_U;            // (2) the camera view's Ucam
   void *Q;                        // [Nf][6] T: J_p,k V*_j^-1 (2x3), camera-major
   void *V, *gp, *Dp, *Vinv;       // [P][6], [P][3], [P][3], [P][6] T
   void *gc, *Dc, *brhs;           // [Cf][6] T
@@ -204,7 +223,8 @@ struct KernelTimer {
 enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
-  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_CULL, K_NUM_KERNELS
+  K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_CULL, K_RIG_BLOCKS,
+  K_RIG_ROWS, K_RIG_UPDATE, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -227,6 +247,11 @@ enum LmPart { LM_ALL = 0, LM_BEFORE_PCG, LM_PCG, LM_AFTER_PCG };
 // the plan.  max_tcols: the longest PCG-tile column list of the plan (selects the PCG form).
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,
                                hipStream_t s, KernelTimer *timer, int part = LM_ALL);
+// One LM iteration of a vehicle-rig problem: the camera plan holds the composed-camera
+// view, the rig plan the rig view (its PCG tiles, prior tiles, rig-block tiles in .red,
+// rig-row tiles in .fin, finish tiles in .fsh).
+hipError_t launch_rig_iteration(int precision, const BatchPlan &cam, const BatchPlan &rig, int pcg_max,
+                                int max_tcols, hipStream_t s, KernelTimer *timer);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
 // Culling and re-triangulation at the accepted state: observations with

@@ -39,7 +39,8 @@ namespace bax {
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
-    "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull"};
+    "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull", "rig_blocks",
+    "rig_rows", "rig_update"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -646,7 +647,7 @@ __device__ inline void rel_pose(const double *Ti, const double *Tj, double A[12]
 __device__ inline double prior_cost(const ProbDev &pd, const double *P, double *s_red) {
   double c = 0.0;
   if (pd.prior_abs > 0.0)
-    for (int i = threadIdx.x; i < pd.C; i += 256) {
+    for (int i = pd.prior_abs_from + (int)threadIdx.x; i < pd.prior_nodes; i += 256) {
       double e = 0.0;
       for (int q = 0; q < 12; ++q) {
         const double d = P[12 * i + q] - pd.pose0[12 * i + q];
@@ -698,7 +699,7 @@ __global__ __launch_bounds__(256) void k_prior_lin(const ProbDev *__restrict__ p
       }
     };
     const double *Tc = P + 12 * cam;
-    if (pd.prior_abs > 0.0) {
+    if (pd.prior_abs > 0.0 && cam >= pd.prior_abs_from) {
       double r[12];
       for (int q = 0; q < 12; ++q) r[q] = Tc[q] - pd.pose0[12 * cam + q];
       add_rows(pd.prior_abs, pd.prior_abs, r, [&](int q, double J[6]) { left_inc_row(Tc, Tc + 9, q, J); });
@@ -773,7 +774,11 @@ __global__ __launch_bounds__(256) void k_prior_apply(const ProbDev *__restrict__
 // PCG start (x = 0, r = b, z = p = M^-1 b) with this row's partials of b.b and r.z.
 template <class T>
 __device__ void finish_camera_row(const ProbDev &pd, const LMState *st, int a, const double tot_in[54]) {
-  const double lam = st->lambda;
+  // the composed-camera view of a rig problem forms its blocks undamped (the rig view
+  // damps the rig unknowns) and keeps U for the rig's Marquardt diagonal
+  const double lam = pd.rig_mode == 1 ? 0.0 : st->lambda;
+  if (pd.rig_mode == 1)
+    for (int i = 0; i < 21; ++i) pd.Ucam[21 * (size_t)a + i] = tot_in[i];
   // the prior terms add to U and g_c (their contributions, formed by k_prior_lin)
   double tot[54];
 #pragma unroll
@@ -2224,9 +2229,10 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   __shared__ double s_red[4];
   double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
   double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
-  if (pd.prior_on) {  // the prior terms at the current (first call only) and trial poses
-    if (!st->init_done) c0 += prior_cost(pd, pd.pose[st->cur], s_red);
-    tc += prior_cost(pd, pd.pose[1 - st->cur], s_red);
+  if (pd.prior_on || pd.rig_mode == 1) {  // the prior terms at the current (first call only) and trial poses
+    double *const *P = pd.rig_mode == 1 ? pd.rig_pose : pd.pose;
+    if (!st->init_done) c0 += prior_cost(pd, P[st->cur], s_red);
+    tc += prior_cost(pd, P[1 - st->cur], s_red);
   }
   const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
   const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
@@ -2443,6 +2449,244 @@ __global__ __launch_bounds__(256) void k_cull(const ProbDev *__restrict__ probs,
     pd.part_cull[2 * tl.idx] = (int32_t)ta;
     pd.part_cull[2 * tl.idx + 1] = (int32_t)tp;
   }
+}
+
+// ------------------------------------------------------------------ vehicle-rig BA
+// Sec. 4.4: the pose of rig camera c at frame f is E_c T_v(f).  The composed-camera
+// view forms the undamped reduced system S_cam, b_cam over the cameras (f, c) with the
+// BA kernels; the rig increments map to camera increments as
+//   xi_(f,c) = Ad(E_c) xi_v(f) + xi_e(c)      (E Exp(xi) E^-1 = Exp(Ad(E) xi)),
+// i.e. xi_cam = B xi_rig, so the rig system is S_rig = B^T S_cam B, b_rig = B^T b_cam,
+// g_rig = B^T g_cam and the rig Hessian's diagonal blocks are B^T U_cam B.  The rig
+// view adds its priors (extrinsic absolute prior, rigidity pairs), damps with the
+// Marquardt diagonal of the rig Hessian and runs the PCG; the update moves vehicles and
+// extrinsics, recomposes the cameras and hands xi_cam = B xi_rig to the points.
+constexpr int kMaxRigCams = 16;
+
+// Ad(E) = [[R, [t]x R], [0, R]] for E = (R, t) held as 12 values, acting on (rho, phi).
+__device__ inline void rig_adjoint(const double *E, double A[36]) {
+  double H[9];
+  hat3(E + 9, H);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      A[6 * i + j] = E[3 * i + j];
+      A[6 * i + 3 + j] = H[3 * i] * E[j] + H[3 * i + 1] * E[3 + j] + H[3 * i + 2] * E[6 + j];
+      A[6 * (i + 3) + j] = 0.0;
+      A[6 * (i + 3) + 3 + j] = E[3 * i + j];
+    }
+}
+
+// Off-diagonal rig blocks of S_rig (written to S) and the undamped diagonal ones (to
+// rdiag): one wave per block, lane (i, j) < 36 holds element (i, j); each contribution
+// L^T S_ab R of a camera block, with L, R = Ad(E_c) for a vehicle side and the identity
+// for an extrinsic side, is formed as S R then L^T (S R) through lane shuffles, and the
+// contributions are summed in FP64 in their fixed order.
+template <class T>
+__global__ __launch_bounds__(256) void k_rig_blocks(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  __shared__ double s_ad[kMaxRigCams][36];
+  const int nr = pd.n_rigcam;
+  if ((int)threadIdx.x < nr) {
+    double A[36];
+    rig_adjoint(pd.pose[st->cur] + 12 * (size_t)(pd.n_frames + threadIdx.x), A);
+    for (int e = 0; e < 36; ++e) s_ad[threadIdx.x][e] = A[e];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = 4 * tl.idx + w;
+  if (b >= pd.nnzb) return;  // no barrier follows
+  const int i = min(lane / 6, 5), j = lane - 6 * (lane / 6);
+  const T *Sc = (const T *)pd.cam_S;
+  double acc = 0.0;
+  for (int x = pd.rb_start[b]; x < pd.rb_start[b + 1]; ++x) {
+    const int pos = pd.rb_pos[x], lr = pd.rb_lr[x];
+    const int lc = (lr & 0xffff) - 1, rc = (lr >> 16) - 1;
+    const double sv = lane < 36 ? (double)Sc[36 * (size_t)pos + lane] : 0.0;
+    double t1 = sv;
+    if (rc >= 0) {  // (S R)_ij = sum_l S_il R_lj
+      t1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < 6; ++l) t1 += __shfl(sv, 6 * i + l, 64) * s_ad[rc][6 * l + j];
+    }
+    double o = t1;
+    if (lc >= 0) {  // (L^T T1)_ij = sum_k L_ki T1_kj
+      o = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) o += s_ad[lc][6 * k + i] * __shfl(t1, 6 * k + j, 64);
+    }
+    acc += o;
+  }
+  if (lane < 36) {
+    const int dr = pd.rb_diag[b];
+    if (dr >= 0)
+      pd.rdiag[36 * (size_t)dr + lane] = acc;
+    else
+      ((T *)pd.S)[36 * (size_t)b + lane] = T(acc);
+  }
+}
+
+// Row sums of one free rig unknown, one wave: over its composed cameras (a vehicle: the
+// rig cameras of its frame, through Ad(E_c); an extrinsic: its camera at every frame)
+// the Hessian block B^T U B (21), g (6) and b (6) in FP64, lane-strided then summed by a
+// fixed butterfly; then the 54-value row [U | U - S_diag | g | b + g] that
+// finish_camera_row turns into the damped diagonal block, the right-hand side b and the
+// block-Jacobi inverse.
+template <class T>
+__global__ __launch_bounds__(64) void k_rig_rows(const ProbDev *__restrict__ probs,
+                                                 const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int x = tl.idx;
+  const int nr = pd.n_rigcam;
+  const bool vehicle = pd.free_cam[x] < pd.n_frames;
+  const int lane = threadIdx.x;
+  const T *gc = (const T *)pd.cam_gc;
+  const T *bc = (const T *)pd.cam_brhs;
+  double acc[33];
+  for (int e = 0; e < 33; ++e) acc[e] = 0.0;
+  for (int k = pd.rr_start[x] + lane; k < pd.rr_start[x + 1]; k += 64) {
+    const int cam = pd.rr_cam[k];
+    const double *Uu = pd.cam_U + 21 * (size_t)cam;
+    double U[36], g[6], bb[6];
+    int u = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c, ++u) U[6 * r + c] = U[6 * c + r] = Uu[u];
+    for (int r = 0; r < 6; ++r) {
+      g[r] = (double)gc[6 * (size_t)cam + r];
+      bb[r] = (double)bc[6 * (size_t)cam + r];
+    }
+    if (vehicle) {
+      double A[36], UA[36];
+      rig_adjoint(pd.pose[st->cur] + 12 * (size_t)(pd.n_frames + cam % nr), A);
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          double v = 0.0;
+          for (int m = 0; m < 6; ++m) v += U[6 * r + m] * A[6 * m + c];
+          UA[6 * r + c] = v;
+        }
+      u = 0;
+      for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c, ++u) {
+          double v = 0.0;
+          for (int m = 0; m < 6; ++m) v += A[6 * m + r] * UA[6 * m + c];
+          acc[u] += v;
+        }
+      for (int r = 0; r < 6; ++r) {
+        double vg = 0.0, vb = 0.0;
+        for (int m = 0; m < 6; ++m) {
+          vg += A[6 * m + r] * g[m];
+          vb += A[6 * m + r] * bb[m];
+        }
+        acc[21 + r] += vg;
+        acc[27 + r] += vb;
+      }
+    } else {
+      for (int e = 0; e < 21; ++e) acc[e] += Uu[e];
+      for (int r = 0; r < 6; ++r) {
+        acc[21 + r] += g[r];
+        acc[27 + r] += bb[r];
+      }
+    }
+  }
+  for (int e = 0; e < 33; ++e) acc[e] = wave_sum(acc[e]);
+  if (lane == 0) {
+    double *o = pd.row_tot + 54 * (size_t)x;
+    const double *Sd = pd.rdiag + 36 * (size_t)x;
+    int u = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c, ++u) {
+        o[u] = acc[u];
+        o[21 + u] = acc[u] - Sd[6 * r + c];
+      }
+    for (int r = 0; r < 6; ++r) {
+      o[42 + r] = acc[21 + r];
+      o[48 + r] = acc[27 + r] + acc[21 + r];
+    }
+  }
+}
+
+// Rig update and recomposition, over the composed-camera view's camera tiles: thread g
+// moves rig node g (T <- Exp(xi) T for a free one, a copy for a fixed one) into the
+// trial buffer with its part of the predicted decrease, and composes trial camera g
+// (frame g / nr, rig camera g % nr) from the same trial vehicle and extrinsic, with its
+// increment xi_cam = Ad(E_c) xi_v + xi_e for the point back-substitution.
+template <class T>
+__global__ __launch_bounds__(256) void k_rig_update(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  __shared__ double s_red[4];
+  const int cur = st->cur;
+  const double lam = st->lambda;
+  const int F = pd.n_frames, nr = pd.n_rigcam;
+  const T *xr = (const T *)pd.rig_x;
+  const int g = tl.idx * kCamTile + threadIdx.x;
+  auto trial = [&](int node, double out[12]) {
+    const double *src = pd.rig_pose[cur] + 12 * (size_t)node;
+    const int a = pd.rig_free_idx[node];
+    if (a < 0) {
+      for (int i = 0; i < 12; ++i) out[i] = src[i];
+      return;
+    }
+    double xi[6], dR[9], dt[3];
+    for (int i = 0; i < 6; ++i) xi[i] = (double)xr[6 * (size_t)a + i];
+    se3_exp(xi, dR, dt);
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c)
+        out[3 * r + c] = dR[3 * r] * src[c] + dR[3 * r + 1] * src[3 + c] + dR[3 * r + 2] * src[6 + c];
+      out[9 + r] = dR[3 * r] * src[9] + dR[3 * r + 1] * src[10] + dR[3 * r + 2] * src[11] + dt[r];
+    }
+  };
+  double dl = 0.0;
+  if (g < F + nr) {
+    double Tn[12];
+    trial(g, Tn);
+    double *dst = pd.rig_pose[1 - cur] + 12 * (size_t)g;
+    for (int i = 0; i < 12; ++i) dst[i] = Tn[i];
+    const int a = pd.rig_free_idx[g];
+    if (a >= 0) {
+      const T *gr = (const T *)pd.rig_gc + 6 * (size_t)a;
+      const T *Dr = (const T *)pd.rig_Dc + 6 * (size_t)a;
+      for (int i = 0; i < 6; ++i) {
+        const double xi = (double)xr[6 * (size_t)a + i];
+        dl += lam * (double)Dr[i] * xi * xi - (double)gr[i] * xi;
+      }
+    }
+  }
+  if (g < pd.C) {
+    const int f = g / nr, c = g - nr * (g / nr);
+    double Tv[12], Te[12];
+    trial(f, Tv);
+    trial(F + c, Te);
+    double *dst = pd.pose[1 - cur] + 12 * (size_t)g;
+    for (int r = 0; r < 3; ++r) {
+      for (int cc = 0; cc < 3; ++cc)
+        dst[3 * r + cc] = Te[3 * r] * Tv[cc] + Te[3 * r + 1] * Tv[3 + cc] + Te[3 * r + 2] * Tv[6 + cc];
+      dst[9 + r] = Te[3 * r] * Tv[9] + Te[3 * r + 1] * Tv[10] + Te[3 * r + 2] * Tv[11] + Te[9 + r];
+    }
+    double xc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int av = pd.rig_free_idx[f], ae = pd.rig_free_idx[F + c];
+    if (av >= 0) {
+      double A[36];
+      rig_adjoint(pd.rig_pose[cur] + 12 * (size_t)(F + c), A);
+      for (int r = 0; r < 6; ++r)
+        for (int m = 0; m < 6; ++m) xc[r] += A[6 * r + m] * (double)xr[6 * (size_t)av + m];
+    }
+    if (ae >= 0)
+      for (int r = 0; r < 6; ++r) xc[r] += (double)xr[6 * (size_t)ae + r];
+    T *xo = (T *)pd.x + 6 * (size_t)g;
+    for (int r = 0; r < 6; ++r) xo[r] = T(xc[r]);
+  }
+  const double tot = block_sum256(dl, s_red);
+  if (threadIdx.x == 0) pd.part_dl_cam[tl.idx] = tot;
 }
 
 // ------------------------------------------------------------------ pose-only Gauss-Newton
@@ -2735,6 +2979,118 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   }
   }
   return hipGetLastError();
+}
+
+// One LM iteration of a vehicle-rig problem (see the vehicle-rig kernels).
+template <class T, class S>
+static hipError_t rig_iteration(const BatchPlan &cp, const BatchPlan &rp, int pcg_max, int max_tcols,
+                                hipStream_t s, KernelTimer *tm) {
+  const size_t ubytes = 6 * (size_t)max_tcols * sizeof(T);
+  const bool one_reduction = ubytes <= g_fused_lds;
+  // composed cameras: linearisation and the undamped reduced system
+  if (cp.n_pt) {
+    Timed t(tm, K_LINEARIZE, s);
+    k_linearize<T, S><<<cp.n_pt, kObsChunk, 0, s>>>(cp.probs, cp.pt);
+  }
+  if (cp.n_ch) {
+    Timed t(tm, K_SCHUR_CHUNK, s);
+    k_schur_chunk<T, S><<<cp.n_ch, chunk_threads<T>(), chunk_lds_bytes(sizeof(T) == 8 ? 0 : 1), s>>>(cp.probs,
+                                                                                                 cp.ch);
+  }
+  if (cp.n_red) {
+    Timed t(tm, K_SCHUR_REDUCE, s);
+    k_schur_reduce<T><<<cp.n_red, 256, 0, s>>>(cp.probs, cp.red);
+  }
+  if (cp.n_fin) {
+    Timed t(tm, K_SCHUR_ROWS, s);
+    k_schur_rows<T><<<cp.n_fin, 1024, 0, s>>>(cp.probs, cp.fin);
+  }
+  if (cp.n_fsh) {
+    Timed t(tm, K_SCHUR_FINISH, s);
+    k_schur_finish<T><<<cp.n_fsh, 64, 0, s>>>(cp.probs, cp.fsh);
+  }
+  if (cp.n_pp) {
+    Timed t(tm, K_POINT_PREP, s);
+    k_point_prep<T, S><<<cp.n_pp, 256, 0, s>>>(cp.probs, cp.pp);
+  }
+  if (cp.n_diag) {
+    Timed t(tm, K_SCHUR_DIAG, s);
+    k_schur_diag<T, S><<<cp.n_diag, 256, 0, s>>>(cp.probs, cp.diag);
+  }
+  if (cp.n_off) {
+    Timed t(tm, K_SCHUR_OFF, s);
+    k_schur_off<T, S><<<cp.n_off, 256, 0, s>>>(cp.probs, cp.off);
+  }
+  // rig unknowns: priors, projection, damping, preconditioner, PCG
+  if (rp.n_pri) {
+    Timed t(tm, K_PRIOR_LIN, s);
+    k_prior_lin<T><<<rp.n_pri, 256, 0, s>>>(rp.probs, rp.pri);
+  }
+  if (rp.n_red) {
+    Timed t(tm, K_RIG_BLOCKS, s);
+    k_rig_blocks<T><<<rp.n_red, 256, 0, s>>>(rp.probs, rp.red);
+  }
+  if (rp.n_fin) {
+    Timed t(tm, K_RIG_ROWS, s);
+    k_rig_rows<T><<<rp.n_fin, 64, 0, s>>>(rp.probs, rp.fin);
+  }
+  if (rp.n_fsh) {
+    Timed t(tm, K_SCHUR_FINISH, s);
+    k_schur_finish<T><<<rp.n_fsh, 64, 0, s>>>(rp.probs, rp.fsh);
+  }
+  if (rp.n_pri) {
+    Timed t(tm, K_PRIOR_APPLY, s);
+    k_prior_apply<T><<<rp.n_pri, 256, 0, s>>>(rp.probs, rp.pri);
+  }
+  if (rp.n_pcg && one_reduction) {
+    {
+      Timed t(tm, K_PCG_SPMV, s);
+      k_cg_start<T><<<rp.n_pcg, 256, 0, s>>>(rp.probs, rp.pcg);
+    }
+    Timed t(tm, K_PCG_CG, s, pcg_max);
+    hipError_t le = hipSuccess;
+    const void *f = CgStep<T>::multi(rp.pcg_rows);
+    for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
+      void *args[] = {(void *)&rp.probs, (void *)&rp.pcg, (void *)&it};
+      le = hipLaunchKernel(f, dim3(rp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+    }
+    if (le != hipSuccess) return le;
+  } else {
+    for (int it = 0; it < pcg_max && rp.n_pcg; ++it) {
+      {
+        Timed t(tm, K_PCG_SPMV, s);
+        k_pcg_spmv<T><<<rp.n_pcg, 256, 0, s>>>(rp.probs, rp.pcg, it);
+      }
+      {
+        Timed t(tm, K_PCG_UPDATE, s);
+        k_pcg_update<T><<<rp.n_pcg, 256, 0, s>>>(rp.probs, rp.pcg, it);
+      }
+    }
+  }
+  // back to the cameras: rig update, recomposition, points, LM control
+  if (cp.n_cam) {
+    Timed t(tm, K_RIG_UPDATE, s);
+    k_rig_update<T><<<cp.n_cam, 256, 0, s>>>(cp.probs, cp.cam);
+  }
+  if (cp.n_pt) {
+    Timed t(tm, K_POINT_TRIAL, s);
+    k_point_trial<T, S><<<cp.n_pt, kObsChunk, 0, s>>>(cp.probs, cp.pt);
+  }
+  if (cp.n_ctl) {
+    Timed t(tm, K_LM_CONTROL, s);
+    k_lm_control<<<cp.n_ctl, 256, 0, s>>>(cp.probs, cp.ctl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rig_iteration(int precision, const BatchPlan &cam, const BatchPlan &rig, int pcg_max,
+                                int max_tcols, hipStream_t s, KernelTimer *timer) {
+  switch (precision) {
+    case 0: return rig_iteration<double, double>(cam, rig, pcg_max, max_tcols, s, timer);
+    case 1: return rig_iteration<float, float>(cam, rig, pcg_max, max_tcols, s, timer);
+    case 2: return rig_iteration<float, _Float16>(cam, rig, pcg_max, max_tcols, s, timer);
+    default: return rig_iteration<float, bf16s>(cam, rig, pcg_max, max_tcols, s, timer);
+  }
 }
 
 hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, int max_tcols,

@@ -65,6 +65,7 @@ struct Symbolic {
 struct GraphEdges {
   std::vector<int2> pairs;
   std::vector<double> meas, w;
+  std::vector<int2> pattern;  // node pairs whose block of S exists without a term of their own
 };
 // Symbolic analysis of a problem.  With edges, the description holds the nodes only
 // (no points or observations) and the edges replace the sequential prior pairs.
