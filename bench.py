@@ -158,6 +158,52 @@ def pose_graph_leg(ba, precision: str, n_frames: int, flags: int = 0, steps: int
                        "frac_of_hbm_peak": round(abytes / cg_s / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def rig_leg(ba, precision: str, flags: int = 0, steps: int = 10) -> dict:
+    """Extrinsic refinement in the vehicle-rig configuration: 200 frames of a 3-camera
+    rig (~20k points, ~192k observations), vehicle poses and shared extrinsics unknown,
+    extrinsic prior and rigidity pairs (weights 100), 10 LM iterations with PCG
+    50 / 1e-6 per solve, `steps` timed solves from the initial state; then one solve
+    with every kernel timed by HIP events (per LM iteration, microseconds)."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+    from synth import make_rig_drive
+    print("bench: generating the rig drive", flush=True, file=sys.stderr)
+    s = make_rig_drive(200, 20000, seed=1006)
+    pairs = np.array([[0, 1], [0, 2]])
+    p = ba.Problem.from_rig(s, prior_ext=100.0, prior_rig=100.0, rig_pairs=pairs, max_iters=LM_ITERS,
+                            pcg_max_iters=50, pcg_rel_tol=1e-6, precision=precision, flags=flags)
+    info = p.info()
+    p.reset().solve()  # warm-up (graph capture)
+    walls, dev = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        p.reset().solve()
+        walls.append(time.perf_counter() - t0)
+        dev.append(p.report()["solve_ms"])
+    res = p.rig_result()
+    p.set_profiling(-1)
+    p.reset().solve()
+    per_iter_us = {k: round(v[0] / LM_ITERS * 1000, 2) for k, v in p.kernel_times().items() if v[1]}
+    p.set_profiling(0)
+    p.close()
+
+    def rel_rot_err(q):  # largest ||R_c R_0^T - R_c,true R_0,true^T||_F over the side cameras
+        R = Rotation.from_quat(np.asarray(q)[:, [1, 2, 3, 0]]).as_matrix()
+        G = Rotation.from_quat(np.asarray(s.qe_gt)[:, [1, 2, 3, 0]]).as_matrix()
+        return float(max(np.linalg.norm(R[k] @ R[0].T - G[k] @ G[0].T) for k in range(1, len(R))))
+
+    wall = float(np.median(walls))
+    return {"workload": f"vehicle-rig BA: {s.n_frames} frames x {s.n_rig} cameras, {info['n_pts']} points, "
+                        f"{info['n_obs']} observations; vehicle poses and shared extrinsics, extrinsic prior "
+                        f"and rigidity pairs",
+            "lm_iters": LM_ITERS, "ms_per_solve": round(1000 * wall, 3),
+            "device_ms_per_solve": round(float(np.median(dev)), 3),
+            "lm_iters_per_s": round(LM_ITERS / wall, 2), "obs_per_s": round(info["n_obs"] * LM_ITERS / wall, 1),
+            "cost0": res["cost0"], "cost": res["cost"],
+            "rel_extrinsic_rot_err": [round(rel_rot_err(s.qe0), 6), round(rel_rot_err(res["qe"]), 6)],
+            "kernel_us_per_iter": per_iter_us}
+
+
 def cpu_baseline(budget_s: float = 30.0) -> dict:
     """The FP64 oracle (explicit Schur complement + block-Jacobi PCG, the same
     schedule) timed on one host core for one LM iteration of the same scene."""
@@ -273,6 +319,8 @@ def main():
     ap.add_argument("--prior-seq", type=float, default=0.0,
                     help="weight of the sequential pose prior between frames i and i+k (0: off)")
     ap.add_argument("--prior-seq-k", type=int, default=1)
+    ap.add_argument("--no-rig", action="store_true",
+                    help="skip the vehicle-rig leg (200 frames x 3 cameras)")
     ap.add_argument("--no-pose-graph", action="store_true",
                     help="skip the pose-graph leg (9000 nodes, 24.7k edges)")
     ap.add_argument("--no-refine", action="store_true",
@@ -400,6 +448,8 @@ def main():
     if not args.no_refine and args.workload == "drive":
         out["refine"] = refine_leg(ba, args.precision, args.points or 250_000,
                                    ba.FLAG_NO_GRAPH if args.no_graph else 0)
+    if not args.no_rig and args.workload == "drive":
+        out["rig"] = rig_leg(ba, args.precision, ba.FLAG_NO_GRAPH if args.no_graph else 0)
     if not args.no_pose_graph and args.workload == "drive":
         out["pose_graph"] = pose_graph_leg(ba, args.precision, 1500, ba.FLAG_NO_GRAPH if args.no_graph else 0)
     if args.serving >= 0:

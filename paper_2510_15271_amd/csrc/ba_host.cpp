@@ -1370,6 +1370,23 @@ static int build_rig(ba_problem *p, const ba_rig_desc *r, const ba_options *opt)
     }
   }
   for (int x = 0; x < Cfr; ++x) rb_diag[sr.diag_pos[x]] = x;
+  // segments of at most kRigSeg contributions, never across two rig blocks
+  std::vector<int32_t> rs_blk(nnzb + 1, 0), rs_c0;
+  for (int bk = 0; bk < nnzb; ++bk) {
+    for (int c = rb_start[bk]; c < rb_start[bk + 1]; c += kRigSeg) rs_c0.push_back(c);
+    rs_blk[bk + 1] = (int32_t)rs_c0.size();
+  }
+  const int n_seg = (int)rs_c0.size();
+  rs_c0.push_back((int32_t)contrib.size());
+  // rs_c0[s + 1] must end segment s inside its block: close each block's last segment
+  {
+    std::vector<int32_t> ends(n_seg);
+    for (int bk = 0; bk < nnzb; ++bk)
+      for (int sg = rs_blk[bk]; sg < rs_blk[bk + 1]; ++sg)
+        ends[sg] = std::min(rs_c0[sg] + kRigSeg, rb_start[bk + 1]);
+    for (int sg = 0; sg + 1 < n_seg; ++sg)
+      if (ends[sg] != rs_c0[sg + 1]) return fail(BA_EDEVICE, "internal: rig segments");
+  }
   // composed cameras of each free rig unknown
   std::vector<int32_t> rr_start(Cfr + 1, 0), rr_cam;
   for (int x = 0; x < Cfr; ++x) {
@@ -1382,21 +1399,23 @@ static int build_rig(ba_problem *p, const ba_rig_desc *r, const ba_options *opt)
   }
   // one more allocation: Ucam, rdiag and the lists
   const size_t C = (size_t)sc.C;
-  size_t off[8], tot = 0;
-  const size_t sizes[8] = {C * 21 * 8, (size_t)Cfr * 36 * 8, rb_start.size() * 4, rb_pos.size() * 4 + 4,
-                           rb_lr.size() * 4 + 4, rb_diag.size() * 4 + 4, rr_start.size() * 4, rr_cam.size() * 4 + 4};
-  for (int i = 0; i < 8; ++i) {
+  constexpr int NA = 11;
+  size_t off[NA], tot = 0;
+  const size_t sizes[NA] = {C * 21 * 8, (size_t)Cfr * 36 * 8, rb_start.size() * 4, rb_pos.size() * 4 + 4,
+                            rb_lr.size() * 4 + 4, rb_diag.size() * 4 + 4, rr_start.size() * 4, rr_cam.size() * 4 + 4,
+                            rs_blk.size() * 4, rs_c0.size() * 4, (size_t)n_seg * 36 * 8 + 8};
+  for (int i = 0; i < NA; ++i) {
     off[i] = tot;
     tot += (sizes[i] + 255) & ~size_t(255);
   }
   e = hipMalloc(&rg.extra, tot);
   if (e != hipSuccess) return hip_fail(e, "rig allocation");
   char *xb = (char *)rg.extra;
-  const void *src[8] = {nullptr, nullptr, rb_start.data(), rb_pos.data(), rb_lr.data(), rb_diag.data(),
-                        rr_start.data(), rr_cam.data()};
-  const size_t nbytes[8] = {0, 0, rb_start.size() * 4, rb_pos.size() * 4, rb_lr.size() * 4, rb_diag.size() * 4,
-                            rr_start.size() * 4, rr_cam.size() * 4};
-  for (int i = 2; i < 8 && e == hipSuccess; ++i)
+  const void *src[NA] = {nullptr, nullptr, rb_start.data(), rb_pos.data(), rb_lr.data(), rb_diag.data(),
+                         rr_start.data(), rr_cam.data(), rs_blk.data(), rs_c0.data(), nullptr};
+  const size_t nbytes[NA] = {0, 0, rb_start.size() * 4, rb_pos.size() * 4, rb_lr.size() * 4, rb_diag.size() * 4,
+                             rr_start.size() * 4, rr_cam.size() * 4, rs_blk.size() * 4, rs_c0.size() * 4, 0};
+  for (int i = 2; i < NA && e == hipSuccess; ++i)
     if (nbytes[i]) e = hipMemcpy(xb + off[i], src[i], nbytes[i], hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "rig upload");
   // the rig view: its LM state is the composed-camera problem's
@@ -1410,7 +1429,11 @@ static int build_rig(ba_problem *p, const ba_rig_desc *r, const ba_options *opt)
   rv.prior_nodes = nodes;
   rv.Nf = 1;  // its row sums come from k_rig_rows
   rv.chunked = 1;
-  rv.n_ch = 0;
+  rv.n_ch = (n_seg + 3) / 4;        // rig-segment tiles (4 segments each)
+  rv.n_rig_seg = n_seg;
+  rv.rs_blk = (const int32_t *)(xb + off[8]);
+  rv.rs_c0 = (const int32_t *)(xb + off[9]);
+  rv.rpart = (double *)(xb + off[10]);
   rv.n_red_tiles = (nnzb + 3) / 4;  // rig-block tiles (4 blocks each)
   rv.n_fin_tiles = Cfr;             // rig-row tiles
   rv.n_fsh_tiles = (Cfr + 63) / 64;

@@ -18,6 +18,7 @@ constexpr int kObsChunk = 256;   // observations processed per pass inside a poi
 constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile, dense rows
 constexpr int kPcgRowsSparse = 16;  // rows per PCG tile when rows hold few blocks
 constexpr int kPcgRowsMax = 32;     // ... and when there are more than 512 such tiles
+constexpr int kRigSeg = 32;         // contributions per segment of a rig block's list
 constexpr int kCamTile = 256;    // cameras per camera-update tile
 constexpr int kOffWaves = 4;     // upper S blocks per off-diagonal workgroup (one wave each)
 constexpr int kPoseThreads = 256;
@@ -159,6 +160,10 @@ struct ProbDev {
   const int32_t *rb_pos;          // (2) camera S block of each contribution
   const int32_t *rb_lr;           // (2) (left rig camera + 1) | (right rig camera + 1) << 16; 0: identity
   const int32_t *rb_diag;         // (2) [nnzb] row of a diagonal rig block, -1 for the others
+  const int32_t *rs_blk;          // (2) [nnzb + 1] segments of each rig block's contribution list
+  const int32_t *rs_c0;           // (2) [n_seg + 1] first contribution of each segment (<= kRigSeg each)
+  double *rpart;                  // (2) [n_seg][36] segment sums
+  int32_t n_rig_seg, pad3;
   double *rdiag;                  // (2) [Cf][36] undamped diagonal rig blocks
   const int32_t *rr_start;        // (2) [Cf + 1] composed cameras of each rig row
   const int32_t *rr_cam;

@@ -2476,14 +2476,17 @@ __device__ inline void rig_adjoint(const double *E, double A[36]) {
     }
 }
 
-// Off-diagonal rig blocks of S_rig (written to S) and the undamped diagonal ones (to
-// rdiag): one wave per block, lane (i, j) < 36 holds element (i, j); each contribution
-// L^T S_ab R of a camera block, with L, R = Ad(E_c) for a vehicle side and the identity
-// for an extrinsic side, is formed as S R then L^T (S R) through lane shuffles, and the
-// contributions are summed in FP64 in their fixed order.
+// Rig blocks of S_rig = B^T S_cam B in two passes.  k_rig_seg: one wave per segment of
+// at most kRigSeg contributions of one rig block; lane (i, j) < 36 holds element
+// (i, j); each contribution L^T S_ab R of a camera block, with L, R = Ad(E_c) for a
+// vehicle side and the identity for an extrinsic side, is formed as S R then L^T (S R)
+// through lane shuffles, every S block of the segment loaded before the arithmetic,
+// and the segment's sum goes to rpart in FP64.  k_rig_blocks: one wave per rig block
+// sums its segments in order and writes the off-diagonal blocks to S and the undamped
+// diagonal ones to rdiag.
 template <class T>
-__global__ __launch_bounds__(256) void k_rig_blocks(const ProbDev *__restrict__ probs,
-                                                    const Tile *__restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_rig_seg(const ProbDev *__restrict__ probs,
+                                                 const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
@@ -2497,36 +2500,68 @@ __global__ __launch_bounds__(256) void k_rig_blocks(const ProbDev *__restrict__ 
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int b = 4 * tl.idx + w;
-  if (b >= pd.nnzb) return;  // no barrier follows
+  const int sg = 4 * tl.idx + w;
+  if (sg >= pd.n_rig_seg) return;  // no barrier follows
   const int i = min(lane / 6, 5), j = lane - 6 * (lane / 6);
   const T *Sc = (const T *)pd.cam_S;
+  const int c0 = pd.rs_c0[sg], n = pd.rs_c0[sg + 1] - c0;
   double acc = 0.0;
-  for (int x = pd.rb_start[b]; x < pd.rb_start[b + 1]; ++x) {
-    const int pos = pd.rb_pos[x], lr = pd.rb_lr[x];
-    const int lc = (lr & 0xffff) - 1, rc = (lr >> 16) - 1;
-    const double sv = lane < 36 ? (double)Sc[36 * (size_t)pos + lane] : 0.0;
-    double t1 = sv;
-    if (rc >= 0) {  // (S R)_ij = sum_l S_il R_lj
-      t1 = 0.0;
+  for (int g0 = 0; g0 < n; g0 += 8) {  // eight contributions loaded before their arithmetic
+    double sv[8];
+    int lr[8];
 #pragma unroll
-      for (int l = 0; l < 6; ++l) t1 += __shfl(sv, 6 * i + l, 64) * s_ad[rc][6 * l + j];
+    for (int h = 0; h < 8; ++h) {
+      const bool live = g0 + h < n;
+      lr[h] = live ? pd.rb_lr[c0 + g0 + h] : 0;
+      sv[h] = (live && lane < 36) ? (double)Sc[36 * (size_t)pd.rb_pos[c0 + g0 + h] + lane] : 0.0;
     }
-    double o = t1;
-    if (lc >= 0) {  // (L^T T1)_ij = sum_k L_ki T1_kj
-      o = 0.0;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) o += s_ad[lc][6 * k + i] * __shfl(t1, 6 * k + j, 64);
+    for (int h = 0; h < 8; ++h) {
+      if (g0 + h < n) {  // uniform across the wave
+        const int lc = (lr[h] & 0xffff) - 1, rc = (lr[h] >> 16) - 1;
+        double t1 = sv[h];
+        if (rc >= 0) {  // (S R)_ij = sum_l S_il R_lj
+          t1 = 0.0;
+#pragma unroll
+          for (int l = 0; l < 6; ++l) t1 += __shfl(sv[h], 6 * i + l, 64) * s_ad[rc][6 * l + j];
+        }
+        double o = t1;
+        if (lc >= 0) {  // (L^T T1)_ij = sum_k L_ki T1_kj
+          o = 0.0;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) o += s_ad[lc][6 * k + i] * __shfl(t1, 6 * k + j, 64);
+        }
+        acc += o;
+      }
     }
-    acc += o;
   }
-  if (lane < 36) {
-    const int dr = pd.rb_diag[b];
-    if (dr >= 0)
-      pd.rdiag[36 * (size_t)dr + lane] = acc;
-    else
-      ((T *)pd.S)[36 * (size_t)b + lane] = T(acc);
+  if (lane < 36) pd.rpart[36 * (size_t)sg + lane] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_rig_blocks(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = 4 * tl.idx + w;
+  if (b >= pd.nnzb || lane >= 36) return;
+  const int s0 = pd.rs_blk[b], s1 = pd.rs_blk[b + 1];
+  double acc = 0.0;
+  for (int sg = s0; sg < s1; sg += 8) {  // eight partials in flight, summed in order
+    double v[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) v[h] = sg + h < s1 ? pd.rpart[36 * (size_t)(sg + h) + lane] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) acc += v[h];
   }
+  const int dr = pd.rb_diag[b];
+  if (dr >= 0)
+    pd.rdiag[36 * (size_t)dr + lane] = acc;
+  else
+    ((T *)pd.S)[36 * (size_t)b + lane] = T(acc);
 }
 
 // Row sums of one free rig unknown, one wave: over its composed cameras (a vehicle: the
@@ -3025,6 +3060,10 @@ static hipError_t rig_iteration(const BatchPlan &cp, const BatchPlan &rp, int pc
   if (rp.n_pri) {
     Timed t(tm, K_PRIOR_LIN, s);
     k_prior_lin<T><<<rp.n_pri, 256, 0, s>>>(rp.probs, rp.pri);
+  }
+  if (rp.n_ch) {
+    Timed t(tm, K_RIG_BLOCKS, s);
+    k_rig_seg<T><<<rp.n_ch, 256, 0, s>>>(rp.probs, rp.ch);
   }
   if (rp.n_red) {
     Timed t(tm, K_RIG_BLOCKS, s);
