@@ -3088,10 +3088,18 @@ static hipError_t rig_iteration(const BatchPlan &cp, const BatchPlan &rp, int pc
     }
     Timed t(tm, K_PCG_CG, s, pcg_max);
     hipError_t le = hipSuccess;
-    const void *f = CgStep<T>::multi(rp.pcg_rows);
-    for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
-      void *args[] = {(void *)&rp.probs, (void *)&rp.pcg, (void *)&it};
-      le = hipLaunchKernel(f, dim3(rp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+    if (rp.n_probs == 1) {  // the rig view's descriptor by value
+      const void *f = CgStep<T>::single(rp.pcg_rows);
+      for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
+        void *args[] = {(void *)&rp.single, (void *)&it};
+        le = hipLaunchKernel(f, dim3(rp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+      }
+    } else {
+      const void *f = CgStep<T>::multi(rp.pcg_rows);
+      for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
+        void *args[] = {(void *)&rp.probs, (void *)&rp.pcg, (void *)&it};
+        le = hipLaunchKernel(f, dim3(rp.n_pcg), dim3(kCgThreads), args, ubytes, s);
+      }
     }
     if (le != hipSuccess) return le;
   } else {
