@@ -157,3 +157,41 @@ def test_pose_graph_validation(balib):
     expect(all_fixed, "fixed")
     expect(lambda gd: None, "robust loss", huber_delta=1.0)
     expect(lambda gd: None, "prior_seq", prior_seq=1.0)
+
+
+def test_rig_validation(balib):
+    """ba_rig_create rejects bad rig descriptions before touching the device."""
+    from synth import make_rig_drive
+    s = make_rig_drive(4, 60, seed=3)
+
+    def expect(needle, mutate=None, pairs=((0, 1),), prior_ext=1.0, prior_rig=1.0, **kw):
+        rd = balib.rig_desc(s, prior_ext, prior_rig, np.array(pairs))
+        if mutate:
+            mutate(rd)
+        h = ctypes.c_void_p()
+        rc = balib.lib().ba_rig_create(ctypes.byref(rd.desc), ctypes.byref(balib.options(**kw)), None,
+                                       ctypes.byref(h))
+        msg = balib.lib().ba_last_error().decode()
+        assert rc == balib.BA_EINVAL and needle in msg, (needle, msg)
+
+    def set_obs(field, value):
+        def f(rd):
+            rd.obs[field][0] = value
+        return f
+
+    expect("frame or rig camera", set_obs("frame", s.n_frames))
+    expect("frame or rig camera", set_obs("cam", s.n_rig))
+    expect("rig pair", pairs=((0, 0),))
+    expect("rig pair", pairs=((0, 3),))
+    expect("twice", pairs=((0, 1), (1, 0)))
+    expect("prior_ext", prior_ext=-1.0)
+    expect("prior_ext", prior_rig=float("nan"))
+    expect("priors from the rig description", prior_abs=1.0)
+
+    def bad_quat(rd):
+        rd.ep[1, :4] = [2.0, 0.0, 0.0, 0.0]
+    expect("quaternion", bad_quat)
+
+    def too_many(rd):
+        rd.desc.n_rig = 17
+    expect("n_rig", too_many)
