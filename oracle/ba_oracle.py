@@ -790,21 +790,22 @@ def triangulate_midpoint(p: Problem, j: int, R=None, t=None):
     return X, True
 
 
-def cull_and_triangulate(p: Problem, tau_px: float):
+def cull_and_triangulate(p: Problem, tau_px: float, method: str = "midpoint"):
     """The culling step after a BA round (Sec. 4.3): an active observation stays
     active iff ||r_k|| <= tau_px at the current state; a point left with fewer than two
     active observations leaves the problem (all its observations inactive); a point
-    that lost observations is re-triangulated from the ones that remain (midpoint),
-    and leaves the problem if that fails.  Updates p.active and p.X in place and
+    that lost observations is re-triangulated from the ones that remain (midpoint, or
+    DLT with method="dlt"), and leaves the problem if that fails.  Updates p.active and p.X in place and
     returns (active observations, points in the problem)."""
     r, valid, _ = residuals(p)
     s = np.sum(r * r, axis=1)
     keep = p.active & valid & (s <= tau_px * tau_px)
     lost = p.active & ~keep
     p.active = keep
+    tri = triangulate_midpoint if method == "midpoint" else triangulate_dlt
     for j in np.unique(p.pt[lost]):
         n = int(np.count_nonzero((p.pt == j) & p.active))
-        X, ok = triangulate_midpoint(p, j) if n >= 2 else (None, False)
+        X, ok = tri(p, j) if n >= 2 else (None, False)
         if ok:
             p.X[j] = X
         else:
@@ -815,17 +816,19 @@ def cull_and_triangulate(p: Problem, tau_px: float):
 
 def refine(p: Problem, stages, rounds: int, opts: LMOptions):
     """The two-stage iterative framework of Sec. 4.3: for each stage (huber_delta,
-    tau_px) -- first a robust loss with a relaxed threshold, then no loss with a strict
-    one -- ``rounds`` times: an LM solve from lambda0, then cull_and_triangulate.
+    tau_px[, method]) -- first a robust loss with a relaxed threshold, then no loss with a
+    strict one -- ``rounds`` times: an LM solve from lambda0, then cull_and_triangulate.
     Returns (p, history) with one (stage, round, cost, active obs, points) per round."""
     p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy(), active=p.active.copy())
     hist = []
-    for si, (delta, tau) in enumerate(stages):
+    for si, stage in enumerate(stages):
+        delta, tau = stage[0], stage[1]
+        method = stage[2] if len(stage) > 2 else "midpoint"
         p.delta = float(delta)
         for rd in range(rounds):
             res = lm_schur(p, opts)
             p.R, p.t, p.X = res.R, res.t, res.X
-            n_act, n_pts = cull_and_triangulate(p, tau)
+            n_act, n_pts = cull_and_triangulate(p, tau, method)
             hist.append((si, rd, res.iter_cost[-1], n_act, n_pts))
     return p, hist
 
@@ -1064,3 +1067,50 @@ def lm_rig(q: RigProblem, opts: LMOptions | None = None) -> LMResult:
     out.R, out.t, out.X = q.Rv, q.tv, q.X
     out.ext = (q.Re, q.te)
     return out
+
+
+def triangulate_dlt(p: Problem, j: int, R=None, t=None):
+    """DLT triangulation of point j from its active observations (Eq. dlt), read as the
+    classical homogeneous linear method in normalized camera coordinates: with
+    (x, y) = K^-1 (u, v) and P = [R | t], each observation gives the rows x P_3 - P_1 and
+    y P_3 - P_2 of A, which express p x (P X~) = 0; X~ minimises ||A X~|| over
+    ||X~|| = 1, the right singular vector of A for its smallest singular value
+    (numpy.linalg.svd), and X = X~[:3] / X~[3].  Returns (X, ok): ok iff at least two
+    active observations, |X~[3]| > 1e-12 and every active observation has depth > Z_MIN."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    ks = np.nonzero((p.pt == j) & p.active)[0]
+    if ks.size < 2:
+        return None, False
+    rows = []
+    for k in ks:
+        i = p.cam[k]
+        fx, fy, cx, cy = p.K[i]
+        x, y = (p.uv[k, 0] - cx) / fx, (p.uv[k, 1] - cy) / fy
+        P = np.concatenate([R[i], t[i][:, None]], axis=1)
+        rows.append(x * P[2] - P[0])
+        rows.append(y * P[2] - P[1])
+    _, _, Vt = np.linalg.svd(np.array(rows))
+    Xh = Vt[-1]
+    if not abs(Xh[3]) > 1e-12:
+        return None, False
+    X = Xh[:3] / Xh[3]
+    for k in ks:
+        i = p.cam[k]
+        if not (R[i][2] @ X + t[i][2]) > Z_MIN:
+            return None, False
+    return X, True
+
+
+def triangulate_points(p: Problem, method: str = "midpoint"):
+    """Every point triangulated from scratch from its active observations, by the midpoint
+    or the DLT method.  Returns (X (P, 3), ok (P,) bool); X is the input point where
+    ok is false."""
+    f = triangulate_midpoint if method == "midpoint" else triangulate_dlt
+    X = np.array(p.X, np.float64)
+    ok = np.zeros(p.n_pts, bool)
+    for j in range(p.n_pts):
+        Xj, okj = f(p, j)
+        if okj:
+            X[j], ok[j] = Xj, True
+    return X, ok

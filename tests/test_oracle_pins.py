@@ -727,3 +727,63 @@ def test_rig_optimum_matches_scipy_least_squares():
     ref = scipy.optimize.least_squares(f, x0, xtol=1e-15, ftol=1e-15, gtol=1e-15)
     c_ref = 0.5 * float(ref.fun @ ref.fun)
     assert abs(r.iter_cost[-1] - c_ref) <= 1e-9 * c_ref
+
+
+def test_dlt_triangulation_is_exact_on_noiseless_rays():
+    s = make_small_drive(10, 200, seed=44, sigma=0.0)
+    p = _gt_problem(s)
+    for j in range(0, p.n_pts, 7):
+        X, ok = O.triangulate_dlt(p, j)
+        assert ok
+        assert np.linalg.norm(X - p.X[j]) <= 1e-8 * (1 + np.linalg.norm(p.X[j]))
+
+
+def test_dlt_minimises_the_algebraic_error_on_the_unit_sphere():
+    """With noise, the DLT point's homogeneous vector attains the minimum of ||A y|| / ||y||
+    that SciPy minimize finds from random starts (the Rayleigh quotient of A^T A)."""
+    s = make_small_drive(10, 120, seed=45, sigma=1.0)
+    p = O.Problem.from_scene(s)
+    rng = np.random.default_rng(1)
+    for j in range(0, p.n_pts, 13):
+        ks = np.nonzero(p.pt == j)[0]
+        X, ok = O.triangulate_dlt(p, j)
+        assert ok
+        rows = []
+        for k in ks:
+            i = p.cam[k]
+            x, y = (p.uv[k, 0] - p.K[i, 2]) / p.K[i, 0], (p.uv[k, 1] - p.K[i, 3]) / p.K[i, 1]
+            P = np.concatenate([p.R[i], p.t[i][:, None]], axis=1)
+            rows += [x * P[2] - P[0], y * P[2] - P[1]]
+        A = np.array(rows)
+
+        def q(y_):
+            return float(np.sum((A @ y_) ** 2) / (y_ @ y_))
+
+        best = min(scipy.optimize.minimize(q, rng.normal(size=4), method="BFGS",
+                                           options={"gtol": 1e-14}).fun for _ in range(4))
+        Xh = np.append(X, 1.0)
+        assert q(Xh) <= best * (1 + 1e-6) + 1e-300
+
+
+def test_midpoint_equals_the_printed_dlt_objective_with_free_scales():
+    """The objective of Eq. dlt with X~ = (X, 1) and a free scale per view, minimised
+    jointly over X and the scales with unit-length pixel rays, is the sum of squared
+    distances to the rays: its least-squares solution (numpy.linalg.lstsq over X and the
+    scales) equals the midpoint point."""
+    s = make_small_drive(8, 60, seed=46, sigma=1.0)
+    p = O.Problem.from_scene(s)
+    for j in range(0, p.n_pts, 9):
+        ks = np.nonzero(p.pt == j)[0]
+        if ks.size < 2:
+            continue
+        M = np.zeros((3 * ks.size, 3 + ks.size))
+        rhs = np.zeros(3 * ks.size)
+        for n, k in enumerate(ks):
+            i = p.cam[k]
+            d = np.array([(p.uv[k, 0] - p.K[i, 2]) / p.K[i, 0], (p.uv[k, 1] - p.K[i, 3]) / p.K[i, 1], 1.0])
+            M[3 * n:3 * n + 3, :3] = p.R[i]
+            M[3 * n:3 * n + 3, 3 + n] = -d / np.linalg.norm(d)
+            rhs[3 * n:3 * n + 3] = -p.t[i]
+        sol = np.linalg.lstsq(M, rhs, rcond=None)[0]
+        X, ok = O.triangulate_midpoint(p, j)
+        assert ok and np.linalg.norm(sol[:3] - X) <= 1e-8 * (1 + np.linalg.norm(X))
