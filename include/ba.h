@@ -183,9 +183,17 @@ int ba_reset(ba_problem *p);
    observations still in the problem.  With profiling on and the "cull" kernel
    selected, ba_get_kernel_times reports the culling launches of the call (HIP
    events around each) and, for the other kernels, the last solve's times. */
+#define BA_TRI_MIDPOINT 0  /* the multi-view midpoint (Sec. 4.3)                            */
+#define BA_TRI_DLT 1       /* the DLT of Eq. dlt in its classical homogeneous form: rows
+                              x P_3 - P_1, y P_3 - P_2 in normalized coordinates, X~ the
+                              unit minimiser of ||A X~|| (smallest eigenvector of A^T A by
+                              Jacobi rotations, FP64), X = X~[:3] / X~[3]; fails when
+                              |X~[3]| <= 1e-12                                              */
 typedef struct {
   double huber_delta;     /* the stage's loss: <= 0 none, > 0 Huber threshold in pixels  */
   double cull_px;         /* outlier threshold on ||r_k|| in pixels, > 0                 */
+  int32_t triangulation;  /* BA_TRI_* method of the stage's re-triangulation             */
+  int32_t reserved;
 } ba_refine_stage;
 typedef struct {
   int32_t stage, round;
@@ -199,6 +207,15 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
               ba_refine_round *hist);
 /* n_obs flags in the caller's observation order: 1 = in the problem. */
 int ba_get_active(const ba_problem *p, uint8_t *active_out);
+/* Batched triangulation from scratch (the triangulation step of Sec. 4.3, one thread
+   per point): every point of d from all its observations, with the cameras held at
+   d->poses, by BA_TRI_MIDPOINT or BA_TRI_DLT, in FP64.  points_out (3 * n_pts) receives
+   the point, or d->points_xyz's value (NaN when that is NULL) where ok_out is 0: fewer
+   than two observations, a degenerate system, or a point not in front of every camera
+   that observes it.  d->points_xyz may be NULL; the other inputs are validated as by
+   ba_create.  device_ms (may be NULL): the kernel's device time. */
+int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, double *points_out,
+                   uint8_t *ok_out, double *device_ms);
 /* Copy the current state and the report of the last solve.  NULL outputs are
    skipped.  poses_out: n_cams entries; points_out: 3 * n_pts doubles. */
 int ba_get_result(const ba_problem *p, ba_pose *poses_out, double *points_out, ba_report *rep);

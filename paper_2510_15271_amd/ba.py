@@ -87,7 +87,11 @@ class RigDesc(C.Structure):
 
 
 class RefineStage(C.Structure):
-    _fields_ = [("huber_delta", C.c_double), ("cull_px", C.c_double)]
+    _fields_ = [("huber_delta", C.c_double), ("cull_px", C.c_double), ("triangulation", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+TRI = {"midpoint": 0, "dlt": 1}
 
 
 class RefineRound(C.Structure):
@@ -136,6 +140,7 @@ def lib():
     L.ba_rig_create.argtypes = [C.POINTER(RigDesc), C.POINTER(Options), vp, C.POINTER(vp)]
     L.ba_rig_get_result.argtypes = [vp, vp, vp, vp, C.POINTER(Report)]
     L.ba_get_active.argtypes = [vp, vp]
+    L.ba_triangulate.argtypes = [C.POINTER(ProblemDesc), i32, vp, vp, vp, dp]
     L.ba_problem_bytes.argtypes = [vp]
     L.ba_problem_bytes.restype = i64
     L.ba_destroy.argtypes = [vp]
@@ -278,6 +283,17 @@ def rig_desc(s, prior_ext=0.0, prior_rig=0.0, rig_pairs=None) -> _RigDesc:
                     s.fixed_e, prior_ext, prior_rig, rig_pairs)
 
 
+def triangulate(desc: _Desc, method="midpoint", stream=None):
+    """ba_triangulate: every point from its observations with the cameras held at the
+    description's poses; returns (points (P, 3), ok (P,) bool, device ms)."""
+    P = int(desc.desc.n_pts)
+    X = np.zeros((P, 3))
+    ok = np.zeros(P, np.uint8)
+    ms = C.c_double()
+    _check(lib().ba_triangulate(C.byref(desc.desc), TRI[method], stream, _ptr(X), _ptr(ok), C.byref(ms)))
+    return X, ok.astype(bool), ms.value
+
+
 def pose_graph_desc(g) -> _GraphDesc:
     return _GraphDesc(g.q0, g.t0, g.edge_i, g.edge_j, g.meas_q, g.meas_t, g.w_rot, g.w_trans,
                       g.fixed, g.edge_type)
@@ -362,9 +378,10 @@ class Problem:
         _check(lib().ba_solve_async(self._h))
 
     def refine(self, stages, rounds):
-        """ba_refine: stages is a sequence of (huber_delta, cull_px); returns one
-        dict per (stage, round), stage-major."""
-        st = (RefineStage * len(stages))(*[RefineStage(float(d), float(t)) for d, t in stages])
+        """ba_refine: stages is a sequence of (huber_delta, cull_px[, "midpoint" | "dlt"]);
+        returns one dict per (stage, round), stage-major."""
+        st = (RefineStage * len(stages))(*[RefineStage(float(g[0]), float(g[1]),
+                                                       TRI[g[2]] if len(g) > 2 else 0, 0) for g in stages])
         hist = (RefineRound * max(len(stages) * int(rounds), 1))()
         _check(lib().ba_refine(self._h, len(stages), st, int(rounds), hist))
         return [{f: getattr(h, f) for f, _ in RefineRound._fields_ if f != "reserved"}

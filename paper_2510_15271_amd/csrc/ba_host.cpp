@@ -1767,6 +1767,8 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
       return fail(BA_EINVAL, "stage %d: huber_delta must be finite", i);
     if (!std::isfinite(stages[i].cull_px) || !(stages[i].cull_px > 0.0))
       return fail(BA_EINVAL, "stage %d: cull_px must be positive and finite", i);
+    if (stages[i].triangulation != BA_TRI_MIDPOINT && stages[i].triangulation != BA_TRI_DLT)
+      return fail(BA_EINVAL, "stage %d: unknown triangulation method %d", i, stages[i].triangulation);
   }
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
@@ -1796,7 +1798,7 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
       if (rc != BA_OK) break;
       const double tau = stages[si].cull_px;
       if (time_cull) (void)hipEventRecord(c0, p->stream);
-      hipError_t e = launch_cull(dp.precision, p->batch.plan, tau * tau, p->stream, nullptr);
+      hipError_t e = launch_cull(dp.precision, p->batch.plan, tau * tau, stages[si].triangulation, p->stream, nullptr);
       if (time_cull) (void)hipEventRecord(c1, p->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(cnt.data(), dp.view.part_cull, cnt.size() * 4, hipMemcpyDeviceToHost, p->stream);
@@ -1842,6 +1844,93 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
   hipError_t e = launch_eval(dp.precision, p->batch.plan, p->stream, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return hip_fail(e, "evaluation");
+  return BA_OK;
+}
+
+int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, double *points_out,
+                   uint8_t *ok_out, double *device_ms) {
+  if (!d) return fail(BA_EINVAL, "problem description is NULL");
+  if (method != BA_TRI_MIDPOINT && method != BA_TRI_DLT) return fail(BA_EINVAL, "unknown triangulation method %d", method);
+  if (!points_out || !ok_out) return fail(BA_EINVAL, "NULL output");
+  if (d->n_cams < 1 || d->n_pts < 1 || d->n_obs < 1) return fail(BA_EINVAL, "n_cams, n_pts and n_obs must be >= 1");
+  if (d->n_obs > (int64_t)INT32_MAX - 1) return fail(BA_EINVAL, "n_obs exceeds 2^31 - 2");
+  if (!d->K || !d->poses || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
+  const int C = d->n_cams, P = d->n_pts;
+  const int64_t N = d->n_obs;
+  const int nK = d->K_per_cam ? C : 1;
+  for (int i = 0; i < nK; ++i) {
+    const ba_intrinsics &k = d->K[i];
+    if (!(std::isfinite(k.fx) && std::isfinite(k.fy) && std::isfinite(k.cx) && std::isfinite(k.cy)) ||
+        k.fx == 0.0 || k.fy == 0.0)
+      return fail(BA_EINVAL, "intrinsics %d invalid", i);
+  }
+  for (int i = 0; i < C; ++i)
+    if (int e = check_pose(d->poses[i], "camera", i)) return e;
+  std::vector<int32_t> start(P + 1, 0);
+  for (int64_t k = 0; k < N; ++k) {
+    const ba_obs &o = d->obs[k];
+    if (o.cam < 0 || o.cam >= C) return fail(BA_EINVAL, "observation %lld: camera %d out of range", (long long)k, o.cam);
+    if (o.pt < 0 || o.pt >= P) return fail(BA_EINVAL, "observation %lld: point %d out of range", (long long)k, o.pt);
+    if (!std::isfinite(o.u) || !std::isfinite(o.v)) return fail(BA_EINVAL, "observation %lld non-finite", (long long)k);
+    start[o.pt + 1]++;
+  }
+  if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
+  for (int j = 0; j < P; ++j) start[j + 1] += start[j];
+  // observations by point (stable), with normalized coordinates
+  std::vector<int32_t> cam(N), fill(start.begin(), start.end() - 1);
+  std::vector<double> xy(2 * N), poses(12 * (size_t)C), X(3 * (size_t)P);
+  for (int64_t k = 0; k < N; ++k) {
+    const ba_obs &o = d->obs[k];
+    const ba_intrinsics &K = d->K[d->K_per_cam ? o.cam : 0];
+    const int32_t at = fill[o.pt]++;
+    cam[at] = o.cam;
+    xy[2 * (size_t)at] = (o.u - K.cx) / K.fx;
+    xy[2 * (size_t)at + 1] = (o.v - K.cy) / K.fy;
+  }
+  for (int i = 0; i < C; ++i) quat_to_pose12(d->poses[i], &poses[12 * (size_t)i]);
+  for (size_t i = 0; i < X.size(); ++i) X[i] = d->points_xyz ? d->points_xyz[i] : NAN;
+  hipStream_t s = (hipStream_t)hip_stream;
+  bool own = false;
+  if (!s) {
+    hipError_t e = hipStreamCreate(&s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    own = true;
+  }
+  const size_t b_start = ((size_t)(P + 1) * 4 + 255) & ~size_t(255), b_cam = ((size_t)N * 4 + 255) & ~size_t(255);
+  const size_t b_xy = (size_t)N * 16, b_pose = (size_t)C * 96, b_X = (size_t)P * 24, b_ok = ((size_t)P + 255) & ~size_t(255);
+  char *mem = nullptr;
+  hipError_t e = hipMalloc((void **)&mem, b_start + b_cam + b_xy + b_pose + b_X + b_ok);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  char *q = mem;
+  int32_t *d_start = (int32_t *)q;
+  int32_t *d_cam = (int32_t *)(q += b_start);
+  double *d_xy = (double *)(q += b_cam);
+  double *d_pose = (double *)(q += b_xy);
+  double *d_X = (double *)(q += b_pose);
+  uint8_t *d_ok = (uint8_t *)(q += b_X);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_cam, cam.data(), cam.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_xy, xy.data(), xy.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_pose, poses.data(), poses.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_X, X.data(), X.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = launch_triangulate(P, d_start, d_cam, d_xy, d_pose, method, d_X, d_ok, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(points_out, d_X, X.size() * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ok_out, d_ok, (size_t)P, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && device_ms) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *device_ms = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (mem) (void)hipFree(mem);
+  if (own) (void)hipStreamDestroy(s);
+  if (e != hipSuccess) return hip_fail(e, "triangulation");
   return BA_OK;
 }
 

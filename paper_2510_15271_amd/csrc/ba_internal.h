@@ -262,7 +262,11 @@ hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, Kernel
 // Culling and re-triangulation at the accepted state: observations with
 // ||r||^2 > tau2 (or depth <= the threshold) leave the problem; points that lost
 // one are re-triangulated (midpoint) from the rest, or leave if that fails.
-hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, hipStream_t s, KernelTimer *timer);
+hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, int method, hipStream_t s,
+                       KernelTimer *timer);
+// Triangulation from scratch (method 0 midpoint, 1 DLT), one thread per point.
+hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
+                              const double *poses, int method, double *X, uint8_t *ok, hipStream_t s);
 // Pose-only Gauss-Newton, one workgroup per request.
 hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
                           double huber_delta, hipStream_t s, KernelTimer *timer);

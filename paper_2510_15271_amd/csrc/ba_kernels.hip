@@ -2336,25 +2336,33 @@ __global__ __launch_bounds__(256) void k_eval(const ProbDev *__restrict__ probs,
 // point; per-tile counts of active observations and of points with at least one
 // go to part_cull.
 
-// Midpoint triangulation from the active observations [k0, k1) of one point: the X
-// minimising the summed squared distances to the observation rays, i.e. the solution
-// of (sum_k (I - d_k d_k^T)) X = sum_k (I - d_k d_k^T) c_k with centre c_k = -R^T t and
-// unit ray d_k along R^T K^-1 (u, v, 1), by the adjugate in FP64.  Fails when the 3x3
-// determinant is <= 1e-12 or some active observation has depth <= kZMin at X.
-template <class T>
-__device__ bool triangulate_midpoint(const ProbDev &pd, const double *poses, int k0, int k1,
-                                     double out[3]) {
-  const T *Kall = (const T *)pd.K;
-  const T *uv = (const T *)pd.obs_uv;
+// Triangulation of one point from observations given by get(k, P, x, y): false if
+// observation k is not used, else the world -> camera pose P (12 values) and the
+// normalized image coordinates (x, y) = K^-1 (u, v).  Both methods run in FP64 and fail
+// when an observation that is used would see the point at depth <= kZMin.
+template <class Get>
+__device__ inline bool tri_depths_ok(int n, Get get, const double X[3]) {
+  for (int k = 0; k < n; ++k) {
+    const double *P;
+    double x, y;
+    if (!get(k, P, x, y)) continue;
+    if (!(P[6] * X[0] + P[7] * X[1] + P[8] * X[2] + P[11] > kZMin)) return false;
+  }
+  return true;
+}
+
+// Midpoint: the X minimising the summed squared distances to the observation rays, the
+// solution of (sum_k (I - d_k d_k^T)) X = sum_k (I - d_k d_k^T) c_k with centre
+// c_k = -R^T t and unit ray d_k along R^T (x, y, 1), by the adjugate.  Fails when the 3x3
+// determinant is <= 1e-12.
+template <class Get>
+__device__ bool tri_midpoint(int n, Get get, double out[3]) {
   double A[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // xx, xy, xz, yy, yz, zz
   double b[3] = {0.0, 0.0, 0.0};
-  for (int k = k0; k < k1; ++k) {
-    if (!pd.obs_act[k]) continue;
-    const int cam = pd.obs_cam[k];
-    const double *P = poses + 12 * cam;
-    const T *K = Kall + 4 * cam;
-    const double a0 = ((double)uv[2 * (size_t)k] - (double)K[2]) / (double)K[0];
-    const double a1 = ((double)uv[2 * (size_t)k + 1] - (double)K[3]) / (double)K[1];
+  for (int k = 0; k < n; ++k) {
+    const double *P;
+    double a0, a1;
+    if (!get(k, P, a0, a1)) continue;
     double d[3], c[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -2386,17 +2394,81 @@ __device__ bool triangulate_midpoint(const ProbDev &pd, const double *poses, int
   out[0] = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
   out[1] = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
   out[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
-  for (int k = k0; k < k1; ++k) {
-    if (!pd.obs_act[k]) continue;
-    const double *P = poses + 12 * pd.obs_cam[k];
-    if (!(P[6] * out[0] + P[7] * out[1] + P[8] * out[2] + P[11] > kZMin)) return false;
+  return tri_depths_ok(n, get, out);
+}
+
+// DLT (the classical homogeneous form): each observation contributes the rows
+// x P_3 - P_1 and y P_3 - P_2 of A; X~ is the unit eigenvector of A^T A (4x4, FP64) for
+// its smallest eigenvalue, found by cyclic Jacobi rotations (8 sweeps), and
+// X = X~[:3] / X~[3].  Fails when |X~[3]| <= 1e-12.
+template <class Get>
+__device__ bool tri_dlt(int n, Get get, double out[3]) {
+  double M[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) M[a][b] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double *P;
+    double x, y;
+    if (!get(k, P, x, y)) continue;
+    // P rows: (R_r0, R_r1, R_r2, t_r)
+    double r1[4], r2[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r1[c] = x * P[6 + c] - P[c];
+      r2[c] = y * P[6 + c] - P[3 + c];
+    }
+    r1[3] = x * P[11] - P[9];
+    r2[3] = y * P[11] - P[10];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) M[a][b] += r1[a] * r1[b] + r2[a] * r2[b];
   }
-  return true;
+  double V[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) V[a][b] = a == b ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 8; ++sweep)
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        const double apq = M[p][q];
+        if (apq == 0.0) continue;
+        const double tau = (M[q][q] - M[p][p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < 4; ++k) {  // columns p, q of M
+          const double mkp = M[k][p], mkq = M[k][q];
+          M[k][p] = c * mkp - s * mkq;
+          M[k][q] = s * mkp + c * mkq;
+        }
+        for (int k = 0; k < 4; ++k) {  // rows p, q of M
+          const double mpk = M[p][k], mqk = M[q][k];
+          M[p][k] = c * mpk - s * mqk;
+          M[q][k] = s * mpk + c * mqk;
+        }
+        for (int k = 0; k < 4; ++k) {  // columns p, q of V
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  int mi = 0;
+  for (int a = 1; a < 4; ++a)
+    if (M[a][a] < M[mi][mi]) mi = a;
+  const double w = V[3][mi];
+  if (!(fabs(w) > 1e-12)) return false;
+  out[0] = V[0][mi] / w;
+  out[1] = V[1][mi] / w;
+  out[2] = V[2][mi] / w;
+  return tri_depths_ok(n, get, out);
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_cull(const ProbDev *__restrict__ probs,
-                                              const Tile *__restrict__ tiles, double tau2) {
+                                              const Tile *__restrict__ tiles, double tau2, int method) {
   static_assert(kPtTile == 256, "one thread per point of a tile");
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
@@ -2433,7 +2505,18 @@ __global__ __launch_bounds__(256) void k_cull(const ProbDev *__restrict__ probs,
     }
     if (lost) {
       double Xn[3];
-      if (n_act >= 2 && triangulate_midpoint<T>(pd, poses, k0, k1, Xn)) {
+      auto get = [&](int kk, const double *&P, double &x, double &y) {
+        const int k = k0 + kk;
+        if (!pd.obs_act[k]) return false;
+        const int cam = pd.obs_cam[k];
+        const T *K = Kall + 4 * cam;
+        P = poses + 12 * cam;
+        x = ((double)uv[2 * (size_t)k] - (double)K[2]) / (double)K[0];
+        y = ((double)uv[2 * (size_t)k + 1] - (double)K[3]) / (double)K[1];
+        return true;
+      };
+      const bool ok = n_act >= 2 && (method == 1 ? tri_dlt(k1 - k0, get, Xn) : tri_midpoint(k1 - k0, get, Xn));
+      if (ok) {
         X[0] = Xn[0];
         X[1] = Xn[1];
         X[2] = Xn[2];
@@ -3160,13 +3243,49 @@ hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, Kernel
   return hipGetLastError();
 }
 
-hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, hipStream_t s, KernelTimer *timer) {
+hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, int method, hipStream_t s,
+                       KernelTimer *timer) {
   if (!bp.n_pt) return hipSuccess;
   Timed t(timer, K_CULL, s);
   if (precision == 0)
-    k_cull<double><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2);
+    k_cull<double><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2, method);
   else
-    k_cull<float><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2);
+    k_cull<float><<<bp.n_pt, 256, 0, s>>>(bp.probs, bp.pt, tau2, method);
+  return hipGetLastError();
+}
+
+// Triangulation from scratch, one thread per point: observations ordered by point
+// (pt_start), each with its camera and normalized coordinates; a point with fewer than
+// two observations, or whose triangulation fails, keeps its input value and ok = 0.
+__global__ __launch_bounds__(256) void k_triangulate(int n_pts, const int32_t *__restrict__ pt_start,
+                                                     const int32_t *__restrict__ cam,
+                                                     const double *__restrict__ xy,
+                                                     const double *__restrict__ poses, int method,
+                                                     double *__restrict__ X, uint8_t *__restrict__ ok) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_pts) return;
+  const int k0 = pt_start[j], n = pt_start[j + 1] - k0;
+  auto get = [&](int kk, const double *&P, double &x, double &y) {
+    const int k = k0 + kk;
+    P = poses + 12 * (size_t)cam[k];
+    x = xy[2 * (size_t)k];
+    y = xy[2 * (size_t)k + 1];
+    return true;
+  };
+  double Xn[3];
+  const bool good = n >= 2 && (method == 1 ? tri_dlt(n, get, Xn) : tri_midpoint(n, get, Xn));
+  if (good) {
+    X[3 * (size_t)j] = Xn[0];
+    X[3 * (size_t)j + 1] = Xn[1];
+    X[3 * (size_t)j + 2] = Xn[2];
+  }
+  ok[j] = good ? 1 : 0;
+}
+
+hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
+                              const double *poses, int method, double *X, uint8_t *ok, hipStream_t s) {
+  if (n_pts <= 0) return hipSuccess;
+  k_triangulate<<<(n_pts + 255) / 256, 256, 0, s>>>(n_pts, pt_start, cam, xy, poses, method, X, ok);
   return hipGetLastError();
 }
 

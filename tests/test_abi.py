@@ -101,7 +101,8 @@ def test_refine_validation(balib):
     L = balib.lib()
 
     def call(stages, rounds, n=None):
-        st = (balib.RefineStage * max(len(stages), 1))(*[balib.RefineStage(d, t) for d, t in stages])
+        st = (balib.RefineStage * max(len(stages), 1))(*[balib.RefineStage(g[0], g[1], g[2] if len(g) > 2 else 0, 0)
+                                                          for g in stages])
         rc = L.ba_refine(None, len(stages) if n is None else n, st, rounds, None)
         return rc, L.ba_last_error().decode()
 
@@ -111,6 +112,8 @@ def test_refine_validation(balib):
                         ((1.0, -2.0), "cull_px"), ((0.0, np.inf), "cull_px")]:
         rc, msg = call([(1.0, 8.0), bad], 2)
         assert rc == balib.BA_EINVAL and "stage 1" in msg and needle in msg, msg
+    rc, msg = call([(1.0, 8.0), (0.0, 3.0, 2)], 2)
+    assert rc == balib.BA_EINVAL and "stage 1" in msg and "triangulation" in msg, msg
     rc, msg = call([(1.0, 8.0), (0.0, 3.0)], 2)
     assert rc == balib.BA_EINVAL and "NULL" in msg
     assert L.ba_get_active(None, None) == balib.BA_EINVAL
@@ -195,3 +198,24 @@ def test_rig_validation(balib):
     def too_many(rd):
         rd.desc.n_rig = 17
     expect("n_rig", too_many)
+
+
+def test_triangulate_validation(balib):
+    s = make_arc_scene(3, 20, seed=1)
+    d = balib.scene_desc(s)
+    L = balib.lib()
+    X = np.zeros((s.n_pts, 3))
+    ok = np.zeros(s.n_pts, np.uint8)
+
+    def call(method=0, out=True):
+        rc = L.ba_triangulate(ctypes.byref(d.desc), method, None, X.ctypes.data_as(ctypes.c_void_p) if out else None,
+                              ok.ctypes.data_as(ctypes.c_void_p), None)
+        return rc, L.ba_last_error().decode()
+
+    rc, msg = call(method=5)
+    assert rc == balib.BA_EINVAL and "method" in msg
+    rc, msg = call(out=False)
+    assert rc == balib.BA_EINVAL and "NULL" in msg
+    d.obs["pt"][0] = s.n_pts
+    rc, msg = call()
+    assert rc == balib.BA_EINVAL and "out of range" in msg
