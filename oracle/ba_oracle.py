@@ -1114,3 +1114,48 @@ def triangulate_points(p: Problem, method: str = "midpoint"):
         if okj:
             X[j], ok[j] = Xj, True
     return X, ok
+
+
+def ransac_pair(h: int, n: int):
+    """Observation pair of hypothesis h on a track of n observations (a fixed schedule
+    that lists every ordered pair once within its first n (n - 1) hypotheses):
+    a = h mod n, b = (a + 1 + (h div n) mod (n - 1)) mod n."""
+    a = h % n
+    return a, (a + 1 + (h // n) % (n - 1)) % n
+
+
+def triangulate_ransac(p: Problem, j: int, tau_px: float, n_hyp: int, method: str = "midpoint",
+                       R=None, t=None):
+    """RANSAC triangulation of track j (Sec. 4.3): hypothesis h = 0 .. n_hyp - 1 takes
+    the observation pair ransac_pair(h, n) of the track (observations in index order),
+    triangulates it by the midpoint of the two rays (triangulate_midpoint on the pair)
+    and, when that succeeds, counts the track's observations with depth > Z_MIN and
+    ||r|| <= tau_px at that point.  The first hypothesis with the most inliers wins; with
+    at least two inliers the point is triangulated from them by ``method``.  Returns
+    (X, ok, inlier flags over the track's observations)."""
+    R = p.R if R is None else R
+    t = p.t if t is None else t
+    ks = np.nonzero(p.pt == j)[0]
+    n = ks.size
+    none = (None, False, np.zeros(n, bool))
+    if n < 2:
+        return none
+    best, best_in = -1, None
+    for h in range(n_hyp):
+        a, b = ransac_pair(h, n)
+        q = dataclasses.replace(p, active=np.zeros(p.n_obs, bool))
+        q.active[[ks[a], ks[b]]] = True
+        X, ok = triangulate_midpoint(q, j, R, t)
+        if not ok:
+            continue
+        Kk = p.K[p.cam[ks]]
+        uv, Pc = project(Kk, R[p.cam[ks]], t[p.cam[ks]], np.broadcast_to(X, (n, 3)))
+        inl = (Pc[:, 2] > Z_MIN) & (np.sum((uv - p.uv[ks]) ** 2, axis=1) <= tau_px * tau_px)
+        if int(inl.sum()) > best:
+            best, best_in = int(inl.sum()), inl
+    if best < 2:
+        return none
+    q = dataclasses.replace(p, active=np.zeros(p.n_obs, bool))
+    q.active[ks[best_in]] = True
+    X, ok = (triangulate_midpoint if method == "midpoint" else triangulate_dlt)(q, j, R, t)
+    return (X, True, best_in) if ok else none

@@ -1,5 +1,6 @@
 """Pins of the FP64 oracle against things other than itself: closed forms,
 finite differences, SciPy routines, invariants and statistics.  CPU only."""
+import dataclasses
 import math
 
 import numpy as np
@@ -787,3 +788,36 @@ def test_midpoint_equals_the_printed_dlt_objective_with_free_scales():
         sol = np.linalg.lstsq(M, rhs, rcond=None)[0]
         X, ok = O.triangulate_midpoint(p, j)
         assert ok and np.linalg.norm(sol[:3] - X) <= 1e-8 * (1 + np.linalg.norm(X))
+
+
+def test_ransac_pair_schedule_lists_every_ordered_pair():
+    for n in range(2, 12):
+        pairs = {O.ransac_pair(h, n) for h in range(n * (n - 1))}
+        assert pairs == {(a, b) for a in range(n) for b in range(n) if a != b}
+
+
+def test_ransac_triangulation_rejects_planted_outliers():
+    """Tracks of a noiseless drive with one or two observations replaced by far-off pixels:
+    RANSAC flags exactly the planted ones as outliers and the point equals the
+    midpoint of the clean observations; on a clean track it equals the plain midpoint."""
+    s = make_small_drive(12, 300, seed=47, sigma=0.0)
+    p = _gt_problem(s)
+    rng = np.random.default_rng(3)
+    counts = np.bincount(p.pt, minlength=p.n_pts)
+    tested = 0
+    for j in np.nonzero(counts >= 5)[0][:40]:
+        ks = np.nonzero(p.pt == j)[0]
+        bad = rng.choice(ks.size, size=1 + tested % 2, replace=False)
+        q = dataclasses.replace(p, uv=p.uv.copy())
+        q.uv[ks[bad]] += rng.uniform(40, 80, (bad.size, 2)) * rng.choice([-1, 1], (bad.size, 2))
+        X, ok, inl = O.triangulate_ransac(q, j, 3.0, 64)
+        want = np.ones(ks.size, bool)
+        want[bad] = False
+        assert ok and np.array_equal(inl, want)
+        assert np.linalg.norm(X - p.X[j]) <= 1e-8 * (1 + np.linalg.norm(p.X[j]))
+        tested += 1
+    assert tested >= 20
+    j = int(np.nonzero(counts >= 3)[0][0])
+    X, ok, inl = O.triangulate_ransac(p, j, 3.0, 64)
+    Xm, okm = O.triangulate_midpoint(p, j)
+    assert ok and inl.all() and np.linalg.norm(X - Xm) <= 1e-12 * (1 + np.linalg.norm(Xm))
