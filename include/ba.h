@@ -216,6 +216,17 @@ int ba_get_active(const ba_problem *p, uint8_t *active_out);
    ba_create.  device_ms (may be NULL): the kernel's device time. */
 int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, double *points_out,
                    uint8_t *ok_out, double *device_ms);
+/* RANSAC triangulation per track (Sec. 4.3), as ba_triangulate plus outlier rejection:
+   hypothesis h = 0 .. n_hyp - 1 of a track of n observations (in the caller's order)
+   takes the pair a = h mod n, b = (a + 1 + (h div n) mod (n - 1)) mod n, a fixed schedule
+   that lists every ordered pair once within n (n - 1) hypotheses; the two-ray midpoint
+   scores the observations in front of their camera with a reprojection error of at most
+   tau_px; the first hypothesis with the most inliers wins, and with at least two the
+   point is triangulated from them by `method`.  inlier_out: n_obs flags in the caller's
+   order (all 0 on a failed track).  BA_EINVAL also for tau_px not positive and finite or
+   n_hyp outside 1..4096. */
+int ba_triangulate_ransac(const ba_problem_desc *d, int32_t method, double tau_px, int32_t n_hyp, void *hip_stream,
+                          double *points_out, uint8_t *ok_out, uint8_t *inlier_out, double *device_ms);
 /* Copy the current state and the report of the last solve.  NULL outputs are
    skipped.  poses_out: n_cams entries; points_out: 3 * n_pts doubles. */
 int ba_get_result(const ba_problem *p, ba_pose *poses_out, double *points_out, ba_report *rep);

@@ -141,6 +141,7 @@ def lib():
     L.ba_rig_get_result.argtypes = [vp, vp, vp, vp, C.POINTER(Report)]
     L.ba_get_active.argtypes = [vp, vp]
     L.ba_triangulate.argtypes = [C.POINTER(ProblemDesc), i32, vp, vp, vp, dp]
+    L.ba_triangulate_ransac.argtypes = [C.POINTER(ProblemDesc), i32, C.c_double, i32, vp, vp, vp, vp, dp]
     L.ba_problem_bytes.argtypes = [vp]
     L.ba_problem_bytes.restype = i64
     L.ba_destroy.argtypes = [vp]
@@ -292,6 +293,18 @@ def triangulate(desc: _Desc, method="midpoint", stream=None):
     ms = C.c_double()
     _check(lib().ba_triangulate(C.byref(desc.desc), TRI[method], stream, _ptr(X), _ptr(ok), C.byref(ms)))
     return X, ok.astype(bool), ms.value
+
+
+def triangulate_ransac(desc: _Desc, tau_px=3.0, n_hyp=64, method="midpoint", stream=None):
+    """ba_triangulate_ransac: returns (points (P, 3), ok (P,) bool, inliers (N,) bool, device ms)."""
+    P, N = int(desc.desc.n_pts), int(desc.desc.n_obs)
+    X = np.zeros((P, 3))
+    ok = np.zeros(P, np.uint8)
+    inl = np.zeros(N, np.uint8)
+    ms = C.c_double()
+    _check(lib().ba_triangulate_ransac(C.byref(desc.desc), TRI[method], float(tau_px), int(n_hyp), stream, _ptr(X),
+                                       _ptr(ok), _ptr(inl), C.byref(ms)))
+    return X, ok.astype(bool), inl.astype(bool), ms.value
 
 
 def pose_graph_desc(g) -> _GraphDesc:

@@ -1847,11 +1847,15 @@ int ba_refine(ba_problem *p, int32_t n_stages, const ba_refine_stage *stages, in
   return BA_OK;
 }
 
-int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, double *points_out,
-                   uint8_t *ok_out, double *device_ms) {
+// Triangulation from scratch on the device (plain, or RANSAC when inlier_out is given).
+static int triangulate_impl(const ba_problem_desc *d, int32_t method, bool ransac, double tau_px, int32_t n_hyp,
+                            void *hip_stream, double *points_out, uint8_t *ok_out, uint8_t *inlier_out,
+                            double *device_ms) {
   if (!d) return fail(BA_EINVAL, "problem description is NULL");
   if (method != BA_TRI_MIDPOINT && method != BA_TRI_DLT) return fail(BA_EINVAL, "unknown triangulation method %d", method);
-  if (!points_out || !ok_out) return fail(BA_EINVAL, "NULL output");
+  if (!points_out || !ok_out || (ransac && !inlier_out)) return fail(BA_EINVAL, "NULL output");
+  if (ransac && !(std::isfinite(tau_px) && tau_px > 0.0)) return fail(BA_EINVAL, "tau_px must be positive and finite");
+  if (ransac && (n_hyp < 1 || n_hyp > 4096)) return fail(BA_EINVAL, "n_hyp must be in 1..4096");
   if (d->n_cams < 1 || d->n_pts < 1 || d->n_obs < 1) return fail(BA_EINVAL, "n_cams, n_pts and n_obs must be >= 1");
   if (d->n_obs > (int64_t)INT32_MAX - 1) return fail(BA_EINVAL, "n_obs exceeds 2^31 - 2");
   if (!d->K || !d->poses || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
@@ -1877,12 +1881,20 @@ int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, d
   if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
   for (int j = 0; j < P; ++j) start[j + 1] += start[j];
   // observations by point (stable), with normalized coordinates
-  std::vector<int32_t> cam(N), fill(start.begin(), start.end() - 1);
-  std::vector<double> xy(2 * N), poses(12 * (size_t)C), X(3 * (size_t)P);
+  std::vector<int32_t> cam(N), fill(start.begin(), start.end() - 1), where(N);
+  std::vector<double> xy(2 * N), poses(12 * (size_t)C), X(3 * (size_t)P), Kc(4 * (size_t)C);
+  for (int i = 0; i < C; ++i) {
+    const ba_intrinsics &K = d->K[d->K_per_cam ? i : 0];
+    Kc[4 * i] = K.fx;
+    Kc[4 * i + 1] = K.fy;
+    Kc[4 * i + 2] = K.cx;
+    Kc[4 * i + 3] = K.cy;
+  }
   for (int64_t k = 0; k < N; ++k) {
     const ba_obs &o = d->obs[k];
     const ba_intrinsics &K = d->K[d->K_per_cam ? o.cam : 0];
     const int32_t at = fill[o.pt]++;
+    where[k] = at;
     cam[at] = o.cam;
     xy[2 * (size_t)at] = (o.u - K.cx) / K.fx;
     xy[2 * (size_t)at + 1] = (o.v - K.cy) / K.fy;
@@ -1898,8 +1910,9 @@ int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, d
   }
   const size_t b_start = ((size_t)(P + 1) * 4 + 255) & ~size_t(255), b_cam = ((size_t)N * 4 + 255) & ~size_t(255);
   const size_t b_xy = (size_t)N * 16, b_pose = (size_t)C * 96, b_X = (size_t)P * 24, b_ok = ((size_t)P + 255) & ~size_t(255);
+  const size_t b_K = (size_t)C * 32, b_in = ((size_t)N + 255) & ~size_t(255);
   char *mem = nullptr;
-  hipError_t e = hipMalloc((void **)&mem, b_start + b_cam + b_xy + b_pose + b_X + b_ok);
+  hipError_t e = hipMalloc((void **)&mem, b_start + b_cam + b_xy + b_pose + b_X + b_ok + b_K + b_in);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1910,17 +1923,27 @@ int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, d
   double *d_pose = (double *)(q += b_xy);
   double *d_X = (double *)(q += b_pose);
   uint8_t *d_ok = (uint8_t *)(q += b_X);
+  double *d_K = (double *)(q += b_ok);
+  uint8_t *d_in = (uint8_t *)(q += b_K);
   if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_cam, cam.data(), cam.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_xy, xy.data(), xy.size() * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_pose, poses.data(), poses.size() * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_X, X.data(), X.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_K, Kc.data(), Kc.size() * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(e0, s);
-  if (e == hipSuccess) e = launch_triangulate(P, d_start, d_cam, d_xy, d_pose, method, d_X, d_ok, s);
+  if (e == hipSuccess)
+    e = ransac ? launch_triangulate_ransac(P, d_start, d_cam, d_xy, d_pose, d_K, tau_px * tau_px, n_hyp, method, d_X,
+                                           d_ok, d_in, s)
+               : launch_triangulate(P, d_start, d_cam, d_xy, d_pose, method, d_X, d_ok, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipMemcpyAsync(points_out, d_X, X.size() * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(ok_out, d_ok, (size_t)P, hipMemcpyDeviceToHost, s);
+  std::vector<uint8_t> in_sorted(ransac ? N : 0);
+  if (e == hipSuccess && ransac) e = hipMemcpyAsync(in_sorted.data(), d_in, (size_t)N, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && ransac)
+    for (int64_t k = 0; k < N; ++k) inlier_out[k] = in_sorted[where[k]];
   if (e == hipSuccess && device_ms) {
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1932,6 +1955,16 @@ int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, d
   if (own) (void)hipStreamDestroy(s);
   if (e != hipSuccess) return hip_fail(e, "triangulation");
   return BA_OK;
+}
+
+int ba_triangulate(const ba_problem_desc *d, int32_t method, void *hip_stream, double *points_out,
+                   uint8_t *ok_out, double *device_ms) {
+  return triangulate_impl(d, method, false, 0.0, 0, hip_stream, points_out, ok_out, nullptr, device_ms);
+}
+
+int ba_triangulate_ransac(const ba_problem_desc *d, int32_t method, double tau_px, int32_t n_hyp, void *hip_stream,
+                          double *points_out, uint8_t *ok_out, uint8_t *inlier_out, double *device_ms) {
+  return triangulate_impl(d, method, true, tau_px, n_hyp, hip_stream, points_out, ok_out, inlier_out, device_ms);
 }
 
 int ba_get_active(const ba_problem *p, uint8_t *active_out) {

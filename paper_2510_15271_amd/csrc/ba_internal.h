@@ -267,6 +267,10 @@ hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, int meth
 // Triangulation from scratch (method 0 midpoint, 1 DLT), one thread per point.
 hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
                               const double *poses, int method, double *X, uint8_t *ok, hipStream_t s);
+// RANSAC triangulation per track: pair hypotheses, inliers by reprojection threshold.
+hipError_t launch_triangulate_ransac(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
+                                     const double *poses, const double *Kc, double tau2, int n_hyp, int method,
+                                     double *X, uint8_t *ok, uint8_t *inl, hipStream_t s);
 // Pose-only Gauss-Newton, one workgroup per request.
 hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
                           double huber_delta, hipStream_t s, KernelTimer *timer);

@@ -3282,6 +3282,102 @@ __global__ __launch_bounds__(256) void k_triangulate(int n_pts, const int32_t *_
   ok[j] = good ? 1 : 0;
 }
 
+// RANSAC triangulation per track, one thread per point: hypothesis h = 0 .. n_hyp - 1
+// takes the observation pair a = h mod n, b = (a + 1 + (h div n) mod (n - 1)) mod n (every
+// ordered pair once within n (n - 1) hypotheses), triangulates it by the two-ray
+// midpoint and counts the track's observations in front of their camera with a
+// reprojection error of at most sqrt(tau2) pixels; the first hypothesis with the most
+// inliers wins, and with at least two inliers the point is triangulated from them
+// (midpoint or DLT).  inl[k] flags the inliers (all 0 when the track fails).
+__global__ __launch_bounds__(256) void k_triangulate_ransac(int n_pts, const int32_t *__restrict__ pt_start,
+                                                            const int32_t *__restrict__ cam,
+                                                            const double *__restrict__ xy,
+                                                            const double *__restrict__ poses,
+                                                            const double *__restrict__ Kc, double tau2,
+                                                            int n_hyp, int method, double *__restrict__ X,
+                                                            uint8_t *__restrict__ ok, uint8_t *__restrict__ inl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_pts) return;
+  const int k0 = pt_start[j], n = pt_start[j + 1] - k0;
+  auto give_up = [&]() {
+    ok[j] = 0;
+    for (int k = 0; k < n; ++k) inl[k0 + k] = 0;
+  };
+  if (n < 2) {
+    give_up();
+    return;
+  }
+  auto obs = [&](int kk, const double *&P, double &x, double &y) {
+    const int k = k0 + kk;
+    P = poses + 12 * (size_t)cam[k];
+    x = xy[2 * (size_t)k];
+    y = xy[2 * (size_t)k + 1];
+  };
+  auto is_inlier = [&](int kk, const double Xp[3]) {
+    const double *P;
+    double x, y;
+    obs(kk, P, x, y);
+    const double pz = P[6] * Xp[0] + P[7] * Xp[1] + P[8] * Xp[2] + P[11];
+    if (!(pz > kZMin)) return false;
+    const double px = P[0] * Xp[0] + P[1] * Xp[1] + P[2] * Xp[2] + P[9];
+    const double py = P[3] * Xp[0] + P[4] * Xp[1] + P[5] * Xp[2] + P[10];
+    const double *K = Kc + 4 * (size_t)cam[k0 + kk];
+    const double r0 = K[0] * (px / pz - x), r1 = K[1] * (py / pz - y);
+    return r0 * r0 + r1 * r1 <= tau2;
+  };
+  auto pair_point = [&](int h, double Xp[3]) {
+    const int a = h % n, b = (a + 1 + (h / n) % (n - 1)) % n;
+    auto get = [&](int kk, const double *&P, double &x, double &y) {
+      if (kk != a && kk != b) return false;
+      obs(kk, P, x, y);
+      return true;
+    };
+    return tri_midpoint(n, get, Xp);
+  };
+  int best = -1, best_h = -1;
+  for (int h = 0; h < n_hyp; ++h) {
+    double Xp[3];
+    if (!pair_point(h, Xp)) continue;
+    int cnt = 0;
+    for (int kk = 0; kk < n; ++kk) cnt += is_inlier(kk, Xp) ? 1 : 0;
+    if (cnt > best) {
+      best = cnt;
+      best_h = h;
+    }
+  }
+  if (best < 2) {
+    give_up();
+    return;
+  }
+  double Xb[3];
+  pair_point(best_h, Xb);
+  for (int kk = 0; kk < n; ++kk) inl[k0 + kk] = is_inlier(kk, Xb) ? 1 : 0;
+  auto get_in = [&](int kk, const double *&P, double &x, double &y) {
+    if (!inl[k0 + kk]) return false;
+    obs(kk, P, x, y);
+    return true;
+  };
+  double Xn[3];
+  const bool good = method == 1 ? tri_dlt(n, get_in, Xn) : tri_midpoint(n, get_in, Xn);
+  if (!good) {
+    give_up();
+    return;
+  }
+  X[3 * (size_t)j] = Xn[0];
+  X[3 * (size_t)j + 1] = Xn[1];
+  X[3 * (size_t)j + 2] = Xn[2];
+  ok[j] = 1;
+}
+
+hipError_t launch_triangulate_ransac(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
+                                     const double *poses, const double *Kc, double tau2, int n_hyp, int method,
+                                     double *X, uint8_t *ok, uint8_t *inl, hipStream_t s) {
+  if (n_pts <= 0) return hipSuccess;
+  k_triangulate_ransac<<<(n_pts + 255) / 256, 256, 0, s>>>(n_pts, pt_start, cam, xy, poses, Kc, tau2, n_hyp,
+                                                           method, X, ok, inl);
+  return hipGetLastError();
+}
+
 hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
                               const double *poses, int method, double *X, uint8_t *ok, hipStream_t s) {
   if (n_pts <= 0) return hipSuccess;
