@@ -1415,8 +1415,14 @@ __global__ __launch_bounds__(64) void k_schur_finish(const ProbDev *__restrict__
   if (a >= pd.Cf) return;
   double tot[54];
   // no records (a pose graph): the rows kernel does not run and every row sum is zero
+  if (pd.Nf > 0) {
+    const double *rt = pd.row_tot + 54 * (size_t)a;
 #pragma unroll
-  for (int i = 0; i < 54; ++i) tot[i] = pd.Nf > 0 ? pd.row_tot[54 * (size_t)a + i] : 0.0;
+    for (int i = 0; i < 54; ++i) tot[i] = rt[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 54; ++i) tot[i] = 0.0;
+  }
   finish_camera_row<T>(pd, st, a, tot);
 }
 
