@@ -325,6 +325,8 @@ def main():
                     help="skip the pose-graph leg (9000 nodes, 24.7k edges)")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the iterative-refinement leg (outlier drive, two stages)")
+    ap.add_argument("--pcg-resident", action="store_true",
+                    help="run each linear solve as one launch with grid barriers (BA_FLAG_PCG_RESIDENT)")
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -357,7 +359,8 @@ def main():
         LM_ITERS = 15
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
-                                 flags=ba.FLAG_NO_GRAPH if args.no_graph else 0,
+                                 flags=(ba.FLAG_NO_GRAPH if args.no_graph else 0) |
+                                       (ba.FLAG_PCG_RESIDENT if args.pcg_resident else 0),
                                  prior_abs=args.prior_abs, prior_seq=args.prior_seq,
                                  prior_seq_k=args.prior_seq_k)
     info = prob.info()

@@ -60,6 +60,9 @@ extern "C" {
 #define BA_STATUS_OK 0
 #define BA_STATUS_DAMPING 1    /* lambda ended at its upper clamp (1e16)     */
 #define BA_STATUS_NUMERICAL 2  /* the cost became non-finite                  */
+#define BA_STATUS_PCG_SYNC 3   /* the resident PCG's grid barrier timed out (its workgroups
+                                  were not all resident at once): the solve stopped with the
+                                  step rejected; solve without BA_FLAG_PCG_RESIDENT         */
 
 typedef struct { double fx, fy, cx, cy; } ba_intrinsics;         /* pinhole, no distortion  */
 typedef struct { double qw, qx, qy, qz, tx, ty, tz; } ba_pose;   /* world -> camera         */
@@ -99,6 +102,17 @@ typedef struct {
    wave per row) whatever the row density, when the tile's columns fit in LDS.  By
    default that layout is used only for more than 8192 free cameras with sparse rows. */
 #define BA_FLAG_PCG_WIDE 8
+/* BA_FLAG_PCG_RESIDENT: run each linear solve of a single-problem solve as ONE launch
+   whose workgroups stay resident and meet at a grid barrier once per iteration, instead
+   of one launch per iteration: each workgroup keeps its S blocks and preconditioner rows
+   in registers for the whole solve, and no launch gaps remain.  The iterates are the
+   same, bit for bit.  Used when every workgroup of the solve fits on the device at once
+   (at most one 1024-thread workgroup per CU for 4-row tiles) and a tile's columns fit one
+   sweep (at most 170); otherwise ignored (ba_problem_info.pcg_resident reports it).  The
+   barrier needs the CUs to itself: do not run two such solves at the same time, nor
+   other long kernels beside one.  A barrier that times out (about a second) stops the
+   solve with status BA_STATUS_PCG_SYNC instead of waiting forever. */
+#define BA_FLAG_PCG_RESIDENT 16
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */
@@ -244,7 +258,7 @@ typedef struct {
   int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for many sparse
                              rows (at least 1024 free cameras, at most 24 blocks per row
                              on average) 16, or 32 beyond 8192 free cameras            */
-  int32_t reserved;
+  int32_t pcg_resident;   /* 1: BA_FLAG_PCG_RESIDENT was asked for and the problem fits it */
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);
 /* Device bytes held by the problem (the admission byte model of the server). */

@@ -65,7 +65,7 @@ class ProblemInfo(C.Structure):
                 ("n_obs", C.c_int32), ("n_pairs", C.c_int64), ("n_up_blocks", C.c_int32),
                 ("nnzb", C.c_int32), ("n_free_obs", C.c_int32), ("precision", C.c_int32),
                 ("schur_form", C.c_int32), ("n_chunks", C.c_int32), ("n_entries", C.c_int64),
-                ("pcg_rows", C.c_int32), ("reserved", C.c_int32)]
+                ("pcg_rows", C.c_int32), ("pcg_resident", C.c_int32)]
 
 
 class PoseEdge(C.Structure):
@@ -171,6 +171,7 @@ def _check(rc):
 FLAG_NO_GRAPH = 2
 FLAG_PAIR_LISTS = 4
 FLAG_PCG_WIDE = 8
+FLAG_PCG_RESIDENT = 16
 
 
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,

@@ -126,7 +126,7 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE))
+  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE | BA_FLAG_PCG_RESIDENT))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   if (!pose_only) {
     if (!(o->prior_abs >= 0.0) || !std::isfinite(o->prior_abs))
@@ -637,6 +637,8 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   tile_lists(!(sparse_rows || (opt->flags & BA_FLAG_PCG_WIDE)) ? kPcgRows : wide ? kPcgRowsMax : kPcgRowsSparse);
   if (sy.pcg_rows == kPcgRowsMax && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRowsSparse);
   if (sy.pcg_rows == kPcgRowsSparse && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
+  sy.pcg_resident = (opt->flags & BA_FLAG_PCG_RESIDENT) &&
+                    resident_pcg_fits(prec, sy.pcg_rows, (Cf + sy.pcg_rows - 1) / sy.pcg_rows, sy.max_tcols);
   if (sy.chunked)
     return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
   return BA_OK;
@@ -736,6 +738,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_pq = L.take(npcg * 8);
   o.part_cg[0] = L.take(3 * npcg * 8);
   o.part_cg[1] = L.take(3 * npcg * 8);
+  o.cg_flag = L.take(npcg * 4);
   o.part_rr = L.take(npcg * 8);
   o.part_cull = L.take(npt * 8);
   o.iter_cost = L.take((max_iters + 1) * 8);
@@ -790,6 +793,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
   pd.n_pcg_tiles = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   pd.pcg_rows = sy.pcg_rows;
+  pd.pcg_resident = sy.pcg_resident ? 1 : 0;
   pd.n_cam_tiles = (C + kCamTile - 1) / kCamTile;
   pd.K = ptr(off.K);
   pd.free_idx = (const int32_t *)ptr(off.free_idx);
@@ -886,6 +890,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_pq = (double *)ptr(off.part_pq);
   pd.part_cg[0] = (double *)ptr(off.part_cg[0]);
   pd.part_cg[1] = (double *)ptr(off.part_cg[1]);
+  pd.cg_flag = (uint32_t *)ptr(off.cg_flag);
   pd.part_rr = (double *)ptr(off.part_rr);
   pd.part_cull = (int32_t *)ptr(off.part_cull);
   pd.st = (LMState *)ptr(off.st);
@@ -1995,7 +2000,7 @@ int ba_get_info(const ba_problem *p, ba_problem_info *out) {
   out->n_chunks = p->sy.chunked ? (int32_t)p->sy.ch_pt.size() - 1 : 0;
   out->n_entries = (int64_t)p->sy.ent_tgt.size();
   out->pcg_rows = p->sy.pcg_rows;
-  out->reserved = 0;
+  out->pcg_resident = p->sy.pcg_resident ? 1 : 0;
   return BA_OK;
 }
 

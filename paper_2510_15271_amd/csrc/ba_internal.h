@@ -66,7 +66,8 @@ struct LMState {
   double sq_sum;           // sum ||r||^2 at the final state (evaluation kernel)
   int32_t iter, max_iters, relin, status;
   int32_t accepted, cur, pcg_done, pcg_iters;
-  int32_t pcg_max, init_done, n_masked, pad0;
+  int32_t pcg_max, init_done, n_masked;
+  int32_t pcg_fault;       // 1: the resident PCG's grid barrier timed out (the solve stops)
 };
 
 // Device view of one problem.  Arrays typed T hold the compute type of the
@@ -79,6 +80,7 @@ struct ProbDev {
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
   int32_t max_tcols;     // longest tile column list
   int32_t pcg_rows;      // rows per PCG tile: kPcgRows, kPcgRowsSparse or kPcgRowsMax
+  int32_t pcg_resident;  // 1: the whole PCG runs in one launch with grid barriers (k_cg_run)
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
   int32_t n_red_tiles;   // reduction tiles (chunk form): 64 elements of the upper blocks each
@@ -190,6 +192,7 @@ struct ProbDev {
   double *part_rz[2];             // [n_pcg_tiles]
   double *part_pq;                // [n_pcg_tiles]
   double *part_cg[2];             // [3][n_pcg_tiles] r.u, w.u, r.r partials by parity
+  uint32_t *cg_flag;              // [n_pcg_tiles] resident PCG: iterations each tile has finished
   double *part_rr;                // [n_pcg_tiles]
   int32_t *part_cull;             // [n_pt_tiles][2] active observations, points with one, after culling
   LMState *st;
@@ -245,6 +248,9 @@ size_t device_lds_limit();
 // Whether the PCG runs in its one-reduction form (one launch per iteration) for
 // a plan whose longest tile column list is max_tcols.
 bool one_reduction_pcg(int precision, int max_tcols);
+// True when the resident PCG (one launch, grid barriers) can run a problem: every
+// tile's columns fit one sweep and all n_tiles workgroups can be resident at once.
+bool resident_pcg_fits(int precision, int rows, int n_tiles, int max_tcols);
 // Parts of one LM iteration: everything, or the launches before the PCG run, the
 // PCG run itself, and the launches after it (so the run can be timed between graphs).
 enum LmPart { LM_ALL = 0, LM_BEFORE_PCG, LM_PCG, LM_AFTER_PCG };

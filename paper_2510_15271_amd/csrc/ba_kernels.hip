@@ -1665,6 +1665,7 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   LMState *st = pd.st;
   __shared__ int s_flag[1];
   __shared__ double s_red[12];
+  if (threadIdx.x == 0) pd.cg_flag[tl.idx] = 0u;  // the resident PCG's barrier flags
   if (threadIdx.x == 0) s_flag[0] = lm_active(st) ? 1 : 0;
   __syncthreads();
   if (!s_flag[0]) return;
@@ -2041,6 +2042,318 @@ __global__ __launch_bounds__(1024) void k_cg_step1(const ProbDev pd, int it) {
   cg_step_body<T, RC>(pd, blockIdx.x, it);
 }
 
+// Loads and stores of the values tiles of the resident PCG hand each other within one
+// launch (partial sums; w, s and r of a tile's own rows): agent-coherent accesses,
+// served at the device's coherence point rather than from an XCD's L2, since the L2s
+// of the eight XCDs are not coherent with each other.
+template <class V>
+__device__ inline V ld_shared(const V *p) {
+  return __hip_atomic_load(const_cast<V *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class V>
+__device__ inline void st_shared(V *p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier of the resident PCG.  Each wave waits until its stores have been
+// acknowledged (the shared values above are written agent-coherent, so acknowledged
+// means visible to every XCD); thread 0 then sets the tile's flag, and wave 0 polls
+// every tile's flag (one agent-coherent load per lane and 64 tiles) until all have
+// reached `stamp`.  Readers take the shared values with agent-coherent loads issued
+// after the poll, so neither an L2 write-back nor an invalidate is needed: the form
+// with a release/acquire pair per workgroup measured 9.3 us per iteration with one
+// counter and 8.3 us with per-tile flags, against 8.0 us for a launch per iteration.
+// The wait is bounded: after kBarPolls polls the workgroup reports failure, so a launch
+// whose workgroups cannot all be resident at once ends instead of waiting forever.
+constexpr int kBarPolls = 1 << 20;
+__device__ inline bool grid_barrier(uint32_t *flag, int n_tiles, int tile, uint32_t stamp, int *s_ok) {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 64) {
+    if (t == 0) st_shared(flag + tile, stamp);
+    bool all = false;
+    for (int n = 0; n < kBarPolls; ++n) {
+      bool mine = true;
+      for (int k = t; k < n_tiles; k += 64) mine = mine && ld_shared(flag + k) >= stamp;
+      all = __all(mine) != 0;
+      if (all) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (t == 0) s_ok[0] = all ? 1 : 0;
+  }
+  __syncthreads();
+  return s_ok[0] != 0;
+}
+
+// The whole one-reduction PCG of one problem in one launch, for a grid whose tiles are
+// all resident at once (checked by the host): the same iterates in the same order as
+// pcg_max launches of k_cg_step1, with a grid barrier where a launch boundary was.
+// What a launch re-read every iteration stays in registers for the whole solve: the
+// tile's S blocks (those a lane group holds; longer rows read the rest each
+// iteration), the M^-1 rows of its columns, and u, p and x of its own rows.  Per
+// iteration a tile reads only the partial sums and w, s and r of its columns, and
+// stores w, s and r of its own rows (x once at the end).  pd.cg_flag holds the
+// barrier's per-tile flags, cleared by k_cg_start.
+// Dynamic LDS of k_cg_run: u of the tile's columns, then their M^-1 rows (FP64).
+__host__ __device__ constexpr size_t cg_run_mrow_offset(int max_tcols, size_t tbytes) {
+  return (6 * (size_t)max_tcols * tbytes + 7) / 8;  // in doubles
+}
+size_t cg_run_lds_bytes(int max_tcols, size_t tbytes) {
+  return 8 * cg_run_mrow_offset(max_tcols, tbytes) + 36 * sizeof(double) * (size_t)max_tcols;
+}
+
+template <class T, int RC>
+__global__ __launch_bounds__(1024) void k_cg_run(const ProbDev pd, int n_iter) {
+  extern __shared__ double s_dyn[];
+  T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
+  // [tile columns][6][6]: M^-1 rows (in LDS rather than registers: the barrier's
+  // acquire invalidates the caches that spilled registers would be reloaded from)
+  double *ml = s_dyn + cg_run_mrow_offset(pd.max_tcols, sizeof(T));
+  __shared__ double s_red[48];
+  __shared__ T s_w[kPcgRowsMax][4][6];
+  __shared__ T s_ro[kPcgRowsMax][6], s_uo[kPcgRowsMax][6];
+  __shared__ int s_flag[2];
+  const int tile = blockIdx.x;
+  LMState *st = pd.st;
+  const int t = threadIdx.x;
+  const int nt = pd.n_pcg_tiles;
+  const int R = RC ? RC : pd.pcg_rows;
+  const int Lr = kCgThreads / R;
+  const int wpr = Lr >= 64 ? Lr / 64 : 1;
+  const int row0 = tile * R, row1 = min(pd.Cf, row0 + R);
+  const int ncmax = pd.max_tcols;  // at most kCgColThreads / 6: one sweep holds every column
+  const int32_t *tcol = pd.tcol + (size_t)tile * ncmax;
+  const T *S = (const T *)pd.S;
+  T *x = (T *)pd.x;
+  if (t == 0) s_flag[0] = (lm_active(st) && !st->pcg_done) ? 1 : 0;
+  __syncthreads();
+  if (!s_flag[0]) return;
+  n_iter = min(n_iter, st->pcg_max);
+  const double tol = st->pcg_tol, bb = st->pcg_bb;
+  // ---- per-solve constants and the own-row state
+  const int l = t / 6, m = t - 6 * (t / 6);
+  const int c = (t < kCgColThreads && l < ncmax) ? tcol[l] : -1;
+  const bool has_col = c >= 0;
+  const bool own = has_col && c >= row0 && c < row1;
+  T um = T(0), pm = T(0), xm = T(0);  // u_it, p_{it-1} (p_{-1} = 0), x_it of an own element
+  if (has_col) {  // each thread reads back only the row it wrote
+#pragma unroll
+    for (int n = 0; n < 6; ++n) ml[6 * t + n] = pd.Minv[36 * (size_t)c + 6 * m + n];
+  }
+  if (own) {
+    um = ((const T *)pd.cg_u[0])[6 * (size_t)c + m];
+    xm = x[6 * (size_t)c + m];
+  }
+  const int lrs = R == kPcgRows ? 8 : (R == kPcgRowsSparse ? 6 : 5);  // log2(Lr)
+  const int lane = t & 63, rw = t >> lrs;
+  const int h = t & (Lr - 1);
+  const int q = Lr >= 64 ? (h >> 6) : 0;
+  const int hs = Lr >= 64 ? (h & 63) : h;
+  const int gps = Lr >= 64 ? 10 : 5;
+  const int g = hs / 6, i = hs - 6 * (hs / 6);
+  const int a = row0 + rw;
+  const int bstep = gps * wpr;
+  const bool spl = g < gps && a < row1;
+  int b0 = 0, b1 = 0;
+  if (spl) {
+    b0 = pd.S_rowptr[a] + gps * q + g;
+    b1 = pd.S_rowptr[a + 1];
+  }
+  constexpr int kCgPre = sizeof(T) == 4 ? 3 : 1;  // S blocks per lane group held for the solve
+  T sreg[kCgPre][6];
+  int lreg[kCgPre];
+#pragma unroll
+  for (int k = 0; k < kCgPre; ++k) {
+    const int blk = b0 + bstep * k;
+    lreg[k] = -1;
+    if (blk < b1) {
+      lreg[k] = pd.S_lcol[blk];
+#pragma unroll
+      for (int n = 0; n < 6; ++n) sreg[k][n] = S[36 * (size_t)blk + 6 * i + n];
+    } else {
+#pragma unroll
+      for (int n = 0; n < 6; ++n) sreg[k][n] = T(0);
+    }
+  }
+  const bool first = tile == 0 && t == 0;
+  double gprev = 1.0, aprev = 1.0;  // gamma_{it-1}, alpha_{it-1}
+  bool ok = true;
+  for (int it = 0; it < n_iter; ++it) {
+    const int pr = it & 1, cu = pr ^ 1;
+    // ---- partials of iteration it and the vectors of this tile's columns
+    double pg = 0.0, pdl = 0.0, prr = 0.0;
+    {
+      const double *part = pd.part_cg[pr];
+      for (int k = t; k < nt; k += kCgThreads) {
+        pg += ld_shared(part + k);
+        pdl += ld_shared(part + nt + k);
+        prr += ld_shared(part + 2 * nt + k);
+      }
+    }
+    T cw[6], cs[6], cr[6];
+    if (has_col) {
+      const T *w0 = (const T *)pd.cg_w[pr];
+      const T *s0 = (const T *)pd.cg_s[pr];
+      const T *r0 = (const T *)pd.cg_r[pr];
+      const size_t b = 6 * (size_t)c;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) {
+        cw[n] = ld_shared(w0 + b + n);
+        cs[n] = ld_shared(s0 + b + n);
+        cr[n] = ld_shared(r0 + b + n);
+      }
+    }
+    pg = wave_sum(pg);
+    pdl = wave_sum(pdl);
+    prr = wave_sum(prr);
+    if (lane == 0) {
+      s_red[t >> 6] = pg;
+      s_red[16 + (t >> 6)] = pdl;
+      s_red[32 + (t >> 6)] = prr;
+    }
+    __syncthreads();
+    double gam = 0.0, del = 0.0, rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      gam += s_red[k];
+      del += s_red[16 + k];
+      rr += s_red[32 + k];
+    }
+    // every tile takes the same decisions from the same sums
+    if (it > 0 && sqrt(rr) <= tol * sqrt(bb)) {
+      if (first) {
+        st->pcg_done = 1;
+        st->pcg_iters = it;
+      }
+      break;
+    }
+    double beta = 0.0, den = del;
+    if (it > 0) {
+      beta = gam / gprev;
+      den = del - beta * gam / aprev;
+    }
+    if (!(den > 0.0)) {
+      if (first) {
+        st->pcg_done = 1;
+        st->pcg_iters = it + 1;
+      }
+      break;
+    }
+    const double alpha = gam / den;
+    if (first) {
+      st->cg_alpha[cu] = alpha;
+      st->cg_gamma[cu] = gam;
+    }
+    gprev = gam;
+    aprev = alpha;
+    const T ta = T(alpha), tb = T(beta);
+    // ---- columns: s_it, r_{it+1}, u_{it+1}; own rows p_it and x_{it+1}
+    T sm = T(0), rm = T(0), un = T(0), pn = T(0);
+    if (has_col) {
+      double mrow[6];
+#pragma unroll
+      for (int n = 0; n < 6; ++n) mrow[n] = ml[6 * t + n];
+      cg_column<T>(m, tb, ta, cw, cs, cr, mrow, sm, rm, un);
+      ul[6 * l + m] = un;
+      if (own) {
+        pn = um + tb * pm;
+        s_ro[c - row0][m] = rm;
+        s_uo[c - row0][m] = un;
+      }
+    }
+    __syncthreads();
+    // ---- w_{it+1} = S u_{it+1} for the tile's rows
+    T acc = T(0);
+    if (spl) {
+#pragma unroll
+      for (int k = 0; k < kCgPre; ++k)
+        if (lreg[k] >= 0) {
+          const T *uc = ul + 6 * lreg[k];
+#pragma unroll
+          for (int n = 0; n < 6; ++n) acc += sreg[k][n] * uc[n];
+        }
+      for (int blk = b0 + bstep * kCgPre; blk < b1; blk += bstep) {
+        const T *Srow = S + 36 * (size_t)blk + 6 * i;
+        const T *uc = ul + 6 * pd.S_lcol[blk];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) acc += Srow[n] * uc[n];
+      }
+    }
+    T wi = T(0);
+    if (Lr >= 64) {
+#pragma unroll
+      for (int gg = 0; gg < 10; ++gg) wi += __shfl(acc, 6 * gg + i, 64);
+    } else {
+      const int sbase = t & 32;
+#pragma unroll
+      for (int gg = 0; gg < 5; ++gg) wi += __shfl(acc, sbase + 6 * gg + i, 64);
+    }
+    if (hs < 6 && a < row1) s_w[rw][q][hs] = wi;
+    __syncthreads();
+    if (own) {
+      const size_t idx = 6 * (size_t)c + m;
+      st_shared((T *)pd.cg_s[cu] + idx, sm);
+      st_shared((T *)pd.cg_r[cu] + idx, rm);
+      pm = pn;
+      xm = xm + ta * pn;
+      um = un;
+    }
+    // ---- w_{it+1} of the tile's rows and its partials of gamma_{it+1}, delta_{it+1},
+    // ||r_{it+1}||^2 (as the per-launch step: wave 0 alone when 6 R <= 64)
+    const bool one_wave = 6 * R <= 64;
+    if (one_wave ? t < 64 : t < 256) {
+      double g2 = 0.0, d2 = 0.0, q2 = 0.0;
+      if (t < 6 * R) {
+        const int rr_ = t / 6, mm = t - 6 * (t / 6);
+        const int a2 = row0 + rr_;
+        if (a2 < row1) {
+          T w = s_w[rr_][0][mm];
+          for (int qq = 1; qq < wpr; ++qq) w += s_w[rr_][qq][mm];
+          st_shared((T *)pd.cg_w[cu] + 6 * (size_t)a2 + mm, w);
+          const double ui = (double)s_uo[rr_][mm], ri = (double)s_ro[rr_][mm];
+          g2 = ri * ui;
+          d2 = (double)w * ui;
+          q2 = ri * ri;
+        }
+      }
+      g2 = wave_sum(g2);
+      d2 = wave_sum(d2);
+      q2 = wave_sum(q2);
+      if (one_wave) {
+        if (t == 0) {
+          double *pn2 = pd.part_cg[cu];
+          st_shared(pn2 + tile, g2);
+          st_shared(pn2 + nt + tile, d2);
+          st_shared(pn2 + 2 * nt + tile, q2);
+        }
+      } else if ((t & 63) == 0) {
+        s_red[3 * (t >> 6)] = g2;
+        s_red[3 * (t >> 6) + 1] = d2;
+        s_red[3 * (t >> 6) + 2] = q2;
+      }
+    }
+    if (!one_wave) {
+      __syncthreads();
+      if (t == 0) {
+        double *pn2 = pd.part_cg[cu];
+        st_shared(pn2 + tile, s_red[0] + s_red[3] + s_red[6] + s_red[9]);
+        st_shared(pn2 + nt + tile, s_red[1] + s_red[4] + s_red[7] + s_red[10]);
+        st_shared(pn2 + 2 * nt + tile, s_red[2] + s_red[5] + s_red[8] + s_red[11]);
+      }
+    }
+    if (!grid_barrier(pd.cg_flag, nt, tile, (uint32_t)(it + 1), s_flag + 1)) {
+      ok = false;
+      break;
+    }
+  }
+  if (own) x[6 * (size_t)c + m] = xm;
+  if (!ok && t == 0) {
+    st->pcg_fault = 1;
+    st->pcg_done = 1;
+  }
+}
+
 // The step kernels of one compute type for a launch whose problems all tile their rows
 // by R (0: mixed, read per problem).
 template <class T>
@@ -2059,6 +2372,14 @@ struct CgStep {
       case kPcgRowsSparse: return (const void *)k_cg_step1<T, kPcgRowsSparse>;
       case kPcgRowsMax: return (const void *)k_cg_step1<T, kPcgRowsMax>;
       default: return (const void *)k_cg_step1<T, 0>;
+    }
+  }
+  static const void *resident(int R) {
+    switch (R) {
+      case kPcgRows: return (const void *)k_cg_run<T, kPcgRows>;
+      case kPcgRowsSparse: return (const void *)k_cg_run<T, kPcgRowsSparse>;
+      case kPcgRowsMax: return (const void *)k_cg_run<T, kPcgRowsMax>;
+      default: return (const void *)k_cg_run<T, 0>;
     }
   }
 };
@@ -2268,7 +2589,8 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   pd.iter_pcg[n] = st->pcg_done ? st->pcg_iters : st->pcg_max;
   // a step that puts more observations behind their cameras is rejected
   const bool more_masked = (int32_t)mt > st->n_masked;
-  if (isfinite(tc) && dL > 0.0 && rho > kAcceptRho && !more_masked) {
+  const bool fault = st->pcg_fault != 0;  // the step is not a PCG result: reject it and stop
+  if (!fault && isfinite(tc) && dL > 0.0 && rho > kAcceptRho && !more_masked) {
     st->cost = tc;
     st->n_masked = (int32_t)mt;
     st->cur = 1 - st->cur;
@@ -2287,9 +2609,10 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   pd.iter_cost[n + 1] = st->cost;
   st->pcg_done = 0;
   st->pcg_iters = 0;
-  st->iter = n + 1;
+  st->iter = fault ? st->max_iters : n + 1;
   if (st->iter >= st->max_iters) {
-    if (!isfinite(st->cost)) st->status = 2;
+    if (fault) st->status = 3;
+    else if (!isfinite(st->cost)) st->status = 2;
     else if (lam >= kLambdaMax) st->status = 1;
     else st->status = 0;
   }
@@ -2966,7 +3289,7 @@ int prepare_kernels() {
     bool ok = true;
     for (int R : {0, kPcgRows, kPcgRowsSparse, kPcgRowsMax})
       for (const void *f : {CgStep<float>::multi(R), CgStep<double>::multi(R), CgStep<float>::single(R),
-                            CgStep<double>::single(R)})
+                            CgStep<double>::single(R), CgStep<float>::resident(R), CgStep<double>::resident(R)})
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)use) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
@@ -3000,6 +3323,22 @@ size_t device_lds_limit() {
 
 bool one_reduction_pcg(int precision, int max_tcols) {
   return 6 * (size_t)max_tcols * (precision == 0 ? 8 : 4) <= g_fused_lds;
+}
+
+bool resident_pcg_fits(int precision, int rows, int n_tiles, int max_tcols) {
+  if (prepare_kernels() != 0 || !one_reduction_pcg(precision, max_tcols)) return false;
+  if (6 * max_tcols > kCgColThreads || n_tiles < 1) return false;
+  const void *f = precision == 0 ? CgStep<double>::resident(rows) : CgStep<float>::resident(rows);
+  const size_t lds = cg_run_lds_bytes(max_tcols, precision == 0 ? 8 : 4);
+  if (lds > g_fused_lds) return false;
+  int dev = 0, n_cu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kCgThreads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (int64_t)n_tiles <= (int64_t)n_cu * per_cu;
 }
 
 template <class T, class S>
@@ -3060,9 +3399,14 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   if (pcg && bp.n_pcg && one_reduction) {
     // one event pair around the whole run: per-launch events would add their own
     // overhead to launches this short
-    Timed t(tm, K_PCG_CG, s, pcg_max);
+    const bool resident = bp.n_probs == 1 && bp.single.pcg_resident;
+    Timed t(tm, K_PCG_CG, s, resident ? 1 : pcg_max);
     hipError_t le = hipSuccess;
-    if (bp.n_probs == 1) {
+    if (resident) {
+      const void *f = CgStep<T>::resident(bp.pcg_rows);
+      void *args[] = {(void *)&bp.single, (void *)&pcg_max};
+      le = hipLaunchKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, cg_run_lds_bytes(max_tcols, sizeof(T)), s);
+    } else if (bp.n_probs == 1) {
       const void *f = CgStep<T>::single(bp.pcg_rows);
       for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {
         void *args[] = {(void *)&bp.single, (void *)&it};

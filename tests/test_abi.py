@@ -72,7 +72,7 @@ def test_create_rejects_duplicates_empty_and_all_fixed(balib):
 def test_options_validation(balib):
     s = make_arc_scene(3, 20, seed=1)
     for kw in [dict(max_iters=0), dict(pcg_max_iters=0), dict(lambda0=0.0),
-               dict(pcg_rel_tol=-1.0), dict(precision=7), dict(huber_delta=np.inf), dict(flags=5), dict(flags=16),
+               dict(pcg_rel_tol=-1.0), dict(precision=7), dict(huber_delta=np.inf), dict(flags=5), dict(flags=32),
                dict(prior_abs=-1.0), dict(prior_seq=np.nan), dict(prior_seq=1.0, prior_seq_k=0),
                dict(prior_seq=1.0, prior_seq_k=65)]:
         _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(balib.scene_desc(s), balib.options(**kw)))

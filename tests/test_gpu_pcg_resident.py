@@ -1,0 +1,98 @@
+"""The resident PCG (BA_FLAG_PCG_RESIDENT: every iteration of a linear solve in one
+launch, workgroups meeting at a grid barrier) against the launch-per-iteration PCG
+and the FP64 oracle, through the C-ABI.  Needs an MI355X."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ba_oracle as O
+from synth import make_config1, make_pose_graph, make_small_drive
+
+pytestmark = pytest.mark.gpu
+
+RESIDENT = 16  # BA_FLAG_PCG_RESIDENT
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run(balib, scene, flags, **kw):
+    _say("device solve:", scene.name, scene.n_cams, scene.n_pts, scene.n_obs, "flags", flags, kw)
+    p = balib.Problem.from_scene(scene, flags=flags, **kw)
+    info = p.info()
+    res = p.solve().result()
+    p.close()
+    return info, res
+
+
+def _same(a, b):
+    assert np.array_equal(a["iter_cost"], b["iter_cost"])
+    assert list(a["pcg_iters"]) == list(b["pcg_iters"])
+    assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["t"], b["t"])
+    assert np.array_equal(a["X"], b["X"])
+    assert a["status"] == b["status"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("extra", [0, 2, 8])
+def test_small_drive_resident_equals_per_launch(balib, prec, extra):
+    """40-camera drive (10 tiles of 4 rows, the last ragged; with BA_FLAG_PCG_WIDE one
+    full and one ragged 32-row tile; with BA_FLAG_NO_GRAPH launched without a graph):
+    the resident solve repeats the per-launch solve bit for bit, and in FP64 every C_n
+    is within 1e-9 of the explicit-Schur oracle solved exactly."""
+    s = make_small_drive(40, 3000, seed=5)
+    kw = dict(max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision=prec)
+    ia, a = _run(balib, s, extra, **kw)
+    ib, b = _run(balib, s, extra | RESIDENT, **kw)
+    _say("info", ia["pcg_rows"], ia["pcg_resident"], ib["pcg_rows"], ib["pcg_resident"], "pcg", b["pcg_iters"])
+    assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == 1
+    assert ib["pcg_rows"] == (32 if extra == 8 else 4)
+    _same(a, b)
+    if prec == "f64":
+        ref = O.lm_schur(O.Problem.from_scene(s), O.LMOptions(max_iters=8, solve="exact"))
+        rel = np.abs(b["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+        _say("max rel cost diff vs oracle", rel.max())
+        assert rel.max() <= 1e-9
+
+
+def test_small_drive_resident_early_stop_and_cap(balib):
+    """A loose tolerance (the solve stops after a few iterations) and a cap of 3
+    iterations: the resident solve stops where the per-launch one does."""
+    s = make_small_drive(30, 2000, seed=21)
+    for kw in (dict(pcg_rel_tol=1e-2, pcg_max_iters=50), dict(pcg_rel_tol=1e-12, pcg_max_iters=3)):
+        _, a = _run(balib, s, 0, max_iters=5, precision="f32", **kw)
+        _, b = _run(balib, s, RESIDENT, max_iters=5, precision="f32", **kw)
+        _say(kw, "pcg", a["pcg_iters"], b["pcg_iters"])
+        _same(a, b)
+
+
+def test_full_size_drive_resident_equals_per_launch(balib):
+    """The 2M-observation drive in the benchmark's configuration (FP32, 10 LM
+    iterations, PCG 50 / 1e-6): 125 resident workgroups, the same run bit for bit as
+    the launch-per-iteration PCG, and a cost that falls below half its start."""
+    s = make_config1()
+    ia, a = _run(balib, s, 0, max_iters=10, precision="f32")
+    ib, b = _run(balib, s, RESIDENT, max_iters=10, precision="f32")
+    _say("info", ib["pcg_rows"], ib["pcg_resident"], "rms", a["rms_px"], b["rms_px"], "pcg", b["pcg_iters"])
+    assert ib["pcg_resident"] == 1
+    _same(a, b)
+    assert b["cost"] < 0.5 * b["cost0"]
+
+
+def test_pose_graph_too_many_tiles_falls_back(balib):
+    """The 1500-frame rig pose graph has more 32-row tiles (282) than the device holds
+    1024-thread workgroups at once: the flag is ignored and the solve is the
+    per-launch one."""
+    g = make_pose_graph(1500)
+    out = []
+    for flags in (0, RESIDENT):
+        p = balib.Problem.from_pose_graph(g, max_iters=5, precision="f32", flags=flags)
+        info = p.info()
+        out.append((info, p.solve().result()))
+        p.close()
+    _say("tiles of", out[1][0]["pcg_rows"], "rows; resident", out[1][0]["pcg_resident"])
+    assert out[1][0]["pcg_resident"] == 0
+    assert np.array_equal(out[0][1]["iter_cost"], out[1][1]["iter_cost"])
