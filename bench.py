@@ -325,8 +325,9 @@ def main():
                     help="skip the pose-graph leg (9000 nodes, 24.7k edges)")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the iterative-refinement leg (outlier drive, two stages)")
-    ap.add_argument("--pcg-resident", action="store_true",
-                    help="run each linear solve as one launch with grid barriers (BA_FLAG_PCG_RESIDENT)")
+    ap.add_argument("--per-launch-pcg", action="store_true",
+                    help="one launch per PCG iteration instead of one resident launch per linear "
+                         "solve (BA_FLAG_PCG_RESIDENT, the default for this lone solve)")
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel device times of one extra solve to stderr")
     args = ap.parse_args()
@@ -360,7 +361,7 @@ def main():
     prob = ba.Problem.from_scene(scene, max_iters=LM_ITERS, pcg_max_iters=50, pcg_rel_tol=1e-6,
                                  precision=args.precision,
                                  flags=(ba.FLAG_NO_GRAPH if args.no_graph else 0) |
-                                       (ba.FLAG_PCG_RESIDENT if args.pcg_resident else 0),
+                                       (0 if args.per_launch_pcg else ba.FLAG_PCG_RESIDENT),
                                  prior_abs=args.prior_abs, prior_seq=args.prior_seq,
                                  prior_seq_k=args.prior_seq_k)
     info = prob.info()
@@ -386,7 +387,7 @@ def main():
     stride = 1 if dominant == "pcg_cg" else (10 if kt[dominant][1] >= 100 else 1)
     prob.set_profiling(0 if args.no_kernel_timing else 1 << names.index(dominant), stride)
     dev_ms = []
-    dom_ms, dom_launch = 0.0, 0
+    dom_ms, dom_launch, pcg_iters = 0.0, 0, 0
     print(f"bench: timing {args.steps} steps", flush=True, file=sys.stderr)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -398,6 +399,7 @@ def main():
               f"{ms:.3f} ms over {nl} launches", flush=True, file=sys.stderr)
         dom_ms += ms
         dom_launch += nl
+        pcg_iters += int(sum(r["pcg_iters"]))
     wall = time.perf_counter() - t0
     prob.set_profiling(0)
 
@@ -405,9 +407,17 @@ def main():
     lm_per_s = LM_ITERS * args.steps / wall
     avg_launch_s = dom_ms / 1000.0 / max(dom_launch, 1)
     abytes = algorithmic_bytes(dominant, info, args.precision)
+    resident = dominant == "pcg_cg" and bool(info["pcg_resident"])
+    iters_per_launch = None
+    if resident:
+        # one launch runs a whole linear solve: its algorithmic bytes are those of one PCG
+        # iteration (S read once, the vectors once) times the iterations it ran
+        iters_per_launch = pcg_iters / max(dom_launch, 1)
+        abytes = abytes * iters_per_launch
     achieved = abytes / avg_launch_s / 1e9 if abytes else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}_{args.precision}.json")
+    tname = f"{dominant}_resident" if resident else dominant
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{tname}_{args.workload}_{args.precision}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             traffic = json.load(f).get("bytes_per_launch")
@@ -416,7 +426,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "algorithmic_bytes": abytes}
+                "algorithmic_bytes": round(abytes)}
+    if resident:
+        roofline["pcg_iterations_per_launch"] = round(iters_per_launch, 2)
+        roofline["avg_pcg_iteration_us"] = round(avg_launch_s * 1e6 / iters_per_launch, 3)
     out = {
         "metric": METRIC,
         "value": round(lm_per_s, 2),
@@ -440,7 +453,9 @@ def main():
                    "schur_form": "point chunks" if info["schur_form"] else "pair lists",
                    "pose_priors": ({"abs": args.prior_abs, "seq": args.prior_seq, "seq_k": args.prior_seq_k}
                                    if args.prior_abs > 0 or args.prior_seq > 0 else None),
-                   "graph": not args.no_graph},
+                   "graph": not args.no_graph,
+                   "pcg": "resident (one launch per linear solve)" if info["pcg_resident"]
+                          else "one launch per iteration"},
         "obs_per_s": round(info["n_obs"] * lm_per_s, 1),
         "device_ms_per_step": round(sum(dev_ms) / len(dev_ms), 3),
         "final_rms_px": r["rms_px"],
@@ -450,7 +465,8 @@ def main():
     prob.close()
     if not args.no_refine and args.workload == "drive":
         out["refine"] = refine_leg(ba, args.precision, args.points or 250_000,
-                                   ba.FLAG_NO_GRAPH if args.no_graph else 0)
+                                   (ba.FLAG_NO_GRAPH if args.no_graph else 0) |
+                                   (0 if args.per_launch_pcg else ba.FLAG_PCG_RESIDENT))
     if not args.no_rig and args.workload == "drive":
         out["rig"] = rig_leg(ba, args.precision, ba.FLAG_NO_GRAPH if args.no_graph else 0)
     if not args.no_pose_graph and args.workload == "drive":

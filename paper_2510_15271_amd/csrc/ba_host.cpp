@@ -1688,7 +1688,7 @@ int ba_solve_async(ba_problem *p) {
     (void)hipEventRecord(p->ev0, p->stream);
     for (int it = 0; it < p->dp.max_iters && e == hipSuccess; ++it) {
       e = hipGraphLaunch(p->seg_exec[0], p->stream);
-      p->timer.begin(K_PCG_CG, p->stream, p->dp.pcg_max);
+      p->timer.begin(K_PCG_CG, p->stream, p->sy.pcg_resident ? 1 : p->dp.pcg_max);
       if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[1], p->stream);
       p->timer.end(K_PCG_CG, p->stream);
       if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[2], p->stream);
