@@ -785,7 +785,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.Nf = sy.Nf;
   pd.chunked = sy.chunked ? 1 : 0;
   pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
-  pd.n_red_tiles = sy.chunked ? (int32_t)(((int64_t)sy.n_up * 36 + 63) / 64) : 0;
+  pd.n_red_tiles = sy.chunked ? (sy.n_up + 3) / 4 : 0;  // four upper blocks (one wave each) per tile
   pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
   pd.n_fsh_tiles = sy.chunked ? (Cf + 63) / 64 : 0;
   pd.n_up = sy.n_up;

@@ -83,7 +83,7 @@ struct ProbDev {
   int32_t pcg_resident;  // 1: the whole PCG runs in one launch with grid barriers (k_cg_run)
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
-  int32_t n_red_tiles;   // reduction tiles (chunk form): 64 elements of the upper blocks each
+  int32_t n_red_tiles;   // reduction tiles (chunk form): four upper blocks each
   int32_t n_fin_tiles;   // camera-row tiles (chunk form): one camera each
   int32_t n_fsh_tiles;   // camera-finish tiles (chunk form): 64 cameras each
   // static structure

@@ -28,6 +28,7 @@
 // fixed summation order, so a problem's result is the same whichever other
 // problems share its launches.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cstdint>
@@ -1327,10 +1328,12 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   }
 }
 
-// Upper blocks: 64 (block, element) pairs per tile, each summed by four waves
-// over four consecutive segments of the block's chunk partials (contiguous rows
-// of 36, chunk order) in FP64; the four segment sums are added in order and the
-// element is written as S_ab = -sum and into S_ba, its transpose.
+// Upper blocks, one wave each (four per workgroup).  The block's chunk partials are
+// contiguous rows of 36 T in chunk order; each lane loads 16 bytes (V elements) of a
+// row, so one wave instruction reads RW whole rows (7 in FP32, 3 in FP64) contiguously.
+// Lane (row slot r, quad q) sums rows r, r + RW, r + 2 RW, ... in FP64 in that order; the
+// RW slot sums are then added in slot order, and the element is written as S_ab = -sum
+// and into S_ba, its transpose.
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict__ probs,
                                                       const Tile *__restrict__ tiles) {
@@ -1338,33 +1341,51 @@ __global__ __launch_bounds__(256) void k_schur_reduce(const ProbDev *__restrict_
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
-  __shared__ double s_seg[4][64];
-  const int el = threadIdx.x & 63, seg = threadIdx.x >> 6;
-  const int g = 64 * tl.idx + el;
-  const int u = g / 36, e = g - 36 * (g / 36);
-  const bool live = u < pd.n_up;
-  double t = 0.0;
-  if (live) {
-    const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
-    const int q = (n + 3) / 4, x0 = seg * q, x1 = min(n, x0 + q);
-    const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent) + e;
-    for (int x = x0; x < x1; x += 16) {  // sixteen partials in flight, summed in order
-      T v[16];
+  constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte load
+  constexpr int Q = 36 / V;               // loads per row
+  constexpr int RW = 64 / Q;              // rows per wave instruction
+  using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const int lane = threadIdx.x & 63;
+  const int u = 4 * tl.idx + (threadIdx.x >> 6);
+  if (u >= pd.n_up) return;  // whole waves: no workgroup barrier follows
+  const int r = lane / Q, q = lane - Q * (lane / Q);
+  const bool act = r < RW;
+  const int b0 = pd.blk_start[pd.Cf + u], n = pd.blk_start[pd.Cf + u + 1] - b0;
+  const T *part = (const T *)pd.part_o + 36 * (size_t)(b0 - pd.n_dent) + V * q;
+  double acc[V];
 #pragma unroll
-      for (int h = 0; h < 16; ++h) v[h] = x + h < x1 ? part[36 * (size_t)(x + h)] : T(0);
+  for (int k = 0; k < V; ++k) acc[k] = 0.0;
+  for (int x0 = r; x0 < n; x0 += 4 * RW) {  // four rows per lane in flight, summed in order
+    Vec v[4];
 #pragma unroll
-      for (int h = 0; h < 16; ++h) t += (double)v[h];
+    for (int h = 0; h < 4; ++h) {
+      const int x = x0 + h * RW;
+      v[h] = (act && x < n) ? *(const Vec *)(part + 36 * (size_t)x) : Vec{};
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const T *e = (const T *)&v[h];
+#pragma unroll
+      for (int k = 0; k < V; ++k) acc[k] += (double)e[k];
     }
   }
-  s_seg[seg][el] = t;
-  __syncthreads();
-  if (seg == 0 && live) {
-    const double tot = s_seg[0][el] + s_seg[1][el] + s_seg[2][el] + s_seg[3][el];
-    const int r = e / 6, cc = e - 6 * (e / 6);
-    const T v = T(-tot);
+  double tot[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    tot[k] = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) tot[k] += __shfl(acc[k], rr * Q + q, 64);
+  }
+  if (lane < Q) {
     T *Sv = (T *)pd.S;
-    Sv[36 * (size_t)pd.up_pos[u] + e] = v;
-    Sv[36 * (size_t)pd.up_tpos[u] + 6 * cc + r] = v;
+    const size_t pu = 36 * (size_t)pd.up_pos[u], pt = 36 * (size_t)pd.up_tpos[u];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int e = V * q + k, rr = e / 6, cc = e - 6 * (e / 6);
+      const T val = T(-tot[k]);
+      Sv[pu + e] = val;
+      Sv[pt + 6 * cc + rr] = val;
+    }
   }
 }
 
