@@ -219,3 +219,56 @@ def test_triangulate_validation(balib):
     d.obs["pt"][0] = s.n_pts
     rc, msg = call()
     assert rc == balib.BA_EINVAL and "out of range" in msg
+
+
+# The binding's ctypes structs and numpy record dtypes, with the C struct each mirrors.
+_MIRRORS = [("Intrinsics", "ba_intrinsics"), ("Pose", "ba_pose"), ("Options", "ba_options"),
+            ("Report", "ba_report"), ("ProblemDesc", "ba_problem_desc"),
+            ("PoseRequest", "ba_pose_request"), ("ProblemInfo", "ba_problem_info"),
+            ("PoseEdge", "ba_pose_edge"), ("PoseGraphDesc", "ba_pose_graph_desc"),
+            ("RigDesc", "ba_rig_desc"), ("RefineStage", "ba_refine_stage"),
+            ("RefineRound", "ba_refine_round"), ("ServerStats", "ba_server_stats_t")]
+_DTYPES = [("OBS_DTYPE", "ba_obs"), ("RIG_OBS_DTYPE", "ba_rig_obs"), ("EDGE_DTYPE", "ba_pose_edge")]
+_DTYPE_FIELDS = {"q": "meas.qw", "t": "meas.tx"}  # EDGE_DTYPE flattens the measured pose
+
+
+def test_binding_layouts_and_constants_match_header(balib, tmp_path):
+    """Every struct the binding mirrors has the C compiler's size and field offsets
+    (a C program built against include/ba.h with gcc prints them), and the binding's
+    flag and method constants equal the header's #defines."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines, expect = [], []
+    for py, c in _MIRRORS:
+        S = getattr(balib, py)
+        lines.append(f'printf("%zu\\n", sizeof({c}));')
+        expect.append(ctypes.sizeof(S))
+        for name, _ in S._fields_:
+            cname = "lambda" if name == "lambda_" else name
+            lines.append(f'printf("%zu\\n", offsetof({c}, {cname}));')
+            expect.append(getattr(S, name).offset)
+    for py, c in _DTYPES:
+        dt = getattr(balib, py)
+        lines.append(f'printf("%zu\\n", sizeof({c}));')
+        expect.append(dt.itemsize)
+        for name in dt.names:
+            lines.append(f'printf("%zu\\n", offsetof({c}, {_DTYPE_FIELDS.get(name, name)}));')
+            expect.append(dt.fields[name][1])
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "ba.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == expect
+    hdr = open(os.path.join(ROOT, "include", "ba.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define (BA_[A-Z0-9_]+) \(?(-?\d+)\)?", hdr)}
+    for name in ("NO_GRAPH", "PAIR_LISTS", "PCG_WIDE", "PCG_RESIDENT"):
+        assert getattr(balib, "FLAG_" + name) == defs["BA_FLAG_" + name], name
+    assert balib.TRI == {"midpoint": defs["BA_TRI_MIDPOINT"], "dlt": defs["BA_TRI_DLT"]}
+    assert balib.PREC == {"f64": defs["BA_PREC_F64"], "f32": defs["BA_PREC_F32"],
+                          "f16j": defs["BA_PREC_F16J"], "bf16j": defs["BA_PREC_BF16J"]}
