@@ -2083,7 +2083,8 @@ __device__ inline void st_shared(V *p, V v) {
 // reached `stamp`.  Readers take the shared values with agent-coherent loads issued
 // after the poll, so neither an L2 write-back nor an invalidate is needed: the form
 // with a release/acquire pair per workgroup measured 9.3 us per iteration with one
-// counter and 8.3 us with per-tile flags, against 8.0 us for a launch per iteration.
+// counter and 8.3 us with per-tile flags, this form 7.2 us, and a launch per iteration
+// 8.0 us (2M-observation drive).
 // The wait is bounded: after kBarPolls polls the workgroup reports failure, so a launch
 // whose workgroups cannot all be resident at once ends instead of waiting forever.
 constexpr int kBarPolls = 1 << 20;
@@ -2110,12 +2111,13 @@ __device__ inline bool grid_barrier(uint32_t *flag, int n_tiles, int tile, uint3
 // The whole one-reduction PCG of one problem in one launch, for a grid whose tiles are
 // all resident at once (checked by the host): the same iterates in the same order as
 // pcg_max launches of k_cg_step1, with a grid barrier where a launch boundary was.
-// What a launch re-read every iteration stays in registers for the whole solve: the
-// tile's S blocks (those a lane group holds; longer rows read the rest each
-// iteration), the M^-1 rows of its columns, and u, p and x of its own rows.  Per
-// iteration a tile reads only the partial sums and w, s and r of its columns, and
-// stores w, s and r of its own rows (x once at the end).  pd.cg_flag holds the
-// barrier's per-tile flags, cleared by k_cg_start.
+// What a launch re-read every iteration stays on chip for the whole solve: the tile's
+// S blocks in registers (those a lane group holds; longer rows read the rest each
+// iteration), the M^-1 rows of its columns in LDS, and u, p and x of its own rows in
+// registers.  Per iteration a tile reads only the partial sums and w, s and r of its
+// columns, and stores w, s and r of its own rows (x once at the end).  pd.cg_flag
+// holds the barrier's per-tile flags, cleared by k_cg_start.
+
 // Dynamic LDS of k_cg_run: u of the tile's columns, then their M^-1 rows (FP64).
 __host__ __device__ constexpr size_t cg_run_mrow_offset(int max_tcols, size_t tbytes) {
   return (6 * (size_t)max_tcols * tbytes + 7) / 8;  // in doubles
@@ -2128,8 +2130,7 @@ template <class T, int RC>
 __global__ __launch_bounds__(1024) void k_cg_run(const ProbDev pd, int n_iter) {
   extern __shared__ double s_dyn[];
   T *ul = (T *)s_dyn;  // [tile columns][6]: u_{it+1} of every column this tile reads
-  // [tile columns][6][6]: M^-1 rows (in LDS rather than registers: the barrier's
-  // acquire invalidates the caches that spilled registers would be reloaded from)
+  // [tile columns][6][6]: M^-1 rows (in LDS: the S blocks fill the registers)
   double *ml = s_dyn + cg_run_mrow_offset(pd.max_tcols, sizeof(T));
   __shared__ double s_red[48];
   __shared__ T s_w[kPcgRowsMax][4][6];
