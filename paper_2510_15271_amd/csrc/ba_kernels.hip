@@ -212,22 +212,6 @@ __device__ inline double block_sum_array(const double *a, int n, double *scratch
   return block_sum256(v, scratch4);
 }
 
-// Sums of N values per thread over a 256-thread block: each value in the same fixed
-// order as block_sum256, with one barrier for all N.  Results in every thread.
-template <int N>
-__device__ inline void block_sum256_n(double (&v)[N], double *scratch) {  // scratch: 4 N
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const double s = wave_sum(v[k]);
-    if (lane == 0) scratch[4 * k + w] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = scratch[4 * k] + scratch[4 * k + 1] + scratch[4 * k + 2] + scratch[4 * k + 3];
-  __syncthreads();
-}
-
 // Sums of three double arrays of length n in one pass (fixed order; a NULL
 // array sums to 0).  Result in every thread.
 __device__ inline void block_sum3(const double *a, const double *b, const double *c, int n,
@@ -1707,16 +1691,11 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   __syncthreads();
   if (!s_flag[0]) return;
   // tile 0 alone sums ||b||^2 over the cameras and sets the flags the first step
-  // reads; with b = 0 every other tile's products are zero and harmless
-  if (tl.idx == 0) {
-    const double bb = block_sum_array(pd.part_bb, pd.Cf, s_red);
-    if (threadIdx.x == 0) {
-      st->pcg_bb = bb;
-      st->pcg_done = (bb > 0.0) ? 0 : 1;
-      st->pcg_iters = 0;
-    }
-    if (!(bb > 0.0)) return;
-  }
+  // reads (its loads issued here, reduced after its rows); with b = 0 every tile's
+  // products are zero and harmless
+  double vbb = 0.0;
+  if (tl.idx == 0)
+    for (int i = threadIdx.x; i < pd.Cf; i += 256) vbb += pd.part_bb[i];
   const T *u = (const T *)pd.cg_u[0];
   const T *r = (const T *)pd.cg_r[0];
   T *w = (T *)pd.cg_w[0];
@@ -1754,6 +1733,15 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
     }
   }
   cg_partials(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
+  if (tl.idx == 0) {
+    __shared__ double s_bb[4];  // not s_red: thread 0 may still be reading the partials there
+    const double bb = block_sum256(vbb, s_bb);  // the order block_sum_array uses
+    if (threadIdx.x == 0) {
+      st->pcg_bb = bb;
+      st->pcg_done = (bb > 0.0) ? 0 : 1;
+      st->pcg_iters = 0;
+    }
+  }
 }
 
 // One PCG iteration per launch, 1024 threads per tile of pd.pcg_rows rows.  A
@@ -2592,25 +2580,22 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   LMState *st = pd.st;
   if (!lm_active(st)) return;
   __shared__ double s_red[4];
-  __shared__ double s_red6[24];
-  // the tile partials, every array's loads issued before one reduction of all six
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // lin cost, trial cost, dL cam, dL pt, masked, trial masked
-  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
-    v[0] += pd.part_lin_cost[i];
-    v[1] += pd.part_trial_cost[i];
-    v[3] += pd.part_dl_pt[i];
-    v[4] += (double)pd.part_masked[i];
-    v[5] += (double)pd.part_trial_masked[i];
-  }
-  for (int i = threadIdx.x; i < pd.n_cam_tiles; i += 256) v[2] += pd.part_dl_cam[i];
-  block_sum256_n<6>(v, s_red6);
-  double c0 = v[0], tc = v[1];
+  double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
+  double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
   if (pd.prior_on || pd.rig_mode == 1) {  // the prior terms at the current (first call only) and trial poses
     double *const *P = pd.rig_mode == 1 ? pd.rig_pose : pd.pose;
     if (!st->init_done) c0 += prior_cost(pd, P[st->cur], s_red);
     tc += prior_cost(pd, P[1 - st->cur], s_red);
   }
-  const double dlc = v[2], dlp = v[3], m0 = v[4], mt = v[5];
+  const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
+  const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
+  double m0 = 0.0, mt = 0.0;
+  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
+    m0 += (double)pd.part_masked[i];
+    mt += (double)pd.part_trial_masked[i];
+  }
+  m0 = block_sum256(m0, s_red);
+  mt = block_sum256(mt, s_red);
   if (threadIdx.x != 0) return;
   const int n = st->iter;
   if (!st->init_done) {
