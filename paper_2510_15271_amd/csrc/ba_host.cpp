@@ -699,6 +699,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.cam_pp = L.take(sy.cam_pp.size() * 4 + 4);
   const bool prior_on = sy.prior_abs > 0.0 || !sy.pp_cam.empty();
   o.prior_diag = L.take(prior_on ? Cf * 27 * 8 : 16);
+  o.part_prior = L.take(prior_on ? 2 * ((std::max(Cf, sy.pp_cam.size()) + 255) / 256) * 8 : 16);
   o.prior_off = L.take(sy.pp_cam.size() * 36 * 8 + 16);
   o.up_pos = L.take(sy.n_up * 4 + 4);
   o.up_tpos = L.take(sy.n_up * 4 + 4);
@@ -829,6 +830,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.prior_abs_from = 0;
   pd.prior_nodes = C;
   pd.n_pri_tiles = pd.prior_on ? (std::max(Cf, pd.n_pp) + 255) / 256 : 0;
+  pd.part_prior = (double *)ptr(off.part_prior);
   pd.pose0 = (const double *)ptr(off.pose_init);
   pd.pp_cam = (const int2 *)ptr(off.pp_cam);
   pd.pp_meas = (const double *)ptr(off.pp_meas);

@@ -139,6 +139,7 @@ struct ProbDev {
   // off-diagonal blocks J_i^T W J_j oriented as the upper block of S
   double prior_abs;
   int32_t prior_on, n_pp, n_pri_tiles, pad1;
+  double *part_prior;             // [2][n_pri_tiles] prior cost at the current and trial poses
   const double *pose0;            // [C][12] the initial poses (prior anchors)
   const int2 *pp_cam;             // [n_pp] (i, j), caller's camera indices, i != j
   const double *pp_meas;          // [n_pp][12] measured A_ij, R row-major then t
@@ -232,7 +233,7 @@ enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
   K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_CULL, K_RIG_BLOCKS,
-  K_RIG_ROWS, K_RIG_UPDATE, K_NUM_KERNELS
+  K_RIG_ROWS, K_RIG_UPDATE, K_PRIOR_COST, K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 

@@ -41,7 +41,7 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
     "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull", "rig_blocks",
-    "rig_rows", "rig_update"};
+    "rig_rows", "rig_update", "prior_cost"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -645,28 +645,63 @@ __device__ inline void rel_pose(const double *Ti, const double *Tj, double A[12]
 
 // 1/2 (lambda_a sum_i e_a + sum_pairs (w_rot |dR|^2 + w_trans |dt|^2)) at the poses P;
 // the block's threads split the terms and sum them in a fixed order.
+__device__ inline double prior_abs_term(const ProbDev &pd, const double *P, int i) {
+  double e = 0.0;
+  for (int q = 0; q < 12; ++q) {
+    const double d = P[12 * i + q] - pd.pose0[12 * i + q];
+    e += d * d;
+  }
+  return 0.5 * pd.prior_abs * e;
+}
+__device__ inline double prior_pair_term(const ProbDev &pd, const double *P, int p) {
+  const int2 ij = pd.pp_cam[p];
+  const double *M = pd.pp_meas + 12 * (size_t)p;
+  double A[12];
+  rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
+  double er = 0.0, et = 0.0;
+  for (int q = 0; q < 9; ++q) er += (A[q] - M[q]) * (A[q] - M[q]);
+  for (int q = 9; q < 12; ++q) et += (A[q] - M[q]) * (A[q] - M[q]);
+  return 0.5 * (pd.pp_w[2 * p] * er + pd.pp_w[2 * p + 1] * et);
+}
 __device__ inline double prior_cost(const ProbDev &pd, const double *P, double *s_red) {
   double c = 0.0;
   if (pd.prior_abs > 0.0)
-    for (int i = pd.prior_abs_from + (int)threadIdx.x; i < pd.prior_nodes; i += 256) {
-      double e = 0.0;
-      for (int q = 0; q < 12; ++q) {
-        const double d = P[12 * i + q] - pd.pose0[12 * i + q];
-        e += d * d;
-      }
-      c += 0.5 * pd.prior_abs * e;
-    }
-  for (int p = threadIdx.x; p < pd.n_pp; p += 256) {
-    const int2 ij = pd.pp_cam[p];
-    const double *M = pd.pp_meas + 12 * (size_t)p;
-    double A[12];
-    rel_pose(P + 12 * ij.x, P + 12 * ij.y, A);
-    double er = 0.0, et = 0.0;
-    for (int q = 0; q < 9; ++q) er += (A[q] - M[q]) * (A[q] - M[q]);
-    for (int q = 9; q < 12; ++q) et += (A[q] - M[q]) * (A[q] - M[q]);
-    c += 0.5 * (pd.pp_w[2 * p] * er + pd.pp_w[2 * p + 1] * et);
-  }
+    for (int i = pd.prior_abs_from + (int)threadIdx.x; i < pd.prior_nodes; i += 256) c += prior_abs_term(pd, P, i);
+  for (int p = threadIdx.x; p < pd.n_pp; p += 256) c += prior_pair_term(pd, P, p);
   return block_sum256(c, s_red);
+}
+
+// The prior cost of a problem in rig_mode 0, spread over its prior tiles (one block
+// each): tile q sums the terms 256 q + t, 256 q + t + 256 n, ... (n tiles) of the
+// absolute nodes and then of the pairs, each thread in that order, and the block in a
+// fixed order; at the trial poses, and at the current poses on the first call (where
+// lm_control records the initial cost).  lm_control adds the tiles' sums in order.
+__global__ __launch_bounds__(256) void k_prior_cost(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st) || pd.rig_mode != 0) return;
+  __shared__ double s_red[4];
+  const int nt = pd.n_pri_tiles, q = tl.idx, t = (int)threadIdx.x, step = 256 * nt;
+  const double *Pc = pd.pose[st->cur], *Pt = pd.pose[1 - st->cur];
+  const bool first = !st->init_done;
+  double cc = 0.0, ct = 0.0;
+  if (pd.prior_abs > 0.0)
+    for (int i = pd.prior_abs_from + 256 * q + t; i < pd.prior_nodes; i += step) {
+      if (first) cc += prior_abs_term(pd, Pc, i);
+      ct += prior_abs_term(pd, Pt, i);
+    }
+  for (int p = 256 * q + t; p < pd.n_pp; p += step) {
+    if (first) cc += prior_pair_term(pd, Pc, p);
+    ct += prior_pair_term(pd, Pt, p);
+  }
+  cc = block_sum256(cc, s_red);
+  ct = block_sum256(ct, s_red);
+  if (t == 0) {
+    pd.part_prior[q] = cc;
+    pd.part_prior[nt + q] = ct;
+  }
 }
 
 // Linearisation of the priors at the current poses: thread g < Cf forms the U (upper
@@ -2582,10 +2617,15 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   __shared__ double s_red[4];
   double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
   double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
-  if (pd.prior_on || pd.rig_mode == 1) {  // the prior terms at the current (first call only) and trial poses
-    double *const *P = pd.rig_mode == 1 ? pd.rig_pose : pd.pose;
-    if (!st->init_done) c0 += prior_cost(pd, P[st->cur], s_red);
-    tc += prior_cost(pd, P[1 - st->cur], s_red);
+  if (pd.rig_mode == 1) {  // the rig priors at the current (first call only) and trial poses
+    if (!st->init_done) c0 += prior_cost(pd, pd.rig_pose[st->cur], s_red);
+    tc += prior_cost(pd, pd.rig_pose[1 - st->cur], s_red);
+  } else if (pd.prior_on) {  // the same, summed over k_prior_cost's tiles
+    const int n = pd.n_pri_tiles;
+    const double pc = block_sum_array(pd.part_prior, n, s_red);
+    const double pt = block_sum_array(pd.part_prior + n, n, s_red);
+    if (!st->init_done) c0 += pc;
+    tc += pt;
   }
   const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
   const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
@@ -3466,6 +3506,10 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   if (bp.n_pt) {
     Timed t(tm, K_POINT_TRIAL, s);
     k_point_trial<T, S><<<bp.n_pt, kObsChunk, 0, s>>>(bp.probs, bp.pt);
+  }
+  if (bp.n_pri) {
+    Timed t(tm, K_PRIOR_COST, s);
+    k_prior_cost<<<bp.n_pri, 256, 0, s>>>(bp.probs, bp.pri);
   }
   if (bp.n_ctl) {
     Timed t(tm, K_LM_CONTROL, s);

@@ -80,7 +80,7 @@ struct Offsets {
   size_t pp_cam, pp_meas, pp_w, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
-  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], cg_flag, part_cull, iter_cost, iter_pcg;
+  size_t part_rz0, part_bb, part_rz[2], part_pq, part_rr, part_cg[2], cg_flag, part_prior, part_cull, iter_cost, iter_pcg;
   size_t total;
 };
 
