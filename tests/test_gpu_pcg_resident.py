@@ -96,3 +96,25 @@ def test_pose_graph_too_many_tiles_falls_back(balib):
     _say("tiles of", out[1][0]["pcg_rows"], "rows; resident", out[1][0]["pcg_resident"])
     assert out[1][0]["pcg_resident"] == 0
     assert np.array_equal(out[0][1]["iter_cost"], out[1][1]["iter_cost"])
+
+
+def test_refine_resident_equals_per_launch(balib):
+    """The two-stage refinement (robust Huber 1 px / 8 px culling, then strict 3 px) on
+    a 60-camera drive with 10 % outliers, FP32, with the benchmark's PCG schedule: the
+    resident PCG gives the same rounds, activity mask, poses and points bit for bit."""
+    s = make_small_drive(60, 6000, seed=62, outlier_frac=0.1, huber_delta=1.0)
+    out = []
+    for flags in (0, RESIDENT):
+        _say("device refine:", s.name, s.n_obs, "flags", flags)
+        p = balib.Problem.from_scene(s, max_iters=8, precision="f32", flags=flags)
+        info = p.info()
+        hist = p.refine([(1.0, 8.0), (0.0, 3.0)], 2)
+        out.append((info, hist, p.active().copy(), p.result()))
+        p.close()
+    (ia, ha, aa, ra), (ib, hb, ab, rb) = out
+    _say("resident", ib["pcg_resident"], "rounds", [h["n_active_obs"] for h in hb])
+    assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == 1
+    assert ha == hb
+    assert np.array_equal(aa, ab)
+    assert np.array_equal(ra["q"], rb["q"]) and np.array_equal(ra["t"], rb["t"])
+    assert np.array_equal(ra["X"], rb["X"])
