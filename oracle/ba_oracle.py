@@ -527,68 +527,88 @@ class LMResult:
     rhos: list
     pcg_iters: list
     status: int
+    nus: list = dataclasses.field(default_factory=list)   # nu after each iteration
 
 
-def _lm_loop(p: Problem, opts: LMOptions, solve_step):
-    """Levenberg-Marquardt (Madsen-Nielsen-Tingleff 2004, Alg. 3.16 with Marquardt
-    scaling).  One iteration = one (possibly reused) linearisation, one damped
-    solve, one trial cost.  Accept iff gain ratio > 1e-3 and the predicted
-    decrease is positive and the trial state masks no more observations (depth
-    <= Z_MIN) than the current one -- a step may not lower the cost by pushing
-    points behind their cameras; on accept lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
-    on reject lambda *= nu, nu *= 2; lambda clamped to [1e-12, 1e16].  The iteration
-    count is fixed (no early stop); a run that ends with lambda at its upper clamp
-    reports STATUS_DAMPING.  A direct solver that finds the damped system not
-    positive definite makes that iteration a rejected step."""
-    p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy())
+def lm_iterate(state, opts: LMOptions, cost_fn, linearize, solve, apply):
+    """The Levenberg-Marquardt iteration (Madsen, Nielsen, Tingleff 2004, Sec. 3.2,
+    with Marquardt's diagonal scaling), independent of what the unknowns are.
+
+    ``cost_fn(state) -> (C, masked)``, ``linearize(state) -> (H, g)`` of the model
+    C(x + d) ~ C + g^T d + d^T H d / 2, ``solve(state, H, g, D, lam) -> (d, pcg_its)``
+    for (H + lam diag(D)) d = -g (d None if the damped system is not numerically
+    positive definite) and ``apply(state, d) -> trial state``.
+
+    One iteration = one linearisation (kept after a rejected step), one damped solve
+    and one trial cost.  D = diag(H) clamped to [1e-6, 1e32].  The predicted decrease
+    of the undamped model is dL = -g^T d - d^T H d / 2 = d^T (lam D d - g) / 2, the gain
+    ratio rho = (C - C_trial) / dL.  The step is accepted iff rho > 1e-3, dL > 0, the
+    trial cost is finite and the trial state masks no more observations (depth <= Z_MIN)
+    than the current one -- a step may not lower the cost by pushing points behind
+    their cameras.  On accept lam *= max(1/3, 1 - (2 rho - 1)^3) and nu = 2; on reject
+    (including a failed solve) lam *= nu and nu *= 2.  lam is clamped to
+    [1e-12, 1e16].  The count is fixed (no early stop); a run that ends with lam at its
+    upper clamp reports STATUS_DAMPING, a non-finite final cost STATUS_NUMERICAL.
+    Returns (final state, LMResult without R, t, X)."""
     lam = opts.lambda0
     nu = 2.0
-    C, masked = cost_and_masked(p)
-    out = LMResult(p.R, p.t, p.X, [C], [], [], [], [], STATUS_OK)
+    C, masked = cost_fn(state)
+    out = LMResult(None, None, None, [C], [], [], [], [], STATUS_OK)
     lin = None
     for _ in range(opts.max_iters):
         if lin is None:
-            lin = normal_equations(p)
-        H, g = lin[0], lin[1]
+            lin = linearize(state)
+        H, g = lin
         D = damping_diag(H.diagonal())
-        delta, pcg_it = solve_step(p, H, g, D, lam, opts)
-        if delta is None:
-            # the damped system is not numerically positive definite (possible only
-            # at the smallest damping, along the scale gauge): a rejected step
-            out.lambdas.append(lam)
-            out.rhos.append(float("nan"))
-            out.pcg_iters.append(pcg_it)
-            out.accepted.append(False)
-            lam = min(max(lam * nu, LAMBDA_MIN), LAMBDA_MAX)
-            nu = 2.0 * nu
-            out.iter_cost.append(C)
-            continue
-        dL = 0.5 * float(delta @ (lam * D * delta - g))
-        nf = int((~p.fixed).sum())
-        Rn, tn, Xn = apply_step(p, delta[:6 * nf], delta[6 * nf:])
-        Cn, masked_n = cost_and_masked(p, Rn, tn, Xn)
-        rho = (C - Cn) / dL if dL != 0 else -np.inf
+        delta, pcg_it = solve(state, H, g, D, lam)
         out.lambdas.append(lam)
-        out.rhos.append(rho)
         out.pcg_iters.append(pcg_it)
-        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO and masked_n <= masked:
-            p.R, p.t, p.X = Rn, tn, Xn
-            C = Cn
-            masked = masked_n
+        accept = False
+        if delta is None:
+            rho = float("nan")
+        else:
+            dL = 0.5 * float(delta @ (lam * D * delta - g))
+            trial = apply(state, delta)
+            Cn, masked_n = cost_fn(trial)
+            rho = (C - Cn) / dL if dL != 0 else -np.inf
+            accept = bool(np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO and masked_n <= masked)
+        out.rhos.append(rho)
+        if accept:
+            state, C, masked = trial, Cn, masked_n
             lam = lam * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
             nu = 2.0
             lin = None
-            out.accepted.append(True)
         else:
             lam = lam * nu
             nu = 2.0 * nu
-            out.accepted.append(False)
         lam = min(max(lam, LAMBDA_MIN), LAMBDA_MAX)
+        out.accepted.append(accept)
+        out.nus.append(nu)
         out.iter_cost.append(C)
     if not np.isfinite(C):
         out.status = STATUS_NUMERICAL
     elif lam >= LAMBDA_MAX:
         out.status = STATUS_DAMPING
+    return state, out
+
+
+def _lm_loop(p: Problem, opts: LMOptions, solve_step):
+    """LM over the cameras and points of a BA problem (``lm_iterate``), the state
+    being the problem itself; ``solve_step(p, H, g, D, lam, opts)`` solves the damped
+    normal equations for d = (d_cameras, d_points)."""
+    p = dataclasses.replace(p, R=p.R.copy(), t=p.t.copy(), X=p.X.copy())
+    nf = int((~p.fixed).sum())
+
+    def linearize(q):
+        H, g = normal_equations(q)[:2]
+        return H, g
+
+    def apply(q, delta):
+        Rn, tn, Xn = apply_step(q, delta[:6 * nf], delta[6 * nf:])
+        return dataclasses.replace(q, R=Rn, t=tn, X=Xn)
+
+    p, out = lm_iterate(p, opts, cost_and_masked, linearize,
+                        lambda q, H, g, D, lam: solve_step(q, H, g, D, lam, opts), apply)
     out.R, out.t, out.X = p.R, p.t, p.X
     return out
 
@@ -1016,54 +1036,19 @@ def rig_apply_step(q: RigProblem, delta: np.ndarray):
 
 
 def lm_rig(q: RigProblem, opts: LMOptions | None = None) -> LMResult:
-    """Levenberg-Marquardt on the vehicle-rig problem with the schedule of _lm_loop
-    (Marquardt scaling on the rig Hessian's diagonal, Nielsen damping, rejection of steps
-    that mask more observations, fixed iteration count), the damped normal equations
-    solved by dense Cholesky.  The result's R, t hold the vehicle poses; the extrinsics
-    are returned in ``ext`` = (Re, te)."""
+    """Levenberg-Marquardt (``lm_iterate``) on the vehicle-rig problem: Marquardt
+    scaling on the rig Hessian's diagonal, the damped normal equations solved by dense
+    Cholesky.  The result's R, t hold the vehicle poses; the extrinsics are returned in
+    ``ext`` = (Re, te)."""
     opts = opts or LMOptions()
     q = dataclasses.replace(q, Rv=q.Rv.copy(), tv=q.tv.copy(), Re=q.Re.copy(), te=q.te.copy(), X=q.X.copy())
-    lam, nu = opts.lambda0, 2.0
-    C, masked = rig_cost_and_masked(q)
-    out = LMResult(q.Rv, q.tv, q.X, [C], [], [], [], [], STATUS_OK)
-    lin = None
-    for _ in range(opts.max_iters):
-        if lin is None:
-            lin = rig_normal_equations(q)
-        H, g = lin
-        D = damping_diag(H.diagonal())
-        delta, _ = _dense_step(None, H, g, D, lam, opts)
-        out.lambdas.append(lam)
-        out.pcg_iters.append(0)
-        if delta is None:
-            out.rhos.append(float("nan"))
-            out.accepted.append(False)
-            lam = min(max(lam * nu, LAMBDA_MIN), LAMBDA_MAX)
-            nu = 2.0 * nu
-            out.iter_cost.append(C)
-            continue
-        dL = 0.5 * float(delta @ (lam * D * delta - g))
-        Rv, tv, Re, te, X = rig_apply_step(q, delta)
-        Cn, masked_n = rig_cost_and_masked(q, Rv, tv, Re, te, X)
-        rho = (C - Cn) / dL if dL != 0 else -np.inf
-        out.rhos.append(rho)
-        if np.isfinite(Cn) and dL > 0 and rho > ACCEPT_RHO and masked_n <= masked:
-            q.Rv, q.tv, q.Re, q.te, q.X = Rv, tv, Re, te, X
-            C, masked = Cn, masked_n
-            lam = lam * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
-            nu = 2.0
-            lin = None
-            out.accepted.append(True)
-        else:
-            lam = lam * nu
-            nu = 2.0 * nu
-            out.accepted.append(False)
-        lam = min(max(lam, LAMBDA_MIN), LAMBDA_MAX)
-        out.iter_cost.append(C)
-    if not np.isfinite(C):
-        out.status = STATUS_NUMERICAL
-    elif lam >= LAMBDA_MAX:
-        out.status = STATUS_DAMPING
+
+    def apply(r, delta):
+        Rv, tv, Re, te, X = rig_apply_step(r, delta)
+        return dataclasses.replace(r, Rv=Rv, tv=tv, Re=Re, te=te, X=X)
+
+    q, out = lm_iterate(q, opts, rig_cost_and_masked, rig_normal_equations,
+                        lambda r, H, g, D, lam: _dense_step(None, H, g, D, lam, opts), apply)
     out.R, out.t, out.X = q.Rv, q.tv, q.X
     out.ext = (q.Re, q.te)
     return out
