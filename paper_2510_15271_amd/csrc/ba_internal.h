@@ -219,6 +219,9 @@ struct PoseDev {
   int32_t n;
   int32_t status;
   double cost;
+  double delta;        // the request's Huber threshold (<= 0: none)
+  int32_t iters;       // the request's Gauss-Newton iterations
+  int32_t reserved;
 };
 
 // Kernel timing hook: the host records events around launches when set.
@@ -279,7 +282,8 @@ hipError_t launch_triangulate_ransac(int n_pts, const int32_t *pt_start, const i
                                      const double *poses, const double *Kc, double tau2, int n_hyp, int method,
                                      double *X, uint8_t *ok, uint8_t *inl, hipStream_t s);
 // Pose-only Gauss-Newton, one workgroup per request.
-hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
-                          double huber_delta, hipStream_t s, KernelTimer *timer);
+// Each request carries its own iteration count and Huber threshold.
+hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, hipStream_t s,
+                          KernelTimer *timer);
 
 }  // namespace bax

@@ -3208,9 +3208,10 @@ __global__ __launch_bounds__(256) void k_rig_update(const ProbDev *__restrict__ 
 // combined in FP64, FP64 6x6 Cholesky solve and FP64 pose update.
 __global__ __launch_bounds__(kPoseThreads) void k_pose_gn(PoseDev *__restrict__ reqs,
                                                           const double *__restrict__ Xall,
-                                                          const float *__restrict__ uvall,
-                                                          int iters, float delta) {
+                                                          const float *__restrict__ uvall) {
   PoseDev &rq = reqs[blockIdx.x];
+  const int iters = rq.iters;
+  const float delta = (float)rq.delta;
   __shared__ double s_pose[12];
   __shared__ double s_sum[4][28];
   __shared__ int s_bad;
@@ -3818,11 +3819,11 @@ hipError_t launch_gather_iters(const BatchPlan &bp, int32_t *out, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, int iters,
-                          double huber_delta, hipStream_t s, KernelTimer *timer) {
+hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, hipStream_t s,
+                          KernelTimer *timer) {
   if (n_req <= 0) return hipSuccess;
   Timed t(timer, K_POSE_GN, s);
-  k_pose_gn<<<n_req, kPoseThreads, 0, s>>>(reqs, X, uv, iters, (float)huber_delta);
+  k_pose_gn<<<n_req, kPoseThreads, 0, s>>>(reqs, X, uv);
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ int check_pose_request(const ba_pose_request &r, int64_t i) {
 }
 
 // Packs requests into one device block: [PoseDev x n][X double][uv float].
-int PoseBatch::pack(const std::vector<const ba_pose_request *> &reqs) {
+int PoseBatch::pack(const std::vector<const ba_pose_request *> &reqs,
+                    const std::vector<const ba_options *> &opts) {
   n = (int)reqs.size();
   int64_t tot = 0;
   for (auto *r : reqs) tot += r->n;
@@ -47,6 +48,8 @@ int PoseBatch::pack(const std::vector<const ba_pose_request *> &reqs) {
     quat_to_pose12(r.pose0, d.pose);
     d.off = o;
     d.n = r.n;
+    d.iters = opts[i]->max_iters;
+    d.delta = opts[i]->huber_delta;
     std::memcpy(&X[3 * o], r.X, 3 * (size_t)r.n * sizeof(double));
     for (int c = 0; c < 2 * r.n; ++c) uv[2 * o + c] = (float)r.uv[c];
     o += r.n;
@@ -60,7 +63,7 @@ size_t PoseBatch::bytes() const {
   return h + x + (size_t)n_corr * 2 * 4;
 }
 
-int PoseBatch::run(char *base, int iters, double delta, hipStream_t s, KernelTimer *tm) {
+int PoseBatch::run(char *base, hipStream_t s, KernelTimer *tm) {
   const size_t h = ((size_t)n * sizeof(PoseDev) + 255) & ~size_t(255);
   const size_t x = ((size_t)n_corr * 3 * 8 + 255) & ~size_t(255);
   PoseDev *dh = (PoseDev *)base;
@@ -69,7 +72,7 @@ int PoseBatch::run(char *base, int iters, double delta, hipStream_t s, KernelTim
   hipError_t e = hipMemcpyAsync(dh, hdr.data(), n * sizeof(PoseDev), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(dX, X.data(), X.size() * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(duv, uv.data(), uv.size() * 4, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_pose_gn(n, dh, dX, duv, iters, delta, s, tm);
+  if (e == hipSuccess) e = launch_pose_gn(n, dh, dX, duv, s, tm);
   if (e == hipSuccess) e = hipMemcpyAsync(hdr.data(), dh, n * sizeof(PoseDev), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(e, "pose batch");
   return BA_OK;
@@ -90,7 +93,7 @@ extern "C" int ba_pose_batch(int32_t n_req, const ba_pose_request *reqs, const b
     rp[i] = &reqs[i];
   }
   PoseBatch pb;
-  pb.pack(rp);
+  pb.pack(rp, std::vector<const ba_options *>(n_req, opt));
   hipStream_t s = (hipStream_t)hip_stream;
   bool own = false;
   hipError_t e = hipSuccess;
@@ -106,7 +109,7 @@ extern "C" int ba_pose_batch(int32_t n_req, const ba_pose_request *reqs, const b
     return hip_fail(e, "pose batch allocation");
   }
   EventTimer timer;  // device time of the pose kernel alone
-  int rc = pb.run((char *)mem, opt->max_iters, opt->huber_delta, s, &timer);
+  int rc = pb.run((char *)mem, s, &timer);
   if (rc == BA_OK) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "pose batch");

@@ -149,10 +149,11 @@ struct PoseBatch {
   std::vector<PoseDev> hdr;
   std::vector<double> X;
   std::vector<float> uv;
-  int pack(const std::vector<const ba_pose_request *> &reqs);
+  // opts[i]: the options of request i (its max_iters and huber_delta)
+  int pack(const std::vector<const ba_pose_request *> &reqs, const std::vector<const ba_options *> &opts);
   size_t bytes() const;
   // Upload, launch and queue the download of the headers into hdr (caller syncs).
-  int run(char *base, int iters, double delta, hipStream_t s, KernelTimer *tm);
+  int run(char *base, hipStream_t s, KernelTimer *tm);
 };
 int check_pose_request(const ba_pose_request &r, int64_t i);
 

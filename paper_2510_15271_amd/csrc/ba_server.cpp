@@ -248,10 +248,13 @@ void ba_server::loop() {
     PoseBatch pb;
     if (!pose_now.empty() && fatal == BA_OK) {
       std::vector<const ba_pose_request *> rp;
-      for (auto &r : pose_now) rp.push_back(&r->preq);
-      pb.pack(rp);
-      if (pb_ok && pb.run((char *)mem + pb_off, pose_now[0]->opt.max_iters,
-                          pose_now[0]->opt.huber_delta, stream, nullptr) != BA_OK)
+      std::vector<const ba_options *> ro;
+      for (auto &r : pose_now) {
+        rp.push_back(&r->preq);
+        ro.push_back(&r->opt);
+      }
+      pb.pack(rp, ro);
+      if (pb_ok && pb.run((char *)mem + pb_off, stream, nullptr) != BA_OK)
         fatal = BA_EDEVICE;
     }
     iters.assign(active.size(), 0);

@@ -113,6 +113,27 @@ def test_pose_requests_through_server_equal_batch(balib):
     assert st["done"] == len(reqs)
 
 
+def test_pose_requests_with_different_options_keep_their_own(balib):
+    """Pose requests admitted in one scheduler step but asking for different
+    iteration counts and Huber thresholds: each result equals, bit for bit,
+    ba_pose_batch run alone with that request's own options."""
+    reqs = make_config4_requests(24, seed=1005)
+    opts = [(10, 1.0), (4, 0.0), (7, 2.5)]
+    refs = {o: balib.pose_batch(reqs, iters=o[0], huber_delta=o[1]) for o in opts}
+    srv = balib.Server(64 << 20, 4)
+    tk = [srv.submit_pose(q, iters=opts[i % 3][0], huber_delta=opts[i % 3][1]) for i, q in enumerate(reqs)]
+    for i, x in enumerate(tk):
+        r = srv.wait(x)
+        ref = refs[opts[i % 3]]
+        assert r["iters"] == opts[i % 3][0]
+        assert np.array_equal(r["q"][0], ref["q"][i]) and np.array_equal(r["t"][0], ref["t"][i]), i
+        assert r["cost"] == ref["cost"][i] and r["status"] == ref["status"][i]
+    srv.close()
+    # the options matter: the three references differ
+    assert not np.array_equal(refs[opts[0]]["t"], refs[opts[1]]["t"])
+    assert not np.array_equal(refs[opts[0]]["cost"], refs[opts[2]]["cost"])
+
+
 def test_destroy_with_queued_requests(balib):
     """Destroying a server cancels what is queued and finishes what runs."""
     scenes = [make_small_drive(20, 1000, seed=140 + i) for i in range(5)]
