@@ -277,6 +277,13 @@ void ba_destroy(ba_problem *p);
    LM iteration replays three graphs (before, during and after the PCG run)
    with the events between them. */
 int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride);
+/* Test hook for the time-out path of BA_FLAG_PCG_RESIDENT: the number of polls of the
+   other workgroups' flags after which the resident PCG's grid barrier gives up
+   (default 1048576, about a second).  With 0 every barrier gives up at once, so every
+   workgroup of the launch exits at its first barrier, the LM iteration rejects its
+   step, and the solve ends with status BA_STATUS_PCG_SYNC and iters = that
+   iteration's number.  Applies from the next solve on; BA_EINVAL for polls < 0. */
+int ba_set_barrier_polls(ba_problem *p, int32_t polls);
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
                         double *ms, int32_t *launches, int32_t *n_out);
 

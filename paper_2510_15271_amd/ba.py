@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libba_mi355x.so")
 
 BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE = 0, -1, -2, -3, -4
 PREC = {"f64": 0, "f32": 1, "f16j": 2, "bf16j": 3}
+STATUS_OK, STATUS_DAMPING, STATUS_NUMERICAL, STATUS_PCG_SYNC = 0, 1, 2, 3
 POSE_MAX_CORR = 4096
 
 
@@ -147,6 +148,7 @@ def lib():
     L.ba_destroy.argtypes = [vp]
     L.ba_destroy.restype = None
     L.ba_set_profiling.argtypes = [vp, i32, i32]
+    L.ba_set_barrier_polls.argtypes = [vp, i32]
     L.ba_get_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_char_p), dp, C.POINTER(i32),
                                       C.POINTER(i32)]
     L.ba_pose_batch.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
@@ -417,6 +419,12 @@ class Problem:
         if m >= 2 ** 31:
             m -= 2 ** 32
         _check(lib().ba_set_profiling(self._h, m, int(stride)))
+        return self
+
+    def set_barrier_polls(self, polls):
+        """Poll bound of the resident PCG's grid barrier (a test hook; 0 makes it give up at once)."""
+        _check(lib().ba_set_barrier_polls(self._h, int(polls)))
+        return self
 
     def info(self):
         i = ProblemInfo()
@@ -502,6 +510,7 @@ def pose_batch(requests, iters=10, huber_delta=1.0, stream=None):
                                status.ctypes.data_as(C.POINTER(C.c_int32)),
                                cost.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)))
     return dict(q=poses[:, :4], t=poses[:, 4:], status=status, cost=cost, device_ms=ms.value)
+
 
 
 class Server:

@@ -992,6 +992,7 @@ LMState DevProblem::fresh_state() const {
   st.cur = host_state.cur;
   st.pcg_max = pcg_max;
   st.init_done = 0;
+  st.bar_polls = bar_polls;
   return st;
 }
 
@@ -2030,6 +2031,13 @@ int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride) {
   p->profiling = mask != 0;
   p->timer.mask = (uint32_t)mask;
   p->timer.stride = stride;
+  return BA_OK;
+}
+
+int ba_set_barrier_polls(ba_problem *p, int32_t polls) {
+  if (!p) return fail(BA_EINVAL, "problem is NULL");
+  if (polls < 0) return fail(BA_EINVAL, "polls must be >= 0");
+  p->dp.bar_polls = polls;
   return BA_OK;
 }
 

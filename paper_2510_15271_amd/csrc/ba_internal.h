@@ -68,7 +68,11 @@ struct LMState {
   int32_t accepted, cur, pcg_done, pcg_iters;
   int32_t pcg_max, init_done, n_masked;
   int32_t pcg_fault;       // 1: the resident PCG's grid barrier timed out (the solve stops)
+  int32_t halted;          // 1: the solve ended before max_iters (after a barrier time-out)
+  int32_t bar_polls;       // polls after which the resident PCG's grid barrier gives up
 };
+// Default of LMState::bar_polls: about a second of polling.
+constexpr int32_t kBarPollsDefault = 1 << 20;
 
 // Device view of one problem.  Arrays typed T hold the compute type of the
 // precision mode (double or float); S is the Jacobian storage type.

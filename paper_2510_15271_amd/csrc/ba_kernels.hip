@@ -393,7 +393,7 @@ __device__ inline void inv_spd6(const double A[36], double out[36]) {
     }
 }
 
-__device__ inline bool lm_active(const LMState *st) { return st->iter < st->max_iters; }
+__device__ inline bool lm_active(const LMState *st) { return st->iter < st->max_iters && !st->halted; }
 
 // ------------------------------------------------------------------ linearize
 // Point tile: points [j0, j1) and their observations [k0, k1) (contiguous, since
@@ -2124,17 +2124,18 @@ __device__ inline void st_shared(V *p, V v) {
 // with a release/acquire pair per workgroup measured 9.3 us per iteration with one
 // counter and 8.3 us with per-tile flags, this form 7.2 us, and a launch per iteration
 // 8.0 us (2M-observation drive).
-// The wait is bounded: after kBarPolls polls the workgroup reports failure, so a launch
-// whose workgroups cannot all be resident at once ends instead of waiting forever.
-constexpr int kBarPolls = 1 << 20;
-__device__ inline bool grid_barrier(uint32_t *flag, int n_tiles, int tile, uint32_t stamp, int *s_ok) {
+// The wait is bounded: after `polls` polls (LMState::bar_polls) the workgroup reports
+// failure, so a launch whose workgroups cannot all be resident at once ends instead of
+// waiting forever.
+__device__ inline bool grid_barrier(uint32_t *flag, int n_tiles, int tile, uint32_t stamp, int polls,
+                                    int *s_ok) {
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   const int t = threadIdx.x;
   if (t < 64) {
     if (t == 0) st_shared(flag + tile, stamp);
     bool all = false;
-    for (int n = 0; n < kBarPolls; ++n) {
+    for (int n = 0; n < polls; ++n) {
       bool mine = true;
       for (int k = t; k < n_tiles; k += 64) mine = mine && ld_shared(flag + k) >= stamp;
       all = __all(mine) != 0;
@@ -2192,6 +2193,7 @@ __global__ __launch_bounds__(1024) void k_cg_run(const ProbDev pd, int n_iter) {
   if (!s_flag[0]) return;
   n_iter = min(n_iter, st->pcg_max);
   const double tol = st->pcg_tol, bb = st->pcg_bb;
+  const int polls = st->bar_polls;
   // ---- per-solve constants and the own-row state
   const int l = t / 6, m = t - 6 * (t / 6);
   const int c = (t < kCgColThreads && l < ncmax) ? tcol[l] : -1;
@@ -2403,7 +2405,7 @@ __global__ __launch_bounds__(1024) void k_cg_run(const ProbDev pd, int n_iter) {
         st_shared(pn2 + 2 * nt + tile, s_red[2] + s_red[5] + s_red[8] + s_red[11]);
       }
     }
-    if (!grid_barrier(pd.cg_flag, nt, tile, (uint32_t)(it + 1), s_flag + 1)) {
+    if (!grid_barrier(pd.cg_flag, nt, tile, (uint32_t)(it + 1), polls, s_flag + 1)) {
       ok = false;
       break;
     }
@@ -2675,8 +2677,9 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   pd.iter_cost[n + 1] = st->cost;
   st->pcg_done = 0;
   st->pcg_iters = 0;
-  st->iter = fault ? st->max_iters : n + 1;
-  if (st->iter >= st->max_iters) {
+  st->iter = n + 1;
+  if (fault) st->halted = 1;  // the remaining iterations do nothing
+  if (st->iter >= st->max_iters || fault) {
     if (fault) st->status = 3;
     else if (!isfinite(st->cost)) st->status = 2;
     else if (lam >= kLambdaMax) st->status = 1;
@@ -3810,7 +3813,10 @@ hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t 
 __global__ void k_gather_iters(const ProbDev *__restrict__ probs, const Tile *__restrict__ ctl, int n,
                                int32_t *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = probs[ctl[i].prob].st->iter;
+  if (i < n) {
+    const LMState *st = probs[ctl[i].prob].st;
+    out[i] = st->halted ? st->max_iters : st->iter;  // a halted solve is finished
+  }
 }
 
 hipError_t launch_gather_iters(const BatchPlan &bp, int32_t *out, hipStream_t s) {

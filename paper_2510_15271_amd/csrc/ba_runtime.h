@@ -87,6 +87,7 @@ struct Offsets {
 // One problem placed in a device block: its descriptor and host-side scalars.
 struct DevProblem {
   int precision = BA_PREC_F32, max_iters = 0, pcg_max = 0;
+  int32_t bar_polls = kBarPollsDefault;  // grid-barrier poll bound of the resident PCG
   double lambda0 = 1e-4, pcg_tol = 1e-6, huber = 0.0;
   int32_t C = 0, Cf = 0, P = 0, N = 0;
   int32_t max_tcols = 0;

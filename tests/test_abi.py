@@ -89,6 +89,7 @@ def test_pose_batch_validation(balib):
     _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch([r]))
 
 
+
 def test_server_create_validation(balib):
     _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1024, 4))
     _expect(balib, balib.BA_EINVAL, lambda: balib.Server(1 << 30, 0))
@@ -267,6 +268,9 @@ def test_binding_layouts_and_constants_match_header(balib, tmp_path):
     assert got == expect
     hdr = open(os.path.join(ROOT, "include", "ba.h")).read()
     defs = {k: int(v) for k, v in re.findall(r"#define (BA_[A-Z0-9_]+) \(?(-?\d+)\)?", hdr)}
+    for name in ("OK", "DAMPING", "NUMERICAL", "PCG_SYNC"):
+        assert getattr(balib, "STATUS_" + name) == defs["BA_STATUS_" + name], name
+    assert balib.POSE_MAX_CORR == defs["BA_POSE_MAX_CORR"]
     for name in ("NO_GRAPH", "PAIR_LISTS", "PCG_WIDE", "PCG_RESIDENT"):
         assert getattr(balib, "FLAG_" + name) == defs["BA_FLAG_" + name], name
     assert balib.TRI == {"midpoint": defs["BA_TRI_MIDPOINT"], "dlt": defs["BA_TRI_DLT"]}

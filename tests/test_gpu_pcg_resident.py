@@ -118,3 +118,53 @@ def test_refine_resident_equals_per_launch(balib):
     assert np.array_equal(aa, ab)
     assert np.array_equal(ra["q"], rb["q"]) and np.array_equal(ra["t"], rb["t"])
     assert np.array_equal(ra["X"], rb["X"])
+
+
+def test_barrier_time_out_rejects_the_step_and_stops(balib):
+    """The barrier's poll bound set to 0 from the host (no workgroup is starved: each
+    gives up at its first barrier and exits): the first LM iteration rejects its step
+    and the solve ends there with BA_STATUS_PCG_SYNC, one iteration reported and the
+    initial state kept.  With the default bound restored the next solve equals a
+    fresh one bit for bit."""
+    s = make_small_drive(40, 3000, seed=5)
+    kw = dict(max_iters=6, precision="f32", flags=RESIDENT)
+    p = balib.Problem.from_scene(s, **kw)
+    assert p.info()["pcg_resident"] == 1
+    init = p.result()
+    p.set_barrier_polls(0)
+    _say("device solve: barrier poll bound 0")
+    r = p.solve().result()
+    _say("status", r["status"], "iters", r["iters"], "costs", r["iter_cost"], "pcg", r["pcg_iters"])
+    assert r["status"] == balib.STATUS_PCG_SYNC
+    assert r["iters"] == 1 and r["accepted"] == 0
+    assert len(r["iter_cost"]) == 2 and r["iter_cost"][0] == r["iter_cost"][1] == r["cost0"] == r["cost"]
+    assert np.array_equal(r["q"], init["q"]) and np.array_equal(r["t"], init["t"])
+    assert np.array_equal(r["X"], init["X"])
+    p.set_barrier_polls(1 << 20)
+    b = p.reset().solve().result()
+    p.close()
+    _, a = _run(balib, s, RESIDENT, max_iters=6, precision="f32")
+    assert b["status"] == 0 and b["iters"] == 6
+    _same(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pose_graph_sixteen_row_tiles_resident_equals_per_launch(balib, prec):
+    """1080-node pose graph: 16 reduced-system rows per workgroup (68 tiles, four waves
+    reducing the partial sums); the resident solve repeats the per-launch one bit for bit."""
+    g = make_pose_graph(180)
+    out = []
+    for flags in (0, RESIDENT):
+        _say("device pose-graph solve: 1080 nodes, flags", flags, prec)
+        p = balib.Problem.from_pose_graph(g, max_iters=6, pcg_max_iters=100, pcg_rel_tol=1e-8,
+                                          precision=prec, flags=flags)
+        info = p.info()
+        out.append((info, p.solve().result()))
+        p.close()
+    (ia, a), (ib, b) = out
+    _say("rows", ib["pcg_rows"], "resident", ib["pcg_resident"], "pcg", list(b["pcg_iters"]))
+    assert ia["pcg_rows"] == 16 and ib["pcg_rows"] == 16
+    assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == 1
+    assert np.array_equal(a["iter_cost"], b["iter_cost"])
+    assert list(a["pcg_iters"]) == list(b["pcg_iters"])
+    assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["t"], b["t"])
