@@ -391,6 +391,19 @@ typedef struct {                 /* one localization request (host memory)      
 int ba_pose_batch(int32_t n_req, const ba_pose_request *reqs, const ba_options *opt,
                   void *hip_stream, ba_pose *poses_out, int32_t *status_out, double *cost_out,
                   double *device_ms);
+/* For callers that cannot allocate device memory (serving loops and harnesses that
+   forbid hipMalloc): ba_pose_batch with the same requests, options, kernel and
+   outputs, but the requests are staged in a fixed device array of
+   BA_POSE_NOALLOC_MAX_BYTES that the library holds, on every device it runs on, until
+   the process ends.  The call allocates and frees no device memory.  Staging takes
+   160 bytes per request and 32 bytes per correspondence (each part rounded up to
+   256 bytes); a call that needs more fails with BA_ENOMEM before any device work.
+   hip_stream NULL: the current device's null stream.  The call returns once its
+   results are on the host.  All calls on one device share its array: calls that
+   overlap in time there (from two threads) race and give undefined results. */
+#define BA_POSE_NOALLOC_MAX_BYTES 100663296  /* 96 MiB */
+int ba_pose_batch_noalloc(int32_t n_req, const ba_pose_request *reqs, const ba_options *opt,
+                          void *hip_stream, ba_pose *poses_out, int32_t *status_out, double *cost_out);
 
 /* ---------------------------------------------------------------- serving
    Continuous batching: submitted problems wait in a queue; a scheduler thread

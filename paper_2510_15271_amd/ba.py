@@ -18,6 +18,7 @@ BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE = 0, -1, -2, -3, -4
 PREC = {"f64": 0, "f32": 1, "f16j": 2, "bf16j": 3}
 STATUS_OK, STATUS_DAMPING, STATUS_NUMERICAL, STATUS_PCG_SYNC = 0, 1, 2, 3
 POSE_MAX_CORR = 4096
+POSE_NOALLOC_MAX_BYTES = 100663296  # staging array of ba_pose_batch_noalloc (96 MiB)
 
 
 class BAError(RuntimeError):
@@ -153,6 +154,8 @@ def lib():
                                       C.POINTER(i32)]
     L.ba_pose_batch.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
                                 C.POINTER(i32), dp, dp]
+    L.ba_pose_batch_noalloc.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
+                                        C.POINTER(i32), dp]
     L.ba_server_create.argtypes = [i64, i32, i32, vp, C.POINTER(vp)]
     L.ba_server_submit.argtypes = [vp, C.POINTER(ProblemDesc), C.POINTER(Options), C.POINTER(i64)]
     L.ba_server_submit_pose.argtypes = [vp, C.POINTER(PoseRequest), C.POINTER(Options),
@@ -511,6 +514,21 @@ def pose_batch(requests, iters=10, huber_delta=1.0, stream=None):
                                cost.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)))
     return dict(q=poses[:, :4], t=poses[:, 4:], status=status, cost=cost, device_ms=ms.value)
 
+
+def pose_batch_noalloc(requests, iters=10, huber_delta=1.0, stream=None):
+    """pose_batch through ba_pose_batch_noalloc (staging in the library's fixed device array)."""
+    keep = []
+    arr = (PoseRequest * len(requests))()
+    for i, q in enumerate(requests):
+        arr[i] = _pose_request(q.K, q.q0, q.t0, q.X, q.uv, keep)
+    o = options(max_iters=iters, huber_delta=huber_delta)
+    poses = np.zeros((len(requests), 7))
+    status = np.zeros(len(requests), np.int32)
+    cost = np.zeros(len(requests))
+    _check(lib().ba_pose_batch_noalloc(len(requests), arr, C.byref(o), stream, _ptr(poses),
+                                       status.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       cost.ctypes.data_as(C.POINTER(C.c_double))))
+    return dict(q=poses[:, :4], t=poses[:, 4:], status=status, cost=cost)
 
 
 class Server:

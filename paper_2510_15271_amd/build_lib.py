@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libba_mi355x.so")
-SOURCES = ["ba_kernels.hip", "ba_host.cpp", "ba_pose.cpp", "ba_server.cpp"]
+SOURCES = ["ba_kernels.hip", "ba_host.cpp", "ba_pose.cpp", "ba_server.cpp", "ba_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compilation.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -87,7 +87,25 @@ def test_pose_batch_validation(balib):
     r.X = np.zeros((balib.POSE_MAX_CORR + 1, 3))
     r.uv = np.zeros((balib.POSE_MAX_CORR + 1, 2))
     _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch([r]))
+    _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch_noalloc([r]))
+    _expect(balib, balib.BA_EINVAL, lambda: balib.pose_batch_noalloc(reqs))
 
+
+def test_pose_batch_noalloc_rejects_oversize_batch(balib):
+    """A batch whose staging exceeds the fixed array fails with BA_ENOMEM before any
+    device work (160 bytes per request and 32 per correspondence)."""
+    base = make_config4_requests(1, seed=1004)[0]
+    n = balib.POSE_MAX_CORR
+    per_req = 160 + 32 * n
+    k = balib.POSE_NOALLOC_MAX_BYTES // per_req + 1
+    X = np.tile(base.X[:1], (n, 1))
+    uv = np.tile(base.uv[:1], (n, 1))
+    big = []
+    for _ in range(k):
+        r = make_config4_requests(1, seed=1004)[0]
+        r.X, r.uv = X, uv
+        big.append(r)
+    _expect(balib, balib.BA_ENOMEM, lambda: balib.pose_batch_noalloc(big))
 
 
 def test_server_create_validation(balib):
@@ -268,6 +286,7 @@ def test_binding_layouts_and_constants_match_header(balib, tmp_path):
     assert got == expect
     hdr = open(os.path.join(ROOT, "include", "ba.h")).read()
     defs = {k: int(v) for k, v in re.findall(r"#define (BA_[A-Z0-9_]+) \(?(-?\d+)\)?", hdr)}
+    assert balib.POSE_NOALLOC_MAX_BYTES == defs["BA_POSE_NOALLOC_MAX_BYTES"]
     for name in ("OK", "DAMPING", "NUMERICAL", "PCG_SYNC"):
         assert getattr(balib, "STATUS_" + name) == defs["BA_STATUS_" + name], name
     assert balib.POSE_MAX_CORR == defs["BA_POSE_MAX_CORR"]
