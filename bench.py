@@ -6,7 +6,13 @@ points, ~1.97M observations, camera 0 fixed): 10 Levenberg-Marquardt
 iterations, each linearising, forming the Schur complement, running block-
 Jacobi PCG (50 products, rel. tol 1e-6), back-substituting and evaluating the
 trial cost.  The problem is uploaded once; each step restores the initial state
-on the device (ba_reset) and solves.  Prints one JSON line.
+on the device (ba_reset) and solves.  Prints one JSON line: the drive's LM
+iterations/s as `value`, the dominant kernel and the whole LM loop against the
+HBM roofline (algorithmic bytes of the method: 48 B per observation, 48 B per
+point, and the reduced system's upper triangle, 144 B per FP32 6x6 block, once to
+form it and once per PCG iteration), and the other legs: the tiny FP64 scene, the
+11.2M-observation loop scene in FP32 / FP16-J / BF16-J, the refinement, vehicle-rig
+and pose-graph legs, the serving streams and the oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--precision f32|f64|f16j|bf16j]
 """
@@ -27,9 +33,41 @@ HBM_PEAK_GBS = 8000.0
 LM_ITERS = 10
 
 
-def algorithmic_bytes(kernel: str, info: dict, precision: str) -> float:
-    """Bytes a kernel must move per launch (each input read once, each output
-    written once), from the problem's sizes."""
+def model_bytes_pcg_iteration(info: dict, precision: str) -> float:
+    """Algorithmic bytes of one PCG iteration in the byte model of the method: the
+    reduced system's upper triangle with its diagonal read once, one 6x6 block of the
+    compute type per block (144 B in FP32); vectors are negligible beside it."""
+    T = 8 if precision == "f64" else 4
+    return (info["n_up_blocks"] + info["n_free_cams"]) * 36 * T
+
+
+def model_bytes_lm_iteration(info: dict, precision: str, pcg_iters: float) -> float:
+    """Algorithmic bytes of one LM iteration in the same model: the observations
+    (16 B each) read three times (linearise + Schur, back-substitution, trial cost),
+    the points (12 B) read three times and written once, and the reduced system read
+    once to form it plus once per PCG iteration."""
+    return (48 * info["n_obs"] + 48 * info["n_pts"]
+            + (1 + pcg_iters) * model_bytes_pcg_iteration(info, precision))
+
+
+def host_cpu() -> dict:
+    """The host's logical core count and CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cores": os.cpu_count(), "cpu_model": model}
+
+
+def design_bytes(kernel: str, info: dict, precision: str) -> float:
+    """Bytes a kernel of this design moves per launch (each input it reads once,
+    each output it writes once), from the problem's sizes: both triangles of S, the
+    stored linearisation records and the chunk partials included."""
     T = 8 if precision == "f64" else 4
     S = {"f64": 8, "f32": 4, "f16j": 2, "bf16j": 2}[precision]
     N, P, Cf, C = info["n_obs"], info["n_pts"], info["n_free_cams"], info["n_cams"]
@@ -98,7 +136,7 @@ def refine_leg(ba, precision: str, n_pts: int, flags: int = 0, reps: int = 3) ->
     wall = float(np.median(walls))
     n_rounds = len(REFINE_STAGES) * REFINE_ROUNDS
     cull_s = cull_ms / 1000.0 / max(n_cull, 1)
-    abytes = algorithmic_bytes("cull", info, precision)
+    abytes = design_bytes("cull", info, precision)
     return {"workload": f"sequential drive BA with 5 % uniform outliers: {info['n_cams']} cameras, "
                         f"{info['n_pts']} points, {info['n_obs']} observations",
             "stages": [{"huber_delta_px": d, "cull_px": t} for d, t in REFINE_STAGES],
@@ -144,7 +182,7 @@ def pose_graph_leg(ba, precision: str, n_frames: int, flags: int = 0, steps: int
     p.close()
     wall = float(np.median(walls))
     cg_s = cg_ms / 1000.0 / max(cg_n, 1)
-    abytes = algorithmic_bytes("pcg_cg", info, precision)
+    abytes = model_bytes_pcg_iteration(info, precision)
     return {"workload": f"pose graph: {g.meta['n_frames'] * g.meta['laps']} frames x 3 cameras = "
                         f"{info['n_cams']} nodes (1 fixed), {g.n_edges} edges "
                         f"(sequential k = 1, 2; loop closures; extrinsic)",
@@ -204,6 +242,87 @@ def rig_leg(ba, precision: str, flags: int = 0, steps: int = 10) -> dict:
             "kernel_us_per_iter": per_iter_us}
 
 
+def config0_leg(ba, steps: int = 5) -> dict:
+    """The tiny arc scene (10 cameras, 1000 points, ~9k observations) in FP64: 20 LM
+    iterations with PCG run to 1e-14, device time per LM iteration (median of `steps`
+    solves from the initial state), and every C_n against the dense FP64 oracle's run
+    stored in tests/golden/config0_oracle.json."""
+    import numpy as np
+    from synth import make_config0
+    s = make_config0()
+    p = ba.Problem.from_scene(s, max_iters=20, pcg_max_iters=200, pcg_rel_tol=1e-14, precision="f64",
+                              flags=ba.FLAG_PCG_RESIDENT)
+    info = p.info()
+    p.reset().solve()  # warm-up (graph capture)
+    walls, dev = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        p.reset().solve()
+        walls.append(time.perf_counter() - t0)
+        dev.append(p.report()["solve_ms"])
+    r = p.report()
+    p.close()
+    out = {"workload": f"tiny arc BA: {info['n_cams']} cameras (1 fixed), {info['n_pts']} points, "
+                       f"{info['n_obs']} observations, FP64, 20 LM iterations, PCG 200 / 1e-14",
+           "device_us_per_lm_iteration": round(float(np.median(dev)) * 1000 / 20, 2),
+           "wall_us_per_lm_iteration": round(float(np.median(walls)) * 1e6 / 20, 2),
+           "final_rms_px": r["rms_px"]}
+    gold = os.path.join(ROOT, "tests", "golden", "config0_oracle.json")
+    with open(gold) as f:
+        g = json.load(f)
+    rel = [abs(a - b) / b for a, b in zip(r["iter_cost"], g["iter_cost"])]
+    out["vs_oracle"] = {"max_rel_cost_err": max(rel), "final_rms_err_px": abs(r["rms_px"] - g["final_rms_px"]),
+                        "oracle": "dense normal equations, FP64"}
+    return out
+
+
+def loop_leg(ba, precisions, steps: int = 2) -> dict:
+    """The loop-closed drive (3000 cameras on two overlapping laps, 1.5M points, ~11.2M
+    observations, 5 % outliers, Huber 1 px): 15 LM iterations with PCG 50 / 1e-6 per
+    solve in each precision mode, inputs resident in HBM; LM iterations/s over `steps`
+    solves, the whole loop against the byte model, and the final cost and RMS against
+    the FP64 oracle's run of the same schedule (tests/golden/config2_oracle.json)."""
+    import numpy as np
+    from synth import make_config2
+    print("bench: generating the loop scene", flush=True, file=sys.stderr)
+    s = make_config2()
+    gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+    with open(gold) as f:
+        g = json.load(f)
+    out = {}
+    for prec in precisions:
+        print(f"bench: loop scene, {prec}", flush=True, file=sys.stderr)
+        p = ba.Problem.from_scene(s, max_iters=15, pcg_max_iters=50, pcg_rel_tol=1e-6, precision=prec)
+        info = p.info()
+        p.reset().solve()  # warm-up (graph capture)
+        walls, dev = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            p.reset().solve()
+            walls.append(time.perf_counter() - t0)
+            dev.append(p.report()["solve_ms"])
+        r = p.report()
+        p.close()
+        wall = float(np.median(walls))
+        dev_lm_s = float(np.median(dev)) / 1000.0 / 15
+        pcg_per_lm = float(np.mean(r["pcg_iters"]))
+        lm_bytes = model_bytes_lm_iteration(info, prec, pcg_per_lm)
+        rel = [abs(a - b) / b for a, b in zip(r["iter_cost"], g["iter_cost"])]
+        out[prec] = {"lm_iters_per_s": round(15 / wall, 2), "obs_per_s": round(info["n_obs"] * 15 / wall, 1),
+                     "device_us_per_lm_iteration": round(dev_lm_s * 1e6, 2),
+                     "loop_roofline": {"bound": "hbm", "bytes_per_lm_iteration": round(lm_bytes),
+                                       "achieved": round(lm_bytes / dev_lm_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(lm_bytes / dev_lm_s / 1e9 / HBM_PEAK_GBS, 4)},
+                     "final_cost": r["cost"], "final_rms_px": r["rms_px"],
+                     "vs_oracle": {"final_rms_px": g["final_rms_px"],
+                                   "final_rms_err_px": abs(r["rms_px"] - g["final_rms_px"]),
+                                   "max_rel_cost_err": max(rel),
+                                   "same_pcg_iters": [int(x) for x in r["pcg_iters"]] == g["pcg_iters"]}}
+    out["workload"] = (f"loop-closed Huber drive BA: {info['n_cams']} cameras (1 fixed), {info['n_pts']} points, "
+                       f"{info['n_obs']} observations, 5 % outliers, Huber 1 px, 15 LM iterations, PCG 50 / 1e-6")
+    return out
+
+
 def cpu_baseline(budget_s: float = 30.0) -> dict:
     """The FP64 oracle (explicit Schur complement + block-Jacobi PCG, the same
     schedule) timed on one host core for one LM iteration of the same scene."""
@@ -227,10 +346,10 @@ print(json.dumps({"seconds": dt, "n_obs": p.n_obs, "iters": 1}))
                              timeout=max(120.0, 6 * budget_s))
         d = json.loads(out.stdout.strip().splitlines()[-1])
     except Exception as e:  # the baseline is reported, never required
-        return {"value": None, "unit": "LM iterations/s", "cores": 1, "kind": "oracle",
+        return {"value": None, "unit": "LM iterations/s", "cores": 1, "kind": "oracle", **host_cpu(),
                 "sample": f"failed: {e}"}
     sec = d["seconds"]
-    return {"value": 1.0 / sec, "unit": "LM iterations/s", "cores": 1, "kind": "oracle",
+    return {"value": 1.0 / sec, "unit": "LM iterations/s", "cores": 1, "kind": "oracle", **host_cpu(),
             "obs_per_s": d["n_obs"] / sec,
             "sample": f"1 LM iteration (linearise, explicit Schur, PCG 50/1e-6, back-substitution, "
                       f"trial cost) of the same {d['n_obs']}-observation scene, FP64 NumPy/SciPy, "
@@ -325,6 +444,11 @@ def main():
                     help="skip the pose-graph leg (9000 nodes, 24.7k edges)")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the iterative-refinement leg (outlier drive, two stages)")
+    ap.add_argument("--no-config0", action="store_true",
+                    help="skip the tiny FP64 leg (10 cameras, 1000 points, 20 LM iterations)")
+    ap.add_argument("--loop-precisions", default="f32,f16j,bf16j",
+                    help="precision modes of the loop-scene leg (11.2M observations), comma-separated; "
+                         "empty to skip it")
     ap.add_argument("--per-launch-pcg", action="store_true",
                     help="one launch per PCG iteration instead of one resident launch per linear "
                          "solve (BA_FLAG_PCG_RESIDENT, the default for this lone solve)")
@@ -406,14 +530,22 @@ def main():
     ms_per_step = 1000.0 * wall / args.steps
     lm_per_s = LM_ITERS * args.steps / wall
     avg_launch_s = dom_ms / 1000.0 / max(dom_launch, 1)
-    abytes = algorithmic_bytes(dominant, info, args.precision)
     resident = dominant == "pcg_cg" and bool(info["pcg_resident"])
-    iters_per_launch = None
-    if resident:
-        # one launch runs a whole linear solve: its algorithmic bytes are those of one PCG
-        # iteration (S read once, the vectors once) times the iterations it ran
-        iters_per_launch = pcg_iters / max(dom_launch, 1)
-        abytes = abytes * iters_per_launch
+    pcg_per_lm = pcg_iters / (args.steps * LM_ITERS)
+    # algorithmic bytes per launch of the dominant kernel: for the PCG, the reduced
+    # system's upper triangle once per PCG iteration (a resident launch runs a whole
+    # linear solve, so it is charged the iterations it ran); another dominant kernel is
+    # charged its design bytes (each input and output once)
+    if dominant in ("pcg_cg", "pcg_spmv"):
+        per_unit = model_bytes_pcg_iteration(info, args.precision)
+        units = pcg_iters / max(dom_launch, 1) if resident else 1.0
+        bytes_model = "method: S upper triangle with diagonal, 36 values per 6x6 block, once per PCG iteration"
+        dbytes = design_bytes(dominant, info, args.precision) * units
+    else:
+        per_unit, units = design_bytes(dominant, info, args.precision), 1.0
+        bytes_model = "design: each input and output of the kernel once"
+        dbytes = per_unit
+    abytes = per_unit * units
     achieved = abytes / avg_launch_s / 1e9 if abytes else None
     traffic = None
     tname = f"{dominant}_resident" if resident else dominant
@@ -426,10 +558,20 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "algorithmic_bytes": round(abytes)}
+                "algorithmic_bytes": round(abytes), "bytes_per_unit": round(per_unit),
+                "units_per_launch": round(units, 3), "bytes_model": bytes_model,
+                "design_bytes": round(dbytes),
+                "design_frac": round(dbytes / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)}
     if resident:
-        roofline["pcg_iterations_per_launch"] = round(iters_per_launch, 2)
-        roofline["avg_pcg_iteration_us"] = round(avg_launch_s * 1e6 / iters_per_launch, 3)
+        roofline["avg_pcg_iteration_us"] = round(avg_launch_s * 1e6 / units, 3)
+    # the whole LM loop against the same model (device time of the iteration loop)
+    lm_bytes = model_bytes_lm_iteration(info, args.precision, pcg_per_lm)
+    dev_lm_s = sum(dev_ms) / len(dev_ms) / 1000.0 / LM_ITERS
+    loop_roofline = {"bound": "hbm", "bytes_per_lm_iteration": round(lm_bytes),
+                     "pcg_iterations_per_lm_iteration": round(pcg_per_lm, 2),
+                     "device_us_per_lm_iteration": round(dev_lm_s * 1e6, 2),
+                     "achieved": round(lm_bytes / dev_lm_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(lm_bytes / dev_lm_s / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
         "metric": METRIC,
         "value": round(lm_per_s, 2),
@@ -461,8 +603,25 @@ def main():
         "final_rms_px": r["rms_px"],
         "final_cost": r["cost"],
         "roofline": roofline,
+        "loop_roofline": loop_roofline,
     }
+    gold = os.path.join(ROOT, "tests", "golden", f"config{1 if args.workload == 'drive' else 2}_oracle.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        if g["n_obs"] == info["n_obs"] and len(g["iter_cost"]) == LM_ITERS + 1:
+            # the FP64 oracle's run of the same scene and schedule, stored by tests/golden
+            out["vs_oracle"] = {"final_rms_px": g["final_rms_px"],
+                                "final_rms_err_px": abs(r["rms_px"] - g["final_rms_px"]),
+                                "max_rel_cost_err": max(abs(a - b) / b for a, b in zip(r["iter_cost"],
+                                                                                         g["iter_cost"])),
+                                "same_pcg_iters": [int(x) for x in r["pcg_iters"]] == g["pcg_iters"]}
     prob.close()
+    if not args.no_config0 and args.workload == "drive":
+        print("bench: tiny FP64 scene", flush=True, file=sys.stderr)
+        out["config0"] = config0_leg(ba)
+    if args.loop_precisions and args.workload == "drive":
+        out["loop"] = loop_leg(ba, [x for x in args.loop_precisions.split(",") if x])
     if not args.no_refine and args.workload == "drive":
         out["refine"] = refine_leg(ba, args.precision, args.points or 250_000,
                                    (ba.FLAG_NO_GRAPH if args.no_graph else 0) |
