@@ -284,6 +284,35 @@ int ba_set_profiling(ba_problem *p, int32_t mask, int32_t stride);
    step, and the solve ends with status BA_STATUS_PCG_SYNC and iters = that
    iteration's number.  Applies from the next solve on; BA_EINVAL for polls < 0. */
 int ba_set_barrier_polls(ba_problem *p, int32_t polls);
+/* Test export of one LM iteration's intermediate quantities, for element-wise
+   checks of the linearisation, the Schur complement (paper Sec. 4.3; the reduced
+   camera system of the method), the PCG solution and the back-substitution.  Runs one
+   LM iteration from the current state as a solve with max_iters = 1 would (lambda =
+   lambda0), leaves the problem in the state that solve leaves, and copies out, in
+   FP64 (values of the compute type widened), into the caller's buffers (NULL skips):
+     S_rowptr   n_free_cams + 1    block rows of S (free cameras in the caller's order)
+     S_col      nnzb               free-camera column of each stored block
+     S          36 nnzb            the damped reduced system S = U* - W V*^-1 W^T,
+                                   every stored 6x6 block (both triangles), row-major
+     b          6 n_free_cams      right-hand side -g_c + W V*^-1 g_p
+     gc         6 n_free_cams      camera gradient J_c^T W r (with the prior terms)
+     dc         6 n_free_cams      the PCG solution (the camera step)
+     gp         3 n_pts            point gradient, caller's point order
+     dp         3 n_pts            the back-substituted point step (trial point minus
+                                   point, in FP64)
+     r          2 n_obs            sqrt(w) r per observation, caller's order, as stored
+                                   for the Schur complement (0 in fixed cameras)
+     Jc, Jp     12 n_obs, 6 n_obs  sqrt(w) J_c and sqrt(w) J_p (row-major 2x6, 2x3) as
+                                   rebuilt from the stored record (0 in fixed cameras)
+   lambda, pcg_iters and accepted report the iteration.  BA_EINVAL for a vehicle-rig
+   problem; BA_ESTATE while a solve is in flight. */
+typedef struct {
+  double lambda;
+  int32_t pcg_iters, accepted;
+  int32_t *S_rowptr, *S_col;
+  double *S, *b, *gc, *dc, *gp, *dp, *r, *Jc, *Jp;
+} ba_debug_iteration;
+int ba_debug_iteration_export(ba_problem *p, ba_debug_iteration *out);
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names,
                         double *ms, int32_t *launches, int32_t *n_out);
 

@@ -57,6 +57,14 @@ class ProblemDesc(C.Structure):
                 ("points_xyz", C.c_void_p), ("n_obs", C.c_int64), ("obs", C.c_void_p)]
 
 
+class DebugIteration(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("pcg_iters", C.c_int32), ("accepted", C.c_int32),
+                ("S_rowptr", C.POINTER(C.c_int32)), ("S_col", C.POINTER(C.c_int32)),
+                ("S", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)), ("gc", C.POINTER(C.c_double)),
+                ("dc", C.POINTER(C.c_double)), ("gp", C.POINTER(C.c_double)), ("dp", C.POINTER(C.c_double)),
+                ("r", C.POINTER(C.c_double)), ("Jc", C.POINTER(C.c_double)), ("Jp", C.POINTER(C.c_double))]
+
+
 class PoseRequest(C.Structure):
     _fields_ = [("K", Intrinsics), ("pose0", Pose), ("n", C.c_int32),
                 ("X", C.c_void_p), ("uv", C.c_void_p)]
@@ -150,6 +158,7 @@ def lib():
     L.ba_destroy.restype = None
     L.ba_set_profiling.argtypes = [vp, i32, i32]
     L.ba_set_barrier_polls.argtypes = [vp, i32]
+    L.ba_debug_iteration_export.argtypes = [vp, C.POINTER(DebugIteration)]
     L.ba_get_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_char_p), dp, C.POINTER(i32),
                                       C.POINTER(i32)]
     L.ba_pose_batch.argtypes = [i32, C.POINTER(PoseRequest), C.POINTER(Options), vp, vp,
@@ -428,6 +437,27 @@ class Problem:
         """Poll bound of the resident PCG's grid barrier (a test hook; 0 makes it give up at once)."""
         _check(lib().ba_set_barrier_polls(self._h, int(polls)))
         return self
+
+    def debug_iteration(self):
+        """ba_debug_iteration_export: one LM iteration from the current state and its
+        intermediate quantities (S blocks in CSR, b, g_c, dc, g_p, dp, sqrt(w) r, J_c, J_p)."""
+        info = self.info()
+        cf, nnzb, n_obs = info["n_free_cams"], info["nnzb"], info["n_obs"]
+        out = dict(S_rowptr=np.zeros(cf + 1, np.int32), S_col=np.zeros(max(nnzb, 1), np.int32),
+                   S=np.zeros((max(nnzb, 1), 6, 6)), b=np.zeros(6 * cf), gc=np.zeros(6 * cf),
+                   dc=np.zeros(6 * cf), gp=np.zeros((max(self.n_pts, 1), 3)), dp=np.zeros((max(self.n_pts, 1), 3)),
+                   r=np.zeros((max(n_obs, 1), 2)), Jc=np.zeros((max(n_obs, 1), 2, 6)),
+                   Jp=np.zeros((max(n_obs, 1), 2, 3)))
+        d = DebugIteration()
+        for k, a in out.items():
+            ct = C.c_int32 if a.dtype == np.int32 else C.c_double
+            setattr(d, k, a.ctypes.data_as(C.POINTER(ct)))
+        _check(lib().ba_debug_iteration_export(self._h, C.byref(d)))
+        out["S_col"], out["S"] = out["S_col"][:nnzb], out["S"][:nnzb]
+        out["gp"], out["dp"] = out["gp"][:self.n_pts], out["dp"][:self.n_pts]
+        out["r"], out["Jc"], out["Jp"] = out["r"][:n_obs], out["Jc"][:n_obs], out["Jp"][:n_obs]
+        out.update(lam=d.lambda_, pcg_iters=d.pcg_iters, accepted=d.accepted)
+        return out
 
     def info(self):
         i = ProblemInfo()

@@ -2041,6 +2041,87 @@ int ba_set_barrier_polls(ba_problem *p, int32_t polls) {
   return BA_OK;
 }
 
+int ba_debug_iteration_export(ba_problem *p, ba_debug_iteration *out) {
+  if (!p || !out) return fail(BA_EINVAL, "NULL argument");
+  if (p->rig) return fail(BA_EINVAL, "the iteration export covers single-view problems, not vehicle rigs");
+  if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
+  DevProblem &dp = p->dp;
+  const ProbDev &v = dp.view;
+  const int cur0 = dp.host_state.cur;
+  dp.pending_state = dp.fresh_state();
+  dp.pending_state.max_iters = 1;
+  hipError_t e = hipMemcpyAsync(v.st, &dp.pending_state, sizeof(LMState), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = launch_lm_iteration(dp.precision, p->batch.plan, dp.pcg_max, dp.max_tcols, p->stream, nullptr);
+  if (e == hipSuccess) e = launch_eval(dp.precision, p->batch.plan, p->stream, nullptr);
+  double *dev = nullptr;  // records widened to FP64: r (2), J_c (12), J_p (6) per observation
+  const size_t N = (size_t)v.N;
+  if (e == hipSuccess && N && (out->r || out->Jc || out->Jp)) {
+    e = hipMalloc(&dev, N * 20 * sizeof(double));
+    if (e == hipSuccess) e = launch_export_records(dp.precision, v, cur0, dev, dev + 2 * N, dev + 14 * N, p->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess) e = hipMemcpy(&dp.host_state, v.st, sizeof(LMState), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    if (dev) (void)hipFree(dev);
+    return hip_fail(e, "iteration export");
+  }
+  p->solved = true;
+  p->solve_ms = 0.0;
+  const LMState &st = dp.host_state;
+  out->lambda = dp.pending_state.lambda;
+  out->accepted = st.accepted;
+  int32_t pi = 0;
+  e = hipMemcpy(&pi, v.iter_pcg, 4, hipMemcpyDeviceToHost);
+  out->pcg_iters = pi;
+  const size_t tb = compute_bytes(dp.precision);
+  // a device array of the compute type, widened to FP64
+  auto fetch = [&](const void *src, size_t n, std::vector<double> &dst) -> hipError_t {
+    dst.resize(n);
+    if (tb == 8) return hipMemcpy(dst.data(), src, n * 8, hipMemcpyDeviceToHost);
+    std::vector<float> f(n);
+    hipError_t r2 = hipMemcpy(f.data(), src, n * 4, hipMemcpyDeviceToHost);
+    for (size_t i = 0; i < n; ++i) dst[i] = f[i];
+    return r2;
+  };
+  const int Cf = v.Cf, P = v.P;
+  std::vector<double> buf;
+  if (e == hipSuccess && out->S_rowptr) std::copy(p->sy.S_rowptr.begin(), p->sy.S_rowptr.end(), out->S_rowptr);
+  if (e == hipSuccess && out->S_col) std::copy(p->sy.S_col.begin(), p->sy.S_col.end(), out->S_col);
+  if (e == hipSuccess && out->S && (e = fetch(v.S, 36 * (size_t)v.nnzb, buf)) == hipSuccess)
+    std::copy(buf.begin(), buf.end(), out->S);
+  const std::pair<const void *, double *> cams[3] = {{v.brhs, out->b}, {v.gc, out->gc}, {v.x, out->dc}};
+  for (const auto &c : cams)
+    if (e == hipSuccess && c.second && (e = fetch(c.first, 6 * (size_t)Cf, buf)) == hipSuccess)
+      std::copy(buf.begin(), buf.end(), c.second);
+  if (e == hipSuccess && out->gp && P > 0 && (e = fetch(v.gp, 3 * (size_t)P, buf)) == hipSuccess)
+    for (int j = 0; j < P; ++j)
+      for (int m = 0; m < 3; ++m) out->gp[3 * (size_t)dp.pt_order[j] + m] = buf[3 * (size_t)j + m];
+  if (e == hipSuccess && out->dp && P > 0) {
+    std::vector<double> X0(3 * (size_t)P), X1(3 * (size_t)P);
+    e = hipMemcpy(X0.data(), v.X[cur0], X0.size() * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(X1.data(), v.X[1 - cur0], X1.size() * 8, hipMemcpyDeviceToHost);
+    for (int j = 0; j < P && e == hipSuccess; ++j)
+      for (int m = 0; m < 3; ++m)
+        out->dp[3 * (size_t)dp.pt_order[j] + m] = X1[3 * (size_t)j + m] - X0[3 * (size_t)j + m];
+  }
+  if (e == hipSuccess && dev) {
+    std::vector<double> rec(N * 20);
+    e = hipMemcpy(rec.data(), dev, rec.size() * 8, hipMemcpyDeviceToHost);
+    for (size_t k = 0; k < N && e == hipSuccess; ++k) {
+      const size_t o = (size_t)dp.obs_order[k];
+      if (out->r)
+        for (int i = 0; i < 2; ++i) out->r[2 * o + i] = rec[2 * k + i];
+      if (out->Jc)
+        for (int i = 0; i < 12; ++i) out->Jc[12 * o + i] = rec[2 * N + 12 * k + i];
+      if (out->Jp)
+        for (int i = 0; i < 6; ++i) out->Jp[6 * o + i] = rec[14 * N + 6 * k + i];
+    }
+  }
+  if (dev) (void)hipFree(dev);
+  if (e != hipSuccess) return hip_fail(e, "iteration export");
+  return BA_OK;
+}
+
 int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **names, double *ms,
                         int32_t *launches, int32_t *n_out) {
   if (!p) return fail(BA_EINVAL, "problem is NULL");

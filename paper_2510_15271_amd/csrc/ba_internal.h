@@ -285,6 +285,10 @@ hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t 
 hipError_t launch_triangulate_ransac(int n_pts, const int32_t *pt_start, const int32_t *cam, const double *xy,
                                      const double *poses, const double *Kc, double tau2, int n_hyp, int method,
                                      double *X, uint8_t *ok, uint8_t *inl, hipStream_t s);
+// Test export: sqrt(w) r (2), sqrt(w) J_c (12) and sqrt(w) J_p (6) of every observation
+// in internal order, in FP64, from the stored records formed at state `cur`.
+hipError_t launch_export_records(int precision, const ProbDev &pd, int cur, double *r, double *Jc, double *Jp,
+                                 hipStream_t s);
 // Pose-only Gauss-Newton, one workgroup per request.
 // Each request carries its own iteration count and Huber threshold.
 hipError_t launch_pose_gn(int n_req, PoseDev *reqs, const double *X, const float *uv, hipStream_t s,

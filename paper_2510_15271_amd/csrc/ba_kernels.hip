@@ -3657,6 +3657,47 @@ hipError_t launch_lm_iteration(int precision, const BatchPlan &bp, int pcg_max, 
   }
 }
 
+// Test export of the stored linearisation: sqrt(w) r, sqrt(w) J_c and sqrt(w) J_p of
+// every observation (internal order) from its record, rebuilt exactly as the Schur
+// and back-substitution kernels rebuild them, in FP64; zeros for observations in
+// fixed cameras (they have no record).  `cur`: the state the records were formed at.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_export_records(const ProbDev pd, int cur, double *__restrict__ r,
+                                                        double *__restrict__ Jc, double *__restrict__ Jp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= pd.N) return;
+  double *ro = r + 2 * (size_t)k, *jco = Jc + 12 * (size_t)k, *jpo = Jp + 6 * (size_t)k;
+  const int cpos = pd.obs_rpos[k];
+  if (cpos < 0) {
+    for (int i = 0; i < 2; ++i) ro[i] = 0.0;
+    for (int i = 0; i < 12; ++i) jco[i] = 0.0;
+    for (int i = 0; i < 6; ++i) jpo[i] = 0.0;
+    return;
+  }
+  const LinRec<T, S> &rec = ((const LinRec<T, S> *)pd.lin)[cpos];
+  T f[7], R[9], J[12], P[6];
+  decode(rec, f);
+  load_rot(pd.pose[cur] + 12 * pd.obs_cam[k], R);
+  jc_from(f, J);
+  jp_from(f, R, P);
+  for (int i = 0; i < 2; ++i) ro[i] = (double)rec.e[i];
+  for (int i = 0; i < 12; ++i) jco[i] = (double)J[i];
+  for (int i = 0; i < 6; ++i) jpo[i] = (double)P[i];
+}
+
+hipError_t launch_export_records(int precision, const ProbDev &pd, int cur, double *r, double *Jc, double *Jp,
+                                 hipStream_t s) {
+  if (pd.N <= 0) return hipSuccess;
+  const int g = (pd.N + 255) / 256;
+  switch (precision) {
+    case 0: k_export_records<double, double><<<g, 256, 0, s>>>(pd, cur, r, Jc, Jp); break;
+    case 1: k_export_records<float, float><<<g, 256, 0, s>>>(pd, cur, r, Jc, Jp); break;
+    case 2: k_export_records<float, _Float16><<<g, 256, 0, s>>>(pd, cur, r, Jc, Jp); break;
+    default: k_export_records<float, bf16s><<<g, 256, 0, s>>>(pd, cur, r, Jc, Jp); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer) {
   if (!bp.n_pt) return hipSuccess;
   Timed t(timer, K_EVAL, s);

@@ -246,7 +246,8 @@ _MIRRORS = [("Intrinsics", "ba_intrinsics"), ("Pose", "ba_pose"), ("Options", "b
             ("PoseRequest", "ba_pose_request"), ("ProblemInfo", "ba_problem_info"),
             ("PoseEdge", "ba_pose_edge"), ("PoseGraphDesc", "ba_pose_graph_desc"),
             ("RigDesc", "ba_rig_desc"), ("RefineStage", "ba_refine_stage"),
-            ("RefineRound", "ba_refine_round"), ("ServerStats", "ba_server_stats_t")]
+            ("RefineRound", "ba_refine_round"), ("ServerStats", "ba_server_stats_t"),
+            ("DebugIteration", "ba_debug_iteration")]
 _DTYPES = [("OBS_DTYPE", "ba_obs"), ("RIG_OBS_DTYPE", "ba_rig_obs"), ("EDGE_DTYPE", "ba_pose_edge")]
 _DTYPE_FIELDS = {"q": "meas.qw", "t": "meas.tx"}  # EDGE_DTYPE flattens the measured pose
 

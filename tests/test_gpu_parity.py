@@ -25,6 +25,37 @@ def _solve(balib, scene, **kw):
     return res
 
 
+def _umeyama(src, dst):
+    """Similarity (s, Q, tau) minimising sum ||dst - (s Q src + tau)||^2 (Umeyama 1991)."""
+    ms, md = src.mean(0), dst.mean(0)
+    A, B = src - ms, dst - md
+    U, sig, Vt = np.linalg.svd(B.T @ A / len(src))
+    E = np.eye(3)
+    if np.linalg.det(U) * np.linalg.det(Vt) < 0:
+        E[2, 2] = -1.0
+    Q = U @ E @ Vt
+    s = np.trace(np.diag(sig) @ E) / (A * A).sum(1).mean()
+    return s, Q, md - s * Q @ ms
+
+
+def _state_diff(res, R_ref, t_ref, X_ref):
+    """Largest differences of the device's final state from the oracle's, in metres
+    (points, camera centres) and in rotation-matrix entries, directly and after the
+    similarity that best maps the device's points onto the oracle's (the scale about
+    the fixed camera is a null direction of the problem)."""
+    R = O.quat_to_rot(res["q"])
+    c = -np.einsum("nji,nj->ni", R, res["t"])
+    c_ref = -np.einsum("nji,nj->ni", R_ref, t_ref)
+    direct = dict(X=np.abs(res["X"] - X_ref).max(), c=np.abs(c - c_ref).max(), R=np.abs(R - R_ref).max())
+    s, Q, tau = _umeyama(res["X"], X_ref)
+    Xa = s * res["X"] @ Q.T + tau
+    ca = s * c @ Q.T + tau
+    Ra = R @ Q.T
+    aligned = dict(X=np.abs(Xa - X_ref).max(), c=np.abs(ca - c_ref).max(), R=np.abs(Ra - R_ref).max(),
+                   scale=abs(s - 1.0))
+    return direct, aligned
+
+
 def _oracle_state(scene, res):
     p = O.Problem.from_scene(scene)
     return p, O.quat_to_rot(res["q"]), res["t"], res["X"]
@@ -40,6 +71,10 @@ def test_config0_f64_per_iteration_cost_matches_dense_oracle(balib):
     rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
     _say("max rel cost diff", rel.max())
     assert rel.max() <= 1e-9
+    direct, aligned = _state_diff(res, ref.R, ref.t, ref.X)
+    _say("final state vs oracle: direct", direct, "aligned", aligned)
+    assert max(direct["X"], direct["c"]) <= 1e-6 and direct["R"] <= 1e-7
+    assert max(aligned["X"], aligned["c"]) <= 1e-6 and aligned["R"] <= 1e-7
     # final state: the oracle's cost at the device's state equals the device's cost
     p, R, t, X = _oracle_state(s, res)
     assert abs(O.cost(p, R, t, X) - res["cost"]) <= 1e-9 * res["cost"]
@@ -60,6 +95,10 @@ def test_small_drive_f64_matches_schur_oracle_across_tiles(balib, flags):
     rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
     _say("max rel cost diff", rel.max(), res["pcg_iters"])
     assert rel.max() <= 1e-9
+    direct, aligned = _state_diff(res, ref.R, ref.t, ref.X)
+    _say("final state vs oracle: direct", direct, "aligned", aligned)
+    assert max(direct["X"], direct["c"]) <= 1e-6 and direct["R"] <= 1e-7
+    assert max(aligned["X"], aligned["c"]) <= 1e-6 and aligned["R"] <= 1e-7
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -129,6 +168,10 @@ def test_huber_outliers_f64_per_iteration_cost(balib):
     rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
     _say("huber f64 rel", rel.max())
     assert rel.max() <= 1e-9
+    direct, aligned = _state_diff(res, ref.R, ref.t, ref.X)
+    _say("final state vs oracle: direct", direct, "aligned", aligned)
+    assert max(direct["X"], direct["c"]) <= 1e-6 and direct["R"] <= 1e-7
+    assert max(aligned["X"], aligned["c"]) <= 1e-6 and aligned["R"] <= 1e-7
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16j", "bf16j"])
