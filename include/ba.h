@@ -113,6 +113,17 @@ typedef struct {
    other long kernels beside one.  A barrier that times out (about a second) stops the
    solve with status BA_STATUS_PCG_SYNC instead of waiting forever. */
 #define BA_FLAG_PCG_RESIDENT 16
+/* BA_FLAG_DENSE_SCHUR: form the Schur complement in its dense co-visibility form, used
+   by default when at most 1024 cameras are free, a point is seen by at least a quarter
+   of them on average, the observation pairs outnumber 32 per block of S and at least
+   half of the free-camera pairs share a point (scenes where every camera sees most
+   points).  S is held dense; for each observation the 6x3 block
+   Z = W V*^-1/2 (with the Cholesky factor of the point's damped block) is formed on
+   the fly, and S = U* - sum Z Z^T is accumulated tile by tile on the matrix cores
+   (MFMA in the compute type; FP16 / BF16 operands in BA_PREC_F16J / BA_PREC_BF16J), so
+   no per-pair lists are stored.  The flag forces the form for any problem of at most
+   1024 free cameras; BA_FLAG_PAIR_LISTS excludes it.  Not used for vehicle rigs. */
+#define BA_FLAG_DENSE_SCHUR 32
 
 typedef struct {
   int32_t iters;          /* iterations run                                               */
@@ -252,7 +263,8 @@ typedef struct {
   int32_t nnzb;           /* stored 6x6 blocks of S (both triangles and the diagonal)  */
   int32_t n_free_obs;     /* observations in free cameras                             */
   int32_t precision;
-  int32_t schur_form;     /* 1: point chunks staged in LDS, 0: per-block pair lists    */
+  int32_t schur_form;     /* 1: point chunks staged in LDS, 0: per-block pair lists,
+                             2: dense co-visibility form                             */
   int32_t n_chunks;       /* point chunks (chunk form)                                 */
   int64_t n_entries;      /* (chunk, block) partial sums (chunk form)                  */
   int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for many sparse
@@ -451,8 +463,12 @@ typedef struct {
 
 int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precision,
                      void *hip_stream, ba_server **out);
-/* Copy and analyse the problem and queue it.  BA_ENOMEM if its bytes alone
-   exceed the budget.  *ticket identifies it in ba_server_wait. */
+/* Check the sizes and options, copy the problem and queue it; its symbolic analysis
+   runs on the server's own threads, so the call returns after the copy.  BA_ENOMEM
+   here when the problem's observation, point and camera arrays alone exceed the
+   budget.  A problem whose content is invalid (as ba_create rejects it) or whose
+   analysed device bytes exceed the budget fails its ticket: ba_server_wait returns
+   BA_EINVAL or BA_ENOMEM.  *ticket identifies it in ba_server_wait. */
 int ba_server_submit(ba_server *s, const ba_problem_desc *d, const ba_options *opt,
                      int64_t *ticket);
 int ba_server_submit_pose(ba_server *s, const ba_pose_request *req, const ba_options *opt,

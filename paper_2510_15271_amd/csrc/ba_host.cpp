@@ -126,7 +126,8 @@ int check_options(const ba_options *o, bool pose_only) {
   if (!std::isfinite(o->huber_delta)) return fail(BA_EINVAL, "huber_delta must be finite");
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
-  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE | BA_FLAG_PCG_RESIDENT))
+  if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE | BA_FLAG_PCG_RESIDENT |
+                   BA_FLAG_DENSE_SCHUR))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   if (!pose_only) {
     if (!(o->prior_abs >= 0.0) || !std::isfinite(o->prior_abs))
@@ -293,7 +294,36 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
   return BA_OK;
 }
 
-int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges) {
+// Whether the free cameras' co-visibility is dense: at least half of the free-camera
+// pairs (a <= b) share a point.  One bitset of free cameras per camera, or-ed with
+// the camera set of every point it sees.
+static bool dense_covisibility(const Symbolic &sy) {
+  const int Cf = sy.Cf, P = sy.P;
+  const int W = (Cf + 63) / 64;
+  std::vector<uint64_t> cov((size_t)Cf * W, 0), pb(W);
+  std::vector<int32_t> cams;
+  for (int j = 0; j < P; ++j) {
+    cams.clear();
+    std::fill(pb.begin(), pb.end(), 0);
+    for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) {
+      const int a = sy.free_idx[sy.obs_cam[k]];
+      if (a < 0) continue;
+      pb[a >> 6] |= uint64_t(1) << (a & 63);
+      cams.push_back(a);
+    }
+    for (int a : cams) {
+      uint64_t *row = &cov[(size_t)a * W];
+      for (int w = 0; w < W; ++w) row[w] |= pb[w];
+    }
+  }
+  int64_t shared = 0;
+  for (int a = 0; a < Cf; ++a)
+    for (int b = a; b < Cf; ++b) shared += (cov[(size_t)a * W + (b >> 6)] >> (b & 63)) & 1;
+  return 2 * shared >= (int64_t)Cf * (Cf + 1) / 2;
+}
+
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges,
+            bool allow_dense) {
   if (!d) return fail(BA_EINVAL, "problem description is NULL");
   if (int e = check_options(opt, false)) return e;
   if (d->n_cams < 1) return fail(BA_EINVAL, "n_cams must be >= 1");
@@ -394,14 +424,24 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   // records: one per observation in a free camera
   int max_free = 0;
   sy.Nf = 0;
+  int64_t free_pairs = 0;
   for (int j = 0; j < P; ++j) {
     int nfj = 0;
     for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) nfj += sy.free_idx[sy.obs_cam[k]] >= 0;
     max_free = std::max(max_free, nfj);
     sy.Nf += nfj;
+    free_pairs += (int64_t)nfj * (nfj - 1) / 2;
   }
   const int prec = opt->precision;
-  sy.chunked = !(opt->flags & BA_FLAG_PAIR_LISTS) && max_free <= chunk_obs_cap(prec) &&
+  // the dense co-visibility form: forced by its flag, or chosen when tracks span at
+  // least a quarter of the free cameras on average, the pairs are many per block of S
+  // and most camera pairs share points (never with pair lists asked for)
+  sy.dense = allow_dense && !edges && Cf <= kDnMaxCams && !(opt->flags & BA_FLAG_PAIR_LISTS) &&
+             dense_form_available() &&
+             ((opt->flags & BA_FLAG_DENSE_SCHUR) ||
+              (4 * (int64_t)sy.Nf >= (int64_t)Cf * P && free_pairs >= 32 * ((int64_t)Cf * (Cf + 1) / 2) &&
+               dense_covisibility(sy)));
+  sy.chunked = !sy.dense && !(opt->flags & BA_FLAG_PAIR_LISTS) && max_free <= chunk_obs_cap(prec) &&
                max_free <= chunk_cam_cap(prec) &&
                chunk_lds_bytes(prec) <= device_lds_limit();
 
@@ -424,8 +464,8 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
       }
     }
   }
-  // record of each observation: point-major in the chunk form, camera-major otherwise
-  if (sy.chunked) {
+  // record of each observation: point-major in the chunk and dense forms, camera-major otherwise
+  if (sy.chunked || sy.dense) {
     sy.obs_rpos.assign(N, -1);
     int32_t r = 0;
     for (int64_t k = 0; k < N; ++k)
@@ -492,7 +532,14 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   sy.pairs.clear();
   sy.up_pair_start.assign(1, 0);
   sy.n_pairs = 0;
-  for (int a = 0; a < Cf; ++a) {
+  if (sy.dense) {  // every block of S is held: no pair enumeration
+    for (int a = 0; a < Cf; ++a) {
+      for (int b = a + 1; b < Cf; ++b) up_col.push_back(b);
+      up_rowptr[a + 1] = (int32_t)up_col.size();
+    }
+    sy.n_pairs = free_pairs;
+  }
+  for (int a = 0; a < Cf && !sy.dense; ++a) {
     touched.clear();
     for (int o = sy.cam_obs_start[a]; o < sy.cam_obs_start[a + 1]; ++o) {
       const int k = sy.cam_obs[o];
@@ -639,6 +686,26 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   if (sy.pcg_rows == kPcgRowsSparse && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
   sy.pcg_resident = (opt->flags & BA_FLAG_PCG_RESIDENT) &&
                     resident_pcg_fits(prec, sy.pcg_rows, (Cf + sy.pcg_rows - 1) / sy.pcg_rows, sy.max_tcols);
+  if (sy.dense) {
+    // first observation of each point in each camera tile: the tile's observations of
+    // the point are the range [ts[t], ts[t + 1]) (fixed cameras in it have no record)
+    const int nt = (Cf + kDnCams - 1) / kDnCams;
+    sy.dn_tiles = nt;
+    const int64_t pairs_t = (int64_t)nt * (nt + 1) / 2;
+    sy.dn_split = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>({(kDnTargetWgs + pairs_t - 1) / pairs_t, (int64_t)P / 1024, 64}));
+    sy.dn_ts.assign((size_t)P * (nt + 1), 0);
+    for (int j = 0; j < P; ++j) {
+      int32_t *ts = &sy.dn_ts[(size_t)j * (nt + 1)];
+      int t = 0;
+      for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) {
+        const int a = sy.free_idx[sy.obs_cam[k]];
+        if (a < 0) continue;
+        while (t <= a / kDnCams) ts[t++] = k;
+      }
+      while (t <= nt) ts[t++] = sy.pt_start[j + 1];
+    }
+  }
   if (sy.chunked)
     return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
   return BA_OK;
@@ -690,7 +757,11 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.blk_start = L.take(sy.blk_start.size() * 4 + 4);
   o.part_d = L.take((size_t)sy.n_dent * 54 * T + 16);
   o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
-  o.row_tot = L.take(sy.chunked ? Cf * 54 * 8 : 16);
+  o.row_tot = L.take(sy.chunked || sy.dense ? Cf * 54 * 8 : 16);
+  o.dn_ts = L.take(sy.dn_ts.size() * 4 + 4);
+  o.dn_pfac = L.take(sy.dense ? P * 9 * T : 16);
+  o.dn_part = L.take(sy.dense ? (size_t)sy.dn_tiles * (sy.dn_tiles + 1) / 2 * sy.dn_split * kDnRows * kDnRows * T
+                              : 16);
   o.pp_cam = L.take(sy.pp_cam.size() * sizeof(int2) + 8);
   o.pp_meas = L.take(sy.pp_meas.size() * 8 + 8);
   o.pp_w = L.take(sy.pp_w.size() * 8 + 8);
@@ -788,7 +859,11 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_ch = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
   pd.n_red_tiles = sy.chunked ? (sy.n_up + 3) / 4 : 0;  // four upper blocks (one wave each) per tile
   pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
-  pd.n_fsh_tiles = sy.chunked ? (Cf + 63) / 64 : 0;
+  pd.n_fsh_tiles = sy.chunked || sy.dense ? (Cf + 63) / 64 : 0;
+  pd.dense = sy.dense ? 1 : 0;
+  pd.dn_tiles = sy.dense ? sy.dn_tiles : 0;
+  pd.dn_pairs = sy.dense ? sy.dn_tiles * (sy.dn_tiles + 1) / 2 : 0;
+  pd.dn_split = sy.dense ? sy.dn_split : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
   pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
@@ -824,6 +899,9 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_d = ptr(off.part_d);
   pd.part_o = ptr(off.part_o);
   pd.row_tot = (double *)ptr(off.row_tot);
+  pd.dn_ts = (const int32_t *)ptr(off.dn_ts);
+  pd.dn_pfac = ptr(off.dn_pfac);
+  pd.dn_part = ptr(off.dn_part);
   pd.prior_abs = sy.prior_abs;
   pd.n_pp = (int32_t)sy.pp_cam.size();
   pd.prior_on = (sy.prior_abs > 0.0 || pd.n_pp > 0) ? 1 : 0;
@@ -955,6 +1033,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.ent_start, sy.ent_start.data(), sy.ent_start.size() * 4));
   chk(up(off.ent_items, sy.ent_items.data(), sy.ent_items.size() * 4));
   chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
+  chk(up(off.dn_ts, sy.dn_ts.data(), sy.dn_ts.size() * 4));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
   chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));
   chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));
@@ -1008,7 +1087,13 @@ void Batch::add(const ProbDev &pd, int slot_tag) {
   probs.push_back(pd);
   tags.push_back(slot_tag);
   for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[0].push_back(Tile{pi, t});
-  if (pd.chunked) {
+  if (pd.dense) {
+    for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[12].push_back(Tile{pi, t});
+    for (int a = 0; a < pd.Cf; ++a) tiles[13].push_back(Tile{pi, a});
+    for (int t = 0; t < pd.dn_pairs * pd.dn_split; ++t) tiles[14].push_back(Tile{pi, t});
+    for (int t = 0; t < pd.dn_pairs; ++t) tiles[15].push_back(Tile{pi, t});
+    for (int t = 0; t < pd.n_fsh_tiles; ++t) tiles[10].push_back(Tile{pi, t});
+  } else if (pd.chunked) {
     for (int c = 0; c < pd.n_ch; ++c) tiles[7].push_back(Tile{pi, c});
     for (int t = 0; t < pd.n_red_tiles; ++t) tiles[8].push_back(Tile{pi, t});
     for (int t = 0; t < pd.n_fin_tiles; ++t) tiles[9].push_back(Tile{pi, t});
@@ -1044,7 +1129,7 @@ int Batch::upload(hipStream_t s) {
   xcd_contiguous(tiles[2]);
   xcd_contiguous(tiles[7]);
   size_t need = probs.size() * sizeof(ProbDev);
-  constexpr int NL = 12;
+  constexpr int NL = 16;
   size_t offs[NL];
   for (int i = 0; i < NL; ++i) {
     need = (need + 255) & ~size_t(255);
@@ -1068,9 +1153,11 @@ int Batch::upload(hipStream_t s) {
   char *b = (char *)dev;
   plan.probs = (const ProbDev *)b;
   const Tile **dst[NL] = {&plan.pt, &plan.diag, &plan.off, &plan.pcg, &plan.cam, &plan.ctl,
-                          &plan.pp, &plan.ch, &plan.red, &plan.fin, &plan.fsh, &plan.pri};
+                          &plan.pp, &plan.ch, &plan.red, &plan.fin, &plan.fsh, &plan.pri,
+                          &plan.dpt, &plan.dcm, &plan.dsy, &plan.dre};
   int32_t *cnt[NL] = {&plan.n_pt, &plan.n_diag, &plan.n_off, &plan.n_pcg, &plan.n_cam, &plan.n_ctl,
-                      &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin, &plan.n_fsh, &plan.n_pri};
+                      &plan.n_pp, &plan.n_ch, &plan.n_red, &plan.n_fin, &plan.n_fsh, &plan.n_pri,
+                      &plan.n_dpt, &plan.n_dcm, &plan.n_dsy, &plan.n_dre};
   for (int i = 0; i < NL; ++i) {
     *dst[i] = (const Tile *)(b + offs[i]);
     *cnt[i] = (int32_t)tiles[i].size();
@@ -1212,7 +1299,9 @@ static int create_problem(const ba_problem_desc *d, const ba_options *opt, void 
   *out = nullptr;
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<ba_problem> p(new ba_problem());
-  if (int e = analyse(d, opt, p->sy, edges)) return e;
+  // before_upload builds a vehicle rig's second view, whose camera view keeps the
+  // chunk or pair-list form (the rig kernels read its per-block layout)
+  if (int e = analyse(d, opt, p->sy, edges, !before_upload)) return e;
   if (prepare_kernels() != 0) return fail(BA_EDEVICE, "no HIP device");
   p->bytes = DevProblem::bytes_for(p->sy, opt->precision, opt->max_iters);
   p->use_graph = (opt->flags & BA_FLAG_NO_GRAPH) == 0;
@@ -1999,7 +2088,7 @@ int ba_get_info(const ba_problem *p, ba_problem_info *out) {
   out->nnzb = p->sy.nnzb;
   out->n_free_obs = p->sy.Nf;
   out->precision = p->dp.precision;
-  out->schur_form = p->sy.chunked ? 1 : 0;
+  out->schur_form = p->sy.dense ? 2 : p->sy.chunked ? 1 : 0;
   out->n_chunks = p->sy.chunked ? (int32_t)p->sy.ch_pt.size() - 1 : 0;
   out->n_entries = (int64_t)p->sy.ent_tgt.size();
   out->pcg_rows = p->sy.pcg_rows;
@@ -2138,6 +2227,84 @@ int ba_get_kernel_times(const ba_problem *p, int32_t max_kernels, const char **n
 }  // extern "C"
 
 namespace bax {
+
+namespace {
+// Byte offsets of the result staging layout (each part 8-byte aligned).
+struct ResultLayout {
+  size_t st, pose[2], X[2], sq, nm, ic, pi, total;
+  ResultLayout(int C, int P, int npt, int max_iters) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      const size_t r = o;
+      o += (b + 7) & ~size_t(7);
+      return r;
+    };
+    st = take(sizeof(LMState));
+    for (int b = 0; b < 2; ++b) pose[b] = take(12 * (size_t)C * 8);
+    for (int b = 0; b < 2; ++b) X[b] = take(3 * (size_t)P * 8);
+    sq = take((size_t)npt * 8);
+    nm = take((size_t)npt * 4);
+    ic = take(((size_t)max_iters + 1) * 8);
+    pi = take((size_t)max_iters * 4);
+    total = o;
+  }
+};
+}  // namespace
+
+size_t DevProblem::result_bytes() const { return ResultLayout(C, P, view.n_pt_tiles, max_iters).total; }
+
+hipError_t DevProblem::enqueue_result(hipStream_t s, char *pinned) const {
+  const ResultLayout L(C, P, view.n_pt_tiles, max_iters);
+  hipError_t e = hipMemcpyAsync(pinned + L.st, view.st, sizeof(LMState), hipMemcpyDeviceToHost, s);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipMemcpyAsync(pinned + L.pose[b], view.pose[b], 12 * (size_t)C * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && P > 0) e = hipMemcpyAsync(pinned + L.X[b], view.X[b], 3 * (size_t)P * 8, hipMemcpyDeviceToHost, s);
+  }
+  const size_t npt = (size_t)view.n_pt_tiles;
+  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.sq, view.part_sq, npt * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.nm, view.part_masked, npt * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pinned + L.ic, view.iter_cost, ((size_t)max_iters + 1) * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pinned + L.pi, view.iter_pcg, (size_t)max_iters * 4, hipMemcpyDeviceToHost, s);
+  return e;
+}
+
+void DevProblem::finish_result(const char *pinned, ba_pose *poses_out, double *points_out, ba_report *rep) const {
+  const ResultLayout L(C, P, view.n_pt_tiles, max_iters);
+  LMState st;
+  std::memcpy(&st, pinned + L.st, sizeof(LMState));
+  const int cur = st.cur;
+  const double *pose = (const double *)(pinned + L.pose[cur]);
+  const double *X = (const double *)(pinned + L.X[cur]);
+  if (poses_out)
+    for (int i = 0; i < C; ++i) poses_out[i] = pose12_to_quat(pose + 12 * (size_t)i);
+  if (points_out)
+    for (int j = 0; j < P; ++j)
+      for (int m = 0; m < 3; ++m) points_out[3 * (size_t)pt_order[j] + m] = X[3 * (size_t)j + m];
+  if (!rep) return;
+  double *ic = rep->iter_cost;
+  int32_t *pi = rep->pcg_iters;
+  std::memset(rep, 0, sizeof(*rep));
+  rep->iter_cost = ic;
+  rep->pcg_iters = pi;
+  rep->iters = st.iter;
+  rep->accepted = st.accepted;
+  rep->status = st.status;
+  rep->cost0 = st.cost0;
+  rep->cost = st.cost;
+  rep->lambda = st.lambda;
+  const double *sq = (const double *)(pinned + L.sq);
+  const int32_t *nm = (const int32_t *)(pinned + L.nm);
+  double tot = 0.0;
+  int64_t masked = 0;
+  for (int i = 0; i < view.n_pt_tiles; ++i) {
+    tot += sq[i];
+    masked += nm[i];
+  }
+  rep->n_masked = (int32_t)masked;
+  rep->rms_px = (n_active - masked) > 0 ? std::sqrt(tot / (double)(n_active - masked)) : 0.0;
+  if (ic) std::memcpy(ic, pinned + L.ic, ((size_t)st.iter + 1) * 8);
+  if (pi && st.iter > 0) std::memcpy(pi, pinned + L.pi, (size_t)st.iter * 4);
+}
 
 int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
                             bool solved, double solve_ms, double setup_ms) {

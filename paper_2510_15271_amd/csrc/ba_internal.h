@@ -42,6 +42,15 @@ inline size_t chunk_lds_bytes(int precision) {
          (size_t)chunk_cam_cap(precision) * (9 * T + 4);
 }
 
+// Dense co-visibility Schur form: cameras in tiles of kDnCams (kDnRows rows of S);
+// one workgroup per (tile pair, point range) accumulates Z_a Z_b^T over its points,
+// where the 6x3 block Z_aj = W_aj L_j^-T (V*_j = L_j L_j^T) exists for each
+// observation, so that sum_j Z_aj Z_bj^T = sum_j W_aj V*_j^-1 W_bj^T.
+constexpr int kDnCams = 16;
+constexpr int kDnRows = 6 * kDnCams;
+constexpr int kDnMaxCams = 1024;     // free cameras beyond which the dense form is not used
+constexpr int kDnTargetWgs = 256;   // workgroups per problem the point ranges aim at
+
 constexpr double kLambdaMin = 1e-12;
 constexpr double kLambdaMax = 1e16;
 constexpr double kDMin = 1e-6;
@@ -89,7 +98,14 @@ struct ProbDev {
   int32_t n_ch;          // point chunks (chunk form)
   int32_t n_red_tiles;   // reduction tiles (chunk form): four upper blocks each
   int32_t n_fin_tiles;   // camera-row tiles (chunk form): one camera each
-  int32_t n_fsh_tiles;   // camera-finish tiles (chunk form): 64 cameras each
+  int32_t n_fsh_tiles;   // camera-finish tiles (chunk and dense forms): 64 cameras each
+  int32_t dense;         // 1: dense co-visibility Schur form
+  int32_t dn_tiles;      // camera tiles (kDnCams free cameras each)
+  int32_t dn_pairs;      // tile pairs (a <= b)
+  int32_t dn_split;      // point ranges per tile pair
+  const int32_t *dn_ts;  // [P][dn_tiles + 1] first observation of each point in each camera tile
+  void *dn_pfac;         // [P][9] T: L^-T (upper: 00 01 02 11 12 22) and h = L^-1 g_p of V*_j = L L^T
+  void *dn_part;         // [dn_pairs][dn_split][kDnRows^2] T: Z Z^T over one point range
   // static structure
   const void *K;                  // [C][4] T: fx, fy, cx, cy
   const int32_t *free_idx;        // [C] free-camera index or -1
@@ -210,6 +226,10 @@ struct BatchPlan {
   const ProbDev *probs;
   const Tile *pt, *diag, *off, *pcg, *cam, *ctl, *pp, *ch, *red, *fin, *fsh, *pri;
   int32_t n_pt, n_diag, n_off, n_pcg, n_cam, n_ctl, n_pp, n_ch, n_red, n_fin, n_fsh, n_pri;
+  // dense form: point tiles (prep), free cameras (camera sums), (tile pair, range)
+  // workgroups (Z Z^T) and tile pairs (reduction)
+  const Tile *dpt, *dcm, *dsy, *dre;
+  int32_t n_dpt, n_dcm, n_dsy, n_dre;
   int32_t n_probs;
   int32_t pcg_rows;  // rows per PCG tile shared by every problem of the batch, 0 if mixed
   ProbDev single;  // host copy of the descriptor when n_probs == 1 (passed by value to short kernels)
@@ -240,7 +260,8 @@ enum KernelId {
   K_LINEARIZE = 0, K_POINT_PREP, K_SCHUR_DIAG, K_SCHUR_OFF, K_PCG_SPMV, K_PCG_UPDATE,
   K_CAM_UPDATE, K_POINT_TRIAL, K_LM_CONTROL, K_EVAL, K_POSE_GN, K_PCG_CG, K_SCHUR_CHUNK,
   K_SCHUR_REDUCE, K_SCHUR_ROWS, K_SCHUR_FINISH, K_PRIOR_LIN, K_PRIOR_APPLY, K_CULL, K_RIG_BLOCKS,
-  K_RIG_ROWS, K_RIG_UPDATE, K_PRIOR_COST, K_NUM_KERNELS
+  K_RIG_ROWS, K_RIG_UPDATE, K_PRIOR_COST, K_DENSE_PREP, K_DENSE_CAMS, K_DENSE_SCHUR, K_DENSE_REDUCE,
+  K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
 
@@ -253,6 +274,8 @@ size_t compute_bytes(int precision);
 int prepare_kernels();
 // Dynamic LDS a workgroup may use on the current device (bytes).
 size_t device_lds_limit();
+// Whether the dense co-visibility form can run on the current device.
+bool dense_form_available();
 // Whether the PCG runs in its one-reduction form (one launch per iteration) for
 // a plan whose longest tile column list is max_tcols.
 bool one_reduction_pcg(int precision, int max_tcols);

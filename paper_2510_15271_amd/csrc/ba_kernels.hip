@@ -41,7 +41,7 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "linearize", "point_prep", "schur_diag", "schur_off", "pcg_spmv", "pcg_update",
     "cam_update", "point_trial", "lm_control", "eval", "pose_gn", "pcg_cg", "schur_chunk",
     "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull", "rig_blocks",
-    "rig_rows", "rig_update", "prior_cost"};
+    "rig_rows", "rig_update", "prior_cost", "dense_prep", "dense_cams", "dense_schur", "dense_reduce"};
 
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
@@ -3325,6 +3325,365 @@ __global__ __launch_bounds__(kPoseThreads) void k_pose_gn(PoseDev *__restrict__ 
   if (threadIdx.x == 0) rq.status = s_bad;
 }
 
+// ------------------------------------------------------------------ dense co-visibility form
+// For scenes where every camera sees most points, S is dense and the pair lists of the
+// sparse forms would outgrow memory (a point seen by L free cameras has L (L - 1) / 2
+// pairs).  This form never lists pairs.  With V*_j = L_j L_j^T (Cholesky of the damped
+// point block) each observation's 6x3 block Z_aj = W_aj L_j^-T, W_aj = J_c^T J_p, gives
+//   sum_j W_aj V*_j^-1 W_bj^T = sum_j Z_aj Z_bj^T   and   sum_j W_aj V*_j^-1 g_p,j = sum_j Z_aj h_j
+// with h_j = L_j^-1 g_p,j: S - U* is a Gram matrix over the points' three directions,
+// a dense contraction that runs on the matrix cores.  Workgroup (tile pair (ta, tb),
+// point range) builds Z for its 16 + 16 cameras and 32 points at a time in LDS and
+// accumulates the 96 x 96 product Z_ta Z_tb^T with MFMA; the ranges' partial products
+// are summed in a fixed order by k_dense_reduce.
+
+// Per point: V* = V + lambda D_p, its inverse (back-substitution), and L^-T (upper:
+// 00 01 02 11 12 22) and h = L^-1 g_p of its Cholesky factor, in FP64.
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_prep(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int j = tl.idx * kPtTile + (int)threadIdx.x;
+  if (j >= pd.P) return;
+  const double lam = st->lambda;
+  const T *V = (const T *)pd.V;
+  const T *Dp = (const T *)pd.Dp;
+  const T *gp = (const T *)pd.gp;
+  double u[6], o[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) u[i] = (double)V[6 * (size_t)j + i];
+  u[0] += lam * (double)Dp[3 * (size_t)j + 0];
+  u[3] += lam * (double)Dp[3 * (size_t)j + 1];
+  u[5] += lam * (double)Dp[3 * (size_t)j + 2];
+  inv_sym3(u, o);
+  T *Vinv = (T *)pd.Vinv + 6 * (size_t)j;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) Vinv[i] = T(o[i]);
+  const double l00 = sqrt(fmax(u[0], 1e-300));
+  const double l10 = u[1] / l00, l20 = u[2] / l00;
+  const double l11 = sqrt(fmax(u[3] - l10 * l10, 1e-300));
+  const double l21 = (u[4] - l20 * l10) / l11;
+  const double l22 = sqrt(fmax(u[5] - l20 * l20 - l21 * l21, 1e-300));
+  // M = L^-1 (lower triangular)
+  const double m00 = 1.0 / l00, m11 = 1.0 / l11, m22 = 1.0 / l22;
+  const double m10 = -l10 * m00 * m11, m21 = -l21 * m11 * m22;
+  const double m20 = -(l20 * m00 + l21 * m10) * m22;
+  const double g0 = (double)gp[3 * (size_t)j], g1 = (double)gp[3 * (size_t)j + 1], g2 = (double)gp[3 * (size_t)j + 2];
+  T *pf = (T *)pd.dn_pfac + 9 * (size_t)j;
+  pf[0] = T(m00);
+  pf[1] = T(m10);
+  pf[2] = T(m20);
+  pf[3] = T(m11);
+  pf[4] = T(m21);
+  pf[5] = T(m22);
+  pf[6] = T(m00 * g0);
+  pf[7] = T(m10 * g0 + m11 * g1);
+  pf[8] = T(m20 * g0 + m21 * g1 + m22 * g2);
+}
+
+// Z (6x3) of one observation: W = J_c^T J_p times the point's L^-T (lt, upper).
+template <class T>
+__device__ inline void dense_z(const T Jc[12], const T Jp[6], const T lt[6], T Z[18]) {
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const T w0 = Jc[m] * Jp[0] + Jc[6 + m] * Jp[3];
+    const T w1 = Jc[m] * Jp[1] + Jc[6 + m] * Jp[4];
+    const T w2 = Jc[m] * Jp[2] + Jc[6 + m] * Jp[5];
+    Z[3 * m] = w0 * lt[0];
+    Z[3 * m + 1] = w0 * lt[1] + w1 * lt[3];
+    Z[3 * m + 2] = w0 * lt[2] + w1 * lt[4] + w2 * lt[5];
+  }
+}
+
+// Camera sums of the dense form, one workgroup per free camera over its observations
+// (camera-major list): U (21), g_c (6) and sum_j Z_aj h_j (6), per thread in the
+// compute type, then in FP64 in a fixed order into the camera's row sums.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_dense_cams(const ProbDev *__restrict__ probs,
+                                                    const Tile *__restrict__ tiles) {
+  constexpr bool k16 = sizeof(S) == 2;
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int a = tl.idx;
+  const int cam = pd.free_cam[a];
+  const double *pose = pd.pose[st->cur] + 12 * cam;
+  T R[9];
+  load_rot(pose, R);
+  const T *K = (const T *)pd.K + 4 * cam;
+  const T delta = T(st->huber_delta);
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *pf = (const T *)pd.dn_pfac;
+  T acc[33];
+#pragma unroll
+  for (int i = 0; i < 33; ++i) acc[i] = T(0);
+  for (int o = pd.cam_obs_start[a] + (int)threadIdx.x; o < pd.cam_obs_start[a + 1]; o += 256) {
+    const int k = pd.cam_obs[o];
+    const int j = pd.obs_pt[k];
+    const LinRec<T, S> rec = lin[pd.obs_rpos[k]];
+    T f[7], Jc[12], Jp[6], lt[6], hv[3], Z[18];
+    decode(rec, f);
+    jc_from(f, Jc);
+    jp_from(f, R, Jp);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) lt[i] = pf[9 * (size_t)j + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) hv[i] = pf[9 * (size_t)j + 6 + i];
+    int u = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc[r] * Jc[cc] + Jc[6 + r] * Jc[6 + cc];
+    if (k16) {
+      // 16-bit storage: the gradient from FP32 Jacobians at the linearisation state
+      double xd, yd, zd;
+      transform(pose, pd.X[st->cur] + 3 * (size_t)j, xd, yd, zd);
+      const T xv = T(xd), yv = T(yd), zv = T(zd);
+      const T *uv = (const T *)pd.obs_uv + 2 * (size_t)k;
+      T r0, r1;
+      if (pd.obs_act[k] && residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+        const T w = huber_w(r0 * r0 + r1 * r1, delta);
+        T Jg[12], Jpg[6];
+        jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc[21 + r] += w * (Jg[r] * r0 + Jg[6 + r] * r1);
+      }
+    } else {
+      const T e0 = rec.e[0], e1 = rec.e[1];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) acc[21 + r] += Jc[r] * e0 + Jc[6 + r] * e1;
+    }
+    dense_z(Jc, Jp, lt, Z);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc[27 + m] += Z[3 * m] * hv[0] + Z[3 * m + 1] * hv[1] + Z[3 * m + 2] * hv[2];
+  }
+  __shared__ double s_t[4][33];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 33; ++i) {
+    const double v = wave_sum((double)acc[i]);
+    if (lane == 0) s_t[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 33) {
+    const int i = threadIdx.x;
+    const double v = s_t[0][i] + s_t[1][i] + s_t[2][i] + s_t[3][i];
+    // row sums: U (0..20), sum Y W^T (21..41, from k_dense_reduce), g_c (42..47), Y g_p (48..53)
+    pd.row_tot[54 * (size_t)a + (i < 21 ? i : 21 + i)] = v;
+  }
+}
+
+// Operand type E of the products, k-values per MFMA instruction KI and points per chunk
+// PC of each (compute, storage) pair: FP64 and FP32 products in their own type
+// (16x16x4), FP16 / BF16 storage with 16-bit operands (16x16x32, FP32 accumulation).
+typedef float dn_f4 __attribute__((ext_vector_type(4)));
+typedef double dn_d4 __attribute__((ext_vector_type(4)));
+typedef _Float16 dn_h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 dn_b8 __attribute__((ext_vector_type(8)));
+template <class T, class S>
+struct DnMma;
+template <>
+struct DnMma<double, double> {
+  using E = double;
+  using V = dn_d4;
+  static constexpr int KI = 4, PC = 16;
+  static constexpr bool row_major_d = false;  // D[i][j]: lane j + 16 (i % 4), register i / 4
+  __device__ static V mma(const E *a, const E *b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(*a, *b, c, 0, 0, 0); }
+};
+template <>
+struct DnMma<float, float> {
+  using E = float;
+  using V = dn_f4;
+  static constexpr int KI = 4, PC = 32;
+  static constexpr bool row_major_d = true;   // D[i][j]: lane j + 16 (i / 4), register i % 4
+  __device__ static V mma(const E *a, const E *b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0); }
+};
+template <>
+struct DnMma<float, _Float16> {
+  using E = _Float16;
+  using V = dn_f4;
+  static constexpr int KI = 32, PC = 32;
+  static constexpr bool row_major_d = true;
+  __device__ static V mma(const E *a, const E *b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const dn_h8 *)a, *(const dn_h8 *)b, c, 0, 0, 0);
+  }
+};
+template <>
+struct DnMma<float, bf16s> {
+  using E = __bf16;
+  using V = dn_f4;
+  static constexpr int KI = 32, PC = 32;
+  static constexpr bool row_major_d = true;
+  __device__ static V mma(const E *a, const E *b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const dn_b8 *)a, *(const dn_b8 *)b, c, 0, 0, 0);
+  }
+};
+// Dynamic LDS of k_dense_schur: two Z tiles of 3 PC k-values by kDnRows rows.
+template <class T, class S>
+constexpr size_t dn_lds_bytes() {
+  return 2 * (size_t)3 * DnMma<T, S>::PC * kDnRows * sizeof(typename DnMma<T, S>::E);
+}
+
+// Tile pair (ta <= tb) of a pair index, row-major over the upper triangle of nt tiles.
+__device__ inline void dn_pair(int pair, int nt, int &ta, int &tb) {
+  int a = 0, rem = pair;
+  while (rem >= nt - a) {
+    rem -= nt - a;
+    ++a;
+  }
+  ta = a;
+  tb = a + rem;
+}
+
+// One (tile pair, point range): Z tiles in LDS laid out [k / KI][row][k % KI] so that
+// the 64 lanes of an operand load read one contiguous run; four waves, each a 48 x 48
+// quarter of the 96 x 96 product (3 x 3 MFMA tiles of 16 x 16).
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__ probs,
+                                                     const Tile *__restrict__ tiles) {
+  using M = DnMma<T, S>;
+  using E = typename M::E;
+  using V = typename M::V;
+  constexpr int KI = M::KI, PC = M::PC, K = 3 * PC, NKS = K / KI, SUB = 256 / PC, KL = KI / 4;
+  extern __shared__ __align__(16) double s_dyn[];
+  E *za = (E *)s_dyn;       // [NKS][kDnRows][KI]
+  E *zb = za + K * kDnRows;  // the same for tile tb (unused when ta == tb)
+  __shared__ T s_R[2][kDnCams][9];
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  const int pair = tl.idx / pd.dn_split, split = tl.idx - pair * pd.dn_split;
+  int ta, tb;
+  dn_pair(pair, pd.dn_tiles, ta, tb);
+  const bool diag = ta == tb;
+  const int nsides = diag ? 1 : 2;
+  const int nt1 = pd.dn_tiles + 1;
+  const int t = threadIdx.x;
+  if (t < 2 * kDnCams) {
+    const int side = t / kDnCams, la = t - kDnCams * side;
+    const int a = (side ? tb : ta) * kDnCams + la;
+    T R[9];
+    if (a < pd.Cf) {
+      load_rot(pd.pose[st->cur] + 12 * pd.free_cam[a], R);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s_R[side][la][i] = R[i];
+  }
+  const int j0 = (int)((int64_t)pd.P * split / pd.dn_split);
+  const int j1 = (int)((int64_t)pd.P * (split + 1) / pd.dn_split);
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *pf = (const T *)pd.dn_pfac;
+  const int lane = t & 63, wv = t >> 6;
+  const int rb0 = 3 * (wv >> 1), cb0 = 3 * (wv & 1);
+  const int li = lane & 15, lq = lane >> 4;
+  V acc[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[r][c][e] = 0;
+  for (int jc = j0; jc < j1; jc += PC) {
+    __syncthreads();  // the previous chunk's products are done (and s_R is visible)
+    for (int i = t; i < nsides * K * kDnRows; i += 256) za[i] = E(0);
+    __syncthreads();
+    {
+      const int jl = t / SUB, sub = t - SUB * (t / SUB);
+      const int j = jc + jl;
+      if (j < j1) {
+        T lt[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) lt[i] = pf[9 * (size_t)j + i];
+        for (int side = 0; side < nsides; ++side) {
+          const int tt = side ? tb : ta;
+          E *z = side ? zb : za;
+          const int k0 = pd.dn_ts[(size_t)j * nt1 + tt], k1 = pd.dn_ts[(size_t)j * nt1 + tt + 1];
+          for (int k = k0 + sub; k < k1; k += SUB) {
+            const int rp = pd.obs_rpos[k];
+            if (rp < 0) continue;  // a fixed camera: no record, no row
+            const int la = pd.free_idx[pd.obs_cam[k]] - tt * kDnCams;
+            T f[7], Jc[12], Jp[6], Z[18];
+            decode(lin[rp], f);
+            jc_from(f, Jc);
+            jp_from(f, &s_R[side][la][0], Jp);
+            dense_z(Jc, Jp, lt, Z);
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const int kk = 3 * jl + c, row = 6 * la + m;
+                z[((kk / KI) * kDnRows + row) * KI + (kk % KI)] = E(Z[3 * m + c]);
+              }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const E *zbb = diag ? za : zb;
+    for (int ks = 0; ks < NKS; ++ks) {
+      const E *ab = za + (ks * kDnRows + li) * KI + lq * KL;
+      const E *bb = zbb + (ks * kDnRows + li) * KI + lq * KL;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          acc[r][c] = M::mma(ab + 16 * (rb0 + r) * KI, bb + 16 * (cb0 + c) * KI, acc[r][c]);
+    }
+  }
+  T *out = (T *)pd.dn_part + (size_t)tl.idx * kDnRows * kDnRows;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * (rb0 + r) + (M::row_major_d ? 4 * lq + e : lq + 4 * e);
+        const int col = 16 * (cb0 + c) + li;
+        out[row * kDnRows + col] = T(acc[r][c][e]);
+      }
+}
+
+// One tile pair: its ranges' partial products summed in FP64 in range order; blocks
+// (a < b) go to S as -sum and its transpose, diagonal blocks' upper halves to the
+// camera's row sums (sum Y W^T), finished with the other sums by k_schur_finish.
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_reduce(const ProbDev *__restrict__ probs,
+                                                      const Tile *__restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const ProbDev &pd = probs[tl.prob];
+  const LMState *st = pd.st;
+  if (!lm_active(st)) return;
+  int ta, tb;
+  dn_pair(tl.idx, pd.dn_tiles, ta, tb);
+  const int ns = pd.dn_split;
+  constexpr int NE = kDnRows * kDnRows;
+  const T *part = (const T *)pd.dn_part + (size_t)tl.idx * ns * NE;
+  T *Sv = (T *)pd.S;
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    const int R = e / kDnRows, Cc = e - kDnRows * (e / kDnRows);
+    const int a = ta * kDnCams + R / 6, b = tb * kDnCams + Cc / 6;
+    if (a >= pd.Cf || b >= pd.Cf || a > b) continue;  // a > b: written as a transpose
+    double sum = 0.0;
+    for (int x = 0; x < ns; ++x) sum += (double)part[(size_t)x * NE + e];
+    const int r = R % 6, c = Cc % 6;
+    if (a == b) {
+      if (r <= c) pd.row_tot[54 * (size_t)a + 21 + 6 * r - r * (r - 1) / 2 + (c - r)] = sum;
+    } else {
+      const T v = T(-sum);
+      Sv[36 * ((size_t)pd.S_rowptr[a] + b) + 6 * r + c] = v;
+      Sv[36 * ((size_t)pd.S_rowptr[b] + a) + 6 * c + r] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 namespace {
 struct Timed {
@@ -3345,6 +3704,8 @@ struct Timed {
 static size_t g_fused_lds = 48 * 1024;
 // Per-workgroup LDS of the device (0 when the chunk form cannot be used).
 static size_t g_lds_limit = 0;
+// Whether the dense form's product kernel may use its LDS on this device.
+static bool g_dense_ok = false;
 
 int prepare_kernels() {
   static bool done = false;
@@ -3382,9 +3743,26 @@ int prepare_kernels() {
       g_lds_limit = 0;  // chunk form unavailable on this device
     }
   }
+  // the dense form's product kernel
+  const void *dense_kernels[4] = {(const void *)k_dense_schur<double, double>,
+                                  (const void *)k_dense_schur<float, float>,
+                                  (const void *)k_dense_schur<float, _Float16>,
+                                  (const void *)k_dense_schur<float, bf16s>};
+  const size_t dense_lds[4] = {dn_lds_bytes<double, double>(), dn_lds_bytes<float, float>(),
+                               dn_lds_bytes<float, _Float16>(), dn_lds_bytes<float, bf16s>()};
+  g_dense_ok = true;
+  for (int p = 0; p < 4; ++p)
+    if (dense_lds[p] + 4096 > (size_t)lim ||
+        hipFuncSetAttribute(dense_kernels[p], hipFuncAttributeMaxDynamicSharedMemorySize, (int)dense_lds[p]) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      g_dense_ok = false;
+    }
   done = true;
   return 0;
 }
+
+bool dense_form_available() { return prepare_kernels() == 0 && g_dense_ok; }
 
 size_t device_lds_limit() {
   if (prepare_kernels() != 0) return 0;
@@ -3436,6 +3814,22 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   if (bp.n_red) {
     Timed t(tm, K_SCHUR_REDUCE, s);
     k_schur_reduce<T><<<bp.n_red, 256, 0, s>>>(bp.probs, bp.red);
+  }
+  if (bp.n_dpt) {
+    Timed t(tm, K_DENSE_PREP, s);
+    k_dense_prep<T><<<bp.n_dpt, 256, 0, s>>>(bp.probs, bp.dpt);
+  }
+  if (bp.n_dcm) {
+    Timed t(tm, K_DENSE_CAMS, s);
+    k_dense_cams<T, S><<<bp.n_dcm, 256, 0, s>>>(bp.probs, bp.dcm);
+  }
+  if (bp.n_dsy) {
+    Timed t(tm, K_DENSE_SCHUR, s);
+    k_dense_schur<T, S><<<bp.n_dsy, 256, dn_lds_bytes<T, S>(), s>>>(bp.probs, bp.dsy);
+  }
+  if (bp.n_dre) {
+    Timed t(tm, K_DENSE_REDUCE, s);
+    k_dense_reduce<T><<<bp.n_dre, 256, 0, s>>>(bp.probs, bp.dre);
   }
   if (bp.n_fin) {
     Timed t(tm, K_SCHUR_ROWS, s);
@@ -3847,22 +4241,6 @@ hipError_t launch_triangulate(int n_pts, const int32_t *pt_start, const int32_t 
                               const double *poses, int method, double *X, uint8_t *ok, hipStream_t s) {
   if (n_pts <= 0) return hipSuccess;
   k_triangulate<<<(n_pts + 255) / 256, 256, 0, s>>>(n_pts, pt_start, cam, xy, poses, method, X, ok);
-  return hipGetLastError();
-}
-
-// Iteration counter of every problem of a batch, in batch order.
-__global__ void k_gather_iters(const ProbDev *__restrict__ probs, const Tile *__restrict__ ctl, int n,
-                               int32_t *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const LMState *st = probs[ctl[i].prob].st;
-    out[i] = st->halted ? st->max_iters : st->iter;  // a halted solve is finished
-  }
-}
-
-hipError_t launch_gather_iters(const BatchPlan &bp, int32_t *out, hipStream_t s) {
-  if (!bp.n_ctl) return hipSuccess;
-  k_gather_iters<<<(bp.n_ctl + 255) / 256, 256, 0, s>>>(bp.probs, bp.ctl, bp.n_ctl, out);
   return hipGetLastError();
 }
 

@@ -35,7 +35,10 @@ struct Symbolic {
   std::vector<int32_t> obs_order; // internal observation -> caller's observation index
   int32_t Nf = 0;                 // observations in free cameras (records)
   int64_t n_pairs = 0;            // observation pairs of one point in two free cameras
-  bool chunked = false;           // point-chunk Schur form (else pair lists)
+  bool chunked = false;           // point-chunk Schur form (else pair lists or dense)
+  bool dense = false;             // dense co-visibility Schur form
+  int32_t dn_tiles = 0, dn_split = 0;
+  std::vector<int32_t> dn_ts;     // [P][dn_tiles + 1] (dense form)
   // pair-list form
   std::vector<int32_t> cam_obs, cam_obs_start;
   std::vector<int32_t> up_pair_start;
@@ -70,13 +73,15 @@ struct GraphEdges {
 };
 // Symbolic analysis of a problem.  With edges, the description holds the nodes only
 // (no points or observations) and the edges replace the sequential prior pairs.
-int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges = nullptr);
+// allow_dense: the dense co-visibility form may be chosen (not for the cameras of a rig).
+int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const GraphEdges *edges = nullptr,
+            bool allow_dense = true);
 
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos, obs_act;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
-  size_t part_d, part_o, row_tot;
+  size_t part_d, part_o, row_tot, dn_ts, dn_pfac, dn_part;
   size_t pp_cam, pp_meas, pp_w, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
@@ -109,13 +114,21 @@ struct DevProblem {
   LMState fresh_state() const;
   int read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
                   bool solved, double solve_ms, double setup_ms);
+  // The same result without a host wait: enqueue_result queues on stream s the copies
+  // of everything the report needs (the state, both pose and point buffers, the
+  // evaluation partials and the per-iteration arrays) into `pinned`, a page-locked
+  // buffer of result_bytes(); once they have landed, finish_result builds the outputs
+  // from it alone.
+  size_t result_bytes() const;
+  hipError_t enqueue_result(hipStream_t s, char *pinned) const;
+  void finish_result(const char *pinned, ba_pose *poses_out, double *points_out, ba_report *rep) const;
 };
 
 // Tile lists of a set of problems, mirrored on the device.
 struct Batch {
   std::vector<ProbDev> probs;
   std::vector<int> tags;
-  std::vector<Tile> tiles[12];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin, fsh, pri
+  std::vector<Tile> tiles[16];  // pt, diag, off, pcg, cam, ctl, pp, ch, red, fin, fsh, pri, dpt, dcm, dsy, dre
   std::vector<char> host;
   void *dev = nullptr;
   size_t cap = 0;

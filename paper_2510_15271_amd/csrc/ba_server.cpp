@@ -2,13 +2,18 @@
 // requests under a device-memory budget.
 //
 // The server owns one device block of budget bytes, carved by a first-fit
-// allocator.  A scheduler thread repeats: admit queued requests in arrival
-// order while a slot is free and their bytes fit; launch one LM iteration for
-// every admitted problem at once (one launch per kernel for the whole batch);
-// run all admitted pose-only requests in one launch; read back which problems
-// finished; evaluate and download those, free their bytes and slots.  A
-// problem's kernels read only its own data and reduce in a fixed order, so its
-// result does not depend on the batch it shares.
+// allocator.  A submitted problem is validated and copied in the caller's
+// thread; its symbolic analysis runs on a pool of host threads.  A scheduler
+// thread repeats: admit analysed problems in ticket order while a slot is free
+// and their bytes fit; launch one LM iteration for every admitted problem at
+// once (one launch per kernel for the whole batch); run all queued pose-only
+// requests in one launch.  Each launch sequence advances every problem it holds
+// by exactly one iteration, so the host counts iterations itself and never waits
+// on the device to learn which problems finished: it queues their evaluation
+// and result copies into page-locked buffers behind an event, frees their bytes
+// and slots, and hands the results over once the event has passed.  At most two
+// launch sequences are in flight.  A problem's kernels read only its own data
+// and reduce in a fixed order, so its result does not depend on the batch it shares.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +24,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -29,7 +35,6 @@
 
 namespace bax {
 
-hipError_t launch_gather_iters(const BatchPlan &bp, int32_t *out, hipStream_t s);
 
 namespace {
 
@@ -96,13 +101,17 @@ struct Req {
   double t_submit = 0, t_done = 0;
   bool done = false;
   int rc = BA_OK;
-  // bundle adjustment
-  Symbolic sy;
+  std::string err;
+  // bundle adjustment: the caller's arrays, copied at submission
+  int32_t n_cams = 0, n_pts = 0, K_per_cam = 0;
   std::vector<ba_intrinsics> K;
-  int32_t K_per_cam = 0;
   std::vector<ba_pose> poses;
+  std::vector<uint8_t> fixed;
   std::vector<double> pts;
+  std::vector<ba_obs> obs;
+  Symbolic sy;
   DevProblem dp;
+  int steps = 0;  // LM iterations launched for it
   // pose-only
   ba_pose_request preq{};
   std::vector<double> pX, puv;
@@ -112,8 +121,45 @@ struct Req {
   std::vector<double> iter_cost;
   std::vector<int32_t> iter_pcg;
   ba_report rep{};
+
+  ba_problem_desc desc() const {
+    ba_problem_desc d{};
+    d.n_cams = n_cams;
+    d.K = K.data();
+    d.K_per_cam = K_per_cam;
+    d.poses = poses.data();
+    d.cam_fixed = fixed.empty() ? nullptr : fixed.data();
+    d.n_pts = n_pts;
+    d.points_xyz = pts.data();
+    d.n_obs = (int64_t)obs.size();
+    d.obs = obs.data();
+    return d;
+  }
 };
 using ReqP = std::shared_ptr<Req>;
+
+// Page-locked host memory for result copies, reused across requests.
+struct Pinned {
+  char *p = nullptr;
+  size_t n = 0;
+};
+
+// Result copies of the problems that finished in one launch sequence, in flight.
+struct Completion {
+  std::vector<ReqP> reqs;
+  std::vector<Pinned> bufs;
+  hipEvent_t ev = nullptr;
+};
+
+constexpr int kLookahead = 2;  // launch sequences the scheduler may run ahead of the device
+
+// A lower bound of the device bytes a problem needs, from its sizes alone: its
+// observation arrays and its point and camera state.
+size_t min_problem_bytes(int64_t n_obs, int32_t n_pts, int32_t n_cams, int precision) {
+  const size_t T = compute_bytes(precision);
+  return (size_t)n_obs * (4 + 4 + 2 * T + 4 + 1) + (size_t)n_pts * (3 * 8 * 3 + 15 * T) +
+         (size_t)n_cams * 12 * 8 * 3;
+}
 
 }  // namespace
 }  // namespace bax
@@ -122,13 +168,16 @@ using namespace bax;
 
 struct ba_server {
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<ReqP> queue;
+  std::condition_variable cv_work, cv_done, cv_ana;
+  std::deque<ReqP> ana_q;            // submitted problems awaiting their analysis
+  int analysing = 0;                 // problems being analysed now
+  std::map<int64_t, ReqP> ready;     // analysed problems, admitted in ticket order
+  std::deque<ReqP> pose_q;
   std::vector<ReqP> active;
+  std::deque<Completion> completing;  // scheduler thread only
   std::unordered_map<int64_t, ReqP> tickets;
   Arena arena;
   void *mem = nullptr;
-  int32_t *d_iters = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int max_slots = 1;
@@ -137,7 +186,11 @@ struct ba_server {
   int64_t next_ticket = 1;
   bool stop = false;
   std::thread th;
-  Batch batch;
+  std::vector<std::thread> ana_th;
+  Batch batch, fin_batch;
+  hipEvent_t ev_step[kLookahead] = {};
+  int64_t n_steps = 0;
+  std::vector<Pinned> pinned_free;
   // statistics
   std::vector<double> lat_ms;
   double first_submit = -1, last_done = -1;
@@ -145,7 +198,14 @@ struct ba_server {
   size_t peak = 0;
   int fatal = BA_OK;
   void loop();
+  void ana_loop();
   void finish(const std::vector<ReqP> &done_now);
+  Pinned take_pinned(size_t n);
+  int complete(bool block);
+  bool idle_locked() const {
+    return ana_q.empty() && analysing == 0 && ready.empty() && pose_q.empty() && active.empty() &&
+           completing.empty();
+  }
 };
 
 void ba_server::finish(const std::vector<ReqP> &done_now) {
@@ -162,8 +222,88 @@ void ba_server::finish(const std::vector<ReqP> &done_now) {
   cv_done.notify_all();
 }
 
+Pinned ba_server::take_pinned(size_t n) {
+  for (size_t i = 0; i < pinned_free.size(); ++i)
+    if (pinned_free[i].n >= n) {
+      Pinned b = pinned_free[i];
+      pinned_free.erase(pinned_free.begin() + i);
+      return b;
+    }
+  Pinned b;
+  const size_t want = std::max<size_t>(n, 1 << 16);
+  if (hipHostMalloc((void **)&b.p, want, hipHostMallocDefault) == hipSuccess) b.n = want;
+  else b.p = nullptr;
+  return b;
+}
+
+// Symbolic analysis of submitted problems, off the caller's thread and the scheduler's.
+void ba_server::ana_loop() {
+  while (true) {
+    ReqP r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_ana.wait(lk, [&] { return stop || !ana_q.empty(); });
+      if (ana_q.empty()) return;
+      r = ana_q.front();
+      ana_q.pop_front();
+      ++analysing;
+    }
+    const ba_problem_desc d = r->desc();
+    int rc = analyse(&d, &r->opt, r->sy);
+    if (rc == BA_OK) {
+      r->bytes = DevProblem::bytes_for(r->sy, r->opt.precision, r->opt.max_iters);
+      if ((int64_t)r->bytes > budget)
+        rc = fail(BA_ENOMEM, "problem needs %lld bytes, budget is %lld", (long long)r->bytes, (long long)budget);
+    }
+    if (rc != BA_OK) {
+      r->rc = rc;
+      r->err = g_last_error;
+    }
+    r->obs = std::vector<ba_obs>();  // the analysis holds everything the upload needs
+    bool failed = rc != BA_OK;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      --analysing;
+      if (!failed && stop) {
+        r->rc = BA_ESTATE;
+        r->err = "server is shutting down";
+        failed = true;
+      }
+      if (!failed) ready[r->ticket] = r;
+    }
+    if (failed) finish({r});
+    cv_work.notify_one();
+  }
+}
+
+// Hand over the problems whose result copies have landed.  block: wait for the oldest.
+int ba_server::complete(bool block) {
+  while (!completing.empty()) {
+    Completion &c = completing.front();
+    hipError_t e = block ? hipEventSynchronize(c.ev) : hipEventQuery(c.ev);
+    if (e == hipErrorNotReady) return BA_OK;
+    block = false;
+    if (e != hipSuccess) return hip_fail(e, "server result copies");
+    for (size_t i = 0; i < c.reqs.size(); ++i) {
+      Req &r = *c.reqs[i];
+      r.out_poses.resize(r.sy.C);
+      r.out_pts.resize(3 * (size_t)r.sy.P);
+      r.iter_cost.resize(r.dp.max_iters + 1);
+      r.iter_pcg.resize(r.dp.max_iters);
+      r.rep.iter_cost = r.iter_cost.data();
+      r.rep.pcg_iters = r.iter_pcg.data();
+      r.dp.finish_result(c.bufs[i].p, r.out_poses.data(), r.out_pts.data(), &r.rep);
+      pinned_free.push_back(c.bufs[i]);
+    }
+    (void)hipEventDestroy(c.ev);
+    std::vector<ReqP> done_now = std::move(c.reqs);
+    completing.pop_front();
+    finish(done_now);
+  }
+  return BA_OK;
+}
+
 void ba_server::loop() {
-  std::vector<int32_t> iters;
   bool dirty = true;
   while (true) {
     std::vector<ReqP> admitted, pose_now;
@@ -172,41 +312,36 @@ void ba_server::loop() {
     bool pb_ok = false;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-      if (stop && queue.empty() && active.empty()) break;
-      // admission in arrival order; a request that does not fit blocks the ones behind it
-      while (!queue.empty() && fatal == BA_OK) {
-        ReqP r = queue.front();
-        if (r->pose) {
-          // pose requests of one step share one block; 512 bytes cover its alignment
-          if (pose_bytes + r->bytes + 512 > arena.largest_free()) break;
-          pose_bytes += r->bytes;
-          pose_now.push_back(r);
-          queue.pop_front();
-          continue;
-        }
-        if (!pose_now.empty()) break;  // keep arrival order across the two kinds
+      cv_work.wait(lk, [&] {
+        return (stop && idle_locked()) || !ready.empty() || !pose_q.empty() || !active.empty() ||
+               !completing.empty();
+      });
+      if (stop && idle_locked()) break;
+      // pose requests of one step share one block; 512 bytes cover its alignment
+      while (!pose_q.empty() && fatal == BA_OK) {
+        ReqP r = pose_q.front();
+        if (pose_bytes + r->bytes + 512 > arena.largest_free()) break;
+        pose_bytes += r->bytes;
+        pose_now.push_back(r);
+        pose_q.pop_front();
+      }
+      if (!pose_now.empty()) pb_ok = arena.alloc(pose_bytes + 512, pb_off);
+      // analysed problems in ticket order; one that does not fit holds back the later ones
+      while (!ready.empty() && fatal == BA_OK) {
+        ReqP r = ready.begin()->second;
         if ((int)(active.size() + admitted.size()) >= max_slots) break;
         size_t off;
         if (!arena.alloc(r->bytes, off)) break;
         r->off = off;
         r->holds_block = true;
         admitted.push_back(r);
-        queue.pop_front();
+        ready.erase(ready.begin());
       }
-      if (!pose_now.empty()) pb_ok = arena.alloc(pose_bytes + 512, pb_off);
       peak = std::max(peak, arena.used);
     }
     std::vector<ReqP> failed;
     for (auto &r : admitted) {
-      ba_problem_desc d{};
-      d.n_cams = r->sy.C;
-      d.K = r->K.data();
-      d.K_per_cam = r->K_per_cam;
-      d.poses = r->poses.data();
-      d.n_pts = r->sy.P;
-      d.points_xyz = r->pts.data();
-      d.n_obs = r->sy.N;
+      const ba_problem_desc d = r->desc();
       int rc = r->dp.init(r->sy, &d, &r->opt, (char *)mem + r->off, stream);
       if (rc == BA_OK) {
         r->dp.pending_state = r->dp.fresh_state();
@@ -214,8 +349,14 @@ void ba_server::loop() {
                                       hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) rc = hip_fail(e, "server state upload");
       }
+      // what the device copy and the report still need is in dp; drop the rest
+      r->sy = Symbolic();
+      r->sy.C = r->dp.C;
+      r->sy.P = r->dp.P;
+      r->pts = std::vector<double>();
       if (rc != BA_OK) {
         r->rc = rc;
+        r->err = g_last_error;
         failed.push_back(r);
       } else {
         std::lock_guard<std::mutex> lk(mu);
@@ -224,29 +365,63 @@ void ba_server::loop() {
       }
     }
     if (!failed.empty()) finish(failed);
-    int pcg_max = 1;
-    if (!active.empty()) {
+    if (!active.empty() && fatal == BA_OK) {
       if (dirty) {
         batch.clear();
         for (size_t i = 0; i < active.size(); ++i) batch.add(active[i]->dp.view, (int)i);
-        if (batch.upload(stream) != BA_OK) {
-          fatal = BA_EDEVICE;
-        }
+        if (batch.upload(stream) != BA_OK) fatal = BA_EDEVICE;
         dirty = false;
       }
-      int max_cf = 1;
+      int pcg_max = 1, max_cf = 1;
       for (auto &r : active) {
         pcg_max = std::max(pcg_max, r->dp.pcg_max);
         max_cf = std::max(max_cf, (int)r->dp.max_tcols);
       }
+      // at most kLookahead launch sequences in flight
+      hipEvent_t &ev = ev_step[n_steps % kLookahead];
+      if (fatal == BA_OK && n_steps >= kLookahead && hipEventSynchronize(ev) != hipSuccess) fatal = BA_EDEVICE;
       if (fatal == BA_OK &&
           launch_lm_iteration(precision, batch.plan, pcg_max, max_cf, stream, nullptr) != hipSuccess)
         fatal = BA_EDEVICE;
-      if (fatal == BA_OK && launch_gather_iters(batch.plan, d_iters, stream) != hipSuccess)
-        fatal = BA_EDEVICE;
+      if (fatal == BA_OK && hipEventRecord(ev, stream) != hipSuccess) fatal = BA_EDEVICE;
+      ++n_steps;
+      // every launch sequence advances each problem it holds by one iteration (batched
+      // solves never stop early), so the host knows which ones are finished
+      std::vector<ReqP> fin, keep;
+      for (auto &r : active) (++r->steps >= r->dp.max_iters ? fin : keep).push_back(r);
+      if (!fin.empty() && fatal == BA_OK) {
+        fin_batch.clear();
+        for (auto &r : fin) fin_batch.add(r->dp.view, 0);
+        Completion c;
+        int rc = fin_batch.upload(stream);
+        if (rc == BA_OK && launch_eval(precision, fin_batch.plan, stream, nullptr) != hipSuccess) rc = BA_EDEVICE;
+        for (auto &r : fin) {
+          Pinned b = take_pinned(r->dp.result_bytes());
+          if (!b.p) rc = BA_ENOMEM;
+          if (rc == BA_OK && r->dp.enqueue_result(stream, b.p) != hipSuccess) rc = BA_EDEVICE;
+          c.reqs.push_back(r);
+          c.bufs.push_back(b);
+        }
+        if (rc == BA_OK && hipEventCreateWithFlags(&c.ev, hipEventDisableTiming) != hipSuccess) rc = BA_EDEVICE;
+        if (rc == BA_OK && hipEventRecord(c.ev, stream) != hipSuccess) rc = BA_EDEVICE;
+        if (rc != BA_OK) fatal = rc;
+        {
+          // the blocks are free for later problems: their uploads follow these copies
+          // on the stream
+          std::lock_guard<std::mutex> lk(mu);
+          active = keep;
+          for (auto &r : fin) {
+            if (r->holds_block) arena.release(r->off, r->bytes);
+            r->holds_block = false;
+          }
+        }
+        if (rc == BA_OK) completing.push_back(std::move(c));
+        else for (auto &b : c.bufs) if (b.p) pinned_free.push_back(b);
+        dirty = true;
+      }
     }
-    PoseBatch pb;
     if (!pose_now.empty() && fatal == BA_OK) {
+      PoseBatch pb;
       std::vector<const ba_pose_request *> rp;
       std::vector<const ba_options *> ro;
       for (auto &r : pose_now) {
@@ -254,21 +429,9 @@ void ba_server::loop() {
         ro.push_back(&r->opt);
       }
       pb.pack(rp, ro);
-      if (pb_ok && pb.run((char *)mem + pb_off, stream, nullptr) != BA_OK)
-        fatal = BA_EDEVICE;
-    }
-    iters.assign(active.size(), 0);
-    if (!active.empty() && fatal == BA_OK)
-      if (hipMemcpyAsync(iters.data(), d_iters, active.size() * 4, hipMemcpyDeviceToHost, stream) != hipSuccess)
-        fatal = BA_EDEVICE;
-    if (hipStreamSynchronize(stream) != hipSuccess) fatal = BA_EDEVICE;
-    for (auto &r : admitted) {
-      r->dp.staging_f.clear();
-      r->dp.staging_d.clear();
-      r->sy.pairs = std::vector<int2>();
-      r->sy.ent_items = std::vector<uint32_t>();
-    }
-    if (!pose_now.empty()) {
+      if (pb_ok && pb.run((char *)mem + pb_off, stream, nullptr) != BA_OK) fatal = BA_EDEVICE;
+      // the headers' download goes to pageable memory: wait for it
+      if (hipStreamSynchronize(stream) != hipSuccess) fatal = BA_EDEVICE;
       if (pb_ok) {
         std::lock_guard<std::mutex> lk(mu);
         arena.release(pb_off, pose_bytes + 512);
@@ -286,56 +449,33 @@ void ba_server::loop() {
       }
       finish(pose_now);
     }
+    if (fatal == BA_OK) {
+      const bool nothing_launched = admitted.empty() && pose_now.empty() && active.empty();
+      if (complete(nothing_launched) != BA_OK) fatal = BA_EDEVICE;
+    }
     if (fatal != BA_OK) {
       // fail everything still pending; the device state is unknown
+      (void)hipStreamSynchronize(stream);
       std::vector<ReqP> all;
       {
         std::lock_guard<std::mutex> lk(mu);
         all.insert(all.end(), active.begin(), active.end());
-        all.insert(all.end(), queue.begin(), queue.end());
+        for (auto &kv : ready) all.push_back(kv.second);
+        all.insert(all.end(), pose_q.begin(), pose_q.end());
         active.clear();
-        queue.clear();
+        ready.clear();
+        pose_q.clear();
       }
+      for (auto &c : completing) {
+        all.insert(all.end(), c.reqs.begin(), c.reqs.end());
+        for (auto &b : c.bufs) pinned_free.push_back(b);
+        if (c.ev) (void)hipEventDestroy(c.ev);
+      }
+      completing.clear();
       for (auto &r : all) r->rc = fatal;
       finish(all);
-      continue;
-    }
-    // retire finished problems
-    std::vector<ReqP> fin;
-    std::vector<ReqP> keep;
-    for (size_t i = 0; i < active.size(); ++i) {
-      if (iters[i] >= active[i]->dp.max_iters) fin.push_back(active[i]);
-      else keep.push_back(active[i]);
-    }
-    if (!fin.empty()) {
-      Batch fb;
-      for (auto &r : fin) fb.add(r->dp.view, 0);
-      int rc = fb.upload(stream);
-      if (rc == BA_OK && launch_eval(precision, fb.plan, stream, nullptr) != hipSuccess) rc = BA_EDEVICE;
-      for (auto &r : fin) {
-        if (hipMemcpyAsync(&r->dp.host_state, r->dp.view.st, sizeof(LMState), hipMemcpyDeviceToHost, stream) != hipSuccess)
-          rc = BA_EDEVICE;
-      }
-      if (hipStreamSynchronize(stream) != hipSuccess) rc = BA_EDEVICE;
-      for (auto &r : fin) {
-        if (rc != BA_OK) {
-          r->rc = rc;
-          continue;
-        }
-        r->out_poses.resize(r->sy.C);
-        r->out_pts.resize(3 * (size_t)r->sy.P);
-        r->iter_cost.resize(r->dp.max_iters + 1);
-        r->iter_pcg.resize(r->dp.max_iters);
-        r->rep.iter_cost = r->iter_cost.data();
-        r->rep.pcg_iters = r->iter_pcg.data();
-        r->rc = r->dp.read_result(stream, r->out_poses.data(), r->out_pts.data(), &r->rep, true, 0.0, 0.0);
-      }
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        active = keep;
-      }
       dirty = true;
-      finish(fin);
+      continue;
     }
   }
 }
@@ -362,42 +502,54 @@ int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precis
     s->own_stream = true;
   }
   hipError_t e = hipMalloc(&s->mem, (size_t)hbm_budget_bytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&s->d_iters, (size_t)max_slots * 4);
+  for (int i = 0; i < kLookahead && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&s->ev_step[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     if (s->mem) (void)hipFree(s->mem);
+    for (auto &ev : s->ev_step)
+      if (ev) (void)hipEventDestroy(ev);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
-    return hip_fail(e, "server arena allocation");
+    return hip_fail(e, "server allocation");
   }
   s->arena.reset((size_t)hbm_budget_bytes);
   ba_server *raw = s.get();
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int n_ana = (int)std::max(1u, std::min(8u, hw / 2));
+  for (int i = 0; i < n_ana; ++i) s->ana_th.emplace_back([raw] { raw->ana_loop(); });
   s->th = std::thread([raw] { raw->loop(); });
   *out = s.release();
   return BA_OK;
 }
 
 int ba_server_submit(ba_server *s, const ba_problem_desc *d, const ba_options *opt, int64_t *ticket) {
-  if (!s || !ticket) return fail(BA_EINVAL, "NULL argument");
-  if (opt && opt->precision != s->precision)
+  if (!s || !ticket || !d) return fail(BA_EINVAL, "NULL argument");
+  if (int e = check_options(opt, false)) return e;
+  if (opt->precision != s->precision)
     return fail(BA_EINVAL, "request precision %d differs from the server's %d", opt->precision, s->precision);
+  if (d->n_cams < 1 || d->n_pts < 1 || d->n_obs < 1) return fail(BA_EINVAL, "empty problem");
+  if (d->n_obs > (int64_t)INT32_MAX - 1) return fail(BA_EINVAL, "n_obs exceeds 2^31 - 2");
+  if (!d->K || !d->poses || !d->points_xyz || !d->obs) return fail(BA_EINVAL, "NULL array in problem");
+  if ((int64_t)min_problem_bytes(d->n_obs, d->n_pts, d->n_cams, opt->precision) > s->budget)
+    return fail(BA_ENOMEM, "problem needs more than the budget of %lld bytes", (long long)s->budget);
   auto r = std::make_shared<Req>();
   r->t_submit = now_ms();
-  if (int e = analyse(d, opt, r->sy)) return e;
   r->opt = *opt;
-  r->bytes = DevProblem::bytes_for(r->sy, opt->precision, opt->max_iters);
-  if ((int64_t)r->bytes > s->budget)
-    return fail(BA_ENOMEM, "problem needs %lld bytes, budget is %lld", (long long)r->bytes, (long long)s->budget);
+  r->n_cams = d->n_cams;
+  r->n_pts = d->n_pts;
   r->K_per_cam = d->K_per_cam;
   r->K.assign(d->K, d->K + (d->K_per_cam ? d->n_cams : 1));
   r->poses.assign(d->poses, d->poses + d->n_cams);
+  if (d->cam_fixed) r->fixed.assign(d->cam_fixed, d->cam_fixed + d->n_cams);
   r->pts.assign(d->points_xyz, d->points_xyz + 3 * (size_t)d->n_pts);
+  r->obs.assign(d->obs, d->obs + d->n_obs);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return fail(BA_ESTATE, "server is shutting down");
   r->ticket = s->next_ticket++;
   if (s->first_submit < 0) s->first_submit = r->t_submit;
   s->tickets[r->ticket] = r;
-  s->queue.push_back(r);
+  s->ana_q.push_back(r);
   *ticket = r->ticket;
-  s->cv_work.notify_one();
+  s->cv_ana.notify_one();
   return BA_OK;
 }
 
@@ -420,7 +572,7 @@ int ba_server_submit_pose(ba_server *s, const ba_pose_request *req, const ba_opt
   r->ticket = s->next_ticket++;
   if (s->first_submit < 0) s->first_submit = r->t_submit;
   s->tickets[r->ticket] = r;
-  s->queue.push_back(r);
+  s->pose_q.push_back(r);
   *ticket = r->ticket;
   s->cv_work.notify_one();
   return BA_OK;
@@ -437,7 +589,8 @@ int ba_server_wait(ba_server *s, int64_t ticket, ba_pose *poses_out, double *poi
     s->cv_done.wait(lk, [&] { return r->done; });
     s->tickets.erase(it);
   }
-  if (r->rc != BA_OK) return fail(r->rc, "request %lld failed", (long long)ticket);
+  if (r->rc != BA_OK)
+    return fail(r->rc, "request %lld failed%s%s", (long long)ticket, r->err.empty() ? "" : ": ", r->err.c_str());
   if (poses_out) std::copy(r->out_poses.begin(), r->out_poses.end(), poses_out);
   if (points_out && !r->pose) std::copy(r->out_pts.begin(), r->out_pts.end(), points_out);
   if (rep) {
@@ -469,7 +622,7 @@ int ba_server_stats(ba_server *s, ba_server_stats_t *out) {
   out->p50_ms = pct(0.50);
   out->p99_ms = pct(0.99);
   out->done = s->n_done;
-  out->queued = (int64_t)s->queue.size();
+  out->queued = (int64_t)(s->ana_q.size() + s->analysing + s->ready.size() + s->pose_q.size());
   out->active = (int64_t)s->active.size();
   out->bytes_in_use = (int64_t)s->arena.used;
   out->peak_bytes = (int64_t)s->peak;
@@ -480,23 +633,35 @@ int ba_server_stats(ba_server *s, ba_server_stats_t *out) {
 
 void ba_server_destroy(ba_server *s) {
   if (!s) return;
-  std::vector<ReqP> cancelled;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    cancelled.assign(s->queue.begin(), s->queue.end());
-    s->queue.clear();
+    std::vector<ReqP> cancelled(s->ana_q.begin(), s->ana_q.end());
+    for (auto &kv : s->ready) cancelled.push_back(kv.second);
+    cancelled.insert(cancelled.end(), s->pose_q.begin(), s->pose_q.end());
+    s->ana_q.clear();
+    s->ready.clear();
+    s->pose_q.clear();
     for (auto &r : cancelled) {
       r->rc = BA_ESTATE;
+      r->err = "cancelled: the server was destroyed";
       r->done = true;
     }
+    s->cv_ana.notify_all();
     s->cv_work.notify_all();
     s->cv_done.notify_all();
   }
+  for (auto &t : s->ana_th) t.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_work.notify_all();
+  }
   if (s->th.joinable()) s->th.join();
   (void)hipStreamSynchronize(s->stream);
+  for (auto &b : s->pinned_free) (void)hipHostFree(b.p);
+  for (auto &ev : s->ev_step)
+    if (ev) (void)hipEventDestroy(ev);
   (void)hipFree(s->mem);
-  (void)hipFree(s->d_iters);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }

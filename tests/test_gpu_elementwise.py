@@ -2,7 +2,7 @@
 oracle, through the C-ABI's test export (ba_debug_iteration_export): the stored
 sqrt(w) r and sqrt(w) J per observation, the reduced system S block by block, its
 right-hand side b and the camera gradient, the PCG solution dc and the
-back-substituted point step dp.  Needs an MI355X.
+back-substituted point step dp, in each of the three Schur forms.  Needs an MI355X.
 
 Bars (FP64 build): r, J, S, b and g within 1e-12 of the oracle's values, relative to
 the array's largest magnitude; dc and dp within 1e-10 of the oracle's exact solve of
@@ -65,14 +65,15 @@ def _dense(dev, nf):
     return S
 
 
-CASES = [("config0", make_config0, 0), ("config0", make_config0, PAIR_LISTS),
-         ("drive", lambda: make_small_drive(40, 3000, seed=5), 0),
-         ("drive", lambda: make_small_drive(40, 3000, seed=5), PAIR_LISTS),
-         ("huber", lambda: make_small_drive(30, 2500, seed=9, outlier_frac=0.05, huber_delta=1.0), 0)]
+# (name, scene, flags, Schur form: 0 pair lists, 1 point chunks, 2 dense co-visibility)
+CASES = [("config0", make_config0, 0, 2), ("config0", make_config0, PAIR_LISTS, 0),
+         ("drive", lambda: make_small_drive(40, 3000, seed=5), 0, 1),
+         ("drive", lambda: make_small_drive(40, 3000, seed=5), PAIR_LISTS, 0),
+         ("huber", lambda: make_small_drive(30, 2500, seed=9, outlier_frac=0.05, huber_delta=1.0), 0, 1)]
 
 
-@pytest.mark.parametrize("name,make,flags", CASES, ids=[f"{c[0]}-{c[2]}" for c in CASES])
-def test_first_iteration_elementwise_f64(balib, name, make, flags):
+@pytest.mark.parametrize("name,make,flags,form", CASES, ids=[f"{c[0]}-{c[2]}" for c in CASES])
+def test_first_iteration_elementwise_f64(balib, name, make, flags, form):
     s = make()
     ref = _oracle_iteration(s)
     _say("device iteration export:", name, s.n_cams, s.n_pts, s.n_obs, "flags", flags)
@@ -81,7 +82,7 @@ def test_first_iteration_elementwise_f64(balib, name, make, flags):
     info = p.info()
     dev = p.debug_iteration()
     p.close()
-    assert info["schur_form"] == (0 if flags & PAIR_LISTS else 1)
+    assert info["schur_form"] == form
     nf = ref["nf"]
     Sd = _dense(dev, nf)
     # the stored pattern holds every nonzero block of the oracle's S

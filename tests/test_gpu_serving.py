@@ -92,9 +92,21 @@ def test_admission_respects_budget_and_slots(balib):
     assert st["peak_bytes"] <= budget
     assert st["done"] == 6 and st["queued"] == 0 and st["active"] == 0
     big = make_small_drive(80, 9000, seed=130)
-    with pytest.raises(balib.BAError) as e:
-        srv.submit(balib.scene_desc(big), balib.options(max_iters=5))
+    with pytest.raises(balib.BAError) as e:  # refused at submission or, once analysed, at wait
+        srv.wait(srv.submit(balib.scene_desc(big), balib.options(max_iters=5)))
     assert e.value.code == balib.BA_ENOMEM
+    # invalid content fails its own ticket and no other
+    bad = make_small_drive(20, 1000, seed=131)
+    bad.obs_cam = bad.obs_cam.copy()
+    bad.obs_pt = bad.obs_pt.copy()
+    bad.obs_cam[1], bad.obs_pt[1] = bad.obs_cam[0], bad.obs_pt[0]  # one (camera, point) observed twice
+    good = make_small_drive(20, 1000, seed=132)
+    tb = srv.submit(balib.scene_desc(bad), balib.options(max_iters=3))
+    tg = srv.submit(balib.scene_desc(good), balib.options(max_iters=3))
+    with pytest.raises(balib.BAError) as e:
+        srv.wait(tb)
+    assert e.value.code == balib.BA_EINVAL and "twice" in str(e.value)
+    assert srv.wait(tg)["iters"] == 3
     srv.close()
 
 
