@@ -356,12 +356,16 @@ print(json.dumps({"seconds": dt, "n_obs": p.n_obs, "iters": 1}))
                       f"{sec:.1f} s on 1 thread"}
 
 
-def serving_leg(ba, n_ba: int, precision: str) -> dict:
-    """p50/p99 latency of mixed-size streams through the continuous-batching server
-    (submission to result on the host): the 4096-request pose-only localization
-    stream submitted at once, and the first n_ba problems of the 512-problem BA
-    stream (cameras and points log-uniform), first saturated (all submitted at
-    t = 0), then with seeded Poisson arrivals at 0.8 of the saturated rate."""
+def serving_leg(ba, n_ba: int, precision: str, precisions=("f16j", "bf16j"), slots: int = 16,
+                poisson=(0.5, 0.8)) -> dict:
+    """p50/p99 latency (submission to result on the host) and throughput of the
+    continuous-batching server under an 8 GB budget: the 4096-request pose-only
+    localization stream submitted at once, and the first n_ba problems of the
+    512-problem BA stream (cameras and points log-uniform, 20 LM iterations, PCG
+    50 / 1e-6), first saturated (all submitted at t = 0), then with seeded Poisson
+    arrivals at 0.5 and 0.8 of the saturated rate; then saturated again in each of
+    `precisions`, with every problem's final RMS set against the same problem's in
+    `precision` (the FP32 form with FP64 reductions by default)."""
     import numpy as np
     from synth import make_config3_problem, make_config3_sizes, make_config4_requests
     out = {}
@@ -383,34 +387,55 @@ def serving_leg(ba, n_ba: int, precision: str) -> dict:
     print(f"bench: generating {n_ba} BA stream problems", flush=True, file=sys.stderr)
     descs = [ba.scene_desc(make_config3_problem(r, int(nc[r]), int(npt[r]))) for r in range(n_ba)]
     nobs = [int(d.desc.n_obs) for d in descs]
-    opts = ba.options(max_iters=20, pcg_max_iters=50, pcg_rel_tol=1e-6, precision=precision)
 
-    def run(gaps):
-        srv = ba.Server(8 << 30, 16, precision)
+    def run(gaps, prec):
+        opts = ba.options(max_iters=20, pcg_max_iters=50, pcg_rel_tol=1e-6, precision=prec)
+        srv = ba.Server(8 << 30, slots, prec)
         t0 = time.perf_counter()
         tks = []
         for d, g in zip(descs, gaps):
             if g > 0:
                 time.sleep(g)
             tks.append(srv.submit(d, opts))
-        res = [srv.wait(t) for t in tks]
+        res, refused = [], 0
+        for t in tks:
+            try:
+                res.append(srv.wait(t))
+            except ba.BAError:
+                res.append(None)
+                refused += 1
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        return wall, st, res
+        print(f"bench: BA stream {prec}: {wall:.2f} s, p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms",
+              flush=True, file=sys.stderr)
+        return wall, st, res, refused
 
-    wall, st, res = run([0.0] * n_ba)
+    def summary(wall, st, refused):
+        return {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                "solves_per_s": round(n_ba / wall, 2), "wall_s": round(wall, 3), "refused": refused,
+                "peak_bytes": st["peak_bytes"]}
+
+    wall, st, base, refused = run([0.0] * n_ba, precision)
     rate = n_ba / wall
-    out["ba_stream_saturated"] = {"problems": n_ba, "obs_total": sum(nobs), "obs_max": max(nobs),
-                                  "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
-                                  "solves_per_s": round(rate, 2), "lm_iters": 20,
-                                  "peak_bytes": st["peak_bytes"]}
-    rng = np.random.default_rng(3003)
-    gaps = rng.exponential(1.0 / (0.8 * rate), n_ba)
-    gaps[0] = 0.0
-    wall, st, _ = run(list(gaps))
-    out["ba_stream_poisson_0.8"] = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
-                                    "solves_per_s": round(n_ba / wall, 2)}
+    out["ba_stream"] = {"problems": n_ba, "obs_total": sum(nobs), "obs_max": max(nobs), "lm_iters": 20,
+                        "budget_bytes": 8 << 30, "slots": slots, "precision": precision,
+                        "schur_forms": "dense co-visibility (chosen per problem)"}
+    out["ba_stream_saturated"] = summary(wall, st, refused)
+    rms = np.array([r["rms_px"] if r else np.nan for r in base])
+    out["ba_stream_saturated"]["final_rms_px_median"] = round(float(np.nanmedian(rms)), 6)
+    for frac in poisson:
+        rng = np.random.default_rng(3000 + int(round(10 * frac)))
+        gaps = rng.exponential(1.0 / (frac * rate), n_ba)
+        gaps[0] = 0.0
+        wall, st, _, refused = run(list(gaps), precision)
+        out[f"ba_stream_poisson_{frac}"] = {**summary(wall, st, refused), "offered_per_s": round(frac * rate, 2)}
+    for prec in precisions:
+        wall, st, res, refused = run([0.0] * n_ba, prec)
+        d = np.array([abs(r["rms_px"] - rms[i]) if r else np.nan for i, r in enumerate(res)])
+        out[f"ba_stream_saturated_{prec}"] = {**summary(wall, st, refused),
+                                              "final_rms_diff_vs_" + precision + "_px_max": float(np.nanmax(d)),
+                                              "final_rms_diff_vs_" + precision + "_px_median": float(np.nanmedian(d))}
     return out
 
 
@@ -429,8 +454,13 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time only whole steps (lets solves replay their graph)")
-    ap.add_argument("--serving", type=int, default=24, metavar="N",
+    ap.add_argument("--serving", type=int, default=512, metavar="N",
                     help="BA problems of the mixed-size stream in the serving leg (0: pose stream only, -1: skip)")
+    ap.add_argument("--serving-precisions", default="f16j,bf16j",
+                    help="storage modes whose saturated BA stream is set against the FP32 one")
+    ap.add_argument("--serving-poisson", default="0.5,0.8",
+                    help="Poisson arrival rates of the BA stream, as fractions of the saturated rate")
+    ap.add_argument("--serving-slots", type=int, default=16, help="problems the server batches at once")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (3 times), to calibrate HBM counters")
     ap.add_argument("--prior-abs", type=float, default=0.0,
@@ -632,7 +662,9 @@ def main():
         out["pose_graph"] = pose_graph_leg(ba, args.precision, 1500, ba.FLAG_NO_GRAPH if args.no_graph else 0)
     if args.serving >= 0:
         print("bench: serving streams", flush=True, file=sys.stderr)
-        out["serving"] = serving_leg(ba, args.serving, args.precision)
+        out["serving"] = serving_leg(ba, args.serving, args.precision,
+                                     [x for x in args.serving_precisions.split(",") if x], args.serving_slots,
+                                     [float(x) for x in args.serving_poisson.split(",") if x])
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", flush=True, file=sys.stderr)
         out["cpu_baseline"] = cpu_baseline()

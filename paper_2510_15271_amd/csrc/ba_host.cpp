@@ -861,6 +861,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
   pd.n_fsh_tiles = sy.chunked || sy.dense ? (Cf + 63) / 64 : 0;
   pd.dense = sy.dense ? 1 : 0;
+  pd.seg_scan = (int64_t)N >= 16 * (int64_t)std::max(P, 1) ? 1 : 0;
   pd.dn_tiles = sy.dense ? sy.dn_tiles : 0;
   pd.dn_pairs = sy.dense ? sy.dn_tiles * (sy.dn_tiles + 1) / 2 : 0;
   pd.dn_split = sy.dense ? sy.dn_split : 0;

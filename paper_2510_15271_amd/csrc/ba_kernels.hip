@@ -138,6 +138,48 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Adds one pass of kObsChunk observations' NV values (c; jl = their point in the
+// tile, -1 for none) into the points' accumulators s_acc, for problems whose points
+// have long tracks.  The observations of one point are consecutive, so an inclusive
+// segmented scan across each wave (six shuffle steps) leaves every wave's part of a
+// point at its last lane; the chunk's last lane of the point then adds the point's
+// wave parts in wave order.  s_c and s_loc are scratch of kObsChunk rows.
+template <class T, int NV>
+__device__ inline void seg_add_scan(T c[NV], int jl, T (*s_acc)[NV], T (*s_c)[NV], int *s_loc) {
+  const int t = threadIdx.x, lane = t & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int oj = __shfl_up(jl, d, 64);
+    T o[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) o[i] = __shfl_up(c[i], d, 64);
+    if (lane >= d && oj == jl)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) c[i] += o[i];
+  }
+  s_loc[t] = jl;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) s_c[t][i] = c[i];
+  __syncthreads();
+  if (jl >= 0 && (t == kObsChunk - 1 || s_loc[t + 1] != jl)) {
+    const int w = t >> 6;
+    int w0 = w;
+    while (w0 > 0 && s_loc[(w0 << 6) - 1] == jl) --w0;
+    T tot[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = w0 < w ? s_c[(w0 << 6) + 63][i] : c[i];
+    for (int x = w0 + 1; x < w; ++x)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) tot[i] += s_c[(x << 6) + 63][i];
+    if (w0 < w)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) tot[i] += c[i];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s_acc[jl][i] += tot[i];
+  }
+  __syncthreads();
+}
+
 // Reduce-scatter of M values over the 64 lanes of a wavefront by recursive
 // halving: at each of the six steps a lane keeps one half of its vector (by one
 // bit of its lane index), adds its partner's copy of that half and sends the
@@ -489,6 +531,10 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
       }
       const int cpos = pd.obs_rpos[k];  // records are kept for free cameras only
       if (cpos >= 0) lin[cpos] = rec;
+    }
+    if (pd.seg_scan) {
+      seg_add_scan<T, 9>(c, jl, s_acc, s_c, s_loc);
+      continue;
     }
     s_loc[threadIdx.x] = jl;
 #pragma unroll
@@ -2538,6 +2584,10 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[m] = Jp[m] * u0 + Jp[3 + m] * u1;
       }
+    }
+    if (pd.seg_scan) {
+      seg_add_scan<T, 3>(c, jl, s_acc, s_c, s_loc);
+      continue;
     }
     s_loc[threadIdx.x] = jl;
 #pragma unroll
