@@ -687,23 +687,30 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   sy.pcg_resident = (opt->flags & BA_FLAG_PCG_RESIDENT) &&
                     resident_pcg_fits(prec, sy.pcg_rows, (Cf + sy.pcg_rows - 1) / sy.pcg_rows, sy.max_tcols);
   if (sy.dense) {
-    // first observation of each point in each camera tile: the tile's observations of
-    // the point are the range [ts[t], ts[t + 1]) (fixed cameras in it have no record)
+    // first record of each point in each camera tile: the point's records in the tile
+    // are the range [ts[t], ts[t + 1]) (records are point-major, in camera order), and
+    // each record's free camera
     const int nt = (Cf + kDnCams - 1) / kDnCams;
     sy.dn_tiles = nt;
     const int64_t pairs_t = (int64_t)nt * (nt + 1) / 2;
+    // point ranges: enough workgroups for the problem, each at most kDnRangePts points
+    // so that no range outlasts the others by much
     sy.dn_split = (int32_t)std::max<int64_t>(
-        1, std::min<int64_t>({(kDnTargetWgs + pairs_t - 1) / pairs_t, (int64_t)P / 1024, 64}));
+        {1, std::min<int64_t>((kDnTargetWgs + pairs_t - 1) / pairs_t, (int64_t)P / 1024),
+         ((int64_t)P + kDnRangePts - 1) / kDnRangePts});
     sy.dn_ts.assign((size_t)P * (nt + 1), 0);
+    sy.dn_rcam.assign(sy.Nf, 0);
+    int32_t r = 0;
     for (int j = 0; j < P; ++j) {
       int32_t *ts = &sy.dn_ts[(size_t)j * (nt + 1)];
       int t = 0;
       for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) {
         const int a = sy.free_idx[sy.obs_cam[k]];
         if (a < 0) continue;
-        while (t <= a / kDnCams) ts[t++] = k;
+        while (t <= a / kDnCams) ts[t++] = r;
+        sy.dn_rcam[r++] = a;
       }
-      while (t <= nt) ts[t++] = sy.pt_start[j + 1];
+      while (t <= nt) ts[t++] = r;
     }
   }
   if (sy.chunked)
@@ -759,6 +766,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.part_o = L.take((size_t)sy.n_oent * 36 * T + 16);
   o.row_tot = L.take(sy.chunked || sy.dense ? Cf * 54 * 8 : 16);
   o.dn_ts = L.take(sy.dn_ts.size() * 4 + 4);
+  o.dn_rcam = L.take(sy.dn_rcam.size() * 4 + 4);
   o.dn_pfac = L.take(sy.dense ? P * 9 * T : 16);
   o.dn_part = L.take(sy.dense ? (size_t)sy.dn_tiles * (sy.dn_tiles + 1) / 2 * sy.dn_split * kDnRows * kDnRows * T
                               : 16);
@@ -901,6 +909,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.part_o = ptr(off.part_o);
   pd.row_tot = (double *)ptr(off.row_tot);
   pd.dn_ts = (const int32_t *)ptr(off.dn_ts);
+  pd.dn_rcam = (const int32_t *)ptr(off.dn_rcam);
   pd.dn_pfac = ptr(off.dn_pfac);
   pd.dn_part = ptr(off.dn_part);
   pd.prior_abs = sy.prior_abs;
@@ -1035,6 +1044,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.ent_items, sy.ent_items.data(), sy.ent_items.size() * 4));
   chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
   chk(up(off.dn_ts, sy.dn_ts.data(), sy.dn_ts.size() * 4));
+  chk(up(off.dn_rcam, sy.dn_rcam.data(), sy.dn_rcam.size() * 4));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
   chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));
   chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));
@@ -1092,7 +1102,7 @@ void Batch::add(const ProbDev &pd, int slot_tag) {
     for (int t = 0; t < pd.n_pt_tiles; ++t) tiles[12].push_back(Tile{pi, t});
     for (int a = 0; a < pd.Cf; ++a) tiles[13].push_back(Tile{pi, a});
     for (int t = 0; t < pd.dn_pairs * pd.dn_split; ++t) tiles[14].push_back(Tile{pi, t});
-    for (int t = 0; t < pd.dn_pairs; ++t) tiles[15].push_back(Tile{pi, t});
+    for (int t = 0; t < pd.dn_pairs * kDnCams; ++t) tiles[15].push_back(Tile{pi, t});
     for (int t = 0; t < pd.n_fsh_tiles; ++t) tiles[10].push_back(Tile{pi, t});
   } else if (pd.chunked) {
     for (int c = 0; c < pd.n_ch; ++c) tiles[7].push_back(Tile{pi, c});

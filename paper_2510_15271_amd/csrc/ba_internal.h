@@ -50,6 +50,7 @@ constexpr int kDnCams = 16;
 constexpr int kDnRows = 6 * kDnCams;
 constexpr int kDnMaxCams = 1024;     // free cameras beyond which the dense form is not used
 constexpr int kDnTargetWgs = 256;   // workgroups per problem the point ranges aim at
+constexpr int kDnRangePts = 2048;   // points per range at most
 
 constexpr double kLambdaMin = 1e-12;
 constexpr double kLambdaMax = 1e16;
@@ -105,7 +106,8 @@ struct ProbDev {
   int32_t dn_tiles;      // camera tiles (kDnCams free cameras each)
   int32_t dn_pairs;      // tile pairs (a <= b)
   int32_t dn_split;      // point ranges per tile pair
-  const int32_t *dn_ts;  // [P][dn_tiles + 1] first observation of each point in each camera tile
+  const int32_t *dn_ts;  // [P][dn_tiles + 1] first record of each point in each camera tile
+  const int32_t *dn_rcam;  // [Nf] free camera of each record
   void *dn_pfac;         // [P][9] T: L^-T (upper: 00 01 02 11 12 22) and h = L^-1 g_p of V*_j = L L^T
   void *dn_part;         // [dn_pairs][dn_split][kDnRows^2] T: Z Z^T over one point range
   // static structure

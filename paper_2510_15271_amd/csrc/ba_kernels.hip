@@ -3451,9 +3451,10 @@ __device__ inline void dense_z(const T Jc[12], const T Jp[6], const T lt[6], T Z
 // Camera sums of the dense form, one workgroup per free camera over its observations
 // (camera-major list): U (21), g_c (6) and sum_j Z_aj h_j (6), per thread in the
 // compute type, then in FP64 in a fixed order into the camera's row sums.
+constexpr int kDnCamThreads = 1024;
 template <class T, class S>
-__global__ __launch_bounds__(256) void k_dense_cams(const ProbDev *__restrict__ probs,
-                                                    const Tile *__restrict__ tiles) {
+__global__ __launch_bounds__(kDnCamThreads) void k_dense_cams(const ProbDev *__restrict__ probs,
+                                                              const Tile *__restrict__ tiles) {
   constexpr bool k16 = sizeof(S) == 2;
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
@@ -3471,7 +3472,7 @@ __global__ __launch_bounds__(256) void k_dense_cams(const ProbDev *__restrict__ 
   T acc[33];
 #pragma unroll
   for (int i = 0; i < 33; ++i) acc[i] = T(0);
-  for (int o = pd.cam_obs_start[a] + (int)threadIdx.x; o < pd.cam_obs_start[a + 1]; o += 256) {
+  for (int o = pd.cam_obs_start[a] + (int)threadIdx.x; o < pd.cam_obs_start[a + 1]; o += kDnCamThreads) {
     const int k = pd.cam_obs[o];
     const int j = pd.obs_pt[k];
     const LinRec<T, S> rec = lin[pd.obs_rpos[k]];
@@ -3511,7 +3512,8 @@ __global__ __launch_bounds__(256) void k_dense_cams(const ProbDev *__restrict__ 
 #pragma unroll
     for (int m = 0; m < 6; ++m) acc[27 + m] += Z[3 * m] * hv[0] + Z[3 * m + 1] * hv[1] + Z[3 * m + 2] * hv[2];
   }
-  __shared__ double s_t[4][33];
+  constexpr int NW = kDnCamThreads / 64;
+  __shared__ double s_t[NW][33];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 33; ++i) {
@@ -3521,7 +3523,9 @@ __global__ __launch_bounds__(256) void k_dense_cams(const ProbDev *__restrict__ 
   __syncthreads();
   if (threadIdx.x < 33) {
     const int i = threadIdx.x;
-    const double v = s_t[0][i] + s_t[1][i] + s_t[2][i] + s_t[3][i];
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += s_t[w][i];
     // row sums: U (0..20), sum Y W^T (21..41, from k_dense_reduce), g_c (42..47), Y g_p (48..53)
     pd.row_tot[54 * (size_t)a + (i < 21 ? i : 21 + i)] = v;
   }
@@ -3591,7 +3595,10 @@ __device__ inline void dn_pair(int pair, int nt, int &ta, int &tb) {
 
 // One (tile pair, point range): Z tiles in LDS laid out [k / KI][row][k % KI] so that
 // the 64 lanes of an operand load read one contiguous run; four waves, each a 48 x 48
-// quarter of the 96 x 96 product (3 x 3 MFMA tiles of 16 x 16).
+// quarter of the 96 x 96 product (3 x 3 MFMA tiles of 16 x 16).  Thread (point jl,
+// sub) forms the Z blocks of records sub, sub + SUB, ... of its point in each tile;
+// the records of the next chunk are loaded into registers before the products of the
+// current one, so their latency hides behind the matrix cores.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__ probs,
                                                      const Tile *__restrict__ tiles) {
@@ -3599,6 +3606,7 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   using E = typename M::E;
   using V = typename M::V;
   constexpr int KI = M::KI, PC = M::PC, K = 3 * PC, NKS = K / KI, SUB = 256 / PC, KL = KI / 4;
+  constexpr int NSLOT = kDnCams / SUB;  // records of one point and tile per thread
   extern __shared__ __align__(16) double s_dyn[];
   E *za = (E *)s_dyn;       // [NKS][kDnRows][KI]
   E *zb = za + K * kDnRows;  // the same for tile tb (unused when ta == tb)
@@ -3634,6 +3642,36 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   const int lane = t & 63, wv = t >> 6;
   const int rb0 = 3 * (wv >> 1), cb0 = 3 * (wv & 1);
   const int li = lane & 15, lq = lane >> 4;
+  const int jl = t / SUB, sub = t - SUB * (t / SUB);
+  // the next chunk's records of this thread: stored Jacobian values and tile camera
+  S nf[2][NSLOT][7];
+  int nla[2][NSLOT];
+  T nlt[6];
+  auto fetch = [&](int jc) {
+    const int j = jc + jl;
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) nla[side][q] = -1;
+    if (j >= j1) return;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) nlt[i] = pf[9 * (size_t)j + i];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side >= nsides) break;
+      const int tt = side ? tb : ta;
+      const int r0 = pd.dn_ts[(size_t)j * nt1 + tt], r1 = pd.dn_ts[(size_t)j * nt1 + tt + 1];
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) {
+        const int r = r0 + sub + SUB * q;
+        if (r < r1) {
+#pragma unroll
+          for (int i = 0; i < 7; ++i) nf[side][q][i] = lin[r].f[i];
+          nla[side][q] = pd.dn_rcam[r] - tt * kDnCams;
+        }
+      }
+    }
+  };
   V acc[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -3641,42 +3679,41 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[r][c][e] = 0;
+  fetch(j0);
   for (int jc = j0; jc < j1; jc += PC) {
     __syncthreads();  // the previous chunk's products are done (and s_R is visible)
-    for (int i = t; i < nsides * K * kDnRows; i += 256) za[i] = E(0);
-    __syncthreads();
     {
-      const int jl = t / SUB, sub = t - SUB * (t / SUB);
-      const int j = jc + jl;
-      if (j < j1) {
-        T lt[6];
+      // zero the tiles with 16-byte stores, then write the chunk's Z blocks
+      float4 *z4 = (float4 *)za;
+      const int n4 = nsides * K * kDnRows * (int)sizeof(E) / 16;
+      for (int i = t; i < n4; i += 256) z4[i] = float4{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 6; ++i) lt[i] = pf[9 * (size_t)j + i];
-        for (int side = 0; side < nsides; ++side) {
-          const int tt = side ? tb : ta;
-          E *z = side ? zb : za;
-          const int k0 = pd.dn_ts[(size_t)j * nt1 + tt], k1 = pd.dn_ts[(size_t)j * nt1 + tt + 1];
-          for (int k = k0 + sub; k < k1; k += SUB) {
-            const int rp = pd.obs_rpos[k];
-            if (rp < 0) continue;  // a fixed camera: no record, no row
-            const int la = pd.free_idx[pd.obs_cam[k]] - tt * kDnCams;
-            T f[7], Jc[12], Jp[6], Z[18];
-            decode(lin[rp], f);
-            jc_from(f, Jc);
-            jp_from(f, &s_R[side][la][0], Jp);
-            dense_z(Jc, Jp, lt, Z);
+    for (int side = 0; side < 2; ++side) {
+      if (side >= nsides) break;
+      E *z = side ? zb : za;
 #pragma unroll
-            for (int m = 0; m < 6; ++m)
+      for (int q = 0; q < NSLOT; ++q) {
+        const int la = nla[side][q];
+        if (la < 0) continue;
+        T f[7], Jc[12], Jp[6], Z[18];
 #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const int kk = 3 * jl + c, row = 6 * la + m;
-                z[((kk / KI) * kDnRows + row) * KI + (kk % KI)] = E(Z[3 * m + c]);
-              }
+        for (int i = 0; i < 7; ++i) f[i] = Codec<S>::dec(nf[side][q][i]);
+        jc_from(f, Jc);
+        jp_from(f, &s_R[side][la][0], Jp);
+        dense_z(Jc, Jp, nlt, Z);
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int kk = 3 * jl + c, row = 6 * la + m;
+            z[((kk / KI) * kDnRows + row) * KI + (kk % KI)] = E(Z[3 * m + c]);
           }
-        }
       }
     }
     __syncthreads();
+    if (jc + PC < j1) fetch(jc + PC);  // in flight during the products below
     const E *zbb = diag ? za : zb;
     for (int ks = 0; ks < NKS; ++ks) {
       const E *ab = za + (ks * kDnRows + li) * KI + lq * KL;
@@ -3701,9 +3738,10 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
       }
 }
 
-// One tile pair: its ranges' partial products summed in FP64 in range order; blocks
-// (a < b) go to S as -sum and its transpose, diagonal blocks' upper halves to the
-// camera's row sums (sum Y W^T), finished with the other sums by k_schur_finish.
+// One camera row (6 rows) of one tile pair: the ranges' partial products summed in FP64
+// in range order; blocks (a < b) go to S as -sum and its transpose, diagonal blocks'
+// upper halves to the camera's row sums (sum Y W^T), finished with the other sums by
+// k_schur_finish.  Tile index = pair * kDnCams + row camera.
 template <class T>
 __global__ __launch_bounds__(256) void k_dense_reduce(const ProbDev *__restrict__ probs,
                                                       const Tile *__restrict__ tiles) {
@@ -3711,19 +3749,22 @@ __global__ __launch_bounds__(256) void k_dense_reduce(const ProbDev *__restrict_
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
+  const int pair = tl.idx / kDnCams, lr = tl.idx - kDnCams * pair;
   int ta, tb;
-  dn_pair(tl.idx, pd.dn_tiles, ta, tb);
+  dn_pair(pair, pd.dn_tiles, ta, tb);
+  const int a = ta * kDnCams + lr;
+  if (a >= pd.Cf) return;
   const int ns = pd.dn_split;
   constexpr int NE = kDnRows * kDnRows;
-  const T *part = (const T *)pd.dn_part + (size_t)tl.idx * ns * NE;
+  const T *part = (const T *)pd.dn_part + (size_t)pair * ns * NE + 6 * lr * kDnRows;
   T *Sv = (T *)pd.S;
-  for (int e = threadIdx.x; e < NE; e += 256) {
-    const int R = e / kDnRows, Cc = e - kDnRows * (e / kDnRows);
-    const int a = ta * kDnCams + R / 6, b = tb * kDnCams + Cc / 6;
-    if (a >= pd.Cf || b >= pd.Cf || a > b) continue;  // a > b: written as a transpose
+  for (int e = threadIdx.x; e < 6 * kDnRows; e += 256) {
+    const int r = e / kDnRows, Cc = e - kDnRows * (e / kDnRows);
+    const int b = tb * kDnCams + Cc / 6;
+    if (b >= pd.Cf || a > b) continue;  // a > b: written as a transpose
     double sum = 0.0;
     for (int x = 0; x < ns; ++x) sum += (double)part[(size_t)x * NE + e];
-    const int r = R % 6, c = Cc % 6;
+    const int c = Cc % 6;
     if (a == b) {
       if (r <= c) pd.row_tot[54 * (size_t)a + 21 + 6 * r - r * (r - 1) / 2 + (c - r)] = sum;
     } else {
@@ -3871,7 +3912,7 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   }
   if (bp.n_dcm) {
     Timed t(tm, K_DENSE_CAMS, s);
-    k_dense_cams<T, S><<<bp.n_dcm, 256, 0, s>>>(bp.probs, bp.dcm);
+    k_dense_cams<T, S><<<bp.n_dcm, kDnCamThreads, 0, s>>>(bp.probs, bp.dcm);
   }
   if (bp.n_dsy) {
     Timed t(tm, K_DENSE_SCHUR, s);
