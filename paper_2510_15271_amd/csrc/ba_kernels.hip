@@ -3552,7 +3552,7 @@ template <>
 struct DnMma<float, float> {
   using E = float;
   using V = dn_f4;
-  static constexpr int KI = 4, PC = 32;
+  static constexpr int KI = 4, PC = 16;
   static constexpr bool row_major_d = true;   // D[i][j]: lane j + 16 (i / 4), register i % 4
   __device__ static V mma(const E *a, const E *b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0); }
 };
