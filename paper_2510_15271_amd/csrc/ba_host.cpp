@@ -696,7 +696,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
     // point ranges: enough workgroups for the problem, each at most kDnRangePts points
     // so that no range outlasts the others by much
     sy.dn_split = (int32_t)std::max<int64_t>(
-        {1, std::min<int64_t>((kDnTargetWgs + pairs_t - 1) / pairs_t, (int64_t)P / 1024),
+        {1, std::min<int64_t>((kDnTargetWgs + pairs_t - 1) / pairs_t, (int64_t)P / 256),
          ((int64_t)P + kDnRangePts - 1) / kDnRangePts});
     sy.dn_ts.assign((size_t)P * (nt + 1), 0);
     sy.dn_rcam.assign(sy.Nf, 0);
