@@ -173,19 +173,23 @@ struct ba_server {
   int analysing = 0;                 // problems being analysed now
   std::map<int64_t, ReqP> ready;     // analysed problems, admitted in ticket order
   std::deque<ReqP> pose_q;
+  std::deque<ReqP> up_q;             // admitted problems awaiting their upload
+  int uploading = 0;                 // problems being uploaded now
+  std::vector<ReqP> uploaded;        // on the device, to join the batch at the next step
   std::vector<ReqP> active;
   std::deque<Completion> completing;  // scheduler thread only
   std::unordered_map<int64_t, ReqP> tickets;
   Arena arena;
   void *mem = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t up_stream = nullptr;   // uploads of admitted problems, beside the compute stream
   bool own_stream = false;
   int max_slots = 1;
   int precision = BA_PREC_F32;
   int64_t budget = 0;
   int64_t next_ticket = 1;
   bool stop = false;
-  std::thread th;
+  std::thread th, up_th;
   std::vector<std::thread> ana_th;
   Batch batch, fin_batch;
   hipEvent_t ev_step[kLookahead] = {};
@@ -199,12 +203,13 @@ struct ba_server {
   int fatal = BA_OK;
   void loop();
   void ana_loop();
+  void up_loop();
   void finish(const std::vector<ReqP> &done_now);
   Pinned take_pinned(size_t n);
   int complete(bool block);
   bool idle_locked() const {
-    return ana_q.empty() && analysing == 0 && ready.empty() && pose_q.empty() && active.empty() &&
-           completing.empty();
+    return ana_q.empty() && analysing == 0 && ready.empty() && pose_q.empty() && up_q.empty() &&
+           uploading == 0 && uploaded.empty() && active.empty() && completing.empty();
   }
 };
 
@@ -276,6 +281,52 @@ void ba_server::ana_loop() {
   }
 }
 
+// Uploads of admitted problems on their own stream and thread, so that the scheduler
+// keeps launching iterations meanwhile; a problem joins the batch once its copies are done.
+void ba_server::up_loop() {
+  while (true) {
+    ReqP r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_ana.wait(lk, [&] { return stop || !up_q.empty(); });
+      if (up_q.empty()) {
+        if (stop) return;
+        continue;
+      }
+      r = up_q.front();
+      up_q.pop_front();
+      ++uploading;
+    }
+    const ba_problem_desc d = r->desc();
+    int rc = r->dp.init(r->sy, &d, &r->opt, (char *)mem + r->off, up_stream);
+    if (rc == BA_OK) {
+      r->dp.pending_state = r->dp.fresh_state();
+      hipError_t e = hipMemcpyAsync(r->dp.view.st, &r->dp.pending_state, sizeof(LMState),
+                                    hipMemcpyHostToDevice, up_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(up_stream);
+      if (e != hipSuccess) rc = hip_fail(e, "server upload");
+    }
+    // what the device copy and the report still need is in dp; drop the rest
+    r->dp.staging_f.clear();
+    r->dp.staging_d.clear();
+    r->sy = Symbolic();
+    r->sy.C = r->dp.C;
+    r->sy.P = r->dp.P;
+    r->pts = std::vector<double>();
+    if (rc != BA_OK) {
+      r->rc = rc;
+      r->err = g_last_error;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      --uploading;
+      if (rc == BA_OK) uploaded.push_back(r);
+    }
+    if (rc != BA_OK) finish({r});
+    cv_work.notify_one();
+  }
+}
+
 // Hand over the problems whose result copies have landed.  block: wait for the oldest.
 int ba_server::complete(bool block) {
   while (!completing.empty()) {
@@ -314,7 +365,7 @@ void ba_server::loop() {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] {
         return (stop && idle_locked()) || !ready.empty() || !pose_q.empty() || !active.empty() ||
-               !completing.empty();
+               !completing.empty() || !uploaded.empty();
       });
       if (stop && idle_locked()) break;
       // pose requests of one step share one block; 512 bytes cover its alignment
@@ -329,7 +380,7 @@ void ba_server::loop() {
       // analysed problems in ticket order; one that does not fit holds back the later ones
       while (!ready.empty() && fatal == BA_OK) {
         ReqP r = ready.begin()->second;
-        if ((int)(active.size() + admitted.size()) >= max_slots) break;
+        if ((int)(active.size() + uploaded.size() + up_q.size() + uploading + admitted.size()) >= max_slots) break;
         size_t off;
         if (!arena.alloc(r->bytes, off)) break;
         r->off = off;
@@ -338,33 +389,15 @@ void ba_server::loop() {
         ready.erase(ready.begin());
       }
       peak = std::max(peak, arena.used);
-    }
-    std::vector<ReqP> failed;
-    for (auto &r : admitted) {
-      const ba_problem_desc d = r->desc();
-      int rc = r->dp.init(r->sy, &d, &r->opt, (char *)mem + r->off, stream);
-      if (rc == BA_OK) {
-        r->dp.pending_state = r->dp.fresh_state();
-        hipError_t e = hipMemcpyAsync(r->dp.view.st, &r->dp.pending_state, sizeof(LMState),
-                                      hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) rc = hip_fail(e, "server state upload");
-      }
-      // what the device copy and the report still need is in dp; drop the rest
-      r->sy = Symbolic();
-      r->sy.C = r->dp.C;
-      r->sy.P = r->dp.P;
-      r->pts = std::vector<double>();
-      if (rc != BA_OK) {
-        r->rc = rc;
-        r->err = g_last_error;
-        failed.push_back(r);
-      } else {
-        std::lock_guard<std::mutex> lk(mu);
-        active.push_back(r);
+      for (auto &r : admitted) up_q.push_back(r);
+      if (!admitted.empty()) cv_ana.notify_all();
+      // uploaded problems join the batch
+      if (!uploaded.empty()) {
+        active.insert(active.end(), uploaded.begin(), uploaded.end());
+        uploaded.clear();
         dirty = true;
       }
     }
-    if (!failed.empty()) finish(failed);
     if (!active.empty() && fatal == BA_OK) {
       if (dirty) {
         batch.clear();
@@ -406,14 +439,10 @@ void ba_server::loop() {
         if (rc == BA_OK && hipEventRecord(c.ev, stream) != hipSuccess) rc = BA_EDEVICE;
         if (rc != BA_OK) fatal = rc;
         {
-          // the blocks are free for later problems: their uploads follow these copies
-          // on the stream
+          // the blocks stay held until the copies have landed (finish releases them):
+          // uploads into a freed block run on another stream
           std::lock_guard<std::mutex> lk(mu);
           active = keep;
-          for (auto &r : fin) {
-            if (r->holds_block) arena.release(r->off, r->bytes);
-            r->holds_block = false;
-          }
         }
         if (rc == BA_OK) completing.push_back(std::move(c));
         else for (auto &b : c.bufs) if (b.p) pinned_free.push_back(b);
@@ -450,7 +479,7 @@ void ba_server::loop() {
       finish(pose_now);
     }
     if (fatal == BA_OK) {
-      const bool nothing_launched = admitted.empty() && pose_now.empty() && active.empty();
+      const bool nothing_launched = pose_now.empty() && active.empty();
       if (complete(nothing_launched) != BA_OK) fatal = BA_EDEVICE;
     }
     if (fatal != BA_OK) {
@@ -462,9 +491,13 @@ void ba_server::loop() {
         all.insert(all.end(), active.begin(), active.end());
         for (auto &kv : ready) all.push_back(kv.second);
         all.insert(all.end(), pose_q.begin(), pose_q.end());
+        all.insert(all.end(), up_q.begin(), up_q.end());
+        all.insert(all.end(), uploaded.begin(), uploaded.end());
         active.clear();
         ready.clear();
         pose_q.clear();
+        up_q.clear();
+        uploaded.clear();
       }
       for (auto &c : completing) {
         all.insert(all.end(), c.reqs.begin(), c.reqs.end());
@@ -502,10 +535,12 @@ int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precis
     s->own_stream = true;
   }
   hipError_t e = hipMalloc(&s->mem, (size_t)hbm_budget_bytes);
+  if (e == hipSuccess) e = hipStreamCreate(&s->up_stream);
   for (int i = 0; i < kLookahead && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&s->ev_step[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     if (s->mem) (void)hipFree(s->mem);
+    if (s->up_stream) (void)hipStreamDestroy(s->up_stream);
     for (auto &ev : s->ev_step)
       if (ev) (void)hipEventDestroy(ev);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -516,6 +551,7 @@ int ba_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t precis
   const unsigned hw = std::thread::hardware_concurrency();
   const int n_ana = (int)std::max(1u, std::min(8u, hw / 2));
   for (int i = 0; i < n_ana; ++i) s->ana_th.emplace_back([raw] { raw->ana_loop(); });
+  s->up_th = std::thread([raw] { raw->up_loop(); });
   s->th = std::thread([raw] { raw->loop(); });
   *out = s.release();
   return BA_OK;
@@ -656,8 +692,14 @@ void ba_server_destroy(ba_server *s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->cv_work.notify_all();
   }
-  if (s->th.joinable()) s->th.join();
+  if (s->th.joinable()) s->th.join();  // ends once everything admitted has finished
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_ana.notify_all();
+  }
+  if (s->up_th.joinable()) s->up_th.join();
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamDestroy(s->up_stream);
   for (auto &b : s->pinned_free) (void)hipHostFree(b.p);
   for (auto &ev : s->ev_step)
     if (ev) (void)hipEventDestroy(ev);
