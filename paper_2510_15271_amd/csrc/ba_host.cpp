@@ -700,14 +700,17 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
          ((int64_t)P + kDnRangePts - 1) / kDnRangePts});
     sy.dn_ts.assign((size_t)P * (nt + 1), 0);
     sy.dn_rcam.assign(sy.Nf, 0);
+    sy.dn_mask.assign((size_t)P * nt, 0);
     int32_t r = 0;
     for (int j = 0; j < P; ++j) {
       int32_t *ts = &sy.dn_ts[(size_t)j * (nt + 1)];
+      uint16_t *mk = &sy.dn_mask[(size_t)j * nt];
       int t = 0;
       for (int k = sy.pt_start[j]; k < sy.pt_start[j + 1]; ++k) {
         const int a = sy.free_idx[sy.obs_cam[k]];
         if (a < 0) continue;
         while (t <= a / kDnCams) ts[t++] = r;
+        mk[a / kDnCams] |= (uint16_t)(1u << (a % kDnCams));
         sy.dn_rcam[r++] = a;
       }
       while (t <= nt) ts[t++] = r;
@@ -767,6 +770,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.row_tot = L.take(sy.chunked || sy.dense ? Cf * 54 * 8 : 16);
   o.dn_ts = L.take(sy.dn_ts.size() * 4 + 4);
   o.dn_rcam = L.take(sy.dn_rcam.size() * 4 + 4);
+  o.dn_mask = L.take(sy.dn_mask.size() * 2 + 4);
   o.dn_pfac = L.take(sy.dense ? P * 9 * T : 16);
   o.dn_part = L.take(sy.dense ? (size_t)sy.dn_tiles * (sy.dn_tiles + 1) / 2 * sy.dn_split * kDnRows * kDnRows * T
                               : 16);
@@ -910,6 +914,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.row_tot = (double *)ptr(off.row_tot);
   pd.dn_ts = (const int32_t *)ptr(off.dn_ts);
   pd.dn_rcam = (const int32_t *)ptr(off.dn_rcam);
+  pd.dn_mask = (const uint16_t *)ptr(off.dn_mask);
   pd.dn_pfac = ptr(off.dn_pfac);
   pd.dn_part = ptr(off.dn_part);
   pd.prior_abs = sy.prior_abs;
@@ -1045,6 +1050,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
   chk(up(off.dn_ts, sy.dn_ts.data(), sy.dn_ts.size() * 4));
   chk(up(off.dn_rcam, sy.dn_rcam.data(), sy.dn_rcam.size() * 4));
+  chk(up(off.dn_mask, sy.dn_mask.data(), sy.dn_mask.size() * 2));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
   chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));
   chk(up(off.diag_pos, sy.diag_pos.data(), sy.diag_pos.size() * 4));

@@ -3596,9 +3596,11 @@ __device__ inline void dn_pair(int pair, int nt, int &ta, int &tb) {
 // One (tile pair, point range): Z tiles in LDS laid out [k / KI][row][k % KI] so that
 // the 64 lanes of an operand load read one contiguous run; four waves, each a 48 x 48
 // quarter of the 96 x 96 product (3 x 3 MFMA tiles of 16 x 16).  Thread (point jl,
-// sub) forms the Z blocks of records sub, sub + SUB, ... of its point in each tile;
-// the records of the next chunk are loaded into registers before the products of the
-// current one, so their latency hides behind the matrix cores.
+// sub) owns camera slots sub, sub + SUB, ... of its point in each tile and writes their
+// Z blocks, or zeros where the camera does not see the point (the point's camera mask
+// gives presence and the record's place in the point's range).  The records of the next
+// chunk are loaded into registers before the current chunk's products, so their latency
+// hides behind the matrix cores.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__ probs,
                                                      const Tile *__restrict__ tiles) {
@@ -3606,7 +3608,7 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   using E = typename M::E;
   using V = typename M::V;
   constexpr int KI = M::KI, PC = M::PC, K = 3 * PC, NKS = K / KI, SUB = 256 / PC, KL = KI / 4;
-  constexpr int NSLOT = kDnCams / SUB;  // records of one point and tile per thread
+  constexpr int NSLOT = kDnCams / SUB;  // camera slots of one point and tile per thread
   extern __shared__ __align__(16) double s_dyn[];
   E *za = (E *)s_dyn;       // [NKS][kDnRows][KI]
   E *zb = za + K * kDnRows;  // the same for tile tb (unused when ta == tb)
@@ -3620,7 +3622,7 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   dn_pair(pair, pd.dn_tiles, ta, tb);
   const bool diag = ta == tb;
   const int nsides = diag ? 1 : 2;
-  const int nt1 = pd.dn_tiles + 1;
+  const int nt = pd.dn_tiles, nt1 = pd.dn_tiles + 1;
   const int t = threadIdx.x;
   if (t < 2 * kDnCams) {
     const int side = t / kDnCams, la = t - kDnCams * side;
@@ -3643,16 +3645,16 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   const int rb0 = 3 * (wv >> 1), cb0 = 3 * (wv & 1);
   const int li = lane & 15, lq = lane >> 4;
   const int jl = t / SUB, sub = t - SUB * (t / SUB);
-  // the next chunk's records of this thread: stored Jacobian values and tile camera
+  // the next chunk's records of this thread's camera slots (stored Jacobian values)
   S nf[2][NSLOT][7];
-  int nla[2][NSLOT];
+  bool npr[2][NSLOT];
   T nlt[6];
   auto fetch = [&](int jc) {
     const int j = jc + jl;
 #pragma unroll
     for (int side = 0; side < 2; ++side)
 #pragma unroll
-      for (int q = 0; q < NSLOT; ++q) nla[side][q] = -1;
+      for (int q = 0; q < NSLOT; ++q) npr[side][q] = false;
     if (j >= j1) return;
 #pragma unroll
     for (int i = 0; i < 6; ++i) nlt[i] = pf[9 * (size_t)j + i];
@@ -3660,14 +3662,16 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
     for (int side = 0; side < 2; ++side) {
       if (side >= nsides) break;
       const int tt = side ? tb : ta;
-      const int r0 = pd.dn_ts[(size_t)j * nt1 + tt], r1 = pd.dn_ts[(size_t)j * nt1 + tt + 1];
+      const int r0 = pd.dn_ts[(size_t)j * nt1 + tt];
+      const uint32_t mk = pd.dn_mask[(size_t)j * nt + tt];
 #pragma unroll
       for (int q = 0; q < NSLOT; ++q) {
-        const int r = r0 + sub + SUB * q;
-        if (r < r1) {
+        const int la = sub + SUB * q;
+        if ((mk >> la) & 1u) {
+          const int r = r0 + __popc(mk & ((1u << la) - 1u));
 #pragma unroll
           for (int i = 0; i < 7; ++i) nf[side][q][i] = lin[r].f[i];
-          nla[side][q] = pd.dn_rcam[r] - tt * kDnCams;
+          npr[side][q] = true;
         }
       }
     }
@@ -3682,27 +3686,25 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   fetch(j0);
   for (int jc = j0; jc < j1; jc += PC) {
     __syncthreads();  // the previous chunk's products are done (and s_R is visible)
-    {
-      // zero the tiles with 16-byte stores, then write the chunk's Z blocks
-      float4 *z4 = (float4 *)za;
-      const int n4 = nsides * K * kDnRows * (int)sizeof(E) / 16;
-      for (int i = t; i < n4; i += 256) z4[i] = float4{0.f, 0.f, 0.f, 0.f};
-    }
-    __syncthreads();
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       if (side >= nsides) break;
       E *z = side ? zb : za;
 #pragma unroll
       for (int q = 0; q < NSLOT; ++q) {
-        const int la = nla[side][q];
-        if (la < 0) continue;
-        T f[7], Jc[12], Jp[6], Z[18];
+        const int la = sub + SUB * q;
+        T Z[18];
+        if (npr[side][q]) {
+          T f[7], Jc[12], Jp[6];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) f[i] = Codec<S>::dec(nf[side][q][i]);
-        jc_from(f, Jc);
-        jp_from(f, &s_R[side][la][0], Jp);
-        dense_z(Jc, Jp, nlt, Z);
+          for (int i = 0; i < 7; ++i) f[i] = Codec<S>::dec(nf[side][q][i]);
+          jc_from(f, Jc);
+          jp_from(f, &s_R[side][la][0], Jp);
+          dense_z(Jc, Jp, nlt, Z);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 18; ++i) Z[i] = T(0);
+        }
 #pragma unroll
         for (int m = 0; m < 6; ++m)
 #pragma unroll
@@ -3715,6 +3717,7 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
     __syncthreads();
     if (jc + PC < j1) fetch(jc + PC);  // in flight during the products below
     const E *zbb = diag ? za : zb;
+#pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const E *ab = za + (ks * kDnRows + li) * KI + lq * KL;
       const E *bb = zbb + (ks * kDnRows + li) * KI + lq * KL;
