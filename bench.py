@@ -356,8 +356,92 @@ print(json.dumps({"seconds": dt, "n_obs": p.n_obs, "iters": 1}))
                       f"{sec:.1f} s on 1 thread"}
 
 
+def cpu_serving_baseline(sizes, budget_s: float = 30.0) -> dict:
+    """The oracle on the serving streams, on the host: the pose-only GN oracle over a
+    pool of one single-threaded process per host core (the first 512 requests of the
+    4096-request stream, timed whole); and the explicit-Schur LM oracle (PCG 50 / 1e-6)
+    timed for one LM iteration on a sample of BA-stream requests at fixed size ranks,
+    fitted as seconds per observation pair (pairs ~ N (N / P - 1) / 2), extrapolated to
+    20 iterations of every request, and replayed as the saturated stream (all arrivals at
+    t = 0, first come first served) on as many single-threaded workers as host cores.
+    `sizes`: (n_obs, n_pts) of every BA-stream request in stream order."""
+    import numpy as np
+    code = r"""
+import json, os, sys, time
+import multiprocessing as mp
+sys.path.insert(0, %r)
+import numpy as np
+from synth import make_config3_problem, make_config3_sizes, make_config4_requests
+from oracle import ba_oracle as O
+
+def pose(q):
+    return O.pose_only_gn(q.K, q.q0, q.t0, q.X, q.uv, 1.0, 10)[2]
+
+if __name__ == "__main__":
+    n = os.cpu_count()
+    reqs = make_config4_requests(4096)[:512]
+    with mp.Pool(n) as pool:
+        pool.map(pose, reqs[:n])
+        t = time.perf_counter()
+        pool.map(pose, reqs, chunksize=8)
+        dt = time.perf_counter() - t
+    out = {"pose_requests": len(reqs), "pose_seconds": dt, "cores": n}
+    nc, npt = make_config3_sizes()
+    sample = json.loads(sys.argv[1])
+    times = []
+    for r in sample:
+        s = make_config3_problem(r, int(nc[r]), int(npt[r]))
+        p = O.Problem.from_scene(s)
+        t = time.perf_counter()
+        O.lm_schur(p, O.LMOptions(max_iters=1, solve="pcg", pcg_max_iters=50, pcg_rel_tol=1e-6))
+        times.append([r, p.n_obs, p.n_pts, time.perf_counter() - t])
+    out["ba_sample"] = times
+    print(json.dumps(out))
+""" % ROOT
+    nobs = np.array([x[0] for x in sizes], float)
+    npts = np.array([x[1] for x in sizes], float)
+    pairs = nobs * np.maximum(nobs / npts - 1.0, 0.0) / 2.0
+    order = np.argsort(pairs)
+    # seven requests at the 2nd-40th size percentiles keep the sample to tens of seconds
+    sample = [int(order[int(q * (len(order) - 1))]) for q in (0.02, 0.06, 0.10, 0.15, 0.20, 0.30, 0.40)]
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    try:
+        out = subprocess.run([sys.executable, "-c", code, json.dumps(sample)], env=env, capture_output=True,
+                             text=True, timeout=max(300.0, 10 * budget_s))
+        d = json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception as e:  # the baseline is reported, never required
+        return {"kind": "oracle", "sample": f"failed: {e}", **host_cpu()}
+    n = d["cores"]
+    res = {"kind": "oracle", "cores": n, **host_cpu(),
+           "pose_stream": {"requests_per_s": round(d["pose_requests"] / d["pose_seconds"], 1),
+                           "sample": f"the first {d['pose_requests']} requests of the 4096-request stream, "
+                                     f"10 GN iterations, one single-threaded process per core"}}
+    samp = np.array([[x[1], x[2], x[3]] for x in d["ba_sample"]], float)
+    sp = samp[:, 0] * np.maximum(samp[:, 0] / samp[:, 1] - 1.0, 0.0) / 2.0
+    c = float((sp * samp[:, 2]).sum() / (sp * sp).sum())  # seconds per pair per LM iteration
+    est = 20.0 * c * pairs  # seconds per request, 20 LM iterations
+    free_at = np.zeros(n)
+    lat = []
+    for e in est:  # saturated stream, first come first served on n workers
+        w = int(np.argmin(free_at))
+        free_at[w] += e
+        lat.append(free_at[w])
+    lat = np.sort(np.array(lat))
+    res["ba_stream"] = {"solves_per_s": round(len(est) / float(free_at.max()), 4),
+                        "p50_ms": round(1000 * float(np.percentile(lat, 50)), 1),
+                        "p99_ms": round(1000 * float(np.percentile(lat, 99)), 1),
+                        "seconds_per_pair_iteration": c,
+                        "sample": f"one LM iteration of requests {sample} (the 2nd to 40th percentiles of "
+                                  f"pair count), {', '.join(f'{x[3]:.2f} s' for x in d['ba_sample'])}; "
+                                  f"extrapolated: seconds per observation pair fitted, 20 iterations "
+                                  f"of every request, saturated stream replayed on {n} workers"}
+    return res
+
+
 def serving_leg(ba, n_ba: int, precision: str, precisions=("f16j", "bf16j"), slots: int = 16,
-                poisson=(0.5, 0.8)) -> dict:
+                poisson=(0.5, 0.8), cpu: bool = True) -> dict:
     """p50/p99 latency (submission to result on the host) and throughput of the
     continuous-batching server under an 8 GB budget: the 4096-request pose-only
     localization stream submitted at once, and the first n_ba problems of the
@@ -423,6 +507,7 @@ def serving_leg(ba, n_ba: int, precision: str, precisions=("f16j", "bf16j"), slo
                         "schur_forms": "dense co-visibility (chosen per problem)"}
     out["ba_stream_saturated"] = summary(wall, st, refused)
     rms = np.array([r["rms_px"] if r else np.nan for r in base])
+    sizes = [(int(d.desc.n_obs), int(d.desc.n_pts)) for d in descs]
     out["ba_stream_saturated"]["final_rms_px_median"] = round(float(np.nanmedian(rms)), 6)
     for frac in poisson:
         rng = np.random.default_rng(3000 + int(round(10 * frac)))
@@ -436,6 +521,9 @@ def serving_leg(ba, n_ba: int, precision: str, precisions=("f16j", "bf16j"), slo
         out[f"ba_stream_saturated_{prec}"] = {**summary(wall, st, refused),
                                               "final_rms_diff_vs_" + precision + "_px_max": float(np.nanmax(d)),
                                               "final_rms_diff_vs_" + precision + "_px_median": float(np.nanmedian(d))}
+    if cpu:
+        print("bench: timing the oracle on the serving streams", flush=True, file=sys.stderr)
+        out["cpu_baseline"] = cpu_serving_baseline(sizes)
     return out
 
 
@@ -664,7 +752,8 @@ def main():
         print("bench: serving streams", flush=True, file=sys.stderr)
         out["serving"] = serving_leg(ba, args.serving, args.precision,
                                      [x for x in args.serving_precisions.split(",") if x], args.serving_slots,
-                                     [float(x) for x in args.serving_poisson.split(",") if x])
+                                     [float(x) for x in args.serving_poisson.split(",") if x],
+                                     not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", flush=True, file=sys.stderr)
         out["cpu_baseline"] = cpu_baseline()
