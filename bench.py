@@ -542,6 +542,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels instead of replaying a graph")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time only whole steps (lets solves replay their graph)")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="no warm-up solve enqueued kernel by kernel: every solve replays graphs "
+                         "(for a kernel trace of the mode the product runs)")
     ap.add_argument("--serving", type=int, default=512, metavar="N",
                     help="BA problems of the mixed-size stream in the serving leg (0: pose stream only, -1: skip)")
     ap.add_argument("--serving-precisions", default="f16j,bf16j",
@@ -609,14 +612,21 @@ def main():
     info = prob.info()
     names = list(prob.kernel_times().keys())
 
-    # warm-up; the first one also times every kernel to find the dominant one
-    prob.set_profiling(-1)
-    for w in range(max(1, args.warmup)):
-        prob.reset().solve()
-        if w == 0:
-            kt = prob.kernel_times()
-            prob.set_profiling(0)
-    dominant = max(kt, key=lambda k: kt[k][0])
+    # warm-up; the first one also times every kernel to find the dominant one (with
+    # --graph-only no launch is enqueued outside a graph: the PCG is taken as dominant)
+    if args.graph_only:
+        for w in range(max(1, args.warmup)):
+            prob.reset().solve()
+        kt = {k: (0.0, 0) for k in names}
+        dominant = "pcg_cg"
+    else:
+        prob.set_profiling(-1)
+        for w in range(max(1, args.warmup)):
+            prob.reset().solve()
+            if w == 0:
+                kt = prob.kernel_times()
+                prob.set_profiling(0)
+        dominant = max(kt, key=lambda k: kt[k][0])
     if args.profile_all:
         tot = sum(v[0] for v in kt.values())
         for k, (ms, n) in sorted(kt.items(), key=lambda x: -x[1][0]):
@@ -664,7 +674,7 @@ def main():
         bytes_model = "design: each input and output of the kernel once"
         dbytes = per_unit
     abytes = per_unit * units
-    achieved = abytes / avg_launch_s / 1e9 if abytes else None
+    achieved = abytes / avg_launch_s / 1e9 if abytes and avg_launch_s > 0 else None
     traffic = None
     tname = f"{dominant}_resident" if resident else dominant
     tfile = os.path.join(ROOT, "profiles", f"traffic_{tname}_{args.workload}_{args.precision}.json")
@@ -679,8 +689,8 @@ def main():
                 "algorithmic_bytes": round(abytes), "bytes_per_unit": round(per_unit),
                 "units_per_launch": round(units, 3), "bytes_model": bytes_model,
                 "design_bytes": round(dbytes),
-                "design_frac": round(dbytes / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)}
-    if resident:
+                "design_frac": round(dbytes / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4) if avg_launch_s > 0 else None}
+    if resident and units > 0:
         roofline["avg_pcg_iteration_us"] = round(avg_launch_s * 1e6 / units, 3)
     # the whole LM loop against the same model (device time of the iteration loop)
     lm_bytes = model_bytes_lm_iteration(info, args.precision, pcg_per_lm)
