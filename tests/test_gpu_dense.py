@@ -133,3 +133,53 @@ def test_dense_problems_in_a_served_mix(balib):
         _say(s.name, "form", info["schur_form"], "mix", r["iter_cost"][-1], "alone", a["iter_cost"][-1])
         assert np.array_equal(r["iter_cost"], a["iter_cost"])
         assert np.array_equal(r["X"], a["X"]) and np.array_equal(r["t"], a["t"])
+
+
+def test_dense_with_resident_pcg_equals_per_launch(balib):
+    """The dense form under the resident PCG (rows of 24 blocks, 6 tiles): the same
+    run bit for bit as the launch-per-iteration PCG, in FP64 and FP32."""
+    s = make_arc_scene(25, 2000, seed=79)
+    for prec in ("f64", "f32"):
+        out = []
+        for flags in (0, 16):
+            info, r = _run(balib, s, max_iters=6, precision=prec, flags=flags)
+            out.append((info, r))
+        (ia, a), (ib, b) = out
+        assert ia["schur_form"] == ib["schur_form"] == 2
+        assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == 1
+        assert np.array_equal(a["iter_cost"], b["iter_cost"])
+        assert np.array_equal(a["X"], b["X"]) and np.array_equal(a["q"], b["q"])
+        assert list(a["pcg_iters"]) == list(b["pcg_iters"])
+
+
+def test_dense_with_pose_priors_f64(balib):
+    """Absolute and sequential pose priors (Sec. 4.3 objective) with the dense form,
+    FP64: every C_n within 1e-9 of the explicit-Schur oracle."""
+    s = make_arc_scene(18, 1200, seed=80)
+    kw = dict(prior_abs=20.0, prior_seq=500.0, seq_k=3)
+    ref = O.lm_schur(O.Problem.from_scene(s, **kw), O.LMOptions(max_iters=8, solve="exact"))
+    info, res = _run(balib, s, max_iters=8, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64",
+                     prior_abs=20.0, prior_seq=500.0, prior_seq_k=3)
+    assert info["schur_form"] == 2
+    rel = np.abs(res["iter_cost"] - np.array(ref.iter_cost)) / np.array(ref.iter_cost)
+    _say("dense priors rel", rel.max())
+    assert rel.max() <= 1e-9
+
+
+def test_dense_refine_f64_matches_oracle_round_by_round(balib):
+    """The two-stage refinement (culling with midpoint re-triangulation) on an arc
+    scene with 10 % outliers in the dense form, FP64: each round's cost within 1e-9 of
+    the oracle's, the active counts equal and the final mask identical."""
+    s = make_arc_scene(16, 1500, seed=81, outlier_frac=0.1, huber_delta=1.0)
+    stages = [(1.0, 8.0), (0.0, 3.0)]
+    ref, hist = O.refine(O.Problem.from_scene(s), stages, 2, O.LMOptions(max_iters=6, solve="exact"))
+    p = balib.Problem.from_scene(s, max_iters=6, pcg_max_iters=400, pcg_rel_tol=1e-14, precision="f64")
+    assert p.info()["schur_form"] == 2
+    dh = p.refine(stages, 2)
+    act = p.active()
+    p.close()
+    for h, (si, rd, cost, na, npt) in zip(dh, hist):
+        _say("round", si, rd, "cost", h["cost"], cost, "obs", h["n_active_obs"], na)
+        assert abs(h["cost"] - cost) <= 1e-9 * cost
+        assert (h["n_active_obs"], h["n_active_pts"]) == (na, npt)
+    assert np.array_equal(act.astype(bool), ref.active)
