@@ -273,6 +273,13 @@ typedef struct {
   int32_t pcg_resident;   /* 1: BA_FLAG_PCG_RESIDENT was asked for and the problem fits it */
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);
+/* The symbolic analysis of ba_create alone, for planning: validates d and opt as
+   ba_create does and fills *info (the sizes ba_get_info would report; pcg_resident is
+   1 only where a device is present to check residency) and *bytes (the device bytes
+   ba_create would allocate, the server's admission charge).  Uploads nothing and needs
+   no device: with none present, the Schur form is chosen as for a gfx950 device.
+   info and bytes may be NULL. */
+int ba_analyse(const ba_problem_desc *d, const ba_options *opt, ba_problem_info *info, int64_t *bytes);
 /* Device bytes held by the problem (the admission byte model of the server). */
 int64_t ba_problem_bytes(const ba_problem *p);
 void ba_destroy(ba_problem *p);

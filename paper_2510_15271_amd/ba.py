@@ -145,6 +145,8 @@ def lib():
     L.ba_reset.argtypes = [vp]
     L.ba_get_result.argtypes = [vp, vp, vp, C.POINTER(Report)]
     L.ba_get_info.argtypes = [vp, C.POINTER(ProblemInfo)]
+    L.ba_analyse.argtypes = [C.POINTER(ProblemDesc), C.POINTER(Options), C.POINTER(ProblemInfo),
+                             C.POINTER(i64)]
     L.ba_refine.argtypes = [vp, i32, C.POINTER(RefineStage), i32, C.POINTER(RefineRound)]
     L.ba_pose_graph_create.argtypes = [C.POINTER(PoseGraphDesc), C.POINTER(Options), vp, C.POINTER(vp)]
     L.ba_rig_create.argtypes = [C.POINTER(RigDesc), C.POINTER(Options), vp, C.POINTER(vp)]
@@ -560,6 +562,14 @@ def pose_batch_noalloc(requests, iters=10, huber_delta=1.0, stream=None):
                                        status.ctypes.data_as(C.POINTER(C.c_int32)),
                                        cost.ctypes.data_as(C.POINTER(C.c_double))))
     return dict(q=poses[:, :4], t=poses[:, 4:], status=status, cost=cost)
+
+
+def analyse(desc: "_Desc", opts: "Options"):
+    """ba_analyse: the symbolic analysis alone; returns (info dict, device bytes)."""
+    i = ProblemInfo()
+    b = C.c_int64()
+    _check(lib().ba_analyse(C.byref(desc.desc), C.byref(opts), C.byref(i), C.byref(b)))
+    return {f: getattr(i, f) for f, _ in ProblemInfo._fields_}, b.value
 
 
 class Server:

@@ -2094,22 +2094,39 @@ int ba_get_active(const ba_problem *p, uint8_t *active_out) {
   return BA_OK;
 }
 
+}  // extern "C"
+
+static void fill_info(const Symbolic &sy, int64_t n_pairs, int precision, ba_problem_info *out) {
+  out->n_cams = sy.C;
+  out->n_free_cams = sy.Cf;
+  out->n_pts = sy.P;
+  out->n_obs = sy.N;
+  out->n_pairs = n_pairs;
+  out->n_up_blocks = sy.n_up;
+  out->nnzb = sy.nnzb;
+  out->n_free_obs = sy.Nf;
+  out->precision = precision;
+  out->schur_form = sy.dense ? 2 : sy.chunked ? 1 : 0;
+  out->n_chunks = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
+  out->n_entries = (int64_t)sy.ent_tgt.size();
+  out->pcg_rows = sy.pcg_rows;
+  out->pcg_resident = sy.pcg_resident ? 1 : 0;
+}
+
+extern "C" {
+
 int ba_get_info(const ba_problem *p, ba_problem_info *out) {
   if (!p || !out) return fail(BA_EINVAL, "NULL argument");
-  out->n_cams = p->sy.C;
-  out->n_free_cams = p->sy.Cf;
-  out->n_pts = p->sy.P;
-  out->n_obs = p->sy.N;
-  out->n_pairs = p->n_pairs;
-  out->n_up_blocks = p->sy.n_up;
-  out->nnzb = p->sy.nnzb;
-  out->n_free_obs = p->sy.Nf;
-  out->precision = p->dp.precision;
-  out->schur_form = p->sy.dense ? 2 : p->sy.chunked ? 1 : 0;
-  out->n_chunks = p->sy.chunked ? (int32_t)p->sy.ch_pt.size() - 1 : 0;
-  out->n_entries = (int64_t)p->sy.ent_tgt.size();
-  out->pcg_rows = p->sy.pcg_rows;
-  out->pcg_resident = p->sy.pcg_resident ? 1 : 0;
+  fill_info(p->sy, p->n_pairs, p->dp.precision, out);
+  return BA_OK;
+}
+
+int ba_analyse(const ba_problem_desc *d, const ba_options *opt, ba_problem_info *info, int64_t *bytes) {
+  if (!d || !opt) return fail(BA_EINVAL, "NULL argument");
+  Symbolic sy;
+  if (int e = analyse(d, opt, sy)) return e;
+  if (info) fill_info(sy, sy.n_pairs, opt->precision, info);
+  if (bytes) *bytes = (int64_t)DevProblem::bytes_for(sy, opt->precision, opt->max_iters);
   return BA_OK;
 }
 

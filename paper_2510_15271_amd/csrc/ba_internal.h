@@ -277,9 +277,11 @@ size_t compute_bytes(int precision);
 
 // Query device limits that select kernel forms; call before any graph capture.
 int prepare_kernels();
-// Dynamic LDS a workgroup may use on the current device (bytes).
+// Dynamic LDS a workgroup may use on the current device (bytes); a gfx950's when no
+// device is present.
 size_t device_lds_limit();
-// Whether the dense co-visibility form can run on the current device.
+// Whether the dense co-visibility form can run on the current device (on a gfx950 when
+// no device is present).
 bool dense_form_available();
 // Whether the PCG runs in its one-reduction form (one launch per iteration) for
 // a plan whose longest tile column list is max_tcols.

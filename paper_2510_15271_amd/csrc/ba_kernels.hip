@@ -3856,10 +3856,14 @@ int prepare_kernels() {
   return 0;
 }
 
-bool dense_form_available() { return prepare_kernels() == 0 && g_dense_ok; }
+// With no device present (an analysis for planning), the forms are chosen as for a
+// gfx950 device: 160 KB of LDS per workgroup, so both the chunk and the dense form fit.
+constexpr size_t kGfx950Lds = 160 * 1024;
+
+bool dense_form_available() { return prepare_kernels() == 0 ? g_dense_ok : true; }
 
 size_t device_lds_limit() {
-  if (prepare_kernels() != 0) return 0;
+  if (prepare_kernels() != 0) return kGfx950Lds;
   return g_lds_limit;
 }
 
