@@ -433,6 +433,9 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
     free_pairs += (int64_t)nfj * (nfj - 1) / 2;
   }
   const int prec = opt->precision;
+  // points with long tracks (16 or more observations on average) take tiles of fewer
+  // points, so that a problem spreads over more workgroups, and wave-scan sums
+  sy.pt_tile = N >= 16 * (int64_t)std::max(P, 1) ? kPtTileLong : kPtTile;
   // the dense co-visibility form: forced by its flag, or chosen when tracks span at
   // least a quarter of the free cameras on average, the pairs are many per block of S
   // and most camera pairs share points (never with pair lists asked for)
@@ -736,7 +739,7 @@ struct Layout {
 size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offsets &o) {
   const size_t T = compute_bytes(precision);
   const size_t C = sy.C, Cf = sy.Cf, P = sy.P, N = sy.N;
-  const size_t npt = (P + kPtTile - 1) / kPtTile;
+  const size_t npt = (P + sy.pt_tile - 1) / sy.pt_tile;
   const size_t npcg = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   const size_t ncam = (C + kCamTile - 1) / kCamTile;
   Layout L;
@@ -873,13 +876,14 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
   pd.n_fsh_tiles = sy.chunked || sy.dense ? (Cf + 63) / 64 : 0;
   pd.dense = sy.dense ? 1 : 0;
-  pd.seg_scan = (int64_t)N >= 16 * (int64_t)std::max(P, 1) ? 1 : 0;
+  pd.seg_scan = sy.pt_tile == kPtTileLong ? 1 : 0;
   pd.dn_tiles = sy.dense ? sy.dn_tiles : 0;
   pd.dn_pairs = sy.dense ? sy.dn_tiles * (sy.dn_tiles + 1) / 2 : 0;
   pd.dn_split = sy.dense ? sy.dn_split : 0;
   pd.n_up = sy.n_up;
   pd.nnzb = sy.nnzb;
-  pd.n_pt_tiles = (P + kPtTile - 1) / kPtTile;
+  pd.n_pt_tiles = (P + sy.pt_tile - 1) / sy.pt_tile;
+  pd.pt_tile = sy.pt_tile;
   pd.n_pcg_tiles = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   pd.pcg_rows = sy.pcg_rows;
   pd.pcg_resident = sy.pcg_resident ? 1 : 0;

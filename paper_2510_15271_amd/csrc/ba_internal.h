@@ -13,7 +13,8 @@
 
 namespace bax {
 
-constexpr int kPtTile = 256;     // points per point-major tile (one workgroup)
+constexpr int kPtTile = 256;     // points per point-major tile (one workgroup), at most
+constexpr int kPtTileLong = 32;  // ... for problems whose points have long tracks
 constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile (one per thread)
 constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile, dense rows
 constexpr int kPcgRowsSparse = 16;  // rows per PCG tile when rows hold few blocks
@@ -102,6 +103,7 @@ struct ProbDev {
   int32_t n_fsh_tiles;   // camera-finish tiles (chunk and dense forms): 64 cameras each
   int32_t seg_scan;      // 1: tracks are long (at least 16 observations per point on
                          // average): per-point sums over observations by wave scans
+  int32_t pt_tile;       // points per point tile: kPtTile, or kPtTileLong for long tracks
   int32_t dense;         // 1: dense co-visibility Schur form
   int32_t dn_tiles;      // camera tiles (kDnCams free cameras each)
   int32_t dn_pairs;      // tile pairs (a <= b)

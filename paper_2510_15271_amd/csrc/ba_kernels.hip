@@ -452,8 +452,8 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
   if (!lm_active(st) || !st->relin) return;
   const int cur = st->cur;
   const T delta = T(st->huber_delta);
-  const int j0 = tl.idx * kPtTile;
-  const int j1 = min(pd.P, j0 + kPtTile);
+  const int j0 = tl.idx * pd.pt_tile;
+  const int j1 = min(pd.P, j0 + pd.pt_tile);
   const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
 
   __shared__ T s_acc[kPtTile][9];
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(256) void k_point_prep(const ProbDev *__restrict__ 
   LMState *st = pd.st;
   if (!lm_active(st)) return;
   const double lam = st->lambda;
-  const int j0 = tl.idx * kPtTile;
-  const int j1 = min(pd.P, j0 + kPtTile);
+  const int j0 = tl.idx * pd.pt_tile;
+  const int j1 = min(pd.P, j0 + pd.pt_tile);
   __shared__ T s_vi[kPtTile][6];
   const T *V = (const T *)pd.V;
   const T *Dp = (const T *)pd.Dp;
@@ -2545,8 +2545,8 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
   const int cur = st->cur;
   const double lam = st->lambda;
   const T delta = T(st->huber_delta);
-  const int j0 = tl.idx * kPtTile;
-  const int j1 = min(pd.P, j0 + kPtTile);
+  const int j0 = tl.idx * pd.pt_tile;
+  const int j1 = min(pd.P, j0 + pd.pt_tile);
   const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
   __shared__ T s_acc[kPtTile][3];
   __shared__ T s_c[kObsChunk][3];
@@ -2746,8 +2746,8 @@ __global__ __launch_bounds__(256) void k_eval(const ProbDev *__restrict__ probs,
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   const int cur = st->cur;
-  const int j0 = tl.idx * kPtTile;
-  const int j1 = min(pd.P, j0 + kPtTile);
+  const int j0 = tl.idx * pd.pt_tile;
+  const int j1 = min(pd.P, j0 + pd.pt_tile);
   const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
   const T *Kall = (const T *)pd.K;
   const T *uv = (const T *)pd.obs_uv;
@@ -2917,14 +2917,14 @@ __device__ bool tri_dlt(int n, Get get, double out[3]) {
 template <class T>
 __global__ __launch_bounds__(256) void k_cull(const ProbDev *__restrict__ probs,
                                               const Tile *__restrict__ tiles, double tau2, int method) {
-  static_assert(kPtTile == 256, "one thread per point of a tile");
+  static_assert(kPtTile == 256, "one thread per point of the largest tile");
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   const int cur = pd.st->cur;
-  const int j = tl.idx * kPtTile + (int)threadIdx.x;
+  const int j = tl.idx * pd.pt_tile + (int)threadIdx.x;
   __shared__ double s_red[4];
   int n_act = 0;
-  if (j < pd.P) {
+  if ((int)threadIdx.x < pd.pt_tile && j < pd.P) {
     const int k0 = pd.pt_start[j], k1 = pd.pt_start[j + 1];
     const T *Kall = (const T *)pd.K;
     const T *uv = (const T *)pd.obs_uv;
@@ -3396,8 +3396,8 @@ __global__ __launch_bounds__(256) void k_dense_prep(const ProbDev *__restrict__ 
   const ProbDev &pd = probs[tl.prob];
   const LMState *st = pd.st;
   if (!lm_active(st)) return;
-  const int j = tl.idx * kPtTile + (int)threadIdx.x;
-  if (j >= pd.P) return;
+  const int j = tl.idx * pd.pt_tile + (int)threadIdx.x;
+  if ((int)threadIdx.x >= pd.pt_tile || j >= pd.P) return;
   const double lam = st->lambda;
   const T *V = (const T *)pd.V;
   const T *Dp = (const T *)pd.Dp;

@@ -37,6 +37,7 @@ struct Symbolic {
   int64_t n_pairs = 0;            // observation pairs of one point in two free cameras
   bool chunked = false;           // point-chunk Schur form (else pair lists or dense)
   bool dense = false;             // dense co-visibility Schur form
+  int32_t pt_tile = kPtTile;      // points per point tile (kPtTileLong for long tracks)
   int32_t dn_tiles = 0, dn_split = 0;
   std::vector<int32_t> dn_ts;     // [P][dn_tiles + 1] (dense form)
   std::vector<int32_t> dn_rcam;   // [Nf] (dense form)
