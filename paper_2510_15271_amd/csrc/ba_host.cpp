@@ -434,7 +434,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   }
   const int prec = opt->precision;
   // points with long tracks (16 or more observations on average) take tiles of fewer
-  // points, so that a problem spreads over more workgroups, and wave-scan sums
+  // points, so that a problem spreads over more workgroups
   sy.pt_tile = N >= 16 * (int64_t)std::max(P, 1) ? kPtTileLong : kPtTile;
   // the dense co-visibility form: forced by its flag, or chosen when tracks span at
   // least a quarter of the free cameras on average, the pairs are many per block of S
@@ -876,7 +876,6 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.n_fin_tiles = sy.chunked && sy.Nf > 0 ? Cf : 0;
   pd.n_fsh_tiles = sy.chunked || sy.dense ? (Cf + 63) / 64 : 0;
   pd.dense = sy.dense ? 1 : 0;
-  pd.seg_scan = sy.pt_tile == kPtTileLong ? 1 : 0;
   pd.dn_tiles = sy.dense ? sy.dn_tiles : 0;
   pd.dn_pairs = sy.dense ? sy.dn_tiles * (sy.dn_tiles + 1) / 2 : 0;
   pd.dn_split = sy.dense ? sy.dn_split : 0;

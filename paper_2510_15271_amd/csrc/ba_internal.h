@@ -101,8 +101,6 @@ struct ProbDev {
   int32_t n_red_tiles;   // reduction tiles (chunk form): four upper blocks each
   int32_t n_fin_tiles;   // camera-row tiles (chunk form): one camera each
   int32_t n_fsh_tiles;   // camera-finish tiles (chunk and dense forms): 64 cameras each
-  int32_t seg_scan;      // 1: tracks are long (at least 16 observations per point on
-                         // average): per-point sums over observations by wave scans
   int32_t pt_tile;       // points per point tile: kPtTile, or kPtTileLong for long tracks
   int32_t dense;         // 1: dense co-visibility Schur form
   int32_t dn_tiles;      // camera tiles (kDnCams free cameras each)

@@ -139,8 +139,8 @@ __device__ inline T wave_sum(T v) {
 }
 
 // Adds one pass of kObsChunk observations' NV values (c; jl = their point in the
-// tile, -1 for none) into the points' accumulators s_acc, for problems whose points
-// have long tracks.  The observations of one point are consecutive, so an inclusive
+// tile, -1 for none) into the points' accumulators s_acc.  The observations of one
+// point are consecutive, so an inclusive
 // segmented scan across each wave (six shuffle steps) leaves every wave's part of a
 // point at its last lane; the chunk's last lane of the point then adds the point's
 // wave parts in wave order.  s_c and s_loc are scratch of kObsChunk rows.
@@ -532,22 +532,7 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
       const int cpos = pd.obs_rpos[k];  // records are kept for free cameras only
       if (cpos >= 0) lin[cpos] = rec;
     }
-    if (pd.seg_scan) {
-      seg_add_scan<T, 9>(c, jl, s_acc, s_c, s_loc);
-      continue;
-    }
-    s_loc[threadIdx.x] = jl;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) s_c[threadIdx.x][i] = c[i];
-    __syncthreads();
-    if (jl >= 0 && (threadIdx.x == 0 || s_loc[threadIdx.x - 1] != jl)) {
-      for (int t = threadIdx.x + 1; t < kObsChunk && s_loc[t] == jl; ++t)
-#pragma unroll
-        for (int i = 0; i < 9; ++i) c[i] += s_c[t][i];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) s_acc[jl][i] += c[i];
-    }
-    __syncthreads();
+    seg_add_scan<T, 9>(c, jl, s_acc, s_c, s_loc);
   }
   T *V = (T *)pd.V;
   T *gp = (T *)pd.gp;
@@ -2585,22 +2570,7 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
         for (int m = 0; m < 3; ++m) c[m] = Jp[m] * u0 + Jp[3 + m] * u1;
       }
     }
-    if (pd.seg_scan) {
-      seg_add_scan<T, 3>(c, jl, s_acc, s_c, s_loc);
-      continue;
-    }
-    s_loc[threadIdx.x] = jl;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) s_c[threadIdx.x][i] = c[i];
-    __syncthreads();
-    if (jl >= 0 && (threadIdx.x == 0 || s_loc[threadIdx.x - 1] != jl)) {
-      for (int t = threadIdx.x + 1; t < kObsChunk && s_loc[t] == jl; ++t)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) c[i] += s_c[t][i];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) s_acc[jl][i] += c[i];
-    }
-    __syncthreads();
+    seg_add_scan<T, 3>(c, jl, s_acc, s_c, s_loc);
   }
   // phase 2: dp_j, trial point, point part of the predicted decrease
   const T *Vinv = (const T *)pd.Vinv;
