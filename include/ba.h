@@ -113,6 +113,12 @@ typedef struct {
    other long kernels beside one.  A barrier that times out (about a second) stops the
    solve with status BA_STATUS_PCG_SYNC instead of waiting forever. */
 #define BA_FLAG_PCG_RESIDENT 16
+/* BA_FLAG_PCG_COOPERATIVE: with BA_FLAG_PCG_RESIDENT, start the resident solve as a
+   cooperative launch, so the runtime itself places every workgroup at once (or fails the
+   launch) instead of relying on the occupancy count alone; for callers that share the
+   device with other work.  Costs about 20 us per linear solve on an idle device.  No
+   effect without BA_FLAG_PCG_RESIDENT or where the resident form does not fit. */
+#define BA_FLAG_PCG_COOPERATIVE 64
 /* BA_FLAG_DENSE_SCHUR: form the Schur complement in its dense co-visibility form, used
    by default when at most 1024 cameras are free, a point is seen by at least a quarter
    of them on average, the observation pairs outnumber 32 per block of S and at least
@@ -270,7 +276,8 @@ typedef struct {
   int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for many sparse
                              rows (at least 1024 free cameras, at most 24 blocks per row
                              on average) 16, or 32 beyond 8192 free cameras            */
-  int32_t pcg_resident;   /* 1: BA_FLAG_PCG_RESIDENT was asked for and the problem fits it */
+  int32_t pcg_resident;   /* 1: BA_FLAG_PCG_RESIDENT was asked for and the problem fits it;
+                             2: the same, started as a cooperative launch                  */
 } ba_problem_info;
 int ba_get_info(const ba_problem *p, ba_problem_info *out);
 /* The symbolic analysis of ba_create alone, for planning: validates d and opt as

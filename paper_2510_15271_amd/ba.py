@@ -189,6 +189,7 @@ FLAG_PAIR_LISTS = 4
 FLAG_PCG_WIDE = 8
 FLAG_PCG_RESIDENT = 16
 FLAG_DENSE_SCHUR = 32
+FLAG_PCG_COOPERATIVE = 64
 
 
 def options(max_iters=10, pcg_max_iters=50, pcg_rel_tol=1e-6, lambda0=1e-4, huber_delta=0.0,

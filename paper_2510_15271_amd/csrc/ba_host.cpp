@@ -127,7 +127,7 @@ int check_options(const ba_options *o, bool pose_only) {
   if (o->precision < BA_PREC_F64 || o->precision > BA_PREC_BF16J)
     return fail(BA_EINVAL, "unknown precision %d", o->precision);
   if (o->flags & ~(BA_FLAG_NO_GRAPH | BA_FLAG_PAIR_LISTS | BA_FLAG_PCG_WIDE | BA_FLAG_PCG_RESIDENT |
-                   BA_FLAG_DENSE_SCHUR))
+                   BA_FLAG_DENSE_SCHUR | BA_FLAG_PCG_COOPERATIVE))
     return fail(BA_EINVAL, "unknown option flags 0x%x", o->flags);
   if (!pose_only) {
     if (!(o->prior_abs >= 0.0) || !std::isfinite(o->prior_abs))
@@ -689,6 +689,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   if (sy.pcg_rows == kPcgRowsSparse && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRows);
   sy.pcg_resident = (opt->flags & BA_FLAG_PCG_RESIDENT) &&
                     resident_pcg_fits(prec, sy.pcg_rows, (Cf + sy.pcg_rows - 1) / sy.pcg_rows, sy.max_tcols);
+  sy.pcg_coop = sy.pcg_resident && (opt->flags & BA_FLAG_PCG_COOPERATIVE);
   if (sy.dense) {
     // first record of each point in each camera tile: the point's records in the tile
     // are the range [ts[t], ts[t + 1]) (records are point-major, in camera order), and
@@ -885,7 +886,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.pt_tile = sy.pt_tile;
   pd.n_pcg_tiles = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   pd.pcg_rows = sy.pcg_rows;
-  pd.pcg_resident = sy.pcg_resident ? 1 : 0;
+  pd.pcg_resident = sy.pcg_resident ? (sy.pcg_coop ? 2 : 1) : 0;
   pd.n_cam_tiles = (C + kCamTile - 1) / kCamTile;
   pd.K = ptr(off.K);
   pd.free_idx = (const int32_t *)ptr(off.free_idx);
@@ -2113,7 +2114,7 @@ static void fill_info(const Symbolic &sy, int64_t n_pairs, int precision, ba_pro
   out->n_chunks = sy.chunked ? (int32_t)sy.ch_pt.size() - 1 : 0;
   out->n_entries = (int64_t)sy.ent_tgt.size();
   out->pcg_rows = sy.pcg_rows;
-  out->pcg_resident = sy.pcg_resident ? 1 : 0;
+  out->pcg_resident = sy.pcg_resident ? (sy.pcg_coop ? 2 : 1) : 0;
 }
 
 extern "C" {

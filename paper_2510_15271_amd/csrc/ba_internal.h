@@ -95,7 +95,7 @@ struct ProbDev {
   int32_t n_pt_tiles, n_pcg_tiles, n_cam_tiles;
   int32_t max_tcols;     // longest tile column list
   int32_t pcg_rows;      // rows per PCG tile: kPcgRows, kPcgRowsSparse or kPcgRowsMax
-  int32_t pcg_resident;  // 1: the whole PCG runs in one launch with grid barriers (k_cg_run)
+  int32_t pcg_resident;  // 1: the whole PCG runs in one launch with grid barriers (k_cg_run); 2: launched cooperatively
   int32_t chunked;       // 1: point-chunk Schur form, 0: pair-list form
   int32_t n_ch;          // point chunks (chunk form)
   int32_t n_red_tiles;   // reduction tiles (chunk form): four upper blocks each

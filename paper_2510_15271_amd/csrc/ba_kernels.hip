@@ -3937,7 +3937,13 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
     if (resident) {
       const void *f = CgStep<T>::resident(bp.pcg_rows);
       void *args[] = {(void *)&bp.single, (void *)&pcg_max};
-      le = hipLaunchKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, cg_run_lds_bytes(max_tcols, sizeof(T)), s);
+      const unsigned lds = (unsigned)cg_run_lds_bytes(max_tcols, sizeof(T));
+      // cooperative: the runtime places every workgroup at once or fails the launch;
+      // otherwise the occupancy count made at set-up stands, and in both cases the grid
+      // barrier's bounded wait turns starvation into a reported status
+      le = bp.single.pcg_resident == 2
+               ? hipLaunchCooperativeKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, lds, s)
+               : hipLaunchKernel(f, dim3(bp.n_pcg), dim3(kCgThreads), args, lds, s);
     } else if (bp.n_probs == 1) {
       const void *f = CgStep<T>::single(bp.pcg_rows);
       for (int it = 0; it < pcg_max && le == hipSuccess; ++it) {

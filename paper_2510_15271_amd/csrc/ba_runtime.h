@@ -66,6 +66,7 @@ struct Symbolic {
   int32_t max_tcols = 0;
   int32_t pcg_rows = kPcgRows;    // rows per PCG tile
   bool pcg_resident = false;      // the whole PCG in one launch (BA_FLAG_PCG_RESIDENT, when it fits)
+  bool pcg_coop = false;          // ... started as a cooperative launch (BA_FLAG_PCG_COOPERATIVE)
 };
 // Edges of a pose graph: node pairs (i, j), measured A_ij (12 values each, R row-major
 // then t) and weights (rotation, translation).

@@ -72,7 +72,7 @@ def test_create_rejects_duplicates_empty_and_all_fixed(balib):
 def test_options_validation(balib):
     s = make_arc_scene(3, 20, seed=1)
     for kw in [dict(max_iters=0), dict(pcg_max_iters=0), dict(lambda0=0.0),
-               dict(pcg_rel_tol=-1.0), dict(precision=7), dict(huber_delta=np.inf), dict(flags=5), dict(flags=64),
+               dict(pcg_rel_tol=-1.0), dict(precision=7), dict(huber_delta=np.inf), dict(flags=5), dict(flags=128),
                dict(prior_abs=-1.0), dict(prior_seq=np.nan), dict(prior_seq=1.0, prior_seq_k=0),
                dict(prior_seq=1.0, prior_seq_k=65)]:
         _expect(balib, balib.BA_EINVAL, lambda: balib.Problem(balib.scene_desc(s), balib.options(**kw)))
@@ -291,7 +291,7 @@ def test_binding_layouts_and_constants_match_header(balib, tmp_path):
     for name in ("OK", "DAMPING", "NUMERICAL", "PCG_SYNC"):
         assert getattr(balib, "STATUS_" + name) == defs["BA_STATUS_" + name], name
     assert balib.POSE_MAX_CORR == defs["BA_POSE_MAX_CORR"]
-    for name in ("NO_GRAPH", "PAIR_LISTS", "PCG_WIDE", "PCG_RESIDENT", "DENSE_SCHUR"):
+    for name in ("NO_GRAPH", "PAIR_LISTS", "PCG_WIDE", "PCG_RESIDENT", "DENSE_SCHUR", "PCG_COOPERATIVE"):
         assert getattr(balib, "FLAG_" + name) == defs["BA_FLAG_" + name], name
     assert balib.TRI == {"midpoint": defs["BA_TRI_MIDPOINT"], "dlt": defs["BA_TRI_DLT"]}
     assert balib.PREC == {"f64": defs["BA_PREC_F64"], "f32": defs["BA_PREC_F32"],

@@ -37,10 +37,11 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("extra", [0, 2, 8])
+@pytest.mark.parametrize("extra", [0, 2, 8, 64, 66])
 def test_small_drive_resident_equals_per_launch(balib, prec, extra):
     """40-camera drive (10 tiles of 4 rows, the last ragged; with BA_FLAG_PCG_WIDE one
-    full and one ragged 32-row tile; with BA_FLAG_NO_GRAPH launched without a graph):
+    full and one ragged 32-row tile; with BA_FLAG_NO_GRAPH launched without a graph;
+    with BA_FLAG_PCG_COOPERATIVE started as a cooperative launch, in a graph or not):
     the resident solve repeats the per-launch solve bit for bit, and in FP64 every C_n
     is within 1e-9 of the explicit-Schur oracle solved exactly."""
     s = make_small_drive(40, 3000, seed=5)
@@ -48,7 +49,7 @@ def test_small_drive_resident_equals_per_launch(balib, prec, extra):
     ia, a = _run(balib, s, extra, **kw)
     ib, b = _run(balib, s, extra | RESIDENT, **kw)
     _say("info", ia["pcg_rows"], ia["pcg_resident"], ib["pcg_rows"], ib["pcg_resident"], "pcg", b["pcg_iters"])
-    assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == 1
+    assert ia["pcg_resident"] == 0 and ib["pcg_resident"] == (2 if extra & 64 else 1)
     assert ib["pcg_rows"] == (32 if extra == 8 else 4)
     _same(a, b)
     if prec == "f64":
@@ -72,7 +73,8 @@ def test_small_drive_resident_early_stop_and_cap(balib):
 def test_full_size_drive_resident_equals_per_launch(balib):
     """The 2M-observation drive in the benchmark's configuration (FP32, 10 LM
     iterations, PCG 50 / 1e-6): 125 resident workgroups, the same run bit for bit as
-    the launch-per-iteration PCG, and a cost that falls below half its start."""
+    the launch-per-iteration PCG (also when started as a cooperative launch), and a
+    cost that falls below half its start."""
     s = make_config1()
     ia, a = _run(balib, s, 0, max_iters=10, precision="f32")
     ib, b = _run(balib, s, RESIDENT, max_iters=10, precision="f32")
@@ -80,6 +82,9 @@ def test_full_size_drive_resident_equals_per_launch(balib):
     assert ib["pcg_resident"] == 1
     _same(a, b)
     assert b["cost"] < 0.5 * b["cost0"]
+    ic, c = _run(balib, s, RESIDENT | 64, max_iters=10, precision="f32")
+    assert ic["pcg_resident"] == 2
+    _same(a, c)
 
 
 def test_pose_graph_too_many_tiles_falls_back(balib):
@@ -120,16 +125,17 @@ def test_refine_resident_equals_per_launch(balib):
     assert np.array_equal(ra["X"], rb["X"])
 
 
-def test_barrier_time_out_rejects_the_step_and_stops(balib):
+@pytest.mark.parametrize("coop", [0, 64])
+def test_barrier_time_out_rejects_the_step_and_stops(balib, coop):
     """The barrier's poll bound set to 0 from the host (no workgroup is starved: each
     gives up at its first barrier and exits): the first LM iteration rejects its step
     and the solve ends there with BA_STATUS_PCG_SYNC, one iteration reported and the
     initial state kept.  With the default bound restored the next solve equals a
-    fresh one bit for bit."""
+    fresh one bit for bit.  The same with a cooperative launch."""
     s = make_small_drive(40, 3000, seed=5)
-    kw = dict(max_iters=6, precision="f32", flags=RESIDENT)
+    kw = dict(max_iters=6, precision="f32", flags=RESIDENT | coop)
     p = balib.Problem.from_scene(s, **kw)
-    assert p.info()["pcg_resident"] == 1
+    assert p.info()["pcg_resident"] == (2 if coop else 1)
     init = p.result()
     p.set_barrier_polls(0)
     _say("device solve: barrier poll bound 0")
