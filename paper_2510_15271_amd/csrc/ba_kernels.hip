@@ -114,6 +114,75 @@ __device__ inline void jp_from(const T f[4], const T R[9], T Jp[6]) {
   }
 }
 
+// Products with the camera Jacobian.  Each of its two rows holds a structural zero
+// (row 0 at column 1, row 1 at column 0, see jc_from); the products below skip those
+// terms and accumulate through chains of fused multiply-adds, acc = fma(x, y, acc),
+// instead of forming each two-term sum first and adding it.
+template <class T>
+__device__ inline T fmac(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+
+// z = J_c^T m for the 2x2 m = [m00 m01; m10 m11]: z0 its first column, z1 its second.
+template <class T>
+__device__ inline void jct_m(const T Jc[12], T m00, T m01, T m10, T m11, T z0[6], T z1[6]) {
+  z0[0] = Jc[0] * m00;
+  z1[0] = Jc[0] * m01;
+  z0[1] = Jc[7] * m10;
+  z1[1] = Jc[7] * m11;
+#pragma unroll
+  for (int r = 2; r < 6; ++r) {
+    z0[r] = fmac(Jc[6 + r], m10, Jc[r] * m00);
+    z1[r] = fmac(Jc[6 + r], m11, Jc[r] * m01);
+  }
+}
+
+// acc (6x6, row-major) += [z0 z1] J_b for a 6x2 left factor.
+template <class T>
+__device__ inline void acc_zj(T acc[36], const T z0[6], const T z1[6], const T Jb[12]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      T v = acc[6 * r + c];
+      if (c != 1) v = fmac(z0[r], Jb[c], v);
+      if (c != 0) v = fmac(z1[r], Jb[6 + c], v);
+      acc[6 * r + c] = v;
+    }
+}
+
+// acc (upper triangle of a 6x6, rows in order, 21 values) += [z0 z1] J_b.
+template <class T>
+__device__ inline void acc_zj_upper(T acc[21], const T z0[6], const T z1[6], const T Jb[12]) {
+  int u = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r; c < 6; ++c, ++u) {
+      T v = acc[u];
+      if (c != 1) v = fmac(z0[r], Jb[c], v);
+      if (c != 0) v = fmac(z1[r], Jb[6 + c], v);
+      acc[u] = v;
+    }
+}
+
+// acc (upper triangle, 21 values) += J_c^T J_c; the (0, 1) element is zero for
+// every observation and is left as it is.
+template <class T>
+__device__ inline void acc_jtj_upper(T acc[21], const T Jc[12]) {
+  int u = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r; c < 6; ++c, ++u) {
+      T v = acc[u];
+      if (r != 1 && c != 1) v = fmac(Jc[r], Jc[c], v);
+      if (r != 0 && c != 0) v = fmac(Jc[6 + r], Jc[6 + c], v);
+      acc[u] = v;
+    }
+}
+
 template <class T>
 __device__ inline void load_rot(const double *pose, T R[9]) {
 #pragma unroll
@@ -969,19 +1038,9 @@ __global__ __launch_bounds__(256) void k_schur_diag(const ProbDev *__restrict__ 
     const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
     const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
     T Z0[6], Z1[6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      Z0[r] = Jc0[r] * m00 + Jc1[r] * m10;
-      Z1[r] = Jc0[r] * m01 + Jc1[r] * m11;
-    }
-    int u = 0;
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int c = r; c < 6; ++c, ++u) {
-        acc[u] += Jc0[r] * Jc0[c] + Jc1[r] * Jc1[c];
-        acc[21 + u] += Z0[r] * Jc0[c] + Z1[r] * Jc1[c];
-      }
+    jct_m(Jc, m00, m01, m10, m11, Z0, Z1);
+    acc_jtj_upper(acc, Jc);
+    acc_zj_upper(acc + 21, Z0, Z1, Jc);
     T e0 = rec.e[0], e1 = rec.e[1];
     T G0[6], G1[6];
 #pragma unroll
@@ -1080,13 +1139,9 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
     const T m01 = q[0] * Jpb[3] + q[1] * Jpb[4] + q[2] * Jpb[5];
     const T m10 = q[3] * Jpb[0] + q[4] * Jpb[1] + q[5] * Jpb[2];
     const T m11 = q[3] * Jpb[3] + q[4] * Jpb[4] + q[5] * Jpb[5];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      const T z0 = Jca[r] * m00 + Jca[6 + r] * m10;
-      const T z1 = Jca[r] * m01 + Jca[6 + r] * m11;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * Jcb[c] + z1 * Jcb[6 + c];
-    }
+    T z0[6], z1[6];
+    jct_m(Jca, m00, m01, m10, m11, z0, z1);
+    acc_zj(acc, z0, z1, Jcb);
   }
   // butterfly: every lane ends with all 36 sums; lane e keeps entry e
   T mine = T(0);
@@ -1153,13 +1208,9 @@ __device__ inline void pair_accumulate(T acc[36], const T *fa_lds, const T *q_ld
   const T m01 = q[0] * Jpb[3] + q[1] * Jpb[4] + q[2] * Jpb[5];
   const T m10 = q[3] * Jpb[0] + q[4] * Jpb[1] + q[5] * Jpb[2];
   const T m11 = q[3] * Jpb[3] + q[4] * Jpb[4] + q[5] * Jpb[5];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    const T z0 = Jca[r] * m00 + Jca[6 + r] * m10;
-    const T z1 = Jca[r] * m01 + Jca[6 + r] * m11;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) acc[6 * r + c] += z0 * Jcb[c] + z1 * Jcb[6 + c];
-  }
+  T z0[6], z1[6];
+  jct_m(Jca, m00, m01, m10, m11, z0, z1);
+  acc_zj(acc, z0, z1, Jcb);
 }
 
 template <class T, class S>
@@ -1327,11 +1378,7 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         T Jc[12];
         jc_from(fe, Jc);
         const T *Jc0 = Jc, *Jc1 = Jc + 6;
-        int u = 0;
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc0[r] * Jc0[cc] + Jc1[r] * Jc1[cc];
+        acc_jtj_upper(acc, Jc);
 #pragma unroll
         for (int r = 0; r < 6; ++r) acc[27 + r] += Jc0[r] * qq[6] + Jc1[r] * qq[7];
         if (k16) {
@@ -1361,19 +1408,13 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         T Jc[12], Jp[6];
         jc_from(f, Jc);
         jp_from(f, R, Jp);
-        const T *Jc0 = Jc, *Jc1 = Jc + 6;
         const T m00 = q[0] * Jp[0] + q[1] * Jp[1] + q[2] * Jp[2];
         const T m01 = q[0] * Jp[3] + q[1] * Jp[4] + q[2] * Jp[5];
         const T m10 = q[3] * Jp[0] + q[4] * Jp[1] + q[5] * Jp[2];
         const T m11 = q[3] * Jp[3] + q[4] * Jp[4] + q[5] * Jp[5];
-        int u = 0;
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          const T z0 = Jc0[r] * m00 + Jc1[r] * m10;
-          const T z1 = Jc0[r] * m01 + Jc1[r] * m11;
-#pragma unroll
-          for (int cc = r; cc < 6; ++cc, ++u) acw[u] += z0 * Jc0[cc] + z1 * Jc1[cc];
-        }
+        T z0[6], z1[6];
+        jct_m(Jc, m00, m01, m10, m11, z0, z1);
+        acc_zj_upper(acw, z0, z1, Jc);
       }
 #pragma unroll
       for (int i = 0; i < 21; ++i) o[21 + i] = acw[i];
@@ -3454,11 +3495,7 @@ __global__ __launch_bounds__(kDnCamThreads) void k_dense_cams(const ProbDev *__r
     for (int i = 0; i < 6; ++i) lt[i] = pf[9 * (size_t)j + i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) hv[i] = pf[9 * (size_t)j + 6 + i];
-    int u = 0;
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int cc = r; cc < 6; ++cc, ++u) acc[u] += Jc[r] * Jc[cc] + Jc[6 + r] * Jc[6 + cc];
+    acc_jtj_upper(acc, Jc);
     if (k16) {
       // 16-bit storage: the gradient from FP32 Jacobians at the linearisation state
       double xd, yd, zd;
