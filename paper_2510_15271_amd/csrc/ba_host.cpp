@@ -434,8 +434,14 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
   }
   const int prec = opt->precision;
   // points with long tracks (16 or more observations on average) take tiles of fewer
-  // points, so that a problem spreads over more workgroups
-  sy.pt_tile = N >= 16 * (int64_t)std::max(P, 1) ? kPtTileLong : kPtTile;
+  // points, so that a problem spreads over more workgroups.  Otherwise a tile walks its
+  // observations in passes of one per thread, one after another, so a problem whose
+  // full tiles would not give every CU 8 of them takes tiles of half the points: twice
+  // the workgroups, still all resident at once, each with half the passes (the 2M-
+  // observation drive: 977 -> 1954 tiles, point_trial 62 -> 50 us)
+  sy.pt_tile = N >= 16 * (int64_t)std::max(P, 1)                ? kPtTileLong
+               : (P + kPtTile - 1) / kPtTile < (int64_t)kPtTileFill ? kPtTile / 2
+                                                                    : kPtTile;
   // the dense co-visibility form: forced by its flag, or chosen when tracks span at
   // least a quarter of the free cameras on average, the pairs are many per block of S
   // and most camera pairs share points (never with pair lists asked for)

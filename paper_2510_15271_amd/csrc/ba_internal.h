@@ -15,6 +15,7 @@ namespace bax {
 
 constexpr int kPtTile = 256;     // points per point-major tile (one workgroup), at most
 constexpr int kPtTileLong = 32;  // ... for problems whose points have long tracks
+constexpr int kPtTileFill = 2048;  // fewer full tiles than this (8 per CU): half-size tiles
 constexpr int kObsChunk = 256;   // observations processed per pass inside a point tile (one per thread)
 constexpr int kPcgRows = 4;      // reduced-camera-system rows per PCG tile, dense rows
 constexpr int kPcgRowsSparse = 16;  // rows per PCG tile when rows hold few blocks

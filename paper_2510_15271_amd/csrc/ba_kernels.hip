@@ -2678,28 +2678,48 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   LMState *st = pd.st;
   if (!lm_active(st)) return;
   __shared__ double s_red[4];
-  double c0 = block_sum_array(pd.part_lin_cost, pd.n_pt_tiles, s_red);
-  double tc = block_sum_array(pd.part_trial_cost, pd.n_pt_tiles, s_red);
+  __shared__ double s_red6[6][4];
+  // prior terms first, so that no tile sum below is live across their loops
+  double pc = 0.0, pt = 0.0;
+  const bool pri = pd.rig_mode == 1 || pd.prior_on;
   if (pd.rig_mode == 1) {  // the rig priors at the current (first call only) and trial poses
-    if (!st->init_done) c0 += prior_cost(pd, pd.rig_pose[st->cur], s_red);
-    tc += prior_cost(pd, pd.rig_pose[1 - st->cur], s_red);
+    if (!st->init_done) pc = prior_cost(pd, pd.rig_pose[st->cur], s_red);
+    pt = prior_cost(pd, pd.rig_pose[1 - st->cur], s_red);
   } else if (pd.prior_on) {  // the same, summed over k_prior_cost's tiles
     const int n = pd.n_pri_tiles;
-    const double pc = block_sum_array(pd.part_prior, n, s_red);
-    const double pt = block_sum_array(pd.part_prior + n, n, s_red);
+    pc = block_sum_array(pd.part_prior, n, s_red);
+    pt = block_sum_array(pd.part_prior + n, n, s_red);
+  }
+  // the tile sums, each in the order of block_sum_array (thread-strided, then the
+  // four waves in order), all loaded in one pass and reduced through one barrier
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // lin cost, trial cost, dl_pt, masked, trial masked, dl_cam
+  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
+    v[0] += pd.part_lin_cost[i];
+    v[1] += pd.part_trial_cost[i];
+    v[2] += pd.part_dl_pt[i];
+    v[3] += (double)pd.part_masked[i];
+    v[4] += (double)pd.part_trial_masked[i];
+  }
+  for (int i = threadIdx.x; i < pd.n_cam_tiles; i += 256) v[5] += pd.part_dl_cam[i];
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double x = wave_sum(v[q]);
+      if (lane == 0) s_red6[q][w] = x;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double sum6[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) sum6[q] = s_red6[q][0] + s_red6[q][1] + s_red6[q][2] + s_red6[q][3];
+  double c0 = sum6[0], tc = sum6[1];
+  if (pri) {
     if (!st->init_done) c0 += pc;
     tc += pt;
   }
-  const double dlc = block_sum_array(pd.part_dl_cam, pd.n_cam_tiles, s_red);
-  const double dlp = block_sum_array(pd.part_dl_pt, pd.n_pt_tiles, s_red);
-  double m0 = 0.0, mt = 0.0;
-  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
-    m0 += (double)pd.part_masked[i];
-    mt += (double)pd.part_trial_masked[i];
-  }
-  m0 = block_sum256(m0, s_red);
-  mt = block_sum256(mt, s_red);
-  if (threadIdx.x != 0) return;
+  const double dlp = sum6[2], m0 = sum6[3], mt = sum6[4], dlc = sum6[5];
   const int n = st->iter;
   if (!st->init_done) {
     st->cost = c0;

@@ -86,7 +86,7 @@ def test_config0_f64_per_iteration_cost_matches_dense_oracle(balib):
 
 @pytest.mark.parametrize("flags", [0, 8])
 def test_small_drive_f64_matches_schur_oracle_across_tiles(balib, flags):
-    """Sequential drive with 12 point tiles and a ragged tail, FP64: per-iteration
+    """Sequential drive with 24 point tiles of 128 and a ragged tail, FP64: per-iteration
     cost within 1e-9 of the explicit-Schur oracle solved exactly; also with the PCG
     at 32 rows per workgroup (BA_FLAG_PCG_WIDE: one full and one ragged tile)."""
     s = make_small_drive(40, 3000, seed=5)
@@ -103,7 +103,7 @@ def test_small_drive_f64_matches_schur_oracle_across_tiles(balib, flags):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_chunk_and_pair_list_forms(balib, prec):
-    """Both Schur forms on the same drive (40 cameras, 12 point tiles, ragged
+    """Both Schur forms on the same drive (40 cameras, 24 point tiles, ragged
     tail): FP64 per-iteration cost within 1e-9 of the explicit-Schur oracle for
     each form; in FP32 the two forms agree with each other to 1e-4 per iteration
     (they sum S in different orders; the first step, which lowers the cost 25-fold,
