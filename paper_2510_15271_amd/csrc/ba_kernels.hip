@@ -538,18 +538,36 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
   const double *Xs = pd.X[cur];
   double cost = 0.0;
   int masked = 0;
+  // the observation's own fields for the next pass are loaded while the current pass
+  // is processed
+  int nj = 0, ncam = 0, ncpos = -1;
+  bool non = false;
+  T nu = T(0), nv = T(0);
+  auto fetch = [&](int k) {
+    if (k < k1) {
+      nj = pd.obs_pt[k];
+      ncam = pd.obs_cam[k];
+      ncpos = pd.obs_rpos[k];
+      non = pd.obs_act[k] != 0;
+      nu = uv[2 * (size_t)k];
+      nv = uv[2 * (size_t)k + 1];
+    }
+  };
+  fetch(k0 + (int)threadIdx.x);
   __syncthreads();
 
   for (int base = k0; base < k1; base += kObsChunk) {
     const int k = base + threadIdx.x;
+    const int j = nj, cam = ncam, cpos = ncpos;
+    const bool on = non;
+    const T ou = nu, ov = nv;
+    fetch(k + kObsChunk);
     T c[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) c[i] = T(0);
     int jl = -1;
     if (k < k1) {
-      const int j = pd.obs_pt[k];
       jl = j - j0;
-      const int cam = pd.obs_cam[k];
       const double *pose = poses + 12 * cam;
       double xd, yd, zd;
       transform(pose, Xs + 3 * j, xd, yd, zd);
@@ -557,8 +575,7 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
       const T *K = Kall + 4 * cam;
       T r0, r1;
       LinRec<T, S> rec;
-      const bool on = pd.obs_act[k] != 0;
-      if (on && residual<T>(K, x, y, z, uv[2 * k], uv[2 * k + 1], r0, r1)) {
+      if (on && residual<T>(K, x, y, z, ou, ov, r0, r1)) {
         const T s = r0 * r0 + r1 * r1;
         const T w = huber_w(s, delta);
         const T sw = sqrt(w);
@@ -598,8 +615,7 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
         for (int i = 0; i < 7; ++i) rec.f[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
       }
-      const int cpos = pd.obs_rpos[k];  // records are kept for free cameras only
-      if (cpos >= 0) lin[cpos] = rec;
+      if (cpos >= 0) lin[cpos] = rec;  // records are kept for free cameras only
     }
     seg_add_scan<T, 9>(c, jl, s_acc, s_c, s_loc);
   }
@@ -1239,6 +1255,24 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   const int j0 = pd.ch_pt[c], j1 = pd.ch_pt[c + 1];
   const int f0 = pd.ch_f0[c];
   const double *poses = pd.pose[st->cur];
+  // the chunk's first records (two per thread): indices and compact records are
+  // loaded before the point inverses, so that their latency overlaps them
+  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
+  const T *gp = (const T *)pd.gp;
+  const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
+  int kk[2], rp[2], cam[2], jj[2];
+  LinRec<T, S> rec[2];
+  auto fetch = [&](int base) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      kk[h] = base + h * nth + (int)threadIdx.x;
+      rp[h] = kk[h] < k1 ? pd.obs_rpos[kk[h]] : -1;
+      cam[h] = kk[h] < k1 ? pd.obs_cam[kk[h]] : 0;
+      jj[h] = kk[h] < k1 ? pd.obs_pt[kk[h]] : j0;
+      if (rp[h] >= 0) rec[h] = lin[rp[h]];
+    }
+  };
+  fetch(k0);
   // a. point inverses
   {
     const double lam = st->lambda;
@@ -1261,87 +1295,74 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
       }
     }
   }
-  __syncthreads();
-  // b. rotations of the chunk's cameras, records of the chunk (two observations
-  // per thread in flight)
+  // b. rotations of the chunk's cameras (independent of a, before its barrier)
   {
     const int q0 = pd.ch_cam_start[c], nq = pd.ch_cam_start[c + 1] - q0;
     for (int x = threadIdx.x; x < nq; x += nth) {
-      const int cam = pd.ch_cam[q0 + x];
+      const int cm = pd.ch_cam[q0 + x];
       T R[9];
-      load_rot(poses + 12 * cam, R);
+      load_rot(poses + 12 * cm, R);
 #pragma unroll
       for (int i = 0; i < 9; ++i) s_R[9 * x + i] = R[i];
-      s_cam[x] = cam;
+      s_cam[x] = cm;
     }
   }
-  {
-    const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-    const T *gp = (const T *)pd.gp;
-    const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
-    for (int base = k0; base < k1; base += 2 * nth) {
-      int kk[2], rp[2], cam[2], jj[2];
-      LinRec<T, S> rec[2];
+  __syncthreads();
+  // b. the records into LDS (chunks hold at most two records per thread, so the loop
+  // body runs once; the loop keeps larger chunks correct)
+  for (int base = k0; base < k1; base += 2 * nth) {
+    if (base != k0) fetch(base);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        kk[h] = base + h * nth + (int)threadIdx.x;
-        rp[h] = kk[h] < k1 ? pd.obs_rpos[kk[h]] : -1;
-        cam[h] = kk[h] < k1 ? pd.obs_cam[kk[h]] : 0;
-        jj[h] = kk[h] < k1 ? pd.obs_pt[kk[h]] : j0;
-        if (rp[h] >= 0) rec[h] = lin[rp[h]];
-      }
+    for (int h = 0; h < 2; ++h) {
+      if (rp[h] < 0) continue;  // past the chunk, or a fixed camera: no record
+      const int l = rp[h] - f0;
+      const int j = jj[h];
+      T f[7], R[9], Jp[6];
+      decode(rec[h], f);
+      load_rot(poses + 12 * cam[h], R);
+      jp_from(f, R, Jp);
+      const T *vi = s_vi + 6 * (j - j0);
+      const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
+      T q[6];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (rp[h] < 0) continue;  // past the chunk, or a fixed camera: no record
-        const int l = rp[h] - f0;
-        const int j = jj[h];
-        T f[7], R[9], Jp[6];
-        decode(rec[h], f);
-        load_rot(poses + 12 * cam[h], R);
-        jp_from(f, R, Jp);
-        const T *vi = s_vi + 6 * (j - j0);
-        const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
-        T q[6];
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int m = 0; m < 3; ++m)
+          q[3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
+      const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
+      T fe[8], qq[8];
 #pragma unroll
-          for (int m = 0; m < 3; ++m)
-            q[3 * r + m] = Jp[3 * r] * M[m] + Jp[3 * r + 1] * M[3 + m] + Jp[3 * r + 2] * M[6 + m];
-        const T g0 = gp[3 * j], g1 = gp[3 * j + 1], g2 = gp[3 * j + 2];
-        T fe[8], qq[8];
+      for (int i = 0; i < 7; ++i) fe[i] = f[i];
+      fe[7] = rec[h].e[0];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) fe[i] = f[i];
-        fe[7] = rec[h].e[0];
+      for (int i = 0; i < 6; ++i) qq[i] = q[i];
+      qq[6] = q[0] * g0 + q[1] * g1 + q[2] * g2;
+      qq[7] = q[3] * g0 + q[4] * g1 + q[5] * g2;
+      store8(s_fe + 8 * l, fe);
+      store8(s_qq + 8 * l, qq);
+      if (k16) {
+        // 16-bit storage: this record's gradient term w J_c^T r from FP32 Jacobians
+        const int cm = cam[h];
+        const double *pose = poses + 12 * cm;
+        const T *K = (const T *)pd.K + 4 * cm;
+        const T *uv = (const T *)pd.obs_uv + 2 * (size_t)kk[h];
+        double xd, yd, zd;
+        transform(pose, pd.X[st->cur] + 3 * (size_t)j, xd, yd, zd);
+        const T xv = T(xd), yv = T(yd), zv = T(zd);
+        T r0, r1, gk[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) qq[i] = q[i];
-        qq[6] = q[0] * g0 + q[1] * g1 + q[2] * g2;
-        qq[7] = q[3] * g0 + q[4] * g1 + q[5] * g2;
-        store8(s_fe + 8 * l, fe);
-        store8(s_qq + 8 * l, qq);
-        if (k16) {
-          // 16-bit storage: this record's gradient term w J_c^T r from FP32 Jacobians
-          const int cm = cam[h];
-          const double *pose = poses + 12 * cm;
-          const T *K = (const T *)pd.K + 4 * cm;
-          const T *uv = (const T *)pd.obs_uv + 2 * (size_t)kk[h];
-          double xd, yd, zd;
-          transform(pose, pd.X[st->cur] + 3 * (size_t)j, xd, yd, zd);
-          const T xv = T(xd), yv = T(yd), zv = T(zd);
-          T r0, r1, gk[6];
+        for (int r = 0; r < 6; ++r) gk[r] = T(0);
+        if (pd.obs_act[kk[h]] && residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
+          const T w = huber_w(r0 * r0 + r1 * r1, T(st->huber_delta));
+          T Jg[12], Jpg[6];
+          jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
 #pragma unroll
-          for (int r = 0; r < 6; ++r) gk[r] = T(0);
-          if (pd.obs_act[kk[h]] && residual<T>(K, xv, yv, zv, uv[0], uv[1], r0, r1)) {
-            const T w = huber_w(r0 * r0 + r1 * r1, T(st->huber_delta));
-            T Jg[12], Jpg[6];
-            jacobians<T>(K, pose, xv, yv, zv, Jg, Jpg);
-#pragma unroll
-            for (int r = 0; r < 6; ++r) gk[r] = w * (Jg[r] * r0 + Jg[6 + r] * r1);
-          }
-#pragma unroll
-          for (int r = 0; r < 6; ++r) s_e1[6 * l + r] = gk[r];
-        } else {
-          s_e1[l] = rec[h].e[1];
+          for (int r = 0; r < 6; ++r) gk[r] = w * (Jg[r] * r0 + Jg[6 + r] * r1);
         }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) s_e1[6 * l + r] = gk[r];
+      } else {
+        s_e1[l] = rec[h].e[1];
       }
     }
   }
