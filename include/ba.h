@@ -99,8 +99,8 @@ typedef struct {
 #define BA_FLAG_NO_GRAPH 2
 #define BA_FLAG_PAIR_LISTS 4
 /* BA_FLAG_PCG_WIDE: run the PCG with 32 reduced-system rows per workgroup (half a
-   wave per row) whatever the row density, when the tile's columns fit in LDS.  By
-   default that layout is used only for more than 8192 free cameras with sparse rows. */
+   wave per row) whatever the problem size, when the tile's columns fit in LDS.  By
+   default that layout is used only for more than 8192 free cameras. */
 #define BA_FLAG_PCG_WIDE 8
 /* BA_FLAG_PCG_RESIDENT: run each linear solve of a single-problem solve as ONE launch
    whose workgroups stay resident and meet at a grid barrier once per iteration, instead
@@ -273,9 +273,9 @@ typedef struct {
                              2: dense co-visibility form                             */
   int32_t n_chunks;       /* point chunks (chunk form)                                 */
   int64_t n_entries;      /* (chunk, block) partial sums (chunk form)                  */
-  int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for many sparse
-                             rows (at least 1024 free cameras, at most 24 blocks per row
-                             on average) 16, or 32 beyond 8192 free cameras            */
+  int32_t pcg_rows;       /* reduced-system rows per PCG workgroup: 4; for at least
+                             1024 free cameras 16, or 32 beyond 8192 free cameras
+                             (4 again where a tile's columns would not fit in LDS)     */
   int32_t pcg_resident;   /* 1: BA_FLAG_PCG_RESIDENT was asked for and the problem fits it;
                              2: the same, started as a cooperative launch                  */
 } ba_problem_info;

@@ -661,9 +661,8 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
     }
   // distinct columns of each PCG tile and each block's position in its tile's list;
   // the lists are stored at a fixed stride (the longest list), padded with -1.
-  // A tile holds kPcgRows rows, or kPcgRowsSparse when the rows hold few blocks and
-  // there are many of them: each launch sums every tile's partials in every tile, so
-  // the tile count must stay modest, and sparse rows leave most of a 4-row tile idle.
+  // A tile holds kPcgRows rows, or kPcgRowsSparse when there are many rows: each launch
+  // sums every tile's partials in every tile, so the tile count must stay modest.
   auto tile_lists = [&](int R) {
     const int ntile = (Cf + R - 1) / R;
     sy.pcg_rows = R;
@@ -685,10 +684,13 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
     for (int t = 0; t < ntile; ++t)
       std::copy(lists[t].begin(), lists[t].end(), sy.tcol.begin() + (size_t)t * sy.max_tcols);
   };
-  // Sparse rows take 16 rows per tile, or 32 (half a wave each) once 16-row tiles
-  // would outnumber what the device runs at once (two 1024-thread workgroups per CU);
-  // a tile whose columns do not fit in LDS falls back to fewer rows.
-  const bool sparse_rows = Cf >= 1024 && sy.nnzb <= 24 * (int64_t)Cf;
+  // At least 1024 rows take 16 rows per tile, or 32 (half a wave each) once 16-row
+  // tiles would outnumber what the device runs at once (two 1024-thread workgroups per
+  // CU): 4-row tiles would outnumber the CUs, so that a step would run in several
+  // rounds of workgroups (the 3000-camera loop scene, 148 blocks per row: 19.8 us per
+  // step with 750 tiles, 9.6 us with 188), and on sparse rows they would leave most
+  // lanes idle.  A tile whose columns do not fit in LDS falls back to fewer rows.
+  const bool sparse_rows = Cf >= 1024;
   const bool wide = (opt->flags & BA_FLAG_PCG_WIDE) || (Cf + kPcgRowsSparse - 1) / kPcgRowsSparse > 512;
   tile_lists(!(sparse_rows || (opt->flags & BA_FLAG_PCG_WIDE)) ? kPcgRows : wide ? kPcgRowsMax : kPcgRowsSparse);
   if (sy.pcg_rows == kPcgRowsMax && !one_reduction_pcg(prec, sy.max_tcols)) tile_lists(kPcgRowsSparse);

@@ -1787,33 +1787,43 @@ __global__ __launch_bounds__(256) void k_pcg_update(const ProbDev *__restrict__ 
 // and its partials of gamma_{i+1}, delta_{i+1} and ||r_{i+1}||^2.  Vectors and
 // partials alternate between two buffers by parity; the cg_start launch forms
 // w_0 = S u_0 and the first partials.
+template <int NW>
 __device__ inline void cg_partials(double *part, int n_tiles, int tile, double g, double d, double rr,
-                                   double *s12) {
+                                   double *s3nw) {
   g = wave_sum(g);
   d = wave_sum(d);
   rr = wave_sum(rr);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
-    s12[w] = g;
-    s12[4 + w] = d;
-    s12[8 + w] = rr;
+    s3nw[w] = g;
+    s3nw[NW + w] = d;
+    s3nw[2 * NW + w] = rr;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    part[tile] = s12[0] + s12[1] + s12[2] + s12[3];
-    part[n_tiles + tile] = s12[4] + s12[5] + s12[6] + s12[7];
-    part[2 * n_tiles + tile] = s12[8] + s12[9] + s12[10] + s12[11];
+    double a = s3nw[0], b = s3nw[NW], c = s3nw[2 * NW];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) {
+      a += s3nw[k];
+      b += s3nw[NW + k];
+      c += s3nw[2 * NW + k];
+    }
+    part[tile] = a;
+    part[n_tiles + tile] = b;
+    part[2 * n_tiles + tile] = c;
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ probs,
-                                                  const Tile *__restrict__ tiles) {
+// NW waves per tile, wave w taking rows w, w + NW, ...: 4 for 4-row tiles (and mixed
+// batches), 16 for tiles of 16 or 32 rows, so that no wave walks more than two rows.
+template <class T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_cg_start(const ProbDev *__restrict__ probs,
+                                                      const Tile *__restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
   LMState *st = pd.st;
   __shared__ int s_flag[1];
-  __shared__ double s_red[12];
+  __shared__ double s_red[3 * NW];
   if (threadIdx.x == 0) pd.cg_flag[tl.idx] = 0u;  // the resident PCG's barrier flags
   if (threadIdx.x == 0) s_flag[0] = lm_active(st) ? 1 : 0;
   __syncthreads();
@@ -1822,7 +1832,7 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   // reads (its loads issued here, reduced after its rows); with b = 0 every tile's
   // products are zero and harmless
   double vbb = 0.0;
-  if (tl.idx == 0)
+  if (tl.idx == 0 && threadIdx.x < 256)
     for (int i = threadIdx.x; i < pd.Cf; i += 256) vbb += pd.part_bb[i];
   const T *u = (const T *)pd.cg_u[0];
   const T *r = (const T *)pd.cg_r[0];
@@ -1833,7 +1843,7 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane / 6, i = lane % 6;
   double pg = 0.0, pdl = 0.0, prr = 0.0;
-  for (int rr = wv; rr < pd.pcg_rows; rr += 4) {  // each wave takes every fourth row
+  for (int rr = wv; rr < pd.pcg_rows; rr += NW) {
     const int a = tl.idx * pd.pcg_rows + rr;
     if (a >= pd.Cf) break;
     T acc = T(0);
@@ -1860,10 +1870,12 @@ __global__ __launch_bounds__(256) void k_cg_start(const ProbDev *__restrict__ pr
       prr += ri * ri;
     }
   }
-  cg_partials(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
+  cg_partials<NW>(pd.part_cg[0], pd.n_pcg_tiles, tl.idx, pg, pdl, prr, s_red);
   if (tl.idx == 0) {
-    __shared__ double s_bb[4];  // not s_red: thread 0 may still be reading the partials there
-    const double bb = block_sum256(vbb, s_bb);  // the order block_sum_array uses
+    // not s_red: thread 0 may still be reading the partials there.  The order of
+    // block_sum_array over 256 threads; waves past the fourth add zeros
+    __shared__ double s_bb[NW];
+    const double bb = block_sum_w<NW>(vbb, s_bb);
     if (threadIdx.x == 0) {
       st->pcg_bb = bb;
       st->pcg_done = (bb > 0.0) ? 0 : 1;
@@ -4003,7 +4015,10 @@ static hipError_t lm_iteration(const BatchPlan &bp, int pcg_max, int max_tcols, 
   }
   if (bp.n_pcg && one_reduction) {
     Timed t(tm, K_PCG_SPMV, s);
-    k_cg_start<T><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg);
+    if (bp.pcg_rows >= kPcgRowsSparse)
+      k_cg_start<T, 16><<<bp.n_pcg, 1024, 0, s>>>(bp.probs, bp.pcg);
+    else
+      k_cg_start<T, 4><<<bp.n_pcg, 256, 0, s>>>(bp.probs, bp.pcg);
   }
   }
   if (pcg && bp.n_pcg && one_reduction) {
@@ -4137,7 +4152,10 @@ static hipError_t rig_iteration(const BatchPlan &cp, const BatchPlan &rp, int pc
   if (rp.n_pcg && one_reduction) {
     {
       Timed t(tm, K_PCG_SPMV, s);
-      k_cg_start<T><<<rp.n_pcg, 256, 0, s>>>(rp.probs, rp.pcg);
+      if (rp.pcg_rows >= kPcgRowsSparse)
+        k_cg_start<T, 16><<<rp.n_pcg, 1024, 0, s>>>(rp.probs, rp.pcg);
+      else
+        k_cg_start<T, 4><<<rp.n_pcg, 256, 0, s>>>(rp.probs, rp.pcg);
     }
     Timed t(tm, K_PCG_CG, s, pcg_max);
     hipError_t le = hipSuccess;
