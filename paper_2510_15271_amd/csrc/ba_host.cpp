@@ -727,6 +727,13 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
       }
       while (t <= nt) ts[t++] = r;
     }
+    // the camera-major walk of dense_cams reads each observation's record position and
+    // point from here, in order, instead of gathering them by observation index
+    sy.dn_crec.resize(sy.cam_obs.size());
+    for (size_t o = 0; o < sy.cam_obs.size(); ++o) {
+      const int k = sy.cam_obs[o];
+      sy.dn_crec[o] = make_int2(sy.obs_rpos[k], sy.obs_pt[k]);
+    }
   }
   if (sy.chunked)
     return build_chunks(sy, up_rowptr, up_col, chunk_pts_cap(prec), chunk_obs_cap(prec), chunk_cam_cap(prec));
@@ -782,6 +789,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.row_tot = L.take(sy.chunked || sy.dense ? Cf * 54 * 8 : 16);
   o.dn_ts = L.take(sy.dn_ts.size() * 4 + 4);
   o.dn_rcam = L.take(sy.dn_rcam.size() * 4 + 4);
+  o.dn_crec = L.take(sy.dn_crec.size() * 8 + 8);
   o.dn_mask = L.take(sy.dn_mask.size() * 2 + 4);
   o.dn_pfac = L.take(sy.dense ? P * 9 * T : 16);
   o.dn_part = L.take(sy.dense ? (size_t)sy.dn_tiles * (sy.dn_tiles + 1) / 2 * sy.dn_split * kDnRows * kDnRows * T
@@ -926,6 +934,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.row_tot = (double *)ptr(off.row_tot);
   pd.dn_ts = (const int32_t *)ptr(off.dn_ts);
   pd.dn_rcam = (const int32_t *)ptr(off.dn_rcam);
+  pd.dn_crec = (const int2 *)ptr(off.dn_crec);
   pd.dn_mask = (const uint16_t *)ptr(off.dn_mask);
   pd.dn_pfac = ptr(off.dn_pfac);
   pd.dn_part = ptr(off.dn_part);
@@ -1062,6 +1071,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
   chk(up(off.dn_ts, sy.dn_ts.data(), sy.dn_ts.size() * 4));
   chk(up(off.dn_rcam, sy.dn_rcam.data(), sy.dn_rcam.size() * 4));
+  chk(up(off.dn_crec, sy.dn_crec.data(), sy.dn_crec.size() * 8));
   chk(up(off.dn_mask, sy.dn_mask.data(), sy.dn_mask.size() * 2));
   chk(up(off.up_pos, sy.up_pos.data(), sy.up_pos.size() * 4));
   chk(up(off.up_tpos, sy.up_tpos.data(), sy.up_tpos.size() * 4));

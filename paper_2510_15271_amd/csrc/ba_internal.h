@@ -109,6 +109,7 @@ struct ProbDev {
   int32_t dn_split;      // point ranges per tile pair
   const int32_t *dn_ts;  // [P][dn_tiles + 1] first record of each point in each camera tile
   const int32_t *dn_rcam;  // [Nf] free camera of each record
+  const int2 *dn_crec;     // [Nf] (record, point) of each camera-major observation
   const uint16_t *dn_mask; // [P][dn_tiles] bit c: camera c of the tile observes the point
   void *dn_pfac;         // [P][9] T: L^-T (upper: 00 01 02 11 12 22) and h = L^-1 g_p of V*_j = L L^T
   void *dn_part;         // [dn_pairs][dn_split][kDnRows^2] T: Z Z^T over one point range

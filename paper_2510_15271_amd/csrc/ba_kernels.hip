@@ -3537,9 +3537,9 @@ __global__ __launch_bounds__(kDnCamThreads) void k_dense_cams(const ProbDev *__r
 #pragma unroll
   for (int i = 0; i < 33; ++i) acc[i] = T(0);
   for (int o = pd.cam_obs_start[a] + (int)threadIdx.x; o < pd.cam_obs_start[a + 1]; o += kDnCamThreads) {
-    const int k = pd.cam_obs[o];
-    const int j = pd.obs_pt[k];
-    const LinRec<T, S> rec = lin[pd.obs_rpos[k]];
+    const int2 cr = pd.dn_crec[o];  // record position, point
+    const int j = cr.y;
+    const LinRec<T, S> rec = lin[cr.x];
     T f[7], Jc[12], Jp[6], lt[6], hv[3], Z[18];
     decode(rec, f);
     jc_from(f, Jc);
@@ -3551,6 +3551,7 @@ __global__ __launch_bounds__(kDnCamThreads) void k_dense_cams(const ProbDev *__r
     acc_jtj_upper(acc, Jc);
     if (k16) {
       // 16-bit storage: the gradient from FP32 Jacobians at the linearisation state
+      const int k = pd.cam_obs[o];
       double xd, yd, zd;
       transform(pose, pd.X[st->cur] + 3 * (size_t)j, xd, yd, zd);
       const T xv = T(xd), yv = T(yd), zv = T(zd);

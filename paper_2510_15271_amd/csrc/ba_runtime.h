@@ -41,6 +41,7 @@ struct Symbolic {
   int32_t dn_tiles = 0, dn_split = 0;
   std::vector<int32_t> dn_ts;     // [P][dn_tiles + 1] (dense form)
   std::vector<int32_t> dn_rcam;   // [Nf] (dense form)
+  std::vector<int2> dn_crec;      // [Nf] (dense form) record and point of each camera-major observation
   std::vector<uint16_t> dn_mask;  // [P][dn_tiles] (dense form)
   // pair-list form
   std::vector<int32_t> cam_obs, cam_obs_start;
@@ -85,7 +86,7 @@ struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos, obs_act;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
   size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
-  size_t part_d, part_o, row_tot, dn_ts, dn_rcam, dn_mask, dn_pfac, dn_part;
+  size_t part_d, part_o, row_tot, dn_ts, dn_rcam, dn_crec, dn_mask, dn_pfac, dn_part;
   size_t pp_cam, pp_meas, pp_w, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
   size_t part_lin_cost, part_masked, part_sq, part_trial_cost, part_trial_masked, part_dl_pt, part_dl_cam;
