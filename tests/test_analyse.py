@@ -56,3 +56,20 @@ def test_analysis_rejects_invalid_input(balib):
     with pytest.raises(balib.BAError) as e:
         balib.analyse(balib.scene_desc(s), balib.options())
     assert e.value.code == balib.BA_EINVAL and "twice" in str(e.value)
+
+
+@pytest.mark.parametrize("n_cams,mean_track,flags,rows", [
+    (40, 8.0, 0, 4),       # few rows: 4 per tile
+    (40, 8.0, 8, 32),      # BA_FLAG_PCG_WIDE
+    (1100, 8.0, 0, 16),    # 1024 or more free cameras, sparse rows
+    (1100, 24.0, 0, 16),   # ... and rows of about 47 blocks: 4-row tiles would outnumber the CUs
+])
+def test_pcg_rows_per_tile(balib, n_cams, mean_track, flags, rows):
+    """Rows of the reduced system per PCG workgroup: 4 below 1024 free cameras, 16 from
+    there on whatever the row density, 32 with BA_FLAG_PCG_WIDE."""
+    s = make_small_drive(n_cams, 20 * n_cams, seed=9, mean_track=mean_track)
+    info, _ = balib.analyse(balib.scene_desc(s), balib.options(flags=flags))
+    _, nnzb, nf = _pairs_and_pattern(s) if n_cams < 200 else (0, info["nnzb"], info["n_free_cams"])
+    assert info["pcg_rows"] == rows, (info["pcg_rows"], nnzb / nf)
+    if mean_track > 20:
+        assert nnzb > 24 * nf  # the rows are dense: the rule does not ask for sparse rows
