@@ -3637,10 +3637,20 @@ struct DnMma<float, bf16s> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const dn_b8 *)a, *(const dn_b8 *)b, c, 0, 0, 0);
   }
 };
+// LDS layout of a Z tile in k_dense_schur: k-value kk of row r at
+// (kk / KI) * kDnRows * RS + r * RS + kk % KI, where a camera's six rows are spread
+// (row m of camera slot a at kDnCams * m + a), so that the 16 cameras a wave stores at
+// once fall in distinct banks, and a row holds KI values plus, for 16-bit operands, 8 of
+// padding, so that the 16-byte operand reads of 16 consecutive rows do not share banks.
+template <class T, class S>
+constexpr int dn_row_stride() {
+  return DnMma<T, S>::KI + (sizeof(typename DnMma<T, S>::E) == 2 ? 8 : 0);
+}
 // Dynamic LDS of k_dense_schur: two Z tiles of 3 PC k-values by kDnRows rows.
 template <class T, class S>
 constexpr size_t dn_lds_bytes() {
-  return 2 * (size_t)3 * DnMma<T, S>::PC * kDnRows * sizeof(typename DnMma<T, S>::E);
+  return 2 * (size_t)(3 * DnMma<T, S>::PC / DnMma<T, S>::KI) * kDnRows * dn_row_stride<T, S>() *
+         sizeof(typename DnMma<T, S>::E);
 }
 
 // Tile pair (ta <= tb) of a pair index, row-major over the upper triangle of nt tiles.
@@ -3670,9 +3680,10 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
   using V = typename M::V;
   constexpr int KI = M::KI, PC = M::PC, K = 3 * PC, NKS = K / KI, SUB = 256 / PC, KL = KI / 4;
   constexpr int NSLOT = kDnCams / SUB;  // camera slots of one point and tile per thread
+  constexpr int RS = dn_row_stride<T, S>(), BS = kDnRows * RS;  // row and k-block strides
   extern __shared__ __align__(16) double s_dyn[];
-  E *za = (E *)s_dyn;       // [NKS][kDnRows][KI]
-  E *zb = za + K * kDnRows;  // the same for tile tb (unused when ta == tb)
+  E *za = (E *)s_dyn;        // [NKS][kDnRows][RS]
+  E *zb = za + NKS * BS;     // the same for tile tb (unused when ta == tb)
   __shared__ T s_R[2][kDnCams][9];
   const Tile tl = tiles[blockIdx.x];
   const ProbDev &pd = probs[tl.prob];
@@ -3770,8 +3781,8 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
         for (int m = 0; m < 6; ++m)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const int kk = 3 * jl + c, row = 6 * la + m;
-            z[((kk / KI) * kDnRows + row) * KI + (kk % KI)] = E(Z[3 * m + c]);
+            const int kk = 3 * jl + c, row = kDnCams * m + la;
+            z[(kk / KI) * BS + row * RS + (kk % KI)] = E(Z[3 * m + c]);
           }
       }
     }
@@ -3780,13 +3791,13 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
     const E *zbb = diag ? za : zb;
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
-      const E *ab = za + (ks * kDnRows + li) * KI + lq * KL;
-      const E *bb = zbb + (ks * kDnRows + li) * KI + lq * KL;
+      const E *ab = za + ks * BS + li * RS + lq * KL;
+      const E *bb = zbb + ks * BS + li * RS + lq * KL;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          acc[r][c] = M::mma(ab + 16 * (rb0 + r) * KI, bb + 16 * (cb0 + c) * KI, acc[r][c]);
+          acc[r][c] = M::mma(ab + 16 * (rb0 + r) * RS, bb + 16 * (cb0 + c) * RS, acc[r][c]);
     }
   }
   T *out = (T *)pd.dn_part + (size_t)tl.idx * kDnRows * kDnRows;
@@ -3796,8 +3807,11 @@ __global__ __launch_bounds__(256) void k_dense_schur(const ProbDev *__restrict__
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = 16 * (rb0 + r) + (M::row_major_d ? 4 * lq + e : lq + 4 * e);
-        const int col = 16 * (cb0 + c) + li;
+        // LDS rows back to camera-major rows (6 per camera)
+        const int prow = 16 * (rb0 + r) + (M::row_major_d ? 4 * lq + e : lq + 4 * e);
+        const int pcol = 16 * (cb0 + c) + li;
+        const int row = 6 * (prow % kDnCams) + prow / kDnCams;
+        const int col = 6 * (pcol % kDnCams) + pcol / kDnCams;
         out[row * kDnRows + col] = T(acc[r][c][e]);
       }
 }
