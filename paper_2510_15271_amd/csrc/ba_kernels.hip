@@ -1187,35 +1187,41 @@ __global__ __launch_bounds__(256) void k_schur_off(const ProbDev *__restrict__ p
 template <class T>
 constexpr int chunk_threads() { return sizeof(T) == 8 ? kChThreads / 2 : kChThreads; }
 
-// Rows of 8 values in LDS (16-byte aligned), moved with 16-byte accesses.
-__device__ inline void load8(const float *p, float o[8]) {
-  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+// Rows of 8 values in LDS, kept as two arrays of 4-value halves (row l's halves at
+// p = base + 4 l and p + hs, hs = 4 x the row capacity) and moved with 16-byte accesses:
+// 16 lanes reading or writing consecutive rows then cover the 64 banks once, where whole
+// 32-byte rows put two lanes on each bank group, and rows taken in any order spread over
+// 16 bank groups instead of 8.
+__device__ inline void load8(const float *p, int hs, float o[8]) {
+  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + hs);
   o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
   o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
 }
-__device__ inline void load8(const double *p, double o[8]) {
+__device__ inline void load8(const double *p, int hs, double o[8]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const double2 a = *(const double2 *)(p + 2 * i);
+    const double2 a = *(const double2 *)((i < 2 ? p : p + hs) + 2 * (i & 1));
     o[2 * i] = a.x;
     o[2 * i + 1] = a.y;
   }
 }
-__device__ inline void store8(float *p, const float v[8]) {
+__device__ inline void store8(float *p, int hs, const float v[8]) {
   *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
-  *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  *(float4 *)(p + hs) = make_float4(v[4], v[5], v[6], v[7]);
 }
-__device__ inline void store8(double *p, const double v[8]) {
+__device__ inline void store8(double *p, int hs, const double v[8]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) *(double2 *)(p + 2 * i) = make_double2(v[2 * i], v[2 * i + 1]);
+  for (int i = 0; i < 4; ++i)
+    *(double2 *)((i < 2 ? p : p + hs) + 2 * (i & 1)) = make_double2(v[2 * i], v[2 * i + 1]);
 }
 
 template <class T>
-__device__ inline void pair_accumulate(T acc[36], const T *fa_lds, const T *q_lds, const T *fb_lds, const T *Rb) {
+__device__ inline void pair_accumulate(T acc[36], const T *fa_lds, const T *q_lds, const T *fb_lds, int hs,
+                                       const T *Rb) {
   T fa[8], q[8], fb[8];
-  load8(fa_lds, fa);
-  load8(q_lds, q);
-  load8(fb_lds, fb);
+  load8(fa_lds, hs, fa);
+  load8(q_lds, hs, q);
+  load8(fb_lds, hs, fb);
   T Jca[12], Jcb[12], Jpb[6];
   jc_from(fa, Jca);
   jc_from(fb, Jcb);
@@ -1242,8 +1248,9 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   // per record two rows of 8 (16-byte aligned, read with vector loads):
   // fe = f[0..6], e[0]; qq = Q[0..5], Q g_p[0..1]
   T *s_vi = (T *)s_dyn;           // [pcap][6]
-  T *s_fe = s_vi + 6 * pcap;      // [cap][8]
-  T *s_qq = s_fe + 8 * cap;       // [cap][8]
+  T *s_fe = s_vi + 6 * pcap;      // [2][cap][4]: rows of 8 in halves
+  T *s_qq = s_fe + 8 * cap;       // [2][cap][4]
+  constexpr int hs = 4 * cap;     // offset of a row's second half
   T *s_e1 = s_qq + 8 * cap;       // [cap] e[1]; 16-bit storage: [cap][6] FP32 gradient terms
   T *s_R = s_e1 + (k16 ? 6 : 1) * cap;  // [ccap][9] rotations of the chunk's cameras
   int *s_cam = (int *)(s_R + 9 * ccap);  // [ccap]
@@ -1338,8 +1345,8 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
       for (int i = 0; i < 6; ++i) qq[i] = q[i];
       qq[6] = q[0] * g0 + q[1] * g1 + q[2] * g2;
       qq[7] = q[3] * g0 + q[4] * g1 + q[5] * g2;
-      store8(s_fe + 8 * l, fe);
-      store8(s_qq + 8 * l, qq);
+      store8(s_fe + 4 * l, hs, fe);
+      store8(s_qq + 4 * l, hs, qq);
       if (k16) {
         // 16-bit storage: this record's gradient term w J_c^T r from FP32 Jacobians
         const int cm = cam[h];
@@ -1394,8 +1401,8 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         if (h >= n) break;
         const int l = (int)items[h];
         T fe[8], qq[8];
-        load8(s_fe + 8 * l, fe);
-        load8(s_qq + 8 * l, qq);
+        load8(s_fe + 4 * l, hs, fe);
+        load8(s_qq + 4 * l, hs, qq);
         T Jc[12];
         jc_from(fe, Jc);
         const T *Jc0 = Jc, *Jc1 = Jc + 6;
@@ -1424,8 +1431,8 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         if (h >= n) break;
         const int l = (int)items[h];
         T f[8], q[8];
-        load8(s_fe + 8 * l, f);
-        load8(s_qq + 8 * l, q);
+        load8(s_fe + 4 * l, hs, f);
+        load8(s_qq + 4 * l, hs, q);
         T Jc[12], Jp[6];
         jc_from(f, Jc);
         jp_from(f, R, Jp);
@@ -1447,7 +1454,7 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
       for (int h = 0; h < kChSubItems; ++h) {
         if (h >= n) break;
         const int p = (int)(items[h] & 0xffffu), qq = (int)(items[h] >> 16);
-        pair_accumulate<T>(acc, s_fe + 8 * p, s_qq + 8 * p, s_fe + 8 * qq, R);
+        pair_accumulate<T>(acc, s_fe + 4 * p, s_qq + 4 * p, s_fe + 4 * qq, hs, R);
       }
       T *o = pof + 36 * (size_t)slot;
 #pragma unroll
