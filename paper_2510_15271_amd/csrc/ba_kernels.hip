@@ -3385,32 +3385,43 @@ __global__ __launch_bounds__(kPoseThreads) void k_pose_gn(PoseDev *__restrict__ 
       for (int i = 0; i < 28; ++i) s_sum[w][i] = dacc[i];
     __syncthreads();
     if (threadIdx.x == 0) {
+      // every loop below has constant bounds and is unrolled, so that the 6x6 solve
+      // stays in registers (with its arrays indexed at run time it ran from scratch
+      // memory)
       double tot[28];
+#pragma unroll
       for (int i = 0; i < 28; ++i) tot[i] = s_sum[0][i] + s_sum[1][i] + s_sum[2][i] + s_sum[3][i];
       if (it == iters) {
         rq.cost = tot[27];
       } else {
         double H[36];
-        int u = 0;
-        for (int r = 0; r < 6; ++r)
-          for (int cc = r; cc < 6; ++cc, ++u) {
-            H[6 * r + cc] = tot[u];
-            H[6 * cc + r] = tot[u];
-          }
-        // Cholesky solve H d = -g
+        {
+          int u = 0;
+#pragma unroll
+          for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int cc = r; cc < 6; ++cc, ++u) {
+              H[6 * r + cc] = tot[u];
+              H[6 * cc + r] = tot[u];
+            }
+        }
+        // Cholesky solve H d = -g; a non-positive pivot marks the system singular (the
+        // columns after it are formed with a unit pivot and not used)
         double L[36];
         bool ok = true;
+#pragma unroll
         for (int i = 0; i < 36; ++i) L[i] = 0.0;
-        for (int j = 0; j < 6 && ok; ++j) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
           double s = H[7 * j];
+#pragma unroll
           for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
-          if (!(s > 0.0)) {
-            ok = false;
-            break;
-          }
-          L[7 * j] = sqrt(s);
+          ok = ok && s > 0.0;
+          L[7 * j] = ok ? sqrt(s) : 1.0;
+#pragma unroll
           for (int i = j + 1; i < 6; ++i) {
             double t = H[6 * i + j];
+#pragma unroll
             for (int k = 0; k < j; ++k) t -= L[6 * i + k] * L[6 * j + k];
             L[6 * i + j] = t / L[7 * j];
           }
@@ -3419,23 +3430,30 @@ __global__ __launch_bounds__(kPoseThreads) void k_pose_gn(PoseDev *__restrict__ 
           s_bad = 1;
         } else {
           double yv[6], d[6];
+#pragma unroll
           for (int i = 0; i < 6; ++i) {
             double s = -tot[21 + i];
+#pragma unroll
             for (int k = 0; k < i; ++k) s -= L[6 * i + k] * yv[k];
             yv[i] = s / L[7 * i];
           }
+#pragma unroll
           for (int i = 5; i >= 0; --i) {
             double s = yv[i];
+#pragma unroll
             for (int k = i + 1; k < 6; ++k) s -= L[6 * k + i] * d[k];
             d[i] = s / L[7 * i];
           }
           double dR[9], dt[3], np[12];
           se3_exp(d, dR, dt);
+#pragma unroll
           for (int r = 0; r < 3; ++r) {
+#pragma unroll
             for (int cc = 0; cc < 3; ++cc)
               np[3 * r + cc] = dR[3 * r] * s_pose[cc] + dR[3 * r + 1] * s_pose[3 + cc] + dR[3 * r + 2] * s_pose[6 + cc];
             np[9 + r] = dR[3 * r] * s_pose[9] + dR[3 * r + 1] * s_pose[10] + dR[3 * r + 2] * s_pose[11] + dt[r];
           }
+#pragma unroll
           for (int i = 0; i < 12; ++i) s_pose[i] = np[i];
         }
       }
