@@ -1943,6 +1943,11 @@ __device__ __forceinline__ void cg_step_body(const ProbDev &pd, const int tile, 
   __shared__ int s_flag[1];
   const Tile tl{0, tile};
   const LMState *st = pd.st;
+  // A launch that finds the solve finished leaves before issuing any other load: the
+  // graph of an LM iteration holds every allowed PCG step, and once the PCG has
+  // converged the rest only pass through here.  (A tile that sees the flag its own
+  // launch's tile 0 has just set leaves as it would after its own convergence test.)
+  if (!(lm_active(st) && !st->pcg_done && it < st->pcg_max)) return;
   const int t = threadIdx.x;
   const int pr = it & 1, cu = (it + 1) & 1;
   const int nt = pd.n_pcg_tiles;
