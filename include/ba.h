@@ -462,7 +462,9 @@ int ba_pose_batch_noalloc(int32_t n_req, const ba_pose_request *reqs, const ba_o
 
 /* ---------------------------------------------------------------- serving
    Continuous batching: submitted problems wait in a queue; a scheduler thread
-   admits them while a slot is free and their device bytes fit the budget, and
+   admits them in submission order while a slot is free and their device bytes fit
+   the budget (a later problem that fits may go ahead of one that does not, up to 16
+   times, after which admission waits for the one passed over), and
    advances every admitted problem by one LM iteration per batched launch
    sequence; a finished problem retires, frees its bytes and its slot, and the
    next queued one joins the running batch.  Pose-only requests run in batched

@@ -5,7 +5,8 @@
 // allocator.  A submitted problem is validated and copied in the caller's
 // thread; its symbolic analysis runs on a pool of host threads.  A scheduler
 // thread repeats: admit analysed problems in ticket order while a slot is free
-// and their bytes fit; launch one LM iteration for every admitted problem at
+// and their bytes fit (a later problem that fits may pass one that does not, a
+// bounded number of times); launch one LM iteration for every admitted problem at
 // once (one launch per kernel for the whole batch); run all queued pose-only
 // requests in one launch.  Each launch sequence advances every problem it holds
 // by exactly one iteration, so the host counts iterations itself and never waits
@@ -112,6 +113,7 @@ struct Req {
   Symbolic sy;
   DevProblem dp;
   int steps = 0;  // LM iterations launched for it
+  int passed = 0; // later problems admitted while it waited for memory
   // pose-only
   ba_pose_request preq{};
   std::vector<double> pX, puv;
@@ -152,6 +154,9 @@ struct Completion {
 };
 
 constexpr int kLookahead = 2;  // launch sequences the scheduler may run ahead of the device
+// Later problems that may be admitted ahead of one that waits for memory; past that,
+// admission waits for it, so that a large request is not starved by small ones.
+constexpr int kMaxPassed = 16;
 
 // A lower bound of the device bytes a problem needs, from its sizes alone: its
 // observation arrays and its point and camera state.
@@ -377,16 +382,26 @@ void ba_server::loop() {
         pose_q.pop_front();
       }
       if (!pose_now.empty()) pb_ok = arena.alloc(pose_bytes + 512, pb_off);
-      // analysed problems in ticket order; one that does not fit holds back the later ones
-      while (!ready.empty() && fatal == BA_OK) {
-        ReqP r = ready.begin()->second;
-        if ((int)(active.size() + uploaded.size() + up_q.size() + uploading + admitted.size()) >= max_slots) break;
-        size_t off;
-        if (!arena.alloc(r->bytes, off)) break;
-        r->off = off;
-        r->holds_block = true;
-        admitted.push_back(r);
-        ready.erase(ready.begin());
+      // analysed problems in ticket order; a later one that fits may go ahead of one that
+      // does not fit, until that one has been passed kMaxPassed times
+      {
+        std::vector<Req *> waiting;  // earlier problems that did not fit, in ticket order
+        for (auto it = ready.begin(); it != ready.end() && fatal == BA_OK;) {
+          if ((int)(active.size() + uploaded.size() + up_q.size() + uploading + admitted.size()) >= max_slots) break;
+          if (!waiting.empty() && waiting.front()->passed >= kMaxPassed) break;
+          ReqP r = it->second;
+          size_t off;
+          if (!arena.alloc(r->bytes, off)) {
+            waiting.push_back(r.get());
+            ++it;
+            continue;
+          }
+          for (Req *w : waiting) ++w->passed;
+          r->off = off;
+          r->holds_block = true;
+          admitted.push_back(r);
+          it = ready.erase(it);
+        }
       }
       peak = std::max(peak, arena.used);
       for (auto &r : admitted) up_q.push_back(r);

@@ -110,6 +110,44 @@ def test_admission_respects_budget_and_slots(balib):
     srv.close()
 
 
+def test_small_request_passes_one_waiting_for_memory(balib):
+    """A budget for one large problem and one small one: large A runs, large B (submitted
+    next) waits for memory, and small C, submitted after B, is admitted beside A instead
+    of waiting behind B, so it finishes before A does; every result equals, bit for bit,
+    the problem solved alone."""
+    A = make_small_drive(60, 6000, seed=140)
+    B = make_small_drive(60, 6000, seed=141)
+    Cs = make_small_drive(15, 600, seed=142)
+    iters = {"A": 300, "B": 5, "C": 3}
+    sizes = {}
+    for name, s in (("A", A), ("B", B), ("C", Cs)):
+        p = balib.Problem.from_scene(s, max_iters=iters[name])
+        sizes[name] = p.nbytes
+        p.close()
+    budget = sizes["A"] + sizes["C"] + (1 << 20)
+    _say("bytes", sizes, "budget", budget)
+    assert sizes["B"] > sizes["C"] + (1 << 20)  # A and B do not fit together
+    srv = balib.Server(budget, 4)
+    t0 = time.perf_counter()
+    ta = srv.submit(balib.scene_desc(A), balib.options(max_iters=iters["A"]))
+    tb = srv.submit(balib.scene_desc(B), balib.options(max_iters=iters["B"]))
+    time.sleep(0.05)  # A is running and B analysed and waiting when C arrives
+    t_c = time.perf_counter()
+    tc = srv.submit(balib.scene_desc(Cs), balib.options(max_iters=iters["C"]))
+    rc, ra, rb = srv.wait(tc), srv.wait(ta), srv.wait(tb)
+    st = srv.stats()
+    srv.close()
+    done_a = ra["latency_ms"] / 1e3
+    done_c = (t_c - t0) + rc["latency_ms"] / 1e3
+    _say("A done at", done_a, "s, C done at", done_c, "s, B latency", rb["latency_ms"], "ms", st)
+    assert done_c < done_a
+    assert st["peak_bytes"] <= budget
+    for name, s, r in (("A", A, ra), ("B", B, rb), ("C", Cs, rc)):
+        a = _alone(balib, s, iters[name], "f32")
+        assert np.array_equal(r["iter_cost"], a["iter_cost"]), name
+        assert np.array_equal(r["X"], a["X"]) and np.array_equal(r["t"], a["t"]), name
+
+
 def test_pose_requests_through_server_equal_batch(balib):
     reqs = make_config4_requests(40, seed=1004)
     ref = balib.pose_batch(reqs, iters=10, huber_delta=1.0)
