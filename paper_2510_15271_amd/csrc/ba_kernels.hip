@@ -1855,8 +1855,28 @@ __global__ __launch_bounds__(64 * NW) void k_cg_start(const ProbDev *__restrict_
     if (a >= pd.Cf) break;
     T acc = T(0);
     if (lane < 60) {
+      // four blocks at a time, their loads issued before the first product (the sum
+      // stays in block order)
       const int b1 = pd.S_rowptr[a + 1];
-      for (int blk = pd.S_rowptr[a] + g; blk < b1; blk += 10) {
+      int blk = pd.S_rowptr[a] + g;
+      for (; blk + 30 < b1; blk += 40) {
+        T sv[4][6], uv[4][6];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = pd.S_col[blk + 10 * q];
+          const T *Srow = S + 36 * (size_t)(blk + 10 * q) + 6 * i;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            sv[q][m] = Srow[m];
+            uv[q][m] = u[6 * c + m];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int m = 0; m < 6; ++m) acc += sv[q][m] * uv[q][m];
+      }
+      for (; blk < b1; blk += 10) {
         const int c = pd.S_col[blk];
         const T *Srow = S + 36 * (size_t)blk + 6 * i;
 #pragma unroll
