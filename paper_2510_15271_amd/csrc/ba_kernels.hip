@@ -2273,8 +2273,16 @@ __device__ inline bool grid_barrier(uint32_t *flag, int n_tiles, int tile, uint3
     if (t == 0) st_shared(flag + tile, stamp);
     bool all = false;
     for (int n = 0; n < polls; ++n) {
+      // a lane's flags (up to four: 256 tiles) are loaded together, so that one poll
+      // costs one round trip; a loop over them waited for each load before the next
+      // (lanes past the last tile load its flag again: every load is unconditional)
       bool mine = true;
-      for (int k = t; k < n_tiles; k += 64) mine = mine && ld_shared(flag + k) >= stamp;
+      uint32_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = ld_shared(flag + min(t + 64 * q, n_tiles - 1));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mine = mine & (v[q] >= stamp);
+      for (int k = t + 256; k < n_tiles; k += 64) mine = mine & (ld_shared(flag + k) >= stamp);
       all = __all(mine) != 0;
       if (all) break;
       __builtin_amdgcn_s_sleep(1);
