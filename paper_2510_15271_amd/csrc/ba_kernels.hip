@@ -2766,12 +2766,33 @@ __global__ __launch_bounds__(256) void k_lm_control(const ProbDev *__restrict__ 
   // the tile sums, each in the order of block_sum_array (thread-strided, then the
   // four waves in order), all loaded in one pass and reduced through one barrier
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // lin cost, trial cost, dl_pt, masked, trial masked, dl_cam
-  for (int i = threadIdx.x; i < pd.n_pt_tiles; i += 256) {
-    v[0] += pd.part_lin_cost[i];
-    v[1] += pd.part_trial_cost[i];
-    v[2] += pd.part_dl_pt[i];
-    v[3] += (double)pd.part_masked[i];
-    v[4] += (double)pd.part_trial_masked[i];
+  {
+    // a thread's loads of kU strides are all issued before its sums, which run in
+    // index order (loads past the end read the last tile and add nothing)
+    constexpr int kU = 8;
+    const int n = pd.n_pt_tiles;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
+      double l0[kU], l1[kU], l2[kU];
+      int32_t m0[kU], m1[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = min(i0 + 256 * u, n - 1);
+        l0[u] = pd.part_lin_cost[i];
+        l1[u] = pd.part_trial_cost[i];
+        l2[u] = pd.part_dl_pt[i];
+        m0[u] = pd.part_masked[i];
+        m1[u] = pd.part_trial_masked[i];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (i0 + 256 * u < n) {
+          v[0] += l0[u];
+          v[1] += l1[u];
+          v[2] += l2[u];
+          v[3] += (double)m0[u];
+          v[4] += (double)m1[u];
+        }
+    }
   }
   for (int i = threadIdx.x; i < pd.n_cam_tiles; i += 256) v[5] += pd.part_dl_cam[i];
   {
