@@ -197,7 +197,8 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
   sy.ent_tgt.clear();
   sy.ent_cam.clear();
   sy.ent_slot.clear();
-  sy.ent_start.assign(1, 0);
+  sy.ent_start.clear();
+  sy.ent_len.clear();
   sy.ent_items.clear();
   sy.n_dent = sy.n_oent = 0;
   std::vector<int32_t> la, ll;  // local camera and local record of one point's observations
@@ -208,7 +209,7 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
     int32_t a, b;
     size_t i0, i1;
   };
-  std::vector<Ent> wave, thread;  // diagonal and upper entries of one chunk
+  std::vector<Ent> wave, thread, ordered;  // diagonal and upper entries of one chunk; both in launch order
   for (int c = 0; c < n_ch; ++c) {
     const int f0 = sy.ch_f0[c];
     const int q0 = sy.ch_cam_start[c], nq = sy.ch_cam_start[c + 1] - q0;
@@ -259,24 +260,39 @@ static int build_chunks(Symbolic &sy, const std::vector<int32_t> &up_rowptr,
     const auto longer = [](const Ent &p, const Ent &q) { return p.i1 - p.i0 > q.i1 - q.i0; };
     std::stable_sort(wave.begin(), wave.end(), longer);
     std::stable_sort(thread.begin(), thread.end(), longer);
-    for (const std::vector<Ent> *lst : {&wave, &thread})
-      for (const Ent &en : *lst) {
-        if (en.a == en.b) {
-          sy.ent_tgt.push_back(en.a);
-          sy.ent_cam.push_back(lcam[en.a]);
-          sy.ent_slot.push_back(sy.n_dent++);
-        } else {
-          const auto beg = up_col.begin() + up_rowptr[en.a], end = up_col.begin() + up_rowptr[en.a + 1];
-          const auto pos = std::lower_bound(beg, end, en.b);
-          if (pos == end || *pos != en.b) return fail(BA_EDEVICE, "internal: block (%d, %d) missing", en.a, en.b);
-          sy.ent_tgt.push_back(Cf + (int32_t)(pos - up_col.begin()));
-          sy.ent_cam.push_back(lcam[en.b]);
-          sy.ent_slot.push_back(sy.n_oent++);
-        }
-        for (size_t i = en.i0; i < en.i1; ++i) sy.ent_items.push_back(sorted[i]);
-        if (sy.ent_items.size() > (size_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 chunk items");
-        sy.ent_start.push_back((int32_t)sy.ent_items.size());
+    ordered.clear();
+    for (const std::vector<Ent> *lst : {&wave, &thread}) ordered.insert(ordered.end(), lst->begin(), lst->end());
+    for (const Ent &en : ordered) {
+      if (en.a == en.b) {
+        sy.ent_tgt.push_back(en.a);
+        sy.ent_cam.push_back(lcam[en.a]);
+        sy.ent_slot.push_back(sy.n_dent++);
+      } else {
+        const auto beg = up_col.begin() + up_rowptr[en.a], end = up_col.begin() + up_rowptr[en.a + 1];
+        const auto pos = std::lower_bound(beg, end, en.b);
+        if (pos == end || *pos != en.b) return fail(BA_EDEVICE, "internal: block (%d, %d) missing", en.a, en.b);
+        sy.ent_tgt.push_back(Cf + (int32_t)(pos - up_col.begin()));
+        sy.ent_cam.push_back(lcam[en.b]);
+        sy.ent_slot.push_back(sy.n_oent++);
       }
+    }
+    // items in slices of kEntSlice entries (a wavefront's, in launch order): item h of the
+    // slice's entry l at h * kEntSlice + l, so that the threads of a wavefront read item h
+    // of their entries from one contiguous run; shorter entries leave zeros
+    for (size_t s0 = 0; s0 < ordered.size(); s0 += kEntSlice) {
+      const size_t sn = std::min(ordered.size() - s0, (size_t)kEntSlice);
+      size_t H = 0;
+      for (size_t l = 0; l < sn; ++l) H = std::max(H, ordered[s0 + l].i1 - ordered[s0 + l].i0);
+      const size_t base = sy.ent_items.size();
+      if (base + H * kEntSlice > (size_t)INT32_MAX) return fail(BA_EINVAL, "more than 2^31 chunk items");
+      sy.ent_items.resize(base + H * kEntSlice, 0u);
+      for (size_t l = 0; l < sn; ++l) {
+        const Ent &en = ordered[s0 + l];
+        for (size_t h = 0; h < en.i1 - en.i0; ++h) sy.ent_items[base + h * kEntSlice + l] = sorted[en.i0 + h];
+        sy.ent_start.push_back((int32_t)(base + l));
+        sy.ent_len.push_back((uint8_t)(en.i1 - en.i0));
+      }
+    }
     sy.ch_ent.push_back((int32_t)sy.ent_tgt.size());
     for (int x = sy.ch_cam_start[c]; x < sy.ch_cam_start[c + 1]; ++x) lcam[sy.free_idx[sy.ch_cam[x]]] = -1;
   }
@@ -782,6 +798,7 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.ent_cam = L.take(sy.ent_cam.size() * 4 + 4);
   o.ent_slot = L.take(sy.ent_slot.size() * 4 + 4);
   o.ent_start = L.take(sy.ent_start.size() * 4 + 4);
+  o.ent_len = L.take(sy.ent_len.size() + 4);
   o.ent_items = L.take(sy.ent_items.size() * 4 + 4);
   o.blk_start = L.take(sy.blk_start.size() * 4 + 4);
   o.part_d = L.take((size_t)sy.n_dent * 54 * T + 16);
@@ -926,6 +943,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   pd.ent_cam = (const int32_t *)ptr(off.ent_cam);
   pd.ent_slot = (const int32_t *)ptr(off.ent_slot);
   pd.ent_start = (const int32_t *)ptr(off.ent_start);
+  pd.ent_len = (const uint8_t *)ptr(off.ent_len);
   pd.ent_items = (const uint32_t *)ptr(off.ent_items);
   pd.blk_start = (const int32_t *)ptr(off.blk_start);
   pd.n_dent = sy.n_dent;
@@ -1067,6 +1085,7 @@ int DevProblem::init(const Symbolic &sy, const ba_problem_desc *d, const ba_opti
   chk(up(off.ent_cam, sy.ent_cam.data(), sy.ent_cam.size() * 4));
   chk(up(off.ent_slot, sy.ent_slot.data(), sy.ent_slot.size() * 4));
   chk(up(off.ent_start, sy.ent_start.data(), sy.ent_start.size() * 4));
+  chk(up(off.ent_len, sy.ent_len.data(), sy.ent_len.size()));
   chk(up(off.ent_items, sy.ent_items.data(), sy.ent_items.size() * 4));
   chk(up(off.blk_start, sy.blk_start.data(), sy.blk_start.size() * 4));
   chk(up(off.dn_ts, sy.dn_ts.data(), sy.dn_ts.size() * 4));
@@ -1379,6 +1398,8 @@ static int create_problem(const ba_problem_desc *d, const ba_options *opt, void 
   p->sy.pairs.shrink_to_fit();
   p->sy.ent_items.clear();
   p->sy.ent_items.shrink_to_fit();
+  p->sy.ent_len.clear();
+  p->sy.ent_len.shrink_to_fit();
   p->sy.obs_order.clear();
   p->sy.obs_order.shrink_to_fit();
   p->dp.staging_f.clear();

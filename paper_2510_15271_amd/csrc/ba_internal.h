@@ -30,6 +30,7 @@ constexpr int kPoseThreads = 256;
 constexpr int kChPts = 256;
 constexpr int kChThreads = 1024;
 constexpr int kChSubItems = 32;  // items per chunk entry (one thread each)
+constexpr int kEntSlice = 64;    // chunk entries whose items are interleaved (one wavefront's)
 inline int chunk_obs_cap(int precision) { return precision == 0 ? 1024 : precision == 1 ? 1984 : 1600; }
 inline int chunk_pts_cap(int precision) { return precision == 0 ? kChPts / 2 : kChPts; }
 inline int chunk_cam_cap(int precision) { return precision == 0 ? 128 : 256; }
@@ -141,8 +142,9 @@ struct ProbDev {
   const int32_t *ent_cam;         // chunk-local camera whose rotation the entry needs
   const int32_t *ent_slot;        // position of the entry's partial in part_d / part_o (its
                                   // position in its block's list, upper blocks counted from 0)
-  const int32_t *ent_start;       // [n_ent + 1] item range
-  const uint32_t *ent_items;
+  const int32_t *ent_start;       // [n_ent] first item; item h of the entry at ent_start + h * kEntSlice
+  const uint8_t *ent_len;         // [n_ent] items
+  const uint32_t *ent_items;      // per chunk, slices of kEntSlice entries: [slice][h][entry of the slice]
   const int32_t *blk_start;       // [Cf + n_up + 1] entries of each block, in chunk order
   int32_t n_dent;                 // diagonal entries (part_d rows)
   const int32_t *up_pos;          // [n_up] block (a, b) in S

@@ -1381,13 +1381,13 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   T *pof = (T *)pd.part_o;
   for (int e = e0 + threadIdx.x; e < e1; e += nth) {
     const int tgt = pd.ent_tgt[e];
-    const int i0 = pd.ent_start[e], n = pd.ent_start[e + 1] - i0;
+    const int i0 = pd.ent_start[e], n = pd.ent_len[e];
     const int slot = pd.ent_slot[e];
     const int lc = pd.ent_cam[e];
     const T *R = s_R + 9 * lc;
     uint32_t items[kChSubItems];
 #pragma unroll
-    for (int h = 0; h < kChSubItems; ++h) items[h] = h < n ? pd.ent_items[i0 + h] : 0u;
+    for (int h = 0; h < kChSubItems; ++h) items[h] = h < n ? pd.ent_items[i0 + kEntSlice * h] : 0u;
     if (tgt < pd.Cf) {
       // diagonal block of camera cam over its observations, in two passes to bound
       // the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
@@ -1839,8 +1839,18 @@ __global__ __launch_bounds__(64 * NW) void k_cg_start(const ProbDev *__restrict_
   // reads (its loads issued here, reduced after its rows); with b = 0 every tile's
   // products are zero and harmless
   double vbb = 0.0;
-  if (tl.idx == 0 && threadIdx.x < 256)
-    for (int i = threadIdx.x; i < pd.Cf; i += 256) vbb += pd.part_bb[i];
+  if (tl.idx == 0 && threadIdx.x < 256) {
+    constexpr int kU = 8;  // a thread's loads of kU strides issued together, summed in order
+    const int n = pd.Cf;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) v[u] = pd.part_bb[min(i0 + 256 * u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (i0 + 256 * u < n) vbb += v[u];
+    }
+  }
   const T *u = (const T *)pd.cg_u[0];
   const T *r = (const T *)pd.cg_r[0];
   T *w = (T *)pd.cg_w[0];

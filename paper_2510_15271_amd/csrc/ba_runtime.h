@@ -51,6 +51,7 @@ struct Symbolic {
   std::vector<int32_t> ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam;
   std::vector<int32_t> ent_tgt, ent_cam, ent_slot, ent_start;
   std::vector<uint32_t> ent_items;
+  std::vector<uint8_t> ent_len;
   std::vector<int32_t> blk_start;
   int32_t n_dent = 0, n_oent = 0;
   // relative-pose pairs (caller's camera indices): sequential prior pairs or pose-graph
@@ -85,7 +86,7 @@ int analyse(const ba_problem_desc *d, const ba_options *opt, Symbolic &sy, const
 struct Offsets {
   size_t st, K, free_idx, free_cam, obs_cam, obs_pt, obs_uv, pt_start, cam_obs, cam_obs_start, obs_rpos, obs_act;
   size_t up_pair_start, pairs, up_pos, up_tpos, diag_pos, S_rowptr, S_col, tcol, S_lcol;
-  size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_items, blk_start;
+  size_t ch_pt, ch_f0, ch_ent, ch_cam_start, ch_cam, ent_tgt, ent_cam, ent_slot, ent_start, ent_len, ent_items, blk_start;
   size_t part_d, part_o, row_tot, dn_ts, dn_rcam, dn_crec, dn_mask, dn_pfac, dn_part;
   size_t pp_cam, pp_meas, pp_w, pp_up, cam_pp_start, cam_pp, prior_diag, prior_off;
   size_t pose[2], X[2], pose_init, X_init, lin, Q, V, gp, Dp, Vinv, gc, Dc, brhs, S, Minv, vec[14];
