@@ -43,6 +43,17 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "schur_reduce", "schur_rows", "schur_finish", "prior_lin", "prior_apply", "cull", "rig_blocks",
     "rig_rows", "rig_update", "prior_cost", "dense_prep", "dense_cams", "dense_schur", "dense_reduce"};
 
+// A pointer read from a problem's device view is generic to the compiler, which then
+// issues flat memory instructions; a flat access also counts against the LDS wait
+// counter, so an LDS read waits for every such access still in flight.  Accesses made
+// through as_global(p) are global ones.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ global_t<T> *as_global(T *p) {
+  return (global_t<T> *)p;
+}
+
 // ------------------------------------------------------------------ storage codecs
 // Jacobians are stored scaled by sqrt(w).  FP16 storage keeps them times 2^-4 so
 // that entries up to 1e6 stay finite; BF16 has the FP32 exponent range.
@@ -87,6 +98,25 @@ struct LinRec {
   S f[7];
   T e[2];  // sqrt(w) r
 };
+
+// A record between registers and global memory, as 32-bit words.
+template <class R>
+__device__ __forceinline__ R load_rec(const global_t<const R> *p) {
+  static_assert(sizeof(R) % 4 == 0, "records are whole words");
+  R r;
+  const auto w = (const global_t<const uint32_t> *)p;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(R) / 4); ++i) d[i] = w[i];
+  return r;
+}
+template <class R>
+__device__ __forceinline__ void store_rec(global_t<R> *p, const R &r) {
+  const auto w = (global_t<uint32_t> *)p;
+  const uint32_t *d = reinterpret_cast<const uint32_t *>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(R) / 4); ++i) w[i] = d[i];
+}
 
 template <class T, class S>
 __device__ inline void decode(const LinRec<T, S> &rec, T f[7]) {
@@ -184,9 +214,13 @@ __device__ inline void acc_jtj_upper(T acc[21], const T Jc[12]) {
 }
 
 template <class T>
-__device__ inline void load_rot(const double *pose, T R[9]) {
+__device__ inline void load_rot(const global_t<const double> *pose, T R[9]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) R[i] = T(pose[i]);
+}
+template <class T>
+__device__ inline void load_rot(const double *pose, T R[9]) {  // pose: a pose buffer in global memory
+  load_rot(as_global(pose), R);
 }
 
 size_t lin_record_bytes(int precision) {
@@ -360,8 +394,8 @@ __device__ inline T huber_rho(T s, T delta) {
 }
 
 // World -> camera transform in FP64 from the FP64 state.
-__device__ inline void transform(const double *pose, const double *X, double &x, double &y,
-                                 double &z) {
+template <class PP, class XP>  // pointers to double, generic or global
+__device__ inline void transform(PP pose, XP X, double &x, double &y, double &z) {
   x = pose[0] * X[0] + pose[1] * X[1] + pose[2] * X[2] + pose[9];
   y = pose[3] * X[0] + pose[4] * X[1] + pose[5] * X[2] + pose[10];
   z = pose[6] * X[0] + pose[7] * X[1] + pose[8] * X[2] + pose[11];
@@ -369,8 +403,8 @@ __device__ inline void transform(const double *pose, const double *X, double &x,
 
 // Residual of one observation in compute type T.  Returns false when the
 // point is at or behind the depth threshold (observation masked).
-template <class T>
-__device__ inline bool residual(const T *K, T x, T y, T z, T uo, T vo, T &r0, T &r1) {
+template <class T, class KP>  // KP: pointer to T, generic or global
+__device__ inline bool residual(KP K, T x, T y, T z, T uo, T vo, T &r0, T &r1) {
   if (!(z > T(kZMin))) {
     r0 = r1 = T(0);
     return false;
@@ -531,11 +565,13 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
   __shared__ double s_red[kObsChunk / 64];
   for (int i = threadIdx.x; i < kPtTile * 9; i += kObsChunk) (&s_acc[0][0])[i] = T(0);
 
-  const T *Kall = (const T *)pd.K;
-  const T *uv = (const T *)pd.obs_uv;
-  LinRec<T, S> *lin = (LinRec<T, S> *)pd.lin;
-  const double *poses = pd.pose[cur];
-  const double *Xs = pd.X[cur];
+  const auto Kall = as_global((const T *)pd.K);
+  const auto uv = as_global((const T *)pd.obs_uv);
+  const auto lin = as_global((LinRec<T, S> *)pd.lin);
+  const auto poses = as_global((const double *)pd.pose[cur]);
+  const auto Xs = as_global((const double *)pd.X[cur]);
+  const auto obs_pt = as_global(pd.obs_pt), obs_cam = as_global(pd.obs_cam), obs_rpos = as_global(pd.obs_rpos);
+  const auto obs_act = as_global((const uint8_t *)pd.obs_act);
   double cost = 0.0;
   int masked = 0;
   // the observation's own fields for the next pass are loaded while the current pass
@@ -545,10 +581,10 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
   T nu = T(0), nv = T(0);
   auto fetch = [&](int k) {
     if (k < k1) {
-      nj = pd.obs_pt[k];
-      ncam = pd.obs_cam[k];
-      ncpos = pd.obs_rpos[k];
-      non = pd.obs_act[k] != 0;
+      nj = obs_pt[k];
+      ncam = obs_cam[k];
+      ncpos = obs_rpos[k];
+      non = obs_act[k] != 0;
       nu = uv[2 * (size_t)k];
       nv = uv[2 * (size_t)k + 1];
     }
@@ -568,11 +604,11 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
     int jl = -1;
     if (k < k1) {
       jl = j - j0;
-      const double *pose = poses + 12 * cam;
+      const auto pose = poses + 12 * cam;
       double xd, yd, zd;
       transform(pose, Xs + 3 * j, xd, yd, zd);
       const T x = T(xd), y = T(yd), z = T(zd);
-      const T *K = Kall + 4 * cam;
+      const auto K = Kall + 4 * cam;
       T r0, r1;
       LinRec<T, S> rec;
       if (on && residual<T>(K, x, y, z, ou, ov, r0, r1)) {
@@ -615,13 +651,13 @@ __global__ __launch_bounds__(kObsChunk) void k_linearize(const ProbDev *__restri
         for (int i = 0; i < 7; ++i) rec.f[i] = Codec<S>::enc(0.0f);
         rec.e[0] = rec.e[1] = T(0);
       }
-      if (cpos >= 0) lin[cpos] = rec;  // records are kept for free cameras only
+      if (cpos >= 0) store_rec(lin + cpos, rec);  // records are kept for free cameras only
     }
     seg_add_scan<T, 9>(c, jl, s_acc, s_c, s_loc);
   }
-  T *V = (T *)pd.V;
-  T *gp = (T *)pd.gp;
-  T *Dp = (T *)pd.Dp;
+  const auto V = as_global((T *)pd.V);
+  const auto gp = as_global((T *)pd.gp);
+  const auto Dp = as_global((T *)pd.Dp);
   for (int jl = threadIdx.x; jl < j1 - j0; jl += kObsChunk) {
     const int j = j0 + jl;
 #pragma unroll
@@ -1264,8 +1300,8 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   const double *poses = pd.pose[st->cur];
   // the chunk's first records (two per thread): indices and compact records are
   // loaded before the point inverses, so that their latency overlaps them
-  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-  const T *gp = (const T *)pd.gp;
+  const auto lin = as_global((const LinRec<T, S> *)pd.lin);
+  const auto gp = as_global((const T *)pd.gp);
   const int k0 = pd.pt_start[j0], k1 = pd.pt_start[j1];
   int kk[2], rp[2], cam[2], jj[2];
   LinRec<T, S> rec[2];
@@ -1273,19 +1309,19 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       kk[h] = base + h * nth + (int)threadIdx.x;
-      rp[h] = kk[h] < k1 ? pd.obs_rpos[kk[h]] : -1;
-      cam[h] = kk[h] < k1 ? pd.obs_cam[kk[h]] : 0;
-      jj[h] = kk[h] < k1 ? pd.obs_pt[kk[h]] : j0;
-      if (rp[h] >= 0) rec[h] = lin[rp[h]];
+      rp[h] = kk[h] < k1 ? as_global(pd.obs_rpos)[kk[h]] : -1;
+      cam[h] = kk[h] < k1 ? as_global(pd.obs_cam)[kk[h]] : 0;
+      jj[h] = kk[h] < k1 ? as_global(pd.obs_pt)[kk[h]] : j0;
+      if (rp[h] >= 0) rec[h] = load_rec(lin + rp[h]);
     }
   };
   fetch(k0);
   // a. point inverses
   {
     const double lam = st->lambda;
-    const T *V = (const T *)pd.V;
-    const T *Dp = (const T *)pd.Dp;
-    T *Vinv = (T *)pd.Vinv;
+    const auto V = as_global((const T *)pd.V);
+    const auto Dp = as_global((const T *)pd.Dp);
+    const auto Vinv = as_global((T *)pd.Vinv);
     for (int jl = threadIdx.x; jl < j1 - j0; jl += nth) {
       const int j = j0 + jl;
       double u[6], o[6];
@@ -1377,22 +1413,23 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   // c. entries, one thread each: sums over at most kChSubItems items of one
   // block, all item indices loaded before the arithmetic
   const int e0 = pd.ch_ent[c], e1 = pd.ch_ent[c + 1];
-  T *pdg = (T *)pd.part_d;
-  T *pof = (T *)pd.part_o;
+  const auto pdg = as_global((T *)pd.part_d);
+  const auto pof = as_global((T *)pd.part_o);
+  const auto items_g = as_global(pd.ent_items);
   for (int e = e0 + threadIdx.x; e < e1; e += nth) {
-    const int tgt = pd.ent_tgt[e];
-    const int i0 = pd.ent_start[e], n = pd.ent_len[e];
-    const int slot = pd.ent_slot[e];
-    const int lc = pd.ent_cam[e];
+    const int tgt = as_global(pd.ent_tgt)[e];
+    const int i0 = as_global(pd.ent_start)[e], n = as_global(pd.ent_len)[e];
+    const int slot = as_global(pd.ent_slot)[e];
+    const int lc = as_global(pd.ent_cam)[e];
     const T *R = s_R + 9 * lc;
     uint32_t items[kChSubItems];
 #pragma unroll
-    for (int h = 0; h < kChSubItems; ++h) items[h] = h < n ? pd.ent_items[i0 + kEntSlice * h] : 0u;
+    for (int h = 0; h < kChSubItems; ++h) items[h] = h < n ? items_g[i0 + kEntSlice * h] : 0u;
     if (tgt < pd.Cf) {
       // diagonal block of camera cam over its observations, in two passes to bound
       // the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
       const int cam = s_cam[lc];
-      T *o = pdg + 54 * (size_t)slot;
+      const auto o = pdg + 54 * (size_t)slot;
       T acc[33];
 #pragma unroll
       for (int i = 0; i < 33; ++i) acc[i] = T(0);
@@ -1456,7 +1493,7 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
         const int p = (int)(items[h] & 0xffffu), qq = (int)(items[h] >> 16);
         pair_accumulate<T>(acc, s_fe + 4 * p, s_qq + 4 * p, s_fe + 4 * qq, hs, R);
       }
-      T *o = pof + 36 * (size_t)slot;
+      const auto o = pof + 36 * (size_t)slot;
 #pragma unroll
       for (int i = 0; i < 36; ++i) o[i] = acc[i];
     }
@@ -2663,8 +2700,11 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
   __shared__ double s_X[kPtTile][3];
   __shared__ double s_red[kObsChunk / 64];
   for (int i = threadIdx.x; i < kPtTile * 3; i += kObsChunk) (&s_acc[0][0])[i] = T(0);
-  const LinRec<T, S> *lin = (const LinRec<T, S> *)pd.lin;
-  const T *x = (const T *)pd.x;
+  const auto lin = as_global((const LinRec<T, S> *)pd.lin);
+  const auto x = as_global((const T *)pd.x);
+  const auto obs_pt = as_global(pd.obs_pt), obs_cam = as_global(pd.obs_cam), obs_rpos = as_global(pd.obs_rpos);
+  const auto obs_act = as_global((const uint8_t *)pd.obs_act);
+  const auto free_idx = as_global(pd.free_idx);
   __syncthreads();
   // phase 1: sum_k W_k^T dc_{cam(k)} = sum_k J_p^T (J_c dc) per point
   for (int base = k0; base < k1; base += kObsChunk) {
@@ -2672,17 +2712,18 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
     T c[3] = {T(0), T(0), T(0)};
     int jl = -1;
     if (k < k1) {
-      jl = pd.obs_pt[k] - j0;
-      const int cpos = pd.obs_rpos[k];
+      jl = obs_pt[k] - j0;
+      const int cpos = obs_rpos[k];
       if (cpos >= 0) {
-        const int cam = pd.obs_cam[k];
-        const int a = pd.free_idx[cam];
+        const int cam = obs_cam[k];
+        const int a = free_idx[cam];
         T f[7], R[9], Jc[12], Jp[6];
-        decode(lin[cpos], f);
+        const LinRec<T, S> rec = load_rec(lin + cpos);
+        decode(rec, f);
         load_rot(pd.pose[cur] + 12 * cam, R);  // the linearisation state
         jc_from(f, Jc);
         jp_from(f, R, Jp);
-        const T *dc = x + 6 * a;
+        const auto dc = x + 6 * a;
         T u0 = T(0), u1 = T(0);
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -2697,19 +2738,19 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
     seg_add_scan<T, 3>(c, jl, s_acc, s_c, s_loc);
   }
   // phase 2: dp_j, trial point, point part of the predicted decrease
-  const T *Vinv = (const T *)pd.Vinv;
-  const T *gp = (const T *)pd.gp;
-  const T *Dp = (const T *)pd.Dp;
+  const auto Vinv = as_global((const T *)pd.Vinv);
+  const auto gp = as_global((const T *)pd.gp);
+  const auto Dp = as_global((const T *)pd.Dp);
   double dl = 0.0;
   for (int jl = threadIdx.x; jl < j1 - j0; jl += kObsChunk) {
     const int j = j0 + jl;
-    const T *vi = Vinv + 6 * (size_t)j;
+    const auto vi = Vinv + 6 * (size_t)j;
     const T M[9] = {vi[0], vi[1], vi[2], vi[1], vi[3], vi[4], vi[2], vi[4], vi[5]};
     T rhs[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) rhs[i] = -gp[3 * j + i] - s_acc[jl][i];
-    const double *X = pd.X[cur] + 3 * (size_t)j;
-    double *Xn = pd.X[1 - cur] + 3 * (size_t)j;
+    const auto X = as_global((const double *)pd.X[cur]) + 3 * (size_t)j;
+    const auto Xn = as_global(pd.X[1 - cur]) + 3 * (size_t)j;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const T d = M[3 * i] * rhs[0] + M[3 * i + 1] * rhs[1] + M[3 * i + 2] * rhs[2];
@@ -2722,15 +2763,15 @@ __global__ __launch_bounds__(kObsChunk) void k_point_trial(const ProbDev *__rest
   }
   __syncthreads();
   // phase 3: trial cost at (T', X')
-  const T *Kall = (const T *)pd.K;
-  const T *uv = (const T *)pd.obs_uv;
-  const double *poses = pd.pose[1 - cur];
+  const auto Kall = as_global((const T *)pd.K);
+  const auto uv = as_global((const T *)pd.obs_uv);
+  const auto poses = as_global((const double *)pd.pose[1 - cur]);
   double cost = 0.0;
   int masked = 0;
   for (int k = k0 + threadIdx.x; k < k1; k += kObsChunk) {
-    if (!pd.obs_act[k]) continue;
-    const int jl = pd.obs_pt[k] - j0;
-    const int cam = pd.obs_cam[k];
+    if (!obs_act[k]) continue;
+    const int jl = obs_pt[k] - j0;
+    const int cam = obs_cam[k];
     double xd, yd, zd;
     transform(poses + 12 * cam, s_X[jl], xd, yd, zd);
     T r0, r1;
