@@ -1428,7 +1428,6 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
     if (tgt < pd.Cf) {
       // diagonal block of camera cam over its observations, in two passes to bound
       // the live accumulators: U, g_c, Y g_p (33), then Y W^T (21)
-      const int cam = s_cam[lc];
       const auto o = pdg + 54 * (size_t)slot;
       T acc[33];
 #pragma unroll
