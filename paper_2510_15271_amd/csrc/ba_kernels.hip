@@ -1411,7 +1411,8 @@ __global__ __launch_bounds__(chunk_threads<T>()) void k_schur_chunk(const ProbDe
   }
   __syncthreads();
   // c. entries, one thread each: sums over at most kChSubItems items of one
-  // block, all item indices loaded before the arithmetic
+  // block, all item indices loaded before the arithmetic (item h of the 64 entries of
+  // a wavefront is one contiguous run: one coalesced load)
   const int e0 = pd.ch_ent[c], e1 = pd.ch_ent[c + 1];
   const auto pdg = as_global((T *)pd.part_d);
   const auto pof = as_global((T *)pd.part_o);
