@@ -1325,8 +1325,10 @@ struct ba_problem {
   bool use_graph = true;
   hipGraph_t graph = nullptr;       // the launch sequence of one solve, captured once
   hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t seg_graph[3] = {};     // one LM iteration in three parts (before / PCG run / after)
-  hipGraphExec_t seg_exec[3] = {};
+  // the LM iterations around their PCG runs: before the first run, the run, after a run and
+  // before the next one, after the last run
+  hipGraph_t seg_graph[4] = {};
+  hipGraphExec_t seg_exec[4] = {};
   EventTimer timer;  // times the kernels selected by timer.mask
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
@@ -1821,14 +1823,21 @@ int ba_solve_async(ba_problem *p) {
     return BA_OK;
   } else if (p->use_graph && !p->rig && p->timer.mask == (1u << K_PCG_CG) &&
              one_reduction_pcg(p->dp.precision, p->dp.max_tcols)) {
-    // Only the PCG run is timed: replay one LM iteration as three graphs (their
-    // launches are the same in every iteration) with the timing events between them.
+    // Only the PCG run is timed: the solve is replayed as graphs between the PCG runs
+    // (their launches are the same in every iteration), with the timing events around
+    // each run: two graph launches per LM iteration.
     if (!p->seg_exec[0]) {
-      for (int part = 0; part < 3; ++part) {
+      for (int part = 0; part < 4; ++part) {
         e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture");
+        // 0: before the first run; 1: a run; 2: after a run, then before the next; 3: after
+        // the last run
+        const int first = part == 0 ? LM_BEFORE_PCG : part == 1 ? LM_PCG : LM_AFTER_PCG;
         hipError_t el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols,
-                                            p->stream, nullptr, LM_BEFORE_PCG + part);
+                                            p->stream, nullptr, first);
+        if (part == 2 && el == hipSuccess)
+          el = launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols, p->stream,
+                                   nullptr, LM_BEFORE_PCG);
         e = hipStreamEndCapture(p->stream, &p->seg_graph[part]);
         if (el != hipSuccess) return hip_fail(el, "kernel launch during capture");
         if (e != hipSuccess) return hip_fail(e, "graph capture");
@@ -1838,12 +1847,12 @@ int ba_solve_async(ba_problem *p) {
     }
     p->timer.reset();
     (void)hipEventRecord(p->ev0, p->stream);
+    if (p->dp.max_iters > 0) e = hipGraphLaunch(p->seg_exec[0], p->stream);
     for (int it = 0; it < p->dp.max_iters && e == hipSuccess; ++it) {
-      e = hipGraphLaunch(p->seg_exec[0], p->stream);
       p->timer.begin(K_PCG_CG, p->stream, p->sy.pcg_resident ? 1 : p->dp.pcg_max);
-      if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[1], p->stream);
+      e = hipGraphLaunch(p->seg_exec[1], p->stream);
       p->timer.end(K_PCG_CG, p->stream);
-      if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[2], p->stream);
+      if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[it + 1 < p->dp.max_iters ? 2 : 3], p->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "graph launch");
   } else {
@@ -2180,7 +2189,7 @@ void ba_destroy(ba_problem *p) {
   if (p->pending) (void)hipStreamSynchronize(p->stream);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     if (p->seg_exec[i]) (void)hipGraphExecDestroy(p->seg_exec[i]);
     if (p->seg_graph[i]) (void)hipGraphDestroy(p->seg_graph[i]);
   }
