@@ -1850,7 +1850,10 @@ int ba_solve_async(ba_problem *p) {
     if (p->dp.max_iters > 0) e = hipGraphLaunch(p->seg_exec[0], p->stream);
     for (int it = 0; it < p->dp.max_iters && e == hipSuccess; ++it) {
       p->timer.begin(K_PCG_CG, p->stream, p->sy.pcg_resident ? 1 : p->dp.pcg_max);
-      e = hipGraphLaunch(p->seg_exec[1], p->stream);
+      // the resident run is one kernel: launched directly, not as a one-node graph
+      e = p->sy.pcg_resident ? launch_lm_iteration(p->dp.precision, p->batch.plan, p->dp.pcg_max, p->dp.max_tcols,
+                                                   p->stream, nullptr, LM_PCG)
+                             : hipGraphLaunch(p->seg_exec[1], p->stream);
       p->timer.end(K_PCG_CG, p->stream);
       if (e == hipSuccess) e = hipGraphLaunch(p->seg_exec[it + 1 < p->dp.max_iters ? 2 : 3], p->stream);
     }
