@@ -1333,6 +1333,8 @@ struct ba_problem {
   double kernel_ms[K_NUM_KERNELS] = {};
   int32_t kernel_launches[K_NUM_KERNELS] = {};
   double solve_ms = 0.0;
+  char *rep_pin = nullptr;  // page-locked: the fresh state's upload slot and the report block
+  bool rep_ok = false;      // rep_pin holds the last solve's report
 };
 
 extern "C" {
@@ -1787,9 +1789,18 @@ int ba_pose_graph_create(const ba_pose_graph_desc *g, const ba_options *opt, voi
 int ba_solve_async(ba_problem *p) {
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending) return fail(BA_ESTATE, "a solve is already in flight");
-  p->dp.pending_state = p->dp.fresh_state();  // source of the async copy: must outlive it
-  hipError_t e = hipMemcpyAsync(p->dp.view.st, &p->dp.pending_state, sizeof(LMState),
-                                hipMemcpyHostToDevice, p->stream);
+  p->rep_ok = false;
+  if (!p->rep_pin) {
+    hipError_t ea = hipHostMalloc((void **)&p->rep_pin, p->dp.report_bytes(), hipHostMallocDefault);
+    if (ea != hipSuccess) {
+      p->rep_pin = nullptr;
+      return hip_fail(ea, "report buffer");
+    }
+  }
+  // the fresh state goes up from page-locked memory (the slot is free: no solve is in flight)
+  const LMState fresh = p->dp.fresh_state();
+  std::memcpy(p->rep_pin, &fresh, sizeof(LMState));
+  hipError_t e = hipMemcpyAsync(p->dp.view.st, p->rep_pin, sizeof(LMState), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(e, "state upload");
   KernelTimer *tm = p->profiling ? &p->timer : nullptr;
   if (p->use_graph && !p->profiling) {
@@ -1819,6 +1830,8 @@ int ba_solve_async(ba_problem *p) {
     // the final evaluation stays outside the graph and is not timed
     e = launch_eval(p->dp.precision, p->batch.plan, p->stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    e = p->dp.enqueue_report(p->stream, p->rep_pin);
+    if (e != hipSuccess) return hip_fail(e, "report copy");
     p->pending = true;
     return BA_OK;
   } else if (p->use_graph && !p->rig && p->timer.mask == (1u << K_PCG_CG) &&
@@ -1871,6 +1884,8 @@ int ba_solve_async(ba_problem *p) {
   (void)hipEventRecord(p->ev1, p->stream);
   e = launch_eval(p->dp.precision, p->batch.plan, p->stream, tm);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  e = p->dp.enqueue_report(p->stream, p->rep_pin);
+  if (e != hipSuccess) return hip_fail(e, "report copy");
   p->pending = true;
   return BA_OK;
 }
@@ -1884,8 +1899,8 @@ int ba_wait(ba_problem *p) {
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
   p->solve_ms = ms;
-  e = hipMemcpy(&p->dp.host_state, p->dp.view.st, sizeof(LMState), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "state download");
+  std::memcpy(&p->dp.host_state, p->rep_pin + DevProblem::report_state_offset(), sizeof(LMState));
+  p->rep_ok = true;
   if (p->profiling) p->timer.collect(p->kernel_ms, p->kernel_launches);
   p->solved = true;
   return BA_OK;
@@ -1901,7 +1916,8 @@ int ba_get_result(const ba_problem *pc, ba_pose *poses_out, double *points_out, 
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending)
     if (int e = ba_wait(p)) return e;
-  return p->dp.read_result(p->stream, poses_out, points_out, rep, p->solved, p->solve_ms, p->setup_ms);
+  return p->dp.read_result(p->stream, poses_out, points_out, rep, p->solved, p->solve_ms, p->setup_ms,
+                           p->rep_ok ? p->rep_pin : nullptr);
 }
 
 int ba_reset(ba_problem *p) {
@@ -1924,6 +1940,7 @@ int ba_reset(ba_problem *p) {
   dp.host_state = LMState{};
   dp.host_state.cur = 0;
   p->solved = false;
+  p->rep_ok = false;
   return BA_OK;
 }
 
@@ -2199,6 +2216,7 @@ void ba_destroy(ba_problem *p) {
   if (p->mem) (void)hipFree(p->mem);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->rep_pin) (void)hipHostFree(p->rep_pin);
   if (p->own_stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -2342,6 +2360,45 @@ struct ResultLayout {
 
 size_t DevProblem::result_bytes() const { return ResultLayout(C, P, view.n_pt_tiles, max_iters).total; }
 
+namespace {
+// Byte offsets of the report block (each part 8-byte aligned): the upload slot of the
+// fresh state, then the state after the solve, the evaluation partials and the
+// per-iteration arrays.
+struct ReportLayout {
+  size_t up, st, sq, nm, ic, pi, total;
+  ReportLayout(int npt, int max_iters) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      const size_t r = o;
+      o += (b + 7) & ~size_t(7);
+      return r;
+    };
+    up = take(sizeof(LMState));
+    st = take(sizeof(LMState));
+    sq = take((size_t)npt * 8);
+    nm = take((size_t)npt * 4);
+    ic = take(((size_t)max_iters + 1) * 8);
+    pi = take((size_t)max_iters * 4);
+    total = o;
+  }
+};
+}  // namespace
+
+size_t DevProblem::report_bytes() const { return ReportLayout(view.n_pt_tiles, max_iters).total; }
+size_t DevProblem::report_state_offset() { return ReportLayout(0, 0).st; }
+
+hipError_t DevProblem::enqueue_report(hipStream_t s, char *pinned) const {
+  const ReportLayout L(view.n_pt_tiles, max_iters);
+  hipError_t e = hipMemcpyAsync(pinned + L.st, view.st, sizeof(LMState), hipMemcpyDeviceToHost, s);
+  const size_t npt = (size_t)view.n_pt_tiles;
+  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.sq, view.part_sq, npt * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.nm, view.part_masked, npt * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pinned + L.ic, view.iter_cost, ((size_t)max_iters + 1) * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && max_iters > 0)
+    e = hipMemcpyAsync(pinned + L.pi, view.iter_pcg, (size_t)max_iters * 4, hipMemcpyDeviceToHost, s);
+  return e;
+}
+
 hipError_t DevProblem::enqueue_result(hipStream_t s, char *pinned) const {
   const ResultLayout L(C, P, view.n_pt_tiles, max_iters);
   hipError_t e = hipMemcpyAsync(pinned + L.st, view.st, sizeof(LMState), hipMemcpyDeviceToHost, s);
@@ -2396,9 +2453,12 @@ void DevProblem::finish_result(const char *pinned, ba_pose *poses_out, double *p
 }
 
 int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
-                            bool solved, double solve_ms, double setup_ms) {
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "sync");
+                            bool solved, double solve_ms, double setup_ms, const char *rep_pin) {
+  hipError_t e = hipSuccess;
+  if (!rep_pin || poses_out || points_out) {  // a staged report has landed already
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "sync");
+  }
   const int cur = host_state.cur;
   if (poses_out) {
     std::vector<double> buf(12 * (size_t)C);
@@ -2430,11 +2490,17 @@ int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_ou
       rep->lambda = st.lambda;
       rep->solve_ms = solve_ms;
       const int npt = view.n_pt_tiles;
+      const ReportLayout RL(npt, max_iters);
       std::vector<double> sq(npt);
       std::vector<int32_t> nm(npt);
-      e = hipMemcpy(sq.data(), view.part_sq, npt * 8, hipMemcpyDeviceToHost);
-      if (e == hipSuccess) e = hipMemcpy(nm.data(), view.part_masked, npt * 4, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) return hip_fail(e, "report download");
+      if (rep_pin) {
+        std::memcpy(sq.data(), rep_pin + RL.sq, npt * 8);
+        std::memcpy(nm.data(), rep_pin + RL.nm, npt * 4);
+      } else {
+        e = hipMemcpy(sq.data(), view.part_sq, npt * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(nm.data(), view.part_masked, npt * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "report download");
+      }
       double tot = 0.0;
       int64_t masked = 0;
       for (int i = 0; i < npt; ++i) {
@@ -2444,11 +2510,13 @@ int DevProblem::read_result(hipStream_t s, ba_pose *poses_out, double *points_ou
       rep->n_masked = (int32_t)masked;
       rep->rms_px = (n_active - masked) > 0 ? std::sqrt(tot / (double)(n_active - masked)) : 0.0;
       if (ic) {
-        e = hipMemcpy(ic, view.iter_cost, (st.iter + 1) * 8, hipMemcpyDeviceToHost);
+        e = rep_pin ? (std::memcpy(ic, rep_pin + RL.ic, (st.iter + 1) * 8), hipSuccess)
+                    : hipMemcpy(ic, view.iter_cost, (st.iter + 1) * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "report download");
       }
       if (pi && st.iter > 0) {
-        e = hipMemcpy(pi, view.iter_pcg, st.iter * 4, hipMemcpyDeviceToHost);
+        e = rep_pin ? (std::memcpy(pi, rep_pin + RL.pi, st.iter * 4), hipSuccess)
+                    : hipMemcpy(pi, view.iter_pcg, st.iter * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "report download");
       }
     }

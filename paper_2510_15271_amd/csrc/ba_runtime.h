@@ -118,8 +118,17 @@ struct DevProblem {
   int init(const Symbolic &sy, const ba_problem_desc *d, const ba_options *opt, char *base,
            hipStream_t s);
   LMState fresh_state() const;
+  // rep_pin: the solve's report block staged by enqueue_report (already landed), or
+  // nullptr to read the report from the device
   int read_result(hipStream_t s, ba_pose *poses_out, double *points_out, ba_report *rep,
-                  bool solved, double solve_ms, double setup_ms);
+                  bool solved, double solve_ms, double setup_ms, const char *rep_pin = nullptr);
+  // The report of a solve without host round trips: enqueue_report queues on stream s
+  // the copies of the state, the evaluation partials and the per-iteration arrays into
+  // `pinned`, a page-locked buffer of report_bytes() (its first LMState is the upload
+  // slot of the next solve's fresh state, see report_upload).
+  size_t report_bytes() const;
+  hipError_t enqueue_report(hipStream_t s, char *pinned) const;
+  static size_t report_state_offset();
   // The same result without a host wait: enqueue_result queues on stream s the copies
   // of everything the report needs (the state, both pose and point buffers, the
   // evaluation partials and the per-iteration arrays) into `pinned`, a page-locked
