@@ -768,6 +768,30 @@ struct Layout {
 };
 }  // namespace
 
+namespace {
+// Byte offsets of the report block (each part 8-byte aligned): the upload slot of the
+// fresh state, then the state after the solve, the evaluation partials and the
+// per-iteration arrays.
+struct ReportLayout {
+  size_t up, st, sq, nm, ic, pi, total;
+  ReportLayout(int npt, int max_iters) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      const size_t r = o;
+      o += (b + 7) & ~size_t(7);
+      return r;
+    };
+    up = take(sizeof(LMState));
+    st = take(sizeof(LMState));
+    sq = take((size_t)npt * 8);
+    nm = take((size_t)npt * 4);
+    ic = take(((size_t)max_iters + 1) * 8);
+    pi = take((size_t)max_iters * 4);
+    total = o;
+  }
+};
+}  // namespace
+
 size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offsets &o) {
   const size_t T = compute_bytes(precision);
   const size_t C = sy.C, Cf = sy.Cf, P = sy.P, N = sy.N;
@@ -775,7 +799,11 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   const size_t npcg = (Cf + sy.pcg_rows - 1) / sy.pcg_rows;
   const size_t ncam = (C + kCamTile - 1) / kCamTile;
   Layout L;
-  o.st = L.take(sizeof(LMState));
+  // the report block: the state, the evaluation partials and the per-iteration arrays,
+  // placed as in the page-locked report, so that one copy brings a solve's report up
+  const ReportLayout RL((int)npt, max_iters);
+  const size_t rep = L.take(RL.total);
+  o.st = rep + RL.st;
   o.K = L.take(C * 4 * T);
   o.free_idx = L.take(C * 4);
   o.free_cam = L.take(Cf * 4);
@@ -846,8 +874,8 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.Minv = L.take(Cf * 36 * 8);
   for (int i = 0; i < 14; ++i) o.vec[i] = L.take(Cf * 6 * T);
   o.part_lin_cost = L.take(npt * 8);
-  o.part_masked = L.take(npt * 4);
-  o.part_sq = L.take(npt * 8);
+  o.part_masked = rep + RL.nm;
+  o.part_sq = rep + RL.sq;
   o.part_trial_cost = L.take(npt * 8);
   o.part_trial_masked = L.take(npt * 4);
   o.part_dl_pt = L.take(npt * 8);
@@ -862,8 +890,8 @@ size_t DevProblem::plan(const Symbolic &sy, int precision, int max_iters, Offset
   o.cg_flag = L.take(npcg * 4);
   o.part_rr = L.take(npcg * 8);
   o.part_cull = L.take(npt * 8);
-  o.iter_cost = L.take((max_iters + 1) * 8);
-  o.iter_pcg = L.take(max_iters * 4);
+  o.iter_cost = rep + RL.ic;
+  o.iter_pcg = rep + RL.pi;
   o.total = L.off;
   return L.off;
 }
@@ -2360,43 +2388,14 @@ struct ResultLayout {
 
 size_t DevProblem::result_bytes() const { return ResultLayout(C, P, view.n_pt_tiles, max_iters).total; }
 
-namespace {
-// Byte offsets of the report block (each part 8-byte aligned): the upload slot of the
-// fresh state, then the state after the solve, the evaluation partials and the
-// per-iteration arrays.
-struct ReportLayout {
-  size_t up, st, sq, nm, ic, pi, total;
-  ReportLayout(int npt, int max_iters) {
-    size_t o = 0;
-    auto take = [&](size_t b) {
-      const size_t r = o;
-      o += (b + 7) & ~size_t(7);
-      return r;
-    };
-    up = take(sizeof(LMState));
-    st = take(sizeof(LMState));
-    sq = take((size_t)npt * 8);
-    nm = take((size_t)npt * 4);
-    ic = take(((size_t)max_iters + 1) * 8);
-    pi = take((size_t)max_iters * 4);
-    total = o;
-  }
-};
-}  // namespace
 
 size_t DevProblem::report_bytes() const { return ReportLayout(view.n_pt_tiles, max_iters).total; }
 size_t DevProblem::report_state_offset() { return ReportLayout(0, 0).st; }
 
 hipError_t DevProblem::enqueue_report(hipStream_t s, char *pinned) const {
+  // the device block has the same layout (plan): one copy from the state to the end
   const ReportLayout L(view.n_pt_tiles, max_iters);
-  hipError_t e = hipMemcpyAsync(pinned + L.st, view.st, sizeof(LMState), hipMemcpyDeviceToHost, s);
-  const size_t npt = (size_t)view.n_pt_tiles;
-  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.sq, view.part_sq, npt * 8, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && npt) e = hipMemcpyAsync(pinned + L.nm, view.part_masked, npt * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(pinned + L.ic, view.iter_cost, ((size_t)max_iters + 1) * 8, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && max_iters > 0)
-    e = hipMemcpyAsync(pinned + L.pi, view.iter_pcg, (size_t)max_iters * 4, hipMemcpyDeviceToHost, s);
-  return e;
+  return hipMemcpyAsync(pinned + L.st, view.st, L.total - L.st, hipMemcpyDeviceToHost, s);
 }
 
 hipError_t DevProblem::enqueue_result(hipStream_t s, char *pinned) const {
