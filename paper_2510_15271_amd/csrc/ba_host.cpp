@@ -1952,12 +1952,10 @@ int ba_reset(ba_problem *p) {
   if (!p) return fail(BA_EINVAL, "problem is NULL");
   if (p->pending) return fail(BA_ESTATE, "a solve is in flight");
   DevProblem &dp = p->dp;
-  hipError_t e = hipMemcpyAsync(dp.view.pose[0], dp.dev + dp.off.pose_init, 12 * (size_t)dp.C * 8,
-                                hipMemcpyDeviceToDevice, p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dp.view.X[0], dp.dev + dp.off.X_init, 3 * (size_t)dp.P * 8,
-                       hipMemcpyDeviceToDevice, p->stream);
-  if (e == hipSuccess && dp.N > 0) e = hipMemsetAsync(dp.view.obs_act, 1, (size_t)dp.N, p->stream);
+  // one launch in place of two copies and a fill
+  hipError_t e = launch_reset(dp.view.pose[0], (const double *)(dp.dev + dp.off.pose_init), 12 * (size_t)dp.C,
+                              dp.view.X[0], (const double *)(dp.dev + dp.off.X_init), 3 * (size_t)dp.P,
+                              dp.view.obs_act, (size_t)dp.N, p->stream);
   if (e == hipSuccess && p->rig) {
     DevProblem &rd = p->rig->dp;
     e = hipMemcpyAsync(rd.view.pose[0], rd.dev + rd.off.pose_init, 12 * (size_t)rd.C * 8, hipMemcpyDeviceToDevice,

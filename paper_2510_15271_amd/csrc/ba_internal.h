@@ -307,6 +307,10 @@ hipError_t launch_rig_iteration(int precision, const BatchPlan &cam, const Batch
                                 int max_tcols, hipStream_t s, KernelTimer *timer);
 // Evaluate sum ||r||^2 and the masked count at the accepted state.
 hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, KernelTimer *timer);
+// Restores pose[0], X[0] from their initial copies and sets every observation active
+// (act: a 256-byte-aligned device array of n_act bytes).
+hipError_t launch_reset(double *pose, const double *pose_init, size_t n_pose, double *X, const double *X_init,
+                        size_t n_X, uint8_t *act, size_t n_act, hipStream_t s);
 // Culling and re-triangulation at the accepted state: observations with
 // ||r||^2 > tau2 (or depth <= the threshold) leave the problem; points that lost
 // one are re-triangulated (midpoint) from the rest, or leave if that fails.

@@ -4417,6 +4417,32 @@ hipError_t launch_eval(int precision, const BatchPlan &bp, hipStream_t s, Kernel
   return hipGetLastError();
 }
 
+// A problem's initial state restored in one launch: the pose and point buffers of index 0
+// from their initial copies, and every observation active again.
+__global__ __launch_bounds__(256) void k_reset(double *__restrict__ pose, const double *__restrict__ pose_init,
+                                               int64_t n_pose, double *__restrict__ X,
+                                               const double *__restrict__ X_init, int64_t n_X,
+                                               uint32_t *__restrict__ act_words, int64_t n_words,
+                                               uint8_t *__restrict__ act_tail, int n_tail) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < n_pose; i += stride) pose[i] = pose_init[i];
+  for (int64_t i = i0; i < n_X; i += stride) X[i] = X_init[i];
+  for (int64_t i = i0; i < n_words; i += stride) act_words[i] = 0x01010101u;
+  if (i0 < n_tail) act_tail[i0] = 1;
+}
+
+hipError_t launch_reset(double *pose, const double *pose_init, size_t n_pose, double *X, const double *X_init,
+                        size_t n_X, uint8_t *act, size_t n_act, hipStream_t s) {
+  // act: the start of a 256-byte-aligned allocation, so that its words are aligned
+  const size_t n_words = n_act / 4;
+  const size_t most = std::max(std::max(n_pose, n_X), n_words);
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>((most + 255) / 256, 2048));
+  k_reset<<<grid, 256, 0, s>>>(pose, pose_init, (int64_t)n_pose, X, X_init, (int64_t)n_X, (uint32_t *)act,
+                               (int64_t)n_words, act + 4 * n_words, (int)(n_act - 4 * n_words));
+  return hipGetLastError();
+}
+
 hipError_t launch_cull(int precision, const BatchPlan &bp, double tau2, int method, hipStream_t s,
                        KernelTimer *timer) {
   if (!bp.n_pt) return hipSuccess;
