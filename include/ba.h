@@ -179,7 +179,11 @@ int ba_create(const ba_problem_desc *d, const ba_options *opt, void *hip_stream,
 /* Run opt->max_iters LM iterations from the current state (lambda reset to
    lambda0) and wait for them.  The state after the call is the last accepted one. */
 int ba_solve(ba_problem *p);
-/* Enqueue the iterations on the problem's stream and return; ba_wait blocks. */
+/* Enqueue the iterations on the problem's stream and return; ba_wait blocks.  The
+   solve's report (state, final evaluation, per-iteration costs and PCG counts) is
+   copied into page-locked memory of the problem behind the solve, so that after
+   ba_wait a report from ba_get_result needs no device traffic.  The first call
+   allocates that buffer (BA_ENOMEM or BA_EDEVICE if it cannot). */
 int ba_solve_async(ba_problem *p);
 int ba_wait(ba_problem *p);
 /* Restore the poses and points given to ba_create (device-side copy; the
