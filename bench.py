@@ -642,17 +642,21 @@ def main():
     dom_ms, dom_launch, pcg_iters = 0.0, 0, 0
     print(f"bench: timing {args.steps} steps", flush=True, file=sys.stderr)
     t0 = time.perf_counter()
+    steps_log = []  # printed after the timed region
     for _ in range(args.steps):
         prob.reset().solve()
         r = prob.report()
         dev_ms.append(r["solve_ms"])
         ms, nl = prob.kernel_times()[dominant]
-        print(f"bench: step {r['iters']} iters, {r['solve_ms']:.3f} ms device, {dominant} "
-              f"{ms:.3f} ms over {nl} launches", flush=True, file=sys.stderr)
+        steps_log.append((r["iters"], r["solve_ms"], ms, nl))
         dom_ms += ms
         dom_launch += nl
         pcg_iters += int(sum(r["pcg_iters"]))
     wall = time.perf_counter() - t0
+    for it, sm, ms, nl in steps_log:
+        print(f"bench: step {it} iters, {sm:.3f} ms device, {dominant} {ms:.3f} ms over {nl} launches",
+              file=sys.stderr)
+    sys.stderr.flush()
     prob.set_profiling(0)
 
     ms_per_step = 1000.0 * wall / args.steps
