@@ -276,17 +276,20 @@ def test_config1_full_size_against_stored_oracle_run(balib):
     assert res["cost"] < 0.5 * res["cost0"]
 
 
+@pytest.mark.parametrize("stride", [1, 2])
 @pytest.mark.parametrize("flags", [0, 16])
-def test_profiled_solves_equal_unprofiled(balib, flags):
+def test_profiled_solves_equal_unprofiled(balib, flags, stride):
     """Timing changes how launches are issued (one graph, segment graphs with the PCG
     runs timed by events between them, launch by launch), never what they compute: all
     give identical results; a second timed solve replays the segment graphs and reads
-    its events again.  flags 16: the resident PCG (one launch per linear solve)."""
+    its events again.  flags 16: the resident PCG (one launch per linear solve).
+    stride 2: every second LM iteration's PCG run is timed, the others stay inside the
+    graphs between the timed runs."""
     s = make_small_drive(30, 2000, seed=21)
     p = balib.Problem.from_scene(s, max_iters=5, precision="f32", flags=flags)
     names = list(p.kernel_times().keys())
     a = p.solve().result()
-    p.set_profiling(1 << names.index("pcg_cg"))
+    p.set_profiling(1 << names.index("pcg_cg"), stride)
     b = p.reset().solve().result()
     ms, n = p.kernel_times()["pcg_cg"]
     b2 = p.reset().solve().result()
@@ -295,7 +298,8 @@ def test_profiled_solves_equal_unprofiled(balib, flags):
     c = p.reset().solve().result()
     p.close()
     _say("pcg_cg", ms, ms2, "ms over", n, n2, "launches")
-    assert n == n2 == (5 if flags else 5 * 50) and ms > 0 and ms2 > 0
+    runs = len(range(0, 5, stride))  # LM iterations 0, stride, 2 stride, ... of 5
+    assert n == n2 == (runs if flags else runs * 50) and ms > 0 and ms2 > 0
     for r in (b, b2, c):
         assert np.array_equal(r["iter_cost"], a["iter_cost"])
         assert np.array_equal(r["X"], a["X"]) and np.array_equal(r["q"], a["q"])
